@@ -1,0 +1,237 @@
+"""Benchmark of the DNN-MG fine-level correction step on one MI355X.
+
+One step = prolongation -> fine residual -> patch gather -> patch network ->
+multiplicity-averaged extension -> right-hand side -> restriction (the hot
+path after the coarse solve), captured in one HIP graph and replayed.
+
+Default workload: the single-simulation channel, coarse 64x16x16 cells
+(16,384 patches), fine 128x32x32 cells (140,481 nodes), FP32 stencils and a
+BF16 network 165-256-256-81.  Prints one JSON line; `value` is patches/s.
+Also reported: the same step with an FP32 network, and the large channel
+(131,072 patches, FP8 network of width 512) with the residual indicator.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_VALU_PEAK_TFLOPS = 157.3  # published vector FP32 (packed FMA); non-packed issue is half
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+
+# Algorithmic work per unit of the dominant kernel (residual):
+# FP32 flops per fine cell of the sum-factorised Q1 residual with LPS terms.
+RESIDUAL_FLOP_PER_CELL = None  # filled from paper_2307_14837_amd.flops
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-variants", action="store_true", help="only the default workload")
+    return ap.parse_args()
+
+
+def src_hash(*names):
+    h = hashlib.sha256()
+    for n in names:
+        h.update(open(os.path.join(ROOT, "paper_2307_14837_amd", "csrc", n), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(kernel_file, workload):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it was
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"pmc_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    k = rec.get("kernels", {}).get(kernel_file)
+    if not k or k.get("src_hash") != src_hash(kernel_file + ".hip"):
+        return None
+    return k.get("bytes_per_launch")
+
+
+def time_graph(st, steps, warmup):
+    import torch
+
+    st.capture()
+    for _ in range(warmup):
+        st.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        st.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def time_kernel(fn, reps):
+    """Average duration of one launch of fn(): `reps` back-to-back launches are
+    captured in one HIP graph (no host launch gaps) and timed with HIP events
+    on the stream the graph is replayed on."""
+    import torch
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        fn()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(reps):
+            fn()
+    g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def build_step(w, dtype, seed=0, indicator=False):
+    import dnnmg_synth as syn
+    from paper_2307_14837_amd import stepper
+
+    inp = syn.step_inputs(w, seed=seed)
+    params = syn.mlp_params(165, w.hidden, 81, seed=seed)
+    st = stepper.CorrectionStep(w.box, w.ns, params, dtype=dtype, indicator=indicator)
+    st.load(inp.xc, inp.vprev)
+    return st, inp, params
+
+
+def run_variant(w, dtype, steps, warmup, indicator=False):
+    st, inp, params = build_step(w, dtype, indicator=indicator)
+    ms, wall = time_graph(st, steps, warmup)
+    return {"workload": w.name, "dtype": dtype, "indicator": indicator, "ms_per_step": ms,
+            "patches_per_s": st.np / (ms * 1e-3), "fine_dof_per_s": 4 * st.nf / (ms * 1e-3)}
+
+
+def accuracy(w, dtype):
+    """rel-L2 of the corrected velocity correction d and of b^L against the
+    FP64 oracle on the same inputs (test infrastructure)."""
+    import oracle
+
+    st, inp, params = build_step(w, dtype)
+    out = st.run_numpy(inp.xc, inp.vprev)
+    p32 = [np.asarray(p, np.float32).astype(np.float64) for p in params]
+    ref = oracle.correction_step(w.box, w.ns, p32, inp.xc, out["vprev32"])
+    rel = lambda a, b: float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+    return {"d": rel(out["d"], ref["d"]), "r": rel(out["r"], ref["r"]), "bc": rel(out["bc"], ref["bc"])}
+
+
+def cpu_baseline(w):
+    """The oracle as it stands, one full correction step of the same workload
+    on one host core (the oracle is single-threaded C)."""
+    import dnnmg_synth as syn
+    import oracle
+
+    inp = syn.step_inputs(w, seed=0)
+    params = [np.asarray(p, np.float32).astype(np.float64) for p in syn.mlp_params(165, w.hidden, 81, seed=0)]
+    oracle.lib()
+    t0 = time.perf_counter()
+    oracle.correction_step(w.box, w.ns, params, inp.xc, inp.vprev)
+    dt = time.perf_counter() - t0
+    return {"value": w.box.n_patches / dt, "unit": "patches/s", "cores": 1, "kind": "oracle",
+            "sample": f"one full correction step of {w.name} ({w.box.n_patches} patches) in FP64, "
+                      f"{dt:.2f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    import dnnmg_synth as syn
+    from paper_2307_14837_amd import _lib as L
+    from paper_2307_14837_amd import flops
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    w = syn.cfg2()
+    st, inp, params = build_step(w, "bf16")
+    print(f"[bench] {w.name}: {st.np} patches, {st.nf} fine nodes; timing {args.steps} graph replays",
+          file=sys.stderr, flush=True)
+    ms, wall = time_graph(st, args.steps, args.warmup)
+
+    # dominant kernel: the fine residual (VALU bound), timed live with HIP events
+    reps = 50
+    res_ms = time_kernel(lambda: L.dnnmg_residual(st.box, st.ns, st.xt, st.vprev, st.r, st.ws_res), reps)
+    ncells = 8 * st.np
+    flop = flops.residual_flops_per_cell() * ncells
+    achieved = flop / (res_ms * 1e-3) / 1e12
+    traffic = traffic_from_profile("residual", w.name)
+    kernel_ms = {
+        "residual": res_ms,
+        "prolong": time_kernel(lambda: L.dnnmg_prolong(st.box, st.xc, st.xt), reps),
+        "gather": time_kernel(lambda: L.dnnmg_patch_gather(st.box, st.xt, st.r, st.X, st.xdtype, 192,
+                                                          st.shift, st.inv_scale), reps),
+        "forward": time_kernel(lambda: L.dnnmg_patch_forward(st.net, st.np, st.X, 192, st.Y), reps),
+        "scatter": time_kernel(lambda: L.dnnmg_scatter_avg(st.box, st.Y, st.xcorr, vbase=st.xt), reps),
+        "rhs": time_kernel(lambda: L.dnnmg_rhs(st.box, st.ns, st.xcorr, st.b), reps),
+        "restrict": time_kernel(lambda: L.dnnmg_restrict(st.box, st.b, st.bc), reps),
+    }
+    mlp_flop = flops.mlp_flops_per_patch(256) * st.np
+    out = {
+        "metric": "DNN-MG correction step throughput (patches/s; fine DOF/s also given)",
+        "value": st.np / (ms * 1e-3),
+        "unit": "patches/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": w.name, "patches": st.np, "fine_nodes": st.nf, "fine_dofs": 4 * st.nf,
+                   "network": "165-256-256-81 tanh, BF16 MFMA, FP32 accumulate",
+                   "stencils": "FP32 (prolongation from FP64, restriction to FP64)",
+                   "parallelism": "1 GPU", "graph": "hipGraph replay of the whole step"},
+        "fine_dof_per_s": 4 * st.nf / (ms * 1e-3),
+        "roofline": {"kernel": "dnnmg_residual", "bound": "alu", "achieved": achieved,
+                     "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": traffic,
+                     "avg_launch_ms": res_ms, "flop_per_launch": flop},
+        "kernel_ms": kernel_ms,
+        "mlp_tflops": mlp_flop / (kernel_ms["forward"] * 1e-3) / 1e12,
+        "wall_s_timed": wall,
+    }
+    if not args.no_variants:
+        print("[bench] variants: fp32 network, indicator, large FP8 channel", file=sys.stderr, flush=True)
+        out["variants"] = [
+            run_variant(w, "fp32", args.steps, args.warmup),
+            run_variant(w, "bf16", args.steps, args.warmup, indicator=True),
+            run_variant(syn.cfg5(), "fp8", max(args.steps // 4, 10), max(args.warmup // 4, 3), indicator=True),
+        ]
+        print("[bench] accuracy vs oracle", file=sys.stderr, flush=True)
+        out["accuracy_rel_l2"] = {"bf16": accuracy(w, "bf16"), "fp32": accuracy(w, "fp32")}
+    if not args.no_cpu:
+        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

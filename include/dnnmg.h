@@ -1,0 +1,219 @@
+/*
+ * dnnmg.h - C ABI of the MI355X (gfx950) DNN-MG fine-level correction library.
+ *
+ * The library evaluates the per-time-step correction of DNN-MG (arXiv
+ * 2307.14837, Algorithm 1, the steps after the coarse Newton solve):
+ *   prolongate the coarse solution one level      dnnmg_prolong
+ *   fine Crank-Nicolson residual                  dnnmg_residual
+ *   gather patch inputs (operator Q)              dnnmg_patch_gather
+ *   patch network forward / backward              dnnmg_patch_forward / _backward
+ *   multiplicity-averaged extension (operator L)  dnnmg_scatter_avg
+ *   right-hand side for the next step             dnnmg_rhs
+ *   restriction of that rhs to the coarse level   dnnmg_restrict
+ * plus the index maps, FP64 norms for the residual indicator, the AdamW
+ * update and weight packing for the network.
+ *
+ * Conventions for every entry point
+ *   - Return value: DNNMG_OK (0) or a negative DNNMG_ERR_* code;
+ *     dnnmg_last_error() returns a message for the calling thread.
+ *   - All arguments are validated on the host before anything is enqueued,
+ *     so an error leaves no partial work on the stream.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = legacy default
+ *     stream).  No call synchronises, allocates device memory or keeps a
+ *     pointer after it returns.  The caller owns every buffer.
+ *   - Device pointers must be 16-byte aligned unless stated otherwise.
+ *   - Mesh: a box [0,len0]x[0,len1]x[0,len2] with n[a] coarse cells per axis;
+ *     the fine mesh has 2 n[a] cells per axis.  Nodes per axis: 2n (fine) /
+ *     n (coarse) on periodic axes, 2n+1 / n+1 otherwise.  Node index
+ *     i + Nx (j + Ny k).  Fields are SoA [component][node] (u, v, w, p).
+ *   - Patch M = coarse cell (I,J,K), M = I + n0 (J + n1 K); its 27 local
+ *     nodes are iota = a + 3b + 9c, fine node (2I+a, 2J+b, 2K+c) (Sec. 4.2).
+ *   - Periodic axes need an even n >= 2.
+ */
+#ifndef DNNMG_H
+#define DNNMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DNNMG_OK 0
+#define DNNMG_ERR_ARG (-1)         /* null or misaligned pointer, bad scalar */
+#define DNNMG_ERR_SHAPE (-2)       /* mesh, width, leading dimension or size */
+#define DNNMG_ERR_UNSUPPORTED (-3) /* dtype or width not built */
+#define DNNMG_ERR_HIP (-4)         /* a HIP runtime call or launch failed */
+
+/* Mesh.  dirichlet_mask bit 2a = low face of axis a carries Dirichlet velocity
+ * data, bit 2a+1 = high face; faces without the bit are do-nothing (natural)
+ * boundaries.  Bits on periodic axes are ignored. */
+typedef struct dnnmg_box {
+    int32_t n[3];
+    double len[3];
+    uint32_t periodic_mask;
+    uint32_t dirichlet_mask;
+} dnnmg_box;
+
+/* Crank-Nicolson step and stabilisation parameters, eq. (stabparams):
+ * alpha_T = alpha0 / (nu/h_T^2 + |v|_inf,T / h_T + 1/dt), delta_T likewise. */
+typedef struct dnnmg_ns {
+    double nu, dt, alpha0, delta0;
+} dnnmg_ns;
+
+/* Network element types */
+#define DNNMG_F32 0
+#define DNNMG_BF16 1
+#define DNNMG_FP8_E4M3 2 /* OCP E4M3FN, max 448, saturating */
+
+/* Patch network 165 -> H -> H -> 81 with tanh (Sec. 3; width H in
+ * {64,128,256,512}).  W[l] are packed by dnnmg_mlp_pack; b[l] are FP32
+ * biases (length H, H, 81).  Products accumulate in FP32 and bias and tanh are
+ * applied in FP32.  Element types per layer (1, 2, 3):
+ *   DNNMG_F32       FP32, FP32, FP32   (inputs X FP32)
+ *   DNNMG_BF16      BF16, BF16, BF16   (inputs X BF16)
+ *   DNNMG_FP8_E4M3  BF16, FP8,  BF16   (inputs X BF16; H >= 128): the H x H
+ *                   product runs in OCP E4M3 with per-tensor scales, W2 =
+ *                   W2q * w_scale[1] and layer-2 inputs a = aq * a_scale[1];
+ *                   the other scales are ignored. */
+typedef struct dnnmg_mlp {
+    int32_t n_in;  /* must be 165 */
+    int32_t hidden;
+    int32_t n_out; /* must be 81 */
+    int32_t dtype; /* DNNMG_F32 | DNNMG_BF16 | DNNMG_FP8_E4M3 */
+    const void *W[3];
+    const float *b[3];
+    float w_scale[3];
+    float a_scale[3];
+} dnnmg_mlp;
+
+/* Per-feature standardisation of the 165 network inputs, z = (X - shift) *
+ * inv_scale, applied by the gather (device arrays of 165 floats; NULL =
+ * identity). */
+typedef struct dnnmg_feat {
+    const float *shift;
+    const float *inv_scale;
+} dnnmg_feat;
+
+int dnnmg_version(void);
+const char *dnnmg_last_error(void);
+
+/* Host-only size queries.  Any output pointer may be NULL. */
+int dnnmg_box_sizes(const dnnmg_box *box, int64_t *n_fine, int64_t *n_coarse,
+                    int64_t *n_patches);
+
+/* dof(P_M, iota) and valence (Sec. 4.2, the dof map and the vector mu of the
+ * extension operator).  map: int32 [n_patches][27] fine node indices;
+ * mult: uint8 [n_fine], number of patches holding each node (1, 2, 4 or 8). */
+int dnnmg_patch_dofmap(const dnnmg_box *box, int32_t *map, uint8_t *mult, void *stream);
+
+/* Prolongation of Algorithm 1: Q1 interpolation of the coarse solution onto
+ * the fine mesh.  xc: FP64 [ncomp][n_coarse]; xf: FP32 [ncomp][n_fine];
+ * 1 <= ncomp <= 4.  xc and xf must not overlap. */
+int dnnmg_prolong(const dnnmg_box *box, int ncomp, const double *xc, float *xf, void *stream);
+
+/* Fine residual of Algorithm 1, r = F - A(x), for the Crank-Nicolson system
+ * (4cranknicholson3) with the two-level local projection stabilisation of
+ * eq. (disc:ns) (projection onto the Q1 space of each patch).
+ *   x     FP32 [4][n_fine]  current iterate (u, v, w, p)
+ *   vprev FP32 [3][n_fine]  velocity of the previous step (builds F)
+ *   fmid  FP32 [3][n_fine]  (f_{n-1} + f_n) / 2, or NULL for no forcing
+ *   r     FP32 [4][n_fine]  output; velocity rows on Dirichlet faces are 0
+ *   ws    device workspace of at least dnnmg_residual_workspace(box) bytes
+ * Element integrals use 2x2x2 Gauss points on every fine cell. */
+size_t dnnmg_residual_workspace(const dnnmg_box *box);
+int dnnmg_residual(const dnnmg_box *box, const dnnmg_ns *ns, const float *x, const float *vprev,
+                   const float *fmid, float *r, void *ws, size_t ws_bytes, void *stream);
+
+/* Right-hand side of (4cranknicholson3) for the next step (Algorithm 1,
+ * "Rhs"): b_a = (1/k)(v_a, phi) - 1/2 (v.grad v_a, phi) - nu/2 (grad v_a,
+ * grad phi) + (fmid_a, phi); pressure rows 0; Dirichlet velocity rows 0.
+ *   v FP32 [3][n_fine]; fmid FP32 [3][n_fine] = (f_n + f_{n+1})/2 or NULL;
+ *   b FP32 [4][n_fine]. */
+int dnnmg_rhs(const dnnmg_box *box, const dnnmg_ns *ns, const float *v, const float *fmid,
+              float *b, void *stream);
+
+/* Restriction of Algorithm 1: bc = P^T bf, the transpose of dnnmg_prolong,
+ * accumulated and stored in FP64.  bf: FP32 [ncomp][n_fine];
+ * bc: FP64 [ncomp][n_coarse]. */
+int dnnmg_restrict(const dnnmg_box *box, int ncomp, const float *bf, double *bc, void *stream);
+
+/* Operator Q of eq. (defQ) applied to the prolongated solution and to the
+ * residual, plus the coarse cell sizes (the geometry inputs of Sec. 4.2):
+ * row M = [u(dof(M,0..26)), v(..), w(..), r_u(..), r_v(..), r_w(..), H0, H1,
+ * H2], standardised by `feat` and stored as `dtype` in X [n_patches][ldx]
+ * (ldx >= 165; columns 165..ldx-1 are written as zero).  For FP8 the stored
+ * value is round_e4m3(z / x_scale) (x_scale = the network's a_scale[0]);
+ * otherwise x_scale is ignored.  x: FP32 [>=3][n_fine]; r: FP32 [>=3][n_fine]. */
+int dnnmg_patch_gather(const dnnmg_box *box, const float *x, const float *r, const dnnmg_feat *feat,
+                       int dtype, float x_scale, void *X, int64_t ldx, void *stream);
+
+/* Packed weight layout used by the network kernels.  dnnmg_mlp_packed_bytes
+ * gives the size for layer `layer` (0, 1, 2) of a width-`hidden` network of
+ * element type dtype; dnnmg_mlp_pack converts an FP32 row-major
+ * [fan_in][fan_out] matrix W (device) into it (FP8: Wq = round(W / w_scale)). */
+size_t dnnmg_mlp_packed_bytes(int dtype, int hidden, int layer);
+int dnnmg_mlp_pack(int dtype, int hidden, int layer, const float *W, float w_scale, void *Wp,
+                   void *stream);
+
+/* Patch network N applied to every row of X (Sec. 4.2, patch-wise
+ * prediction): Y = W3^T tanh(W2^T tanh(W1^T x + b1) + b2) + b3, FP32
+ * accumulation, FP32 outputs Y [n][81].  X has the network's dtype and
+ * leading dimension ldx >= 165 (padding columns must be zero).  If `saved` is
+ * not NULL the hidden activations are stored for dnnmg_patch_backward:
+ * bf16 [2][n][hidden] for BF16, fp32 [2][n][hidden] for F32 (FP8 does not
+ * save).  n may be 0. */
+int dnnmg_patch_forward(const dnnmg_mlp *net, int64_t n, const void *X, int64_t ldx, float *Y,
+                        void *saved, void *stream);
+size_t dnnmg_patch_saved_bytes(const dnnmg_mlp *net, int64_t n);
+
+/* Training objective of Sec. 4.2 restricted to patches: loss = (1/n) sum_M
+ * ||Y_M - T_M||^2.  Writes its gradient dY = 2 (Y - T) / n (FP32 [n][81]);
+ * the loss itself is dnnmg_norm2_f64(Y, T) / n. */
+int dnnmg_mse_grad(int64_t n, const float *Y, const float *T, float *dY, void *stream);
+
+/* Gradients of sum_M <dY_M, Y_M> with respect to the network parameters
+ * (chain rule through both tanh layers; the input gradient is not formed),
+ * for F32 or BF16 networks.  net gives dtype and width; W2 and W3 are the FP32
+ * master weights of layers 2 and 3 (row-major [fan_in][fan_out]); X and ldx
+ * are the forward's inputs and `saved` its activations.  dW[l] (FP32
+ * row-major [fan_in][fan_out]) and db[l] are overwritten.  Products use
+ * FP32 MFMA with FP32 accumulation; sums over patches are split into fixed
+ * ranges and added in a fixed order (deterministic).  ws: device workspace of
+ * dnnmg_patch_backward_workspace(net, n) bytes. */
+size_t dnnmg_patch_backward_workspace(const dnnmg_mlp *net, int64_t n);
+int dnnmg_patch_backward(const dnnmg_mlp *net, const float *W2, const float *W3, int64_t n,
+                         const void *X, int64_t ldx, const void *saved, const float *dY,
+                         float *dW[3], float *db[3], void *ws, size_t ws_bytes, void *stream);
+
+/* AdamW step (Sec. 3), t >= 1, in place on FP32 master weights theta and
+ * moments m, v (n elements, gradient g):
+ *   m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ *   theta -= lr wd theta + lr (m/(1-b1^t)) / (sqrt(v/(1-b2^t)) + eps). */
+int dnnmg_adamw_step(int64_t n, float *theta, float *m, float *v, const float *g, float lr,
+                     float b1, float b2, float eps, float wd, int64_t t, void *stream);
+
+/* Extension L of eq. (defL): d = mu (.) sum_M L(Y[M], P_M), mu = 1/valence,
+ * computed per fine node as a gather over the patches holding it, in
+ * ascending patch order (deterministic, no atomics).  Y FP32 [n_patches][81]
+ * (component-major per patch); Dirichlet velocity nodes get no correction.
+ * vbase == NULL: d FP32 [3][n_fine] receives the correction.
+ * vbase != NULL: vbase FP32 [4][n_fine] is the prolongated iterate (v~, p~)
+ * and d FP32 [4][n_fine] receives the corrected iterate (v~ + L(Y), p~); the
+ * network gives no pressure correction (Sec. 4.2). */
+int dnnmg_scatter_avg(const dnnmg_box *box, const float *Y, const float *vbase, float *d,
+                      void *stream);
+
+/* Squared Euclidean norm in FP64 of a (or of a - b if b != NULL) over n
+ * FP32 elements, written to *out (device).  Used for the residual indicator
+ * eta = ||r(v~ + d)|| / ||r(v~)||.  Fixed-order two-level reduction
+ * (deterministic); ws: device workspace of dnnmg_norm2_workspace() bytes. */
+size_t dnnmg_norm2_workspace(void);
+int dnnmg_norm2_f64(int64_t n, const float *a, const float *b, double *out, void *ws,
+                    size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DNNMG_H */

@@ -265,3 +265,25 @@ def round_bf16(x) -> np.ndarray:
 def round_e4m3(x) -> np.ndarray:
     f = lib().or_round_e4m3
     return np.vectorize(lambda t: f(float(t)), otypes=[np.float64])(np.asarray(x, dtype=np.float64))
+
+
+def correction_step(box, ns, params, xc, vprev, shift=None, inv_scale=None, indicator=False):
+    """Algorithm 1 after the coarse solve, step by step in FP64:
+    x~ = P x^L; r = F - A(x~); X = Q(x~, r, geometry); Y = N(X);
+    x_corr = (v~ + L(Y), p~); b = Rhs(v~ + d); b^L = R b.
+    With indicator, also r(x_corr) and eta = ||r(x_corr)|| / ||r(x~)||."""
+    xt = prolong(box, xc)
+    r = residual(box, ns, xt, vprev)
+    X = gather(box, xt, r, shift, inv_scale)
+    Y = mlp_forward(X, *params)
+    d = scatter(box, Y)
+    vcorr = xt[:3] + d
+    b = rhs(box, ns, vcorr)
+    bc = restrict(box, b)
+    out = dict(xt=xt, r=r, X=X, Y=Y, d=d, vcorr=vcorr, b=b, bc=bc)
+    if indicator:
+        xcorr = np.concatenate([vcorr, xt[3:4]])
+        r2 = residual(box, ns, xcorr, vprev)
+        out["r2"] = r2
+        out["eta"] = float(np.sqrt(norm2(r2) / norm2(r)))
+    return out

@@ -1,0 +1,299 @@
+"""ctypes binding of libdnnmg.so: same entry-point names as include/dnnmg.h.
+
+Argument marshalling only: each wrapper checks that the torch tensors it is
+given are on the GPU, contiguous and of the expected dtype and size, then
+passes raw device pointers and the current HIP stream to the library.  There
+is no fallback: if the library is missing, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdnnmg.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'` "
+        "(hipcc for gfx950). There is no CPU fallback.")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK = 0
+F32, BF16, FP8_E4M3 = 0, 1, 2
+N_IN, N_OUT, IN_PAD, OUT_PAD = 165, 81, 192, 96
+
+c_i64 = ctypes.c_int64
+c_vp = ctypes.c_void_p
+c_f = ctypes.c_float
+c_sz = ctypes.c_size_t
+
+
+class Box(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("len", ctypes.c_double * 3),
+                ("periodic_mask", ctypes.c_uint32), ("dirichlet_mask", ctypes.c_uint32)]
+
+    @classmethod
+    def of(cls, spec) -> "Box":
+        if isinstance(spec, Box):
+            return spec
+        b = cls()
+        for a in range(3):
+            b.n[a] = int(spec.n[a])
+            b.len[a] = float(spec.len[a])
+        b.periodic_mask = int(spec.periodic_mask)
+        b.dirichlet_mask = int(spec.dirichlet_mask)
+        return b
+
+
+class NS(ctypes.Structure):
+    _fields_ = [("nu", ctypes.c_double), ("dt", ctypes.c_double),
+                ("alpha0", ctypes.c_double), ("delta0", ctypes.c_double)]
+
+    @classmethod
+    def of(cls, p) -> "NS":
+        if isinstance(p, NS):
+            return p
+        return cls(float(p.nu), float(p.dt), float(p.alpha0), float(p.delta0))
+
+
+class MLP(ctypes.Structure):
+    _fields_ = [("n_in", ctypes.c_int32), ("hidden", ctypes.c_int32), ("n_out", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("W", c_vp * 3), ("b", c_vp * 3),
+                ("w_scale", c_f * 3), ("a_scale", c_f * 3)]
+
+
+class Feat(ctypes.Structure):
+    _fields_ = [("shift", c_vp), ("inv_scale", c_vp)]
+
+
+def _sig(name, argtypes, restype=ctypes.c_int):
+    f = getattr(_lib, name)
+    f.argtypes = argtypes
+    f.restype = restype
+    return f
+
+
+_P = ctypes.POINTER
+_sig("dnnmg_version", [])
+_sig("dnnmg_last_error", [], ctypes.c_char_p)
+_sig("dnnmg_box_sizes", [_P(Box), _P(c_i64), _P(c_i64), _P(c_i64)])
+_sig("dnnmg_patch_dofmap", [_P(Box), c_vp, c_vp, c_vp])
+_sig("dnnmg_prolong", [_P(Box), ctypes.c_int, c_vp, c_vp, c_vp])
+_sig("dnnmg_residual_workspace", [_P(Box)], c_sz)
+_sig("dnnmg_residual", [_P(Box), _P(NS), c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp])
+_sig("dnnmg_rhs", [_P(Box), _P(NS), c_vp, c_vp, c_vp, c_vp])
+_sig("dnnmg_restrict", [_P(Box), ctypes.c_int, c_vp, c_vp, c_vp])
+_sig("dnnmg_patch_gather", [_P(Box), c_vp, c_vp, _P(Feat), ctypes.c_int, c_f, c_vp, c_i64, c_vp])
+_sig("dnnmg_mlp_packed_bytes", [ctypes.c_int, ctypes.c_int, ctypes.c_int], c_sz)
+_sig("dnnmg_mlp_pack", [ctypes.c_int, ctypes.c_int, ctypes.c_int, c_vp, c_f, c_vp, c_vp])
+_sig("dnnmg_patch_forward", [_P(MLP), c_i64, c_vp, c_i64, c_vp, c_vp, c_vp])
+_sig("dnnmg_patch_saved_bytes", [_P(MLP), c_i64], c_sz)
+_sig("dnnmg_scatter_avg", [_P(Box), c_vp, c_vp, c_vp, c_vp])
+_sig("dnnmg_norm2_workspace", [], c_sz)
+_sig("dnnmg_norm2_f64", [c_i64, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp])
+_sig("dnnmg_mse_grad", [c_i64, c_vp, c_vp, c_vp, c_vp])
+_sig("dnnmg_patch_backward_workspace", [_P(MLP), c_i64], c_sz)
+_sig("dnnmg_patch_backward", [_P(MLP), c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_vp, c_vp * 3, c_vp * 3,
+                              c_vp, c_sz, c_vp])
+_sig("dnnmg_adamw_step", [c_i64, c_vp, c_vp, c_vp, c_vp, c_f, c_f, c_f, c_f, c_f, c_i64, c_vp])
+
+EXPORTS = [
+    "dnnmg_version", "dnnmg_last_error", "dnnmg_box_sizes", "dnnmg_patch_dofmap", "dnnmg_prolong",
+    "dnnmg_residual_workspace", "dnnmg_residual", "dnnmg_rhs", "dnnmg_restrict",
+    "dnnmg_patch_gather", "dnnmg_mlp_packed_bytes", "dnnmg_mlp_pack", "dnnmg_patch_forward",
+    "dnnmg_patch_saved_bytes", "dnnmg_scatter_avg", "dnnmg_norm2_workspace", "dnnmg_norm2_f64",
+    "dnnmg_mse_grad", "dnnmg_patch_backward_workspace", "dnnmg_patch_backward", "dnnmg_adamw_step",
+]
+
+
+class DnnmgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libdnnmg error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc != OK:
+        raise DnnmgError(rc, _lib.dnnmg_last_error().decode())
+
+
+def lib():
+    return _lib
+
+
+def _stream(stream):
+    if stream is None:
+        return c_vp(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return c_vp(stream.cuda_stream)
+    return c_vp(int(stream))
+
+
+def _ptr(t, dtype=None, numel=None, name="tensor"):
+    """Device pointer of a contiguous CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU torch tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name} has {t.numel()} elements, needs {numel}")
+    return c_vp(t.data_ptr())
+
+
+def box_sizes(box):
+    b = Box.of(box)
+    nf, nc, np_ = c_i64(), c_i64(), c_i64()
+    _check(_lib.dnnmg_box_sizes(ctypes.byref(b), ctypes.byref(nf), ctypes.byref(nc), ctypes.byref(np_)))
+    return nf.value, nc.value, np_.value
+
+
+def dnnmg_patch_dofmap(box, dofmap=None, mult=None, stream=None):
+    b = Box.of(box)
+    nf, _, npch = box_sizes(b)
+    _check(_lib.dnnmg_patch_dofmap(ctypes.byref(b), _ptr(dofmap, torch.int32, npch * 27, "map"),
+                                   _ptr(mult, torch.uint8, nf, "mult"), _stream(stream)))
+
+
+def dnnmg_prolong(box, xc, xf, ncomp=4, stream=None):
+    b = Box.of(box)
+    nf, nc, _ = box_sizes(b)
+    _check(_lib.dnnmg_prolong(ctypes.byref(b), ncomp, _ptr(xc, torch.float64, ncomp * nc, "xc"),
+                              _ptr(xf, torch.float32, ncomp * nf, "xf"), _stream(stream)))
+
+
+def residual_workspace_bytes(box) -> int:
+    return int(_lib.dnnmg_residual_workspace(ctypes.byref(Box.of(box))))
+
+
+def dnnmg_residual(box, ns, x, vprev, r, ws, fmid=None, stream=None):
+    b = Box.of(box)
+    nf, _, _ = box_sizes(b)
+    _check(_lib.dnnmg_residual(ctypes.byref(b), ctypes.byref(NS.of(ns)),
+                               _ptr(x, torch.float32, 4 * nf, "x"),
+                               _ptr(vprev, torch.float32, 3 * nf, "vprev"),
+                               _ptr(fmid, torch.float32, 3 * nf, "fmid"),
+                               _ptr(r, torch.float32, 4 * nf, "r"),
+                               _ptr(ws, None, None, "ws"), ws.numel() * ws.element_size(),
+                               _stream(stream)))
+
+
+def dnnmg_rhs(box, ns, v, b_out, fmid=None, stream=None):
+    b = Box.of(box)
+    nf, _, _ = box_sizes(b)
+    _check(_lib.dnnmg_rhs(ctypes.byref(b), ctypes.byref(NS.of(ns)), _ptr(v, torch.float32, 3 * nf, "v"),
+                          _ptr(fmid, torch.float32, 3 * nf, "fmid"),
+                          _ptr(b_out, torch.float32, 4 * nf, "b"), _stream(stream)))
+
+
+def dnnmg_restrict(box, bf, bc, ncomp=4, stream=None):
+    b = Box.of(box)
+    nf, nc, _ = box_sizes(b)
+    _check(_lib.dnnmg_restrict(ctypes.byref(b), ncomp, _ptr(bf, torch.float32, ncomp * nf, "bf"),
+                               _ptr(bc, torch.float64, ncomp * nc, "bc"), _stream(stream)))
+
+
+_DT_TORCH = {F32: torch.float32, BF16: torch.bfloat16, FP8_E4M3: torch.uint8}
+
+
+def dnnmg_patch_gather(box, x, r, X, dtype, ldx, shift=None, inv_scale=None, x_scale=1.0, stream=None):
+    b = Box.of(box)
+    nf, _, npch = box_sizes(b)
+    feat = Feat(None if shift is None else _ptr(shift, torch.float32, 165, "shift"),
+                None if inv_scale is None else _ptr(inv_scale, torch.float32, 165, "inv_scale"))
+    if X.numel() * X.element_size() < npch * ldx * {F32: 4, BF16: 2, FP8_E4M3: 1}[dtype]:
+        raise ValueError("X too small")
+    _check(_lib.dnnmg_patch_gather(ctypes.byref(b), _ptr(x, torch.float32, 3 * nf, "x"),
+                                   _ptr(r, torch.float32, 3 * nf, "r"), ctypes.byref(feat), dtype,
+                                   float(x_scale), _ptr(X, None, None, "X"), ldx, _stream(stream)))
+
+
+def packed_bytes(dtype, hidden, layer) -> int:
+    return int(_lib.dnnmg_mlp_packed_bytes(dtype, hidden, layer))
+
+
+def dnnmg_mlp_pack(dtype, hidden, layer, W, Wp, w_scale=1.0, stream=None):
+    if Wp.numel() * Wp.element_size() < packed_bytes(dtype, hidden, layer):
+        raise ValueError("packed buffer too small")
+    _check(_lib.dnnmg_mlp_pack(dtype, hidden, layer, _ptr(W, torch.float32, None, "W"), float(w_scale),
+                               _ptr(Wp, None, None, "Wp"), _stream(stream)))
+
+
+def make_mlp(dtype, hidden, Wp, bias, w_scale=(1.0, 1.0, 1.0), a_scale=(1.0, 1.0, 1.0)) -> MLP:
+    net = MLP()
+    net.n_in, net.hidden, net.n_out, net.dtype = N_IN, hidden, N_OUT, dtype
+    for l in range(3):
+        net.W[l] = Wp[l].data_ptr()
+        net.b[l] = bias[l].data_ptr()
+        net.w_scale[l] = float(w_scale[l])
+        net.a_scale[l] = float(a_scale[l])
+    return net
+
+
+def saved_bytes(net: MLP, n: int) -> int:
+    return int(_lib.dnnmg_patch_saved_bytes(ctypes.byref(net), n))
+
+
+def dnnmg_patch_forward(net: MLP, n, X, ldx, Y, saved=None, stream=None):
+    _check(_lib.dnnmg_patch_forward(ctypes.byref(net), int(n), _ptr(X, None, None, "X"), int(ldx),
+                                    _ptr(Y, torch.float32, n * N_OUT, "Y"),
+                                    _ptr(saved, None, None, "saved"), _stream(stream)))
+
+
+def dnnmg_scatter_avg(box, Y, d, vbase=None, stream=None):
+    b = Box.of(box)
+    nf, _, npch = box_sizes(b)
+    nd = 3 if vbase is None else 4
+    _check(_lib.dnnmg_scatter_avg(ctypes.byref(b), _ptr(Y, torch.float32, npch * N_OUT, "Y"),
+                                  _ptr(vbase, torch.float32, 4 * nf, "vbase"),
+                                  _ptr(d, torch.float32, nd * nf, "d"), _stream(stream)))
+
+
+def norm2_workspace_bytes() -> int:
+    return int(_lib.dnnmg_norm2_workspace())
+
+
+def dnnmg_norm2_f64(a, out, ws, b=None, n=None, stream=None):
+    n = a.numel() if n is None else n
+    _check(_lib.dnnmg_norm2_f64(int(n), _ptr(a, torch.float32, n, "a"), _ptr(b, torch.float32, n, "b"),
+                                _ptr(out, torch.float64, 1, "out"), _ptr(ws, None, None, "ws"),
+                                ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def dnnmg_mse_grad(Y, T, dY, n=None, stream=None):
+    n = Y.numel() // N_OUT if n is None else n
+    _check(_lib.dnnmg_mse_grad(int(n), _ptr(Y, torch.float32, n * N_OUT, "Y"),
+                               _ptr(T, torch.float32, n * N_OUT, "T"),
+                               _ptr(dY, torch.float32, n * N_OUT, "dY"), _stream(stream)))
+
+
+def backward_workspace_bytes(net: MLP, n: int) -> int:
+    return int(_lib.dnnmg_patch_backward_workspace(ctypes.byref(net), int(n)))
+
+
+def dnnmg_patch_backward(net: MLP, W2, W3, n, X, ldx, saved, dY, dW, db, ws, stream=None):
+    H = net.hidden
+    dw = (c_vp * 3)(*[_ptr(t, torch.float32, sz, "dW").value for t, sz in
+                      zip(dW, (N_IN * H, H * H, H * N_OUT))])
+    dbs = (c_vp * 3)(*[_ptr(t, torch.float32, sz, "db").value for t, sz in zip(db, (H, H, N_OUT))])
+    _check(_lib.dnnmg_patch_backward(ctypes.byref(net), _ptr(W2, torch.float32, H * H, "W2"),
+                                     _ptr(W3, torch.float32, H * N_OUT, "W3"), int(n),
+                                     _ptr(X, None, None, "X"), int(ldx), _ptr(saved, None, None, "saved"),
+                                     _ptr(dY, torch.float32, n * N_OUT, "dY"), dw, dbs,
+                                     _ptr(ws, None, None, "ws"), ws.numel() * ws.element_size(),
+                                     _stream(stream)))
+
+
+def dnnmg_adamw_step(theta, m, v, g, lr, t, b1=0.9, b2=0.999, eps=1e-8, wd=1e-5, stream=None):
+    n = theta.numel()
+    _check(_lib.dnnmg_adamw_step(int(n), _ptr(theta, torch.float32, n, "theta"), _ptr(m, torch.float32, n, "m"),
+                                 _ptr(v, torch.float32, n, "v"), _ptr(g, torch.float32, n, "g"),
+                                 float(lr), float(b1), float(b2), float(eps), float(wd), int(t),
+                                 _stream(stream)))

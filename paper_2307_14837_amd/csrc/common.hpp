@@ -1,0 +1,74 @@
+// Internal helpers shared by the HIP translation units of libdnnmg.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "dnnmg.h"
+
+namespace dnnmg {
+
+// ------------------------------------------------------------ error state --
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int hip_check(hipError_t e, const char *what);
+
+inline bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+// ------------------------------------------------------------------- mesh --
+// Unsigned 32-bit division by a runtime constant: q = floor(n / d) for
+// n < 2^31, via a 32x32 high multiply (round-up reciprocal method).
+struct FastDiv {
+    uint32_t d, m, s;
+};
+FastDiv make_fastdiv(uint32_t d);
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv &f) {
+    uint32_t hi = __umulhi(n, f.m);
+    return (uint32_t)(((uint64_t)hi + n) >> f.s);
+}
+
+// Two-level structured mesh in the form the kernels use.  Fine node
+// (i,j,k) -> i + nf[0] (j + nf[1] k); coarse likewise with nc.
+struct Mesh {
+    int32_t n[3];   // coarse cells per axis
+    int32_t nf[3];  // fine nodes per axis
+    int32_t nc[3];  // coarse nodes per axis
+    int32_t per[3]; // periodic axis flags
+    uint32_t dmask; // Dirichlet face bits (2a low, 2a+1 high)
+    int64_t n_fine, n_coarse, n_patches;
+    float h[3];     // fine cell sizes
+    float H[3];     // coarse cell sizes
+    double hd[3];
+    FastDiv fx, fy, cx, cy, px, py; // fine/coarse/patch lattice divisors
+};
+
+// Validates the box (positive sizes, even n >= 2 on periodic axes, node
+// counts below 2^31) and fills the kernel description.
+int make_mesh(const dnnmg_box *box, Mesh *m);
+
+__device__ __forceinline__ int wrap(int i, int N, int per) {
+    if (per) {
+        if (i < 0) i += N;
+        else if (i >= N) i -= N;
+    }
+    return i;
+}
+
+__device__ __forceinline__ bool on_dirichlet(const Mesh &m, int i, int j, int k) {
+    int c[3] = {i, j, k};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (m.per[a]) continue;
+        if (c[a] == 0 && ((m.dmask >> (2 * a)) & 1u)) return true;
+        if (c[a] == m.nf[a] - 1 && ((m.dmask >> (2 * a + 1)) & 1u)) return true;
+    }
+    return false;
+}
+
+inline unsigned blocks_for(int64_t n, int threads) {
+    return (unsigned)((n + threads - 1) / threads);
+}
+
+} // namespace dnnmg

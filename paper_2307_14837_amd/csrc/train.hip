@@ -1,0 +1,277 @@
+// Training kernels for the patch network (arXiv 2307.14837, Sec. 4.2 training
+// objective; Sec. 3 AdamW): gradient of the patch loss, backward pass through
+// the two tanh layers, and the AdamW update on FP32 master weights.
+//
+// The backward pass is five products of the forward's shapes:
+//   dZ2 = (dY W3^T) (.) (1 - A2^2),   dZ1 = (dZ2 W2^T) (.) (1 - A1^2)
+//   dW3 = A2^T dY,  dW2 = A1^T dZ2,  dW1 = X^T dZ1,  db = column sums.
+// They run on one tiled GEMM kernel (64x64 output tiles, LDS-staged operands,
+// v_mfma_f32_16x16x4f32 with FP32 accumulation).  The weight gradients reduce
+// over patches; they are split over K (patch ranges) and the partial tiles are
+// summed in a fixed order, so results are run-to-run identical.
+#include "common.hpp"
+#include "lowp.hpp"
+#include "mlp.hpp"
+
+namespace dnnmg {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T> __device__ __forceinline__ float ld(const T *p, int64_t i);
+template <> __device__ __forceinline__ float ld<float>(const float *p, int64_t i) { return p[i]; }
+template <> __device__ __forceinline__ float ld<uint16_t>(const uint16_t *p, int64_t i) {
+    return bf16_to_f32(p[i]);
+}
+
+constexpr int BM = 64, BN = 64, BK = 16;
+
+// C[M x N] (+= split) = op(A) op(B); op(A)[m][k] = TA ? A[k*lda + m] : A[m*lda + k],
+// op(B)[k][n] = TB ? B[n*ldb + k] : B[k*ldb + n].  EPI: C *= (1 - S[m][n]^2).
+// blockIdx.z = split index over K; C + z*M*N receives that split's partial.
+template <bool TA, bool TB, typename TAe, typename TBe, typename TSe, bool EPI>
+__global__ void __launch_bounds__(256)
+    k_gemm(int64_t M, int64_t N, int64_t K, int64_t kchunk, const TAe *__restrict__ A, int64_t lda,
+           const TBe *__restrict__ B, int64_t ldb, float *__restrict__ C, int64_t ldc,
+           const TSe *__restrict__ S, int64_t lds_) {
+    __shared__ float As[BK][BM + 4];
+    __shared__ float Bs[BK][BN + 4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
+    const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+    const int64_t kend = kbeg + kchunk < K ? kbeg + kchunk : K;
+    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+    const int g = lane >> 4, i16 = lane & 15;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+        // stage A tile (BM x BK) and B tile (BK x BN), 4 elements per thread each
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            int e = tid + 256 * r; // 0..1023
+            int mm, kk;
+            if (TA) { mm = e % BM; kk = e / BM; } else { kk = e % BK; mm = e / BK; }
+            int64_t gm = m0 + mm, gk = k0 + kk;
+            float v = 0.f;
+            if (gm < M && gk < kend) v = TA ? ld(A, gk * lda + gm) : ld(A, gm * lda + gk);
+            As[kk][mm] = v;
+            int nn;
+            if (TB) { kk = e % BK; nn = e / BK; } else { nn = e % BN; kk = e / BN; }
+            int64_t gn = n0 + nn;
+            gk = k0 + kk;
+            v = 0.f;
+            if (gn < N && gk < kend) v = TB ? ld(B, gn * ldb + gk) : ld(B, gk * ldb + gn);
+            Bs[kk][nn] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < BK; ks += 4) {
+            float af[2], bfv[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) af[a] = As[ks + g][wm + 16 * a + i16];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) bfv[b] = Bs[ks + g][wn + 16 * b + i16];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[a], bfv[b], acc[a][b], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    float *Cz = C + (int64_t)blockIdx.z * M * N;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                int64_t gm = m0 + wm + 16 * a + 4 * g + e;
+                int64_t gn = n0 + wn + 16 * b + i16;
+                if (gm < M && gn < N) {
+                    float v = acc[a][b][e];
+                    if (EPI) {
+                        float s = ld(S, gm * lds_ + gn);
+                        v *= 1.0f - s * s;
+                    }
+                    if (gridDim.z == 1) C[gm * ldc + gn] = v;
+                    else Cz[gm * N + gn] = v;
+                }
+            }
+}
+
+// out[i] = sum_z part[z][i], fixed order
+__global__ void k_sum_splits(int64_t len, int nz, const float *__restrict__ part, float *__restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= len) return;
+    float s = 0.f;
+    for (int z = 0; z < nz; ++z) s += part[(int64_t)z * len + i];
+    out[i] = s;
+}
+
+// column sums of a row-major [rows][cols] FP32 matrix, split over row chunks
+__global__ void k_colsum(int64_t rows, int64_t cols, int64_t chunk, const float *__restrict__ A,
+                         float *__restrict__ part) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cols) return;
+    int64_t r0 = (int64_t)blockIdx.y * chunk, r1 = r0 + chunk < rows ? r0 + chunk : rows;
+    float s = 0.f;
+    for (int64_t r = r0; r < r1; ++r) s += A[r * cols + c];
+    part[(int64_t)blockIdx.y * cols + c] = s;
+}
+
+__global__ void k_mse_grad(int64_t len, float scale, const float *__restrict__ Y,
+                           const float *__restrict__ T, float *__restrict__ dY) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) dY[i] = scale * (Y[i] - T[i]);
+}
+
+__global__ void k_adamw(int64_t n, float *__restrict__ th, float *__restrict__ m, float *__restrict__ v,
+                        const float *__restrict__ g, float lr, float b1, float b2, float eps, float wd,
+                        float inv_c1, float inv_sqrt_c2) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float gi = g[i];
+    float mi = b1 * m[i] + (1.0f - b1) * gi;
+    float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    float t = th[i];
+    float upd = (mi * inv_c1) / (sqrtf(vi) * inv_sqrt_c2 + eps);
+    th[i] = t - lr * wd * t - lr * upd;
+}
+
+struct BwdPlan {
+    int64_t n, H, splits, kchunk, rows_chunk, rsplits;
+    size_t off_dz2, off_dz1, off_part, off_cpart, total;
+};
+
+static BwdPlan plan_bwd(int H, int64_t n) {
+    BwdPlan p;
+    p.n = n;
+    p.H = H;
+    p.splits = (n + 2047) / 2048;
+    if (p.splits > 64) p.splits = 64;
+    if (p.splits < 1) p.splits = 1;
+    p.kchunk = ((n + p.splits - 1) / p.splits + BK - 1) / BK * BK;
+    p.rsplits = p.splits;
+    p.rows_chunk = (n + p.rsplits - 1) / p.rsplits;
+    if (p.rows_chunk < 1) p.rows_chunk = 1;
+    size_t a = 256;
+    auto up = [&](size_t b) { return (b + a - 1) / a * a; };
+    p.off_dz2 = 0;
+    p.off_dz1 = up(p.off_dz2 + sizeof(float) * n * H);
+    p.off_part = up(p.off_dz1 + sizeof(float) * n * H);
+    size_t part = sizeof(float) * p.splits * (size_t)((size_t)N_IN * H + (size_t)H * H + (size_t)H * N_OUT);
+    p.off_cpart = up(p.off_part + part);
+    p.total = up(p.off_cpart + sizeof(float) * p.rsplits * (size_t)(2 * H + N_OUT));
+    return p;
+}
+
+template <bool TA, bool TB, typename TAe, typename TBe, typename TSe, bool EPI>
+static void gemm(int64_t M, int64_t N, int64_t K, int64_t splits, int64_t kchunk, const TAe *A,
+                 int64_t lda, const TBe *B, int64_t ldb, float *C, int64_t ldc, float *part,
+                 const TSe *S, int64_t lds_, hipStream_t s) {
+    dim3 grid((unsigned)((M + BM - 1) / BM), (unsigned)((N + BN - 1) / BN), (unsigned)splits);
+    k_gemm<TA, TB, TAe, TBe, TSe, EPI><<<grid, 256, 0, s>>>(M, N, K, kchunk, A, lda, B, ldb,
+                                                            splits == 1 ? C : part, ldc, S, lds_);
+    if (splits > 1) k_sum_splits<<<blocks_for(M * N, 256), 256, 0, s>>>(M * N, (int)splits, part, C);
+}
+
+template <typename TX, typename TS>
+static void backward_impl(const BwdPlan &p, const TX *X, int64_t ldx, const TS *saved, const float *W2,
+                          const float *W3, const float *dY, float *dW[3], float *db[3], char *ws,
+                          hipStream_t s) {
+    const int64_t n = p.n, H = p.H;
+    float *dz2 = (float *)(ws + p.off_dz2);
+    float *dz1 = (float *)(ws + p.off_dz1);
+    float *part = (float *)(ws + p.off_part);
+    float *cpart = (float *)(ws + p.off_cpart);
+    const TS *A1 = saved, *A2 = saved + n * H;
+    // dZ2 = (dY W3^T) (.) (1 - A2^2): W3 is [H][81] -> op(B)[k=o][n=h] = W3[h][o]
+    gemm<false, true, float, float, TS, true>(n, H, N_OUT, 1, N_OUT + BK, dY, N_OUT, W3, N_OUT, dz2, H,
+                                              nullptr, A2, H, s);
+    // dZ1 = (dZ2 W2^T) (.) (1 - A1^2): W2 is [H_in][H_out] -> op(B)[k=j][n=h] = W2[h][j]
+    gemm<false, true, float, float, TS, true>(n, H, H, 1, H + BK, dz2, H, W2, H, dz1, H, nullptr, A1, H,
+                                              s);
+    // weight gradients, split over patches
+    gemm<true, false, TS, float, float, false>(H, N_OUT, n, p.splits, p.kchunk, A2, H, dY, N_OUT, dW[2],
+                                               N_OUT, part, nullptr, 0, s);
+    gemm<true, false, TS, float, float, false>(H, H, n, p.splits, p.kchunk, A1, H, dz2, H, dW[1], H,
+                                               part, nullptr, 0, s);
+    gemm<true, false, TX, float, float, false>(N_IN, H, n, p.splits, p.kchunk, X, ldx, dz1, H, dW[0], H,
+                                               part, nullptr, 0, s);
+    // bias gradients
+    const float *srcs[3] = {dz1, dz2, dY};
+    const int64_t cols[3] = {H, H, N_OUT};
+    for (int l = 0; l < 3; ++l) {
+        dim3 grid(blocks_for(cols[l], 128), (unsigned)p.rsplits);
+        k_colsum<<<grid, 128, 0, s>>>(n, cols[l], p.rows_chunk, srcs[l], cpart);
+        k_sum_splits<<<blocks_for(cols[l], 256), 256, 0, s>>>(cols[l], (int)p.rsplits, cpart, db[l]);
+    }
+}
+
+} // namespace dnnmg
+
+using namespace dnnmg;
+
+extern "C" int dnnmg_mse_grad(int64_t n, const float *Y, const float *T, float *dY, void *stream) {
+    if (n < 0) return fail(DNNMG_ERR_SHAPE, "dnnmg_mse_grad: n < 0");
+    if (n == 0) return DNNMG_OK;
+    if (!Y || !T || !dY) return fail(DNNMG_ERR_ARG, "dnnmg_mse_grad: NULL pointer");
+    int64_t len = n * N_OUT;
+    k_mse_grad<<<blocks_for(len, 256), 256, 0, (hipStream_t)stream>>>(len, 2.0f / (float)n, Y, T, dY);
+    return hip_check(hipGetLastError(), "dnnmg_mse_grad launch");
+}
+
+extern "C" int dnnmg_adamw_step(int64_t n, float *theta, float *m, float *v, const float *g, float lr,
+                                float b1, float b2, float eps, float wd, int64_t t, void *stream) {
+    if (n < 0 || t < 1) return fail(DNNMG_ERR_ARG, "dnnmg_adamw_step: need n >= 0 and t >= 1");
+    if (n == 0) return DNNMG_OK;
+    if (!theta || !m || !v || !g) return fail(DNNMG_ERR_ARG, "dnnmg_adamw_step: NULL pointer");
+    if (!(b1 >= 0.f && b1 < 1.f && b2 >= 0.f && b2 < 1.f && eps > 0.f))
+        return fail(DNNMG_ERR_ARG, "dnnmg_adamw_step: bad betas or eps");
+    double c1 = 1.0 - pow((double)b1, (double)t), c2 = 1.0 - pow((double)b2, (double)t);
+    k_adamw<<<blocks_for(n, 256), 256, 0, (hipStream_t)stream>>>(
+        n, theta, m, v, g, lr, b1, b2, eps, wd, (float)(1.0 / c1), (float)(1.0 / sqrt(c2)));
+    return hip_check(hipGetLastError(), "dnnmg_adamw_step launch");
+}
+
+extern "C" size_t dnnmg_patch_backward_workspace(const dnnmg_mlp *net, int64_t n) {
+    if (!net || n < 0) return 0;
+    return plan_bwd(net->hidden, n).total;
+}
+
+extern "C" int dnnmg_patch_backward(const dnnmg_mlp *net, const float *W2, const float *W3, int64_t n,
+                                    const void *X, int64_t ldx, const void *saved, const float *dY,
+                                    float *dW[3], float *db[3], void *ws, size_t ws_bytes,
+                                    void *stream) {
+    if (!net) return fail(DNNMG_ERR_ARG, "dnnmg_patch_backward: net is NULL");
+    if (net->n_in != N_IN || net->n_out != N_OUT)
+        return fail(DNNMG_ERR_SHAPE, "dnnmg_patch_backward: network must be 165 -> H -> H -> 81");
+    if (net->dtype != DNNMG_F32 && net->dtype != DNNMG_BF16)
+        return fail(DNNMG_ERR_UNSUPPORTED, "dnnmg_patch_backward: dtype %d (F32 or BF16 only)", net->dtype);
+    const int H = net->hidden;
+    if (H != 64 && H != 128 && H != 256 && H != 512)
+        return fail(DNNMG_ERR_UNSUPPORTED, "dnnmg_patch_backward: hidden %d", H);
+    if (n < 1) return fail(DNNMG_ERR_SHAPE, "dnnmg_patch_backward: n must be >= 1");
+    if (ldx < N_IN) return fail(DNNMG_ERR_SHAPE, "dnnmg_patch_backward: ldx < 165");
+    if (!W2 || !W3 || !X || !saved || !dY || !dW || !db || !ws)
+        return fail(DNNMG_ERR_ARG, "dnnmg_patch_backward: NULL pointer");
+    for (int l = 0; l < 3; ++l)
+        if (!dW[l] || !db[l]) return fail(DNNMG_ERR_ARG, "dnnmg_patch_backward: dW/db[%d] NULL", l);
+    BwdPlan p = plan_bwd(H, n);
+    if (ws_bytes < p.total)
+        return fail(DNNMG_ERR_SHAPE, "dnnmg_patch_backward: workspace %zu < %zu bytes", ws_bytes, p.total);
+    hipStream_t s = (hipStream_t)stream;
+    if (net->dtype == DNNMG_F32)
+        backward_impl<float, float>(p, (const float *)X, ldx, (const float *)saved, W2, W3, dY, dW, db,
+                                    (char *)ws, s);
+    else
+        backward_impl<uint16_t, uint16_t>(p, (const uint16_t *)X, ldx, (const uint16_t *)saved, W2, W3, dY,
+                                          dW, db, (char *)ws, s);
+    return hip_check(hipGetLastError(), "dnnmg_patch_backward launch");
+}

@@ -1,0 +1,428 @@
+// Grid-transfer and patch kernels of the DNN-MG correction (Algorithm 1 and
+// Sec. 4.2 of arXiv 2307.14837): dof map and valence, Q1 prolongation, its
+// transpose (restriction of the right-hand side), the patch gather Q with
+// feature standardisation and quantisation, the multiplicity-averaged
+// extension L, and FP64 norms.  All of these move little arithmetic per byte
+// and are bound by HBM bandwidth; threads map to consecutive x nodes so that
+// the fine-field streams are coalesced.
+#include "common.hpp"
+#include "lowp.hpp"
+
+namespace dnnmg {
+
+// ----------------------------------------------------------- dof map ------
+
+__global__ void k_dofmap(Mesh m, int32_t *__restrict__ map) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m.n_patches * 27) return;
+    uint32_t M = (uint32_t)(t / 27), iota = (uint32_t)(t - (int64_t)M * 27);
+    uint32_t J_K = fdiv(M, m.px), I = M - J_K * m.n[0];
+    uint32_t K = fdiv(J_K, m.py), J = J_K - K * m.n[1];
+    int a = iota % 3, b = (iota / 3) % 3, c = iota / 9;
+    int i = wrap(2 * I + a, m.nf[0], m.per[0]);
+    int j = wrap(2 * J + b, m.nf[1], m.per[1]);
+    int k = wrap(2 * K + c, m.nf[2], m.per[2]);
+    map[t] = i + m.nf[0] * (j + m.nf[1] * k);
+}
+
+// valence of a fine node = product over axes of the patches sharing it:
+// 2 at even lattice indices that are interior (or on a periodic axis), else 1
+__device__ __forceinline__ int valence(const Mesh &m, int i, int j, int k) {
+    int c[3] = {i, j, k}, v = 1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        if (!(c[a] & 1) && (m.per[a] || (c[a] > 0 && c[a] < 2 * m.n[a]))) v *= 2;
+    return v;
+}
+
+__global__ void k_mult(Mesh m, uint8_t *__restrict__ mult) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m.n_fine) return;
+    uint32_t jk = fdiv((uint32_t)t, m.fx), i = (uint32_t)t - jk * m.nf[0];
+    uint32_t k = fdiv(jk, m.fy), j = jk - k * m.nf[1];
+    mult[t] = (uint8_t)valence(m, i, j, k);
+}
+
+// ------------------------------------------------------- prolongation -----
+// 1-D Q1 interpolation: even fine index = coarse node, odd = mean of the two
+// coarse neighbours (wrapping on periodic axes).  One thread per coarse node
+// C = (I, J, K) writes the fine nodes 2C + (a, b, c), a, b, c in {0, 1}, that
+// exist, from the 2x2x2 coarse block C .. C+1: all loads are issued at once
+// (one memory round trip per thread).  Accumulated in FP64 from the FP64
+// coarse solution, rounded once to FP32.
+__global__ void __launch_bounds__(256) k_prolong(Mesh m, int ncomp, const double *__restrict__ xc,
+                                                 float *__restrict__ xf) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m.n_coarse) return;
+    uint32_t JK = fdiv((uint32_t)t, m.cx), I = (uint32_t)t - JK * m.nc[0];
+    uint32_t K = fdiv(JK, m.cy), J = JK - K * m.nc[1];
+    const int C[3] = {(int)I, (int)J, (int)K};
+    int hi[3];   // index of the upper coarse neighbour (clamped where absent)
+    bool odd[3]; // does the odd fine node 2C + 1 exist on this axis?
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int up = C[a] + 1;
+        if (m.per[a]) up = up == m.nc[a] ? 0 : up;
+        odd[a] = m.per[a] || C[a] + 1 < m.nc[a];
+        hi[a] = odd[a] ? up : C[a];
+    }
+    const int64_t ncn = m.n_coarse, nfn = m.n_fine;
+    int64_t cidx[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        int ii = (q & 1) ? hi[0] : C[0], jj = (q & 2) ? hi[1] : C[1], kk = (q & 4) ? hi[2] : C[2];
+        cidx[q] = ii + (int64_t)m.nc[0] * (jj + (int64_t)m.nc[1] * kk);
+    }
+    const int64_t f0 = 2 * (int64_t)I + (int64_t)m.nf[0] * (2 * (int64_t)J + (int64_t)m.nf[1] * 2 * K);
+    for (int comp = 0; comp < ncomp; ++comp) {
+        const double *x = xc + comp * ncn;
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = x[cidx[q]];
+        // x pass, y pass, z pass: value at offset 0 = corner, at 1 = mean
+        double px[8];
+#pragma unroll
+        for (int q = 0; q < 8; q += 2) { px[q] = v[q]; px[q + 1] = 0.5 * (v[q] + v[q + 1]); }
+        double py[8];
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                py[a + 4 * c] = px[a + 4 * c];
+                py[a + 2 + 4 * c] = 0.5 * (px[a + 4 * c] + px[a + 2 + 4 * c]);
+            }
+        double pz[8];
+#pragma unroll
+        for (int ab = 0; ab < 4; ++ab) { pz[ab] = py[ab]; pz[ab + 4] = 0.5 * (py[ab] + py[ab + 4]); }
+        float *out = xf + comp * nfn + f0;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            if (c && !odd[2]) break;
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                if (b && !odd[1]) break;
+                float *row = out + (int64_t)m.nf[0] * (b + (int64_t)m.nf[1] * c);
+                row[0] = (float)pz[2 * b + 4 * c];
+                if (odd[0]) row[1] = (float)pz[1 + 2 * b + 4 * c];
+            }
+        }
+    }
+}
+
+// --------------------------------------------------------- restriction ----
+// bc(I) = sum over fine nodes i in {2I-1, 2I, 2I+1} (per axis) of
+// w(i, I) bf(i), w = 1 at the coincident node and 1/2 at the two neighbours;
+// absent neighbours (domain edge) get weight 0.  27 loads per component are
+// issued together; FP64 accumulation.
+__global__ void __launch_bounds__(256) k_restrict(Mesh m, int ncomp, const float *__restrict__ bf,
+                                                  double *__restrict__ bc) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m.n_coarse) return;
+    uint32_t JK = fdiv((uint32_t)t, m.cx), I = (uint32_t)t - JK * m.nc[0];
+    uint32_t K = fdiv(JK, m.cy), J = JK - K * m.nc[1];
+    const int C[3] = {(int)I, (int)J, (int)K};
+    int f[3][3];
+    double w[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            int fi = 2 * C[a] + d - 1;
+            bool ok = true;
+            if (m.per[a]) fi = wrap(fi, m.nf[a], 1);
+            else if (fi < 0 || fi >= m.nf[a]) { ok = false; fi = 2 * C[a]; }
+            f[a][d] = fi;
+            w[a][d] = ok ? (d == 1 ? 1.0 : 0.5) : 0.0;
+        }
+    for (int comp = 0; comp < ncomp; ++comp) {
+        const float *b = bf + (int64_t)comp * m.n_fine;
+        float v[27];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    v[a + 3 * bb + 9 * c] =
+                        b[f[0][a] + (int64_t)m.nf[0] * (f[1][bb] + (int64_t)m.nf[1] * f[2][c])];
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int bb = 0; bb < 3; ++bb) {
+                double row = w[0][0] * v[9 * c + 3 * bb] + w[0][1] * v[1 + 9 * c + 3 * bb] +
+                             w[0][2] * v[2 + 9 * c + 3 * bb];
+                acc += w[1][bb] * w[2][c] * row;
+            }
+        bc[(int64_t)comp * m.n_coarse + t] = acc;
+    }
+}
+
+// ----------------------------------------------------------- gather Q -----
+// One thread writes 4 consecutive columns of a patch row.  Columns
+// 27 c + iota (c < 6) read field c of [u, v, w, r_u, r_v, r_w] at
+// dof(M, iota); 162..164 are the coarse cell sizes; the rest is zero padding.
+template <int DT>
+__global__ void __launch_bounds__(256)
+    k_gather(Mesh m, const float *__restrict__ x, const float *__restrict__ r,
+             const float *__restrict__ shift, const float *__restrict__ inv_scale, float qinv,
+             void *__restrict__ Xout, int64_t ldx) {
+    // block = GP patches x (ldx / 4) column quads
+    const int quads = (int)(ldx / 4);
+    const int local = threadIdx.x / quads;
+    const int64_t M = (int64_t)blockIdx.x * (blockDim.x / quads) + local;
+    if (local >= (int)(blockDim.x / quads) || M >= m.n_patches) return;
+    const int col0 = (int)(threadIdx.x - local * quads) * 4;
+    uint32_t J_K = fdiv((uint32_t)M, m.px), I = (uint32_t)M - J_K * m.n[0];
+    uint32_t K = fdiv(J_K, m.py), J = J_K - K * m.n[1];
+    float z[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        int col = col0 + q;
+        float v = 0.0f;
+        if (col < 162) {
+            int c = col / 27, iota = col - 27 * c;
+            int a = iota % 3, b = (iota / 3) % 3, cc = iota / 9;
+            int i = wrap(2 * I + a, m.nf[0], m.per[0]);
+            int j = wrap(2 * J + b, m.nf[1], m.per[1]);
+            int k = wrap(2 * K + cc, m.nf[2], m.per[2]);
+            int64_t node = i + (int64_t)m.nf[0] * (j + (int64_t)m.nf[1] * k);
+            v = c < 3 ? x[c * m.n_fine + node] : r[(c - 3) * m.n_fine + node];
+        } else if (col < 165) {
+            v = m.H[col - 162];
+        }
+        if (col < 165) {
+            if (shift) v -= shift[col];
+            if (inv_scale) v *= inv_scale[col];
+        }
+        z[q] = v;
+    }
+    if (DT == DNNMG_F32) {
+        float4 o = make_float4(z[0], z[1], z[2], z[3]);
+        *(float4 *)((float *)Xout + M * ldx + col0) = o;
+    } else if (DT == DNNMG_BF16) {
+        uint2 o;
+        o.x = pack_bf16x2(z[0], z[1]);
+        o.y = pack_bf16x2(z[2], z[3]);
+        *(uint2 *)((uint16_t *)Xout + M * ldx + col0) = o;
+    } else {
+        uint32_t o = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) o |= (uint32_t)f32_to_e4m3(z[q] * qinv) << (8 * q);
+        *(uint32_t *)((uint8_t *)Xout + M * ldx + col0) = o;
+    }
+}
+
+// ----------------------------------------------------- extension L --------
+// Per fine node: the patches holding it along each axis (ascending patch
+// index, at most two) and the node's local coordinate in each; the mean of
+// the network outputs over these patches.  The 2x2x2 candidate set is fixed
+// (absent candidates carry weight 0) so all loads are issued at once.
+struct Hold1 {
+    int P[2];
+    int loc[2];
+    float w[2];
+    int cnt;
+};
+
+__device__ __forceinline__ Hold1 holders(int i, int n, int per) {
+    Hold1 h;
+    if (i & 1) {
+        h.P[0] = h.P[1] = (i - 1) >> 1;
+        h.loc[0] = h.loc[1] = 1;
+        h.w[0] = 1.f;
+        h.w[1] = 0.f;
+        h.cnt = 1;
+        return h;
+    }
+    int hi = i >> 1;   // patch starting here (local 0)
+    int lo = hi - 1;   // patch ending here (local 2)
+    if (per) {
+        if (lo < 0) lo += n;
+        bool lo_first = lo < hi; // ascending patch order
+        h.P[0] = lo_first ? lo : hi;
+        h.loc[0] = lo_first ? 2 : 0;
+        h.P[1] = lo_first ? hi : lo;
+        h.loc[1] = lo_first ? 0 : 2;
+        h.w[0] = h.w[1] = 1.f;
+        h.cnt = 2;
+        return h;
+    }
+    bool has_lo = lo >= 0, has_hi = hi < n;
+    h.P[0] = has_lo ? lo : hi;
+    h.loc[0] = has_lo ? 2 : 0;
+    h.P[1] = has_hi ? hi : h.P[0];
+    h.loc[1] = has_hi ? 0 : h.loc[0];
+    h.w[0] = 1.f;
+    h.w[1] = (has_lo && has_hi) ? 1.f : 0.f;
+    h.cnt = (int)has_lo + (int)has_hi;
+    return h;
+}
+
+__global__ void __launch_bounds__(256) k_scatter(Mesh m, const float *__restrict__ Y,
+                                                 const float *__restrict__ vbase,
+                                                 float *__restrict__ d) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m.n_fine) return;
+    uint32_t jk = fdiv((uint32_t)t, m.fx), i = (uint32_t)t - jk * m.nf[0];
+    uint32_t k = fdiv(jk, m.fy), j = jk - k * m.nf[1];
+    float acc[3] = {0.0f, 0.0f, 0.0f};
+    const bool dir = on_dirichlet(m, i, j, k);
+    Hold1 hx = holders(i, m.n[0], m.per[0]);
+    Hold1 hy = holders(j, m.n[1], m.per[1]);
+    Hold1 hz = holders(k, m.n[2], m.per[2]);
+    float y[8][3], wgt[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        int a = q & 1, b = (q >> 1) & 1, c = q >> 2;
+        int64_t M = hx.P[a] + (int64_t)m.n[0] * (hy.P[b] + (int64_t)m.n[1] * hz.P[c]);
+        int iota = hx.loc[a] + 3 * hy.loc[b] + 9 * hz.loc[c];
+        const float *src = Y + M * 81 + iota;
+        y[q][0] = src[0];
+        y[q][1] = src[27];
+        y[q][2] = src[54];
+        wgt[q] = hx.w[a] * hy.w[b] * hz.w[c];
+    }
+    // sum in ascending patch order (z, then y, then x of the candidates)
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) acc[cc] = fmaf(wgt[q], y[q][cc], acc[cc]);
+    const float inv = 1.0f / (float)(hx.cnt * hy.cnt * hz.cnt); // power of two: exact
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        float v = dir ? 0.0f : acc[c] * inv;
+        if (vbase) v += vbase[c * m.n_fine + t];
+        d[c * m.n_fine + t] = v;
+    }
+    // the network predicts no pressure correction: the corrected iterate
+    // keeps the prolongated pressure
+    if (vbase) d[3 * m.n_fine + t] = vbase[3 * m.n_fine + t];
+}
+
+// -------------------------------------------------------------- norms -----
+constexpr int NORM_BLOCKS = 1024;
+
+__global__ void __launch_bounds__(256) k_norm_partial(int64_t n, const float *__restrict__ a,
+                                                      const float *__restrict__ b,
+                                                      double *__restrict__ part) {
+    double s = 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        double e = (double)a[t] - (b ? (double)b[t] : 0.0);
+        s += e * e;
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) k_norm_final(int nparts, const double *__restrict__ part,
+                                                    double *__restrict__ out) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int t = threadIdx.x; t < nparts; t += 256) s += part[t];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+} // namespace dnnmg
+
+using namespace dnnmg;
+
+#define STREAM ((hipStream_t)stream)
+
+extern "C" int dnnmg_patch_dofmap(const dnnmg_box *box, int32_t *map, uint8_t *mult, void *stream) {
+    Mesh m;
+    int rc = make_mesh(box, &m);
+    if (rc) return rc;
+    if (!map && !mult) return fail(DNNMG_ERR_ARG, "dnnmg_patch_dofmap: map and mult are both NULL");
+    if (map) k_dofmap<<<blocks_for(m.n_patches * 27, 256), 256, 0, STREAM>>>(m, map);
+    if (mult) k_mult<<<blocks_for(m.n_fine, 256), 256, 0, STREAM>>>(m, mult);
+    return hip_check(hipGetLastError(), "dnnmg_patch_dofmap launch");
+}
+
+extern "C" int dnnmg_prolong(const dnnmg_box *box, int ncomp, const double *xc, float *xf,
+                             void *stream) {
+    Mesh m;
+    int rc = make_mesh(box, &m);
+    if (rc) return rc;
+    if (ncomp < 1 || ncomp > 4) return fail(DNNMG_ERR_ARG, "dnnmg_prolong: ncomp %d not in 1..4", ncomp);
+    if (!xc || !xf) return fail(DNNMG_ERR_ARG, "dnnmg_prolong: NULL pointer");
+    k_prolong<<<blocks_for(m.n_coarse, 256), 256, 0, STREAM>>>(m, ncomp, xc, xf);
+    return hip_check(hipGetLastError(), "dnnmg_prolong launch");
+}
+
+extern "C" int dnnmg_restrict(const dnnmg_box *box, int ncomp, const float *bf, double *bc,
+                              void *stream) {
+    Mesh m;
+    int rc = make_mesh(box, &m);
+    if (rc) return rc;
+    if (ncomp < 1 || ncomp > 4) return fail(DNNMG_ERR_ARG, "dnnmg_restrict: ncomp %d not in 1..4", ncomp);
+    if (!bf || !bc) return fail(DNNMG_ERR_ARG, "dnnmg_restrict: NULL pointer");
+    k_restrict<<<blocks_for(m.n_coarse, 256), 256, 0, STREAM>>>(m, ncomp, bf, bc);
+    return hip_check(hipGetLastError(), "dnnmg_restrict launch");
+}
+
+extern "C" int dnnmg_patch_gather(const dnnmg_box *box, const float *x, const float *r,
+                                  const dnnmg_feat *feat, int dtype, float x_scale, void *X,
+                                  int64_t ldx, void *stream) {
+    Mesh m;
+    int rc = make_mesh(box, &m);
+    if (rc) return rc;
+    if (!x || !r || !X) return fail(DNNMG_ERR_ARG, "dnnmg_patch_gather: NULL pointer");
+    if (!aligned16(X)) return fail(DNNMG_ERR_ARG, "dnnmg_patch_gather: X not 16-byte aligned");
+    int align = dtype == DNNMG_F32 ? 4 : dtype == DNNMG_BF16 ? 8 : 16;
+    if (ldx < 165 || ldx % align)
+        return fail(DNNMG_ERR_SHAPE, "dnnmg_patch_gather: ldx %lld must be >= 165 and a multiple of %d",
+                    (long long)ldx, align);
+    const float *sh = feat ? feat->shift : nullptr;
+    const float *sc = feat ? feat->inv_scale : nullptr;
+    if (ldx / 4 > 256) return fail(DNNMG_ERR_SHAPE, "dnnmg_patch_gather: ldx %lld > 1024", (long long)ldx);
+    int per_block = (int)(256 / (ldx / 4));
+    unsigned g = blocks_for(m.n_patches, per_block);
+    if (dtype == DNNMG_F32)
+        k_gather<DNNMG_F32><<<g, 256, 0, STREAM>>>(m, x, r, sh, sc, 1.0f, X, ldx);
+    else if (dtype == DNNMG_BF16)
+        k_gather<DNNMG_BF16><<<g, 256, 0, STREAM>>>(m, x, r, sh, sc, 1.0f, X, ldx);
+    else if (dtype == DNNMG_FP8_E4M3) {
+        if (!(x_scale > 0.0f)) return fail(DNNMG_ERR_ARG, "dnnmg_patch_gather: x_scale must be > 0 for FP8");
+        k_gather<DNNMG_FP8_E4M3><<<g, 256, 0, STREAM>>>(m, x, r, sh, sc, 1.0f / x_scale, X, ldx);
+    } else
+        return fail(DNNMG_ERR_UNSUPPORTED, "dnnmg_patch_gather: dtype %d", dtype);
+    return hip_check(hipGetLastError(), "dnnmg_patch_gather launch");
+}
+
+extern "C" int dnnmg_scatter_avg(const dnnmg_box *box, const float *Y, const float *vbase, float *d,
+                                 void *stream) {
+    Mesh m;
+    int rc = make_mesh(box, &m);
+    if (rc) return rc;
+    if (!Y || !d) return fail(DNNMG_ERR_ARG, "dnnmg_scatter_avg: NULL pointer");
+    k_scatter<<<blocks_for(m.n_fine, 256), 256, 0, STREAM>>>(m, Y, vbase, d);
+    return hip_check(hipGetLastError(), "dnnmg_scatter_avg launch");
+}
+
+extern "C" size_t dnnmg_norm2_workspace(void) { return NORM_BLOCKS * sizeof(double); }
+
+extern "C" int dnnmg_norm2_f64(int64_t n, const float *a, const float *b, double *out, void *ws,
+                               size_t ws_bytes, void *stream) {
+    if (n < 0) return fail(DNNMG_ERR_SHAPE, "dnnmg_norm2_f64: n < 0");
+    if (!a || !out || !ws) return fail(DNNMG_ERR_ARG, "dnnmg_norm2_f64: NULL pointer");
+    if (ws_bytes < dnnmg_norm2_workspace())
+        return fail(DNNMG_ERR_SHAPE, "dnnmg_norm2_f64: workspace %zu < %zu bytes", ws_bytes,
+                    dnnmg_norm2_workspace());
+    k_norm_partial<<<NORM_BLOCKS, 256, 0, STREAM>>>(n, a, b, (double *)ws);
+    k_norm_final<<<1, 256, 0, STREAM>>>(NORM_BLOCKS, (const double *)ws, out);
+    return hip_check(hipGetLastError(), "dnnmg_norm2_f64 launch");
+}

@@ -1,0 +1,67 @@
+"""Algorithmic work per unit of the hot-path kernels (used for roofline figures).
+
+Flops count FP32 (or FP64) arithmetic as issued by the algorithm as written
+in the kernels: add/sub/mul/max = 1, fused multiply-add = 2, sqrt/div = 1.
+Halo recomputation, padding and inactive lanes are not counted.
+Bytes count each input array read once and each output written once.
+"""
+
+# ---- building blocks of the sum-factorised 2x2x2 Gauss quadrature ----------
+LIN2 = 5                 # two Gauss-point values of a linear function: sub + 2 fma
+EVAL_VAL = 12 * LIN2     # values at 8 Gauss points: 3 passes x 4 lines
+EVAL_VG = 24 + 34 + 40 + 16  # values + 3 gradient components (x, y, z passes, 1/h scaling)
+INTEGRATE = 76 + 56 + 36     # transpose to 8 vertex integrals of (F, Gx, Gy, Gz)
+INTEGRATE_FLUX = 52 + 56 + 36  # transpose of (Gx, Gy, Gz) only
+PI_VERTICES = 24         # patch-corner values -> the fine cell's vertex values
+PI_TRANSPOSE = 36        # vertex integrals -> patch-corner integrals
+
+
+def residual_flops_per_cell(lps: bool = True) -> int:
+    """Crank-Nicolson residual r = F - A(x) per fine cell (Q1, 2x2x2 Gauss)."""
+    stab = 47 + 9                                  # |v|_inf over vertices, alpha_T, delta_T
+    values = 3 * EVAL_VAL + 3 * EVAL_VAL + EVAL_VAL  # x~, vp, p~ at Gauss points
+    per_comp = (16                                  # vp - x~, vp + x~ at vertices
+                + EVAL_VG + EVAL_VAL                # grad(vp + x~)_a, (vp - x~)_a
+                + 8 + 24 + 8                        # 1/k, -nu/2, pressure term
+                + EVAL_VG + 56                      # -1/2 vp . grad vp_a
+                + EVAL_VG + 56 + 8                  # -1/2 x~ . grad x~_a, divergence
+                + INTEGRATE)                        # vertex integrals
+    cont = EVAL_VG + 56 + INTEGRATE                    # grad p~, -div x~ (8 pts)
+    if lps:
+        values += 3 * PI_VERTICES + 3 * EVAL_VAL          # pi x~
+        per_comp += EVAL_VG + 128 + INTEGRATE_FLUX + PI_TRANSPOSE  # delta term, own + corners
+        cont += PI_VERTICES + EVAL_VG + INTEGRATE_FLUX + 8 + PI_TRANSPOSE  # alpha term
+    scale_and_sum = 64 + 64 + 4                      # quadrature weight, LDS sums, corner adds
+    return stab + values + 3 * per_comp + cont + scale_and_sum
+
+
+def rhs_flops_per_cell() -> int:
+    """Right-hand side b = Rhs(v) per fine cell."""
+    per_comp = EVAL_VG + 8 + 24 + 7 * 8 + INTEGRATE
+    return 3 * EVAL_VAL + 3 * per_comp + 24 + 24
+
+
+def mlp_flops_per_patch(hidden: int, n_in: int = 165, n_out: int = 81) -> int:
+    """Useful multiply-add flops of the 165-H-H-81 network per patch."""
+    return 2 * (n_in * hidden + hidden * hidden + hidden * n_out)
+
+
+def mlp_issued_flops_per_patch(hidden: int) -> int:
+    """Flops issued on the padded MFMA shapes (K 165 -> 192, N 81 -> 96)."""
+    return 2 * (192 * hidden + hidden * hidden + hidden * 96)
+
+
+# ---- bytes per fine node (FP32 fields, each read or written once) ----------
+BYTES_PER_FINE_NODE = {
+    "prolong": 4 * 4 + 4 * 8 / 8,        # write 4 FP32 fields; read 4 FP64 coarse fields (1/8 node)
+    "residual": 4 * 4 + 3 * 4 + 4 * 4,   # read x (4), vp (3); write r (4)
+    "rhs": 3 * 4 + 4 * 4,                # read v (3); write b (4)
+    "scatter": 81 * 4 / 8 + 4 * 4 + 4 * 4,  # read Y (81 per patch), x~ (4); write x_corr (4)
+    "restrict": 4 * 4 + 4 * 8 / 8,       # read b (4); write 4 FP64 coarse fields
+}
+
+
+def gather_bytes_per_patch(x_bytes: int, ldx: int = 192) -> float:
+    """Read 6 fine fields at the patch's nodes (about 8 fine nodes own one patch),
+    write one padded row of the network input."""
+    return 8 * 6 * 4 + ldx * x_bytes

@@ -1,0 +1,139 @@
+"""One DNN-MG correction step on the GPU (arXiv 2307.14837, Algorithm 1 after
+the coarse solve): prolongate -> fine residual -> gather Q -> patch network ->
+extension L (plus v~) -> right-hand side -> restriction, optionally followed
+by the residual indicator (residual of the corrected state and two FP64
+norms).  Every arithmetic step runs in libdnnmg's HIP kernels; this module
+only owns device buffers (torch allocations), packs the network once and can
+capture the whole step in a HIP graph.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+DTYPES = {"fp32": L.F32, "bf16": L.BF16, "fp8": L.FP8_E4M3}
+_TORCH = {L.F32: torch.float32, L.BF16: torch.bfloat16, L.FP8_E4M3: torch.uint8}
+LDX = L.IN_PAD  # 192: K padded for the MFMA granule
+TANH_SCALE = 1.0 / 448.0  # FP8 scale of the tanh outputs (|tanh| < 1 maps inside +-448)
+
+
+class CorrectionStep:
+    """Buffers and launch sequence of one correction step for one box.
+
+    params: [W1, b1, W2, b2, W3, b3] (numpy or torch, W as [fan_in][fan_out]).
+    shift / inv_scale: per-feature standardisation of the 165 inputs (None =
+    identity).  FP8 networks quantise W2 with amax / 448 and the tanh outputs
+    entering layer 2 with the fixed scale 1 / 448.
+    """
+
+    def __init__(self, box, ns, params, dtype="bf16", device="cuda:0", shift=None, inv_scale=None,
+                 indicator=False):
+        self.box = L.Box.of(box)
+        self.ns = L.NS.of(ns)
+        self.dev = torch.device(device)
+        self.dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+        self.nf, self.nc, self.np = L.box_sizes(self.box)
+        self.hidden = int(np.shape(params[0])[1])
+        self.indicator = indicator
+        f32 = dict(dtype=torch.float32, device=self.dev)
+        f64 = dict(dtype=torch.float64, device=self.dev)
+        self.xc = torch.zeros(4 * self.nc, **f64)
+        self.xt = torch.zeros(4 * self.nf, **f32)       # prolongated (u, v, w, p)
+        self.vprev = torch.zeros(3 * self.nf, **f32)
+        self.r = torch.zeros(4 * self.nf, **f32)
+        self.ws_res = torch.zeros(L.residual_workspace_bytes(self.box), dtype=torch.uint8, device=self.dev)
+        # FP8 networks take BF16 inputs (their first layer is BF16)
+        self.xdtype = L.F32 if self.dtype == L.F32 else L.BF16
+        self.X = torch.zeros(self.np * LDX, dtype=_TORCH[self.xdtype], device=self.dev)
+        self.Y = torch.zeros(self.np * L.N_OUT, **f32)
+        self.xcorr = torch.zeros(4 * self.nf, **f32)    # (v~ + d, p~)
+        self.b = torch.zeros(4 * self.nf, **f32)
+        self.bc = torch.zeros(4 * self.nc, **f64)
+        if indicator:
+            self.r2 = torch.zeros(4 * self.nf, **f32)
+            self.norms = torch.zeros(2, **f64)
+            self.ws_norm = torch.zeros(L.norm2_workspace_bytes(), dtype=torch.uint8, device=self.dev)
+        self.shift = None if shift is None else torch.as_tensor(np.asarray(shift, np.float32)).to(self.dev)
+        self.inv_scale = None if inv_scale is None else torch.as_tensor(np.asarray(inv_scale, np.float32)).to(self.dev)
+        self.set_params(params)
+        self.graph = None
+
+    # ------------------------------------------------------------- network --
+    def set_params(self, params):
+        H = self.hidden
+        self.W32 = [torch.as_tensor(np.asarray(params[2 * l], np.float32)).contiguous().to(self.dev) for l in range(3)]
+        self.bias = [torch.as_tensor(np.asarray(params[2 * l + 1], np.float32)).contiguous().to(self.dev) for l in range(3)]
+        self.w_scale = [1.0, 1.0, 1.0]
+        if self.dtype == L.FP8_E4M3:
+            self.w_scale = [1.0, max(float(self.W32[1].abs().max().item()), 1e-30) / 448.0, 1.0]
+        self.Wp = []
+        for l in range(3):
+            buf = torch.zeros(L.packed_bytes(self.dtype, H, l), dtype=torch.uint8, device=self.dev)
+            L.dnnmg_mlp_pack(self.dtype, H, l, self.W32[l], buf, w_scale=self.w_scale[l])
+            self.Wp.append(buf)
+        self._make_net()
+
+    def _make_net(self):
+        a = [1.0, TANH_SCALE, 1.0] if self.dtype == L.FP8_E4M3 else [1.0, 1.0, 1.0]
+        self.net = L.make_mlp(self.dtype, self.hidden, self.Wp, self.bias, self.w_scale, a)
+
+    # ---------------------------------------------------------------- step --
+    def load(self, xc, vprev):
+        self.xc.copy_(torch.as_tensor(np.asarray(xc, np.float64).ravel()))
+        self.vprev.copy_(torch.as_tensor(np.asarray(vprev, np.float32).ravel()))
+
+    def step(self, stream=None):
+        box, ns = self.box, self.ns
+        L.dnnmg_prolong(box, self.xc, self.xt, stream=stream)
+        L.dnnmg_residual(box, ns, self.xt, self.vprev, self.r, self.ws_res, stream=stream)
+        L.dnnmg_patch_gather(box, self.xt, self.r, self.X, self.xdtype, LDX, self.shift, self.inv_scale,
+                             stream=stream)
+        L.dnnmg_patch_forward(self.net, self.np, self.X, LDX, self.Y, stream=stream)
+        # corrected iterate (v~ + d, p~)
+        L.dnnmg_scatter_avg(box, self.Y, self.xcorr, vbase=self.xt, stream=stream)
+        L.dnnmg_rhs(box, ns, self.xcorr, self.b, stream=stream)
+        L.dnnmg_restrict(box, self.b, self.bc, stream=stream)
+        if self.indicator:
+            L.dnnmg_residual(box, ns, self.xcorr, self.vprev, self.r2, self.ws_res, stream=stream)
+            L.dnnmg_norm2_f64(self.r, self.norms[0:1], self.ws_norm, stream=stream)
+            L.dnnmg_norm2_f64(self.r2, self.norms[1:2], self.ws_norm, stream=stream)
+
+    def capture(self):
+        """Capture step() into a HIP graph (torch.cuda.CUDAGraph wraps hipGraph)."""
+        s = torch.cuda.Stream(device=self.dev)
+        s.wait_stream(torch.cuda.current_stream(self.dev))
+        with torch.cuda.stream(s):
+            self.step()  # warm-up outside the graph
+        torch.cuda.current_stream(self.dev).wait_stream(s)
+        torch.cuda.synchronize(self.dev)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.step()
+        self.graph = g
+        return g
+
+    def replay(self):
+        self.graph.replay()
+
+    def run_numpy(self, xc, vprev):
+        self.load(xc, vprev)
+        self.step()
+        torch.cuda.synchronize(self.dev)
+        xt = self.xt.cpu().numpy().reshape(4, -1).astype(np.float64)
+        xcorr = self.xcorr.cpu().numpy().reshape(4, -1).astype(np.float64)
+        out = {
+            "xt": xt,
+            "r": self.r.cpu().numpy().reshape(4, -1).astype(np.float64),
+            "Y": self.Y.cpu().numpy().reshape(-1, 81).astype(np.float64),
+            "vcorr": xcorr[:3],
+            "d": xcorr[:3] - xt[:3],
+            "b": self.b.cpu().numpy().reshape(4, -1).astype(np.float64),
+            "bc": self.bc.cpu().numpy().reshape(4, -1),
+            "vprev32": self.vprev.cpu().numpy().reshape(3, -1).astype(np.float64),
+        }
+        if self.indicator:
+            n = self.norms.cpu().numpy()
+            out["eta"] = float(np.sqrt(n[1] / n[0])) if n[0] > 0 else float("inf")
+        return out

@@ -1,0 +1,326 @@
+"""GPU parity: every HIP kernel against the FP64 oracle on the same seeded inputs.
+
+Bars: index maps and valences bit-exact; FP32 prolongation, residual, rhs,
+gather, scatter within rel-L2 1e-5 (FP64 restriction 1e-12); network outputs
+within rel-L2 1e-5 (FP32), 2e-2 (BF16), 5e-2 (FP8) of the FP64 oracle, plus
+tighter checks against the oracle run on the same rounded operands.
+"""
+import numpy as np
+import pytest
+import torch
+
+import dnnmg_synth as syn
+from gpu_util import dev, f32, rel_l2, say, to_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_2307_14837_amd as L
+
+    assert torch.cuda.is_available()
+    return L
+
+
+BOXES = {
+    "cfg1": syn.cfg1().box,
+    "chan_small": syn.channel_box((4, 2, 2)),
+    "chan_mid": syn.channel_box((12, 5, 3)),
+    "per_uneven": syn.BoxSpec((6, 4, 2), (1.0, 0.7, 0.4), 7, 0),
+    "mixed": syn.BoxSpec((10, 6, 4), (1.2, 0.8, 0.5), 1, syn.Y_LO | syn.Y_HI | syn.Z_HI),
+    "cfg2": syn.cfg2().box,
+}
+
+
+def fields(box, seed, prolongated=True, orc=None):
+    """x (4 x N_f, FP32-representable), vp (3 x N_f)."""
+    rng = np.random.default_rng(seed)
+    if prolongated:
+        xc = rng.standard_normal((4, box.n_coarse))
+        x = orc.prolong(box, xc)
+    else:
+        x = rng.standard_normal((4, box.n_fine))
+    vp = x[:3] + 0.3 * rng.standard_normal((3, box.n_fine))
+    return f32(x), f32(vp)
+
+
+@pytest.mark.parametrize("name", list(BOXES))
+def test_dofmap_bit_exact(L, orc, name):
+    box = BOXES[name]
+    say("dofmap", name)
+    m_ref, mult_ref = orc.dofmap(box)
+    nf, nc, npch = L.box_sizes(box)
+    assert (nf, nc, npch) == (box.n_fine, box.n_coarse, box.n_patches)
+    m = torch.empty(npch * 27, dtype=torch.int32, device=dev())
+    mult = torch.empty(nf, dtype=torch.uint8, device=dev())
+    L.dnnmg_patch_dofmap(box, m, mult)
+    torch.cuda.synchronize()
+    assert np.array_equal(m.cpu().numpy().reshape(-1, 27), m_ref)
+    assert np.array_equal(mult.cpu().numpy(), mult_ref)
+
+
+@pytest.mark.parametrize("name", list(BOXES))
+def test_prolong_restrict(L, orc, name):
+    box = BOXES[name]
+    say("prolong/restrict", name)
+    rng = np.random.default_rng(1)
+    xc = rng.standard_normal((4, box.n_coarse))
+    xf = torch.empty(4 * box.n_fine, dtype=torch.float32, device=dev())
+    L.dnnmg_prolong(box, to_gpu(xc), xf)
+    ref = orc.prolong(box, xc)
+    got = xf.cpu().numpy().reshape(4, -1)
+    assert rel_l2(got, ref) <= 1e-7
+    assert np.max(np.abs(got - ref)) <= 2 ** -23 * np.max(np.abs(ref)) * 2
+    # restriction of an FP32 fine vector in FP64
+    bf = f32(rng.standard_normal((4, box.n_fine)))
+    bc = torch.empty(4 * box.n_coarse, dtype=torch.float64, device=dev())
+    L.dnnmg_restrict(box, to_gpu(bf), bc)
+    ref = orc.restrict(box, bf.astype(np.float64))
+    assert rel_l2(bc.cpu().numpy().reshape(4, -1), ref) <= 1e-13
+
+
+def run_residual(L, box, ns, x, vp, fmid=None):
+    nf = box.n_fine
+    r = torch.empty(4 * nf, dtype=torch.float32, device=dev())
+    ws = torch.empty(L.residual_workspace_bytes(box), dtype=torch.uint8, device=dev())
+    L.dnnmg_residual(box, ns, to_gpu(x.ravel()), to_gpu(vp.ravel()), r, ws,
+                     fmid=None if fmid is None else to_gpu(fmid.ravel()))
+    return r.cpu().numpy().reshape(4, nf)
+
+
+@pytest.mark.parametrize("name", list(BOXES))
+@pytest.mark.parametrize("prolongated", [True, False])
+def test_residual(L, orc, name, prolongated):
+    box = BOXES[name]
+    say("residual", name, "prolongated" if prolongated else "general")
+    ns = syn.NSParams(1e-3, 0.01) if name != "cfg2" else syn.cfg2().ns
+    x, vp = fields(box, 3, prolongated, orc)
+    got = run_residual(L, box, ns, x, vp)
+    ref = orc.residual(box, ns, x.astype(np.float64), vp.astype(np.float64))
+    err = rel_l2(got, ref)
+    say("  rel-L2", err)
+    assert err <= 1e-5
+    # per-field check so a small field cannot hide behind a large one
+    for f in range(4):
+        assert rel_l2(got[f], ref[f]) <= 1e-5, f
+
+
+def test_residual_forcing_and_lps_weights(L, orc):
+    box = BOXES["mixed"]
+    say("residual forcing + strong LPS")
+    ns = syn.NSParams(0.05, 0.02, 0.5, 0.8)
+    x, vp = fields(box, 4, False, orc)
+    fm = f32(np.random.default_rng(5).standard_normal((3, box.n_fine)))
+    got = run_residual(L, box, ns, x, vp, fm)
+    ref = orc.residual(box, ns, x.astype(np.float64), vp.astype(np.float64), fm.astype(np.float64))
+    assert rel_l2(got, ref) <= 1e-5
+
+
+@pytest.mark.parametrize("name", list(BOXES))
+def test_rhs(L, orc, name):
+    box = BOXES[name]
+    say("rhs", name)
+    ns = syn.NSParams(1e-3, 0.01)
+    rng = np.random.default_rng(6)
+    v = f32(rng.standard_normal((3, box.n_fine)))
+    fm = f32(rng.standard_normal((3, box.n_fine)))
+    for forcing in (None, fm):
+        b = torch.empty(4 * box.n_fine, dtype=torch.float32, device=dev())
+        L.dnnmg_rhs(box, ns, to_gpu(v.ravel()), b, fmid=None if forcing is None else to_gpu(forcing.ravel()))
+        ref = orc.rhs(box, ns, v.astype(np.float64), None if forcing is None else forcing.astype(np.float64))
+        got = b.cpu().numpy().reshape(4, -1)
+        assert rel_l2(got, ref) <= 1e-5
+        assert np.all(got[3] == 0)
+
+
+@pytest.mark.parametrize("name", ["cfg1", "chan_small", "per_uneven", "cfg2"])
+def test_gather_scatter(L, orc, name):
+    box = BOXES[name]
+    say("gather/scatter", name)
+    rng = np.random.default_rng(7)
+    x = f32(rng.standard_normal((4, box.n_fine)))
+    r = f32(rng.standard_normal((4, box.n_fine)) * 1e-3)
+    shift = f32(rng.standard_normal(165) * 0.1)
+    inv = f32(rng.uniform(0.5, 2.0, 165))
+    ref = orc.gather(box, x.astype(np.float64), r.astype(np.float64), shift.astype(np.float64),
+                     inv.astype(np.float64))
+    npch = box.n_patches
+    ldx = 192
+    X = torch.empty(npch * ldx, dtype=torch.float32, device=dev())
+    L.dnnmg_patch_gather(box, to_gpu(x.ravel()), to_gpu(r.ravel()), X, L.F32, ldx,
+                         shift=to_gpu(shift), inv_scale=to_gpu(inv))
+    got = X.cpu().numpy().reshape(npch, ldx)
+    assert np.all(got[:, 165:] == 0)
+    np.testing.assert_allclose(got[:, :165], ref, rtol=2e-7, atol=1e-7)
+    # bf16: within one bf16 rounding of the exact value
+    Xb = torch.empty(npch * ldx, dtype=torch.bfloat16, device=dev())
+    L.dnnmg_patch_gather(box, to_gpu(x.ravel()), to_gpu(r.ravel()), Xb, L.BF16, ldx,
+                         shift=to_gpu(shift), inv_scale=to_gpu(inv))
+    gb = Xb.float().cpu().numpy().reshape(npch, ldx)[:, :165]
+    assert np.all(np.abs(gb - ref) <= 1.01 * 2.0 ** -8 * np.abs(ref) + 1e-30)
+    # fp8 codes: within one e4m3 step of round(z / scale)
+    scale = float(np.abs(ref).max() / 448.0)
+    X8 = torch.empty(npch * ldx, dtype=torch.uint8, device=dev())
+    L.dnnmg_patch_gather(box, to_gpu(x.ravel()), to_gpu(r.ravel()), X8, L.FP8_E4M3, ldx,
+                         shift=to_gpu(shift), inv_scale=to_gpu(inv), x_scale=scale)
+    g8 = X8.cpu().view(torch.float8_e4m3fn).float().numpy().reshape(npch, ldx)[:, :165]
+    exact = orc.round_e4m3(ref / scale)
+    close = np.abs(g8 - exact) <= 2.0 ** -3 * np.abs(exact) + 2.0 ** -9
+    assert close.all()
+    assert np.mean(g8 == exact) > 0.99
+    # scatter of network-like outputs
+    Y = f32(rng.standard_normal((npch, 81)))
+    d = torch.empty(3 * box.n_fine, dtype=torch.float32, device=dev())
+    L.dnnmg_scatter_avg(box, to_gpu(Y.ravel()), d)
+    dref = orc.scatter(box, Y.astype(np.float64))
+    assert rel_l2(d.cpu().numpy().reshape(3, -1), dref) <= 1e-6
+    # with the base iterate added: (v~ + L(Y), p~)
+    d4 = torch.empty(4 * box.n_fine, dtype=torch.float32, device=dev())
+    L.dnnmg_scatter_avg(box, to_gpu(Y.ravel()), d4, vbase=to_gpu(x.ravel()))
+    g4 = d4.cpu().numpy().reshape(4, -1)
+    assert rel_l2(g4[:3], dref + x[:3]) <= 1e-6
+    assert np.array_equal(g4[3], x[3])
+
+
+def pack_net(L, dtype, params, w_scale=(1.0, 1.0, 1.0)):
+    H = params[0].shape[1]
+    Wp, bias = [], []
+    for l in range(3):
+        W = to_gpu(f32(params[2 * l]))
+        buf = torch.empty(L.packed_bytes(dtype, H, l), dtype=torch.uint8, device=dev())
+        L.dnnmg_mlp_pack(dtype, H, l, W, buf, w_scale=w_scale[l])
+        Wp.append(buf)
+        bias.append(to_gpu(f32(params[2 * l + 1])))
+    return Wp, bias
+
+
+def run_forward(L, dtype, params, Xq, ldx, a_scale=(1.0, 1.0, 1.0), w_scale=(1.0, 1.0, 1.0), saved=False):
+    H = params[0].shape[1]
+    n = Xq.shape[0] // ldx if Xq.dim() == 1 else Xq.shape[0]
+    Wp, bias = pack_net(L, dtype, params, w_scale)
+    net = L.make_mlp(dtype, H, Wp, bias, w_scale, a_scale)
+    Y = torch.empty(max(n, 1) * 81, dtype=torch.float32, device=dev())
+    sv = None
+    if saved:
+        sv = torch.empty(L.saved_bytes(net, n), dtype=torch.uint8, device=dev())
+    L.dnnmg_patch_forward(net, n, Xq, ldx, Y, saved=sv)
+    torch.cuda.synchronize()
+    return Y.cpu().numpy()[: n * 81].reshape(n, 81), sv
+
+
+def padded(X, ldx):
+    out = np.zeros((X.shape[0], ldx), dtype=np.float32)
+    out[:, : X.shape[1]] = X
+    return out
+
+
+@pytest.mark.parametrize("n", [1, 33, 64, 1000, 4099])
+def test_mlp_fp32(L, orc, n):
+    say("mlp fp32 n", n)
+    params = syn.mlp_params(165, 128, 81, seed=1, bias_scale=0.1)
+    X = f32(np.random.default_rng(2).standard_normal((n, 165)))
+    Y, _ = run_forward(L, L.F32, params, to_gpu(padded(X, 192).ravel()), 192)
+    p32 = [f32(p).astype(np.float64) for p in params]
+    ref = orc.mlp_forward(X.astype(np.float64), *p32)
+    assert rel_l2(Y, ref) <= 1e-5
+
+
+def emulate_lowp(orc, X, params, rnd, scales=None):
+    """Oracle network on rounded operands: inputs, weights and the hidden
+    activations rounded by `rnd` (the same formats the GPU stores)."""
+    W1, b1, W2, b2, W3, b3 = [f32(p).astype(np.float64) for p in params]
+    if scales is None:
+        r = rnd
+        a1 = r(np.tanh(r(X) @ r(W1) + b1))
+        a2 = r(np.tanh(a1 @ r(W2) + b2))
+        return a2 @ r(W3) + b3
+    ws, as_ = scales
+    q = lambda v, s: rnd(v / s) * s
+    a1 = q(np.tanh(q(X, as_[0]) @ q(W1, ws[0]) + b1), as_[1])
+    a2 = q(np.tanh(a1 @ q(W2, ws[1]) + b2), as_[2])
+    return a2 @ q(W3, ws[2]) + b3
+
+
+@pytest.mark.parametrize("H", [128, 256, 512])
+@pytest.mark.parametrize("n", [17, 2048, 5003])
+def test_mlp_bf16(L, orc, H, n):
+    say("mlp bf16 H", H, "n", n)
+    params = syn.mlp_params(165, H, 81, seed=3, bias_scale=0.1)
+    X = f32(np.random.default_rng(4).standard_normal((n, 165)))
+    Xb = to_gpu(padded(X, 192)).to(torch.bfloat16).contiguous().view(-1)
+    Y, _ = run_forward(L, L.BF16, params, Xb, 192)
+    ref = orc.mlp_forward(X.astype(np.float64), *[f32(p).astype(np.float64) for p in params])
+    err = rel_l2(Y, ref)
+    say("  rel-L2 vs fp64", err)
+    assert err <= 2e-2
+    emu = emulate_lowp(orc, X.astype(np.float64), params, orc.round_bf16)
+    assert rel_l2(Y, emu) <= 2e-3
+
+
+@pytest.mark.parametrize("H", [128, 256, 512])
+@pytest.mark.parametrize("n", [77, 3001])
+def test_mlp_fp8(L, orc, H, n):
+    """FP8 network: BF16 first and last layers, E4M3 hidden product (K = 128 MFMA)."""
+    say("mlp fp8 H", H, "n", n)
+    params = syn.mlp_params(165, H, 81, seed=5, bias_scale=0.1)
+    X = f32(np.random.default_rng(6).standard_normal((n, 165)))
+    w2s = float(np.abs(f32(params[2])).max() / 448.0)
+    ws = [1.0, w2s, 1.0]
+    as_ = [1.0, 1.0 / 448.0, 1.0]
+    Xb = to_gpu(padded(X, 192)).to(torch.bfloat16).contiguous().view(-1)
+    Y, _ = run_forward(L, L.FP8_E4M3, params, Xb, 192, a_scale=as_, w_scale=ws)
+    ref = orc.mlp_forward(X.astype(np.float64), *[f32(p).astype(np.float64) for p in params])
+    err = rel_l2(Y, ref)
+    say("  rel-L2 vs fp64", err)
+    assert err <= 5e-2
+    # the same network on the same rounded operands in FP64
+    W1, b1, W2, b2, W3, b3 = [f32(p).astype(np.float64) for p in params]
+    rb = orc.round_bf16
+    q8 = lambda v, s: orc.round_e4m3(v / s) * s
+    a1 = q8(np.tanh(rb(X.astype(np.float64)) @ rb(W1) + b1), as_[1])
+    a2 = rb(np.tanh(a1 @ q8(W2, w2s) + b2))
+    emu = a2 @ rb(W3) + b3
+    e2 = rel_l2(Y, emu)
+    say("  rel-L2 vs emulated fp8", e2)
+    assert e2 <= 5e-3
+
+
+def test_mlp_saved_activations(L, orc):
+    say("mlp saved activations")
+    params = syn.mlp_params(165, 64, 81, seed=7, bias_scale=0.1)
+    n = 100
+    X = f32(np.random.default_rng(8).standard_normal((n, 165)))
+    Y, sv = run_forward(L, L.F32, params, to_gpu(padded(X, 192).ravel()), 192, saved=True)
+    _, A1, A2 = orc.mlp_forward(X.astype(np.float64), *[f32(p).astype(np.float64) for p in params],
+                                want_hidden=True)
+    s = sv.view(torch.float32).cpu().numpy().reshape(2, n, 64)
+    assert rel_l2(s[0], A1) <= 1e-6 and rel_l2(s[1], A2) <= 1e-6
+
+
+def test_forward_empty_and_errors(L):
+    say("forward n=0 and argument errors")
+    params = syn.mlp_params(165, 64, 81, seed=1)
+    Wp, bias = pack_net(L, L.F32, params)
+    net = L.make_mlp(L.F32, 64, Wp, bias)
+    X = torch.zeros(192, dtype=torch.float32, device=dev())
+    Y = torch.zeros(81, dtype=torch.float32, device=dev())
+    L.dnnmg_patch_forward(net, 0, X, 192, Y)
+    with pytest.raises(L.DnnmgError):
+        L.dnnmg_patch_forward(net, 1, X, 100, Y)  # ldx too small
+    bad = L.make_mlp(L.F32, 100, Wp, bias)
+    with pytest.raises(L.DnnmgError):
+        L.dnnmg_patch_forward(bad, 1, X, 192, Y)
+
+
+def test_norm2(L):
+    say("norm2")
+    rng = np.random.default_rng(9)
+    for n in (1, 1000, 1234567):
+        a = f32(rng.standard_normal(n)); b = f32(rng.standard_normal(n))
+        out = torch.zeros(1, dtype=torch.float64, device=dev())
+        ws = torch.empty(L.norm2_workspace_bytes(), dtype=torch.uint8, device=dev())
+        L.dnnmg_norm2_f64(to_gpu(a), out, ws)
+        np.testing.assert_allclose(out.item(), np.sum(a.astype(np.float64) ** 2), rtol=1e-12)
+        L.dnnmg_norm2_f64(to_gpu(a), out, ws, b=to_gpu(b))
+        np.testing.assert_allclose(out.item(), np.sum((a.astype(np.float64) - b) ** 2), rtol=1e-12)

@@ -1,0 +1,73 @@
+"""End-to-end correction step on the GPU against the oracle chain, and the
+HIP-graph replay against eager execution."""
+import numpy as np
+import pytest
+import torch
+
+import dnnmg_synth as syn
+from gpu_util import rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def stepper():
+    from paper_2307_14837_amd import stepper
+
+    assert torch.cuda.is_available()
+    return stepper
+
+
+def p32(params):
+    return [np.asarray(p, np.float32).astype(np.float64) for p in params]
+
+
+@pytest.mark.parametrize("dtype,tol", [("fp32", 1e-5), ("bf16", 2e-2)])
+def test_step_cfg1(stepper, orc, dtype, tol):
+    w = syn.cfg1()
+    say("step cfg1", dtype)
+    inp = syn.step_inputs(w, seed=0)
+    params = syn.mlp_params(165, w.hidden, 81, seed=0)
+    st = stepper.CorrectionStep(w.box, w.ns, params, dtype=dtype, indicator=True)
+    out = st.run_numpy(inp.xc, inp.vprev)
+    ref = orc.correction_step(w.box, w.ns, p32(params), inp.xc, out["vprev32"], indicator=True)
+    assert rel_l2(out["xt"], ref["xt"]) <= 1e-7
+    assert rel_l2(out["r"], ref["r"]) <= 1e-5
+    for key in ("Y", "d", "vcorr", "b", "bc"):
+        e = rel_l2(out[key], ref[key])
+        say(f"  {key} rel-L2 {e:.2e}")
+        assert e <= tol, key
+    assert abs(out["eta"] - ref["eta"]) <= max(tol, 1e-5) * ref["eta"]
+
+
+def test_step_cfg2_bf16(stepper, orc):
+    w = syn.cfg2()
+    say("step cfg2 bf16")
+    inp = syn.step_inputs(w, seed=0)
+    params = syn.mlp_params(165, w.hidden, 81, seed=0)
+    st = stepper.CorrectionStep(w.box, w.ns, params, dtype="bf16")
+    out = st.run_numpy(inp.xc, inp.vprev)
+    ref = orc.correction_step(w.box, w.ns, p32(params), inp.xc, out["vprev32"])
+    assert rel_l2(out["r"], ref["r"]) <= 1e-5
+    for key in ("d", "b", "bc"):
+        e = rel_l2(out[key], ref[key])
+        say(f"  {key} rel-L2 {e:.2e}")
+        assert e <= 2e-2, key
+
+
+def test_graph_replay_matches_eager(stepper):
+    w = syn.cfg1()
+    say("graph replay cfg1")
+    inp = syn.step_inputs(w, seed=1)
+    params = syn.mlp_params(165, w.hidden, 81, seed=1)
+    st = stepper.CorrectionStep(w.box, w.ns, params, dtype="bf16", indicator=True)
+    eager = st.run_numpy(inp.xc, inp.vprev)
+    st.capture()
+    for rep in range(4):
+        st.bc.zero_()
+        st.xcorr.zero_()
+        torch.cuda.synchronize()
+        st.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(st.bc.cpu().numpy().reshape(4, -1), eager["bc"]), rep
+        assert np.array_equal(st.xcorr.cpu().numpy().reshape(4, -1)[:3], eager["vcorr"].astype(np.float32))
