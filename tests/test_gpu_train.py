@@ -1,0 +1,116 @@
+"""GPU training kernels against the oracle: loss gradient, backward pass
+(weight and bias gradients), AdamW; BF16 and FP32 networks, ragged sizes."""
+import numpy as np
+import pytest
+import torch
+
+import dnnmg_synth as syn
+from gpu_util import dev, f32, rel_l2, say, to_gpu
+from test_gpu_parity import pack_net, padded
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_2307_14837_amd as L
+
+    assert torch.cuda.is_available()
+    return L
+
+
+def gpu_grads(L, dtype, params, X, T):
+    H = params[0].shape[1]
+    n = X.shape[0]
+    Wp, bias = pack_net(L, dtype, params)
+    net = L.make_mlp(dtype, H, Wp, bias)
+    xt = torch.float32 if dtype == L.F32 else torch.bfloat16
+    Xg = to_gpu(padded(X, 192)).to(xt).contiguous().view(-1)
+    Y = torch.empty(n * 81, dtype=torch.float32, device=dev())
+    saved = torch.empty(L.saved_bytes(net, n), dtype=torch.uint8, device=dev())
+    L.dnnmg_patch_forward(net, n, Xg, 192, Y, saved=saved)
+    Tg = to_gpu(f32(T).ravel())
+    dY = torch.empty_like(Y)
+    L.dnnmg_mse_grad(Y, Tg, dY, n=n)
+    dW = [torch.empty(s, dtype=torch.float32, device=dev()) for s in (165 * H, H * H, H * 81)]
+    db = [torch.empty(s, dtype=torch.float32, device=dev()) for s in (H, H, 81)]
+    ws = torch.empty(L.backward_workspace_bytes(net, n), dtype=torch.uint8, device=dev())
+    W2 = to_gpu(f32(params[2]).ravel()); W3 = to_gpu(f32(params[4]).ravel())
+    L.dnnmg_patch_backward(net, W2, W3, n, Xg, 192, saved, dY, dW, db, ws)
+    out = torch.zeros(1, dtype=torch.float64, device=dev())
+    wsn = torch.empty(L.norm2_workspace_bytes(), dtype=torch.uint8, device=dev())
+    L.dnnmg_norm2_f64(Y, out, wsn, b=Tg, n=n * 81)
+    torch.cuda.synchronize()
+    shapes = [(165, H), (H, H), (H, 81)]
+    g = []
+    for l in range(3):
+        g += [dW[l].cpu().numpy().reshape(shapes[l]).astype(np.float64), db[l].cpu().numpy().astype(np.float64)]
+    return g, out.item() / n, dY.cpu().numpy().reshape(n, 81)
+
+
+def oracle_grads(orc, params, X, T):
+    p = [f32(q).astype(np.float64) for q in params]
+    Y, A1, A2 = orc.mlp_forward(X.astype(np.float64), *p, want_hidden=True)
+    loss, dY = orc.mse(Y, T.astype(np.float64))
+    dW1, db1, dW2, db2, dW3, db3 = orc.mlp_backward(X.astype(np.float64), p[2], p[4], A1, A2, dY)
+    return [dW1, db1, dW2, db2, dW3, db3], loss, dY
+
+
+@pytest.mark.parametrize("H,n", [(64, 1), (64, 257), (128, 4099), (256, 2048)])
+def test_backward_fp32(L, orc, H, n):
+    say("backward fp32 H", H, "n", n)
+    params = syn.mlp_params(165, H, 81, seed=11, bias_scale=0.1)
+    rng = np.random.default_rng(12)
+    X = f32(rng.standard_normal((n, 165)))
+    T = f32(rng.standard_normal((n, 81)) * 0.5)
+    g, loss, dY = gpu_grads(L, L.F32, params, X, T)
+    gr, lr_, dYr = oracle_grads(orc, params, X, T)
+    assert abs(loss - lr_) <= 1e-5 * abs(lr_)
+    assert rel_l2(dY, dYr) <= 1e-5
+    for i, (a, b) in enumerate(zip(g, gr)):
+        e = rel_l2(a, b)
+        say(f"  grad {i} rel-L2 {e:.2e}")
+        assert e <= 1e-5, i
+
+
+@pytest.mark.parametrize("H,n", [(128, 333), (256, 4096)])
+def test_backward_bf16(L, orc, H, n):
+    say("backward bf16 H", H, "n", n)
+    params = syn.mlp_params(165, H, 81, seed=13, bias_scale=0.1)
+    rng = np.random.default_rng(14)
+    X = f32(rng.standard_normal((n, 165)))
+    T = f32(rng.standard_normal((n, 81)) * 0.5)
+    g, loss, _ = gpu_grads(L, L.BF16, params, X, T)
+    gr, lr_, _ = oracle_grads(orc, params, X, T)
+    assert abs(loss - lr_) <= 2e-2 * abs(lr_)
+    for i, (a, b) in enumerate(zip(g, gr)):
+        e = rel_l2(a, b)
+        say(f"  grad {i} rel-L2 {e:.2e}")
+        assert e <= 2e-2, i
+
+
+def test_backward_deterministic(L):
+    say("backward run-to-run identical")
+    params = syn.mlp_params(165, 128, 81, seed=3)
+    rng = np.random.default_rng(4)
+    X = f32(rng.standard_normal((5000, 165))); T = f32(rng.standard_normal((5000, 81)))
+    g1, _, _ = gpu_grads(L, L.BF16, params, X, T)
+    g2, _, _ = gpu_grads(L, L.BF16, params, X, T)
+    for a, b in zip(g1, g2):
+        assert np.array_equal(a, b)
+
+
+def test_adamw(L, orc):
+    say("adamw 10 steps")
+    rng = np.random.default_rng(5)
+    n = 100003
+    th0 = f32(rng.standard_normal(n))
+    grads = [f32(rng.standard_normal(n)) for _ in range(10)]
+    th = to_gpu(th0.copy()); m = torch.zeros(n, dtype=torch.float32, device=dev()); v = torch.zeros_like(m)
+    tr = th0.astype(np.float64); mr = np.zeros(n); vr = np.zeros(n)
+    for t, gr in enumerate(grads, start=1):
+        L.dnnmg_adamw_step(th, m, v, to_gpu(gr), 1e-3, t, wd=1e-2)
+        orc.adamw(tr, mr, vr, gr.astype(np.float64), 1e-3, 0.9, 0.999, 1e-8, 1e-2, t)
+    torch.cuda.synchronize()
+    got = th.cpu().numpy()
+    assert np.max(np.abs(got - tr)) <= 1e-6 * np.max(np.abs(tr))
