@@ -213,6 +213,38 @@ size_t dnnmg_norm2_workspace(void);
 int dnnmg_norm2_f64(int64_t n, const float *a, const float *b, double *out, void *ws,
                     size_t ws_bytes, void *stream);
 
+/* Plain fine-level correction used by the residual-indicator fallback:
+ * `sweeps` additive patch sweeps with the local problems of the Vanka
+ * smoother (Sec. 2.4) on the patches of Sec. 4.2, in place on x FP32
+ * [4][n_fine]:  r = F - A(x) (as dnnmg_residual, with vprev and fmid); on
+ * every patch solve its local problem; x += omega * mu (.) sum_P L(delta_P)
+ * (the averaging of eq. (defL)).  The local matrix A_P is the operator
+ * linearised at the current velocity with frozen convection, restricted to
+ * the patch's 108 unknowns (Galerkin terms of the 64 cells touching the
+ * patch, pressure stabilisation of its own 8 cells); Dirichlet velocities
+ * stay fixed.
+ *   coupled = 0: momentum equations with the pressure held,
+ *                K_P delta_a = r_a per velocity component (the fallback);
+ *   coupled = 1: the full 108 x 108 velocity-pressure local systems.
+ * ws: device workspace of dnnmg_vanka_workspace(box) bytes. */
+size_t dnnmg_vanka_workspace(const dnnmg_box *box);
+int dnnmg_vanka_sweeps(const dnnmg_box *box, const dnnmg_ns *ns, float *x, const float *vprev,
+                       const float *fmid, int sweeps, float omega, int coupled, void *ws,
+                       size_t ws_bytes, void *stream);
+
+/* Residual-indicator fallback (taken on the device, no host synchronisation):
+ * norms = {||r(x~)||^2, ||r(x_corr)||^2} (device FP64, from dnnmg_norm2_f64).
+ * If eta = ||r(x_corr)|| / ||r(x~)|| exceeds theta (or is NaN), x_corr FP32
+ * [4][n_fine] is replaced by `sweeps` pressure-held sweeps of
+ * dnnmg_vanka_sweeps started from x~; otherwise x_corr is left as it is and
+ * the launched kernels exit at once.  flag_out (device int, optional)
+ * receives 1 when the fallback was taken.  ws: dnnmg_fallback_workspace(box)
+ * bytes. */
+size_t dnnmg_fallback_workspace(const dnnmg_box *box);
+int dnnmg_fallback(const dnnmg_box *box, const dnnmg_ns *ns, const float *xt, const float *vprev,
+                   const float *fmid, const double *norms, double theta, int sweeps, float omega,
+                   float *xcorr, int *flag_out, void *ws, size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

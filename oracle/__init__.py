@@ -82,6 +82,7 @@ def lib():
         L.or_mse.argtypes = [i64, ctypes.c_int, dp, dp, dp]
         L.or_adamw.argtypes = [i64, dp, dp, dp, dp, d, d, d, d, d, i64]
         L.or_norm2.argtypes = [i64, dp, dp]
+        L.or_vanka_sweep.argtypes = [P(Box), P(NS), dp, dp, dp, d, ctypes.c_int, dp]
         _lib = L
     return _lib
 
@@ -267,7 +268,8 @@ def round_e4m3(x) -> np.ndarray:
     return np.vectorize(lambda t: f(float(t)), otypes=[np.float64])(np.asarray(x, dtype=np.float64))
 
 
-def correction_step(box, ns, params, xc, vprev, shift=None, inv_scale=None, indicator=False):
+def correction_step(box, ns, params, xc, vprev, shift=None, inv_scale=None, indicator=False,
+                    theta=1.0, fallback_sweeps=4, omega=1.0):
     """Algorithm 1 after the coarse solve, step by step in FP64:
     x~ = P x^L; r = F - A(x~); X = Q(x~, r, geometry); Y = N(X);
     x_corr = (v~ + L(Y), p~); b = Rhs(v~ + d); b^L = R b.
@@ -278,12 +280,59 @@ def correction_step(box, ns, params, xc, vprev, shift=None, inv_scale=None, indi
     Y = mlp_forward(X, *params)
     d = scatter(box, Y)
     vcorr = xt[:3] + d
-    b = rhs(box, ns, vcorr)
-    bc = restrict(box, b)
-    out = dict(xt=xt, r=r, X=X, Y=Y, d=d, vcorr=vcorr, b=b, bc=bc)
+    out = dict(xt=xt, r=r, X=X, Y=Y, d=d)
     if indicator:
+        # residual indicator; above theta the plain fine correction
+        # (pressure-held patch sweeps from x~) replaces the network's
         xcorr = np.concatenate([vcorr, xt[3:4]])
         r2 = residual(box, ns, xcorr, vprev)
         out["r2"] = r2
         out["eta"] = float(np.sqrt(norm2(r2) / norm2(r)))
+        out["fell_back"] = int(not (norm2(r2) <= theta ** 2 * norm2(r)))
+        if out["fell_back"]:
+            xv = xt.copy()
+            for _ in range(fallback_sweeps):
+                xv = vanka_sweep(box, ns, xv, vprev, omega=omega, coupled=False)
+            vcorr = xv[:3]
+    b = rhs(box, ns, vcorr)
+    bc = restrict(box, b)
+    out.update(vcorr=vcorr, b=b, bc=bc)
+    return out
+
+
+def vanka_matrix(box, ns, w, M) -> np.ndarray:
+    """Local 108 x 108 matrix of the plain fine-level correction on patch M
+    (Picard linearisation at velocity w, the patch's own cells; see the C
+    source for the blocks)."""
+    bx = _box(box)
+    w = _f64(w).reshape(-1, fine_nodes(bx))
+    A = np.zeros((108, 108))
+    lib().or_vanka_matrix(ctypes.byref(bx), ctypes.byref(_ns(ns)), _dp(w), ctypes.c_int64(M), _dp(A))
+    return A
+
+
+def dense_solve(A, b) -> np.ndarray:
+    A = np.array(A, dtype=np.float64, order="C")
+    x = np.array(b, dtype=np.float64)
+    rc = lib().or_dense_solve(ctypes.c_int(A.shape[0]), _dp(A), _dp(x))
+    if rc:
+        raise np.linalg.LinAlgError("singular")
+    return x
+
+
+def vanka_sweep(box, ns, x, vprev, fmid=None, omega=1.0, coupled=False) -> np.ndarray:
+    """One additive patch sweep with L-averaging: the plain fine-level
+    correction used by the residual-indicator fallback (coupled=False:
+    momentum equations at fixed pressure; coupled=True: full local
+    velocity-pressure systems)."""
+    bx = _box(box)
+    nf = fine_nodes(bx)
+    x = _f64(x).reshape(4, nf)
+    vprev = _f64(vprev).reshape(3, nf)
+    fmid = None if fmid is None else _f64(fmid).reshape(3, nf)
+    out = np.zeros((4, nf))
+    rc = lib().or_vanka_sweep(ctypes.byref(bx), ctypes.byref(_ns(ns)), _dp(x), _dp(vprev), _dp(fmid),
+                              ctypes.c_double(omega), ctypes.c_int(int(coupled)), _dp(out))
+    if rc:
+        raise np.linalg.LinAlgError("singular local matrix")
     return out

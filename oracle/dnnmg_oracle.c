@@ -615,3 +615,234 @@ double or_round_e4m3(double x) {
     if (r > 448.0) r = 448.0;
     return x < 0 ? -r : r;
 }
+
+/* ------------------------------- plain fine-level correction (patch Vanka) */
+
+/* Shape functions of patch-local node (a,b,c) in {0,1,2}^3 on the fine cell
+ * with offset (ox,oy,oz) in the patch, at the cell-local point xi: value and
+ * gradient (zero if the node is not a vertex of the cell). */
+static void fine_shape(const double h[3], int a, int b, int c, int ox, int oy, int oz,
+                       const double xi[3], double *phi, double dphi[3]) {
+    int la = a - ox, lb = b - oy, lc = c - oz;
+    if (la < 0 || la > 1 || lb < 0 || lb > 1 || lc < 0 || lc > 1) {
+        *phi = 0.0;
+        dphi[0] = dphi[1] = dphi[2] = 0.0;
+        return;
+    }
+    *phi = l1(la, xi[0]) * l1(lb, xi[1]) * l1(lc, xi[2]);
+    dphi[0] = dl1(la) / h[0] * l1(lb, xi[1]) * l1(lc, xi[2]);
+    dphi[1] = l1(la, xi[0]) * dl1(lb) / h[1] * l1(lc, xi[2]);
+    dphi[2] = l1(la, xi[0]) * l1(lb, xi[1]) * dl1(lc) / h[2];
+}
+
+/* Coarse (patch) shape function of a corner node, zero for other nodes. */
+static void coarse_shape(const double H[3], int a, int b, int c, const double xc[3],
+                         double *Phi, double dPhi[3]) {
+    if ((a & 1) || (b & 1) || (c & 1)) {
+        *Phi = 0.0;
+        dPhi[0] = dPhi[1] = dPhi[2] = 0.0;
+        return;
+    }
+    int A = a / 2, B = b / 2, C = c / 2;
+    *Phi = l1(A, xc[0]) * l1(B, xc[1]) * l1(C, xc[2]);
+    dPhi[0] = dl1(A) / H[0] * l1(B, xc[1]) * l1(C, xc[2]);
+    dPhi[1] = l1(A, xc[0]) * dl1(B) / H[1] * l1(C, xc[2]);
+    dPhi[2] = l1(A, xc[0]) * l1(B, xc[1]) * dl1(C) / H[2];
+}
+
+/* Local matrix of the plain fine-level correction on patch M (the Vanka
+ * local problem of Sec. 2.4 on the patch's 27 nodes): the rows and columns of
+ * the patch's 108 unknowns [u(27) v(27) w(27) p(27)] (local node iota =
+ * a + 3b + 9c) taken from the Crank-Nicolson operator linearised at the
+ * velocity w with frozen convection (Picard).  Galerkin terms come from every
+ * fine cell that has a patch node as a vertex (the 4x4x4 cell block around
+ * the patch), so each row is the full operator row restricted to the patch:
+ *   velocity-velocity (per component): (1/k)(phi_j, phi_i)
+ *        + 1/2 (w.grad phi_j, phi_i) + nu/2 (grad phi_j, grad phi_i)
+ *   velocity row (a,i), pressure column j: -(phi_j, d_a phi_i)
+ *   pressure row i, velocity column (a,j): (d_a phi_j, phi_i)
+ * The pressure stabilisation alpha_T (grad(phi_j - pi phi_j), grad(phi_i -
+ * pi phi_i)) is taken over the patch's own cells (pi = interpolation onto
+ * the patch's Q1 space), the convection stabilisation is left out.  Velocity
+ * dofs on Dirichlet faces get identity rows and columns.  A is row-major
+ * 108 x 108, row = test function, column = trial function. */
+void or_vanka_matrix(const or_box *bx, const or_ns *ns, const double *w, int64_t M, double *A) {
+    const int64_t nfn = or_fine_nodes(bx);
+    double h[3], H[3];
+    for (int a = 0; a < 3; ++a) {
+        h[a] = bx->len[a] / (2.0 * bx->n[a]);
+        H[a] = 2.0 * h[a];
+    }
+    const double vol = h[0] * h[1] * h[2];
+    const double gp = 0.5 / sqrt(3.0);
+    const double gq[2] = {0.5 - gp, 0.5 + gp};
+    const double hT = sqrt(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]);
+    int64_t I = M % bx->n[0], J = (M / bx->n[0]) % bx->n[1], K = M / ((int64_t)bx->n[0] * bx->n[1]);
+    int dir[27];
+    for (int t = 0; t < 27; ++t)
+        dir[t] = is_dirichlet(bx, 2 * I + t % 3, 2 * J + (t / 3) % 3, 2 * K + t / 9);
+    for (int t = 0; t < 108 * 108; ++t) A[t] = 0.0;
+    /* cells with patch-local origin o in {-1,0,1,2}^3 */
+    for (int cz = -1; cz <= 2; ++cz)
+        for (int cy = -1; cy <= 2; ++cy)
+            for (int cx = -1; cx <= 2; ++cx) {
+                int64_t g0[3] = {2 * I + cx, 2 * J + cy, 2 * K + cz};
+                int exists = 1;
+                for (int a = 0; a < 3; ++a)
+                    if (!periodic(bx, a) && (g0[a] < 0 || g0[a] >= 2 * (int64_t)bx->n[a])) exists = 0;
+                if (!exists) continue;
+                const int own = cx >= 0 && cx <= 1 && cy >= 0 && cy <= 1 && cz >= 0 && cz <= 1;
+                /* velocity at the cell's vertices and its stabilisation parameter */
+                double wv8[3][8], vmax = 0.0;
+                for (int v = 0; v < 8; ++v) {
+                    int64_t g = fine_node(bx, g0[0] + (v & 1), g0[1] + ((v >> 1) & 1), g0[2] + (v >> 2));
+                    double s2 = 0.0;
+                    for (int d = 0; d < 3; ++d) {
+                        wv8[d][v] = w[d * nfn + g];
+                        s2 += wv8[d][v] * wv8[d][v];
+                    }
+                    if (sqrt(s2) > vmax) vmax = sqrt(s2);
+                }
+                double alphaT = ns->alpha0 / (ns->nu / (hT * hT) + vmax / hT + 1.0 / ns->dt);
+                for (int q = 0; q < 8; ++q) {
+                    double xi[3] = {gq[q & 1], gq[(q >> 1) & 1], gq[(q >> 2) & 1]};
+                    double xc[3] = {(cx + xi[0]) * 0.5, (cy + xi[1]) * 0.5, (cz + xi[2]) * 0.5};
+                    double wq = 0.125 * vol;
+                    double phi[27], dphi[27][3], Phi[27], dPhi[27][3];
+                    for (int t = 0; t < 27; ++t) {
+                        int a = t % 3, b = (t / 3) % 3, c = t / 9;
+                        fine_shape(h, a, b, c, cx, cy, cz, xi, &phi[t], dphi[t]);
+                        if (own) coarse_shape(H, a, b, c, xc, &Phi[t], dPhi[t]);
+                    }
+                    double wv[3] = {0, 0, 0};
+                    for (int v = 0; v < 8; ++v) {
+                        double pv = l1(v & 1, xi[0]) * l1((v >> 1) & 1, xi[1]) * l1(v >> 2, xi[2]);
+                        for (int d = 0; d < 3; ++d) wv[d] += wv8[d][v] * pv;
+                    }
+                    for (int i = 0; i < 27; ++i)
+                        for (int j = 0; j < 27; ++j) {
+                            double conv = wv[0] * dphi[j][0] + wv[1] * dphi[j][1] + wv[2] * dphi[j][2];
+                            double kin = (1.0 / ns->dt) * phi[j] * phi[i] + 0.5 * conv * phi[i] +
+                                         0.5 * ns->nu *
+                                             (dphi[j][0] * dphi[i][0] + dphi[j][1] * dphi[i][1] +
+                                              dphi[j][2] * dphi[i][2]);
+                            for (int a = 0; a < 3; ++a) {
+                                A[(27 * a + i) * 108 + 27 * a + j] += wq * kin;
+                                A[(27 * a + i) * 108 + 81 + j] += wq * (-phi[j] * dphi[i][a]);
+                                A[(81 + i) * 108 + 27 * a + j] += wq * (dphi[j][a] * phi[i]);
+                            }
+                            if (own) {
+                                double lps = 0.0;
+                                for (int d = 0; d < 3; ++d)
+                                    lps += (dphi[j][d] - dPhi[j][d]) * (dphi[i][d] - dPhi[i][d]);
+                                A[(81 + i) * 108 + 81 + j] += wq * alphaT * lps;
+                            }
+                        }
+                }
+            }
+    for (int t = 0; t < 27; ++t) {
+        if (!dir[t]) continue;
+        for (int a = 0; a < 3; ++a) {
+            int r = 27 * a + t;
+            for (int c = 0; c < 108; ++c) {
+                A[r * 108 + c] = 0.0;
+                A[c * 108 + r] = 0.0;
+            }
+            A[r * 108 + r] = 1.0;
+        }
+    }
+}
+
+/* Solve A x = b (n x n, row-major, overwritten) by Gaussian elimination with
+ * partial pivoting; b is overwritten by x.  Returns 0, or -1 if singular. */
+int or_dense_solve(int n, double *A, double *b) {
+    for (int k = 0; k < n; ++k) {
+        int p = k;
+        for (int i = k + 1; i < n; ++i)
+            if (fabs(A[i * n + k]) > fabs(A[p * n + k])) p = i;
+        if (A[p * n + k] == 0.0) return -1;
+        if (p != k) {
+            for (int c = 0; c < n; ++c) {
+                double t = A[k * n + c];
+                A[k * n + c] = A[p * n + c];
+                A[p * n + c] = t;
+            }
+            double t = b[k];
+            b[k] = b[p];
+            b[p] = t;
+        }
+        for (int i = k + 1; i < n; ++i) {
+            double f = A[i * n + k] / A[k * n + k];
+            if (f == 0.0) continue;
+            for (int c = k; c < n; ++c) A[i * n + c] -= f * A[k * n + c];
+            b[i] -= f * b[k];
+        }
+    }
+    for (int k = n - 1; k >= 0; --k) {
+        double s = b[k];
+        for (int c = k + 1; c < n; ++c) s -= A[k * n + c] * b[c];
+        b[k] = s / A[k * n + k];
+    }
+    return 0;
+}
+
+/* One sweep of the plain fine-level correction, additive over patches with
+ * the averaging of the extension operator L, eq. (defL): r = residual(x);
+ * on every patch solve a local problem with the local matrix at the current
+ * velocity; x_out = x + omega * mu (.) sum_P L(delta_P), Dirichlet
+ * velocities unchanged.
+ *   coupled = 1: the full 108 x 108 velocity-pressure system A_P delta_P = r_P
+ *                (all four fields corrected);
+ *   coupled = 0: the momentum equations with the pressure held at its
+ *                current value: K_P delta_a = r_a for each velocity component
+ *                (K_P = velocity block of A_P); the pressure is not changed,
+ *                as the network's correction leaves it to the coarse level.
+ * Returns 0 or -1. */
+int or_vanka_sweep(const or_box *bx, const or_ns *ns, const double *x, const double *vp,
+                   const double *fmid, double omega, int coupled, double *xout) {
+    const int64_t nfn = or_fine_nodes(bx), np = or_patches(bx);
+    double *r = (double *)malloc(sizeof(double) * 4 * nfn);
+    double *d = (double *)calloc(4 * nfn, sizeof(double));
+    double *A = (double *)malloc(sizeof(double) * 108 * 108);
+    int32_t *map = (int32_t *)malloc(sizeof(int32_t) * 27 * np);
+    uint8_t *mult = (uint8_t *)malloc(nfn);
+    uint8_t *dir = (uint8_t *)malloc(nfn);
+    int rc = 0;
+    or_residual(bx, ns, x, vp, fmid, r);
+    or_dofmap(bx, map, mult);
+    or_dirichlet_flags(bx, dir);
+    for (int64_t M = 0; M < np && rc == 0; ++M) {
+        double rhs[108];
+        or_vanka_matrix(bx, ns, x, M, A);
+        for (int f = 0; f < 4; ++f)
+            for (int t = 0; t < 27; ++t) rhs[27 * f + t] = r[f * nfn + map[M * 27 + t]];
+        if (coupled) {
+            if (or_dense_solve(108, A, rhs)) rc = -1;
+        } else {
+            double Kb[27 * 27], tmp[27];
+            for (int a = 0; a < 3; ++a) {
+                for (int i = 0; i < 27; ++i)
+                    for (int j = 0; j < 27; ++j) Kb[i * 27 + j] = A[i * 108 + j];
+                for (int i = 0; i < 27; ++i) tmp[i] = rhs[27 * a + i];
+                if (or_dense_solve(27, Kb, tmp)) rc = -1;
+                for (int i = 0; i < 27; ++i) rhs[27 * a + i] = tmp[i];
+            }
+            for (int i = 0; i < 27; ++i) rhs[81 + i] = 0.0;
+        }
+        for (int f = 0; f < 4; ++f)
+            for (int t = 0; t < 27; ++t) d[f * nfn + map[M * 27 + t]] += rhs[27 * f + t];
+    }
+    for (int64_t n = 0; n < nfn; ++n)
+        for (int f = 0; f < 4; ++f) {
+            double v = d[f * nfn + n] / mult[n];
+            if (f < 3 && dir[n]) v = 0.0;
+            xout[f * nfn + n] = x[f * nfn + n] + omega * v;
+        }
+    free(r);
+    free(d);
+    free(A);
+    free(map);
+    free(mult);
+    free(dir);
+    return rc;
+}

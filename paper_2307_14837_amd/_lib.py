@@ -99,6 +99,12 @@ _sig("dnnmg_mse_grad", [c_i64, c_vp, c_vp, c_vp, c_vp])
 _sig("dnnmg_patch_backward_workspace", [_P(MLP), c_i64], c_sz)
 _sig("dnnmg_patch_backward", [_P(MLP), c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_vp, c_vp * 3, c_vp * 3,
                               c_vp, c_sz, c_vp])
+_sig("dnnmg_vanka_workspace", [_P(Box)], c_sz)
+_sig("dnnmg_vanka_sweeps", [_P(Box), _P(NS), c_vp, c_vp, c_vp, ctypes.c_int, c_f, ctypes.c_int, c_vp, c_sz,
+                            c_vp])
+_sig("dnnmg_fallback_workspace", [_P(Box)], c_sz)
+_sig("dnnmg_fallback", [_P(Box), _P(NS), c_vp, c_vp, c_vp, c_vp, ctypes.c_double, ctypes.c_int, c_f, c_vp,
+                        c_vp, c_vp, c_sz, c_vp])
 _sig("dnnmg_adamw_step", [c_i64, c_vp, c_vp, c_vp, c_vp, c_f, c_f, c_f, c_f, c_f, c_i64, c_vp])
 
 EXPORTS = [
@@ -107,6 +113,7 @@ EXPORTS = [
     "dnnmg_patch_gather", "dnnmg_mlp_packed_bytes", "dnnmg_mlp_pack", "dnnmg_patch_forward",
     "dnnmg_patch_saved_bytes", "dnnmg_scatter_avg", "dnnmg_norm2_workspace", "dnnmg_norm2_f64",
     "dnnmg_mse_grad", "dnnmg_patch_backward_workspace", "dnnmg_patch_backward", "dnnmg_adamw_step",
+    "dnnmg_vanka_workspace", "dnnmg_vanka_sweeps", "dnnmg_fallback_workspace", "dnnmg_fallback",
 ]
 
 
@@ -297,3 +304,33 @@ def dnnmg_adamw_step(theta, m, v, g, lr, t, b1=0.9, b2=0.999, eps=1e-8, wd=1e-5,
                                  _ptr(v, torch.float32, n, "v"), _ptr(g, torch.float32, n, "g"),
                                  float(lr), float(b1), float(b2), float(eps), float(wd), int(t),
                                  _stream(stream)))
+
+
+def vanka_workspace_bytes(box) -> int:
+    return int(_lib.dnnmg_vanka_workspace(ctypes.byref(Box.of(box))))
+
+
+def dnnmg_vanka_sweeps(box, ns, x, vprev, ws, sweeps=1, omega=1.0, coupled=False, fmid=None, stream=None):
+    b = Box.of(box)
+    nf, _, _ = box_sizes(b)
+    _check(_lib.dnnmg_vanka_sweeps(ctypes.byref(b), ctypes.byref(NS.of(ns)), _ptr(x, torch.float32, 4 * nf, "x"),
+                                   _ptr(vprev, torch.float32, 3 * nf, "vprev"),
+                                   _ptr(fmid, torch.float32, 3 * nf, "fmid"), int(sweeps), float(omega),
+                                   int(bool(coupled)), _ptr(ws, None, None, "ws"), ws.numel() * ws.element_size(),
+                                   _stream(stream)))
+
+
+def fallback_workspace_bytes(box) -> int:
+    return int(_lib.dnnmg_fallback_workspace(ctypes.byref(Box.of(box))))
+
+
+def dnnmg_fallback(box, ns, xt, vprev, norms, xcorr, ws, theta=1.0, sweeps=4, omega=1.0, flag_out=None,
+                   fmid=None, stream=None):
+    b = Box.of(box)
+    nf, _, _ = box_sizes(b)
+    _check(_lib.dnnmg_fallback(ctypes.byref(b), ctypes.byref(NS.of(ns)), _ptr(xt, torch.float32, 4 * nf, "xt"),
+                               _ptr(vprev, torch.float32, 3 * nf, "vprev"),
+                               _ptr(fmid, torch.float32, 3 * nf, "fmid"), _ptr(norms, torch.float64, 2, "norms"),
+                               float(theta), int(sweeps), float(omega), _ptr(xcorr, torch.float32, 4 * nf, "xcorr"),
+                               _ptr(flag_out, torch.int32, 1, "flag_out"), _ptr(ws, None, None, "ws"),
+                               ws.numel() * ws.element_size(), _stream(stream)))

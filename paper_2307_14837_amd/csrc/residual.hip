@@ -220,8 +220,10 @@ struct ResParams {
 template <int MODE>
 __global__ void __launch_bounds__(ResTile<MODE>::NT)
     k_residual(Mesh m, ResParams P, const float *__restrict__ x, const float *__restrict__ vp,
-               const float *__restrict__ fmid, float *__restrict__ out, float *__restrict__ aux) {
+               const float *__restrict__ fmid, float *__restrict__ out, float *__restrict__ aux,
+               const int *__restrict__ flag) {
     using T = ResTile<MODE>;
+    if (flag && *flag == 0) return; // predicated launch (fallback path not taken)
     __shared__ float sX[T::NF_STAGE > 0 ? T::NF_STAGE * T::SN : 1];
     __shared__ float sV[T::NF_V * T::VN];
     __shared__ float sAcc[T::NACC * T::VN];
@@ -588,7 +590,8 @@ __global__ void __launch_bounds__(ResTile<MODE>::NT)
 // the per-patch sums of the patches it is a corner of, in ascending patch
 // order.  aux[M][4 j + f]: corner j = A + 2B + 4C of patch M, field f.
 __global__ void __launch_bounds__(256) k_lps_corners(Mesh m, const float *__restrict__ aux,
-                                                     float *__restrict__ r) {
+                                                     float *__restrict__ r, const int *__restrict__ flag) {
+    if (flag && *flag == 0) return;
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= m.n_coarse) return;
     uint32_t JK = fdiv((uint32_t)t, m.cx), I = (uint32_t)t - JK * m.nc[0];
@@ -656,6 +659,15 @@ static dim3 res_grid(const Mesh &m) {
                 (m.nf[2] + T::TZ - 1) / T::TZ);
 }
 
+int residual_launch(const Mesh &m, const dnnmg_ns *ns, const float *x, const float *vprev,
+                    const float *fmid, float *r, float *aux, const int *flag, hipStream_t s) {
+    ResParams P = make_params(m, ns);
+    k_residual<MODE_RES><<<res_grid<MODE_RES>(m), ResTile<MODE_RES>::NT, 0, s>>>(m, P, x, vprev, fmid, r,
+                                                                                 aux, flag);
+    k_lps_corners<<<blocks_for(m.n_coarse, 256), 256, 0, s>>>(m, aux, r, flag);
+    return hip_check(hipGetLastError(), "dnnmg_residual launch");
+}
+
 } // namespace dnnmg
 
 using namespace dnnmg;
@@ -677,12 +689,7 @@ extern "C" int dnnmg_residual(const dnnmg_box *box, const dnnmg_ns *ns, const fl
     if (ws_bytes < (size_t)m.n_patches * 32 * sizeof(float))
         return fail(DNNMG_ERR_SHAPE, "dnnmg_residual: workspace %zu < %zu bytes", ws_bytes,
                     (size_t)m.n_patches * 32 * sizeof(float));
-    ResParams P = make_params(m, ns);
-    hipStream_t s = (hipStream_t)stream;
-    k_residual<MODE_RES><<<res_grid<MODE_RES>(m), ResTile<MODE_RES>::NT, 0, s>>>(
-        m, P, x, vprev, fmid, r, (float *)ws);
-    k_lps_corners<<<blocks_for(m.n_coarse, 256), 256, 0, s>>>(m, (const float *)ws, r);
-    return hip_check(hipGetLastError(), "dnnmg_residual launch");
+    return residual_launch(m, ns, x, vprev, fmid, r, (float *)ws, nullptr, (hipStream_t)stream);
 }
 
 extern "C" int dnnmg_rhs(const dnnmg_box *box, const dnnmg_ns *ns, const float *v, const float *fmid,
@@ -694,6 +701,6 @@ extern "C" int dnnmg_rhs(const dnnmg_box *box, const dnnmg_ns *ns, const float *
     if (!v || !b) return fail(DNNMG_ERR_ARG, "dnnmg_rhs: NULL pointer");
     ResParams P = make_params(m, ns);
     k_residual<MODE_RHS><<<res_grid<MODE_RHS>(m), ResTile<MODE_RHS>::NT, 0, (hipStream_t)stream>>>(
-        m, P, v, nullptr, fmid, b, nullptr);
+        m, P, v, nullptr, fmid, b, nullptr, nullptr);
     return hip_check(hipGetLastError(), "dnnmg_rhs launch");
 }

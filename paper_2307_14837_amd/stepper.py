@@ -29,7 +29,7 @@ class CorrectionStep:
     """
 
     def __init__(self, box, ns, params, dtype="bf16", device="cuda:0", shift=None, inv_scale=None,
-                 indicator=False):
+                 indicator=False, theta=1.0, fallback_sweeps=4):
         self.box = L.Box.of(box)
         self.ns = L.NS.of(ns)
         self.dev = torch.device(device)
@@ -51,10 +51,13 @@ class CorrectionStep:
         self.xcorr = torch.zeros(4 * self.nf, **f32)    # (v~ + d, p~)
         self.b = torch.zeros(4 * self.nf, **f32)
         self.bc = torch.zeros(4 * self.nc, **f64)
+        self.theta, self.fallback_sweeps = float(theta), int(fallback_sweeps)
         if indicator:
             self.r2 = torch.zeros(4 * self.nf, **f32)
             self.norms = torch.zeros(2, **f64)
             self.ws_norm = torch.zeros(L.norm2_workspace_bytes(), dtype=torch.uint8, device=self.dev)
+            self.ws_fb = torch.zeros(L.fallback_workspace_bytes(self.box), dtype=torch.uint8, device=self.dev)
+            self.fell_back = torch.zeros(1, dtype=torch.int32, device=self.dev)
         self.shift = None if shift is None else torch.as_tensor(np.asarray(shift, np.float32)).to(self.dev)
         self.inv_scale = None if inv_scale is None else torch.as_tensor(np.asarray(inv_scale, np.float32)).to(self.dev)
         self.set_params(params)
@@ -93,12 +96,17 @@ class CorrectionStep:
         L.dnnmg_patch_forward(self.net, self.np, self.X, LDX, self.Y, stream=stream)
         # corrected iterate (v~ + d, p~)
         L.dnnmg_scatter_avg(box, self.Y, self.xcorr, vbase=self.xt, stream=stream)
-        L.dnnmg_rhs(box, ns, self.xcorr, self.b, stream=stream)
-        L.dnnmg_restrict(box, self.b, self.bc, stream=stream)
         if self.indicator:
+            # eta = ||r(x_corr)|| / ||r(x~)||; above theta the plain fine
+            # correction replaces the network's (decided on the device)
             L.dnnmg_residual(box, ns, self.xcorr, self.vprev, self.r2, self.ws_res, stream=stream)
             L.dnnmg_norm2_f64(self.r, self.norms[0:1], self.ws_norm, stream=stream)
             L.dnnmg_norm2_f64(self.r2, self.norms[1:2], self.ws_norm, stream=stream)
+            L.dnnmg_fallback(box, ns, self.xt, self.vprev, self.norms, self.xcorr, self.ws_fb,
+                             theta=self.theta, sweeps=self.fallback_sweeps, flag_out=self.fell_back,
+                             stream=stream)
+        L.dnnmg_rhs(box, ns, self.xcorr, self.b, stream=stream)
+        L.dnnmg_restrict(box, self.b, self.bc, stream=stream)
 
     def capture(self):
         """Capture step() into a HIP graph (torch.cuda.CUDAGraph wraps hipGraph)."""
@@ -136,4 +144,5 @@ class CorrectionStep:
         if self.indicator:
             n = self.norms.cpu().numpy()
             out["eta"] = float(np.sqrt(n[1] / n[0])) if n[0] > 0 else float("inf")
+            out["fell_back"] = int(self.fell_back.item())
         return out

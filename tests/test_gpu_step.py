@@ -28,9 +28,11 @@ def test_step_cfg1(stepper, orc, dtype, tol):
     say("step cfg1", dtype)
     inp = syn.step_inputs(w, seed=0)
     params = syn.mlp_params(165, w.hidden, 81, seed=0)
-    st = stepper.CorrectionStep(w.box, w.ns, params, dtype=dtype, indicator=True)
+    # theta = inf: the indicator is evaluated but the fallback never taken
+    st = stepper.CorrectionStep(w.box, w.ns, params, dtype=dtype, indicator=True, theta=float("inf"))
     out = st.run_numpy(inp.xc, inp.vprev)
-    ref = orc.correction_step(w.box, w.ns, p32(params), inp.xc, out["vprev32"], indicator=True)
+    ref = orc.correction_step(w.box, w.ns, p32(params), inp.xc, out["vprev32"], indicator=True,
+                              theta=float("inf"))
     assert rel_l2(out["xt"], ref["xt"]) <= 1e-7
     assert rel_l2(out["r"], ref["r"]) <= 1e-5
     for key in ("Y", "d", "vcorr", "b", "bc"):
@@ -71,3 +73,35 @@ def test_graph_replay_matches_eager(stepper):
         torch.cuda.synchronize()
         assert np.array_equal(st.bc.cpu().numpy().reshape(4, -1), eager["bc"]), rep
         assert np.array_equal(st.xcorr.cpu().numpy().reshape(4, -1)[:3], eager["vcorr"].astype(np.float32))
+
+
+@pytest.mark.parametrize("mode", ["never", "always", "nan_weights", "huge_weights"])
+def test_indicator_fallback(stepper, orc, mode):
+    """Residual-indicator fallback forced from the host: theta = inf (never),
+    theta = 0 (always), NaN weights and weights scaled by 1e3 (both must fall
+    back, decided on the device)."""
+    w = syn.cfg1()
+    say("fallback", mode)
+    inp = syn.step_inputs(w, seed=2)
+    params = syn.mlp_params(165, w.hidden, 81, seed=2)
+    theta = {"never": float("inf"), "always": 0.0}.get(mode, 1.0)
+    if mode == "nan_weights":
+        params[4] = params[4].copy(); params[4][0, 0] = np.nan
+    if mode == "huge_weights":
+        params[4] = params[4] * 1e3
+    st = stepper.CorrectionStep(w.box, w.ns, params, dtype="fp32", indicator=True, theta=theta,
+                                fallback_sweeps=3)
+    out = st.run_numpy(inp.xc, inp.vprev)
+    ref = orc.correction_step(w.box, w.ns, p32(params), inp.xc, out["vprev32"], indicator=True,
+                              theta=theta, fallback_sweeps=3)
+    assert out["fell_back"] == ref["fell_back"] == (0 if mode == "never" else 1)
+    assert np.all(np.isfinite(out["vcorr"])) and np.all(np.isfinite(out["bc"]))
+    tol = 1e-4 if out["fell_back"] else 1e-5
+    for key in ("vcorr", "bc"):
+        e = rel_l2(out[key], ref[key])
+        say(f"  {key} rel-L2 {e:.2e}")
+        assert e <= tol, key
+    if mode != "never":
+        # the plain correction lowers the momentum residual of x~
+        r_fb = orc.residual(w.box, w.ns, np.concatenate([out["vcorr"], out["xt"][3:4]]), out["vprev32"])
+        assert np.linalg.norm(r_fb[:3]) < np.linalg.norm(ref["r"][:3])

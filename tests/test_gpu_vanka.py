@@ -1,0 +1,61 @@
+"""Plain fine-level correction (patch-Vanka sweeps) on the GPU against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import dnnmg_synth as syn
+from gpu_util import dev, f32, rel_l2, say, to_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_2307_14837_amd as L
+
+    assert torch.cuda.is_available()
+    return L
+
+
+CASES = {
+    "cfg1": (syn.cfg1().box, syn.cfg1().ns),
+    "chan_small": (syn.channel_box((4, 2, 2)), syn.NSParams(1e-3, 0.005)),
+    "mixed": (syn.BoxSpec((6, 4, 2), (1.2, 0.8, 0.5), 1, syn.Y_LO | syn.Y_HI | syn.Z_HI),
+              syn.NSParams(0.01, 0.01, 0.05, 0.1)),
+}
+
+
+def inputs(box, orc, seed):
+    rng = np.random.default_rng(seed)
+    xc = rng.standard_normal((4, box.n_coarse))
+    x = orc.prolong(box, xc)
+    vp = x[:3] + 0.2 * rng.standard_normal((3, box.n_fine))
+    dmask = syn.boundary_mask(box, True)
+    vp[:, dmask] = x[:3, dmask]
+    return f32(x), f32(vp)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("sweeps", [1, 3])
+@pytest.mark.parametrize("coupled", [False, True])
+def test_vanka_sweeps_match_oracle(L, orc, name, sweeps, coupled):
+    box, ns = CASES[name]
+    say("vanka", name, "sweeps", sweeps, "coupled" if coupled else "pressure held")
+    x, vp = inputs(box, orc, 3)
+    omega = 1.0 if not coupled else 0.7
+    xg = to_gpu(x.ravel().copy())
+    ws = torch.empty(L.vanka_workspace_bytes(box), dtype=torch.uint8, device=dev())
+    L.dnnmg_vanka_sweeps(box, ns, xg, to_gpu(vp.ravel()), ws, sweeps=sweeps, omega=omega, coupled=coupled)
+    got = xg.cpu().numpy().reshape(4, -1).astype(np.float64)
+    ref = x.astype(np.float64)
+    for _ in range(sweeps):
+        ref = orc.vanka_sweep(box, ns, ref, vp.astype(np.float64), omega=omega, coupled=coupled)
+    e = rel_l2(got - x, ref - x)
+    say(f"  correction rel-L2 {e:.2e}")
+    assert e <= 2e-3 if coupled else e <= 1e-4
+    if not coupled:
+        assert np.array_equal(got[3], x[3].astype(np.float64))
+        r0 = np.linalg.norm(orc.residual(box, ns, x.astype(np.float64), vp.astype(np.float64))[:3])
+        r1 = np.linalg.norm(orc.residual(box, ns, got, vp.astype(np.float64))[:3])
+        say(f"  momentum residual {r0:.3e} -> {r1:.3e}")
+        assert r1 < r0 / 3.0 ** sweeps

@@ -517,3 +517,148 @@ def test_lps_convection_term_sign(orc):
         assert e < 0.0
         np.testing.assert_allclose(r_on2 - r_off, 2 * (r_on - r_off), rtol=1e-9,
                                    atol=1e-12 * np.abs(r_on - r_off).max())
+
+
+# ------------------------------------------- plain fine correction (Vanka) --
+
+def fd_jacobian(orc, box, P, x0, vp, eps=1e-6):
+    """-dr/dx by central differences of the oracle residual."""
+    nf = box.n_fine
+    J = np.zeros((4 * nf, 4 * nf))
+    for c in range(4 * nf):
+        e = np.zeros(4 * nf); e[c] = eps
+        rp = orc.residual(box, P, (x0.ravel() + e).reshape(4, nf), vp)
+        rm = orc.residual(box, P, (x0.ravel() - e).reshape(4, nf), vp)
+        J[:, c] = -(rp - rm).ravel() / (2 * eps)
+    return J
+
+
+def to_local(box, A_global, orc):
+    """Reorder a global [field][node] matrix of a one-patch box to the local
+    [field][iota] ordering (the dof map of the single patch)."""
+    m, _ = orc.dofmap(box)
+    nf = box.n_fine
+    idx = np.concatenate([f * nf + m[0] for f in range(4)])
+    return A_global[np.ix_(idx, idx)]
+
+
+def test_vanka_matrix_is_jacobian_at_rest(orc):
+    """On a box that is one patch, the local matrix at w = 0 equals the exact
+    Jacobian of the Crank-Nicolson operator (finite differences of the
+    residual): mass, viscosity, pressure gradient, divergence and the
+    pressure LPS term."""
+    box = open_box((1, 1, 1), (0.7, 0.5, 0.9))
+    P = ns(nu=0.03, dt=0.02, a0=0.3)
+    nf = box.n_fine
+    J = to_local(box, fd_jacobian(orc, box, P, np.zeros((4, nf)), np.zeros((3, nf))), orc)
+    A = orc.vanka_matrix(box, P, np.zeros((3, nf)), 0)
+    np.testing.assert_allclose(A, J, rtol=1e-6, atol=1e-9 * np.abs(J).max())
+
+
+def test_vanka_matrix_rows_are_global_rows(orc):
+    """On a periodic box, with the LPS terms off, the local matrix at w = 0 is
+    the exact Jacobian restricted to the patch's rows and columns (it
+    includes the neighbouring cells' contributions to shared rows)."""
+    box = periodic_box((2, 2, 2), (1.0, 0.8, 1.2))
+    P = ns(nu=0.03, dt=0.02, a0=0.0, d0=0.0)
+    nf = box.n_fine
+    Jg = fd_jacobian(orc, box, P, np.zeros((4, nf)), np.zeros((3, nf)))
+    m, _ = orc.dofmap(box)
+    for M in (0, 5):
+        idx = np.concatenate([f * nf + m[M] for f in range(4)])
+        A = orc.vanka_matrix(box, P, np.zeros((3, nf)), M)
+        np.testing.assert_allclose(A, Jg[np.ix_(idx, idx)], rtol=1e-6, atol=1e-9 * np.abs(Jg).max())
+
+
+def test_vanka_matrix_convection_constant_field(orc):
+    """With a constant velocity c the Picard convection block is
+    1/2 sum_d c_d C_d (Kronecker products of textbook 1-D matrices)."""
+    box = open_box((1, 1, 1), (0.7, 0.5, 0.9))
+    P = ns(nu=0.03, dt=0.02, a0=0.0)
+    nf = box.n_fine
+    c = np.array([0.4, -0.9, 0.3])
+    A0 = orc.vanka_matrix(box, P, np.zeros((3, nf)), 0)
+    Ac = orc.vanka_matrix(box, P, np.tile(c[:, None], (1, nf)), 0)
+    m = fine_mats(box)
+    Mx, My, Mz = m["M"]; Cx, Cy, Cz = m["C"]
+    C3 = [kron3(Cx, My, Mz), kron3(Mx, Cy, Mz), kron3(Mx, My, Cz)]
+    conv = 0.5 * sum(c[d] * C3[d].toarray() for d in range(3))
+    mp, _ = orc.dofmap(box)
+    conv = conv[np.ix_(mp[0], mp[0])]
+    for a in range(3):
+        blk = slice(27 * a, 27 * a + 27)
+        np.testing.assert_allclose((Ac - A0)[blk, blk], conv, rtol=1e-10, atol=1e-14)
+    # only the velocity-velocity blocks change
+    Ac[:81, :81] = A0[:81, :81]
+    np.testing.assert_array_equal(Ac, A0)
+
+
+def test_vanka_matrix_dirichlet_identity(orc):
+    box = syn.channel_box((1, 1, 1))
+    nf = box.n_fine
+    A = orc.vanka_matrix(box, ns(), np.random.default_rng(0).standard_normal((3, nf)), 0)
+    dmask = syn.boundary_mask(box, True)
+    mp, _ = orc.dofmap(box)
+    for t in range(27):
+        if dmask[mp[0][t]]:
+            for a in range(3):
+                r = 27 * a + t
+                e = np.zeros(108); e[r] = 1.0
+                assert np.array_equal(A[r], e) and np.array_equal(A[:, r], e)
+
+
+def test_dense_solve_matches_numpy(orc):
+    rng = np.random.default_rng(1)
+    A = rng.standard_normal((108, 108)); b = rng.standard_normal(108)
+    np.testing.assert_allclose(orc.dense_solve(A, b), np.linalg.solve(A, b), rtol=1e-9, atol=1e-11)
+
+
+@pytest.mark.parametrize("coupled", [True, False])
+def test_vanka_sweep_composition(orc, coupled):
+    """A sweep adds the L-average of the local solutions, checked against
+    numpy.linalg.solve on every patch (full system, or the velocity block per
+    component with the pressure held)."""
+    box = syn.BoxSpec((2, 2, 2), (1.0, 1.0, 1.0), 7, 0)
+    P = syn.cfg1().ns
+    rng = np.random.default_rng(2)
+    nf = box.n_fine
+    modes = syn.fourier_modes(rng)
+    vp = syn.fourier_velocity(modes, syn.node_coords(box, True), box.len)
+    x = np.zeros((4, nf)); x[:3] = vp + 0.05 * rng.standard_normal((3, nf))
+    x[3] = 0.1 * rng.standard_normal(nf)
+    out = orc.vanka_sweep(box, P, x, vp, omega=0.7, coupled=coupled)
+    r = orc.residual(box, P, x, vp)
+    m, mult = orc.dofmap(box)
+    d = np.zeros((4, nf))
+    for M in range(box.n_patches):
+        A = orc.vanka_matrix(box, P, x[:3], M)
+        rhs = np.concatenate([r[f][m[M]] for f in range(4)])
+        if coupled:
+            dl = np.linalg.solve(A, rhs)
+        else:
+            dl = np.concatenate([np.linalg.solve(A[:27, :27], rhs[27 * a: 27 * a + 27]) for a in range(3)]
+                                + [np.zeros(27)])
+        for f in range(4):
+            np.add.at(d[f], m[M], dl[27 * f: 27 * f + 27])
+    np.testing.assert_allclose(out, x + 0.7 * d / mult[None, :], rtol=1e-9, atol=1e-12)
+    if not coupled:
+        assert np.array_equal(out[3], x[3])
+
+
+@pytest.mark.parametrize("box", [syn.channel_box((4, 2, 2)), syn.cfg1().box])
+def test_vanka_velocity_sweeps_converge(orc, box):
+    """The pressure-held sweeps drive the momentum residual down geometrically
+    (rough prolongated field, factor >= 3 per sweep), leaving the pressure."""
+    P = syn.NSParams(1e-3, 0.005)
+    rng = np.random.default_rng(3)
+    x = orc.prolong(box, rng.standard_normal((4, box.n_coarse)))
+    vp = x[:3] + 0.2 * rng.standard_normal((3, box.n_fine))
+    dm = syn.boundary_mask(box, True)
+    vp[:, dm] = x[:3, dm]
+    norms = []
+    for _ in range(4):
+        norms.append(np.linalg.norm(orc.residual(box, P, x, vp)[:3]))
+        x = orc.vanka_sweep(box, P, x, vp, omega=1.0, coupled=False)
+    norms.append(np.linalg.norm(orc.residual(box, P, x, vp)[:3]))
+    for a, b in zip(norms, norms[1:]):
+        assert b < a / 3.0, norms
