@@ -246,3 +246,41 @@ def random_fine_field(box: BoxSpec, ncomp: int, seed: int) -> np.ndarray:
 
 def random_coarse_field(box: BoxSpec, ncomp: int, seed: int) -> np.ndarray:
     return np.random.default_rng(seed).standard_normal((ncomp, box.n_coarse))
+
+
+def channel_initial(box: BoxSpec, amp: float = 0.3, seed: int = 0):
+    """Divergence-free initial channel velocity at fine and coarse nodes: the
+    inflow profile plus the curl of psi_z = a sin^2(pi x / L) s(y) s(z),
+    s(t) = sin^2(pi t / H), which vanishes with its gradient on the inflow
+    face and the walls.  Returns (fine [3][N_f], coarse [3][N_c])."""
+    rng = np.random.default_rng(seed)
+    a = amp * (1.0 + 0.2 * rng.standard_normal())
+    Lx, H = box.len[0], box.len[1]
+    out = []
+    for fine in (True, False):
+        p = node_coords(box, fine)
+        x, y, z = p
+        sx = np.sin(np.pi * x / Lx) ** 2
+        sy, sz = np.sin(np.pi * y / H) ** 2, np.sin(np.pi * z / box.len[2]) ** 2
+        dsy = 2 * np.sin(np.pi * y / H) * np.cos(np.pi * y / H) * np.pi / H
+        dsx = 2 * np.sin(np.pi * x / Lx) * np.cos(np.pi * x / Lx) * np.pi / Lx
+        v = np.zeros_like(p)
+        v[0] = channel_profile(y, z, H) + a * sx * dsy * sz
+        v[1] = -a * dsx * sy * sz
+        out.append(v)
+    return out[0], out[1]
+
+
+def channel_dirichlet(box: BoxSpec, fine: bool):
+    """(mask [4][N], values [4][N]) of the channel's Dirichlet velocity data:
+    the inflow profile on x = 0, zero on the walls; pressure free."""
+    p = node_coords(box, fine)
+    m = boundary_mask(box, fine)
+    mask = np.zeros((4, p.shape[1]), dtype=bool)
+    mask[:3] = m[None, :]
+    vals = np.zeros((4, p.shape[1]))
+    inflow = m & (lattice_index(box, fine)[0] == 0)
+    walls = m & ~inflow
+    vals[0, inflow] = channel_profile(p[1, inflow], p[2, inflow], box.len[1])
+    vals[:3, walls] = 0.0
+    return mask, vals

@@ -1,0 +1,115 @@
+"""Training of the patch network on the GPU with the library's own kernels
+(arXiv 2307.14837, Sec. 4.2 "Training of DNN-MG"; AdamW of Sec. 3).
+
+Objective: the mean over patches of ||Y_M - T_M||^2, where the target T_M is
+the ground-truth fine velocity minus the prolongated coarse velocity on the
+patch's 81 velocity unknowns (the network predicts the correction d).
+Each optimisation step runs, on one stream and without host round trips:
+forward with saved activations, loss gradient, backward (five products),
+AdamW on the FP32 master weights, and re-packing of the low-precision
+copies the forward kernels read.  Inputs are standardised per feature
+(shift / inv_scale) and the targets by one scalar, folded into the output
+layer when the weights are exported.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from .stepper import DTYPES, LDX
+
+_XT = {L.F32: torch.float32, L.BF16: torch.bfloat16}
+
+
+class PatchTrainer:
+    def __init__(self, params, dtype="bf16", lr=1e-3, weight_decay=1e-5, betas=(0.9, 0.999), eps=1e-8,
+                 device="cuda:0", max_batch=65536):
+        self.dev = torch.device(device)
+        self.dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+        if self.dtype not in (L.F32, L.BF16):
+            raise ValueError("training runs in FP32 or BF16")
+        self.hidden = int(np.shape(params[0])[1])
+        self.lr, self.wd, self.betas, self.eps = lr, weight_decay, betas, eps
+        f32 = dict(dtype=torch.float32, device=self.dev)
+        self.theta = [torch.as_tensor(np.asarray(p, np.float32)).contiguous().view(-1).to(self.dev) for p in params]
+        self.m = [torch.zeros_like(t) for t in self.theta]
+        self.v = [torch.zeros_like(t) for t in self.theta]
+        self.grad = [torch.zeros_like(t) for t in self.theta]
+        self.t = 0
+        H = self.hidden
+        self.Wp = [torch.zeros(L.packed_bytes(self.dtype, H, l), dtype=torch.uint8, device=self.dev) for l in range(3)]
+        self.net = L.make_mlp(self.dtype, H, self.Wp, [self.theta[1], self.theta[3], self.theta[5]])
+        self._repack()
+        self.max_batch = max_batch
+        self.Y = torch.zeros(max_batch * L.N_OUT, **f32)
+        self.dY = torch.zeros(max_batch * L.N_OUT, **f32)
+        self.saved = torch.zeros(L.saved_bytes(self.net, max_batch), dtype=torch.uint8, device=self.dev)
+        self.ws = torch.zeros(L.backward_workspace_bytes(self.net, max_batch), dtype=torch.uint8, device=self.dev)
+        self.ws_norm = torch.zeros(L.norm2_workspace_bytes(), dtype=torch.uint8, device=self.dev)
+        self.loss_dev = torch.zeros(1, dtype=torch.float64, device=self.dev)
+
+    def _repack(self, stream=None):
+        for l in range(3):
+            L.dnnmg_mlp_pack(self.dtype, self.hidden, l, self.theta[2 * l], self.Wp[l], stream=stream)
+
+    def step(self, X, T, n, stream=None):
+        """One AdamW step on a batch: X [n][192] (network dtype), T FP32 [n][81]."""
+        if n > self.max_batch:
+            raise ValueError("batch larger than max_batch")
+        L.dnnmg_patch_forward(self.net, n, X, LDX, self.Y, saved=self.saved, stream=stream)
+        L.dnnmg_mse_grad(self.Y, T, self.dY, n=n, stream=stream)
+        L.dnnmg_norm2_f64(self.Y, self.loss_dev, self.ws_norm, b=T, n=n * L.N_OUT, stream=stream)
+        L.dnnmg_patch_backward(self.net, self.theta[2], self.theta[4], n, X, LDX, self.saved, self.dY,
+                               [self.grad[0], self.grad[2], self.grad[4]],
+                               [self.grad[1], self.grad[3], self.grad[5]], self.ws, stream=stream)
+        self.t += 1
+        for p, m, v, g in zip(self.theta, self.m, self.v, self.grad):
+            L.dnnmg_adamw_step(p, m, v, g, self.lr, self.t, b1=self.betas[0], b2=self.betas[1], eps=self.eps,
+                               wd=self.wd, stream=stream)
+        self._repack(stream)
+
+    def loss(self, n):
+        """Patch loss of the last step (synchronises)."""
+        return float(self.loss_dev.item()) / n
+
+    def params(self, target_scale=1.0):
+        """Trained parameters as numpy [W1, b1, W2, b2, W3, b3]; the output
+        layer is multiplied by the target scale used in training."""
+        H = self.hidden
+        shapes = [(L.N_IN, H), (H,), (H, H), (H,), (H, L.N_OUT), (L.N_OUT,)]
+        out = [t.detach().cpu().numpy().reshape(s).astype(np.float64) for t, s in zip(self.theta, shapes)]
+        out[4] = out[4] * target_scale
+        out[5] = out[5] * target_scale
+        return out
+
+
+def gather_inputs(box, ns, xc_list, vprev_list, dtype=L.F32, shift=None, inv_scale=None, device="cuda:0"):
+    """Network inputs of many steps of one box through the library's
+    prolongation, residual and gather kernels: [steps * N_p][192]."""
+    dev = torch.device(device)
+    nf, nc, npch = L.box_sizes(box)
+    xc = torch.zeros(4 * nc, dtype=torch.float64, device=dev)
+    vp = torch.zeros(3 * nf, dtype=torch.float32, device=dev)
+    xt = torch.zeros(4 * nf, dtype=torch.float32, device=dev)
+    r = torch.zeros(4 * nf, dtype=torch.float32, device=dev)
+    ws = torch.zeros(L.residual_workspace_bytes(box), dtype=torch.uint8, device=dev)
+    X = torch.zeros(len(xc_list) * npch * LDX, dtype=_XT[dtype], device=dev)
+    sh = None if shift is None else torch.as_tensor(np.asarray(shift, np.float32)).to(dev)
+    sc = None if inv_scale is None else torch.as_tensor(np.asarray(inv_scale, np.float32)).to(dev)
+    for s, (c, v) in enumerate(zip(xc_list, vprev_list)):
+        xc.copy_(torch.as_tensor(np.asarray(c, np.float64).ravel()))
+        vp.copy_(torch.as_tensor(np.asarray(v, np.float32).ravel()))
+        L.dnnmg_prolong(box, xc, xt)
+        L.dnnmg_residual(box, ns, xt, vp, r, ws)
+        L.dnnmg_patch_gather(box, xt, r, X[s * npch * LDX:(s + 1) * npch * LDX], dtype, LDX, sh, sc)
+    return X
+
+
+def feature_stats(X32, n_rows):
+    """Per-feature shift and inverse scale from FP32 inputs [n][192] (host)."""
+    A = X32.view(n_rows, LDX)[:, : L.N_IN].double().cpu().numpy()
+    mu = A.mean(axis=0)
+    sd = A.std(axis=0)
+    inv = np.where(sd > 1e-12 * np.maximum(1.0, np.abs(mu)), 1.0 / np.where(sd > 0, sd, 1.0), 1.0)
+    return mu.astype(np.float32), inv.astype(np.float32)
