@@ -107,22 +107,129 @@ def time_kernel(fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
-def build_step(w, dtype, seed=0, indicator=False):
+def build_step(w, dtype, seed=0, indicator=False, theta=1.0):
     import dnnmg_synth as syn
     from paper_2307_14837_amd import stepper
 
     inp = syn.step_inputs(w, seed=seed)
     params = syn.mlp_params(165, w.hidden, 81, seed=seed)
-    st = stepper.CorrectionStep(w.box, w.ns, params, dtype=dtype, indicator=indicator)
+    st = stepper.CorrectionStep(w.box, w.ns, params, dtype=dtype, indicator=indicator, theta=theta)
     st.load(inp.xc, inp.vprev)
     return st, inp, params
 
 
-def run_variant(w, dtype, steps, warmup, indicator=False):
-    st, inp, params = build_step(w, dtype, indicator=indicator)
+def run_variant(w, dtype, steps, warmup, indicator=False, fallback="never"):
+    """indicator: the residual test runs every step; fallback "never"
+    (threshold infinite: test only) or "always" (threshold 0: the
+    fallback sweeps replace the correction every step)."""
+    theta = float("inf") if fallback == "never" else 0.0
+    st, inp, params = build_step(w, dtype, indicator=indicator, theta=theta)
     ms, wall = time_graph(st, steps, warmup)
-    return {"workload": w.name, "dtype": dtype, "indicator": indicator, "ms_per_step": ms,
+    return {"workload": w.name, "dtype": dtype, "indicator": indicator,
+            "fallback": fallback if indicator else None, "ms_per_step": ms,
             "patches_per_s": st.np / (ms * 1e-3), "fine_dof_per_s": 4 * st.nf / (ms * 1e-3)}
+
+
+def run_batched(dtype, steps, warmup):
+    """The 32 uneven periodic boxes in one plan: fused persistent network
+    stage, autotuned, whole step in one HIP graph."""
+    import dnnmg_synth as syn
+    from paper_2307_14837_amd import batched
+
+    boxes = syn.cfg3_boxes(seed=0)
+    ns = syn.NSParams(1e-3, 0.01)
+    params = syn.mlp_params(165, 256, 81, seed=0)
+    xcs, vps = [], []
+    for i, b in enumerate(boxes):
+        inp = syn.step_inputs(syn.Workload("b", b, ns, 256, dtype, "fourier"), seed=i)
+        xcs.append(inp.xc)
+        vps.append(inp.vprev)
+    bs = batched.BatchedStep(boxes, ns, params, dtype=dtype)
+    bs.load(xcs, vps)
+    ppw, grid = bs.autotune(reps=5)
+    ms, _ = time_graph(bs, steps, warmup)
+    npch, nf = bs.plan.n_patches, bs.plan.n_fine
+    return {"workload": "cfg3_32_periodic_boxes", "boxes": len(boxes), "patches": npch, "fine_nodes": nf,
+            "dtype": dtype, "fused_batched": True, "autotuned": {"patches_per_wave": ppw, "grid": grid},
+            "ms_per_step": ms, "patches_per_s": npch / (ms * 1e-3), "fine_dof_per_s": 4 * nf / (ms * 1e-3)}
+
+
+def run_per_box_plain(dtype, steps, warmup):
+    """The same 32 boxes as separate plain steps (unfused gather, FP32 network),
+    all 32 captured in one HIP graph."""
+    import torch
+
+    import dnnmg_synth as syn
+    from paper_2307_14837_amd import stepper
+
+    boxes = syn.cfg3_boxes(seed=0)
+    ns = syn.NSParams(1e-3, 0.01)
+    params = syn.mlp_params(165, 256, 81, seed=0)
+    sts = []
+    for i, b in enumerate(boxes):
+        inp = syn.step_inputs(syn.Workload("b", b, ns, 256, dtype, "fourier"), seed=i)
+        st = stepper.CorrectionStep(b, ns, params, dtype=dtype, fused=False)
+        st.load(inp.xc, inp.vprev)
+        sts.append(st)
+
+    class All:
+        def step(self):
+            for st in sts:
+                st.step()
+
+        def capture(self):
+            s = torch.cuda.Stream()
+            s.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(s):
+                self.step()
+            torch.cuda.current_stream().wait_stream(s)
+            torch.cuda.synchronize()
+            self.g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(self.g):
+                self.step()
+
+        def replay(self):
+            self.g.replay()
+
+    ms, _ = time_graph(All(), steps, warmup)
+    npch = sum(b.n_patches for b in boxes)
+    nf = sum(b.n_fine for b in boxes)
+    return {"workload": "cfg3_32_periodic_boxes", "boxes": len(boxes), "patches": npch, "dtype": dtype,
+            "fused_batched": False, "ms_per_step": ms, "patches_per_s": npch / (ms * 1e-3),
+            "fine_dof_per_s": 4 * nf / (ms * 1e-3)}
+
+
+def run_training(steps):
+    """One AdamW step of the patch network at the training batch size
+    (65,536 patches, width 256, BF16 compute, FP32 master weights)."""
+    import torch
+
+    import dnnmg_synth as syn
+    from paper_2307_14837_amd import train
+
+    n, H = 65536, 256
+    params = syn.mlp_params(165, H, 81, seed=0)
+    tr = train.PatchTrainer(params, dtype="bf16", max_batch=n)
+    rng = np.random.default_rng(0)
+    X = torch.zeros(n * 192, dtype=torch.bfloat16, device="cuda")
+    Xv = torch.as_tensor(rng.standard_normal((n, 165)).astype(np.float32))
+    X.view(n, 192)[:, :165] = Xv.to("cuda").to(torch.bfloat16)
+    T = torch.as_tensor(rng.standard_normal((n, 81)).astype(np.float32)).view(-1).to("cuda")
+    for _ in range(3):
+        tr.step(X, T, n)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        tr.step(X, T, n)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    from paper_2307_14837_amd import flops
+
+    fl = 3 * flops.mlp_flops_per_patch(H) * n  # forward + backward (about 2x forward)
+    return {"workload": "training_batch_65536_width256", "dtype": "bf16 forward, fp32 backward/master",
+            "ms_per_step": ms, "patches_per_s": n / (ms * 1e-3), "approx_tflops": fl / (ms * 1e-3) / 1e12}
 
 
 def accuracy(w, dtype):
@@ -181,9 +288,12 @@ def main():
     flop = flops.residual_flops_per_cell() * ncells
     achieved = flop / (res_ms * 1e-3) / 1e12
     traffic = traffic_from_profile("residual", w.name)
+    L.dnnmg_patch_gather(st.box, st.xt, st.r, st.X, st.xdtype, 192, st.shift, st.inv_scale)
     kernel_ms = {
         "residual": res_ms,
         "prolong": time_kernel(lambda: L.dnnmg_prolong(st.box, st.xc, st.xt), reps),
+        "gather_forward_fused": time_kernel(lambda: L.dnnmg_patch_gather_forward(st.box, st.net, st.xt, st.r, st.Y,
+                                                                                st.shift, st.inv_scale), reps),
         "gather": time_kernel(lambda: L.dnnmg_patch_gather(st.box, st.xt, st.r, st.X, st.xdtype, 192,
                                                           st.shift, st.inv_scale), reps),
         "forward": time_kernel(lambda: L.dnnmg_patch_forward(st.net, st.np, st.X, 192, st.Y), reps),
@@ -222,8 +332,13 @@ def main():
         print("[bench] variants: fp32 network, indicator, large FP8 channel", file=sys.stderr, flush=True)
         out["variants"] = [
             run_variant(w, "fp32", args.steps, args.warmup),
-            run_variant(w, "bf16", args.steps, args.warmup, indicator=True),
+            run_variant(w, "bf16", args.steps, args.warmup, indicator=True, fallback="never"),
+            run_variant(w, "bf16", args.steps, args.warmup, indicator=True, fallback="always"),
             run_variant(syn.cfg5(), "fp8", max(args.steps // 4, 10), max(args.warmup // 4, 3), indicator=True),
+            run_variant(syn.cfg5(), "bf16", max(args.steps // 4, 10), max(args.warmup // 4, 3)),
+            run_batched("bf16", max(args.steps // 4, 10), max(args.warmup // 4, 3)),
+            run_per_box_plain("fp32", max(args.steps // 4, 10), max(args.warmup // 4, 3)),
+            run_training(20),
         ]
         print("[bench] accuracy vs oracle", file=sys.stderr, flush=True)
         out["accuracy_rel_l2"] = {"bf16": accuracy(w, "bf16"), "fp32": accuracy(w, "fp32")}

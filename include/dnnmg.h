@@ -110,7 +110,9 @@ int dnnmg_patch_dofmap(const dnnmg_box *box, int32_t *map, uint8_t *mult, void *
 
 /* Prolongation of Algorithm 1: Q1 interpolation of the coarse solution onto
  * the fine mesh.  xc: FP64 [ncomp][n_coarse]; xf: FP32 [ncomp][n_fine];
- * 1 <= ncomp <= 4.  xc and xf must not overlap. */
+ * 1 <= ncomp <= 4.  The coarse values are rounded to FP32 and averaged axis
+ * by axis in FP32 (the patch interpolant of the residual kernel, so the LPS
+ * terms of a prolongated field vanish exactly).  xc and xf must not overlap. */
 int dnnmg_prolong(const dnnmg_box *box, int ncomp, const double *xc, float *xf, void *stream);
 
 /* Fine residual of Algorithm 1, r = F - A(x), for the Crank-Nicolson system
@@ -244,6 +246,51 @@ size_t dnnmg_fallback_workspace(const dnnmg_box *box);
 int dnnmg_fallback(const dnnmg_box *box, const dnnmg_ns *ns, const float *xt, const float *vprev,
                    const float *fmid, const double *norms, double theta, int sweeps, float omega,
                    float *xcorr, int *flag_out, void *ws, size_t ws_bytes, void *stream);
+
+/* Operators Q and N fused (eqs. defQ and NN): the network's first-layer
+ * inputs are built in registers from x~ (FP32 [4][n_fine]) and r (FP32
+ * [4][n_fine]) with the standardisation `feat`, so the gathered batch is
+ * never stored; Y FP32 [n_patches][81].  Same arithmetic as
+ * dnnmg_patch_gather followed by dnnmg_patch_forward (F32, BF16 and FP8
+ * networks of width 128, 256 or 512). */
+int dnnmg_patch_gather_forward(const dnnmg_box *box, const dnnmg_mlp *net, const float *xt, const float *r,
+                               const dnnmg_feat *feat, float *Y, void *stream);
+
+/* Batch of independent boxes (same dnnmg_ns and network, uneven sizes).
+ * Field arrays of a batch concatenate the boxes' SoA blocks in box order:
+ * box b's fine field with c components starts at c * (sum of n_fine of the
+ * boxes before b), coarse fields likewise, patch rows at the patch prefix.
+ * The plan holds the layout and launch geometry (host memory); its device
+ * descriptor table lives in the caller's workspace (dnnmg_plan_workspace
+ * bytes, kept alive with the plan) and is uploaded on `stream`. */
+typedef struct dnnmg_plan dnnmg_plan;
+size_t dnnmg_plan_workspace(const dnnmg_box *boxes, int nbox);
+int dnnmg_plan_create(const dnnmg_box *boxes, int nbox, const dnnmg_ns *ns, void *ws, size_t ws_bytes,
+                      dnnmg_plan **plan, void *stream);
+int dnnmg_plan_destroy(dnnmg_plan *plan);
+int dnnmg_plan_sizes(const dnnmg_plan *plan, int64_t *n_fine, int64_t *n_coarse, int64_t *n_patches);
+/* Tuned choice of the network stage: patches per wave (16 or 32) and the
+ * persistent grid size (0 = one block per 64-patch tile). */
+int dnnmg_plan_choice(const dnnmg_plan *plan, int *patches_per_wave, int *grid);
+
+/* One correction step (Algorithm 1 after the coarse solve) for every box of
+ * the plan in six launches, independent of the number of boxes:
+ * prolongation, residual (+ LPS corners), fused gather + network
+ * (persistent over the patch tiles of all boxes), extension giving the
+ * corrected iterate (v~ + d, p~), right-hand side, restriction (FP64).
+ * Buffers (batch layout): xc FP64 [4 comps], vprev FP32 [3], xt, r, xcorr,
+ * b FP32 [4], Y FP32 [patches][81], bc FP64 [4].  No forcing.  The step can
+ * be captured in a HIP graph. */
+int dnnmg_batch_step(const dnnmg_plan *plan, const dnnmg_mlp *net, const float *shift, const float *inv_scale,
+                     const double *xc, const float *vprev, float *xt, float *r, float *Y, float *xcorr,
+                     float *b, double *bc, void *stream);
+/* Autotuner (setup call, synchronises the stream): times the network stage
+ * on the batch's own inputs for every candidate (16 or 32 patches per wave;
+ * one block per tile or a persistent grid of 1, 2, 4 or 8 blocks per
+ * compute unit) with `reps` launches each, and keeps the fastest. */
+int dnnmg_plan_autotune(dnnmg_plan *plan, const dnnmg_mlp *net, const float *shift, const float *inv_scale,
+                        const double *xc, const float *vprev, float *xt, float *r, float *Y, float *xcorr,
+                        float *b, double *bc, int reps, void *stream);
 
 #ifdef __cplusplus
 }

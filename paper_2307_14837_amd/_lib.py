@@ -105,6 +105,15 @@ _sig("dnnmg_vanka_sweeps", [_P(Box), _P(NS), c_vp, c_vp, c_vp, ctypes.c_int, c_f
 _sig("dnnmg_fallback_workspace", [_P(Box)], c_sz)
 _sig("dnnmg_fallback", [_P(Box), _P(NS), c_vp, c_vp, c_vp, c_vp, ctypes.c_double, ctypes.c_int, c_f, c_vp,
                         c_vp, c_vp, c_sz, c_vp])
+_sig("dnnmg_patch_gather_forward", [_P(Box), _P(MLP), c_vp, c_vp, _P(Feat), c_vp, c_vp])
+_sig("dnnmg_plan_workspace", [c_vp, ctypes.c_int], c_sz)
+_sig("dnnmg_plan_create", [c_vp, ctypes.c_int, _P(NS), c_vp, c_sz, _P(c_vp), c_vp])
+_sig("dnnmg_plan_destroy", [c_vp])
+_sig("dnnmg_plan_sizes", [c_vp, _P(c_i64), _P(c_i64), _P(c_i64)])
+_sig("dnnmg_plan_choice", [c_vp, _P(ctypes.c_int), _P(ctypes.c_int)])
+_sig("dnnmg_batch_step", [c_vp, _P(MLP), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp])
+_sig("dnnmg_plan_autotune", [c_vp, _P(MLP), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
+                             ctypes.c_int, c_vp])
 _sig("dnnmg_adamw_step", [c_i64, c_vp, c_vp, c_vp, c_vp, c_f, c_f, c_f, c_f, c_f, c_i64, c_vp])
 
 EXPORTS = [
@@ -114,6 +123,8 @@ EXPORTS = [
     "dnnmg_patch_saved_bytes", "dnnmg_scatter_avg", "dnnmg_norm2_workspace", "dnnmg_norm2_f64",
     "dnnmg_mse_grad", "dnnmg_patch_backward_workspace", "dnnmg_patch_backward", "dnnmg_adamw_step",
     "dnnmg_vanka_workspace", "dnnmg_vanka_sweeps", "dnnmg_fallback_workspace", "dnnmg_fallback",
+    "dnnmg_patch_gather_forward", "dnnmg_plan_workspace", "dnnmg_plan_create", "dnnmg_plan_destroy",
+    "dnnmg_plan_sizes", "dnnmg_plan_choice", "dnnmg_batch_step", "dnnmg_plan_autotune",
 ]
 
 
@@ -334,3 +345,60 @@ def dnnmg_fallback(box, ns, xt, vprev, norms, xcorr, ws, theta=1.0, sweeps=4, om
                                float(theta), int(sweeps), float(omega), _ptr(xcorr, torch.float32, 4 * nf, "xcorr"),
                                _ptr(flag_out, torch.int32, 1, "flag_out"), _ptr(ws, None, None, "ws"),
                                ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def dnnmg_patch_gather_forward(box, net: MLP, xt, r, Y, shift=None, inv_scale=None, stream=None):
+    b = Box.of(box)
+    nf, _, npch = box_sizes(b)
+    feat = Feat(None if shift is None else _ptr(shift, torch.float32, 165, "shift"),
+                None if inv_scale is None else _ptr(inv_scale, torch.float32, 165, "inv_scale"))
+    _check(_lib.dnnmg_patch_gather_forward(ctypes.byref(b), ctypes.byref(net), _ptr(xt, torch.float32, 4 * nf, "xt"),
+                                           _ptr(r, torch.float32, 4 * nf, "r"), ctypes.byref(feat),
+                                           _ptr(Y, torch.float32, npch * N_OUT, "Y"), _stream(stream)))
+
+
+class Plan:
+    """Owner of a dnnmg_plan handle and its device workspace."""
+
+    def __init__(self, boxes, ns, device="cuda:0", stream=None):
+        self.boxes = (Box * len(boxes))(*[Box.of(b) for b in boxes])
+        self.nbox = len(boxes)
+        nbytes = int(_lib.dnnmg_plan_workspace(self.boxes, self.nbox))
+        if nbytes == 0:
+            raise DnnmgError(-2, "invalid box list")
+        self.ws = torch.zeros(nbytes, dtype=torch.uint8, device=device)
+        self.ns = NS.of(ns)
+        h = c_vp()
+        _check(_lib.dnnmg_plan_create(self.boxes, self.nbox, ctypes.byref(self.ns), _ptr(self.ws), nbytes,
+                                      ctypes.byref(h), _stream(stream)))
+        self.handle = h
+        nf, nc, npch = c_i64(), c_i64(), c_i64()
+        _check(_lib.dnnmg_plan_sizes(h, ctypes.byref(nf), ctypes.byref(nc), ctypes.byref(npch)))
+        self.n_fine, self.n_coarse, self.n_patches = nf.value, nc.value, npch.value
+
+    def choice(self):
+        a, b = ctypes.c_int(), ctypes.c_int()
+        _check(_lib.dnnmg_plan_choice(self.handle, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def _args(self, net, shift, inv_scale, bufs):
+        nf, nc, npch = self.n_fine, self.n_coarse, self.n_patches
+        return [ctypes.byref(net), _ptr(shift, torch.float32, 165, "shift"),
+                _ptr(inv_scale, torch.float32, 165, "inv_scale"),
+                _ptr(bufs["xc"], torch.float64, 4 * nc, "xc"), _ptr(bufs["vprev"], torch.float32, 3 * nf, "vprev"),
+                _ptr(bufs["xt"], torch.float32, 4 * nf, "xt"), _ptr(bufs["r"], torch.float32, 4 * nf, "r"),
+                _ptr(bufs["Y"], torch.float32, npch * N_OUT, "Y"), _ptr(bufs["xcorr"], torch.float32, 4 * nf, "xcorr"),
+                _ptr(bufs["b"], torch.float32, 4 * nf, "b"), _ptr(bufs["bc"], torch.float64, 4 * nc, "bc")]
+
+    def step(self, net, bufs, shift=None, inv_scale=None, stream=None):
+        _check(_lib.dnnmg_batch_step(self.handle, *self._args(net, shift, inv_scale, bufs), _stream(stream)))
+
+    def autotune(self, net, bufs, shift=None, inv_scale=None, reps=5, stream=None):
+        _check(_lib.dnnmg_plan_autotune(self.handle, *self._args(net, shift, inv_scale, bufs), int(reps),
+                                        _stream(stream)))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            _lib.dnnmg_plan_destroy(h)
+            self.handle = None

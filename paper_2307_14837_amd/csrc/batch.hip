@@ -1,0 +1,249 @@
+// Batched correction step over many independent boxes of uneven size, with a
+// launch plan and an autotuner.  The per-box field blocks are concatenated
+// (BoxDesc); one step is six launches whatever the number of boxes:
+//   prolongation, residual (+ LPS corners), fused gather + network
+//   (persistent: blocks walk the patch tiles of all boxes), extension
+//   (v~ + d), right-hand side, restriction.
+// The plan keeps the layout, the launch geometry and the tuned choices of
+// the network stage (patches per wave, persistent grid size).
+#include <vector>
+
+#include "common.hpp"
+#include "mlp.hpp"
+
+namespace dnnmg {
+
+ResParams make_params(const Mesh &m, const dnnmg_ns *ns);
+void residual_tiles(const Mesh &m, int rt[3]);
+void residual_batch_launch(const BoxDesc *D, int nbox, int64_t ntiles, int64_t ncoarse_blocks, const float *x,
+                           const float *vp, float *r, float *aux, hipStream_t s);
+void rhs_batch_launch(const BoxDesc *D, int nbox, int64_t ntiles, const float *v, float *b, hipStream_t s);
+void prolong_batch_launch(const BoxDesc *D, int nbox, int64_t nblk, const double *xc, float *xf, hipStream_t s);
+void restrict_batch_launch(const BoxDesc *D, int nbox, int64_t nblk, const float *bf, double *bc, hipStream_t s);
+void scatter_batch_launch(const BoxDesc *D, int nbox, int64_t nblk, const float *Y, const float *vbase, float *xc,
+                          hipStream_t s);
+int gather_fwd_launch(const dnnmg_mlp *net, int np, const BoxDesc *D, int nbox, const BoxDesc &one,
+                      int64_t ntiles, int grid, const float *xt, const float *r, const float *shift,
+                      const float *inv, float *Y, hipStream_t s);
+
+} // namespace dnnmg
+
+using namespace dnnmg;
+
+struct dnnmg_plan {
+    int nbox;
+    dnnmg_ns ns;
+    std::vector<BoxDesc> desc;
+    BoxDesc *d_desc;   // in the caller's workspace
+    float *aux;        // LPS corner workspace (32 floats per patch)
+    int64_t n_fine, n_coarse, n_patches;
+    int64_t blk_fine, blk_coarse, tiles, ptiles;
+    int np;            // tuned: patches per wave / 16 of the network stage
+    int grid;          // tuned: persistent grid of the network stage (0 = one block per tile)
+};
+
+static size_t up256(size_t b) { return (b + 255) / 256 * 256; }
+
+static int layout(dnnmg_plan *p, const dnnmg_box *boxes, int nbox) {
+    p->desc.resize(nbox);
+    int64_t of = 0, oc = 0, op = 0, bf = 0, bc = 0, bt = 0, bp = 0;
+    for (int i = 0; i < nbox; ++i) {
+        BoxDesc &d = p->desc[i];
+        int rc = make_mesh(&boxes[i], &d.m);
+        if (rc) return rc;
+        d.rp = make_params(d.m, &p->ns);
+        int rt[3];
+        residual_tiles(d.m, rt);
+        for (int a = 0; a < 3; ++a) d.rtiles[a] = rt[a];
+        d.off_fine = of;
+        d.off_coarse = oc;
+        d.off_patch = op;
+        d.blk_fine = bf;
+        d.blk_coarse = bc;
+        d.blk_tile = bt;
+        d.blk_ptile = bp;
+        of += d.m.n_fine;
+        oc += d.m.n_coarse;
+        op += d.m.n_patches;
+        bf += (d.m.n_fine + 255) / 256;
+        bc += (d.m.n_coarse + 255) / 256;
+        bt += (int64_t)rt[0] * rt[1] * rt[2];
+        bp += (d.m.n_patches + 64 * p->np - 1) / (64 * p->np);
+    }
+    p->n_fine = of;
+    p->n_coarse = oc;
+    p->n_patches = op;
+    p->blk_fine = bf;
+    p->blk_coarse = bc;
+    p->tiles = bt;
+    p->ptiles = bp;
+    return DNNMG_OK;
+}
+
+static int upload(dnnmg_plan *p, hipStream_t s) {
+    return hip_check(hipMemcpyAsync(p->d_desc, p->desc.data(), sizeof(BoxDesc) * p->nbox, hipMemcpyHostToDevice, s),
+                     "plan upload");
+}
+
+extern "C" size_t dnnmg_plan_workspace(const dnnmg_box *boxes, int nbox) {
+    if (!boxes || nbox < 1) return 0;
+    int64_t np = 0;
+    for (int i = 0; i < nbox; ++i) {
+        Mesh m;
+        if (make_mesh(&boxes[i], &m)) return 0;
+        np += m.n_patches;
+    }
+    return up256(sizeof(BoxDesc) * nbox) + up256(sizeof(float) * 32 * np);
+}
+
+extern "C" int dnnmg_plan_create(const dnnmg_box *boxes, int nbox, const dnnmg_ns *ns, void *ws, size_t ws_bytes,
+                                 dnnmg_plan **out, void *stream) {
+    if (!boxes || nbox < 1 || !ns || !ws || !out) return fail(DNNMG_ERR_ARG, "dnnmg_plan_create: bad argument");
+    if (!(ns->dt > 0.0)) return fail(DNNMG_ERR_ARG, "dnnmg_plan_create: dt must be > 0");
+    size_t need = dnnmg_plan_workspace(boxes, nbox);
+    if (need == 0) return fail(DNNMG_ERR_SHAPE, "dnnmg_plan_create: invalid box");
+    if (ws_bytes < need) return fail(DNNMG_ERR_SHAPE, "dnnmg_plan_create: workspace %zu < %zu bytes", ws_bytes, need);
+    dnnmg_plan *p = new dnnmg_plan();
+    p->nbox = nbox;
+    p->ns = *ns;
+    p->np = 1;
+    p->grid = 0;
+    int rc = layout(p, boxes, nbox);
+    if (rc) {
+        delete p;
+        return rc;
+    }
+    p->d_desc = (BoxDesc *)ws;
+    p->aux = (float *)((char *)ws + up256(sizeof(BoxDesc) * nbox));
+    if ((rc = upload(p, (hipStream_t)stream))) {
+        delete p;
+        return rc;
+    }
+    *out = p;
+    return DNNMG_OK;
+}
+
+extern "C" int dnnmg_plan_destroy(dnnmg_plan *p) {
+    delete p;
+    return DNNMG_OK;
+}
+
+extern "C" int dnnmg_plan_sizes(const dnnmg_plan *p, int64_t *n_fine, int64_t *n_coarse, int64_t *n_patches) {
+    if (!p) return fail(DNNMG_ERR_ARG, "dnnmg_plan_sizes: plan is NULL");
+    if (n_fine) *n_fine = p->n_fine;
+    if (n_coarse) *n_coarse = p->n_coarse;
+    if (n_patches) *n_patches = p->n_patches;
+    return DNNMG_OK;
+}
+
+extern "C" int dnnmg_plan_choice(const dnnmg_plan *p, int *patches_per_wave, int *grid) {
+    if (!p) return fail(DNNMG_ERR_ARG, "dnnmg_plan_choice: plan is NULL");
+    if (patches_per_wave) *patches_per_wave = 16 * p->np;
+    if (grid) *grid = p->grid;
+    return DNNMG_OK;
+}
+
+static int step_impl(const dnnmg_plan *p, const dnnmg_mlp *net, const float *shift, const float *inv,
+                     const double *xc, const float *vprev, float *xt, float *r, float *Y, float *xcorr, float *b,
+                     double *bc, hipStream_t s) {
+    const BoxDesc *D = p->d_desc;
+    prolong_batch_launch(D, p->nbox, p->blk_coarse, xc, xt, s);
+    residual_batch_launch(D, p->nbox, p->tiles, p->blk_coarse, xt, vprev, r, p->aux, s);
+    BoxDesc none{};
+    int rc = gather_fwd_launch(net, p->np, D, p->nbox, none, p->ptiles, p->grid, xt, r, shift, inv, Y, s);
+    if (rc) return rc;
+    scatter_batch_launch(D, p->nbox, p->blk_fine, Y, xt, xcorr, s);
+    rhs_batch_launch(D, p->nbox, p->tiles, xcorr, b, s);
+    restrict_batch_launch(D, p->nbox, p->blk_coarse, b, bc, s);
+    return hip_check(hipGetLastError(), "dnnmg_batch_step launch");
+}
+
+static int check_step(const dnnmg_plan *p, const dnnmg_mlp *net, const double *xc, const float *vprev, float *xt,
+                      float *r, float *Y, float *xcorr, float *b, double *bc) {
+    if (!p) return fail(DNNMG_ERR_ARG, "batch step: plan is NULL");
+    int rc = check_net(net);
+    if (rc) return rc;
+    if (!xc || !vprev || !xt || !r || !Y || !xcorr || !b || !bc)
+        return fail(DNNMG_ERR_ARG, "batch step: NULL buffer");
+    return DNNMG_OK;
+}
+
+extern "C" int dnnmg_batch_step(const dnnmg_plan *p, const dnnmg_mlp *net, const float *shift,
+                                const float *inv_scale, const double *xc, const float *vprev, float *xt, float *r,
+                                float *Y, float *xcorr, float *b, double *bc, void *stream) {
+    int rc = check_step(p, net, xc, vprev, xt, r, Y, xcorr, b, bc);
+    if (rc) return rc;
+    return step_impl(p, net, shift, inv_scale, xc, vprev, xt, r, Y, xcorr, b, bc, (hipStream_t)stream);
+}
+
+extern "C" int dnnmg_plan_autotune(dnnmg_plan *p, const dnnmg_mlp *net, const float *shift, const float *inv_scale,
+                                   const double *xc, const float *vprev, float *xt, float *r, float *Y, float *xcorr,
+                                   float *b, double *bc, int reps, void *stream) {
+    int rc = check_step(p, net, xc, vprev, xt, r, Y, xcorr, b, bc);
+    if (rc) return rc;
+    if (reps < 1) reps = 1;
+    hipStream_t s = (hipStream_t)stream;
+    // inputs of the network stage
+    prolong_batch_launch(p->d_desc, p->nbox, p->blk_coarse, xc, xt, s);
+    residual_batch_launch(p->d_desc, p->nbox, p->tiles, p->blk_coarse, xt, vprev, r, p->aux, s);
+    int dev = 0, ncu = 256;
+    if ((rc = hip_check(hipGetDevice(&dev), "autotune device"))) return rc;
+    if ((rc = hip_check(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev), "autotune CU count")))
+        return rc;
+    hipEvent_t e0, e1;
+    if ((rc = hip_check(hipEventCreate(&e0), "autotune event"))) return rc;
+    if ((rc = hip_check(hipEventCreate(&e1), "autotune event"))) {
+        (void)hipEventDestroy(e0);
+        return rc;
+    }
+    float best = 1e30f;
+    int best_np = p->np, best_grid = p->grid;
+    const int nps[2] = {1, 2};
+    for (int npi = 0; npi < 2 && !rc; ++npi) {
+        int np = nps[npi];
+        // NP = 2 is built for BF16 (H <= 256) and FP8 networks
+        bool has2 = (net->dtype == DNNMG_BF16 && net->hidden <= 256) || net->dtype == DNNMG_FP8_E4M3;
+        if (np == 2 && !has2) continue;
+        p->np = np;
+        // recompute the patch-tile prefix for this tile size and upload
+        int64_t bp = 0;
+        for (auto &d : p->desc) {
+            d.blk_ptile = bp;
+            bp += (d.m.n_patches + 64 * np - 1) / (64 * np);
+        }
+        p->ptiles = bp;
+        if ((rc = upload(p, s))) break;
+        const int grids[5] = {0, ncu, 2 * ncu, 4 * ncu, 8 * ncu};
+        for (int gi = 0; gi < 5 && !rc; ++gi) {
+            int grid = grids[gi];
+            if (grid > p->ptiles) continue;
+            BoxDesc none{};
+            gather_fwd_launch(net, np, p->d_desc, p->nbox, none, p->ptiles, grid, xt, r, shift, inv_scale, Y, s);
+            if ((rc = hip_check(hipEventRecord(e0, s), "autotune event record"))) break;
+            for (int k = 0; k < reps; ++k)
+                gather_fwd_launch(net, np, p->d_desc, p->nbox, none, p->ptiles, grid, xt, r, shift, inv_scale, Y, s);
+            if ((rc = hip_check(hipEventRecord(e1, s), "autotune event record"))) break;
+            if ((rc = hip_check(hipEventSynchronize(e1), "autotune launch"))) break;
+            float ms = 0.f;
+            if ((rc = hip_check(hipEventElapsedTime(&ms, e0, e1), "autotune timing"))) break;
+            if (ms < best) {
+                best = ms;
+                best_np = np;
+                best_grid = grid;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p->np = best_np;
+    p->grid = best_grid;
+    int64_t bp = 0;
+    for (auto &d : p->desc) {
+        d.blk_ptile = bp;
+        bp += (d.m.n_patches + 64 * p->np - 1) / (64 * p->np);
+    }
+    p->ptiles = bp;
+    if (!rc) rc = upload(p, s);
+    if (!rc) rc = hip_check(hipStreamSynchronize(s), "autotune sync");
+    return rc;
+}

@@ -71,4 +71,36 @@ inline unsigned blocks_for(int64_t n, int threads) {
     return (unsigned)((n + threads - 1) / threads);
 }
 
+// Crank-Nicolson / stabilisation constants of one box, in kernel form.
+struct ResParams {
+    float inv_dt, half_nu, alpha0, delta0, nu;
+    float ih[3];
+    float hT, wq; // cell diameter, quadrature weight |T| / 8
+};
+
+// One box of a batch of independent simulations.  Field arrays of a batch
+// are the concatenation of the boxes' SoA blocks: box b's fine field with c
+// components starts at c * off_fine, its coarse field at c * off_coarse, its
+// patch rows at off_patch.  blk_* are the first block index of the box in
+// each batched launch (prefix sums over the boxes).
+struct BoxDesc {
+    Mesh m;
+    ResParams rp;
+    int64_t off_fine, off_coarse, off_patch;
+    int64_t blk_fine, blk_coarse, blk_tile, blk_ptile;
+    int32_t rtiles[3]; // residual tile grid of the box
+};
+
+// Box holding block `blk` of a batched launch: the last b with first[b] <= blk.
+template <typename F>
+__device__ __forceinline__ int find_box(int nbox, int64_t blk, F first) {
+    int lo = 0, hi = nbox - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (first(mid) <= blk) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 } // namespace dnnmg

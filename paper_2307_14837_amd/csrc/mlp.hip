@@ -228,6 +228,126 @@ __global__ void __launch_bounds__(256)
                                                    base, n, Y, nullptr, 0, sbytes);
 }
 
+// ---------------------------------------------- fused gather + network ----
+// Layer-1 fragments built directly from the node fields (operator Q of
+// eq. (defQ) with the standardisation), so the gathered batch never goes
+// through HBM.  Column col of the input row of patch (I,J,K): field
+// col / 27 of [u, v, w, r_u, r_v, r_w] at local node col % 27; 162..164 the
+// coarse cell sizes; zero padding to 192.
+__device__ __forceinline__ float input_col(const Mesh &m, int I, int J, int K, int col,
+                                           const float *__restrict__ xt, const float *__restrict__ r,
+                                           const float *__restrict__ shift, const float *__restrict__ inv) {
+    if (col >= N_IN) return 0.0f;
+    float v;
+    if (col < 162) {
+        int c = col / 27, iota = col - 27 * c;
+        int a = iota % 3, b = (iota / 3) % 3, cc = iota / 9;
+        int i = wrap(2 * I + a, m.nf[0], m.per[0]);
+        int j = wrap(2 * J + b, m.nf[1], m.per[1]);
+        int k = wrap(2 * K + cc, m.nf[2], m.per[2]);
+        int64_t node = i + (int64_t)m.nf[0] * (j + (int64_t)m.nf[1] * k);
+        v = c < 3 ? xt[c * m.n_fine + node] : r[(c - 3) * m.n_fine + node];
+    } else {
+        v = m.H[col - 162];
+    }
+    if (shift) v -= shift[col];
+    if (inv) v *= inv[col];
+    return v;
+}
+
+// Persistent: blocks walk the 64-patch tiles of all boxes (tile -> box by
+// the prefix sums blk_ptile); D == nullptr means the single box `one`.
+template <int DT, int H, int NP>
+__global__ void __launch_bounds__(256)
+    k_mlp_gather_fwd(const BoxDesc *__restrict__ D, int nbox, BoxDesc one, int64_t ntiles,
+                     const float *__restrict__ xt_all, const float *__restrict__ r_all,
+                     const float *__restrict__ shift, const float *__restrict__ inv,
+                     const void *__restrict__ W0, const void *__restrict__ W1, const void *__restrict__ W2,
+                     const float *__restrict__ b0, const float *__restrict__ b1, const float *__restrict__ b2,
+                     float *__restrict__ Y_all, float s1, float q1inv) {
+    constexpr int K1 = layer_kind(DT, 0), K2 = layer_kind(DT, 1), K3 = layer_kind(DT, 2);
+    constexpr int E1 = kind_E(K1);
+    constexpr int NCH0 = IN_PAD / (4 * E1);
+    constexpr int NCH1 = H / (4 * kind_E(K2));
+    constexpr int NCH2 = H / (4 * kind_E(K3));
+    using F1 = typename Frag<K1>::T;
+    using F2 = typename Frag<K2>::T;
+    using F3 = typename Frag<K3>::T;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, p = lane & 15;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int b = D ? find_box(nbox, tile, [&](int i) { return D[i].blk_ptile; }) : 0;
+        const BoxDesc &d = D ? D[b] : one;
+        const Mesh m = d.m;
+        const float *xt = xt_all + 4 * d.off_fine;
+        const float *r = r_all + 4 * d.off_fine;
+        float *Y = Y_all + 81 * d.off_patch;
+        const int64_t n = m.n_patches;
+        const int64_t base = (tile - d.blk_ptile) * 64 * NP + 16 * NP * wave;
+        if (base >= n) continue; // wave-uniform; no block-wide barrier below
+        F1 Bx[NP][NCH0];
+#pragma unroll
+        for (int t = 0; t < NP; ++t) {
+            const int64_t row = base + 16 * t + p;
+            int I = 0, J = 0, K = 0;
+            if (row < n) {
+                uint32_t JK = fdiv((uint32_t)row, m.px);
+                I = (int)((uint32_t)row - JK * m.n[0]);
+                K = (int)fdiv(JK, m.py);
+                J = (int)(JK - (uint32_t)K * m.n[1]);
+            }
+#pragma unroll
+            for (int kc = 0; kc < NCH0; ++kc) {
+                if constexpr (K1 == KF32) {
+                    Bx[t][kc] = row < n ? input_col(m, I, J, K, kc * 4 + g, xt, r, shift, inv) : 0.0f;
+                } else {
+                    float v[8];
+#pragma unroll
+                    for (int e = 0; e < 8; ++e)
+                        v[e] = row < n ? input_col(m, I, J, K, kc * 32 + g * 8 + e, xt, r, shift, inv) : 0.0f;
+                    F1 f;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) f[q] = pack_bf16x2(v[2 * q], v[2 * q + 1]);
+                    Bx[t][kc] = f;
+                }
+            }
+        }
+        F2 Ba[NP][NCH1];
+        layer<K1, K2, H / 16, NCH0, NP, false, H>((const F1 *)W0, b0, Bx, Ba, 1.0f, q1inv, lane, g, p, base, n,
+                                                  Y, nullptr, 0, 2);
+        F3 Bb[NP][NCH2];
+        layer<K2, K3, H / 16, NCH1, NP, false, H>((const F2 *)W1, b1, Ba, Bb, s1, 1.0f, lane, g, p, base, n, Y,
+                                                  nullptr, 0, 2);
+        F3 dummy[NP][H / (4 * kind_E(K3))];
+        layer<K3, K3, OUT_PAD / 16, NCH2, NP, true, H>((const F3 *)W2, b2, Bb, dummy, 1.0f, 1.0f, lane, g, p,
+                                                       base, n, Y, nullptr, 0, 2);
+    }
+}
+
+int gather_fwd_launch(const dnnmg_mlp *net, int np, const BoxDesc *D, int nbox, const BoxDesc &one,
+                      int64_t ntiles, int grid, const float *xt, const float *r, const float *shift,
+                      const float *inv, float *Y, hipStream_t s) {
+    float s1 = 1.f, q1 = 1.f;
+    if (net->dtype == DNNMG_FP8_E4M3) {
+        s1 = net->w_scale[1] * net->a_scale[1];
+        q1 = 1.0f / net->a_scale[1];
+    }
+    if (grid <= 0 || grid > ntiles) grid = (int)ntiles;
+#define GF(DT, HH, NPV)                                                                                  \
+    if (net->dtype == DT && net->hidden == HH && np == NPV) {                                           \
+        k_mlp_gather_fwd<DT, HH, NPV><<<grid, 256, 0, s>>>(D, nbox, one, ntiles, xt, r, shift, inv,      \
+                                                           net->W[0], net->W[1], net->W[2], net->b[0],  \
+                                                           net->b[1], net->b[2], Y, s1, q1);             \
+        return hip_check(hipGetLastError(), "fused gather+forward launch");                             \
+    }
+    GF(DNNMG_F32, 128, 1) GF(DNNMG_F32, 256, 1)
+    GF(DNNMG_BF16, 128, 1) GF(DNNMG_BF16, 256, 1) GF(DNNMG_BF16, 512, 1)
+    GF(DNNMG_BF16, 128, 2) GF(DNNMG_BF16, 256, 2)
+    GF(DNNMG_FP8_E4M3, 256, 1) GF(DNNMG_FP8_E4M3, 512, 1) GF(DNNMG_FP8_E4M3, 256, 2) GF(DNNMG_FP8_E4M3, 512, 2)
+#undef GF
+    return fail(DNNMG_ERR_UNSUPPORTED, "fused gather+forward: dtype %d width %d", net->dtype, net->hidden);
+}
+
 template <int DT, int H, int NP>
 static int launch_fwd(const dnnmg_mlp *net, int64_t n, const void *X, int64_t ldx, float *Y,
                       void *saved, hipStream_t s) {
@@ -339,4 +459,17 @@ extern "C" int dnnmg_patch_forward(const dnnmg_mlp *net, int64_t n, const void *
     FWD(DNNMG_FP8_E4M3, 128, 2) FWD(DNNMG_FP8_E4M3, 256, 2) FWD(DNNMG_FP8_E4M3, 512, 2)
 #undef FWD
     return fail(DNNMG_ERR_UNSUPPORTED, "dnnmg_patch_forward: dtype %d width %d", net->dtype, H);
+}
+
+extern "C" int dnnmg_patch_gather_forward(const dnnmg_box *box, const dnnmg_mlp *net, const float *xt,
+                                          const float *r, const dnnmg_feat *feat, float *Y, void *stream) {
+    int rc = check_net(net);
+    if (rc) return rc;
+    BoxDesc one{};
+    if ((rc = make_mesh(box, &one.m))) return rc;
+    if (!xt || !r || !Y) return fail(DNNMG_ERR_ARG, "dnnmg_patch_gather_forward: NULL pointer");
+    const float *sh = feat ? feat->shift : nullptr;
+    const float *sc = feat ? feat->inv_scale : nullptr;
+    int64_t ntiles = (one.m.n_patches + 63) / 64;
+    return gather_fwd_launch(net, 1, nullptr, 1, one, ntiles, 0, xt, r, sh, sc, Y, (hipStream_t)stream);
 }

@@ -204,32 +204,35 @@ struct ResTile {
     static constexpr int SX = TX + 3, SY = TY + 3, SZ = TZ + 3, SN = SX * SY * SZ;
     static constexpr int VX = TX + 2, VY = TY + 2, VZ = TZ + 2, VN = VX * VY * VZ;
     static constexpr int NPX = TX / 2, NPY = TY / 2, NPZ = TZ / 2, NP = NPX * NPY * NPZ;
-    static constexpr int NT = 384;
+    static constexpr int NT = 256;
     static constexpr int ROUNDS = (NCELL + NT - 1) / NT;
     static constexpr int NF_STAGE = MODE == MODE_RES ? 4 : 0; // x, p on the wide range
     static constexpr int NF_V = 3;                            // vp (res) or v (rhs)
     static constexpr int NACC = MODE == MODE_RES ? 4 : 3;
+    // Cells are assigned to threads sorted by colour (parity class), so a
+    // wave holds at most two colours and the colour phases of the LDS
+    // accumulation cost each wave little more than one pass.  Colour bit pa
+    // of axis a selects the cells whose global index has parity pa; the tile
+    // origin is even and the cell layer starts at origin - 1.
+    static constexpr int cnt(int E, int p) { return p ? (E + 1) / 2 : E / 2; }
+    static constexpr int csize(int c) { return cnt(EX, c & 1) * cnt(EY, (c >> 1) & 1) * cnt(EZ, c >> 2); }
+    static constexpr int cstart(int c) { return c == 0 ? 0 : cstart(c - 1) + csize(c - 1); }
 };
 
-struct ResParams {
-    float inv_dt, half_nu, alpha0, delta0, nu;
-    float ih[3];
-    float hT, wq; // cell diameter, quadrature weight |T| / 8
-};
-
+// One tile (bx, by, bz) of owned nodes of one box.
 template <int MODE>
-__global__ void __launch_bounds__(ResTile<MODE>::NT)
-    k_residual(Mesh m, ResParams P, const float *__restrict__ x, const float *__restrict__ vp,
-               const float *__restrict__ fmid, float *__restrict__ out, float *__restrict__ aux,
-               const int *__restrict__ flag) {
+__device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P, int bx, int by, int bz,
+                                              const float *__restrict__ x, const float *__restrict__ vp,
+                                              const float *__restrict__ fmid, float *__restrict__ out,
+                                              float *__restrict__ aux) {
     using T = ResTile<MODE>;
-    if (flag && *flag == 0) return; // predicated launch (fallback path not taken)
     __shared__ float sX[T::NF_STAGE > 0 ? T::NF_STAGE * T::SN : 1];
     __shared__ float sV[T::NF_V * T::VN];
+    __shared__ float sF[3 * T::VN]; // forcing, when given
     __shared__ float sAcc[T::NACC * T::VN];
     __shared__ float sAux[MODE == MODE_RES ? T::NP * 32 : 1];
 
-    const int x0 = blockIdx.x * T::TX, y0 = blockIdx.y * T::TY, z0 = blockIdx.z * T::TZ;
+    const int x0 = bx * T::TX, y0 = by * T::TY, z0 = bz * T::TZ;
     const int tid = threadIdx.x;
     const int64_t nfn = m.n_fine;
 
@@ -264,10 +267,9 @@ __global__ void __launch_bounds__(ResTile<MODE>::NT)
                 for (int f = 0; f < 4; ++f) sX[f * T::SN + s] = tmp[it][f];
         }
     }
-    {
+    auto stage_v = [&](const float *__restrict__ src, float *dst, bool zero_acc) {
         constexpr int IT = (T::VN + T::NT - 1) / T::NT;
         float tmp[IT][3];
-        const float *src = MODE == MODE_RES ? vp : x;
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
             int s = tid + it * T::NT;
@@ -283,100 +285,102 @@ __global__ void __launch_bounds__(ResTile<MODE>::NT)
             int s = tid + it * T::NT;
             if (s < T::VN) {
 #pragma unroll
-                for (int f = 0; f < 3; ++f) sV[f * T::VN + s] = tmp[it][f];
+                for (int f = 0; f < 3; ++f) dst[f * T::VN + s] = tmp[it][f];
+                if (zero_acc)
 #pragma unroll
-                for (int f = 0; f < T::NACC; ++f) sAcc[f * T::VN + s] = 0.0f;
+                    for (int f = 0; f < T::NACC; ++f) sAcc[f * T::VN + s] = 0.0f;
             }
         }
-    }
+    };
+    stage_v(MODE == MODE_RES ? vp : x, sV, true);
+    if (fmid) stage_v(fmid, sF, false);
     if (MODE == MODE_RES)
         for (int s = tid; s < T::NP * 32; s += T::NT) sAux[s] = 0.0f;
     __syncthreads();
 
     const int ncx = 2 * m.n[0], ncy = 2 * m.n[1], ncz = 2 * m.n[2]; // fine cells per axis
+    const float ih0 = P.ih[0], ih1 = P.ih[1], ih2 = P.ih[2];
 
-    for (int round = 0; round < T::ROUNDS; ++round) {
-        int e = tid + round * T::NT;
-        bool live = e < T::NCELL;
-        int ex = 0, ey = 0, ez = 0;
-        if (live) {
-            ex = e % T::EX;
-            ey = (e / T::EX) % T::EY;
-            ez = e / (T::EX * T::EY);
+    // Cell of slot e (colour-sorted), its global lower corner and existence.
+    struct Cell {
+        int ex, ey, ez, gx, gy, gz, colour, ox, oy, oz;
+        bool live;
+    };
+    auto cell_of = [&](int e) {
+        Cell C;
+        C.live = e < T::NCELL;
+        C.ex = C.ey = C.ez = 0;
+        if (C.live) {
+            int c = 0;
+#pragma unroll
+            for (int q = 1; q < 8; ++q)
+                if (e >= T::cstart(q)) c = q;
+            int px = c & 1, py = (c >> 1) & 1, pz = c >> 2;
+            int k = e - T::cstart(c);
+            int cx = T::cnt(T::EX, px), cy = T::cnt(T::EY, py);
+            C.ex = 2 * (k % cx) + (1 - px);
+            C.ey = 2 * ((k / cx) % cy) + (1 - py);
+            C.ez = 2 * (k / (cx * cy)) + (1 - pz);
         }
-        // global cell (lower corner node) and its existence
-        int gx = x0 - 1 + ex, gy = y0 - 1 + ey, gz = z0 - 1 + ez;
-        if (live) {
-            if (m.per[0]) gx = wrap(gx, ncx, 1); else live &= gx >= 0 && gx < ncx;
-            if (m.per[1]) gy = wrap(gy, ncy, 1); else live &= gy >= 0 && gy < ncy;
-            if (m.per[2]) gz = wrap(gz, ncz, 1); else live &= gz >= 0 && gz < ncz;
+        C.gx = x0 - 1 + C.ex;
+        C.gy = y0 - 1 + C.ey;
+        C.gz = z0 - 1 + C.ez;
+        if (C.live) {
+            if (m.per[0]) C.gx = wrap(C.gx, ncx, 1); else C.live &= C.gx >= 0 && C.gx < ncx;
+            if (m.per[1]) C.gy = wrap(C.gy, ncy, 1); else C.live &= C.gy >= 0 && C.gy < ncy;
+            if (m.per[2]) C.gz = wrap(C.gz, ncz, 1); else C.live &= C.gz >= 0 && C.gz < ncz;
         }
-        const int colour = ((ex + 1) & 1) | (((ey + 1) & 1) << 1) | (((ez + 1) & 1) << 2);
         // offset of the cell inside its patch (the tile origin is even)
-        const int ox = (ex + 1) & 1, oy = (ey + 1) & 1, oz = (ez + 1) & 1;
+        C.ox = (C.ex + 1) & 1;
+        C.oy = (C.ey + 1) & 1;
+        C.oz = (C.ez + 1) & 1;
+        C.colour = C.ox | (C.oy << 1) | (C.oz << 2);
+        return C;
+    };
+    // Node slots of vertex j = a + 2b + 4c: base + offset, so the LDS
+    // accesses take immediate offsets.
+    auto voff = [](int j) { return (j & 1) + T::VX * (((j >> 1) & 1) + T::VY * (j >> 2)); };
+    auto xoff = [](int j) { return (j & 1) + T::SX * (((j >> 1) & 1) + T::SY * (j >> 2)); };
+    auto coff = [](int j) { return 2 * ((j & 1) + T::SX * (((j >> 1) & 1) + T::SY * (j >> 2))); };
 
+    // ---- pass A: Galerkin terms of every cell (and the LPS test) ----
+    bool need[T::ROUNDS];
+#pragma unroll
+    for (int round = 0; round < T::ROUNDS; ++round) {
+        const Cell C = cell_of(tid + round * T::NT);
+        need[round] = false;
         float acc[T::NACC][8];
-        float cor[4][8];
 #pragma unroll
         for (int f = 0; f < T::NACC; ++f)
 #pragma unroll
             for (int j = 0; j < 8; ++j) acc[f][j] = 0.0f;
-#pragma unroll
-        for (int f = 0; f < 4; ++f)
-#pragma unroll
-            for (int j = 0; j < 8; ++j) cor[f][j] = 0.0f;
 
-        if (live) {
-            // vertex slots in the staged arrays
-            int vs[8], xs[8], cs[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                int a = j & 1, b = (j >> 1) & 1, c = j >> 2;
-                vs[j] = (ex + a) + T::VX * ((ey + b) + T::VY * (ez + c));
-                xs[j] = (ex + 1 + a) + T::SX * ((ey + 1 + b) + T::SY * (ez + 1 + c));
-                // patch corner j: staged coordinate of the patch origin + 2 (a,b,c)
-                int px = ex + 1 - ox, py = ey + 1 - oy, pz = ez + 1 - oz;
-                cs[j] = (px + 2 * a) + T::SX * ((py + 2 * b) + T::SY * (pz + 2 * c));
-            }
-            const float ih0 = P.ih[0], ih1 = P.ih[1], ih2 = P.ih[2];
-
-            if (MODE == MODE_RHS) {
+        if (C.live) {
+            const int vb = C.ex + T::VX * (C.ey + T::VY * C.ez);
+            if constexpr (MODE == MODE_RHS) {
                 float w[3][8];
 #pragma unroll
                 for (int d = 0; d < 3; ++d)
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) w[d][j] = sV[d * T::VN + vs[j]];
+                    for (int j = 0; j < 8; ++j) w[d][j] = sV[d * T::VN + vb + voff(j)];
                 float wv[3][8];
 #pragma unroll
                 for (int d = 0; d < 3; ++d) eval_val(w[d], wv[d]);
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    float va[8], g0[8], g1[8], g2[8];
+                    // (1/k) v_a + (f^{n-1} + f^n)/2 at the vertices (one fma with
+                    // or without forcing, so every kernel instance rounds
+                    // alike), then at the Gauss points
+                    float fv[8], F[8], va[8], g0[8], g1[8], g2[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j)
+                        fv[j] = fmaf(P.inv_dt, w[a][j], fmid ? sF[a * T::VN + vb + voff(j)] : 0.0f);
+                    eval_val(fv, F);
                     eval_vg(w[a], ih0, ih1, ih2, va, g0, g1, g2);
-                    float F[8];
-                    if (fmid) {
-                        float fj[8], fq[8];
-                        const int64_t gbase = 0;
-                        (void)gbase;
-#pragma unroll
-                        for (int j = 0; j < 8; ++j) {
-                            int ii = gx + (j & 1), jj = gy + ((j >> 1) & 1), kk = gz + (j >> 2);
-                            ii = wrap(ii, m.nf[0], m.per[0]);
-                            jj = wrap(jj, m.nf[1], m.per[1]);
-                            kk = wrap(kk, m.nf[2], m.per[2]);
-                            fj[j] = fmid[a * nfn + ii + (int64_t)m.nf[0] * (jj + (int64_t)m.nf[1] * kk)];
-                        }
-                        eval_val(fj, fq);
-#pragma unroll
-                        for (int q = 0; q < 8; ++q) F[q] = fq[q];
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < 8; ++q) F[q] = 0.0f;
-                    }
 #pragma unroll
                     for (int q = 0; q < 8; ++q) {
                         float conv = wv[0][q] * g0[q] + wv[1][q] * g1[q] + wv[2][q] * g2[q];
-                        F[q] += P.inv_dt * va[q] - 0.5f * conv;
+                        F[q] -= 0.5f * conv;
                         g0[q] *= -P.half_nu;
                         g1[q] *= -P.half_nu;
                         g2[q] *= -P.half_nu;
@@ -384,59 +388,65 @@ __global__ void __launch_bounds__(ResTile<MODE>::NT)
                     integrate<true, true, true>(F, g0, g1, g2, ih0, ih1, ih2, acc[a]);
                 }
             } else {
-                // current iterate (x~, p~) at the cell vertices and patch corners
-                float vv[3][8], pp[8], cv[3][8], cp[8];
+                const int xb = (C.ex + 1) + T::SX * ((C.ey + 1) + T::SY * (C.ez + 1));
+                const int cb = (C.ex + 1 - C.ox) + T::SX * ((C.ey + 1 - C.oy) + T::SY * (C.ez + 1 - C.oz));
+                // The LPS terms vanish identically where x~ on the patch
+                // equals its patch interpolant.  When the vertex values and the
+                // interpolant computed here agree bit for bit every LPS
+                // contribution of the cell is exactly zero; other cells get
+                // them in pass B.
+                bool flat = true;
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
+                for (int d = 0; d < 4; ++d) {
+                    float cv[8], pv[8];
 #pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        vv[d][j] = sX[d * T::SN + xs[j]];
-                        cv[d][j] = sX[d * T::SN + cs[j]];
-                    }
-                    pp[j] = sX[3 * T::SN + xs[j]];
-                    cp[j] = sX[3 * T::SN + cs[j]];
+                    for (int j = 0; j < 8; ++j) cv[j] = sX[d * T::SN + cb + coff(j)];
+                    pi_vertices(cv, C.ox, C.oy, C.oz, pv);
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) flat &= pv[j] == sX[d * T::SN + xb + xoff(j)];
                 }
-                // stabilisation parameters (stabparams): |v|_inf over the vertices
-                float vmax2 = 0.0f;
-#pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    vmax2 = fmaxf(vmax2, vv[0][j] * vv[0][j] + vv[1][j] * vv[1][j] + vv[2][j] * vv[2][j]);
-                float den = P.nu * (1.0f / (P.hT * P.hT)) + sqrtf(vmax2) / P.hT + P.inv_dt;
-                float alphaT = P.alpha0 / den, deltaT = P.delta0 / den;
+                need[round] = !flat;
 
-                // values at Gauss points of x~, vp and pi x~
-                float xv[3][8], pv[3][8], piv[3][8], pq[8], div[8];
-                float pvert[3][8]; // pi x~ at the cell vertices
+                // x~ and vp at the Gauss points, pressure, divergence
+                float xv[3][8], pv[3][8], pq[8], div[8];
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    eval_val(vv[d], xv[d]);
                     float w[8];
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) w[j] = sV[d * T::VN + vs[j]];
+                    for (int j = 0; j < 8; ++j) w[j] = sX[d * T::SN + xb + xoff(j)];
+                    eval_val(w, xv[d]);
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) w[j] = sV[d * T::VN + vb + voff(j)];
                     eval_val(w, pv[d]);
-                    pi_vertices(cv[d], ox, oy, oz, pvert[d]);
-                    eval_val(pvert[d], piv[d]);
                 }
-                eval_val(pp, pq);
+                {
+                    float w[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) w[j] = sX[3 * T::SN + xb + xoff(j)];
+                    eval_val(w, pq);
+                }
 #pragma unroll
                 for (int q = 0; q < 8; ++q) div[q] = 0.0f;
 
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    float wa[8], dif[8], sum[8];
+                    float wa[8], va[8], dif[8], sum[8];
 #pragma unroll
                     for (int j = 0; j < 8; ++j) {
-                        wa[j] = sV[a * T::VN + vs[j]];
-                        dif[j] = wa[j] - vv[a][j];
-                        sum[j] = wa[j] + vv[a][j];
+                        wa[j] = sV[a * T::VN + vb + voff(j)];
+                        va[j] = sX[a * T::SN + xb + xoff(j)];
+                        // (1/k)(vp_a - v_a) + (f^{n-1} + f^n)/2 at the vertices
+                        // (one fma whether or not there is forcing, so every
+                        // kernel instance rounds alike)
+                        dif[j] = fmaf(P.inv_dt, wa[j] - va[j], fmid ? sF[a * T::VN + vb + voff(j)] : 0.0f);
+                        sum[j] = wa[j] + va[j];
                     }
                     float F[8], Gx[8], Gy[8], Gz[8], tmp[8];
-                    // (1/k)(vp_a - v_a) and -nu/2 grad(vp_a + v_a), + p d_a phi
+                    // -nu/2 grad(vp_a + v_a), + p d_a phi
                     eval_vg(sum, ih0, ih1, ih2, tmp, Gx, Gy, Gz);
                     eval_val(dif, F);
 #pragma unroll
                     for (int q = 0; q < 8; ++q) {
-                        F[q] *= P.inv_dt;
                         Gx[q] *= -P.half_nu;
                         Gy[q] *= -P.half_nu;
                         Gz[q] *= -P.half_nu;
@@ -444,120 +454,166 @@ __global__ void __launch_bounds__(ResTile<MODE>::NT)
                     float *Ga = a == 0 ? Gx : (a == 1 ? Gy : Gz);
 #pragma unroll
                     for (int q = 0; q < 8; ++q) Ga[q] += pq[q];
-                    if (fmid) {
-                        float fj[8], fq[8];
-#pragma unroll
-                        for (int j = 0; j < 8; ++j) {
-                            int ii = gx + (j & 1), jj = gy + ((j >> 1) & 1), kk = gz + (j >> 2);
-                            ii = wrap(ii, m.nf[0], m.per[0]);
-                            jj = wrap(jj, m.nf[1], m.per[1]);
-                            kk = wrap(kk, m.nf[2], m.per[2]);
-                            fj[j] = fmid[a * nfn + ii + (int64_t)m.nf[0] * (jj + (int64_t)m.nf[1] * kk)];
-                        }
-                        eval_val(fj, fq);
-#pragma unroll
-                        for (int q = 0; q < 8; ++q) F[q] += fq[q];
-                    }
-                    // -1/2 (vp . grad vp_a)
+                    // -1/2 (vp . grad vp_a) - 1/2 (v . grad v_a)
                     float g0[8], g1[8], g2[8];
                     eval_vg(wa, ih0, ih1, ih2, tmp, g0, g1, g2);
 #pragma unroll
                     for (int q = 0; q < 8; ++q)
                         F[q] -= 0.5f * (pv[0][q] * g0[q] + pv[1][q] * g1[q] + pv[2][q] * g2[q]);
-                    // -1/2 (v . grad v_a); keep v . grad v_a for the LPS term
-                    float conv[8];
-                    eval_vg(vv[a], ih0, ih1, ih2, tmp, g0, g1, g2);
+                    eval_vg(va, ih0, ih1, ih2, tmp, g0, g1, g2);
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        conv[q] = xv[0][q] * g0[q] + xv[1][q] * g1[q] + xv[2][q] * g2[q];
-                        F[q] -= 0.5f * conv[q];
-                    }
-                    if (a == 0)
+                    for (int q = 0; q < 8; ++q)
+                        F[q] -= 0.5f * (xv[0][q] * g0[q] + xv[1][q] * g1[q] + xv[2][q] * g2[q]);
+                    const float *ga = a == 0 ? g0 : (a == 1 ? g1 : g2);
 #pragma unroll
-                        for (int q = 0; q < 8; ++q) div[q] += g0[q];
-                    if (a == 1)
-#pragma unroll
-                        for (int q = 0; q < 8; ++q) div[q] += g1[q];
-                    if (a == 2)
-#pragma unroll
-                        for (int q = 0; q < 8; ++q) div[q] += g2[q];
-                    // LPS: R_a = v.grad v_a - pi v . grad pi v_a, tested with
-                    // v.grad phi (own vertices) and pi v . grad pi phi (corners)
-                    eval_vg(pvert[a], ih0, ih1, ih2, tmp, g0, g1, g2);
-                    float C0[8], C1[8], C2[8];
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        float R = conv[q] - (piv[0][q] * g0[q] + piv[1][q] * g1[q] + piv[2][q] * g2[q]);
-                        float dR = deltaT * R;
-                        Gx[q] -= dR * xv[0][q];
-                        Gy[q] -= dR * xv[1][q];
-                        Gz[q] -= dR * xv[2][q];
-                        C0[q] = dR * piv[0][q];
-                        C1[q] = dR * piv[1][q];
-                        C2[q] = dR * piv[2][q];
-                    }
+                    for (int q = 0; q < 8; ++q) div[q] += ga[q];
                     integrate<true, true, true>(F, Gx, Gy, Gz, ih0, ih1, ih2, acc[a]);
-                    float zero[8], cvals[8];
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) zero[q] = 0.0f;
-                    integrate<true, true, true>(zero, C0, C1, C2, ih0, ih1, ih2, cvals);
-                    pi_transpose(cvals, ox, oy, oz, cor[a]);
                 }
-                // continuity: -(div v, xi) - alpha_T (grad(p - pi p), grad(xi - pi xi))
-                {
-                    float tmp[8], g0[8], g1[8], g2[8], h0[8], h1[8], h2[8], pvv[8];
-                    eval_vg(pp, ih0, ih1, ih2, tmp, g0, g1, g2);
-                    pi_vertices(cp, ox, oy, oz, pvv);
-                    eval_vg(pvv, ih0, ih1, ih2, tmp, h0, h1, h2);
+                // continuity: -(div v, xi)
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        g0[q] = -alphaT * (g0[q] - h0[q]);
-                        g1[q] = -alphaT * (g1[q] - h1[q]);
-                        g2[q] = -alphaT * (g2[q] - h2[q]);
-                        div[q] = -div[q];
-                    }
-                    float lps[8], dv[8];
-                    integrate<true, true, true>(div, g0, g1, g2, ih0, ih1, ih2, acc[3]);
-                    float zero[8];
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) zero[q] = 0.0f;
-                    integrate<true, true, true>(zero, g0, g1, g2, ih0, ih1, ih2, lps);
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) dv[j] = -lps[j];
-                    pi_transpose(dv, ox, oy, oz, cor[3]);
-                }
+                for (int q = 0; q < 8; ++q) div[q] = -div[q];
+                integrate<false, false, false>(div, nullptr, nullptr, nullptr, ih0, ih1, ih2, acc[3]);
             }
 #pragma unroll
             for (int f = 0; f < T::NACC; ++f)
 #pragma unroll
                 for (int j = 0; j < 8; ++j) acc[f][j] *= P.wq;
-#pragma unroll
-            for (int f = 0; f < 4; ++f)
-#pragma unroll
-                for (int j = 0; j < 8; ++j) cor[f][j] *= P.wq;
         }
 
-        // ---- colour-ordered accumulation into LDS ----
-        // patch slot of an owned patch (halo cells ex == 0 etc. belong to a
-        // neighbour's patch and do not contribute corner terms)
-        const bool own_patch = ex >= 1 && ey >= 1 && ez >= 1;
-        const int pslot = own_patch ? ((ex - 1) / 2 + T::NPX * ((ey - 1) / 2 + T::NPY * ((ez - 1) / 2))) : 0;
+        // colour-ordered accumulation into LDS; with colour-sorted slots a
+        // wave takes part in at most two of the phases
+        const int vb = C.ex + T::VX * (C.ey + T::VY * C.ez);
         for (int c = 0; c < 8; ++c) {
-            if (live && colour == c) {
+            if (C.live && C.colour == c) {
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    int s = (ex + (j & 1)) + T::VX * ((ey + ((j >> 1) & 1)) + T::VY * (ez + (j >> 2)));
+                for (int j = 0; j < 8; ++j)
 #pragma unroll
-                    for (int f = 0; f < T::NACC; ++f) sAcc[f * T::VN + s] += acc[f][j];
-                }
-                if (MODE == MODE_RES && own_patch) {
-#pragma unroll
-                    for (int j = 0; j < 8; ++j)
-#pragma unroll
-                        for (int f = 0; f < 4; ++f) sAux[pslot * 32 + 4 * j + f] += cor[f][j];
-                }
+                    for (int f = 0; f < T::NACC; ++f) sAcc[f * T::VN + vb + voff(j)] += acc[f][j];
             }
             __syncthreads();
+        }
+    }
+
+    // ---- pass B: LPS terms of the cells that need them, one equation at a
+    // time (velocity components, then continuity) ----
+    if constexpr (MODE == MODE_RES) {
+        int any = 0;
+#pragma unroll
+        for (int round = 0; round < T::ROUNDS; ++round) any |= need[round];
+        if (__syncthreads_or(any)) {
+            for (int a = 0; a < 4; ++a) {
+#pragma unroll
+                for (int round = 0; round < T::ROUNDS; ++round) {
+                    const Cell C = cell_of(tid + round * T::NT);
+                    float acc[8], cor[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) acc[j] = cor[j] = 0.0f;
+                    const bool own_patch = C.ex >= 1 && C.ey >= 1 && C.ez >= 1;
+                    if (C.live && need[round]) {
+                        const int xb = (C.ex + 1) + T::SX * ((C.ey + 1) + T::SY * (C.ez + 1));
+                        const int cb = (C.ex + 1 - C.ox) + T::SX * ((C.ey + 1 - C.oy) + T::SY * (C.ez + 1 - C.oz));
+                        // stabilisation parameters (stabparams): |v|_inf over the vertices
+                        float vmax2 = 0.0f;
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) {
+                            float u0 = sX[0 * T::SN + xb + xoff(j)], u1 = sX[1 * T::SN + xb + xoff(j)],
+                                  u2 = sX[2 * T::SN + xb + xoff(j)];
+                            vmax2 = fmaxf(vmax2, u0 * u0 + u1 * u1 + u2 * u2);
+                        }
+                        float den = P.nu * (1.0f / (P.hT * P.hT)) + sqrtf(vmax2) / P.hT + P.inv_dt;
+                        if (a < 3) {
+                            // R_a = v.grad v_a - pi v . grad pi v_a, tested with
+                            // v.grad phi (own vertices) and pi v . grad pi phi
+                            // (patch corners)
+                            const float deltaT = P.delta0 / den;
+                            float xv[3][8], piv[3][8], pa[8], va[8];
+#pragma unroll
+                            for (int d = 0; d < 3; ++d) {
+                                float w[8], pw[8];
+#pragma unroll
+                                for (int j = 0; j < 8; ++j) w[j] = sX[d * T::SN + xb + xoff(j)];
+                                eval_val(w, xv[d]);
+#pragma unroll
+                                for (int j = 0; j < 8; ++j) w[j] = sX[d * T::SN + cb + coff(j)];
+                                pi_vertices(w, C.ox, C.oy, C.oz, pw);
+                                eval_val(pw, piv[d]);
+                            }
+                            {
+                                float w[8];
+#pragma unroll
+                                for (int j = 0; j < 8; ++j) w[j] = sX[a * T::SN + cb + coff(j)];
+                                pi_vertices(w, C.ox, C.oy, C.oz, pa);
+#pragma unroll
+                                for (int j = 0; j < 8; ++j) va[j] = sX[a * T::SN + xb + xoff(j)];
+                            }
+                            float tmp[8], g0[8], g1[8], g2[8], h0[8], h1[8], h2[8];
+                            eval_vg(va, ih0, ih1, ih2, tmp, g0, g1, g2);
+                            eval_vg(pa, ih0, ih1, ih2, tmp, h0, h1, h2);
+                            float C0[8], C1[8], C2[8];
+#pragma unroll
+                            for (int q = 0; q < 8; ++q) {
+                                float R = (xv[0][q] * g0[q] + xv[1][q] * g1[q] + xv[2][q] * g2[q]) -
+                                          (piv[0][q] * h0[q] + piv[1][q] * h1[q] + piv[2][q] * h2[q]);
+                                float dR = deltaT * R;
+                                g0[q] = -dR * xv[0][q];
+                                g1[q] = -dR * xv[1][q];
+                                g2[q] = -dR * xv[2][q];
+                                C0[q] = dR * piv[0][q];
+                                C1[q] = dR * piv[1][q];
+                                C2[q] = dR * piv[2][q];
+                                tmp[q] = 0.0f;
+                            }
+                            integrate<true, true, true>(tmp, g0, g1, g2, ih0, ih1, ih2, acc);
+                            float cvals[8];
+                            integrate<true, true, true>(tmp, C0, C1, C2, ih0, ih1, ih2, cvals);
+                            pi_transpose(cvals, C.ox, C.oy, C.oz, cor);
+                        } else {
+                            // -alpha_T (grad(p - pi p), grad(xi - pi xi))
+                            const float alphaT = P.alpha0 / den;
+                            float w[8], pw[8];
+#pragma unroll
+                            for (int j = 0; j < 8; ++j) w[j] = sX[3 * T::SN + cb + coff(j)];
+                            pi_vertices(w, C.ox, C.oy, C.oz, pw);
+#pragma unroll
+                            for (int j = 0; j < 8; ++j) w[j] = sX[3 * T::SN + xb + xoff(j)] - pw[j];
+                            float tmp[8], g0[8], g1[8], g2[8];
+                            eval_vg(w, ih0, ih1, ih2, tmp, g0, g1, g2);
+#pragma unroll
+                            for (int q = 0; q < 8; ++q) {
+                                g0[q] *= -alphaT;
+                                g1[q] *= -alphaT;
+                                g2[q] *= -alphaT;
+                                tmp[q] = 0.0f;
+                            }
+                            integrate<true, true, true>(tmp, g0, g1, g2, ih0, ih1, ih2, acc);
+                            float dv[8];
+#pragma unroll
+                            for (int j = 0; j < 8; ++j) dv[j] = -acc[j];
+                            pi_transpose(dv, C.ox, C.oy, C.oz, cor);
+                        }
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) {
+                            acc[j] *= P.wq;
+                            cor[j] *= P.wq;
+                        }
+                    }
+                    // patch slot of an owned patch (halo cells ex == 0 etc. belong
+                    // to a neighbour's patch and add no corner terms here)
+                    const int pslot = own_patch ? ((C.ex - 1) / 2 + T::NPX * ((C.ey - 1) / 2 + T::NPY * ((C.ez - 1) / 2))) : 0;
+                    const int vb = C.ex + T::VX * (C.ey + T::VY * C.ez);
+                    const bool act = C.live && need[round];
+                    for (int c = 0; c < 8; ++c) {
+                        if (act && C.colour == c) {
+#pragma unroll
+                            for (int j = 0; j < 8; ++j) sAcc[a * T::VN + vb + voff(j)] += acc[j];
+                            if (own_patch)
+#pragma unroll
+                                for (int j = 0; j < 8; ++j) sAux[pslot * 32 + 4 * j + a] += cor[j];
+                        }
+                        __syncthreads();
+                    }
+                }
+            }
         }
     }
 
@@ -586,13 +642,38 @@ __global__ void __launch_bounds__(ResTile<MODE>::NT)
     }
 }
 
+template <int MODE>
+__global__ void __launch_bounds__(ResTile<MODE>::NT)
+    k_residual(Mesh m, ResParams P, const float *__restrict__ x, const float *__restrict__ vp,
+               const float *__restrict__ fmid, float *__restrict__ out, float *__restrict__ aux,
+               const int *__restrict__ flag) {
+    if (flag && *flag == 0) return; // predicated launch (fallback path not taken)
+    residual_tile<MODE>(m, P, blockIdx.x, blockIdx.y, blockIdx.z, x, vp, fmid, out, aux);
+}
+
+// Batched: one flat grid over the tiles of all boxes.  x is a 4-component
+// iterate in the batch layout (the right-hand side reads its velocity
+// part), vp has 3 components, out 4; aux holds 32 floats per patch.
+template <int MODE>
+__global__ void __launch_bounds__(ResTile<MODE>::NT)
+    k_residual_batch(const BoxDesc *__restrict__ D, int nbox, const float *__restrict__ x,
+                     const float *__restrict__ vp, float *__restrict__ out, float *__restrict__ aux) {
+    const int64_t blk = blockIdx.x;
+    const int b = find_box(nbox, blk, [&](int i) { return D[i].blk_tile; });
+    const BoxDesc &d = D[b];
+    const Mesh m = d.m;
+    const ResParams P = d.rp;
+    int t = (int)(blk - d.blk_tile);
+    int bx = t % d.rtiles[0], by = (t / d.rtiles[0]) % d.rtiles[1], bz = t / (d.rtiles[0] * d.rtiles[1]);
+    residual_tile<MODE>(m, P, bx, by, bz, x + 4 * d.off_fine, MODE == MODE_RES ? vp + 3 * d.off_fine : nullptr,
+                        nullptr, out + 4 * d.off_fine, MODE == MODE_RES ? aux + 32 * d.off_patch : nullptr);
+}
+
 // Adds the corner (pi phi) parts of the LPS terms: a coarse vertex collects
 // the per-patch sums of the patches it is a corner of, in ascending patch
 // order.  aux[M][4 j + f]: corner j = A + 2B + 4C of patch M, field f.
-__global__ void __launch_bounds__(256) k_lps_corners(Mesh m, const float *__restrict__ aux,
-                                                     float *__restrict__ r, const int *__restrict__ flag) {
-    if (flag && *flag == 0) return;
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void lps_corner_node(const Mesh &m, int64_t t, const float *__restrict__ aux,
+                                                float *__restrict__ r) {
     if (t >= m.n_coarse) return;
     uint32_t JK = fdiv((uint32_t)t, m.cx), I = (uint32_t)t - JK * m.nc[0];
     uint32_t K = fdiv(JK, m.cy), J = JK - K * m.nc[1];
@@ -632,7 +713,23 @@ __global__ void __launch_bounds__(256) k_lps_corners(Mesh m, const float *__rest
     r[3 * m.n_fine + g] += s[3];
 }
 
-static ResParams make_params(const Mesh &m, const dnnmg_ns *ns) {
+__global__ void __launch_bounds__(256) k_lps_corners(Mesh m, const float *__restrict__ aux,
+                                                     float *__restrict__ r, const int *__restrict__ flag) {
+    if (flag && *flag == 0) return;
+    lps_corner_node(m, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, aux, r);
+}
+
+__global__ void __launch_bounds__(256) k_lps_corners_batch(const BoxDesc *__restrict__ D, int nbox,
+                                                           const float *__restrict__ aux, float *__restrict__ r) {
+    const int64_t blk = blockIdx.x;
+    const int b = find_box(nbox, blk, [&](int i) { return D[i].blk_coarse; });
+    const BoxDesc &d = D[b];
+    const Mesh m = d.m;
+    lps_corner_node(m, (blk - d.blk_coarse) * blockDim.x + threadIdx.x, aux + 32 * d.off_patch,
+                    r + 4 * d.off_fine);
+}
+
+ResParams make_params(const Mesh &m, const dnnmg_ns *ns) {
     ResParams P;
     P.inv_dt = (float)(1.0 / ns->dt);
     P.half_nu = (float)(0.5 * ns->nu);
@@ -653,7 +750,7 @@ static int check_ns(const dnnmg_ns *ns) {
 }
 
 template <int MODE>
-static dim3 res_grid(const Mesh &m) {
+dim3 res_grid(const Mesh &m) {
     using T = ResTile<MODE>;
     return dim3((m.nf[0] + T::TX - 1) / T::TX, (m.nf[1] + T::TY - 1) / T::TY,
                 (m.nf[2] + T::TZ - 1) / T::TZ);
@@ -666,6 +763,23 @@ int residual_launch(const Mesh &m, const dnnmg_ns *ns, const float *x, const flo
                                                                                  aux, flag);
     k_lps_corners<<<blocks_for(m.n_coarse, 256), 256, 0, s>>>(m, aux, r, flag);
     return hip_check(hipGetLastError(), "dnnmg_residual launch");
+}
+
+void residual_tiles(const Mesh &m, int rt[3]) {
+    dim3 g = res_grid<MODE_RES>(m);
+    rt[0] = g.x;
+    rt[1] = g.y;
+    rt[2] = g.z;
+}
+
+void residual_batch_launch(const BoxDesc *D, int nbox, int64_t ntiles, int64_t ncoarse_blocks, const float *x,
+                           const float *vp, float *r, float *aux, hipStream_t s) {
+    k_residual_batch<MODE_RES><<<(unsigned)ntiles, ResTile<MODE_RES>::NT, 0, s>>>(D, nbox, x, vp, r, aux);
+    k_lps_corners_batch<<<(unsigned)ncoarse_blocks, 256, 0, s>>>(D, nbox, aux, r);
+}
+
+void rhs_batch_launch(const BoxDesc *D, int nbox, int64_t ntiles, const float *v, float *b, hipStream_t s) {
+    k_residual_batch<MODE_RHS><<<(unsigned)ntiles, ResTile<MODE_RHS>::NT, 0, s>>>(D, nbox, v, nullptr, b, nullptr);
 }
 
 } // namespace dnnmg

@@ -48,11 +48,12 @@ __global__ void k_mult(Mesh m, uint8_t *__restrict__ mult) {
 // coarse neighbours (wrapping on periodic axes).  One thread per coarse node
 // C = (I, J, K) writes the fine nodes 2C + (a, b, c), a, b, c in {0, 1}, that
 // exist, from the 2x2x2 coarse block C .. C+1: all loads are issued at once
-// (one memory round trip per thread).  Accumulated in FP64 from the FP64
-// coarse solution, rounded once to FP32.
-__global__ void __launch_bounds__(256) k_prolong(Mesh m, int ncomp, const double *__restrict__ xc,
-                                                 float *__restrict__ xf) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// (one memory round trip per thread).  The FP64 coarse values are rounded to
+// FP32 and averaged axis by axis (x, then y, then z) in FP32, the same
+// operations the residual kernel uses for the patch interpolant, so a
+// prolongated field equals its own patch interpolant bit for bit.
+__device__ __forceinline__ void prolong_node(const Mesh &m, int64_t t, int ncomp, const double *__restrict__ xc,
+                                             float *__restrict__ xf) {
     if (t >= m.n_coarse) return;
     uint32_t JK = fdiv((uint32_t)t, m.cx), I = (uint32_t)t - JK * m.nc[0];
     uint32_t K = fdiv(JK, m.cy), J = JK - K * m.nc[1];
@@ -76,24 +77,24 @@ __global__ void __launch_bounds__(256) k_prolong(Mesh m, int ncomp, const double
     const int64_t f0 = 2 * (int64_t)I + (int64_t)m.nf[0] * (2 * (int64_t)J + (int64_t)m.nf[1] * 2 * K);
     for (int comp = 0; comp < ncomp; ++comp) {
         const double *x = xc + comp * ncn;
-        double v[8];
+        float v[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = x[cidx[q]];
+        for (int q = 0; q < 8; ++q) v[q] = (float)x[cidx[q]];
         // x pass, y pass, z pass: value at offset 0 = corner, at 1 = mean
-        double px[8];
+        float px[8];
 #pragma unroll
-        for (int q = 0; q < 8; q += 2) { px[q] = v[q]; px[q + 1] = 0.5 * (v[q] + v[q + 1]); }
-        double py[8];
+        for (int q = 0; q < 8; q += 2) { px[q] = v[q]; px[q + 1] = 0.5f * (v[q] + v[q + 1]); }
+        float py[8];
 #pragma unroll
         for (int c = 0; c < 2; ++c)
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
                 py[a + 4 * c] = px[a + 4 * c];
-                py[a + 2 + 4 * c] = 0.5 * (px[a + 4 * c] + px[a + 2 + 4 * c]);
+                py[a + 2 + 4 * c] = 0.5f * (px[a + 4 * c] + px[a + 2 + 4 * c]);
             }
-        double pz[8];
+        float pz[8];
 #pragma unroll
-        for (int ab = 0; ab < 4; ++ab) { pz[ab] = py[ab]; pz[ab + 4] = 0.5 * (py[ab] + py[ab + 4]); }
+        for (int ab = 0; ab < 4; ++ab) { pz[ab] = py[ab]; pz[ab + 4] = 0.5f * (py[ab] + py[ab + 4]); }
         float *out = xf + comp * nfn + f0;
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
@@ -102,11 +103,26 @@ __global__ void __launch_bounds__(256) k_prolong(Mesh m, int ncomp, const double
             for (int b = 0; b < 2; ++b) {
                 if (b && !odd[1]) break;
                 float *row = out + (int64_t)m.nf[0] * (b + (int64_t)m.nf[1] * c);
-                row[0] = (float)pz[2 * b + 4 * c];
-                if (odd[0]) row[1] = (float)pz[1 + 2 * b + 4 * c];
+                row[0] = pz[2 * b + 4 * c];
+                if (odd[0]) row[1] = pz[1 + 2 * b + 4 * c];
             }
         }
     }
+}
+
+__global__ void __launch_bounds__(256) k_prolong(Mesh m, int ncomp, const double *__restrict__ xc,
+                                                 float *__restrict__ xf) {
+    prolong_node(m, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, ncomp, xc, xf);
+}
+
+__global__ void __launch_bounds__(256) k_prolong_batch(const BoxDesc *__restrict__ D, int nbox,
+                                                       const double *__restrict__ xc, float *__restrict__ xf) {
+    const int64_t blk = blockIdx.x;
+    const int b = find_box(nbox, blk, [&](int i) { return D[i].blk_coarse; });
+    const BoxDesc &d = D[b];
+    const Mesh m = d.m;
+    prolong_node(m, (blk - d.blk_coarse) * blockDim.x + threadIdx.x, 4, xc + 4 * d.off_coarse,
+                 xf + 4 * d.off_fine);
 }
 
 // --------------------------------------------------------- restriction ----
@@ -114,9 +130,8 @@ __global__ void __launch_bounds__(256) k_prolong(Mesh m, int ncomp, const double
 // w(i, I) bf(i), w = 1 at the coincident node and 1/2 at the two neighbours;
 // absent neighbours (domain edge) get weight 0.  27 loads per component are
 // issued together; FP64 accumulation.
-__global__ void __launch_bounds__(256) k_restrict(Mesh m, int ncomp, const float *__restrict__ bf,
-                                                  double *__restrict__ bc) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void restrict_node(const Mesh &m, int64_t t, int ncomp, const float *__restrict__ bf,
+                                              double *__restrict__ bc) {
     if (t >= m.n_coarse) return;
     uint32_t JK = fdiv((uint32_t)t, m.cx), I = (uint32_t)t - JK * m.nc[0];
     uint32_t K = fdiv(JK, m.cy), J = JK - K * m.nc[1];
@@ -156,6 +171,21 @@ __global__ void __launch_bounds__(256) k_restrict(Mesh m, int ncomp, const float
             }
         bc[(int64_t)comp * m.n_coarse + t] = acc;
     }
+}
+
+__global__ void __launch_bounds__(256) k_restrict(Mesh m, int ncomp, const float *__restrict__ bf,
+                                                  double *__restrict__ bc) {
+    restrict_node(m, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, ncomp, bf, bc);
+}
+
+__global__ void __launch_bounds__(256) k_restrict_batch(const BoxDesc *__restrict__ D, int nbox,
+                                                        const float *__restrict__ bf, double *__restrict__ bc) {
+    const int64_t blk = blockIdx.x;
+    const int b = find_box(nbox, blk, [&](int i) { return D[i].blk_coarse; });
+    const BoxDesc &d = D[b];
+    const Mesh m = d.m;
+    restrict_node(m, (blk - d.blk_coarse) * blockDim.x + threadIdx.x, 4, bf + 4 * d.off_fine,
+                  bc + 4 * d.off_coarse);
 }
 
 // ----------------------------------------------------------- gather Q -----
@@ -259,10 +289,8 @@ __device__ __forceinline__ Hold1 holders(int i, int n, int per) {
     return h;
 }
 
-__global__ void __launch_bounds__(256) k_scatter(Mesh m, const float *__restrict__ Y,
-                                                 const float *__restrict__ vbase,
-                                                 float *__restrict__ d) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void scatter_node(const Mesh &m, int64_t t, const float *__restrict__ Y,
+                                             const float *__restrict__ vbase, float *__restrict__ d) {
     if (t >= m.n_fine) return;
     uint32_t jk = fdiv((uint32_t)t, m.fx), i = (uint32_t)t - jk * m.nf[0];
     uint32_t k = fdiv(jk, m.fy), j = jk - k * m.nf[1];
@@ -300,6 +328,22 @@ __global__ void __launch_bounds__(256) k_scatter(Mesh m, const float *__restrict
     if (vbase) d[3 * m.n_fine + t] = vbase[3 * m.n_fine + t];
 }
 
+__global__ void __launch_bounds__(256) k_scatter(Mesh m, const float *__restrict__ Y,
+                                                 const float *__restrict__ vbase, float *__restrict__ d) {
+    scatter_node(m, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, Y, vbase, d);
+}
+
+__global__ void __launch_bounds__(256) k_scatter_batch(const BoxDesc *__restrict__ D, int nbox,
+                                                       const float *__restrict__ Y, const float *__restrict__ vbase,
+                                                       float *__restrict__ xc) {
+    const int64_t blk = blockIdx.x;
+    const int b = find_box(nbox, blk, [&](int i) { return D[i].blk_fine; });
+    const BoxDesc &dd = D[b];
+    const Mesh m = dd.m;
+    scatter_node(m, (blk - dd.blk_fine) * blockDim.x + threadIdx.x, Y + 81 * dd.off_patch,
+                 vbase + 4 * dd.off_fine, xc + 4 * dd.off_fine);
+}
+
 // -------------------------------------------------------------- norms -----
 constexpr int NORM_BLOCKS = 1024;
 
@@ -334,6 +378,17 @@ __global__ void __launch_bounds__(256) k_norm_final(int nparts, const double *__
         __syncthreads();
     }
     if (threadIdx.x == 0) *out = red[0];
+}
+
+void prolong_batch_launch(const BoxDesc *D, int nbox, int64_t nblk, const double *xc, float *xf, hipStream_t s) {
+    k_prolong_batch<<<(unsigned)nblk, 256, 0, s>>>(D, nbox, xc, xf);
+}
+void restrict_batch_launch(const BoxDesc *D, int nbox, int64_t nblk, const float *bf, double *bc, hipStream_t s) {
+    k_restrict_batch<<<(unsigned)nblk, 256, 0, s>>>(D, nbox, bf, bc);
+}
+void scatter_batch_launch(const BoxDesc *D, int nbox, int64_t nblk, const float *Y, const float *vbase, float *xc,
+                          hipStream_t s) {
+    k_scatter_batch<<<(unsigned)nblk, 256, 0, s>>>(D, nbox, Y, vbase, xc);
 }
 
 } // namespace dnnmg

@@ -29,7 +29,7 @@ class CorrectionStep:
     """
 
     def __init__(self, box, ns, params, dtype="bf16", device="cuda:0", shift=None, inv_scale=None,
-                 indicator=False, theta=1.0, fallback_sweeps=4):
+                 indicator=False, theta=1.0, fallback_sweeps=4, fused=False):
         self.box = L.Box.of(box)
         self.ns = L.NS.of(ns)
         self.dev = torch.device(device)
@@ -37,6 +37,8 @@ class CorrectionStep:
         self.nf, self.nc, self.np = L.box_sizes(self.box)
         self.hidden = int(np.shape(params[0])[1])
         self.indicator = indicator
+        # fused: the gather runs inside the network kernel (no X round trip)
+        self.fused = fused and self.hidden in (128, 256, 512) and not (dtype == "fp32" and self.hidden == 512)
         f32 = dict(dtype=torch.float32, device=self.dev)
         f64 = dict(dtype=torch.float64, device=self.dev)
         self.xc = torch.zeros(4 * self.nc, **f64)
@@ -91,9 +93,13 @@ class CorrectionStep:
         box, ns = self.box, self.ns
         L.dnnmg_prolong(box, self.xc, self.xt, stream=stream)
         L.dnnmg_residual(box, ns, self.xt, self.vprev, self.r, self.ws_res, stream=stream)
-        L.dnnmg_patch_gather(box, self.xt, self.r, self.X, self.xdtype, LDX, self.shift, self.inv_scale,
-                             stream=stream)
-        L.dnnmg_patch_forward(self.net, self.np, self.X, LDX, self.Y, stream=stream)
+        if self.fused:
+            L.dnnmg_patch_gather_forward(box, self.net, self.xt, self.r, self.Y, self.shift, self.inv_scale,
+                                         stream=stream)
+        else:
+            L.dnnmg_patch_gather(box, self.xt, self.r, self.X, self.xdtype, LDX, self.shift, self.inv_scale,
+                                 stream=stream)
+            L.dnnmg_patch_forward(self.net, self.np, self.X, LDX, self.Y, stream=stream)
         # corrected iterate (v~ + d, p~)
         L.dnnmg_scatter_avg(box, self.Y, self.xcorr, vbase=self.xt, stream=stream)
         if self.indicator:

@@ -1,0 +1,120 @@
+"""Batched multi-box step (plan + fused persistent network stage + autotuner)
+against per-box single steps, and HIP-graph replay."""
+import numpy as np
+import pytest
+import torch
+
+import dnnmg_synth as syn
+from gpu_util import dev, rel_l2, say, to_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mods():
+    from paper_2307_14837_amd import _lib as L
+    from paper_2307_14837_amd import batched, stepper
+
+    assert torch.cuda.is_available()
+    return L, batched, stepper
+
+
+def batch_inputs(boxes, seed=0):
+    xcs, vps = [], []
+    for i, b in enumerate(boxes):
+        w = syn.Workload("b", b, syn.NSParams(1e-3, 0.01), 256, "bf16", "fourier")
+        inp = syn.step_inputs(w, seed=seed + i)
+        xcs.append(inp.xc)
+        vps.append(inp.vprev)
+    return xcs, vps
+
+
+BOXES = [syn.BoxSpec(n, (1.0, 1.0, 1.0), 7, 0) for n in [(8, 8, 8), (12, 8, 10), (4, 6, 4), (10, 12, 8),
+                                                          (6, 4, 2), (16, 8, 12)]]
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "fp8"])
+def test_batched_matches_single(mods, dtype):
+    L, batched, stepper = mods
+    say("batched vs single", dtype)
+    ns = syn.NSParams(1e-3, 0.01)
+    H = 256
+    params = syn.mlp_params(165, H, 81, seed=4)
+    xcs, vps = batch_inputs(BOXES)
+    bs = batched.BatchedStep(BOXES, ns, params, dtype=dtype)
+    bs.load(xcs, vps)
+    bs.step()
+    out = bs.results()
+    for b, box in enumerate(BOXES):
+        st = stepper.CorrectionStep(box, ns, params, dtype=dtype)
+        ref = st.run_numpy(xcs[b], vps[b])
+        assert np.array_equal(out[b]["xt"], ref["xt"].astype(np.float32)), b
+        assert np.array_equal(out[b]["Y"], ref["Y"].astype(np.float32)), b
+        assert np.array_equal(out[b]["xcorr"][:3], ref["vcorr"].astype(np.float32)), b
+        assert np.array_equal(out[b]["bc"], ref["bc"]), b
+    # autotuned choice gives the same numbers
+    ppw, grid = bs.autotune(reps=3)
+    say(f"  autotuned: {ppw} patches per wave, persistent grid {grid}")
+    assert ppw in (16, 32)
+    bs.step()
+    out2 = bs.results()
+    for b in range(len(BOXES)):
+        assert np.array_equal(out2[b]["bc"], out[b]["bc"]), b
+
+
+def test_batched_graph_replay(mods):
+    L, batched, _ = mods
+    say("batched graph replay")
+    ns = syn.NSParams(1e-3, 0.01)
+    params = syn.mlp_params(165, 256, 81, seed=5)
+    xcs, vps = batch_inputs(BOXES, seed=10)
+    bs = batched.BatchedStep(BOXES, ns, params, dtype="bf16")
+    bs.load(xcs, vps)
+    bs.autotune(reps=2)
+    bs.step()
+    eager = bs.results()
+    bs.capture()
+    for rep in range(3):
+        bs.bufs["bc"].zero_()
+        torch.cuda.synchronize()
+        bs.replay()
+        got = bs.results()
+        for b in range(len(BOXES)):
+            assert np.array_equal(got[b]["bc"], eager[b]["bc"]), (rep, b)
+
+
+def test_fused_gather_forward_single(mods, orc):
+    L, _, stepper = mods
+    say("fused gather+forward, single box")
+    w = syn.cfg2()
+    inp = syn.step_inputs(w, seed=3)
+    params = syn.mlp_params(165, 256, 81, seed=3)
+    st = stepper.CorrectionStep(w.box, w.ns, params, dtype="bf16", fused=False)
+    ref = st.run_numpy(inp.xc, inp.vprev)
+    Y = torch.zeros_like(st.Y)
+    L.dnnmg_patch_gather_forward(st.box, st.net, st.xt, st.r, Y)
+    torch.cuda.synchronize()
+    assert np.array_equal(Y.cpu().numpy().reshape(-1, 81), ref["Y"].astype(np.float32))
+
+
+def test_cfg3_sized_batch_vs_oracle(mods, orc):
+    """The 32-box workload: one box of the batch against the FP64 oracle."""
+    L, batched, _ = mods
+    boxes = syn.cfg3_boxes(seed=0)
+    say(f"cfg3 batch: {len(boxes)} boxes, {sum(b.n_patches for b in boxes)} patches")
+    ns = syn.NSParams(1e-3, 0.01)
+    params = syn.mlp_params(165, 256, 81, seed=6)
+    xcs, vps = batch_inputs(boxes, seed=20)
+    bs = batched.BatchedStep(boxes, ns, params, dtype="bf16")
+    bs.load(xcs, vps)
+    bs.autotune(reps=2)
+    bs.step()
+    out = bs.results()
+    k = int(np.argmin([b.n_patches for b in boxes]))
+    p32 = [np.asarray(p, np.float32).astype(np.float64) for p in params]
+    vp32 = np.asarray(vps[k], np.float32).astype(np.float64)
+    ref = orc.correction_step(boxes[k], ns, p32, xcs[k], vp32)
+    e = rel_l2(out[k]["xcorr"][:3] - out[k]["xt"][:3], ref["d"])
+    say(f"  box {k} {boxes[k].n}: d rel-L2 vs oracle {e:.2e}")
+    assert e <= 2e-2
+    assert rel_l2(out[k]["bc"], ref["bc"]) <= 2e-2

@@ -71,7 +71,8 @@ def test_prolong_restrict(L, orc, name):
     ref = orc.prolong(box, xc)
     got = xf.cpu().numpy().reshape(4, -1)
     assert rel_l2(got, ref) <= 1e-7
-    assert np.max(np.abs(got - ref)) <= 2 ** -23 * np.max(np.abs(ref)) * 2
+    # FP32 averaging of FP32-rounded coarse values: a few ulp of the field scale
+    assert np.max(np.abs(got - ref)) <= 4 * 2 ** -24 * np.max(np.abs(ref)) * 2
     # restriction of an FP32 fine vector in FP64
     bf = f32(rng.standard_normal((4, box.n_fine)))
     bc = torch.empty(4 * box.n_coarse, dtype=torch.float64, device=dev())
