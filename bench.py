@@ -146,11 +146,11 @@ def run_batched(dtype, steps, warmup):
         vps.append(inp.vprev)
     bs = batched.BatchedStep(boxes, ns, params, dtype=dtype)
     bs.load(xcs, vps)
-    ppw, grid = bs.autotune(reps=5)
+    ppt, grid = bs.autotune(reps=5)
     ms, _ = time_graph(bs, steps, warmup)
     npch, nf = bs.plan.n_patches, bs.plan.n_fine
     return {"workload": "cfg3_32_periodic_boxes", "boxes": len(boxes), "patches": npch, "fine_nodes": nf,
-            "dtype": dtype, "fused_batched": True, "autotuned": {"patches_per_wave": ppw, "grid": grid},
+            "dtype": dtype, "fused_batched": True, "autotuned": {"patches_per_tile": ppt, "grid": grid},
             "ms_per_step": ms, "patches_per_s": npch / (ms * 1e-3), "fine_dof_per_s": 4 * nf / (ms * 1e-3)}
 
 
@@ -301,6 +301,10 @@ def main():
         "rhs": time_kernel(lambda: L.dnnmg_rhs(st.box, st.ns, st.xcorr, st.b), reps),
         "restrict": time_kernel(lambda: L.dnnmg_restrict(st.box, st.b, st.bc), reps),
     }
+    fwd_tiles = {}
+    for tp in (16, 32, 64):
+        fwd_tiles[tp] = time_kernel(lambda: L.dnnmg_patch_forward_tiles(st.net, st.np, st.X, 192, st.Y, tp), reps)
+    kernel_ms["forward_by_tile"] = fwd_tiles
     mlp_flop = flops.mlp_flops_per_patch(256) * st.np
     out = {
         "metric": "DNN-MG correction step throughput (patches/s; fine DOF/s also given)",

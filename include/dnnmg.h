@@ -122,7 +122,8 @@ int dnnmg_prolong(const dnnmg_box *box, int ncomp, const double *xc, float *xf, 
  *   vprev FP32 [3][n_fine]  velocity of the previous step (builds F)
  *   fmid  FP32 [3][n_fine]  (f_{n-1} + f_n) / 2, or NULL for no forcing
  *   r     FP32 [4][n_fine]  output; velocity rows on Dirichlet faces are 0
- *   ws    device workspace of at least dnnmg_residual_workspace(box) bytes
+ *   ws    device workspace of at least dnnmg_residual_workspace(box) bytes,
+ *         16-byte aligned (per-patch LPS corner sums and per-tile flags)
  * Element integrals use 2x2x2 Gauss points on every fine cell. */
 size_t dnnmg_residual_workspace(const dnnmg_box *box);
 int dnnmg_residual(const dnnmg_box *box, const dnnmg_ns *ns, const float *x, const float *vprev,
@@ -168,6 +169,13 @@ int dnnmg_mlp_pack(int dtype, int hidden, int layer, const float *W, float w_sca
  * save).  n may be 0. */
 int dnnmg_patch_forward(const dnnmg_mlp *net, int64_t n, const void *X, int64_t ldx, float *Y,
                         void *saved, void *stream);
+/* dnnmg_patch_forward with an explicit launch geometry, for tuning: each
+ * workgroup takes tiles of tile_patches rows (16, 32 or 64 as built for the
+ * network's type and width; 0 = the library's choice) and the grid has
+ * `grid` workgroups walking the tiles (0 = one workgroup per tile).
+ * DNNMG_ERR_UNSUPPORTED for a tile size not built. */
+int dnnmg_patch_forward_tiles(const dnnmg_mlp *net, int64_t n, const void *X, int64_t ldx, float *Y,
+                              void *saved, int tile_patches, int grid, void *stream);
 size_t dnnmg_patch_saved_bytes(const dnnmg_mlp *net, int64_t n);
 
 /* Training objective of Sec. 4.2 restricted to patches: loss = (1/n) sum_M
@@ -248,11 +256,11 @@ int dnnmg_fallback(const dnnmg_box *box, const dnnmg_ns *ns, const float *xt, co
                    float *xcorr, int *flag_out, void *ws, size_t ws_bytes, void *stream);
 
 /* Operators Q and N fused (eqs. defQ and NN): the network's first-layer
- * inputs are built in registers from x~ (FP32 [4][n_fine]) and r (FP32
+ * inputs are built in on-chip memory from x~ (FP32 [4][n_fine]) and r (FP32
  * [4][n_fine]) with the standardisation `feat`, so the gathered batch is
  * never stored; Y FP32 [n_patches][81].  Same arithmetic as
- * dnnmg_patch_gather followed by dnnmg_patch_forward (F32, BF16 and FP8
- * networks of width 128, 256 or 512). */
+ * dnnmg_patch_gather followed by dnnmg_patch_forward (every network
+ * dnnmg_patch_forward takes). */
 int dnnmg_patch_gather_forward(const dnnmg_box *box, const dnnmg_mlp *net, const float *xt, const float *r,
                                const dnnmg_feat *feat, float *Y, void *stream);
 
@@ -269,9 +277,9 @@ int dnnmg_plan_create(const dnnmg_box *boxes, int nbox, const dnnmg_ns *ns, void
                       dnnmg_plan **plan, void *stream);
 int dnnmg_plan_destroy(dnnmg_plan *plan);
 int dnnmg_plan_sizes(const dnnmg_plan *plan, int64_t *n_fine, int64_t *n_coarse, int64_t *n_patches);
-/* Tuned choice of the network stage: patches per wave (16 or 32) and the
- * persistent grid size (0 = one block per 64-patch tile). */
-int dnnmg_plan_choice(const dnnmg_plan *plan, int *patches_per_wave, int *grid);
+/* Choice of the network stage: patches per workgroup tile (16, 32 or 64;
+ * 32 until tuned) and the persistent grid size (0 = one workgroup per tile). */
+int dnnmg_plan_choice(const dnnmg_plan *plan, int *patches_per_tile, int *grid);
 
 /* One correction step (Algorithm 1 after the coarse solve) for every box of
  * the plan in six launches, independent of the number of boxes:
@@ -285,9 +293,10 @@ int dnnmg_batch_step(const dnnmg_plan *plan, const dnnmg_mlp *net, const float *
                      const double *xc, const float *vprev, float *xt, float *r, float *Y, float *xcorr,
                      float *b, double *bc, void *stream);
 /* Autotuner (setup call, synchronises the stream): times the network stage
- * on the batch's own inputs for every candidate (16 or 32 patches per wave;
- * one block per tile or a persistent grid of 1, 2, 4 or 8 blocks per
- * compute unit) with `reps` launches each, and keeps the fastest. */
+ * on the batch's own inputs for every candidate (16, 32 or 64 patches per
+ * workgroup tile, as built for the network's type and width; one workgroup
+ * per tile or a persistent grid of 1, 2 or 4 workgroups per compute unit)
+ * with `reps` launches each, and keeps the fastest. */
 int dnnmg_plan_autotune(dnnmg_plan *plan, const dnnmg_mlp *net, const float *shift, const float *inv_scale,
                         const double *xc, const float *vprev, float *xt, float *r, float *Y, float *xcorr,
                         float *b, double *bc, int reps, void *stream);

@@ -91,6 +91,7 @@ _sig("dnnmg_patch_gather", [_P(Box), c_vp, c_vp, _P(Feat), ctypes.c_int, c_f, c_
 _sig("dnnmg_mlp_packed_bytes", [ctypes.c_int, ctypes.c_int, ctypes.c_int], c_sz)
 _sig("dnnmg_mlp_pack", [ctypes.c_int, ctypes.c_int, ctypes.c_int, c_vp, c_f, c_vp, c_vp])
 _sig("dnnmg_patch_forward", [_P(MLP), c_i64, c_vp, c_i64, c_vp, c_vp, c_vp])
+_sig("dnnmg_patch_forward_tiles", [_P(MLP), c_i64, c_vp, c_i64, c_vp, c_vp, ctypes.c_int, ctypes.c_int, c_vp])
 _sig("dnnmg_patch_saved_bytes", [_P(MLP), c_i64], c_sz)
 _sig("dnnmg_scatter_avg", [_P(Box), c_vp, c_vp, c_vp, c_vp])
 _sig("dnnmg_norm2_workspace", [], c_sz)
@@ -120,6 +121,7 @@ EXPORTS = [
     "dnnmg_version", "dnnmg_last_error", "dnnmg_box_sizes", "dnnmg_patch_dofmap", "dnnmg_prolong",
     "dnnmg_residual_workspace", "dnnmg_residual", "dnnmg_rhs", "dnnmg_restrict",
     "dnnmg_patch_gather", "dnnmg_mlp_packed_bytes", "dnnmg_mlp_pack", "dnnmg_patch_forward",
+    "dnnmg_patch_forward_tiles",
     "dnnmg_patch_saved_bytes", "dnnmg_scatter_avg", "dnnmg_norm2_workspace", "dnnmg_norm2_f64",
     "dnnmg_mse_grad", "dnnmg_patch_backward_workspace", "dnnmg_patch_backward", "dnnmg_adamw_step",
     "dnnmg_vanka_workspace", "dnnmg_vanka_sweeps", "dnnmg_fallback_workspace", "dnnmg_fallback",
@@ -263,6 +265,13 @@ def dnnmg_patch_forward(net: MLP, n, X, ldx, Y, saved=None, stream=None):
     _check(_lib.dnnmg_patch_forward(ctypes.byref(net), int(n), _ptr(X, None, None, "X"), int(ldx),
                                     _ptr(Y, torch.float32, n * N_OUT, "Y"),
                                     _ptr(saved, None, None, "saved"), _stream(stream)))
+
+
+def dnnmg_patch_forward_tiles(net: MLP, n, X, ldx, Y, tile_patches, grid=0, saved=None, stream=None):
+    _check(_lib.dnnmg_patch_forward_tiles(ctypes.byref(net), int(n), _ptr(X, None, None, "X"), int(ldx),
+                                          _ptr(Y, torch.float32, n * N_OUT, "Y"),
+                                          _ptr(saved, None, None, "saved"), int(tile_patches), int(grid),
+                                          _stream(stream)))
 
 
 def dnnmg_scatter_avg(box, Y, d, vbase=None, stream=None):

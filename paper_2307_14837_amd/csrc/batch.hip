@@ -5,7 +5,7 @@
 //   (persistent: blocks walk the patch tiles of all boxes), extension
 //   (v~ + d), right-hand side, restriction.
 // The plan keeps the layout, the launch geometry and the tuned choices of
-// the network stage (patches per wave, persistent grid size).
+// the network stage (patches per workgroup tile, persistent grid size).
 #include <vector>
 
 #include "common.hpp"
@@ -16,15 +16,12 @@ namespace dnnmg {
 ResParams make_params(const Mesh &m, const dnnmg_ns *ns);
 void residual_tiles(const Mesh &m, int rt[3]);
 void residual_batch_launch(const BoxDesc *D, int nbox, int64_t ntiles, int64_t ncoarse_blocks, const float *x,
-                           const float *vp, float *r, float *aux, hipStream_t s);
+                           const float *vp, float *r, float *aux, int *tflag, hipStream_t s);
 void rhs_batch_launch(const BoxDesc *D, int nbox, int64_t ntiles, const float *v, float *b, hipStream_t s);
 void prolong_batch_launch(const BoxDesc *D, int nbox, int64_t nblk, const double *xc, float *xf, hipStream_t s);
 void restrict_batch_launch(const BoxDesc *D, int nbox, int64_t nblk, const float *bf, double *bc, hipStream_t s);
 void scatter_batch_launch(const BoxDesc *D, int nbox, int64_t nblk, const float *Y, const float *vbase, float *xc,
                           hipStream_t s);
-int gather_fwd_launch(const dnnmg_mlp *net, int np, const BoxDesc *D, int nbox, const BoxDesc &one,
-                      int64_t ntiles, int grid, const float *xt, const float *r, const float *shift,
-                      const float *inv, float *Y, hipStream_t s);
 
 } // namespace dnnmg
 
@@ -35,10 +32,11 @@ struct dnnmg_plan {
     dnnmg_ns ns;
     std::vector<BoxDesc> desc;
     BoxDesc *d_desc;   // in the caller's workspace
-    float *aux;        // LPS corner workspace (32 floats per patch)
+    float *aux;        // LPS corner sums (32 floats per patch)
+    int *tflag;        // LPS flag per residual tile
     int64_t n_fine, n_coarse, n_patches;
     int64_t blk_fine, blk_coarse, tiles, ptiles;
-    int np;            // tuned: patches per wave / 16 of the network stage
+    int pt;            // tuned: patches per network tile / 16
     int grid;          // tuned: persistent grid of the network stage (0 = one block per tile)
 };
 
@@ -68,7 +66,7 @@ static int layout(dnnmg_plan *p, const dnnmg_box *boxes, int nbox) {
         bf += (d.m.n_fine + 255) / 256;
         bc += (d.m.n_coarse + 255) / 256;
         bt += (int64_t)rt[0] * rt[1] * rt[2];
-        bp += (d.m.n_patches + 64 * p->np - 1) / (64 * p->np);
+        bp += (d.m.n_patches + 16 * p->pt - 1) / (16 * p->pt);
     }
     p->n_fine = of;
     p->n_coarse = oc;
@@ -87,13 +85,16 @@ static int upload(dnnmg_plan *p, hipStream_t s) {
 
 extern "C" size_t dnnmg_plan_workspace(const dnnmg_box *boxes, int nbox) {
     if (!boxes || nbox < 1) return 0;
-    int64_t np = 0;
+    int64_t np = 0, nt = 0;
     for (int i = 0; i < nbox; ++i) {
         Mesh m;
         if (make_mesh(&boxes[i], &m)) return 0;
         np += m.n_patches;
+        int rt[3];
+        residual_tiles(m, rt);
+        nt += (int64_t)rt[0] * rt[1] * rt[2];
     }
-    return up256(sizeof(BoxDesc) * nbox) + up256(sizeof(float) * 32 * np);
+    return up256(sizeof(BoxDesc) * nbox) + up256(sizeof(float) * 32 * np) + up256(sizeof(int) * nt);
 }
 
 extern "C" int dnnmg_plan_create(const dnnmg_box *boxes, int nbox, const dnnmg_ns *ns, void *ws, size_t ws_bytes,
@@ -106,7 +107,7 @@ extern "C" int dnnmg_plan_create(const dnnmg_box *boxes, int nbox, const dnnmg_n
     dnnmg_plan *p = new dnnmg_plan();
     p->nbox = nbox;
     p->ns = *ns;
-    p->np = 1;
+    p->pt = 2; // instantiated for every network; the autotuner may change it
     p->grid = 0;
     int rc = layout(p, boxes, nbox);
     if (rc) {
@@ -115,6 +116,7 @@ extern "C" int dnnmg_plan_create(const dnnmg_box *boxes, int nbox, const dnnmg_n
     }
     p->d_desc = (BoxDesc *)ws;
     p->aux = (float *)((char *)ws + up256(sizeof(BoxDesc) * nbox));
+    p->tflag = (int *)((char *)p->aux + up256(sizeof(float) * 32 * p->n_patches));
     if ((rc = upload(p, (hipStream_t)stream))) {
         delete p;
         return rc;
@@ -136,9 +138,9 @@ extern "C" int dnnmg_plan_sizes(const dnnmg_plan *p, int64_t *n_fine, int64_t *n
     return DNNMG_OK;
 }
 
-extern "C" int dnnmg_plan_choice(const dnnmg_plan *p, int *patches_per_wave, int *grid) {
+extern "C" int dnnmg_plan_choice(const dnnmg_plan *p, int *patches_per_tile, int *grid) {
     if (!p) return fail(DNNMG_ERR_ARG, "dnnmg_plan_choice: plan is NULL");
-    if (patches_per_wave) *patches_per_wave = 16 * p->np;
+    if (patches_per_tile) *patches_per_tile = 16 * p->pt;
     if (grid) *grid = p->grid;
     return DNNMG_OK;
 }
@@ -148,9 +150,10 @@ static int step_impl(const dnnmg_plan *p, const dnnmg_mlp *net, const float *shi
                      double *bc, hipStream_t s) {
     const BoxDesc *D = p->d_desc;
     prolong_batch_launch(D, p->nbox, p->blk_coarse, xc, xt, s);
-    residual_batch_launch(D, p->nbox, p->tiles, p->blk_coarse, xt, vprev, r, p->aux, s);
+    residual_batch_launch(D, p->nbox, p->tiles, p->blk_coarse, xt, vprev, r, p->aux, p->tflag, s);
     BoxDesc none{};
-    int rc = gather_fwd_launch(net, p->np, D, p->nbox, none, p->ptiles, p->grid, xt, r, shift, inv, Y, s);
+    int rc = fwd_launch(net, p->pt, true, p->ptiles, p->grid, 0, nullptr, 0, D, p->nbox, none, xt, r, shift, inv,
+                        Y, nullptr, s);
     if (rc) return rc;
     scatter_batch_launch(D, p->nbox, p->blk_fine, Y, xt, xcorr, s);
     rhs_batch_launch(D, p->nbox, p->tiles, xcorr, b, s);
@@ -185,7 +188,7 @@ extern "C" int dnnmg_plan_autotune(dnnmg_plan *p, const dnnmg_mlp *net, const fl
     hipStream_t s = (hipStream_t)stream;
     // inputs of the network stage
     prolong_batch_launch(p->d_desc, p->nbox, p->blk_coarse, xc, xt, s);
-    residual_batch_launch(p->d_desc, p->nbox, p->tiles, p->blk_coarse, xt, vprev, r, p->aux, s);
+    residual_batch_launch(p->d_desc, p->nbox, p->tiles, p->blk_coarse, xt, vprev, r, p->aux, p->tflag, s);
     int dev = 0, ncu = 256;
     if ((rc = hip_check(hipGetDevice(&dev), "autotune device"))) return rc;
     if ((rc = hip_check(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev), "autotune CU count")))
@@ -197,53 +200,52 @@ extern "C" int dnnmg_plan_autotune(dnnmg_plan *p, const dnnmg_mlp *net, const fl
         return rc;
     }
     float best = 1e30f;
-    int best_np = p->np, best_grid = p->grid;
-    const int nps[2] = {1, 2};
-    for (int npi = 0; npi < 2 && !rc; ++npi) {
-        int np = nps[npi];
-        // NP = 2 is built for BF16 (H <= 256) and FP8 networks
-        bool has2 = (net->dtype == DNNMG_BF16 && net->hidden <= 256) || net->dtype == DNNMG_FP8_E4M3;
-        if (np == 2 && !has2) continue;
-        p->np = np;
-        // recompute the patch-tile prefix for this tile size and upload
+    int best_pt = p->pt, best_grid = p->grid;
+    auto set_pt = [&](int pt) {
+        p->pt = pt;
         int64_t bp = 0;
         for (auto &d : p->desc) {
             d.blk_ptile = bp;
-            bp += (d.m.n_patches + 64 * np - 1) / (64 * np);
+            bp += (d.m.n_patches + 16 * pt - 1) / (16 * pt);
         }
         p->ptiles = bp;
-        if ((rc = upload(p, s))) break;
-        const int grids[5] = {0, ncu, 2 * ncu, 4 * ncu, 8 * ncu};
-        for (int gi = 0; gi < 5 && !rc; ++gi) {
+        // the host table is rewritten for the next candidate: finish the copy
+        int e = upload(p, s);
+        return e ? e : hip_check(hipStreamSynchronize(s), "autotune upload");
+    };
+    const int pts[3] = {1, 2, 4};
+    for (int pi = 0; pi < 3 && !rc; ++pi) {
+        const int pt = pts[pi];
+        if (!fwd_has_pt(net, pt)) continue;
+        if ((rc = set_pt(pt))) break;
+        const int grids[4] = {0, ncu, 2 * ncu, 4 * ncu};
+        for (int gi = 0; gi < 4 && !rc; ++gi) {
             int grid = grids[gi];
-            if (grid > p->ptiles) continue;
+            if (grid >= p->ptiles) continue;
             BoxDesc none{};
-            gather_fwd_launch(net, np, p->d_desc, p->nbox, none, p->ptiles, grid, xt, r, shift, inv_scale, Y, s);
+            auto launch = [&]() {
+                return fwd_launch(net, pt, true, p->ptiles, grid, 0, nullptr, 0, p->d_desc, p->nbox, none, xt, r,
+                                  shift, inv_scale, Y, nullptr, s);
+            };
+            if ((rc = launch())) break;
             if ((rc = hip_check(hipEventRecord(e0, s), "autotune event record"))) break;
-            for (int k = 0; k < reps; ++k)
-                gather_fwd_launch(net, np, p->d_desc, p->nbox, none, p->ptiles, grid, xt, r, shift, inv_scale, Y, s);
+            for (int k = 0; k < reps && !rc; ++k) rc = launch();
+            if (rc) break;
             if ((rc = hip_check(hipEventRecord(e1, s), "autotune event record"))) break;
             if ((rc = hip_check(hipEventSynchronize(e1), "autotune launch"))) break;
             float ms = 0.f;
             if ((rc = hip_check(hipEventElapsedTime(&ms, e0, e1), "autotune timing"))) break;
             if (ms < best) {
                 best = ms;
-                best_np = np;
+                best_pt = pt;
                 best_grid = grid;
             }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    p->np = best_np;
     p->grid = best_grid;
-    int64_t bp = 0;
-    for (auto &d : p->desc) {
-        d.blk_ptile = bp;
-        bp += (d.m.n_patches + 64 * p->np - 1) / (64 * p->np);
-    }
-    p->ptiles = bp;
-    if (!rc) rc = upload(p, s);
+    if (!rc) rc = set_pt(best_pt);
     if (!rc) rc = hip_check(hipStreamSynchronize(s), "autotune sync");
     return rc;
 }

@@ -11,8 +11,8 @@
 // that permuted order, so no LDS transpose is needed between layers.
 //
 // Element types: FP32 (v_mfma_f32_16x16x4f32), BF16 (v_mfma_f32_16x16x32_bf16)
-// and OCP FP8 E4M3 (v_mfma_f32_16x16x32_fp8_fp8) with per-tensor scales; all
-// accumulate in FP32 and apply bias and tanh in FP32.
+// and OCP FP8 E4M3 (v_mfma_scale_f32_16x16x128_f8f6f4) with per-tensor
+// scales; all accumulate in FP32 and apply bias and tanh in FP32.
 #include "common.hpp"
 #include "lowp.hpp"
 #include "mlp.hpp"
@@ -38,7 +38,10 @@ __host__ __device__ constexpr int kind_bytes(int k) { return k == KF32 ? 4 : (k 
 
 // ------------------------------------------------------------- packing ----
 // Fragment (ot, kc) of a layer: 64 lanes x E elements; lane 16 g + i holds
-// the weights of output unit 16 ot + i for the K slots (kc, g, e).  Layer-1
+// the weights of output unit 16 ot + i for the K slots (kc, g, e).  The
+// fragments are stored K-chunk major (kc, ot): the fragments all waves read
+// at one step of the K loop are contiguous, which spreads the concurrent
+// reads of many workgroups over the memory channels.  Layer-1
 // slots are the input columns in order.  Hidden inputs arrive in the
 // accumulator layout of the previous layer (lane 16 g + p holds units
 // 16 t + 4 g + 0..3 of tile t), so slot (kc, g, e) is unit
@@ -59,8 +62,8 @@ __global__ void k_pack(int kind, int layer, int fan_in, int fan_out, int ntiles,
     if (t >= total) return;
     int e = (int)(t % E);
     int lane = (int)((t / E) % 64);
-    int kc = (int)((t / (E * 64)) % nchunks);
-    int ot = (int)(t / ((int64_t)E * 64 * nchunks));
+    int ot = (int)((t / (E * 64)) % ntiles);
+    int kc = (int)(t / ((int64_t)E * 64 * ntiles));
     int g = lane >> 4, i = lane & 15;
     int o = 16 * ot + i;
     int k = kslot_to_input(kind, layer, kc, g, e);
@@ -71,6 +74,16 @@ __global__ void k_pack(int kind, int layer, int fan_in, int fan_out, int ntiles,
 }
 
 // ------------------------------------------------------------- forward ----
+// A workgroup of NW waves takes tiles of 16 PT patches.  Each layer's input
+// lives in LDS in the B-fragment layout of its MFMA kind: fragment (t, kc)
+// of patch tile t and K chunk kc is 64 lanes x FB bytes at
+// ((t NCH + kc) 64 + lane) FB.  Output tile ot (16 units) of a layer is
+// computed by wave ot % NW for all PT patch tiles, so every weight fragment
+// (A operand, read from global memory where it stays cache resident) feeds
+// PT products and every activation fragment read from LDS feeds the
+// wave's output tiles.  Bias, tanh and the conversion to the next layer's
+// element type are applied on the accumulators, which are written straight
+// into the next layer's LDS fragments.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -80,6 +93,8 @@ template <int K> struct Frag;
 template <> struct Frag<KF32> { using T = float; };
 template <> struct Frag<KBF16> { using T = u32x4; };  // 8 bf16
 template <> struct Frag<KFP8> { using T = i32x8; };   // 32 fp8
+
+__host__ __device__ constexpr int frag_bytes(int k) { return k == KF32 ? 4 : (k == KBF16 ? 16 : 32); }
 
 template <int K>
 __device__ __forceinline__ f32x4 mfma(typename Frag<K>::T a, typename Frag<K>::T b, f32x4 c) {
@@ -103,66 +118,83 @@ __device__ __forceinline__ float act(float z) {
     else return tanh_fast(z);
 }
 
-// Activations of 4 units (one accumulator of output tile ot) into the B
-// fragments of a layer of kind K (see kslot_to_input).
-template <int K>
-__device__ __forceinline__ void put_act(typename Frag<K>::T *B, int ot, const float v[4], float qinv) {
-    if constexpr (K == KF32) {
+// Activations v[0..3] of units 16 ot + 4 g + e of patch p (lane 16 g + p) of
+// patch tile t into the next layer's LDS fragments (kind KN, NCHN chunks);
+// see kslot_to_input for the slot order.
+template <int KN, int NCHN>
+__device__ __forceinline__ void put_act(unsigned char *out, int t, int ot, int lane, const float v[4], float qinv) {
+    if constexpr (KN == KF32) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) B[4 * ot + e] = v[e];
-    } else if constexpr (K == KBF16) {
-        int kc = ot >> 1, half = ot & 1;
-        B[kc][2 * half] = pack_bf16x2(v[0], v[1]);
-        B[kc][2 * half + 1] = pack_bf16x2(v[2], v[3]);
+        for (int e = 0; e < 4; ++e) ((float *)out)[(t * NCHN + 4 * ot + e) * 64 + lane] = v[e];
+    } else if constexpr (KN == KBF16) {
+        uint2 w = make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
+        *(uint2 *)(out + ((t * NCHN + (ot >> 1)) * 64 + lane) * 16 + 8 * (ot & 1)) = w;
     } else {
-        int kc = ot >> 3, q = ot & 7;
         uint32_t w = 0;
 #pragma unroll
         for (int e = 0; e < 4; ++e) w |= (uint32_t)f32_to_e4m3(v[e] * qinv) << (8 * e);
-        B[kc][q] = (int)w;
+        *(uint32_t *)(out + ((t * NCHN + (ot >> 3)) * 64 + lane) * 32 + 4 * (ot & 7)) = w;
     }
 }
 
-// One dense layer on the wave's NP patch tiles: acc = W^T B, then bias and
-// (unless LAST) tanh into the next layer's fragments.
-template <int K, int KNEXT, int NTILES, int NCH, int NP, bool LAST, int H>
+// One dense layer for the tile: acc = W^T B over the wave's output tiles,
+// then bias and (unless LAST) tanh into the next layer's fragments, or (LAST)
+// the output rows.
+template <int K, int KN, int NTILES, int NCH, int PT, bool LAST, int H, int NW>
 __device__ __forceinline__ void layer(const typename Frag<K>::T *__restrict__ Wl, const float *__restrict__ bias,
-                                      const typename Frag<K>::T (&B)[NP][NCH],
-                                      typename Frag<KNEXT>::T (&Bn)[NP][H / (4 * kind_E(KNEXT))],
-                                      float scale, float qinv, int lane, int g, int p, int64_t base,
-                                      int64_t n, float *__restrict__ Y, void *__restrict__ saved,
-                                      int64_t save_off, int save_bytes) {
+                                      const unsigned char *in, unsigned char *out, float scale, float qinv,
+                                      int wave, int lane, int64_t base, int64_t n, float *__restrict__ Y,
+                                      void *__restrict__ saved, int64_t save_off, int save_bytes) {
+    using FA = typename Frag<K>::T;
+    constexpr int OTW = (NTILES + NW - 1) / NW;
+    constexpr int NCHN = LAST ? 1 : H / (4 * kind_E(KN));
+    const int g = lane >> 4, p = lane & 15;
+    f32x4 acc[OTW][PT];
 #pragma unroll
-    for (int ot = 0; ot < NTILES; ++ot) {
-        f32x4 acc[NP];
+    for (int i = 0; i < OTW; ++i)
 #pragma unroll
-        for (int t = 0; t < NP; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < PT; ++t) acc[i][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // two K chunks per step: the weight loads of a step are issued together
+#pragma unroll 2
+    for (int kc = 0; kc < NCH; ++kc) {
+        FA b[PT];
 #pragma unroll
-        for (int kc = 0; kc < NCH; ++kc) {
-            typename Frag<K>::T a = Wl[((int64_t)ot * NCH + kc) * 64 + lane];
+        for (int t = 0; t < PT; ++t) b[t] = ((const FA *)in)[(t * NCH + kc) * 64 + lane];
 #pragma unroll
-            for (int t = 0; t < NP; ++t) acc[t] = mfma<K>(a, B[t][kc], acc[t]);
+        for (int i = 0; i < OTW; ++i) {
+            const int ot = wave + NW * i;
+            if (NTILES % NW == 0 || ot < NTILES) {
+                FA a = Wl[((int64_t)kc * NTILES + ot) * 64 + lane];
+#pragma unroll
+                for (int t = 0; t < PT; ++t) acc[i][t] = mfma<K>(a, b[t], acc[i][t]);
+            }
         }
-        if constexpr (LAST) {
+    }
 #pragma unroll
-            for (int t = 0; t < NP; ++t) {
-                int64_t row = base + 16 * t + p;
-                if (row >= n) continue;
+    for (int i = 0; i < OTW; ++i) {
+        const int ot = wave + NW * i;
+        if (!(NTILES % NW == 0 || ot < NTILES)) continue;
+        if constexpr (LAST) {
+            // outputs of the tile to LDS rows [16 t + p][81]; written out
+            // contiguously afterwards
+            float *ys = (float *)out;
+#pragma unroll
+            for (int t = 0; t < PT; ++t) {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     int o = 16 * ot + 4 * g + e;
-                    if (o < N_OUT) Y[row * N_OUT + o] = acc[t][e] * scale + bias[o];
+                    if (o < N_OUT) ys[(16 * t + p) * N_OUT + o] = acc[i][t][e] * scale + bias[o];
                 }
             }
         } else {
             const float4 bb = *(const float4 *)(bias + 16 * ot + 4 * g);
             const float bv[4] = {bb.x, bb.y, bb.z, bb.w};
 #pragma unroll
-            for (int t = 0; t < NP; ++t) {
+            for (int t = 0; t < PT; ++t) {
                 float v[4];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) v[e] = act<K>(acc[t][e] * scale + bv[e]);
-                put_act<KNEXT>(Bn[t], ot, v, qinv);
+                for (int e = 0; e < 4; ++e) v[e] = act<K>(acc[i][t][e] * scale + bv[e]);
+                put_act<KN, NCHN>(out, t, ot, lane, v, qinv);
                 if (saved) {
                     int64_t row = base + 16 * t + p;
                     if (row < n) {
@@ -179,191 +211,252 @@ __device__ __forceinline__ void layer(const typename Frag<K>::T *__restrict__ Wl
     }
 }
 
-template <int DT, int H, int NP>
-__global__ void __launch_bounds__(256)
-    k_mlp_fwd(int64_t n, const void *__restrict__ Xv, int64_t ldx, const void *__restrict__ W0,
-              const void *__restrict__ W1, const void *__restrict__ W2, const float *__restrict__ b0,
-              const float *__restrict__ b1, const float *__restrict__ b2, float *__restrict__ Y,
-              void *__restrict__ saved, float s0, float s1, float s2, float q1inv, float q2inv) {
-    constexpr int K1 = layer_kind(DT, 0), K2 = layer_kind(DT, 1), K3 = layer_kind(DT, 2);
-    constexpr int NCH0 = IN_PAD / (4 * kind_E(K1));
-    constexpr int NCH1 = H / (4 * kind_E(K2));
-    constexpr int NCH2 = H / (4 * kind_E(K3));
-    using F1 = typename Frag<K1>::T;
-    using F2 = typename Frag<K2>::T;
-    using F3 = typename Frag<K3>::T;
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int g = lane >> 4, p = lane & 15;
-    const int64_t base = ((int64_t)blockIdx.x * 4 + wave) * 16 * NP;
-    if (base >= n) return;
-    const int sbytes = DT == DNNMG_F32 ? 4 : 2;
+// LDS sizes of the forward kernels: buffer 0 holds the network input, then
+// the layer-3 input; buffer 1 the layer-2 input.
+template <int DT, int H, int PT>
+struct FwdShape {
+    static constexpr int K1 = layer_kind(DT, 0), K2 = layer_kind(DT, 1), K3 = layer_kind(DT, 2);
+    static constexpr int NCH0 = IN_PAD / (4 * kind_E(K1));
+    static constexpr int NCH1 = H / (4 * kind_E(K2));
+    static constexpr int NCH2 = H / (4 * kind_E(K3));
+    static constexpr int IN0 = PT * NCH0 * 64 * frag_bytes(K1);
+    static constexpr int IN1 = PT * NCH1 * 64 * frag_bytes(K2);
+    static constexpr int IN2 = PT * NCH2 * 64 * frag_bytes(K3);
+    static constexpr int YB = 16 * PT * N_OUT * 4; // output rows of the tile
+    static constexpr int BUF0 = IN0 > IN2 ? IN0 : IN2;
+    static constexpr int BUF1 = IN1 > YB ? IN1 : YB;
+    // waves per workgroup: 64-patch tiles take 8 waves (two output tiles of
+    // a hidden layer each), smaller tiles 4
+    static constexpr int NW = PT == 4 ? 8 : 4;
+    static constexpr int NTHR = 64 * NW;
+};
 
-    // layer-1 input fragments straight from the gathered rows (row-major,
-    // E consecutive columns per lane)
-    F1 Bx[NP][NCH0];
+// Network input rows X [n][ldx] (FP32 or BF16) of patches base .. base + 16 PT
+// into the layer-1 fragments: one thread per 16-byte piece of a row, so the
+// rows are read contiguously.
+template <int K1, int NCH0, int PT, int NTHR>
+__device__ __forceinline__ void stage_rows(const void *__restrict__ Xv, int64_t ldx, int64_t base, int64_t n,
+                                           unsigned char *buf, int tid) {
+    constexpr int PIECES = IN_PAD * kind_bytes(K1) / 16; // 16-byte pieces per row
+    for (int it = tid; it < 16 * PT * PIECES; it += NTHR) {
+        const int pl = it / PIECES, pc = it - pl * PIECES;
+        const int64_t row = base + pl;
+        const int t = pl >> 4, p = pl & 15;
+        u32x4 v = u32x4{0u, 0u, 0u, 0u};
+        if (row < n) v = *(const u32x4 *)((const unsigned char *)Xv + (row * ldx) * kind_bytes(K1) + 16 * pc);
+        if constexpr (K1 == KF32) {
+            // columns 4 pc .. 4 pc + 3: chunk pc, lane 16 g + p for g = 0..3
 #pragma unroll
-    for (int t = 0; t < NP; ++t) {
-        int64_t row = base + 16 * t + p;
-#pragma unroll
-        for (int kc = 0; kc < NCH0; ++kc) {
-            if (row < n) {
-                if constexpr (K1 == KF32)
-                    Bx[t][kc] = ((const float *)Xv)[row * ldx + kc * 4 + g];
-                else
-                    Bx[t][kc] = *(const F1 *)((const uint16_t *)Xv + row * ldx + kc * 32 + g * 8);
-            } else {
-                Bx[t][kc] = F1{};
-            }
+            for (int g = 0; g < 4; ++g) ((uint32_t *)buf)[(t * NCH0 + pc) * 64 + 16 * g + p] = v[g];
+        } else {
+            // columns 8 pc .. 8 pc + 7: chunk pc / 4, lane 16 (pc % 4) + p
+            *(u32x4 *)(buf + ((t * NCH0 + (pc >> 2)) * 64 + 16 * (pc & 3) + p) * 16) = v;
         }
     }
-    F2 Ba[NP][NCH1];
-    layer<K1, K2, H / 16, NCH0, NP, false, H>((const F1 *)W0, b0, Bx, Ba, s0, q1inv, lane, g, p, base, n,
-                                              Y, saved, 0, sbytes);
-    F3 Bb[NP][NCH2];
-    layer<K2, K3, H / 16, NCH1, NP, false, H>((const F2 *)W1, b1, Ba, Bb, s1, q2inv, lane, g, p, base, n,
-                                              Y, saved, n * H, sbytes);
-    F3 dummy[NP][H / (4 * kind_E(K3))];
-    layer<K3, K3, OUT_PAD / 16, NCH2, NP, true, H>((const F3 *)W2, b2, Bb, dummy, s2, 1.f, lane, g, p,
-                                                   base, n, Y, nullptr, 0, sbytes);
 }
 
-// ---------------------------------------------- fused gather + network ----
-// Layer-1 fragments built directly from the node fields (operator Q of
-// eq. (defQ) with the standardisation), so the gathered batch never goes
-// through HBM.  Column col of the input row of patch (I,J,K): field
-// col / 27 of [u, v, w, r_u, r_v, r_w] at local node col % 27; 162..164 the
-// coarse cell sizes; zero padding to 192.
-__device__ __forceinline__ float input_col(const Mesh &m, int I, int J, int K, int col,
-                                           const float *__restrict__ xt, const float *__restrict__ r,
-                                           const float *__restrict__ shift, const float *__restrict__ inv) {
-    if (col >= N_IN) return 0.0f;
-    float v;
-    if (col < 162) {
-        int c = col / 27, iota = col - 27 * c;
-        int a = iota % 3, b = (iota / 3) % 3, cc = iota / 9;
-        int i = wrap(2 * I + a, m.nf[0], m.per[0]);
-        int j = wrap(2 * J + b, m.nf[1], m.per[1]);
-        int k = wrap(2 * K + cc, m.nf[2], m.per[2]);
-        int64_t node = i + (int64_t)m.nf[0] * (j + (int64_t)m.nf[1] * k);
-        v = c < 3 ? xt[c * m.n_fine + node] : r[(c - 3) * m.n_fine + node];
+// One input value of patch slot pl, column col, into the layer-1 fragments.
+template <int K1, int NCH0>
+__device__ __forceinline__ void put_input(unsigned char *buf, int pl, int col, float v) {
+    const int t = pl >> 4, p = pl & 15;
+    if constexpr (K1 == KF32) {
+        ((float *)buf)[(t * NCH0 + (col >> 2)) * 64 + 16 * (col & 3) + p] = v;
     } else {
-        v = m.H[col - 162];
+        const int w = col & 31;
+        *(uint16_t *)(buf + ((t * NCH0 + (col >> 5)) * 64 + 16 * (w >> 3) + p) * 16 + 2 * (w & 7)) = f32_to_bf16(v);
     }
-    if (shift) v -= shift[col];
-    if (inv) v *= inv[col];
-    return v;
 }
 
-// Persistent: blocks walk the 64-patch tiles of all boxes (tile -> box by
-// the prefix sums blk_ptile); D == nullptr means the single box `one`.
-template <int DT, int H, int NP>
-__global__ void __launch_bounds__(256)
-    k_mlp_gather_fwd(const BoxDesc *__restrict__ D, int nbox, BoxDesc one, int64_t ntiles,
-                     const float *__restrict__ xt_all, const float *__restrict__ r_all,
-                     const float *__restrict__ shift, const float *__restrict__ inv,
-                     const void *__restrict__ W0, const void *__restrict__ W1, const void *__restrict__ W2,
-                     const float *__restrict__ b0, const float *__restrict__ b1, const float *__restrict__ b2,
-                     float *__restrict__ Y_all, float s1, float q1inv) {
-    constexpr int K1 = layer_kind(DT, 0), K2 = layer_kind(DT, 1), K3 = layer_kind(DT, 2);
-    constexpr int E1 = kind_E(K1);
-    constexpr int NCH0 = IN_PAD / (4 * E1);
-    constexpr int NCH1 = H / (4 * kind_E(K2));
-    constexpr int NCH2 = H / (4 * kind_E(K3));
-    using F1 = typename Frag<K1>::T;
-    using F2 = typename Frag<K2>::T;
-    using F3 = typename Frag<K3>::T;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int g = lane >> 4, p = lane & 15;
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int b = D ? find_box(nbox, tile, [&](int i) { return D[i].blk_ptile; }) : 0;
-        const BoxDesc &d = D ? D[b] : one;
-        const Mesh m = d.m;
-        const float *xt = xt_all + 4 * d.off_fine;
-        const float *r = r_all + 4 * d.off_fine;
-        float *Y = Y_all + 81 * d.off_patch;
-        const int64_t n = m.n_patches;
-        const int64_t base = (tile - d.blk_ptile) * 64 * NP + 16 * NP * wave;
-        if (base >= n) continue; // wave-uniform; no block-wide barrier below
-        F1 Bx[NP][NCH0];
+// Operator Q of eq. (defQ) with the standardisation, straight into the
+// layer-1 fragments: input column 27 c + iota of patch (I,J,K) is field c of
+// [u, v, w, r_u, r_v, r_w] at local node iota = a + 3 b + 9 c'; columns
+// 162..164 are the coarse cell sizes, 165..191 zero.
+template <int K1, int NCH0, int PT, int NTHR>
+__device__ __forceinline__ void stage_gather(const Mesh &m, const float *__restrict__ xt, const float *__restrict__ r,
+                                             const float *__restrict__ shift, const float *__restrict__ inv,
+                                             int64_t base, int64_t n, unsigned char *buf, int tid) {
+    for (int it = tid; it < 16 * PT * 27; it += NTHR) {
+        const int pl = it / 27, iota = it - 27 * pl;
+        const int64_t row = base + pl;
+        float v[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (row < n) {
+            uint32_t JK = fdiv((uint32_t)row, m.px);
+            const int I = (int)((uint32_t)row - JK * m.n[0]);
+            const int K = (int)fdiv(JK, m.py);
+            const int J = (int)(JK - (uint32_t)K * m.n[1]);
+            const int a = iota % 3, b = (iota / 3) % 3, c = iota / 9;
+            const int i = wrap(2 * I + a, m.nf[0], m.per[0]);
+            const int j = wrap(2 * J + b, m.nf[1], m.per[1]);
+            const int k = wrap(2 * K + c, m.nf[2], m.per[2]);
+            const int64_t node = i + (int64_t)m.nf[0] * (j + (int64_t)m.nf[1] * k);
 #pragma unroll
-        for (int t = 0; t < NP; ++t) {
-            const int64_t row = base + 16 * t + p;
-            int I = 0, J = 0, K = 0;
-            if (row < n) {
-                uint32_t JK = fdiv((uint32_t)row, m.px);
-                I = (int)((uint32_t)row - JK * m.n[0]);
-                K = (int)fdiv(JK, m.py);
-                J = (int)(JK - (uint32_t)K * m.n[1]);
+            for (int f = 0; f < 3; ++f) {
+                v[f] = xt[f * m.n_fine + node];
+                v[3 + f] = r[f * m.n_fine + node];
             }
 #pragma unroll
-            for (int kc = 0; kc < NCH0; ++kc) {
-                if constexpr (K1 == KF32) {
-                    Bx[t][kc] = row < n ? input_col(m, I, J, K, kc * 4 + g, xt, r, shift, inv) : 0.0f;
-                } else {
-                    float v[8];
-#pragma unroll
-                    for (int e = 0; e < 8; ++e)
-                        v[e] = row < n ? input_col(m, I, J, K, kc * 32 + g * 8 + e, xt, r, shift, inv) : 0.0f;
-                    F1 f;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) f[q] = pack_bf16x2(v[2 * q], v[2 * q + 1]);
-                    Bx[t][kc] = f;
-                }
+            for (int f = 0; f < 6; ++f) {
+                const int col = 27 * f + iota;
+                if (shift) v[f] -= shift[col];
+                if (inv) v[f] *= inv[col];
             }
         }
-        F2 Ba[NP][NCH1];
-        layer<K1, K2, H / 16, NCH0, NP, false, H>((const F1 *)W0, b0, Bx, Ba, 1.0f, q1inv, lane, g, p, base, n,
-                                                  Y, nullptr, 0, 2);
-        F3 Bb[NP][NCH2];
-        layer<K2, K3, H / 16, NCH1, NP, false, H>((const F2 *)W1, b1, Ba, Bb, s1, 1.0f, lane, g, p, base, n, Y,
-                                                  nullptr, 0, 2);
-        F3 dummy[NP][H / (4 * kind_E(K3))];
-        layer<K3, K3, OUT_PAD / 16, NCH2, NP, true, H>((const F3 *)W2, b2, Bb, dummy, 1.0f, 1.0f, lane, g, p,
-                                                       base, n, Y, nullptr, 0, 2);
+#pragma unroll
+        for (int f = 0; f < 6; ++f) put_input<K1, NCH0>(buf, pl, 27 * f + iota, v[f]);
+    }
+    for (int it = tid; it < 16 * PT * (IN_PAD - 162); it += NTHR) {
+        const int pl = it / (IN_PAD - 162), col = 162 + (it - pl * (IN_PAD - 162));
+        float v = 0.0f;
+        if (col < N_IN && base + pl < n) {
+            v = m.H[col - 162];
+            if (shift) v -= shift[col];
+            if (inv) v *= inv[col];
+        }
+        put_input<K1, NCH0>(buf, pl, col, v);
     }
 }
 
-int gather_fwd_launch(const dnnmg_mlp *net, int np, const BoxDesc *D, int nbox, const BoxDesc &one,
-                      int64_t ntiles, int grid, const float *xt, const float *r, const float *shift,
-                      const float *inv, float *Y, hipStream_t s) {
-    float s1 = 1.f, q1 = 1.f;
+// Forward pass over tiles of 16 PT patches.  GATHER = false: the inputs are
+// the rows of X and tile t covers rows 16 PT t ..; GATHER = true: the inputs
+// are gathered from the node fields of the boxes (D, or the single box `one`
+// when D is null), and tile -> box by the prefix sums blk_ptile.  Workgroups
+// walk the tiles with stride gridDim.x; every thread of a workgroup takes the
+// same tiles, so the barriers inside the loop are uniform.
+template <int DT, int H, int PT, bool GATHER>
+__global__ void __launch_bounds__((FwdShape<DT, H, PT>::NTHR))
+    k_mlp_fwd(int64_t ntiles, int64_t n_rows, const void *__restrict__ Xv, int64_t ldx,
+              const BoxDesc *__restrict__ D, int nbox, BoxDesc one, const float *__restrict__ xt_all,
+              const float *__restrict__ r_all, const float *__restrict__ shift, const float *__restrict__ inv,
+              const void *__restrict__ W0, const void *__restrict__ W1, const void *__restrict__ W2,
+              const float *__restrict__ b0, const float *__restrict__ b1, const float *__restrict__ b2,
+              float *__restrict__ Y_all, void *__restrict__ saved, float s1, float q1inv) {
+    using S = FwdShape<DT, H, PT>;
+    using F1 = typename Frag<S::K1>::T;
+    using F2 = typename Frag<S::K2>::T;
+    using F3 = typename Frag<S::K3>::T;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[S::BUF0 + S::BUF1];
+    unsigned char *buf0 = smem, *buf1 = smem + S::BUF0;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int sbytes = DT == DNNMG_F32 ? 4 : 2;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        int64_t base, n;
+        float *Y = Y_all;
+        if constexpr (GATHER) {
+            const int b = D ? find_box(nbox, tile, [&](int i) { return D[i].blk_ptile; }) : 0;
+            const BoxDesc &d = D ? D[b] : one;
+            n = d.m.n_patches;
+            base = (tile - d.blk_ptile) * 16 * PT;
+            Y = Y_all + 81 * d.off_patch;
+            stage_gather<S::K1, S::NCH0, PT, S::NTHR>(d.m, xt_all + 4 * d.off_fine, r_all + 4 * d.off_fine, shift, inv,
+                                             base, n, buf0, tid);
+        } else {
+            n = n_rows;
+            base = tile * 16 * PT;
+            stage_rows<S::K1, S::NCH0, PT, S::NTHR>(Xv, ldx, base, n, buf0, tid);
+        }
+        __syncthreads();
+        layer<S::K1, S::K2, H / 16, S::NCH0, PT, false, H, S::NW>((const F1 *)W0, b0, buf0, buf1, 1.0f, q1inv, wave,
+                                                          lane, base, n, Y, saved, 0, sbytes);
+        __syncthreads();
+        layer<S::K2, S::K3, H / 16, S::NCH1, PT, false, H, S::NW>((const F2 *)W1, b1, buf1, buf0, s1, 1.0f, wave, lane,
+                                                          base, n, Y, saved, n * H, sbytes);
+        __syncthreads();
+        layer<S::K3, S::K3, OUT_PAD / 16, S::NCH2, PT, true, H, S::NW>((const F3 *)W2, b2, buf0, buf1, 1.0f, 1.0f,
+                                                                        wave, lane, base, n, Y, nullptr, 0, sbytes);
+        __syncthreads();
+        {
+            // the tile's rows are contiguous in Y
+            const int cnt = (int)((n - base < 16 * PT ? n - base : 16 * PT) * N_OUT);
+            const float *ys = (const float *)buf1;
+            float *yd = Y + base * N_OUT;
+            int q0 = 0;
+            if ((((uintptr_t)yd) & 15) == 0) {
+                for (int q = tid; q < cnt / 4; q += S::NTHR) ((float4 *)yd)[q] = ((const float4 *)ys)[q];
+                q0 = cnt / 4 * 4;
+            }
+            for (int q = q0 + tid; q < cnt; q += S::NTHR) yd[q] = ys[q];
+        }
+        __syncthreads();
+    }
+}
+
+static void fp8_scales(const dnnmg_mlp *net, float &s1, float &q1) {
+    s1 = 1.f;
+    q1 = 1.f;
     if (net->dtype == DNNMG_FP8_E4M3) {
-        s1 = net->w_scale[1] * net->a_scale[1];
-        q1 = 1.0f / net->a_scale[1];
-    }
-    if (grid <= 0 || grid > ntiles) grid = (int)ntiles;
-#define GF(DT, HH, NPV)                                                                                  \
-    if (net->dtype == DT && net->hidden == HH && np == NPV) {                                           \
-        k_mlp_gather_fwd<DT, HH, NPV><<<grid, 256, 0, s>>>(D, nbox, one, ntiles, xt, r, shift, inv,      \
-                                                           net->W[0], net->W[1], net->W[2], net->b[0],  \
-                                                           net->b[1], net->b[2], Y, s1, q1);             \
-        return hip_check(hipGetLastError(), "fused gather+forward launch");                             \
-    }
-    GF(DNNMG_F32, 128, 1) GF(DNNMG_F32, 256, 1)
-    GF(DNNMG_BF16, 128, 1) GF(DNNMG_BF16, 256, 1) GF(DNNMG_BF16, 512, 1)
-    GF(DNNMG_BF16, 128, 2) GF(DNNMG_BF16, 256, 2)
-    GF(DNNMG_FP8_E4M3, 256, 1) GF(DNNMG_FP8_E4M3, 512, 1) GF(DNNMG_FP8_E4M3, 256, 2) GF(DNNMG_FP8_E4M3, 512, 2)
-#undef GF
-    return fail(DNNMG_ERR_UNSUPPORTED, "fused gather+forward: dtype %d width %d", net->dtype, net->hidden);
-}
-
-template <int DT, int H, int NP>
-static int launch_fwd(const dnnmg_mlp *net, int64_t n, const void *X, int64_t ldx, float *Y,
-                      void *saved, hipStream_t s) {
-    float s0 = 1.f, s1 = 1.f, s2 = 1.f, q1 = 1.f, q2 = 1.f;
-    if (DT == DNNMG_FP8_E4M3) {
         // only the hidden product is FP8: its weights (w_scale[1]) and its
         // input activations (a_scale[1]) carry scales
         s1 = net->w_scale[1] * net->a_scale[1];
         q1 = 1.0f / net->a_scale[1];
     }
-    int64_t per_block = 4 * 16 * NP;
-    unsigned grid = (unsigned)((n + per_block - 1) / per_block);
-    k_mlp_fwd<DT, H, NP><<<grid, 256, 0, s>>>(n, X, ldx, net->W[0], net->W[1], net->W[2], net->b[0],
-                                              net->b[1], net->b[2], Y, DT == DNNMG_FP8_E4M3 ? nullptr : saved,
-                                              s0, s1, s2, q1, q2);
-    return hip_check(hipGetLastError(), "dnnmg_patch_forward launch");
+}
+
+// Instantiated (dtype, width, PT) forward variants.
+#define DNNMG_FWD_VARIANTS(X)                                                                           \
+    X(DNNMG_F32, 64, 1) X(DNNMG_F32, 64, 2) X(DNNMG_F32, 128, 1) X(DNNMG_F32, 128, 2)                   \
+    X(DNNMG_F32, 256, 1) X(DNNMG_F32, 256, 2)                                                            \
+    X(DNNMG_BF16, 64, 1) X(DNNMG_BF16, 64, 2) X(DNNMG_BF16, 64, 4)                                       \
+    X(DNNMG_BF16, 128, 1) X(DNNMG_BF16, 128, 2) X(DNNMG_BF16, 128, 4)                                    \
+    X(DNNMG_BF16, 256, 1) X(DNNMG_BF16, 256, 2) X(DNNMG_BF16, 256, 4)                                    \
+    X(DNNMG_BF16, 512, 1) X(DNNMG_BF16, 512, 2) X(DNNMG_BF16, 512, 4)                                    \
+    X(DNNMG_FP8_E4M3, 128, 1) X(DNNMG_FP8_E4M3, 128, 2) X(DNNMG_FP8_E4M3, 128, 4)                        \
+    X(DNNMG_FP8_E4M3, 256, 1) X(DNNMG_FP8_E4M3, 256, 2) X(DNNMG_FP8_E4M3, 256, 4)                        \
+    X(DNNMG_FP8_E4M3, 512, 1) X(DNNMG_FP8_E4M3, 512, 2) X(DNNMG_FP8_E4M3, 512, 4)
+
+bool fwd_has_pt(const dnnmg_mlp *net, int pt) {
+#define HAS(DT, HH, P)                                                                                  \
+    if (net->dtype == DT && net->hidden == HH && pt == P) return true;
+    DNNMG_FWD_VARIANTS(HAS)
+#undef HAS
+    return false;
+}
+
+// Patches per tile of 16 PT: the largest instantiated PT that still gives
+// every compute unit a tile, else 1.
+int fwd_default_pt(const dnnmg_mlp *net, int64_t n, int ncu) {
+    for (int pt = 4; pt > 1; pt /= 2)
+        if (fwd_has_pt(net, pt) && n >= (int64_t)ncu * 16 * pt) return pt;
+    return 1;
+}
+
+int fwd_launch(const dnnmg_mlp *net, int pt, bool gather, int64_t ntiles, int grid, int64_t n_rows,
+               const void *X, int64_t ldx, const BoxDesc *D, int nbox, const BoxDesc &one, const float *xt,
+               const float *r, const float *shift, const float *inv, float *Y, void *saved, hipStream_t s) {
+    float s1, q1;
+    fp8_scales(net, s1, q1);
+    if (ntiles <= 0) return DNNMG_OK;
+    if (grid <= 0 || grid > ntiles) grid = (int)ntiles;
+#define LAUNCH(DT, HH, P)                                                                               \
+    if (net->dtype == DT && net->hidden == HH && pt == P) {                                             \
+        if (gather)                                                                                     \
+            k_mlp_fwd<DT, HH, P, true><<<grid, FwdShape<DT, HH, P>::NTHR, 0, s>>>(ntiles, 0, nullptr, 0, D, nbox, one, xt, r,  \
+                                                            shift, inv, net->W[0], net->W[1], net->W[2], \
+                                                            net->b[0], net->b[1], net->b[2], Y, nullptr, \
+                                                            s1, q1);                                     \
+        else                                                                                            \
+            k_mlp_fwd<DT, HH, P, false><<<grid, FwdShape<DT, HH, P>::NTHR, 0, s>>>(ntiles, n_rows, X, ldx, nullptr, 0, one,    \
+                                                             nullptr, nullptr, nullptr, nullptr,        \
+                                                             net->W[0], net->W[1], net->W[2], net->b[0], \
+                                                             net->b[1], net->b[2], Y, saved, s1, q1);    \
+        return hip_check(hipGetLastError(), "patch network forward launch");                            \
+    }
+    DNNMG_FWD_VARIANTS(LAUNCH)
+#undef LAUNCH
+    return fail(DNNMG_ERR_UNSUPPORTED, "patch network forward: dtype %d width %d tile %d", net->dtype,
+                net->hidden, pt);
+}
+
+int device_cus() {
+    static int ncu = 0;
+    if (!ncu) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            ncu = v;
+        else
+            ncu = 256;
+    }
+    return ncu;
 }
 
 int check_net(const dnnmg_mlp *net) {
@@ -435,8 +528,16 @@ extern "C" size_t dnnmg_patch_saved_bytes(const dnnmg_mlp *net, int64_t n) {
     return (size_t)2 * n * net->hidden * es;
 }
 
+extern "C" int dnnmg_patch_forward_tiles(const dnnmg_mlp *net, int64_t n, const void *X, int64_t ldx, float *Y,
+                                         void *saved, int tile_patches, int grid, void *stream);
+
 extern "C" int dnnmg_patch_forward(const dnnmg_mlp *net, int64_t n, const void *X, int64_t ldx,
                                    float *Y, void *saved, void *stream) {
+    return dnnmg_patch_forward_tiles(net, n, X, ldx, Y, saved, 0, 0, stream);
+}
+
+extern "C" int dnnmg_patch_forward_tiles(const dnnmg_mlp *net, int64_t n, const void *X, int64_t ldx, float *Y,
+                                         void *saved, int tile_patches, int grid, void *stream) {
     int rc = check_net(net);
     if (rc) return rc;
     if (n < 0) return fail(DNNMG_ERR_SHAPE, "dnnmg_patch_forward: n < 0");
@@ -450,15 +551,18 @@ extern "C" int dnnmg_patch_forward(const dnnmg_mlp *net, int64_t n, const void *
     if (saved && net->dtype == DNNMG_FP8_E4M3)
         return fail(DNNMG_ERR_UNSUPPORTED, "dnnmg_patch_forward: FP8 networks do not save activations");
     if (saved && !aligned16(saved)) return fail(DNNMG_ERR_ARG, "dnnmg_patch_forward: saved not aligned");
-    hipStream_t s = (hipStream_t)stream;
-    const int H = net->hidden;
-#define FWD(DT, HH, NP)                                                   \
-    if (net->dtype == DT && H == HH) return launch_fwd<DT, HH, NP>(net, n, X, ldx, Y, saved, s);
-    FWD(DNNMG_F32, 64, 1) FWD(DNNMG_F32, 128, 1) FWD(DNNMG_F32, 256, 1)
-    FWD(DNNMG_BF16, 64, 2) FWD(DNNMG_BF16, 128, 2) FWD(DNNMG_BF16, 256, 2) FWD(DNNMG_BF16, 512, 1)
-    FWD(DNNMG_FP8_E4M3, 128, 2) FWD(DNNMG_FP8_E4M3, 256, 2) FWD(DNNMG_FP8_E4M3, 512, 2)
-#undef FWD
-    return fail(DNNMG_ERR_UNSUPPORTED, "dnnmg_patch_forward: dtype %d width %d", net->dtype, H);
+    if (grid < 0) return fail(DNNMG_ERR_ARG, "dnnmg_patch_forward: grid < 0");
+    int pt = fwd_default_pt(net, n, device_cus());
+    if (tile_patches) {
+        pt = tile_patches / 16;
+        if (tile_patches % 16 || !fwd_has_pt(net, pt))
+            return fail(DNNMG_ERR_UNSUPPORTED, "dnnmg_patch_forward: %d patches per tile not built for this network",
+                        tile_patches);
+    }
+    const int64_t ntiles = (n + 16 * pt - 1) / (16 * pt);
+    BoxDesc none{};
+    return fwd_launch(net, pt, false, ntiles, grid, n, X, ldx, nullptr, 0, none, nullptr, nullptr, nullptr, nullptr,
+                      Y, saved, (hipStream_t)stream);
 }
 
 extern "C" int dnnmg_patch_gather_forward(const dnnmg_box *box, const dnnmg_mlp *net, const float *xt,
@@ -470,6 +574,8 @@ extern "C" int dnnmg_patch_gather_forward(const dnnmg_box *box, const dnnmg_mlp 
     if (!xt || !r || !Y) return fail(DNNMG_ERR_ARG, "dnnmg_patch_gather_forward: NULL pointer");
     const float *sh = feat ? feat->shift : nullptr;
     const float *sc = feat ? feat->inv_scale : nullptr;
-    int64_t ntiles = (one.m.n_patches + 63) / 64;
-    return gather_fwd_launch(net, 1, nullptr, 1, one, ntiles, 0, xt, r, sh, sc, Y, (hipStream_t)stream);
+    const int pt = fwd_default_pt(net, one.m.n_patches, device_cus());
+    const int64_t ntiles = (one.m.n_patches + 16 * pt - 1) / (16 * pt);
+    return fwd_launch(net, pt, true, ntiles, 0, 0, nullptr, 0, nullptr, 1, one, xt, r, sh, sc, Y, nullptr,
+                      (hipStream_t)stream);
 }

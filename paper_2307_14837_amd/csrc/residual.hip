@@ -22,6 +22,11 @@
 // integrals, each by three 1-D passes.
 #include "common.hpp"
 
+// Floating-point contraction only within a source expression: every kernel
+// instance (single box, batched, with or without forcing) then rounds the
+// same terms alike, and batched results equal single-box results bit for bit.
+#pragma clang fp contract(on)
+
 namespace dnnmg {
 
 // Gauss points on [0,1]: 1/2 -+ 1/(2 sqrt 3)
@@ -198,39 +203,37 @@ constexpr int MODE_RHS = 1;
 template <int MODE>
 struct ResTile {
     static constexpr int TX = 16, TY = 8, TZ = 4;  // owned nodes
+    static constexpr int NOWN = TX * TY * TZ;
     static constexpr int EX = TX + 1, EY = TY + 1, EZ = TZ + 1; // cells
     static constexpr int NCELL = EX * EY * EZ;
     // staged node range: [o-2, o+T] for x, p (patch corners), [o-1, o+T] for vp
     static constexpr int SX = TX + 3, SY = TY + 3, SZ = TZ + 3, SN = SX * SY * SZ;
     static constexpr int VX = TX + 2, VY = TY + 2, VZ = TZ + 2, VN = VX * VY * VZ;
     static constexpr int NPX = TX / 2, NPY = TY / 2, NPZ = TZ / 2, NP = NPX * NPY * NPZ;
-    static constexpr int NT = 256;
-    static constexpr int ROUNDS = (NCELL + NT - 1) / NT;
+    static constexpr int NT = 768; // one thread per cell (765 cells)
     static constexpr int NF_STAGE = MODE == MODE_RES ? 4 : 0; // x, p on the wide range
     static constexpr int NF_V = 3;                            // vp (res) or v (rhs)
     static constexpr int NACC = MODE == MODE_RES ? 4 : 3;
-    // Cells are assigned to threads sorted by colour (parity class), so a
-    // wave holds at most two colours and the colour phases of the LDS
-    // accumulation cost each wave little more than one pass.  Colour bit pa
-    // of axis a selects the cells whose global index has parity pa; the tile
-    // origin is even and the cell layer starts at origin - 1.
-    static constexpr int cnt(int E, int p) { return p ? (E + 1) / 2 : E / 2; }
-    static constexpr int csize(int c) { return cnt(EX, c & 1) * cnt(EY, (c >> 1) & 1) * cnt(EZ, c >> 2); }
-    static constexpr int cstart(int c) { return c == 0 ? 0 : cstart(c - 1) + csize(c - 1); }
+    static_assert(NT >= NCELL && NT >= NOWN && NT >= 8 * NP, "one pass per role");
 };
 
-// One tile (bx, by, bz) of owned nodes of one box.
+// One tile (bx, by, bz) of owned nodes of one box.  Thread e evaluates cell
+// e; per equation the cells' 8 vertex integrals go to an LDS cell array, and
+// after a barrier thread s < TX TY TZ sums the 8 cells around owned node s
+// in a fixed order (and, for the LPS corner terms, thread 8 P + j the 8
+// cells of owned patch P at corner j), so the sums need no atomics and the
+// result does not depend on scheduling.
 template <int MODE>
 __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P, int bx, int by, int bz,
                                               const float *__restrict__ x, const float *__restrict__ vp,
                                               const float *__restrict__ fmid, float *__restrict__ out,
-                                              float *__restrict__ aux) {
+                                              float *__restrict__ aux, int *__restrict__ tflag) {
     using T = ResTile<MODE>;
     __shared__ float sX[T::NF_STAGE > 0 ? T::NF_STAGE * T::SN : 1];
     __shared__ float sV[T::NF_V * T::VN];
-    __shared__ float sF[3 * T::VN]; // forcing, when given
-    __shared__ float sAcc[T::NACC * T::VN];
-    __shared__ float sAux[MODE == MODE_RES ? T::NP * 32 : 1];
+    __shared__ float sF[3 * T::VN];      // forcing, when given
+    __shared__ float sCell[8 * T::NCELL]; // [vertex j][cell]
+    __shared__ float sCor[MODE == MODE_RES ? 8 * T::NCELL : 1];
 
     const int x0 = bx * T::TX, y0 = by * T::TY, z0 = bz * T::TZ;
     const int tid = threadIdx.x;
@@ -267,7 +270,7 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
                 for (int f = 0; f < 4; ++f) sX[f * T::SN + s] = tmp[it][f];
         }
     }
-    auto stage_v = [&](const float *__restrict__ src, float *dst, bool zero_acc) {
+    auto stage_v = [&](const float *__restrict__ src, float *dst) {
         constexpr int IT = (T::VN + T::NT - 1) / T::NT;
         float tmp[IT][3];
 #pragma unroll
@@ -283,361 +286,326 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
             int s = tid + it * T::NT;
-            if (s < T::VN) {
+            if (s < T::VN)
 #pragma unroll
                 for (int f = 0; f < 3; ++f) dst[f * T::VN + s] = tmp[it][f];
-                if (zero_acc)
-#pragma unroll
-                    for (int f = 0; f < T::NACC; ++f) sAcc[f * T::VN + s] = 0.0f;
-            }
         }
     };
-    stage_v(MODE == MODE_RES ? vp : x, sV, true);
-    if (fmid) stage_v(fmid, sF, false);
-    if (MODE == MODE_RES)
-        for (int s = tid; s < T::NP * 32; s += T::NT) sAux[s] = 0.0f;
+    stage_v(MODE == MODE_RES ? vp : x, sV);
+    if (fmid) stage_v(fmid, sF);
     __syncthreads();
 
     const int ncx = 2 * m.n[0], ncy = 2 * m.n[1], ncz = 2 * m.n[2]; // fine cells per axis
     const float ih0 = P.ih[0], ih1 = P.ih[1], ih2 = P.ih[2];
 
-    // Cell of slot e (colour-sorted), its global lower corner and existence.
-    struct Cell {
-        int ex, ey, ez, gx, gy, gz, colour, ox, oy, oz;
-        bool live;
-    };
-    auto cell_of = [&](int e) {
-        Cell C;
-        C.live = e < T::NCELL;
-        C.ex = C.ey = C.ez = 0;
-        if (C.live) {
-            int c = 0;
-#pragma unroll
-            for (int q = 1; q < 8; ++q)
-                if (e >= T::cstart(q)) c = q;
-            int px = c & 1, py = (c >> 1) & 1, pz = c >> 2;
-            int k = e - T::cstart(c);
-            int cx = T::cnt(T::EX, px), cy = T::cnt(T::EY, py);
-            C.ex = 2 * (k % cx) + (1 - px);
-            C.ey = 2 * ((k / cx) % cy) + (1 - py);
-            C.ez = 2 * (k / (cx * cy)) + (1 - pz);
-        }
-        C.gx = x0 - 1 + C.ex;
-        C.gy = y0 - 1 + C.ey;
-        C.gz = z0 - 1 + C.ez;
-        if (C.live) {
-            if (m.per[0]) C.gx = wrap(C.gx, ncx, 1); else C.live &= C.gx >= 0 && C.gx < ncx;
-            if (m.per[1]) C.gy = wrap(C.gy, ncy, 1); else C.live &= C.gy >= 0 && C.gy < ncy;
-            if (m.per[2]) C.gz = wrap(C.gz, ncz, 1); else C.live &= C.gz >= 0 && C.gz < ncz;
-        }
-        // offset of the cell inside its patch (the tile origin is even)
-        C.ox = (C.ex + 1) & 1;
-        C.oy = (C.ey + 1) & 1;
-        C.oz = (C.ez + 1) & 1;
-        C.colour = C.ox | (C.oy << 1) | (C.oz << 2);
-        return C;
-    };
-    // Node slots of vertex j = a + 2b + 4c: base + offset, so the LDS
-    // accesses take immediate offsets.
+    // ---- this thread's cell: lower corner at origin - 1 + (ex, ey, ez) ----
+    const int e = tid;
+    bool live = e < T::NCELL;
+    const int ex = e % T::EX, ey = (e / T::EX) % T::EY, ez = e / (T::EX * T::EY);
+    const int gx = x0 - 1 + ex, gy = y0 - 1 + ey, gz = z0 - 1 + ez;
+    if (live) {
+        if (!m.per[0]) live &= gx >= 0 && gx < ncx;
+        if (!m.per[1]) live &= gy >= 0 && gy < ncy;
+        if (!m.per[2]) live &= gz >= 0 && gz < ncz;
+    }
+    // offset of the cell inside its patch (the tile origin is even)
+    const int ox = (ex + 1) & 1, oy = (ey + 1) & 1, oz = (ez + 1) & 1;
+    // node slots of vertex j = a + 2b + 4c as base + offset, so the LDS
+    // accesses take immediate offsets
     auto voff = [](int j) { return (j & 1) + T::VX * (((j >> 1) & 1) + T::VY * (j >> 2)); };
     auto xoff = [](int j) { return (j & 1) + T::SX * (((j >> 1) & 1) + T::SY * (j >> 2)); };
     auto coff = [](int j) { return 2 * ((j & 1) + T::SX * (((j >> 1) & 1) + T::SY * (j >> 2))); };
+    const int vb = ex + T::VX * (ey + T::VY * ez);
+    const int xb = (ex + 1) + T::SX * ((ey + 1) + T::SY * (ez + 1));
+    const int cb = (ex + 1 - ox) + T::SX * ((ey + 1 - oy) + T::SY * (ez + 1 - oz));
 
-    // ---- pass A: Galerkin terms of every cell (and the LPS test) ----
-    bool need[T::ROUNDS];
-#pragma unroll
-    for (int round = 0; round < T::ROUNDS; ++round) {
-        const Cell C = cell_of(tid + round * T::NT);
-        need[round] = false;
-        float acc[T::NACC][8];
-#pragma unroll
-        for (int f = 0; f < T::NACC; ++f)
-#pragma unroll
-            for (int j = 0; j < 8; ++j) acc[f][j] = 0.0f;
+    // ---- this thread's owned node: the 8 cells around it, in vertex order ----
+    const bool owner = tid < T::NOWN;
+    const int lx = tid % T::TX, ly = (tid / T::TX) % T::TY, lz = tid / (T::TX * T::TY);
+    // cell (lx + 1 - a, ly + 1 - b, lz + 1 - c) has this node as vertex a + 2b + 4c
+    const int nb = (lx + 1) + T::EX * ((ly + 1) + T::EY * (lz + 1));
+    auto ncell = [](int j) { return -((j & 1) + T::EX * (((j >> 1) & 1) + T::EY * (j >> 2))); };
+    float res[T::NACC];
 
-        if (C.live) {
-            const int vb = C.ex + T::VX * (C.ey + T::VY * C.ez);
-            if constexpr (MODE == MODE_RHS) {
-                float w[3][8];
+    // Cell integrals of equation a -> LDS; the owners sum them.
+    auto reduce = [&](const float c[8], float wq) -> float {
 #pragma unroll
-                for (int d = 0; d < 3; ++d)
+        for (int j = 0; j < 8; ++j)
+            if (live) sCell[j * T::NCELL + e] = c[j] * wq;
+            else if (e < T::NCELL) sCell[j * T::NCELL + e] = 0.0f;
+        __syncthreads();
+        float s = 0.0f;
+        if (owner)
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) w[d][j] = sV[d * T::VN + vb + voff(j)];
-                float wv[3][8];
+            for (int j = 0; j < 8; ++j) s += sCell[j * T::NCELL + nb + ncell(j)];
+        __syncthreads();
+        return s;
+    };
+
+    bool need = false;
+    if constexpr (MODE == MODE_RHS) {
+        float w[3][8], wv[3][8];
 #pragma unroll
-                for (int d = 0; d < 3; ++d) eval_val(w[d], wv[d]);
+        for (int d = 0; d < 3; ++d) {
 #pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    // (1/k) v_a + (f^{n-1} + f^n)/2 at the vertices (one fma with
-                    // or without forcing, so every kernel instance rounds
-                    // alike), then at the Gauss points
-                    float fv[8], F[8], va[8], g0[8], g1[8], g2[8];
+            for (int j = 0; j < 8; ++j) w[d][j] = live ? sV[d * T::VN + vb + voff(j)] : 0.0f;
+            eval_val(w[d], wv[d]);
+        }
 #pragma unroll
-                    for (int j = 0; j < 8; ++j)
-                        fv[j] = fmaf(P.inv_dt, w[a][j], fmid ? sF[a * T::VN + vb + voff(j)] : 0.0f);
-                    eval_val(fv, F);
-                    eval_vg(w[a], ih0, ih1, ih2, va, g0, g1, g2);
+        for (int a = 0; a < 3; ++a) {
+            // (1/k) v_a - 1/2 v . grad v_a (+ (f^{n-1} + f^n)/2) and -nu/2 grad v_a
+            float F[8], va[8], g0[8], g1[8], g2[8], acc[8];
+            eval_vg(w[a], ih0, ih1, ih2, va, g0, g1, g2);
+            if (fmid) {
+                float fv[8];
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        float conv = wv[0][q] * g0[q] + wv[1][q] * g1[q] + wv[2][q] * g2[q];
-                        F[q] -= 0.5f * conv;
-                        g0[q] *= -P.half_nu;
-                        g1[q] *= -P.half_nu;
-                        g2[q] *= -P.half_nu;
-                    }
-                    integrate<true, true, true>(F, g0, g1, g2, ih0, ih1, ih2, acc[a]);
-                }
+                for (int j = 0; j < 8; ++j) fv[j] = live ? sF[a * T::VN + vb + voff(j)] : 0.0f;
+                eval_val(fv, F);
             } else {
-                const int xb = (C.ex + 1) + T::SX * ((C.ey + 1) + T::SY * (C.ez + 1));
-                const int cb = (C.ex + 1 - C.ox) + T::SX * ((C.ey + 1 - C.oy) + T::SY * (C.ez + 1 - C.oz));
-                // The LPS terms vanish identically where x~ on the patch
-                // equals its patch interpolant.  When the vertex values and the
-                // interpolant computed here agree bit for bit every LPS
-                // contribution of the cell is exactly zero; other cells get
-                // them in pass B.
-                bool flat = true;
 #pragma unroll
-                for (int d = 0; d < 4; ++d) {
-                    float cv[8], pv[8];
+                for (int q = 0; q < 8; ++q) F[q] = 0.0f;
+            }
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) cv[j] = sX[d * T::SN + cb + coff(j)];
-                    pi_vertices(cv, C.ox, C.oy, C.oz, pv);
+            for (int q = 0; q < 8; ++q) {
+                float conv = wv[0][q] * g0[q] + wv[1][q] * g1[q] + wv[2][q] * g2[q];
+                F[q] += P.inv_dt * va[q] - 0.5f * conv;
+                g0[q] *= -P.half_nu;
+                g1[q] *= -P.half_nu;
+                g2[q] *= -P.half_nu;
+            }
+            integrate<true, true, true>(F, g0, g1, g2, ih0, ih1, ih2, acc);
+            res[a] = reduce(acc, P.wq);
+        }
+    } else {
+        // The LPS terms vanish identically where x~ on the patch equals its
+        // patch interpolant.  When the vertex values and the interpolant
+        // computed here agree bit for bit every LPS contribution of the cell
+        // is exactly zero; the other cells get them in a second pass.
+        if (live) {
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) flat &= pv[j] == sX[d * T::SN + xb + xoff(j)];
-                }
-                need[round] = !flat;
+            for (int d = 0; d < 4; ++d) {
+                float cv[8], pw[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) cv[j] = sX[d * T::SN + cb + coff(j)];
+                pi_vertices(cv, ox, oy, oz, pw);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) need |= pw[j] != sX[d * T::SN + xb + xoff(j)];
+            }
+        }
+        // x~ and vp at the Gauss points; divergence of x~
+        float xv[3][8], pv[3][8], div[8];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            float w[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) w[j] = live ? sX[d * T::SN + xb + xoff(j)] : 0.0f;
+            eval_val(w, xv[d]);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) w[j] = live ? sV[d * T::VN + vb + voff(j)] : 0.0f;
+            eval_val(w, pv[d]);
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) div[q] = 0.0f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            float wa[8], va[8], dif[8], sum[8], pj[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                wa[j] = live ? sV[a * T::VN + vb + voff(j)] : 0.0f;
+                va[j] = live ? sX[a * T::SN + xb + xoff(j)] : 0.0f;
+                pj[j] = live ? sX[3 * T::SN + xb + xoff(j)] : 0.0f;
+                // (1/k)(vp_a - v_a) + (f^{n-1} + f^n)/2 at the vertices
+                dif[j] = fmaf(P.inv_dt, wa[j] - va[j], fmid && live ? sF[a * T::VN + vb + voff(j)] : 0.0f);
+                sum[j] = wa[j] + va[j];
+            }
+            float F[8], Gx[8], Gy[8], Gz[8], tmp[8], pq[8];
+            // -nu/2 grad(vp_a + v_a), + p d_a phi
+            eval_vg(sum, ih0, ih1, ih2, tmp, Gx, Gy, Gz);
+            eval_val(dif, F);
+            eval_val(pj, pq);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                Gx[q] *= -P.half_nu;
+                Gy[q] *= -P.half_nu;
+                Gz[q] *= -P.half_nu;
+            }
+            float *Ga = a == 0 ? Gx : (a == 1 ? Gy : Gz);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) Ga[q] += pq[q];
+            // -1/2 (vp . grad vp_a) - 1/2 (v . grad v_a)
+            float g0[8], g1[8], g2[8];
+            eval_vg(wa, ih0, ih1, ih2, tmp, g0, g1, g2);
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                F[q] -= 0.5f * (pv[0][q] * g0[q] + pv[1][q] * g1[q] + pv[2][q] * g2[q]);
+            eval_vg(va, ih0, ih1, ih2, tmp, g0, g1, g2);
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                F[q] -= 0.5f * (xv[0][q] * g0[q] + xv[1][q] * g1[q] + xv[2][q] * g2[q]);
+            const float *ga = a == 0 ? g0 : (a == 1 ? g1 : g2);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) div[q] += ga[q];
+            float acc[8];
+            integrate<true, true, true>(F, Gx, Gy, Gz, ih0, ih1, ih2, acc);
+            res[a] = reduce(acc, P.wq);
+        }
+        // continuity: -(div v, xi)
+        {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) div[q] = -div[q];
+            float acc[8];
+            integrate<false, false, false>(div, nullptr, nullptr, nullptr, ih0, ih1, ih2, acc);
+            res[3] = reduce(acc, P.wq);
+        }
+    }
 
-                // x~ and vp at the Gauss points, pressure, divergence
-                float xv[3][8], pv[3][8], pq[8], div[8];
+    // ---- LPS terms of the cells that need them, one equation at a time ----
+    float corner[MODE == MODE_RES ? 4 : 1] = {};
+    // owned patch P = tid / 8, corner j = tid % 8: its cells, in offset order
+    const bool pown = MODE == MODE_RES && tid < 8 * T::NP;
+    const int pslot = tid >> 3, pj = tid & 7;
+    const int ppx = pslot % T::NPX, ppy = (pslot / T::NPX) % T::NPY, ppz = pslot / (T::NPX * T::NPY);
+    // cell of offset o = ox + 2 oy + 4 oz in patch (ppx, ppy, ppz): ex = 2 ppx + 1 + ox
+    const int pcb = (2 * ppx + 1) + T::EX * ((2 * ppy + 1) + T::EY * (2 * ppz + 1));
+    bool any_lps = false;
+    if constexpr (MODE == MODE_RES) {
+        any_lps = __syncthreads_or(need);
+        if (any_lps) {
+            for (int a = 0; a < 4; ++a) {
+                float acc[8], cor[8];
 #pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    float w[8];
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) w[j] = sX[d * T::SN + xb + xoff(j)];
-                    eval_val(w, xv[d]);
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) w[j] = sV[d * T::VN + vb + voff(j)];
-                    eval_val(w, pv[d]);
-                }
-                {
-                    float w[8];
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) w[j] = sX[3 * T::SN + xb + xoff(j)];
-                    eval_val(w, pq);
-                }
-#pragma unroll
-                for (int q = 0; q < 8; ++q) div[q] = 0.0f;
-
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    float wa[8], va[8], dif[8], sum[8];
+                for (int j = 0; j < 8; ++j) acc[j] = cor[j] = 0.0f;
+                if (live && need) {
+                    // stabilisation parameters (stabparams): |v|_inf over the vertices
+                    float vmax2 = 0.0f;
 #pragma unroll
                     for (int j = 0; j < 8; ++j) {
-                        wa[j] = sV[a * T::VN + vb + voff(j)];
-                        va[j] = sX[a * T::SN + xb + xoff(j)];
-                        // (1/k)(vp_a - v_a) + (f^{n-1} + f^n)/2 at the vertices
-                        // (one fma whether or not there is forcing, so every
-                        // kernel instance rounds alike)
-                        dif[j] = fmaf(P.inv_dt, wa[j] - va[j], fmid ? sF[a * T::VN + vb + voff(j)] : 0.0f);
-                        sum[j] = wa[j] + va[j];
+                        float u0 = sX[0 * T::SN + xb + xoff(j)], u1 = sX[1 * T::SN + xb + xoff(j)],
+                              u2 = sX[2 * T::SN + xb + xoff(j)];
+                        vmax2 = fmaxf(vmax2, u0 * u0 + u1 * u1 + u2 * u2);
                     }
-                    float F[8], Gx[8], Gy[8], Gz[8], tmp[8];
-                    // -nu/2 grad(vp_a + v_a), + p d_a phi
-                    eval_vg(sum, ih0, ih1, ih2, tmp, Gx, Gy, Gz);
-                    eval_val(dif, F);
+                    float den = P.nu * (1.0f / (P.hT * P.hT)) + sqrtf(vmax2) / P.hT + P.inv_dt;
+                    if (a < 3) {
+                        // R_a = v.grad v_a - pi v . grad pi v_a, tested with
+                        // v.grad phi (own vertices) and pi v . grad pi phi
+                        // (patch corners)
+                        const float deltaT = P.delta0 / den;
+                        float xv[3][8], piv[3][8], pa[8], va[8];
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        Gx[q] *= -P.half_nu;
-                        Gy[q] *= -P.half_nu;
-                        Gz[q] *= -P.half_nu;
-                    }
-                    float *Ga = a == 0 ? Gx : (a == 1 ? Gy : Gz);
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) Ga[q] += pq[q];
-                    // -1/2 (vp . grad vp_a) - 1/2 (v . grad v_a)
-                    float g0[8], g1[8], g2[8];
-                    eval_vg(wa, ih0, ih1, ih2, tmp, g0, g1, g2);
-#pragma unroll
-                    for (int q = 0; q < 8; ++q)
-                        F[q] -= 0.5f * (pv[0][q] * g0[q] + pv[1][q] * g1[q] + pv[2][q] * g2[q]);
-                    eval_vg(va, ih0, ih1, ih2, tmp, g0, g1, g2);
-#pragma unroll
-                    for (int q = 0; q < 8; ++q)
-                        F[q] -= 0.5f * (xv[0][q] * g0[q] + xv[1][q] * g1[q] + xv[2][q] * g2[q]);
-                    const float *ga = a == 0 ? g0 : (a == 1 ? g1 : g2);
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) div[q] += ga[q];
-                    integrate<true, true, true>(F, Gx, Gy, Gz, ih0, ih1, ih2, acc[a]);
-                }
-                // continuity: -(div v, xi)
-#pragma unroll
-                for (int q = 0; q < 8; ++q) div[q] = -div[q];
-                integrate<false, false, false>(div, nullptr, nullptr, nullptr, ih0, ih1, ih2, acc[3]);
-            }
-#pragma unroll
-            for (int f = 0; f < T::NACC; ++f)
-#pragma unroll
-                for (int j = 0; j < 8; ++j) acc[f][j] *= P.wq;
-        }
-
-        // colour-ordered accumulation into LDS; with colour-sorted slots a
-        // wave takes part in at most two of the phases
-        const int vb = C.ex + T::VX * (C.ey + T::VY * C.ez);
-        for (int c = 0; c < 8; ++c) {
-            if (C.live && C.colour == c) {
-#pragma unroll
-                for (int j = 0; j < 8; ++j)
-#pragma unroll
-                    for (int f = 0; f < T::NACC; ++f) sAcc[f * T::VN + vb + voff(j)] += acc[f][j];
-            }
-            __syncthreads();
-        }
-    }
-
-    // ---- pass B: LPS terms of the cells that need them, one equation at a
-    // time (velocity components, then continuity) ----
-    if constexpr (MODE == MODE_RES) {
-        int any = 0;
-#pragma unroll
-        for (int round = 0; round < T::ROUNDS; ++round) any |= need[round];
-        if (__syncthreads_or(any)) {
-            for (int a = 0; a < 4; ++a) {
-#pragma unroll
-                for (int round = 0; round < T::ROUNDS; ++round) {
-                    const Cell C = cell_of(tid + round * T::NT);
-                    float acc[8], cor[8];
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) acc[j] = cor[j] = 0.0f;
-                    const bool own_patch = C.ex >= 1 && C.ey >= 1 && C.ez >= 1;
-                    if (C.live && need[round]) {
-                        const int xb = (C.ex + 1) + T::SX * ((C.ey + 1) + T::SY * (C.ez + 1));
-                        const int cb = (C.ex + 1 - C.ox) + T::SX * ((C.ey + 1 - C.oy) + T::SY * (C.ez + 1 - C.oz));
-                        // stabilisation parameters (stabparams): |v|_inf over the vertices
-                        float vmax2 = 0.0f;
-#pragma unroll
-                        for (int j = 0; j < 8; ++j) {
-                            float u0 = sX[0 * T::SN + xb + xoff(j)], u1 = sX[1 * T::SN + xb + xoff(j)],
-                                  u2 = sX[2 * T::SN + xb + xoff(j)];
-                            vmax2 = fmaxf(vmax2, u0 * u0 + u1 * u1 + u2 * u2);
-                        }
-                        float den = P.nu * (1.0f / (P.hT * P.hT)) + sqrtf(vmax2) / P.hT + P.inv_dt;
-                        if (a < 3) {
-                            // R_a = v.grad v_a - pi v . grad pi v_a, tested with
-                            // v.grad phi (own vertices) and pi v . grad pi phi
-                            // (patch corners)
-                            const float deltaT = P.delta0 / den;
-                            float xv[3][8], piv[3][8], pa[8], va[8];
-#pragma unroll
-                            for (int d = 0; d < 3; ++d) {
-                                float w[8], pw[8];
-#pragma unroll
-                                for (int j = 0; j < 8; ++j) w[j] = sX[d * T::SN + xb + xoff(j)];
-                                eval_val(w, xv[d]);
-#pragma unroll
-                                for (int j = 0; j < 8; ++j) w[j] = sX[d * T::SN + cb + coff(j)];
-                                pi_vertices(w, C.ox, C.oy, C.oz, pw);
-                                eval_val(pw, piv[d]);
-                            }
-                            {
-                                float w[8];
-#pragma unroll
-                                for (int j = 0; j < 8; ++j) w[j] = sX[a * T::SN + cb + coff(j)];
-                                pi_vertices(w, C.ox, C.oy, C.oz, pa);
-#pragma unroll
-                                for (int j = 0; j < 8; ++j) va[j] = sX[a * T::SN + xb + xoff(j)];
-                            }
-                            float tmp[8], g0[8], g1[8], g2[8], h0[8], h1[8], h2[8];
-                            eval_vg(va, ih0, ih1, ih2, tmp, g0, g1, g2);
-                            eval_vg(pa, ih0, ih1, ih2, tmp, h0, h1, h2);
-                            float C0[8], C1[8], C2[8];
-#pragma unroll
-                            for (int q = 0; q < 8; ++q) {
-                                float R = (xv[0][q] * g0[q] + xv[1][q] * g1[q] + xv[2][q] * g2[q]) -
-                                          (piv[0][q] * h0[q] + piv[1][q] * h1[q] + piv[2][q] * h2[q]);
-                                float dR = deltaT * R;
-                                g0[q] = -dR * xv[0][q];
-                                g1[q] = -dR * xv[1][q];
-                                g2[q] = -dR * xv[2][q];
-                                C0[q] = dR * piv[0][q];
-                                C1[q] = dR * piv[1][q];
-                                C2[q] = dR * piv[2][q];
-                                tmp[q] = 0.0f;
-                            }
-                            integrate<true, true, true>(tmp, g0, g1, g2, ih0, ih1, ih2, acc);
-                            float cvals[8];
-                            integrate<true, true, true>(tmp, C0, C1, C2, ih0, ih1, ih2, cvals);
-                            pi_transpose(cvals, C.ox, C.oy, C.oz, cor);
-                        } else {
-                            // -alpha_T (grad(p - pi p), grad(xi - pi xi))
-                            const float alphaT = P.alpha0 / den;
+                        for (int d = 0; d < 3; ++d) {
                             float w[8], pw[8];
 #pragma unroll
-                            for (int j = 0; j < 8; ++j) w[j] = sX[3 * T::SN + cb + coff(j)];
-                            pi_vertices(w, C.ox, C.oy, C.oz, pw);
+                            for (int j = 0; j < 8; ++j) w[j] = sX[d * T::SN + xb + xoff(j)];
+                            eval_val(w, xv[d]);
 #pragma unroll
-                            for (int j = 0; j < 8; ++j) w[j] = sX[3 * T::SN + xb + xoff(j)] - pw[j];
-                            float tmp[8], g0[8], g1[8], g2[8];
-                            eval_vg(w, ih0, ih1, ih2, tmp, g0, g1, g2);
-#pragma unroll
-                            for (int q = 0; q < 8; ++q) {
-                                g0[q] *= -alphaT;
-                                g1[q] *= -alphaT;
-                                g2[q] *= -alphaT;
-                                tmp[q] = 0.0f;
-                            }
-                            integrate<true, true, true>(tmp, g0, g1, g2, ih0, ih1, ih2, acc);
-                            float dv[8];
-#pragma unroll
-                            for (int j = 0; j < 8; ++j) dv[j] = -acc[j];
-                            pi_transpose(dv, C.ox, C.oy, C.oz, cor);
+                            for (int j = 0; j < 8; ++j) w[j] = sX[d * T::SN + cb + coff(j)];
+                            pi_vertices(w, ox, oy, oz, pw);
+                            eval_val(pw, piv[d]);
                         }
+                        {
+                            float w[8];
 #pragma unroll
-                        for (int j = 0; j < 8; ++j) {
-                            acc[j] *= P.wq;
-                            cor[j] *= P.wq;
+                            for (int j = 0; j < 8; ++j) w[j] = sX[a * T::SN + cb + coff(j)];
+                            pi_vertices(w, ox, oy, oz, pa);
+#pragma unroll
+                            for (int j = 0; j < 8; ++j) va[j] = sX[a * T::SN + xb + xoff(j)];
                         }
-                    }
-                    // patch slot of an owned patch (halo cells ex == 0 etc. belong
-                    // to a neighbour's patch and add no corner terms here)
-                    const int pslot = own_patch ? ((C.ex - 1) / 2 + T::NPX * ((C.ey - 1) / 2 + T::NPY * ((C.ez - 1) / 2))) : 0;
-                    const int vb = C.ex + T::VX * (C.ey + T::VY * C.ez);
-                    const bool act = C.live && need[round];
-                    for (int c = 0; c < 8; ++c) {
-                        if (act && C.colour == c) {
+                        float tmp[8], g0[8], g1[8], g2[8], h0[8], h1[8], h2[8];
+                        eval_vg(va, ih0, ih1, ih2, tmp, g0, g1, g2);
+                        eval_vg(pa, ih0, ih1, ih2, tmp, h0, h1, h2);
+                        float C0[8], C1[8], C2[8];
 #pragma unroll
-                            for (int j = 0; j < 8; ++j) sAcc[a * T::VN + vb + voff(j)] += acc[j];
-                            if (own_patch)
-#pragma unroll
-                                for (int j = 0; j < 8; ++j) sAux[pslot * 32 + 4 * j + a] += cor[j];
+                        for (int q = 0; q < 8; ++q) {
+                            float R = (xv[0][q] * g0[q] + xv[1][q] * g1[q] + xv[2][q] * g2[q]) -
+                                      (piv[0][q] * h0[q] + piv[1][q] * h1[q] + piv[2][q] * h2[q]);
+                            float dR = deltaT * R;
+                            g0[q] = -dR * xv[0][q];
+                            g1[q] = -dR * xv[1][q];
+                            g2[q] = -dR * xv[2][q];
+                            C0[q] = dR * piv[0][q];
+                            C1[q] = dR * piv[1][q];
+                            C2[q] = dR * piv[2][q];
+                            tmp[q] = 0.0f;
                         }
-                        __syncthreads();
+                        integrate<true, true, true>(tmp, g0, g1, g2, ih0, ih1, ih2, acc);
+                        float cvals[8];
+                        integrate<true, true, true>(tmp, C0, C1, C2, ih0, ih1, ih2, cvals);
+                        pi_transpose(cvals, ox, oy, oz, cor);
+                    } else {
+                        // -alpha_T (grad(p - pi p), grad(xi - pi xi))
+                        const float alphaT = P.alpha0 / den;
+                        float w[8], pw[8];
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) w[j] = sX[3 * T::SN + cb + coff(j)];
+                        pi_vertices(w, ox, oy, oz, pw);
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) w[j] = sX[3 * T::SN + xb + xoff(j)] - pw[j];
+                        float tmp[8], g0[8], g1[8], g2[8];
+                        eval_vg(w, ih0, ih1, ih2, tmp, g0, g1, g2);
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) {
+                            g0[q] *= -alphaT;
+                            g1[q] *= -alphaT;
+                            g2[q] *= -alphaT;
+                            tmp[q] = 0.0f;
+                        }
+                        integrate<true, true, true>(tmp, g0, g1, g2, ih0, ih1, ih2, acc);
+                        float dv[8];
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) dv[j] = -acc[j];
+                        pi_transpose(dv, ox, oy, oz, cor);
                     }
                 }
+                // own-vertex parts to the nodes, corner parts to the owned
+                // patches (halo cells ex == 0 etc. belong to a neighbour's patch)
+                const bool own_patch = ex >= 1 && ey >= 1 && ez >= 1;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    if (e < T::NCELL) {
+                        sCell[j * T::NCELL + e] = acc[j] * P.wq;
+                        sCor[j * T::NCELL + e] = own_patch ? cor[j] * P.wq : 0.0f;
+                    }
+                }
+                __syncthreads();
+                if (owner) {
+                    float s = 0.0f;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) s += sCell[j * T::NCELL + nb + ncell(j)];
+                    res[a] += s;
+                }
+                if (pown) {
+                    float s = 0.0f;
+#pragma unroll
+                    for (int o = 0; o < 8; ++o)
+                        s += sCor[pj * T::NCELL + pcb + (o & 1) + T::EX * (((o >> 1) & 1) + T::EY * (o >> 2))];
+                    corner[a] = s;
+                }
+                __syncthreads();
             }
         }
     }
 
-    // ---- write owned nodes ----
-    for (int s = tid; s < T::TX * T::TY * T::TZ; s += T::NT) {
-        int lx = s % T::TX, ly = (s / T::TX) % T::TY, lz = s / (T::TX * T::TY);
+    // ---- write owned nodes and patch corner sums ----
+    if (owner) {
         int gi = x0 + lx, gj = y0 + ly, gk = z0 + lz;
-        if (gi >= m.nf[0] || gj >= m.nf[1] || gk >= m.nf[2]) continue;
-        int64_t g = gi + (int64_t)m.nf[0] * (gj + (int64_t)m.nf[1] * gk);
-        int slot = (lx + 1) + T::VX * ((ly + 1) + T::VY * (lz + 1));
-        bool dir = on_dirichlet(m, gi, gj, gk);
+        if (gi < m.nf[0] && gj < m.nf[1] && gk < m.nf[2]) {
+            int64_t g = gi + (int64_t)m.nf[0] * (gj + (int64_t)m.nf[1] * gk);
+            bool dir = on_dirichlet(m, gi, gj, gk);
 #pragma unroll
-        for (int f = 0; f < 3; ++f) out[f * nfn + g] = dir ? 0.0f : sAcc[f * T::VN + slot];
-        if (MODE == MODE_RES) out[3 * nfn + g] = sAcc[3 * T::VN + slot];
-        else out[3 * nfn + g] = 0.0f;
+            for (int f = 0; f < 3; ++f) out[f * nfn + g] = dir ? 0.0f : res[f];
+            if constexpr (MODE == MODE_RES) out[3 * nfn + g] = res[3];
+            else out[3 * nfn + g] = 0.0f;
+        }
     }
-    if (MODE == MODE_RES) {
-        for (int s = tid; s < T::NP * 32; s += T::NT) {
-            int ps = s / 32, w = s % 32;
-            int px = ps % T::NPX, py = (ps / T::NPX) % T::NPY, pz = ps / (T::NPX * T::NPY);
-            int PI = x0 / 2 + px, PJ = y0 / 2 + py, PK = z0 / 2 + pz;
-            if (PI >= m.n[0] || PJ >= m.n[1] || PK >= m.n[2]) continue;
-            int64_t M = PI + (int64_t)m.n[0] * (PJ + (int64_t)m.n[1] * PK);
-            aux[M * 32 + w] = sAux[s];
+    if constexpr (MODE == MODE_RES) {
+        // the tile's flag says whether its patches' corner sums were written
+        if (tid == 0) *tflag = any_lps ? 1 : 0;
+        if (pown && any_lps) {
+            int PI = x0 / 2 + ppx, PJ = y0 / 2 + ppy, PK = z0 / 2 + ppz;
+            if (PI < m.n[0] && PJ < m.n[1] && PK < m.n[2]) {
+                int64_t M = PI + (int64_t)m.n[0] * (PJ + (int64_t)m.n[1] * PK);
+                *(float4 *)(aux + M * 32 + 4 * pj) = make_float4(corner[0], corner[1], corner[2], corner[3]);
+            }
         }
     }
 }
@@ -646,9 +614,11 @@ template <int MODE>
 __global__ void __launch_bounds__(ResTile<MODE>::NT)
     k_residual(Mesh m, ResParams P, const float *__restrict__ x, const float *__restrict__ vp,
                const float *__restrict__ fmid, float *__restrict__ out, float *__restrict__ aux,
-               const int *__restrict__ flag) {
+               int *__restrict__ tflag, const int *__restrict__ flag) {
     if (flag && *flag == 0) return; // predicated launch (fallback path not taken)
-    residual_tile<MODE>(m, P, blockIdx.x, blockIdx.y, blockIdx.z, x, vp, fmid, out, aux);
+    const int tl = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    residual_tile<MODE>(m, P, blockIdx.x, blockIdx.y, blockIdx.z, x, vp, fmid, out, aux,
+                        MODE == MODE_RES ? tflag + tl : nullptr);
 }
 
 // Batched: one flat grid over the tiles of all boxes.  x is a 4-component
@@ -657,7 +627,8 @@ __global__ void __launch_bounds__(ResTile<MODE>::NT)
 template <int MODE>
 __global__ void __launch_bounds__(ResTile<MODE>::NT)
     k_residual_batch(const BoxDesc *__restrict__ D, int nbox, const float *__restrict__ x,
-                     const float *__restrict__ vp, float *__restrict__ out, float *__restrict__ aux) {
+                     const float *__restrict__ vp, float *__restrict__ out, float *__restrict__ aux,
+                     int *__restrict__ tflag) {
     const int64_t blk = blockIdx.x;
     const int b = find_box(nbox, blk, [&](int i) { return D[i].blk_tile; });
     const BoxDesc &d = D[b];
@@ -666,13 +637,15 @@ __global__ void __launch_bounds__(ResTile<MODE>::NT)
     int t = (int)(blk - d.blk_tile);
     int bx = t % d.rtiles[0], by = (t / d.rtiles[0]) % d.rtiles[1], bz = t / (d.rtiles[0] * d.rtiles[1]);
     residual_tile<MODE>(m, P, bx, by, bz, x + 4 * d.off_fine, MODE == MODE_RES ? vp + 3 * d.off_fine : nullptr,
-                        nullptr, out + 4 * d.off_fine, MODE == MODE_RES ? aux + 32 * d.off_patch : nullptr);
+                        nullptr, out + 4 * d.off_fine, MODE == MODE_RES ? aux + 32 * d.off_patch : nullptr,
+                        MODE == MODE_RES ? tflag + blk : nullptr);
 }
 
 // Adds the corner (pi phi) parts of the LPS terms: a coarse vertex collects
 // the per-patch sums of the patches it is a corner of, in ascending patch
 // order.  aux[M][4 j + f]: corner j = A + 2B + 4C of patch M, field f.
 __device__ __forceinline__ void lps_corner_node(const Mesh &m, int64_t t, const float *__restrict__ aux,
+                                                const int *__restrict__ tflag, const int rt[3],
                                                 float *__restrict__ r) {
     if (t >= m.n_coarse) return;
     uint32_t JK = fdiv((uint32_t)t, m.cx), I = (uint32_t)t - JK * m.nc[0];
@@ -694,16 +667,25 @@ __device__ __forceinline__ void lps_corner_node(const Mesh &m, int64_t t, const 
             if (hi < m.n[a]) { P[a][cnt[a]] = hi; L[a][cnt[a]] = 0; ++cnt[a]; }
         }
     }
+    // a patch's corner sums exist when its residual tile had LPS work
+    constexpr int PX = ResTile<MODE_RES>::NPX, PY = ResTile<MODE_RES>::NPY, PZ = ResTile<MODE_RES>::NPZ;
     float s[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    bool any = false;
     for (int c = 0; c < cnt[2]; ++c)
         for (int b = 0; b < cnt[1]; ++b)
             for (int a = 0; a < cnt[0]; ++a) {
+                const int tl = P[0][a] / PX + rt[0] * (P[1][b] / PY + rt[1] * (P[2][c] / PZ));
+                if (!tflag[tl]) continue;
+                any = true;
                 int64_t M = P[0][a] + (int64_t)m.n[0] * (P[1][b] + (int64_t)m.n[1] * P[2][c]);
                 int j = L[0][a] + 2 * L[1][b] + 4 * L[2][c];
-                const float *src = aux + M * 32 + 4 * j;
-#pragma unroll
-                for (int f = 0; f < 4; ++f) s[f] += src[f];
+                const float4 v = *(const float4 *)(aux + M * 32 + 4 * j);
+                s[0] += v.x;
+                s[1] += v.y;
+                s[2] += v.z;
+                s[3] += v.w;
             }
+    if (!any) return;
     int gi = 2 * I, gj = 2 * J, gk = 2 * K;
     int64_t g = gi + (int64_t)m.nf[0] * (gj + (int64_t)m.nf[1] * gk);
     bool dir = on_dirichlet(m, gi, gj, gk);
@@ -714,19 +696,22 @@ __device__ __forceinline__ void lps_corner_node(const Mesh &m, int64_t t, const 
 }
 
 __global__ void __launch_bounds__(256) k_lps_corners(Mesh m, const float *__restrict__ aux,
+                                                     const int *__restrict__ tflag, int rt0, int rt1, int rt2,
                                                      float *__restrict__ r, const int *__restrict__ flag) {
     if (flag && *flag == 0) return;
-    lps_corner_node(m, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, aux, r);
+    const int rt[3] = {rt0, rt1, rt2};
+    lps_corner_node(m, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, aux, tflag, rt, r);
 }
 
 __global__ void __launch_bounds__(256) k_lps_corners_batch(const BoxDesc *__restrict__ D, int nbox,
-                                                           const float *__restrict__ aux, float *__restrict__ r) {
+                                                           const float *__restrict__ aux,
+                                                           const int *__restrict__ tflag, float *__restrict__ r) {
     const int64_t blk = blockIdx.x;
     const int b = find_box(nbox, blk, [&](int i) { return D[i].blk_coarse; });
     const BoxDesc &d = D[b];
     const Mesh m = d.m;
     lps_corner_node(m, (blk - d.blk_coarse) * blockDim.x + threadIdx.x, aux + 32 * d.off_patch,
-                    r + 4 * d.off_fine);
+                    tflag + d.blk_tile, d.rtiles, r + 4 * d.off_fine);
 }
 
 ResParams make_params(const Mesh &m, const dnnmg_ns *ns) {
@@ -756,12 +741,21 @@ dim3 res_grid(const Mesh &m) {
                 (m.nf[2] + T::TZ - 1) / T::TZ);
 }
 
+// LPS workspace of one box: corner sums (32 floats per patch), then one
+// flag per residual tile.
+static size_t up256(size_t b) { return (b + 255) / 256 * 256; }
+size_t lps_ws_bytes(const Mesh &m) {
+    dim3 g = res_grid<MODE_RES>(m);
+    return up256(sizeof(float) * 32 * m.n_patches) + up256(sizeof(int) * (size_t)g.x * g.y * g.z);
+}
+
 int residual_launch(const Mesh &m, const dnnmg_ns *ns, const float *x, const float *vprev,
                     const float *fmid, float *r, float *aux, const int *flag, hipStream_t s) {
     ResParams P = make_params(m, ns);
-    k_residual<MODE_RES><<<res_grid<MODE_RES>(m), ResTile<MODE_RES>::NT, 0, s>>>(m, P, x, vprev, fmid, r,
-                                                                                 aux, flag);
-    k_lps_corners<<<blocks_for(m.n_coarse, 256), 256, 0, s>>>(m, aux, r, flag);
+    dim3 g = res_grid<MODE_RES>(m);
+    int *tflag = (int *)((char *)aux + up256(sizeof(float) * 32 * m.n_patches));
+    k_residual<MODE_RES><<<g, ResTile<MODE_RES>::NT, 0, s>>>(m, P, x, vprev, fmid, r, aux, tflag, flag);
+    k_lps_corners<<<blocks_for(m.n_coarse, 256), 256, 0, s>>>(m, aux, tflag, g.x, g.y, g.z, r, flag);
     return hip_check(hipGetLastError(), "dnnmg_residual launch");
 }
 
@@ -773,13 +767,14 @@ void residual_tiles(const Mesh &m, int rt[3]) {
 }
 
 void residual_batch_launch(const BoxDesc *D, int nbox, int64_t ntiles, int64_t ncoarse_blocks, const float *x,
-                           const float *vp, float *r, float *aux, hipStream_t s) {
-    k_residual_batch<MODE_RES><<<(unsigned)ntiles, ResTile<MODE_RES>::NT, 0, s>>>(D, nbox, x, vp, r, aux);
-    k_lps_corners_batch<<<(unsigned)ncoarse_blocks, 256, 0, s>>>(D, nbox, aux, r);
+                           const float *vp, float *r, float *aux, int *tflag, hipStream_t s) {
+    k_residual_batch<MODE_RES><<<(unsigned)ntiles, ResTile<MODE_RES>::NT, 0, s>>>(D, nbox, x, vp, r, aux, tflag);
+    k_lps_corners_batch<<<(unsigned)ncoarse_blocks, 256, 0, s>>>(D, nbox, aux, tflag, r);
 }
 
 void rhs_batch_launch(const BoxDesc *D, int nbox, int64_t ntiles, const float *v, float *b, hipStream_t s) {
-    k_residual_batch<MODE_RHS><<<(unsigned)ntiles, ResTile<MODE_RHS>::NT, 0, s>>>(D, nbox, v, nullptr, b, nullptr);
+    k_residual_batch<MODE_RHS><<<(unsigned)ntiles, ResTile<MODE_RHS>::NT, 0, s>>>(D, nbox, v, nullptr, b, nullptr,
+                                                                                nullptr);
 }
 
 } // namespace dnnmg
@@ -789,7 +784,7 @@ using namespace dnnmg;
 extern "C" size_t dnnmg_residual_workspace(const dnnmg_box *box) {
     Mesh m;
     if (make_mesh(box, &m)) return 0;
-    return (size_t)m.n_patches * 32 * sizeof(float);
+    return lps_ws_bytes(m);
 }
 
 extern "C" int dnnmg_residual(const dnnmg_box *box, const dnnmg_ns *ns, const float *x,
@@ -800,9 +795,9 @@ extern "C" int dnnmg_residual(const dnnmg_box *box, const dnnmg_ns *ns, const fl
     if (rc) return rc;
     if ((rc = check_ns(ns))) return rc;
     if (!x || !vprev || !r || !ws) return fail(DNNMG_ERR_ARG, "dnnmg_residual: NULL pointer");
-    if (ws_bytes < (size_t)m.n_patches * 32 * sizeof(float))
-        return fail(DNNMG_ERR_SHAPE, "dnnmg_residual: workspace %zu < %zu bytes", ws_bytes,
-                    (size_t)m.n_patches * 32 * sizeof(float));
+    if (!aligned16(ws)) return fail(DNNMG_ERR_ARG, "dnnmg_residual: workspace not 16-byte aligned");
+    if (ws_bytes < lps_ws_bytes(m))
+        return fail(DNNMG_ERR_SHAPE, "dnnmg_residual: workspace %zu < %zu bytes", ws_bytes, lps_ws_bytes(m));
     return residual_launch(m, ns, x, vprev, fmid, r, (float *)ws, nullptr, (hipStream_t)stream);
 }
 
@@ -815,6 +810,6 @@ extern "C" int dnnmg_rhs(const dnnmg_box *box, const dnnmg_ns *ns, const float *
     if (!v || !b) return fail(DNNMG_ERR_ARG, "dnnmg_rhs: NULL pointer");
     ResParams P = make_params(m, ns);
     k_residual<MODE_RHS><<<res_grid<MODE_RHS>(m), ResTile<MODE_RHS>::NT, 0, (hipStream_t)stream>>>(
-        m, P, v, nullptr, fmid, b, nullptr, nullptr);
+        m, P, v, nullptr, fmid, b, nullptr, nullptr, nullptr);
     return hip_check(hipGetLastError(), "dnnmg_rhs launch");
 }

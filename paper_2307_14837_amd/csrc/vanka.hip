@@ -447,10 +447,10 @@ using namespace dnnmg;
 namespace dnnmg {
 int residual_launch(const Mesh &m, const dnnmg_ns *ns, const float *x, const float *vprev,
                     const float *fmid, float *r, float *aux, const int *flag, hipStream_t s);
+size_t lps_ws_bytes(const Mesh &m);
 size_t vanka_ws_bytes(const Mesh &m) {
     auto up = [](size_t b) { return (b + 255) / 256 * 256; };
-    return up(sizeof(float) * 4 * m.n_fine) + up(sizeof(float) * 32 * m.n_patches) +
-           up(sizeof(float) * 108 * m.n_patches);
+    return up(sizeof(float) * 4 * m.n_fine) + lps_ws_bytes(m) + up(sizeof(float) * 108 * m.n_patches);
 }
 
 int vanka_sweeps(const dnnmg_box *box, const dnnmg_ns *ns, float *x, const float *vprev,
@@ -465,7 +465,7 @@ int vanka_sweeps(const dnnmg_box *box, const dnnmg_ns *ns, float *x, const float
     auto up = [](size_t b) { return (b + 255) / 256 * 256; };
     float *r = (float *)ws;
     float *aux = (float *)(ws + up(sizeof(float) * 4 * m.n_fine));
-    float *D = (float *)(ws + up(sizeof(float) * 4 * m.n_fine) + up(sizeof(float) * 32 * m.n_patches));
+    float *D = (float *)(ws + up(sizeof(float) * 4 * m.n_fine) + lps_ws_bytes(m));
     for (int it = 0; it < sweeps; ++it) {
         if ((rc = residual_launch(m, ns, x, vprev, fmid, r, aux, flag, s))) return rc;
         if (coupled)

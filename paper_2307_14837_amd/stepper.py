@@ -29,7 +29,7 @@ class CorrectionStep:
     """
 
     def __init__(self, box, ns, params, dtype="bf16", device="cuda:0", shift=None, inv_scale=None,
-                 indicator=False, theta=1.0, fallback_sweeps=4, fused=False):
+                 indicator=False, theta=1.0, fallback_sweeps=4, fused=True):
         self.box = L.Box.of(box)
         self.ns = L.NS.of(ns)
         self.dev = torch.device(device)
@@ -38,7 +38,7 @@ class CorrectionStep:
         self.hidden = int(np.shape(params[0])[1])
         self.indicator = indicator
         # fused: the gather runs inside the network kernel (no X round trip)
-        self.fused = fused and self.hidden in (128, 256, 512) and not (dtype == "fp32" and self.hidden == 512)
+        self.fused = bool(fused)
         f32 = dict(dtype=torch.float32, device=self.dev)
         f64 = dict(dtype=torch.float64, device=self.dev)
         self.xc = torch.zeros(4 * self.nc, **f64)

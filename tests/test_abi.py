@@ -47,7 +47,9 @@ def test_host_validation_without_gpu():
 
     box = L.Box.of(syn.cfg2().box)
     assert L.box_sizes(box) == (140481, 18785, 16384)
-    assert L.residual_workspace_bytes(box) == 16384 * 32 * 4
+    # LPS corner sums (32 floats per patch), then one int per residual tile of
+    # 16 x 8 x 4 nodes (9 x 5 x 9 tiles for 129 x 33 x 33 nodes), 256-byte blocks
+    assert L.residual_workspace_bytes(box) == 16384 * 32 * 4 + 1792
     assert L.packed_bytes(L.BF16, 256, 0) == 192 * 256 * 2
     assert L.packed_bytes(L.FP8_E4M3, 512, 1) == 512 * 512  # E4M3 hidden product
     assert L.packed_bytes(L.FP8_E4M3, 512, 2) == 512 * 96 * 2  # BF16 output layer

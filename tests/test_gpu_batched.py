@@ -53,9 +53,9 @@ def test_batched_matches_single(mods, dtype):
         assert np.array_equal(out[b]["xcorr"][:3], ref["vcorr"].astype(np.float32)), b
         assert np.array_equal(out[b]["bc"], ref["bc"]), b
     # autotuned choice gives the same numbers
-    ppw, grid = bs.autotune(reps=3)
-    say(f"  autotuned: {ppw} patches per wave, persistent grid {grid}")
-    assert ppw in (16, 32)
+    ppt, grid = bs.autotune(reps=3)
+    say(f"  autotuned: {ppt} patches per tile, persistent grid {grid}")
+    assert ppt in (16, 32, 64)
     bs.step()
     out2 = bs.results()
     for b in range(len(BOXES)):

@@ -287,6 +287,47 @@ def test_mlp_fp8(L, orc, H, n):
     assert e2 <= 5e-3
 
 
+BUILT_TILES = {("f32", 128): (16, 32), ("bf16", 256): (16, 32, 64), ("bf16", 512): (16, 32, 64),
+               ("fp8", 256): (16, 32, 64), ("fp8", 512): (16, 32, 64)}
+
+
+@pytest.mark.parametrize("name,H", list(BUILT_TILES))
+def test_mlp_tile_geometries_agree(L, orc, name, H):
+    """Every built tile size and a persistent grid give the same bits (each
+    output sums its K chunks in the same order), and match the oracle."""
+    say("mlp tile geometries", name, H)
+    dtype = {"f32": L.F32, "bf16": L.BF16, "fp8": L.FP8_E4M3}[name]
+    n = 1000  # not a multiple of any tile
+    params = syn.mlp_params(165, H, 81, seed=11, bias_scale=0.1)
+    X = f32(np.random.default_rng(12).standard_normal((n, 165)))
+    ws, as_ = (1.0, 1.0, 1.0), (1.0, 1.0, 1.0)
+    if dtype == L.FP8_E4M3:
+        ws = (1.0, float(np.abs(f32(params[2])).max() / 448.0), 1.0)
+        as_ = (1.0, 1.0 / 448.0, 1.0)
+    Xg = to_gpu(padded(X, 192))
+    Xg = (Xg if dtype == L.F32 else Xg.to(torch.bfloat16)).contiguous().view(-1)
+    Wp, bias = pack_net(L, dtype, params, ws)
+    net = L.make_mlp(dtype, H, Wp, bias, ws, as_)
+    outs = {}
+    for tp in (16, 32, 64):
+        for grid in (0, 5):
+            Y = torch.full((n * 81,), float("nan"), dtype=torch.float32, device=dev())
+            try:
+                L.dnnmg_patch_forward_tiles(net, n, Xg, 192, Y, tp, grid)
+            except L.DnnmgError:
+                assert tp not in BUILT_TILES[(name, H)]
+                continue
+            torch.cuda.synchronize()
+            outs[(tp, grid)] = Y.cpu().numpy().reshape(n, 81)
+    assert {k[0] for k in outs} == set(BUILT_TILES[(name, H)])
+    ref = outs[(16, 0)]
+    for k, Y in outs.items():
+        assert np.array_equal(Y, ref), k
+    exact = orc.mlp_forward(X.astype(np.float64), *[f32(p).astype(np.float64) for p in params])
+    tol = {"f32": 1e-5, "bf16": 2e-2, "fp8": 5e-2}[name]
+    assert rel_l2(ref, exact) <= tol
+
+
 def test_mlp_saved_activations(L, orc):
     say("mlp saved activations")
     params = syn.mlp_params(165, 64, 81, seed=7, bias_scale=0.1)
