@@ -27,10 +27,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP32_VALU_PEAK_TFLOPS = 157.3  # published vector FP32 (packed FMA); non-packed issue is half
 BF16_MFMA_PEAK_TFLOPS = 2500.0
-
-# Algorithmic work per unit of the dominant kernel (residual):
-# FP32 flops per fine cell of the sum-factorised Q1 residual with LPS terms.
-RESIDUAL_FLOP_PER_CELL = None  # filled from paper_2307_14837_amd.flops
+PMC_COPY_MIB = 256  # plain copy of known size that calibrates the HBM byte counters
 
 
 def parse():
@@ -40,7 +37,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-variants", action="store_true", help="only the default workload")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="run only the dominant kernel and a plain copy a few times (for rocprofv3 --pmc)")
     return ap.parse_args()
+
+
+RESIDUAL_SOURCES = ("residual.hip", "common.hpp", "common.hip")
 
 
 def src_hash(*names):
@@ -50,17 +52,42 @@ def src_hash(*names):
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(kernel_file, workload):
-    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it was
-    taken on the current kernel source; else None."""
+def traffic_from_profile(entry, workload):
+    """HBM bytes per launch of an entry point from the committed rocprofv3 PMC
+    summary, if it was taken on the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", f"pmc_{workload}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    k = rec.get("kernels", {}).get(kernel_file)
-    if not k or k.get("src_hash") != src_hash(kernel_file + ".hip"):
+    k = rec.get("entries", {}).get(entry)
+    if not k or k.get("src_hash") != src_hash(*RESIDUAL_SOURCES):
         return None
     return k.get("bytes_per_launch")
+
+
+def pmc_probe():
+    """The dominant entry point (prolongation + residual of the default
+    workload) and a plain device copy of PMC_COPY_MIB MiB, three launches
+    each, for counter runs."""
+    import torch
+
+    import dnnmg_synth as syn
+    from paper_2307_14837_amd import _lib as L
+
+    w = syn.cfg2()
+    st, _, _ = build_step(w, "bf16")
+    for _ in range(3):
+        L.dnnmg_prolong_residual(st.box, st.ns, st.xc, st.vprev, st.xt, st.r)
+    torch.cuda.synchronize()
+    n = PMC_COPY_MIB * 2**20 // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    print(json.dumps({"pmc_probe": w.name, "copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n,
+                      "src_hash": src_hash(*RESIDUAL_SOURCES)}), flush=True)
 
 
 def time_graph(st, steps, warmup):
@@ -264,6 +291,9 @@ def cpu_baseline(w):
 
 def main():
     args = parse()
+    if args.pmc_probe:
+        pmc_probe()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -281,16 +311,18 @@ def main():
           file=sys.stderr, flush=True)
     ms, wall = time_graph(st, args.steps, args.warmup)
 
-    # dominant kernel: the fine residual (VALU bound), timed live with HIP events
+    # dominant kernel: prolongation + fine residual (VALU bound), timed live
+    # with HIP events on the stream it runs on
     reps = 50
-    res_ms = time_kernel(lambda: L.dnnmg_residual(st.box, st.ns, st.xt, st.vprev, st.r, st.ws_res), reps)
+    res_ms = time_kernel(lambda: L.dnnmg_prolong_residual(st.box, st.ns, st.xc, st.vprev, st.xt, st.r), reps)
     ncells = 8 * st.np
-    flop = flops.residual_flops_per_cell() * ncells
+    flop = flops.prolong_residual_flops_per_cell() * ncells
     achieved = flop / (res_ms * 1e-3) / 1e12
-    traffic = traffic_from_profile("residual", w.name)
+    traffic = traffic_from_profile("dnnmg_prolong_residual", w.name)
     L.dnnmg_patch_gather(st.box, st.xt, st.r, st.X, st.xdtype, 192, st.shift, st.inv_scale)
     kernel_ms = {
-        "residual": res_ms,
+        "prolong_residual": res_ms,
+        "residual": time_kernel(lambda: L.dnnmg_residual(st.box, st.ns, st.xt, st.vprev, st.r, st.ws_res), reps),
         "prolong": time_kernel(lambda: L.dnnmg_prolong(st.box, st.xc, st.xt), reps),
         "gather_forward_fused": time_kernel(lambda: L.dnnmg_patch_gather_forward(st.box, st.net, st.xt, st.r, st.Y,
                                                                                 st.shift, st.inv_scale), reps),
@@ -324,7 +356,7 @@ def main():
                    "stencils": "FP32 (prolongation from FP64, restriction to FP64)",
                    "parallelism": "1 GPU", "graph": "hipGraph replay of the whole step"},
         "fine_dof_per_s": 4 * st.nf / (ms * 1e-3),
-        "roofline": {"kernel": "dnnmg_residual", "bound": "alu", "achieved": achieved,
+        "roofline": {"kernel": "dnnmg_prolong_residual", "bound": "alu", "achieved": achieved,
                      "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": traffic,
                      "avg_launch_ms": res_ms, "flop_per_launch": flop},

@@ -129,6 +129,18 @@ size_t dnnmg_residual_workspace(const dnnmg_box *box);
 int dnnmg_residual(const dnnmg_box *box, const dnnmg_ns *ns, const float *x, const float *vprev,
                    const float *fmid, float *r, void *ws, size_t ws_bytes, void *stream);
 
+/* Prolongation and fine residual fused (Algorithm 1): xt = P xc exactly as
+ * dnnmg_prolong computes it (ncomp 4), and r = F - A(xt) as dnnmg_residual
+ * computes it, bit for bit, in one pass.  Since xt is patchwise Q1 (the Q1
+ * interpolant of the coarse solution on every patch), the local projection
+ * terms of eq. (disc:ns) vanish identically and are not evaluated, so no
+ * workspace is needed.
+ *   xc FP64 [4][n_coarse]; vprev FP32 [3][n_fine]; fmid FP32 [3][n_fine] or
+ *   NULL; xt FP32 [4][n_fine] and r FP32 [4][n_fine] outputs (must not
+ *   overlap the inputs). */
+int dnnmg_prolong_residual(const dnnmg_box *box, const dnnmg_ns *ns, const double *xc, const float *vprev,
+                           const float *fmid, float *xt, float *r, void *stream);
+
 /* Right-hand side of (4cranknicholson3) for the next step (Algorithm 1,
  * "Rhs"): b_a = (1/k)(v_a, phi) - 1/2 (v.grad v_a, phi) - nu/2 (grad v_a,
  * grad phi) + (fmid_a, phi); pressure rows 0; Dirichlet velocity rows 0.
@@ -136,6 +148,7 @@ int dnnmg_residual(const dnnmg_box *box, const dnnmg_ns *ns, const float *x, con
  *   b FP32 [4][n_fine]. */
 int dnnmg_rhs(const dnnmg_box *box, const dnnmg_ns *ns, const float *v, const float *fmid,
               float *b, void *stream);
+
 
 /* Restriction of Algorithm 1: bc = P^T bf, the transpose of dnnmg_prolong,
  * accumulated and stored in FP64.  bf: FP32 [ncomp][n_fine];
@@ -282,10 +295,11 @@ int dnnmg_plan_sizes(const dnnmg_plan *plan, int64_t *n_fine, int64_t *n_coarse,
 int dnnmg_plan_choice(const dnnmg_plan *plan, int *patches_per_tile, int *grid);
 
 /* One correction step (Algorithm 1 after the coarse solve) for every box of
- * the plan in six launches, independent of the number of boxes:
- * prolongation, residual (+ LPS corners), fused gather + network
- * (persistent over the patch tiles of all boxes), extension giving the
- * corrected iterate (v~ + d, p~), right-hand side, restriction (FP64).
+ * the plan in five kernel launches, independent of the number of boxes:
+ * prolongation fused with the residual (as dnnmg_prolong_residual), fused
+ * gather + network (persistent over the patch tiles of all boxes),
+ * extension giving the corrected iterate (v~ + d, p~), right-hand side,
+ * restriction (FP64).
  * Buffers (batch layout): xc FP64 [4 comps], vprev FP32 [3], xt, r, xcorr,
  * b FP32 [4], Y FP32 [patches][81], bc FP64 [4].  No forcing.  The step can
  * be captured in a HIP graph. */

@@ -86,6 +86,7 @@ _sig("dnnmg_prolong", [_P(Box), ctypes.c_int, c_vp, c_vp, c_vp])
 _sig("dnnmg_residual_workspace", [_P(Box)], c_sz)
 _sig("dnnmg_residual", [_P(Box), _P(NS), c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp])
 _sig("dnnmg_rhs", [_P(Box), _P(NS), c_vp, c_vp, c_vp, c_vp])
+_sig("dnnmg_prolong_residual", [_P(Box), _P(NS), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp])
 _sig("dnnmg_restrict", [_P(Box), ctypes.c_int, c_vp, c_vp, c_vp])
 _sig("dnnmg_patch_gather", [_P(Box), c_vp, c_vp, _P(Feat), ctypes.c_int, c_f, c_vp, c_i64, c_vp])
 _sig("dnnmg_mlp_packed_bytes", [ctypes.c_int, ctypes.c_int, ctypes.c_int], c_sz)
@@ -121,7 +122,7 @@ EXPORTS = [
     "dnnmg_version", "dnnmg_last_error", "dnnmg_box_sizes", "dnnmg_patch_dofmap", "dnnmg_prolong",
     "dnnmg_residual_workspace", "dnnmg_residual", "dnnmg_rhs", "dnnmg_restrict",
     "dnnmg_patch_gather", "dnnmg_mlp_packed_bytes", "dnnmg_mlp_pack", "dnnmg_patch_forward",
-    "dnnmg_patch_forward_tiles",
+    "dnnmg_patch_forward_tiles", "dnnmg_prolong_residual",
     "dnnmg_patch_saved_bytes", "dnnmg_scatter_avg", "dnnmg_norm2_workspace", "dnnmg_norm2_f64",
     "dnnmg_mse_grad", "dnnmg_patch_backward_workspace", "dnnmg_patch_backward", "dnnmg_adamw_step",
     "dnnmg_vanka_workspace", "dnnmg_vanka_sweeps", "dnnmg_fallback_workspace", "dnnmg_fallback",
@@ -211,6 +212,15 @@ def dnnmg_rhs(box, ns, v, b_out, fmid=None, stream=None):
     _check(_lib.dnnmg_rhs(ctypes.byref(b), ctypes.byref(NS.of(ns)), _ptr(v, torch.float32, 3 * nf, "v"),
                           _ptr(fmid, torch.float32, 3 * nf, "fmid"),
                           _ptr(b_out, torch.float32, 4 * nf, "b"), _stream(stream)))
+
+
+def dnnmg_prolong_residual(box, ns, xc, vprev, xt, r, fmid=None, stream=None):
+    b = Box.of(box)
+    nf, nc, _ = box_sizes(b)
+    _check(_lib.dnnmg_prolong_residual(ctypes.byref(b), ctypes.byref(NS.of(ns)), _ptr(xc, torch.float64, 4 * nc, "xc"),
+                                       _ptr(vprev, torch.float32, 3 * nf, "vprev"),
+                                       _ptr(fmid, torch.float32, 3 * nf, "fmid"), _ptr(xt, torch.float32, 4 * nf, "xt"),
+                                       _ptr(r, torch.float32, 4 * nf, "r"), _stream(stream)))
 
 
 def dnnmg_restrict(box, bf, bc, ncomp=4, stream=None):

@@ -1,7 +1,7 @@
 // Batched correction step over many independent boxes of uneven size, with a
 // launch plan and an autotuner.  The per-box field blocks are concatenated
-// (BoxDesc); one step is six launches whatever the number of boxes:
-//   prolongation, residual (+ LPS corners), fused gather + network
+// (BoxDesc); one step is five kernel launches whatever the number of boxes:
+//   prolongation fused with the residual, fused gather + network
 //   (persistent: blocks walk the patch tiles of all boxes), extension
 //   (v~ + d), right-hand side, restriction.
 // The plan keeps the layout, the launch geometry and the tuned choices of
@@ -15,11 +15,10 @@ namespace dnnmg {
 
 ResParams make_params(const Mesh &m, const dnnmg_ns *ns);
 void residual_tiles(const Mesh &m, int rt[3]);
-void residual_batch_launch(const BoxDesc *D, int nbox, int64_t ntiles, int64_t ncoarse_blocks, const float *x,
-                           const float *vp, float *r, float *aux, int *tflag, hipStream_t s);
-void rhs_batch_launch(const BoxDesc *D, int nbox, int64_t ntiles, const float *v, float *b, hipStream_t s);
-void prolong_batch_launch(const BoxDesc *D, int nbox, int64_t nblk, const double *xc, float *xf, hipStream_t s);
+void prolong_residual_batch_launch(const BoxDesc *D, int nbox, int64_t ntiles, const double *xc, const float *vp,
+                                   float *xt, float *r, hipStream_t s);
 void restrict_batch_launch(const BoxDesc *D, int nbox, int64_t nblk, const float *bf, double *bc, hipStream_t s);
+void rhs_batch_launch(const BoxDesc *D, int nbox, int64_t ntiles, const float *v, float *b, hipStream_t s);
 void scatter_batch_launch(const BoxDesc *D, int nbox, int64_t nblk, const float *Y, const float *vbase, float *xc,
                           hipStream_t s);
 
@@ -32,8 +31,6 @@ struct dnnmg_plan {
     dnnmg_ns ns;
     std::vector<BoxDesc> desc;
     BoxDesc *d_desc;   // in the caller's workspace
-    float *aux;        // LPS corner sums (32 floats per patch)
-    int *tflag;        // LPS flag per residual tile
     int64_t n_fine, n_coarse, n_patches;
     int64_t blk_fine, blk_coarse, tiles, ptiles;
     int pt;            // tuned: patches per network tile / 16
@@ -85,16 +82,11 @@ static int upload(dnnmg_plan *p, hipStream_t s) {
 
 extern "C" size_t dnnmg_plan_workspace(const dnnmg_box *boxes, int nbox) {
     if (!boxes || nbox < 1) return 0;
-    int64_t np = 0, nt = 0;
     for (int i = 0; i < nbox; ++i) {
         Mesh m;
         if (make_mesh(&boxes[i], &m)) return 0;
-        np += m.n_patches;
-        int rt[3];
-        residual_tiles(m, rt);
-        nt += (int64_t)rt[0] * rt[1] * rt[2];
     }
-    return up256(sizeof(BoxDesc) * nbox) + up256(sizeof(float) * 32 * np) + up256(sizeof(int) * nt);
+    return up256(sizeof(BoxDesc) * nbox);
 }
 
 extern "C" int dnnmg_plan_create(const dnnmg_box *boxes, int nbox, const dnnmg_ns *ns, void *ws, size_t ws_bytes,
@@ -115,8 +107,6 @@ extern "C" int dnnmg_plan_create(const dnnmg_box *boxes, int nbox, const dnnmg_n
         return rc;
     }
     p->d_desc = (BoxDesc *)ws;
-    p->aux = (float *)((char *)ws + up256(sizeof(BoxDesc) * nbox));
-    p->tflag = (int *)((char *)p->aux + up256(sizeof(float) * 32 * p->n_patches));
     if ((rc = upload(p, (hipStream_t)stream))) {
         delete p;
         return rc;
@@ -149,8 +139,7 @@ static int step_impl(const dnnmg_plan *p, const dnnmg_mlp *net, const float *shi
                      const double *xc, const float *vprev, float *xt, float *r, float *Y, float *xcorr, float *b,
                      double *bc, hipStream_t s) {
     const BoxDesc *D = p->d_desc;
-    prolong_batch_launch(D, p->nbox, p->blk_coarse, xc, xt, s);
-    residual_batch_launch(D, p->nbox, p->tiles, p->blk_coarse, xt, vprev, r, p->aux, p->tflag, s);
+    prolong_residual_batch_launch(D, p->nbox, p->tiles, xc, vprev, xt, r, s);
     BoxDesc none{};
     int rc = fwd_launch(net, p->pt, true, p->ptiles, p->grid, 0, nullptr, 0, D, p->nbox, none, xt, r, shift, inv,
                         Y, nullptr, s);
@@ -187,8 +176,7 @@ extern "C" int dnnmg_plan_autotune(dnnmg_plan *p, const dnnmg_mlp *net, const fl
     if (reps < 1) reps = 1;
     hipStream_t s = (hipStream_t)stream;
     // inputs of the network stage
-    prolong_batch_launch(p->d_desc, p->nbox, p->blk_coarse, xc, xt, s);
-    residual_batch_launch(p->d_desc, p->nbox, p->tiles, p->blk_coarse, xt, vprev, r, p->aux, p->tflag, s);
+    prolong_residual_batch_launch(p->d_desc, p->nbox, p->tiles, xc, vprev, xt, r, s);
     int dev = 0, ncu = 256;
     if ((rc = hip_check(hipGetDevice(&dev), "autotune device"))) return rc;
     if ((rc = hip_check(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev), "autotune CU count")))

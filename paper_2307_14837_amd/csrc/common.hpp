@@ -67,6 +67,16 @@ __device__ __forceinline__ bool on_dirichlet(const Mesh &m, int i, int j, int k)
     return false;
 }
 
+// Workgroups go to the chip's 8 XCDs (each with its own L2) round-robin by
+// workgroup index.  A launch of xcd_blocks(n) workgroups where workgroup b
+// takes item xcd_item(b, gridDim) gives each XCD one contiguous range of
+// items, so neighbouring tiles (which read each other's halos) share an L2.
+constexpr int NXCD = 8;
+inline unsigned xcd_blocks(int64_t n) { return (unsigned)(NXCD * ((n + NXCD - 1) / NXCD)); }
+__device__ __forceinline__ int64_t xcd_item(int64_t b, int64_t nblocks) {
+    return (b % NXCD) * (nblocks / NXCD) + b / NXCD;
+}
+
 inline unsigned blocks_for(int64_t n, int threads) {
     return (unsigned)((n + threads - 1) / threads);
 }

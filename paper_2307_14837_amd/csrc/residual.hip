@@ -8,14 +8,19 @@
 //
 // Work decomposition.  A workgroup owns a block of TX x TY x TZ fine nodes
 // whose origin is even in every axis (so it is aligned to patches).  It
-// stages the fields of the node block plus a halo into LDS, evaluates every
-// fine cell touching an owned node (one extra cell layer on the low side),
-// and accumulates the cells' vertex integrals into an LDS node array in 8
-// colour phases (cells of one parity class share no vertex), so the sum
-// order is fixed and no atomics are used.  Owned nodes are then written
-// once.  The LPS test functions pi(phi_i) live on the corners of a patch;
-// those contributions are summed per owned patch in LDS and written to a
-// workspace, and a second small kernel adds them to the coarse-vertex nodes.
+// stages the fields of the node block plus a halo into LDS and evaluates
+// every fine cell touching an owned node (one extra cell layer on the low
+// side), one thread per cell.  Per equation the cells' vertex integrals go
+// to LDS and each owned node sums its 8 cells in a fixed order, so no
+// atomics are used and the result does not depend on scheduling.  Owned
+// nodes are written once.  The local projection terms vanish exactly on
+// cells where the iterate equals its patch interpolant (always the case for
+// a prolongated coarse solution); they are evaluated in a second pass only
+// for the other cells.  Their test functions pi(phi_i) live on the corners
+// of a patch: those contributions are summed per owned patch and written to
+// a workspace (with a per-tile flag), and a second small kernel adds them to
+// the coarse-vertex nodes.  Tiles are laid out so that each XCD takes one
+// contiguous range of them (halo reads then hit the XCD's own L2).
 //
 // Per cell the quadrature uses sum factorisation: values and gradients at
 // the 8 Gauss points from the 8 vertex values, and the transpose to vertex
@@ -199,6 +204,10 @@ __device__ __forceinline__ void pi_transpose(const float vals[8], int ox, int oy
 // ------------------------------------------------------------ kernel ------
 constexpr int MODE_RES = 0;
 constexpr int MODE_RHS = 1;
+// residual of the prolongation of a coarse iterate, which the tile computes
+// itself (and writes out): the iterate is patchwise Q1, so every local
+// projection term vanishes identically and none is evaluated
+constexpr int MODE_PRES = 2;
 
 template <int MODE>
 struct ResTile {
@@ -211,9 +220,11 @@ struct ResTile {
     static constexpr int VX = TX + 2, VY = TY + 2, VZ = TZ + 2, VN = VX * VY * VZ;
     static constexpr int NPX = TX / 2, NPY = TY / 2, NPZ = TZ / 2, NP = NPX * NPY * NPZ;
     static constexpr int NT = 768; // one thread per cell (765 cells)
-    static constexpr int NF_STAGE = MODE == MODE_RES ? 4 : 0; // x, p on the wide range
+    static constexpr int NF_STAGE = MODE != MODE_RHS ? 4 : 0; // x, p on the wide range
     static constexpr int NF_V = 3;                            // vp (res) or v (rhs)
-    static constexpr int NACC = MODE == MODE_RES ? 4 : 3;
+    static constexpr int NACC = MODE != MODE_RHS ? 4 : 3;
+    // coarse nodes under the staged range (prolongating tiles)
+    static constexpr int CX = TX / 2 + 2, CY = TY / 2 + 2, CZ = TZ / 2 + 2, CN = CX * CY * CZ;
     static_assert(NT >= NCELL && NT >= NOWN && NT >= 8 * NP, "one pass per role");
 };
 
@@ -227,13 +238,16 @@ template <int MODE>
 __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P, int bx, int by, int bz,
                                               const float *__restrict__ x, const float *__restrict__ vp,
                                               const float *__restrict__ fmid, float *__restrict__ out,
-                                              float *__restrict__ aux, int *__restrict__ tflag) {
+                                              float *__restrict__ aux, int *__restrict__ tflag,
+                                              const double *__restrict__ xc = nullptr,
+                                              float *__restrict__ xt_out = nullptr) {
     using T = ResTile<MODE>;
     __shared__ float sX[T::NF_STAGE > 0 ? T::NF_STAGE * T::SN : 1];
     __shared__ float sV[T::NF_V * T::VN];
     __shared__ float sF[3 * T::VN];      // forcing, when given
     __shared__ float sCell[8 * T::NCELL]; // [vertex j][cell]
     __shared__ float sCor[MODE == MODE_RES ? 8 * T::NCELL : 1];
+    __shared__ float sC[MODE == MODE_PRES ? 4 * T::CN : 1]; // coarse iterate, rounded to FP32
 
     const int x0 = bx * T::TX, y0 = by * T::TY, z0 = bz * T::TZ;
     const int tid = threadIdx.x;
@@ -249,6 +263,52 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
     };
     // all loads of a thread are issued before its LDS stores, so the staging
     // costs one memory round trip
+    if constexpr (MODE == MODE_PRES) {
+        // coarse nodes x0/2 - 1 .. of the staged range, then Q1 interpolation
+        // axis by axis (x, y, z) in FP32: the operations of the prolongation
+        // kernel, so x~ is the same to the bit
+        const int64_t ncn = m.n_coarse;
+        for (int s = tid; s < T::CN; s += T::NT) {
+            int ci = x0 / 2 - 1 + s % T::CX, cj = y0 / 2 - 1 + (s / T::CX) % T::CY, ck = z0 / 2 - 1 + s / (T::CX * T::CY);
+            ci = wrap(ci, m.nc[0], m.per[0]);
+            cj = wrap(cj, m.nc[1], m.per[1]);
+            ck = wrap(ck, m.nc[2], m.per[2]);
+            const bool ok = ci >= 0 && ci < m.nc[0] && cj >= 0 && cj < m.nc[1] && ck >= 0 && ck < m.nc[2];
+            const int64_t g = ci + (int64_t)m.nc[0] * (cj + (int64_t)m.nc[1] * ck);
+            float v[4];
+#pragma unroll
+            for (int f = 0; f < 4; ++f) v[f] = ok ? (float)xc[f * ncn + g] : 0.0f;
+#pragma unroll
+            for (int f = 0; f < 4; ++f) sC[f * T::CN + s] = v[f];
+        }
+        __syncthreads();
+        for (int s = tid; s < T::SN; s += T::NT) {
+            const int lx = s % T::SX, ly = (s / T::SX) % T::SY, lz = s / (T::SX * T::SY);
+            bool ok;
+            (void)gnode(x0 - 2 + lx, y0 - 2 + ly, z0 - 2 + lz, ok);
+            // the staged origin x0 - 2 is even: parities and coarse cells follow lx
+            const int ox = lx & 1, oy = ly & 1, oz = lz & 1;
+            const int cb = (lx >> 1) + T::CX * ((ly >> 1) + T::CY * (lz >> 1));
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                const float *c = sC + f * T::CN + cb;
+                float X[2][2] = {{0.f, 0.f}, {0.f, 0.f}}; // [y][z] after the x pass
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int cc = 0; cc < 2; ++cc) {
+                        if ((b && !oy) || (cc && !oz)) continue;
+                        const int o = T::CX * (b + T::CY * cc);
+                        X[b][cc] = ox ? 0.5f * (c[o] + c[o + 1]) : c[o];
+                    }
+                float Yv[2];
+#pragma unroll
+                for (int cc = 0; cc < 2; ++cc) Yv[cc] = oy ? 0.5f * (X[0][cc] + X[1][cc]) : X[0][cc];
+                const float v = oz ? 0.5f * (Yv[0] + Yv[1]) : Yv[0];
+                sX[f * T::SN + s] = ok ? v : 0.0f;
+            }
+        }
+    }
     if constexpr (MODE == MODE_RES) {
         constexpr int IT = (T::SN + T::NT - 1) / T::NT;
         float tmp[IT][4];
@@ -291,7 +351,7 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
                 for (int f = 0; f < 3; ++f) dst[f * T::VN + s] = tmp[it][f];
         }
     };
-    stage_v(MODE == MODE_RES ? vp : x, sV);
+    stage_v(MODE != MODE_RHS ? vp : x, sV);
     if (fmid) stage_v(fmid, sF);
     __syncthreads();
 
@@ -299,9 +359,13 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
     const float ih0 = P.ih[0], ih1 = P.ih[1], ih2 = P.ih[2];
 
     // ---- this thread's cell: lower corner at origin - 1 + (ex, ey, ez) ----
+    // (the few threads past the last cell compute on cell NCELL - 1 and
+    // contribute nothing; dead cells read in-range LDS values and are masked
+    // when their integrals are stored)
     const int e = tid;
     bool live = e < T::NCELL;
-    const int ex = e % T::EX, ey = (e / T::EX) % T::EY, ez = e / (T::EX * T::EY);
+    const int ec = e < T::NCELL ? e : T::NCELL - 1;
+    const int ex = ec % T::EX, ey = (ec / T::EX) % T::EY, ez = ec / (T::EX * T::EY);
     const int gx = x0 - 1 + ex, gy = y0 - 1 + ey, gz = z0 - 1 + ez;
     if (live) {
         if (!m.per[0]) live &= gx >= 0 && gx < ncx;
@@ -348,7 +412,7 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
 #pragma unroll
-            for (int j = 0; j < 8; ++j) w[d][j] = live ? sV[d * T::VN + vb + voff(j)] : 0.0f;
+            for (int j = 0; j < 8; ++j) w[d][j] = sV[d * T::VN + vb + voff(j)];
             eval_val(w[d], wv[d]);
         }
 #pragma unroll
@@ -359,7 +423,7 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
             if (fmid) {
                 float fv[8];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) fv[j] = live ? sF[a * T::VN + vb + voff(j)] : 0.0f;
+                for (int j = 0; j < 8; ++j) fv[j] = sF[a * T::VN + vb + voff(j)];
                 eval_val(fv, F);
             } else {
 #pragma unroll
@@ -381,7 +445,7 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
         // patch interpolant.  When the vertex values and the interpolant
         // computed here agree bit for bit every LPS contribution of the cell
         // is exactly zero; the other cells get them in a second pass.
-        if (live) {
+        if (MODE == MODE_RES && live) {
 #pragma unroll
             for (int d = 0; d < 4; ++d) {
                 float cv[8], pw[8];
@@ -398,10 +462,10 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
         for (int d = 0; d < 3; ++d) {
             float w[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) w[j] = live ? sX[d * T::SN + xb + xoff(j)] : 0.0f;
+            for (int j = 0; j < 8; ++j) w[j] = sX[d * T::SN + xb + xoff(j)];
             eval_val(w, xv[d]);
 #pragma unroll
-            for (int j = 0; j < 8; ++j) w[j] = live ? sV[d * T::VN + vb + voff(j)] : 0.0f;
+            for (int j = 0; j < 8; ++j) w[j] = sV[d * T::VN + vb + voff(j)];
             eval_val(w, pv[d]);
         }
 #pragma unroll
@@ -411,11 +475,11 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
             float wa[8], va[8], dif[8], sum[8], pj[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
-                wa[j] = live ? sV[a * T::VN + vb + voff(j)] : 0.0f;
-                va[j] = live ? sX[a * T::SN + xb + xoff(j)] : 0.0f;
-                pj[j] = live ? sX[3 * T::SN + xb + xoff(j)] : 0.0f;
+                wa[j] = sV[a * T::VN + vb + voff(j)];
+                va[j] = sX[a * T::SN + xb + xoff(j)];
+                pj[j] = sX[3 * T::SN + xb + xoff(j)];
                 // (1/k)(vp_a - v_a) + (f^{n-1} + f^n)/2 at the vertices
-                dif[j] = fmaf(P.inv_dt, wa[j] - va[j], fmid && live ? sF[a * T::VN + vb + voff(j)] : 0.0f);
+                dif[j] = fmaf(P.inv_dt, wa[j] - va[j], fmid ? sF[a * T::VN + vb + voff(j)] : 0.0f);
                 sum[j] = wa[j] + va[j];
             }
             float F[8], Gx[8], Gy[8], Gz[8], tmp[8], pq[8];
@@ -593,8 +657,13 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
             bool dir = on_dirichlet(m, gi, gj, gk);
 #pragma unroll
             for (int f = 0; f < 3; ++f) out[f * nfn + g] = dir ? 0.0f : res[f];
-            if constexpr (MODE == MODE_RES) out[3 * nfn + g] = res[3];
+            if constexpr (MODE != MODE_RHS) out[3 * nfn + g] = res[3];
             else out[3 * nfn + g] = 0.0f;
+            if constexpr (MODE == MODE_PRES) {
+                const int slot = (lx + 2) + T::SX * ((ly + 2) + T::SY * (lz + 2));
+#pragma unroll
+                for (int f = 0; f < 4; ++f) xt_out[f * nfn + g] = sX[f * T::SN + slot];
+            }
         }
     }
     if constexpr (MODE == MODE_RES) {
@@ -614,11 +683,16 @@ template <int MODE>
 __global__ void __launch_bounds__(ResTile<MODE>::NT)
     k_residual(Mesh m, ResParams P, const float *__restrict__ x, const float *__restrict__ vp,
                const float *__restrict__ fmid, float *__restrict__ out, float *__restrict__ aux,
-               int *__restrict__ tflag, const int *__restrict__ flag) {
+               int *__restrict__ tflag, const int *__restrict__ flag, const double *__restrict__ xc,
+               float *__restrict__ xt_out) {
     if (flag && *flag == 0) return; // predicated launch (fallback path not taken)
-    const int tl = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-    residual_tile<MODE>(m, P, blockIdx.x, blockIdx.y, blockIdx.z, x, vp, fmid, out, aux,
-                        MODE == MODE_RES ? tflag + tl : nullptr);
+    using T = ResTile<MODE>;
+    const int rt0 = (m.nf[0] + T::TX - 1) / T::TX, rt1 = (m.nf[1] + T::TY - 1) / T::TY;
+    const int rt2 = (m.nf[2] + T::TZ - 1) / T::TZ;
+    const int tl = (int)xcd_item(blockIdx.x, gridDim.x);
+    if (tl >= rt0 * rt1 * rt2) return;
+    residual_tile<MODE>(m, P, tl % rt0, (tl / rt0) % rt1, tl / (rt0 * rt1), x, vp, fmid, out, aux,
+                        MODE == MODE_RES ? tflag + tl : nullptr, xc, xt_out);
 }
 
 // Batched: one flat grid over the tiles of all boxes.  x is a 4-component
@@ -626,19 +700,22 @@ __global__ void __launch_bounds__(ResTile<MODE>::NT)
 // part), vp has 3 components, out 4; aux holds 32 floats per patch.
 template <int MODE>
 __global__ void __launch_bounds__(ResTile<MODE>::NT)
-    k_residual_batch(const BoxDesc *__restrict__ D, int nbox, const float *__restrict__ x,
+    k_residual_batch(const BoxDesc *__restrict__ D, int nbox, int64_t ntiles, const float *__restrict__ x,
                      const float *__restrict__ vp, float *__restrict__ out, float *__restrict__ aux,
-                     int *__restrict__ tflag) {
-    const int64_t blk = blockIdx.x;
+                     int *__restrict__ tflag, const double *__restrict__ xc, float *__restrict__ xt_out) {
+    const int64_t blk = xcd_item(blockIdx.x, gridDim.x);
+    if (blk >= ntiles) return;
     const int b = find_box(nbox, blk, [&](int i) { return D[i].blk_tile; });
     const BoxDesc &d = D[b];
     const Mesh m = d.m;
     const ResParams P = d.rp;
     int t = (int)(blk - d.blk_tile);
     int bx = t % d.rtiles[0], by = (t / d.rtiles[0]) % d.rtiles[1], bz = t / (d.rtiles[0] * d.rtiles[1]);
-    residual_tile<MODE>(m, P, bx, by, bz, x + 4 * d.off_fine, MODE == MODE_RES ? vp + 3 * d.off_fine : nullptr,
-                        nullptr, out + 4 * d.off_fine, MODE == MODE_RES ? aux + 32 * d.off_patch : nullptr,
-                        MODE == MODE_RES ? tflag + blk : nullptr);
+    residual_tile<MODE>(m, P, bx, by, bz, MODE != MODE_PRES ? x + 4 * d.off_fine : nullptr,
+                        MODE != MODE_RHS ? vp + 3 * d.off_fine : nullptr, nullptr, out + 4 * d.off_fine,
+                        MODE == MODE_RES ? aux + 32 * d.off_patch : nullptr, MODE == MODE_RES ? tflag + blk : nullptr,
+                        MODE == MODE_PRES ? xc + 4 * d.off_coarse : nullptr,
+                        MODE == MODE_PRES ? xt_out + 4 * d.off_fine : nullptr);
 }
 
 // Adds the corner (pi phi) parts of the LPS terms: a coarse vertex collects
@@ -703,16 +780,6 @@ __global__ void __launch_bounds__(256) k_lps_corners(Mesh m, const float *__rest
     lps_corner_node(m, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, aux, tflag, rt, r);
 }
 
-__global__ void __launch_bounds__(256) k_lps_corners_batch(const BoxDesc *__restrict__ D, int nbox,
-                                                           const float *__restrict__ aux,
-                                                           const int *__restrict__ tflag, float *__restrict__ r) {
-    const int64_t blk = blockIdx.x;
-    const int b = find_box(nbox, blk, [&](int i) { return D[i].blk_coarse; });
-    const BoxDesc &d = D[b];
-    const Mesh m = d.m;
-    lps_corner_node(m, (blk - d.blk_coarse) * blockDim.x + threadIdx.x, aux + 32 * d.off_patch,
-                    tflag + d.blk_tile, d.rtiles, r + 4 * d.off_fine);
-}
 
 ResParams make_params(const Mesh &m, const dnnmg_ns *ns) {
     ResParams P;
@@ -754,7 +821,8 @@ int residual_launch(const Mesh &m, const dnnmg_ns *ns, const float *x, const flo
     ResParams P = make_params(m, ns);
     dim3 g = res_grid<MODE_RES>(m);
     int *tflag = (int *)((char *)aux + up256(sizeof(float) * 32 * m.n_patches));
-    k_residual<MODE_RES><<<g, ResTile<MODE_RES>::NT, 0, s>>>(m, P, x, vprev, fmid, r, aux, tflag, flag);
+    k_residual<MODE_RES><<<xcd_blocks((int64_t)g.x * g.y * g.z), ResTile<MODE_RES>::NT, 0, s>>>(
+        m, P, x, vprev, fmid, r, aux, tflag, flag, nullptr, nullptr);
     k_lps_corners<<<blocks_for(m.n_coarse, 256), 256, 0, s>>>(m, aux, tflag, g.x, g.y, g.z, r, flag);
     return hip_check(hipGetLastError(), "dnnmg_residual launch");
 }
@@ -766,15 +834,17 @@ void residual_tiles(const Mesh &m, int rt[3]) {
     rt[2] = g.z;
 }
 
-void residual_batch_launch(const BoxDesc *D, int nbox, int64_t ntiles, int64_t ncoarse_blocks, const float *x,
-                           const float *vp, float *r, float *aux, int *tflag, hipStream_t s) {
-    k_residual_batch<MODE_RES><<<(unsigned)ntiles, ResTile<MODE_RES>::NT, 0, s>>>(D, nbox, x, vp, r, aux, tflag);
-    k_lps_corners_batch<<<(unsigned)ncoarse_blocks, 256, 0, s>>>(D, nbox, aux, tflag, r);
-}
 
 void rhs_batch_launch(const BoxDesc *D, int nbox, int64_t ntiles, const float *v, float *b, hipStream_t s) {
-    k_residual_batch<MODE_RHS><<<(unsigned)ntiles, ResTile<MODE_RHS>::NT, 0, s>>>(D, nbox, v, nullptr, b, nullptr,
-                                                                                nullptr);
+    k_residual_batch<MODE_RHS><<<xcd_blocks(ntiles), ResTile<MODE_RHS>::NT, 0, s>>>(D, nbox, ntiles, v, nullptr, b,
+                                                                                   nullptr, nullptr, nullptr,
+                                                                                   nullptr);
+}
+
+void prolong_residual_batch_launch(const BoxDesc *D, int nbox, int64_t ntiles, const double *xc, const float *vp,
+                                   float *xt, float *r, hipStream_t s) {
+    k_residual_batch<MODE_PRES><<<xcd_blocks(ntiles), ResTile<MODE_PRES>::NT, 0, s>>>(D, nbox, ntiles, nullptr, vp, r,
+                                                                                    nullptr, nullptr, xc, xt);
 }
 
 } // namespace dnnmg
@@ -809,7 +879,23 @@ extern "C" int dnnmg_rhs(const dnnmg_box *box, const dnnmg_ns *ns, const float *
     if ((rc = check_ns(ns))) return rc;
     if (!v || !b) return fail(DNNMG_ERR_ARG, "dnnmg_rhs: NULL pointer");
     ResParams P = make_params(m, ns);
-    k_residual<MODE_RHS><<<res_grid<MODE_RHS>(m), ResTile<MODE_RHS>::NT, 0, (hipStream_t)stream>>>(
-        m, P, v, nullptr, fmid, b, nullptr, nullptr, nullptr);
+    dim3 g = res_grid<MODE_RHS>(m);
+    k_residual<MODE_RHS><<<xcd_blocks((int64_t)g.x * g.y * g.z), ResTile<MODE_RHS>::NT, 0, (hipStream_t)stream>>>(
+        m, P, v, nullptr, fmid, b, nullptr, nullptr, nullptr, nullptr, nullptr);
     return hip_check(hipGetLastError(), "dnnmg_rhs launch");
 }
+
+extern "C" int dnnmg_prolong_residual(const dnnmg_box *box, const dnnmg_ns *ns, const double *xc,
+                                      const float *vprev, const float *fmid, float *xt, float *r, void *stream) {
+    Mesh m;
+    int rc = make_mesh(box, &m);
+    if (rc) return rc;
+    if ((rc = check_ns(ns))) return rc;
+    if (!xc || !vprev || !xt || !r) return fail(DNNMG_ERR_ARG, "dnnmg_prolong_residual: NULL pointer");
+    ResParams P = make_params(m, ns);
+    dim3 g = res_grid<MODE_PRES>(m);
+    k_residual<MODE_PRES><<<xcd_blocks((int64_t)g.x * g.y * g.z), ResTile<MODE_PRES>::NT, 0, (hipStream_t)stream>>>(
+        m, P, nullptr, vprev, fmid, r, nullptr, nullptr, nullptr, xc, xt);
+    return hip_check(hipGetLastError(), "dnnmg_prolong_residual launch");
+}
+

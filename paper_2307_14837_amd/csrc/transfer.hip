@@ -6,6 +6,7 @@
 // and are bound by HBM bandwidth; threads map to consecutive x nodes so that
 // the fine-field streams are coalesced.
 #include "common.hpp"
+#include "extension.hpp"
 #include "lowp.hpp"
 
 namespace dnnmg {
@@ -115,15 +116,6 @@ __global__ void __launch_bounds__(256) k_prolong(Mesh m, int ncomp, const double
     prolong_node(m, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, ncomp, xc, xf);
 }
 
-__global__ void __launch_bounds__(256) k_prolong_batch(const BoxDesc *__restrict__ D, int nbox,
-                                                       const double *__restrict__ xc, float *__restrict__ xf) {
-    const int64_t blk = blockIdx.x;
-    const int b = find_box(nbox, blk, [&](int i) { return D[i].blk_coarse; });
-    const BoxDesc &d = D[b];
-    const Mesh m = d.m;
-    prolong_node(m, (blk - d.blk_coarse) * blockDim.x + threadIdx.x, 4, xc + 4 * d.off_coarse,
-                 xf + 4 * d.off_fine);
-}
 
 // --------------------------------------------------------- restriction ----
 // bc(I) = sum over fine nodes i in {2I-1, 2I, 2I+1} (per axis) of
@@ -248,80 +240,17 @@ __global__ void __launch_bounds__(256)
 // index, at most two) and the node's local coordinate in each; the mean of
 // the network outputs over these patches.  The 2x2x2 candidate set is fixed
 // (absent candidates carry weight 0) so all loads are issued at once.
-struct Hold1 {
-    int P[2];
-    int loc[2];
-    float w[2];
-    int cnt;
-};
-
-__device__ __forceinline__ Hold1 holders(int i, int n, int per) {
-    Hold1 h;
-    if (i & 1) {
-        h.P[0] = h.P[1] = (i - 1) >> 1;
-        h.loc[0] = h.loc[1] = 1;
-        h.w[0] = 1.f;
-        h.w[1] = 0.f;
-        h.cnt = 1;
-        return h;
-    }
-    int hi = i >> 1;   // patch starting here (local 0)
-    int lo = hi - 1;   // patch ending here (local 2)
-    if (per) {
-        if (lo < 0) lo += n;
-        bool lo_first = lo < hi; // ascending patch order
-        h.P[0] = lo_first ? lo : hi;
-        h.loc[0] = lo_first ? 2 : 0;
-        h.P[1] = lo_first ? hi : lo;
-        h.loc[1] = lo_first ? 0 : 2;
-        h.w[0] = h.w[1] = 1.f;
-        h.cnt = 2;
-        return h;
-    }
-    bool has_lo = lo >= 0, has_hi = hi < n;
-    h.P[0] = has_lo ? lo : hi;
-    h.loc[0] = has_lo ? 2 : 0;
-    h.P[1] = has_hi ? hi : h.P[0];
-    h.loc[1] = has_hi ? 0 : h.loc[0];
-    h.w[0] = 1.f;
-    h.w[1] = (has_lo && has_hi) ? 1.f : 0.f;
-    h.cnt = (int)has_lo + (int)has_hi;
-    return h;
-}
-
 __device__ __forceinline__ void scatter_node(const Mesh &m, int64_t t, const float *__restrict__ Y,
                                              const float *__restrict__ vbase, float *__restrict__ d) {
     if (t >= m.n_fine) return;
     uint32_t jk = fdiv((uint32_t)t, m.fx), i = (uint32_t)t - jk * m.nf[0];
     uint32_t k = fdiv(jk, m.fy), j = jk - k * m.nf[1];
-    float acc[3] = {0.0f, 0.0f, 0.0f};
-    const bool dir = on_dirichlet(m, i, j, k);
-    Hold1 hx = holders(i, m.n[0], m.per[0]);
-    Hold1 hy = holders(j, m.n[1], m.per[1]);
-    Hold1 hz = holders(k, m.n[2], m.per[2]);
-    float y[8][3], wgt[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        int a = q & 1, b = (q >> 1) & 1, c = q >> 2;
-        int64_t M = hx.P[a] + (int64_t)m.n[0] * (hy.P[b] + (int64_t)m.n[1] * hz.P[c]);
-        int iota = hx.loc[a] + 3 * hy.loc[b] + 9 * hz.loc[c];
-        const float *src = Y + M * 81 + iota;
-        y[q][0] = src[0];
-        y[q][1] = src[27];
-        y[q][2] = src[54];
-        wgt[q] = hx.w[a] * hy.w[b] * hz.w[c];
-    }
-    // sum in ascending patch order (z, then y, then x of the candidates)
-#pragma unroll
-    for (int q = 0; q < 8; ++q)
-#pragma unroll
-        for (int cc = 0; cc < 3; ++cc) acc[cc] = fmaf(wgt[q], y[q][cc], acc[cc]);
-    const float inv = 1.0f / (float)(hx.cnt * hy.cnt * hz.cnt); // power of two: exact
+    float v[3];
+    extension_at(m, (int)i, (int)j, (int)k, Y, v);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        float v = dir ? 0.0f : acc[c] * inv;
-        if (vbase) v += vbase[c * m.n_fine + t];
-        d[c * m.n_fine + t] = v;
+        if (vbase) v[c] += vbase[c * m.n_fine + t];
+        d[c * m.n_fine + t] = v[c];
     }
     // the network predicts no pressure correction: the corrected iterate
     // keeps the prolongated pressure
@@ -380,9 +309,6 @@ __global__ void __launch_bounds__(256) k_norm_final(int nparts, const double *__
     if (threadIdx.x == 0) *out = red[0];
 }
 
-void prolong_batch_launch(const BoxDesc *D, int nbox, int64_t nblk, const double *xc, float *xf, hipStream_t s) {
-    k_prolong_batch<<<(unsigned)nblk, 256, 0, s>>>(D, nbox, xc, xf);
-}
 void restrict_batch_launch(const BoxDesc *D, int nbox, int64_t nblk, const float *bf, double *bc, hipStream_t s) {
     k_restrict_batch<<<(unsigned)nblk, 256, 0, s>>>(D, nbox, bf, bc);
 }
@@ -390,6 +316,7 @@ void scatter_batch_launch(const BoxDesc *D, int nbox, int64_t nblk, const float 
                           hipStream_t s) {
     k_scatter_batch<<<(unsigned)nblk, 256, 0, s>>>(D, nbox, Y, vbase, xc);
 }
+
 
 } // namespace dnnmg
 

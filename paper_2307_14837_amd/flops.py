@@ -47,6 +47,16 @@ def residual_flops_per_cell(lps: bool = False) -> int:
     return total
 
 
+PROLONG_PER_NODE = 3 * 4  # Q1 interpolation of 4 fields: 12 two-point means per 8 fine nodes, each 2 flops
+
+
+def prolong_residual_flops_per_cell() -> int:
+    """Prolongation fused with the residual, per fine cell (about one fine
+    node per cell): the Galerkin terms without the interpolant test, since a
+    prolongated iterate has no local projection terms."""
+    return residual_flops_per_cell(lps=False) - 4 * PI_VERTICES + PROLONG_PER_NODE
+
+
 def rhs_flops_per_cell() -> int:
     """Right-hand side b = Rhs(v) per fine cell (no forcing)."""
     per_comp = EVAL_VG + 8 + 24 + 7 * 8 + INTEGRATE

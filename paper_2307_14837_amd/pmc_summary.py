@@ -1,0 +1,79 @@
+"""HBM traffic per launch of the dominant entry point from two rocprofv3
+counter runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of
+`bench.py --pmc-probe`, calibrated by the plain copy kernel of known size the
+probe runs in the same process.
+
+    python -m paper_2307_14837_amd.pmc_summary --fetch F.csv --write W.csv \\
+        --probe probe.json --out profiles/pmc_<workload>.json
+
+F.csv / W.csv are rocprofv3 `*_counter_collection.csv` files; probe.json is
+what `bench.py --pmc-probe` printed (its last JSON line is used).
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import json
+from collections import defaultdict
+
+ENTRY_KERNELS = {"dnnmg_prolong_residual": ("k_residual<2>",)}
+COPY_KERNEL = "neg"
+
+
+def per_kernel(path, counter):
+    """Average counter value per dispatch for each kernel name."""
+    vals = defaultdict(dict)
+    for row in csv.DictReader(open(path)):
+        if row.get("Counter_Name") != counter:
+            continue
+        # one value per dispatch (summed over dimensions if the tool splits it)
+        d = vals[row["Kernel_Name"]]
+        d[row["Dispatch_Id"]] = d.get(row["Dispatch_Id"], 0.0) + float(row["Counter_Value"])
+    return {k: sum(v.values()) / len(v) for k, v in vals.items() if v}
+
+
+def find(avgs, needle):
+    hits = [v for k, v in avgs.items() if needle in k]
+    if len(hits) != 1:
+        raise SystemExit(f"expected one kernel matching {needle!r}, found {len(hits)}")
+    return hits[0]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--probe", required=True)
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--command", default="")
+    a = ap.parse_args()
+    probe = [json.loads(l) for l in open(a.probe) if l.startswith('{"pmc_probe"')][-1]
+    fetch = per_kernel(a.fetch, "FETCH_SIZE")
+    write = per_kernel(a.write, "WRITE_SIZE")
+    # calibration: counter KiB of the copy vs its known bytes
+    f_scale = probe["copy_bytes_read"] / (1024.0 * find(fetch, COPY_KERNEL))
+    w_scale = probe["copy_bytes_written"] / (1024.0 * find(write, COPY_KERNEL))
+    entries = {}
+    for entry, kernels in ENTRY_KERNELS.items():
+        ks = {}
+        fb = wb = 0.0
+        for kname in kernels:
+            fk, wk = find(fetch, kname), find(write, kname)
+            ks[kname] = {"fetch_kib": fk, "write_kib": wk}
+            fb += fk * 1024.0 * f_scale
+            wb += wk * 1024.0 * w_scale
+        entries[entry] = {"src_hash": probe["src_hash"], "kernels": ks, "fetch_bytes": fb, "write_bytes": wb,
+                          "bytes_per_launch": fb + wb}
+    out = {"workload": probe["pmc_probe"], "command": a.command,
+           "copy": {"bytes_read": probe["copy_bytes_read"], "bytes_written": probe["copy_bytes_written"],
+                    "fetch_kib": find(fetch, COPY_KERNEL), "write_kib": find(write, COPY_KERNEL),
+                    "fetch_scale": f_scale, "write_scale": w_scale},
+           "entries": entries}
+    with open(a.out, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    print(json.dumps(out, indent=1))
+
+
+if __name__ == "__main__":
+    main()

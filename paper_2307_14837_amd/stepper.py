@@ -91,8 +91,8 @@ class CorrectionStep:
 
     def step(self, stream=None):
         box, ns = self.box, self.ns
-        L.dnnmg_prolong(box, self.xc, self.xt, stream=stream)
-        L.dnnmg_residual(box, ns, self.xt, self.vprev, self.r, self.ws_res, stream=stream)
+        # x~ = P xc and r = F - A(x~) in one pass (no LPS terms on a prolongation)
+        L.dnnmg_prolong_residual(box, ns, self.xc, self.vprev, self.xt, self.r, stream=stream)
         if self.fused:
             L.dnnmg_patch_gather_forward(box, self.net, self.xt, self.r, self.Y, self.shift, self.inv_scale,
                                          stream=stream)

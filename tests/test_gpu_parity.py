@@ -107,6 +107,37 @@ def test_residual(L, orc, name, prolongated):
         assert rel_l2(got[f], ref[f]) <= 1e-5, f
 
 
+@pytest.mark.parametrize("name", list(BOXES))
+def test_prolong_residual_fused(L, orc, name):
+    """Prolongation + residual in one pass equals dnnmg_prolong then
+    dnnmg_residual bit for bit (the separate residual finds every LPS term of
+    a prolongation exactly zero), with and without forcing."""
+    box = BOXES[name]
+    say("prolong+residual fused", name)
+    ns = syn.NSParams(1e-3, 0.01) if name != "cfg2" else syn.cfg2().ns
+    rng = np.random.default_rng(21)
+    xc = rng.standard_normal((4, box.n_coarse))
+    vp = f32(rng.standard_normal((3, box.n_fine)))
+    fm = f32(rng.standard_normal((3, box.n_fine)))
+    nf = box.n_fine
+    xcg, vpg = to_gpu(xc.ravel()), to_gpu(vp.ravel())
+    for forcing in (None, fm):
+        fg = None if forcing is None else to_gpu(forcing.ravel())
+        xt1 = torch.empty(4 * nf, dtype=torch.float32, device=dev())
+        r1 = torch.empty(4 * nf, dtype=torch.float32, device=dev())
+        ws = torch.empty(L.residual_workspace_bytes(box), dtype=torch.uint8, device=dev())
+        L.dnnmg_prolong(box, xcg, xt1)
+        L.dnnmg_residual(box, ns, xt1, vpg, r1, ws, fmid=fg)
+        xt2 = torch.full((4 * nf,), float("nan"), dtype=torch.float32, device=dev())
+        r2 = torch.full((4 * nf,), float("nan"), dtype=torch.float32, device=dev())
+        L.dnnmg_prolong_residual(box, ns, xcg, vpg, xt2, r2, fmid=fg)
+        torch.cuda.synchronize()
+        assert torch.equal(xt1, xt2) and torch.equal(r1, r2)
+        ref = orc.residual(box, ns, xt2.cpu().numpy().reshape(4, -1).astype(np.float64), vp.astype(np.float64),
+                           None if forcing is None else forcing.astype(np.float64))
+        assert rel_l2(r2.cpu().numpy().reshape(4, -1), ref) <= 1e-5
+
+
 def test_residual_forcing_and_lps_weights(L, orc):
     box = BOXES["mixed"]
     say("residual forcing + strong LPS")
