@@ -1,13 +1,20 @@
-"""HBM traffic per launch of the dominant entry point from two rocprofv3
+"""Short text summaries of rocprofv3 output for the profiles folder.
+
+pmc: HBM traffic per launch of the dominant entry point from two rocprofv3
 counter runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of
 `bench.py --pmc-probe`, calibrated by the plain copy kernel of known size the
-probe runs in the same process.
+probe runs in the same process:
 
-    python -m paper_2307_14837_amd.pmc_summary --fetch F.csv --write W.csv \\
-        --probe probe.json --out profiles/pmc_<workload>.json
+    python -m paper_2307_14837_amd.profile_summary pmc --fetch F.csv --write W.csv \\
+        --probe probe.log --out profiles/pmc_<workload>.json
 
-F.csv / W.csv are rocprofv3 `*_counter_collection.csv` files; probe.json is
+F.csv / W.csv are rocprofv3 `*_counter_collection.csv` files; probe.log is
 what `bench.py --pmc-probe` printed (its last JSON line is used).
+
+stats: a Markdown table of a `--kernel-trace --stats` run's kernel_stats.csv:
+
+    python -m paper_2307_14837_amd.profile_summary stats --csv K.csv --out profiles/<name>.md \\
+        --command "<the rocprofv3 command>"
 """
 from __future__ import annotations
 
@@ -39,14 +46,39 @@ def find(avgs, needle):
     return hits[0]
 
 
+def stats(a):
+    rows = list(csv.DictReader(open(a.csv)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [f"# {a.title}", "", "Command:", "", "```", a.command, "```", "",
+             "| kernel | calls | avg us | min us | max us | share % |", "|---|---:|---:|---:|---:|---:|"]
+    for r in rows[: a.top]:
+        name = r["Name"]
+        short = name.split("(")[0] if "(" in name else name
+        lines.append(f"| `{short[:90]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.1f} |")
+    with open(a.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
-    ap.add_argument("--probe", required=True)
-    ap.add_argument("--out", required=True)
-    ap.add_argument("--command", default="")
+    sub = ap.add_subparsers(dest="mode", required=True)
+    sp = sub.add_parser("stats")
+    sp.add_argument("--csv", required=True)
+    sp.add_argument("--out", required=True)
+    sp.add_argument("--command", default="")
+    sp.add_argument("--title", default="rocprofv3 kernel statistics")
+    sp.add_argument("--top", type=int, default=20)
+    ap_p = sub.add_parser("pmc")
+    ap_p.add_argument("--fetch", required=True)
+    ap_p.add_argument("--write", required=True)
+    ap_p.add_argument("--probe", required=True)
+    ap_p.add_argument("--out", required=True)
+    ap_p.add_argument("--command", default="")
     a = ap.parse_args()
+    if a.mode == "stats":
+        return stats(a)
     probe = [json.loads(l) for l in open(a.probe) if l.startswith('{"pmc_probe"')][-1]
     fetch = per_kernel(a.fetch, "FETCH_SIZE")
     write = per_kernel(a.write, "WRITE_SIZE")
