@@ -14,11 +14,12 @@
 namespace dnnmg {
 
 ResParams make_params(const Mesh &m, const dnnmg_ns *ns);
-void residual_tiles(const Mesh &m, int rt[3]);
-void prolong_residual_batch_launch(const BoxDesc *D, int nbox, int64_t ntiles, const double *xc, const float *vp,
-                                   float *xt, float *r, hipStream_t s);
+void residual_tiles(const Mesh &m, int rt[3], int rf[3]);
+void prolong_residual_batch_launch(const BoxDesc *D, int nbox, int64_t nfull, int64_t npart, const double *xc,
+                                   const float *vp, float *xt, float *r, hipStream_t s);
 void restrict_batch_launch(const BoxDesc *D, int nbox, int64_t nblk, const float *bf, double *bc, hipStream_t s);
-void rhs_batch_launch(const BoxDesc *D, int nbox, int64_t ntiles, const float *v, float *b, hipStream_t s);
+void rhs_batch_launch(const BoxDesc *D, int nbox, int64_t nfull, int64_t npart, const float *v, float *b,
+                      hipStream_t s);
 void scatter_batch_launch(const BoxDesc *D, int nbox, int64_t nblk, const float *Y, const float *vbase, float *xc,
                           hipStream_t s);
 
@@ -32,7 +33,7 @@ struct dnnmg_plan {
     std::vector<BoxDesc> desc;
     BoxDesc *d_desc;   // in the caller's workspace
     int64_t n_fine, n_coarse, n_patches;
-    int64_t blk_fine, blk_coarse, tiles, ptiles;
+    int64_t blk_fine, blk_coarse, tiles_full, tiles_part, ptiles;
     int pt;            // tuned: patches per network tile / 16
     int grid;          // tuned: persistent grid of the network stage (0 = one block per tile)
 };
@@ -41,28 +42,34 @@ static size_t up256(size_t b) { return (b + 255) / 256 * 256; }
 
 static int layout(dnnmg_plan *p, const dnnmg_box *boxes, int nbox) {
     p->desc.resize(nbox);
-    int64_t of = 0, oc = 0, op = 0, bf = 0, bc = 0, bt = 0, bp = 0;
+    int64_t of = 0, oc = 0, op = 0, bf = 0, bc = 0, bt = 0, bpart = 0, bp = 0;
     for (int i = 0; i < nbox; ++i) {
         BoxDesc &d = p->desc[i];
         int rc = make_mesh(&boxes[i], &d.m);
         if (rc) return rc;
         d.rp = make_params(d.m, &p->ns);
-        int rt[3];
-        residual_tiles(d.m, rt);
-        for (int a = 0; a < 3; ++a) d.rtiles[a] = rt[a];
+        int rt[3], rf[3];
+        residual_tiles(d.m, rt, rf);
+        for (int a = 0; a < 3; ++a) {
+            d.rtiles[a] = rt[a];
+            d.rfull[a] = rf[a];
+        }
         d.off_fine = of;
         d.off_coarse = oc;
         d.off_patch = op;
         d.blk_fine = bf;
         d.blk_coarse = bc;
-        d.blk_tile = bt;
+        d.blk_full = bt;
+        d.blk_part = bpart;
         d.blk_ptile = bp;
         of += d.m.n_fine;
         oc += d.m.n_coarse;
         op += d.m.n_patches;
         bf += (d.m.n_fine + 255) / 256;
         bc += (d.m.n_coarse + 255) / 256;
-        bt += (int64_t)rt[0] * rt[1] * rt[2];
+        const int64_t nfull = (int64_t)rf[0] * rf[1] * rf[2];
+        bt += nfull;
+        bpart += (int64_t)rt[0] * rt[1] * rt[2] - nfull;
         bp += (d.m.n_patches + 16 * p->pt - 1) / (16 * p->pt);
     }
     p->n_fine = of;
@@ -70,7 +77,8 @@ static int layout(dnnmg_plan *p, const dnnmg_box *boxes, int nbox) {
     p->n_patches = op;
     p->blk_fine = bf;
     p->blk_coarse = bc;
-    p->tiles = bt;
+    p->tiles_full = bt;
+    p->tiles_part = bpart;
     p->ptiles = bp;
     return DNNMG_OK;
 }
@@ -139,13 +147,13 @@ static int step_impl(const dnnmg_plan *p, const dnnmg_mlp *net, const float *shi
                      const double *xc, const float *vprev, float *xt, float *r, float *Y, float *xcorr, float *b,
                      double *bc, hipStream_t s) {
     const BoxDesc *D = p->d_desc;
-    prolong_residual_batch_launch(D, p->nbox, p->tiles, xc, vprev, xt, r, s);
+    prolong_residual_batch_launch(D, p->nbox, p->tiles_full, p->tiles_part, xc, vprev, xt, r, s);
     BoxDesc none{};
     int rc = fwd_launch(net, p->pt, true, p->ptiles, p->grid, 0, nullptr, 0, D, p->nbox, none, xt, r, shift, inv,
                         Y, nullptr, s);
     if (rc) return rc;
     scatter_batch_launch(D, p->nbox, p->blk_fine, Y, xt, xcorr, s);
-    rhs_batch_launch(D, p->nbox, p->tiles, xcorr, b, s);
+    rhs_batch_launch(D, p->nbox, p->tiles_full, p->tiles_part, xcorr, b, s);
     restrict_batch_launch(D, p->nbox, p->blk_coarse, b, bc, s);
     return hip_check(hipGetLastError(), "dnnmg_batch_step launch");
 }
@@ -176,7 +184,7 @@ extern "C" int dnnmg_plan_autotune(dnnmg_plan *p, const dnnmg_mlp *net, const fl
     if (reps < 1) reps = 1;
     hipStream_t s = (hipStream_t)stream;
     // inputs of the network stage
-    prolong_residual_batch_launch(p->d_desc, p->nbox, p->tiles, xc, vprev, xt, r, s);
+    prolong_residual_batch_launch(p->d_desc, p->nbox, p->tiles_full, p->tiles_part, xc, vprev, xt, r, s);
     int dev = 0, ncu = 256;
     if ((rc = hip_check(hipGetDevice(&dev), "autotune device"))) return rc;
     if ((rc = hip_check(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev), "autotune CU count")))

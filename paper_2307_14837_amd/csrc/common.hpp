@@ -97,8 +97,10 @@ struct BoxDesc {
     Mesh m;
     ResParams rp;
     int64_t off_fine, off_coarse, off_patch;
-    int64_t blk_fine, blk_coarse, blk_tile, blk_ptile;
-    int32_t rtiles[3]; // residual tile grid of the box
+    int64_t blk_fine, blk_coarse, blk_ptile;
+    int64_t blk_full, blk_part; // residual tiles: prefix sums of full / partial tiles
+    int32_t rtiles[3];          // residual tile grid of the box
+    int32_t rfull[3];           // its box of full tiles (no node beyond the mesh)
 };
 
 // Box holding block `blk` of a batched launch: the last b with first[b] <= blk.

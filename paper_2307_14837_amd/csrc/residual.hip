@@ -353,25 +353,40 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
     };
     stage_v(MODE != MODE_RHS ? vp : x, sV);
     if (fmid) stage_v(fmid, sF);
+    for (int s = tid; s < 8 * T::NCELL; s += T::NT) {
+        sCell[s] = 0.0f;
+        if constexpr (MODE == MODE_RES) sCor[s] = 0.0f;
+    }
     __syncthreads();
 
     const int ncx = 2 * m.n[0], ncy = 2 * m.n[1], ncz = 2 * m.n[2]; // fine cells per axis
     const float ih0 = P.ih[0], ih1 = P.ih[1], ih2 = P.ih[2];
 
     // ---- this thread's cell: lower corner at origin - 1 + (ex, ey, ez) ----
-    // (the few threads past the last cell compute on cell NCELL - 1 and
-    // contribute nothing; dead cells read in-range LDS values and are masked
-    // when their integrals are stored)
-    const int e = tid;
-    bool live = e < T::NCELL;
-    const int ec = e < T::NCELL ? e : T::NCELL - 1;
-    const int ex = ec % T::EX, ey = (ec / T::EX) % T::EY, ez = ec / (T::EX * T::EY);
-    const int gx = x0 - 1 + ex, gy = y0 - 1 + ey, gz = z0 - 1 + ez;
-    if (live) {
-        if (!m.per[0]) live &= gx >= 0 && gx < ncx;
-        if (!m.per[1]) live &= gy >= 0 && gy < ncy;
-        if (!m.per[2]) live &= gz >= 0 && gz < ncz;
+    // The cells of the tile inside the domain form a box; thread e takes its
+    // e-th cell, so the waves past the live count skip the cell work (a tile
+    // on a non-periodic upper face owns one node layer and few live cells).
+    // Cell integrals go to the cell's slot ce = ex + EX (ey + EY ez); the slots
+    // of cells outside the domain stay zero.
+    int elo[3], ecnt[3];
+    {
+        const int o3[3] = {x0, y0, z0}, n3[3] = {ncx, ncy, ncz}, E3[3] = {T::EX, T::EY, T::EZ};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            int lo = 0, hi = E3[a] - 1;
+            if (!m.per[a]) {
+                lo = max(0, 1 - o3[a]);              // x0 - 1 + ex >= 0
+                hi = min(E3[a] - 1, n3[a] - o3[a]);  // x0 - 1 + ex < cells
+            }
+            elo[a] = lo;
+            ecnt[a] = max(1, hi - lo + 1);
+        }
     }
+    const int e = tid;
+    const bool live = e < ecnt[0] * ecnt[1] * ecnt[2];
+    const int ec = live ? e : 0;
+    const int ex = elo[0] + ec % ecnt[0], ey = elo[1] + (ec / ecnt[0]) % ecnt[1], ez = elo[2] + ec / (ecnt[0] * ecnt[1]);
+    const int ce = ex + T::EX * (ey + T::EY * ez);
     // offset of the cell inside its patch (the tile origin is even)
     const int ox = (ex + 1) & 1, oy = (ey + 1) & 1, oz = (ez + 1) & 1;
     // node slots of vertex j = a + 2b + 4c as base + offset, so the LDS
@@ -393,10 +408,9 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
 
     // Cell integrals of equation a -> LDS; the owners sum them.
     auto reduce = [&](const float c[8], float wq) -> float {
+        if (live)
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
-            if (live) sCell[j * T::NCELL + e] = c[j] * wq;
-            else if (e < T::NCELL) sCell[j * T::NCELL + e] = 0.0f;
+            for (int j = 0; j < 8; ++j) sCell[j * T::NCELL + ce] = c[j] * wq;
         __syncthreads();
         float s = 0.0f;
         if (owner)
@@ -409,16 +423,20 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
     bool need = false;
     if constexpr (MODE == MODE_RHS) {
         float w[3][8], wv[3][8];
+        if (live) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
+            for (int d = 0; d < 3; ++d) {
 #pragma unroll
-            for (int j = 0; j < 8; ++j) w[d][j] = sV[d * T::VN + vb + voff(j)];
-            eval_val(w[d], wv[d]);
+                for (int j = 0; j < 8; ++j) w[d][j] = sV[d * T::VN + vb + voff(j)];
+                eval_val(w[d], wv[d]);
+            }
         }
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             // (1/k) v_a - 1/2 v . grad v_a (+ (f^{n-1} + f^n)/2) and -nu/2 grad v_a
-            float F[8], va[8], g0[8], g1[8], g2[8], acc[8];
+            float acc[8];
+            if (live) {
+            float F[8], va[8], g0[8], g1[8], g2[8];
             eval_vg(w[a], ih0, ih1, ih2, va, g0, g1, g2);
             if (fmid) {
                 float fv[8];
@@ -438,6 +456,7 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
                 g2[q] *= -P.half_nu;
             }
             integrate<true, true, true>(F, g0, g1, g2, ih0, ih1, ih2, acc);
+            }
             res[a] = reduce(acc, P.wq);
         }
     } else {
@@ -456,61 +475,69 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
                 for (int j = 0; j < 8; ++j) need |= pw[j] != sX[d * T::SN + xb + xoff(j)];
             }
         }
-        // x~ and vp at the Gauss points; divergence of x~
-        float xv[3][8], pv[3][8], div[8];
+        // x~, vp and p~ at the Gauss points; divergence of x~
+        float xv[3][8], pv[3][8], pq[8], div[8];
+        if (live) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
+            for (int d = 0; d < 3; ++d) {
+                float w[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) w[j] = sX[d * T::SN + xb + xoff(j)];
+                eval_val(w, xv[d]);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) w[j] = sV[d * T::VN + vb + voff(j)];
+                eval_val(w, pv[d]);
+            }
             float w[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) w[j] = sX[d * T::SN + xb + xoff(j)];
-            eval_val(w, xv[d]);
-#pragma unroll
-            for (int j = 0; j < 8; ++j) w[j] = sV[d * T::VN + vb + voff(j)];
-            eval_val(w, pv[d]);
+            for (int j = 0; j < 8; ++j) w[j] = sX[3 * T::SN + xb + xoff(j)];
+            eval_val(w, pq);
         }
 #pragma unroll
         for (int q = 0; q < 8; ++q) div[q] = 0.0f;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            float wa[8], va[8], dif[8], sum[8], pj[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                wa[j] = sV[a * T::VN + vb + voff(j)];
-                va[j] = sX[a * T::SN + xb + xoff(j)];
-                pj[j] = sX[3 * T::SN + xb + xoff(j)];
-                // (1/k)(vp_a - v_a) + (f^{n-1} + f^n)/2 at the vertices
-                dif[j] = fmaf(P.inv_dt, wa[j] - va[j], fmid ? sF[a * T::VN + vb + voff(j)] : 0.0f);
-                sum[j] = wa[j] + va[j];
-            }
-            float F[8], Gx[8], Gy[8], Gz[8], tmp[8], pq[8];
-            // -nu/2 grad(vp_a + v_a), + p d_a phi
-            eval_vg(sum, ih0, ih1, ih2, tmp, Gx, Gy, Gz);
-            eval_val(dif, F);
-            eval_val(pj, pq);
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                Gx[q] *= -P.half_nu;
-                Gy[q] *= -P.half_nu;
-                Gz[q] *= -P.half_nu;
-            }
-            float *Ga = a == 0 ? Gx : (a == 1 ? Gy : Gz);
-#pragma unroll
-            for (int q = 0; q < 8; ++q) Ga[q] += pq[q];
-            // -1/2 (vp . grad vp_a) - 1/2 (v . grad v_a)
-            float g0[8], g1[8], g2[8];
-            eval_vg(wa, ih0, ih1, ih2, tmp, g0, g1, g2);
-#pragma unroll
-            for (int q = 0; q < 8; ++q)
-                F[q] -= 0.5f * (pv[0][q] * g0[q] + pv[1][q] * g1[q] + pv[2][q] * g2[q]);
-            eval_vg(va, ih0, ih1, ih2, tmp, g0, g1, g2);
-#pragma unroll
-            for (int q = 0; q < 8; ++q)
-                F[q] -= 0.5f * (xv[0][q] * g0[q] + xv[1][q] * g1[q] + xv[2][q] * g2[q]);
-            const float *ga = a == 0 ? g0 : (a == 1 ? g1 : g2);
-#pragma unroll
-            for (int q = 0; q < 8; ++q) div[q] += ga[q];
             float acc[8];
-            integrate<true, true, true>(F, Gx, Gy, Gz, ih0, ih1, ih2, acc);
+            if (live) {
+                float w[8], tmp[8], g0[8], g1[8], g2[8], G0[8], G1[8], G2[8], F[8];
+                // (1/k)(vp_a - v_a) (+ (f^{n-1} + f^n)/2) at the Gauss points
+                if (fmid) {
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) w[j] = sF[a * T::VN + vb + voff(j)];
+                    eval_val(w, F);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) F[q] = 0.0f;
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) F[q] += P.inv_dt * (pv[a][q] - xv[a][q]);
+                // -1/2 vp . grad vp_a; the gradient also enters -nu/2 grad(vp_a + v_a)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) w[j] = sV[a * T::VN + vb + voff(j)];
+                eval_vg(w, ih0, ih1, ih2, tmp, G0, G1, G2);
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    F[q] -= 0.5f * (pv[0][q] * G0[q] + pv[1][q] * G1[q] + pv[2][q] * G2[q]);
+                // -1/2 v . grad v_a, divergence
+#pragma unroll
+                for (int j = 0; j < 8; ++j) w[j] = sX[a * T::SN + xb + xoff(j)];
+                eval_vg(w, ih0, ih1, ih2, tmp, g0, g1, g2);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    F[q] -= 0.5f * (xv[0][q] * g0[q] + xv[1][q] * g1[q] + xv[2][q] * g2[q]);
+                    G0[q] = -P.half_nu * (G0[q] + g0[q]);
+                    G1[q] = -P.half_nu * (G1[q] + g1[q]);
+                    G2[q] = -P.half_nu * (G2[q] + g2[q]);
+                }
+                const float *ga = a == 0 ? g0 : (a == 1 ? g1 : g2);
+                float *Ga = a == 0 ? G0 : (a == 1 ? G1 : G2);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    div[q] += ga[q];
+                    Ga[q] += pq[q]; // + (p, d_a phi)
+                }
+                integrate<true, true, true>(F, G0, G1, G2, ih0, ih1, ih2, acc);
+            }
             res[a] = reduce(acc, P.wq);
         }
         // continuity: -(div v, xi)
@@ -518,7 +545,7 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
 #pragma unroll
             for (int q = 0; q < 8; ++q) div[q] = -div[q];
             float acc[8];
-            integrate<false, false, false>(div, nullptr, nullptr, nullptr, ih0, ih1, ih2, acc);
+            if (live) integrate<false, false, false>(div, nullptr, nullptr, nullptr, ih0, ih1, ih2, acc);
             res[3] = reduce(acc, P.wq);
         }
     }
@@ -623,13 +650,12 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
                 // own-vertex parts to the nodes, corner parts to the owned
                 // patches (halo cells ex == 0 etc. belong to a neighbour's patch)
                 const bool own_patch = ex >= 1 && ey >= 1 && ez >= 1;
+                if (live)
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    if (e < T::NCELL) {
-                        sCell[j * T::NCELL + e] = acc[j] * P.wq;
-                        sCor[j * T::NCELL + e] = own_patch ? cor[j] * P.wq : 0.0f;
+                    for (int j = 0; j < 8; ++j) {
+                        sCell[j * T::NCELL + ce] = acc[j] * P.wq;
+                        sCor[j * T::NCELL + ce] = own_patch ? cor[j] * P.wq : 0.0f;
                     }
-                }
                 __syncthreads();
                 if (owner) {
                     float s = 0.0f;
@@ -679,6 +705,44 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
     }
 }
 
+// Tile order of a launch: the tiles that hold a full block of owned nodes
+// come first (each XCD takes a contiguous range of them), then the partial
+// tiles on the upper faces of non-periodic axes, which hold one node layer.
+// With one full tile per compute unit in the first wave, the cheap partial
+// tiles fill in after instead of doubling the critical path.  t in [0, F):
+// full tile; t in [F, G): partial tiles, as the slabs bz >= Fz, then
+// by >= Fy (bz < Fz), then bx >= Fx (by < Fy, bz < Fz).
+__device__ __forceinline__ void tile_of(int64_t t, const int G[3], const int F[3], int c[3]) {
+    const int64_t nf = (int64_t)F[0] * F[1] * F[2];
+    if (t < nf) {
+        c[0] = (int)(t % F[0]);
+        c[1] = (int)((t / F[0]) % F[1]);
+        c[2] = (int)(t / ((int64_t)F[0] * F[1]));
+        return;
+    }
+    int64_t p = t - nf;
+    const int64_t r1 = (int64_t)(G[2] - F[2]) * G[0] * G[1];
+    if (p < r1) {
+        c[0] = (int)(p % G[0]);
+        c[1] = (int)((p / G[0]) % G[1]);
+        c[2] = F[2] + (int)(p / ((int64_t)G[0] * G[1]));
+        return;
+    }
+    p -= r1;
+    const int64_t r2 = (int64_t)(G[1] - F[1]) * G[0] * F[2];
+    if (p < r2) {
+        c[0] = (int)(p % G[0]);
+        c[1] = F[1] + (int)((p / G[0]) % (G[1] - F[1]));
+        c[2] = (int)(p / ((int64_t)G[0] * (G[1] - F[1])));
+        return;
+    }
+    p -= r2;
+    const int gx = G[0] - F[0];
+    c[0] = F[0] + (int)(p % gx);
+    c[1] = (int)((p / gx) % F[1]);
+    c[2] = (int)(p / ((int64_t)gx * F[1]));
+}
+
 template <int MODE>
 __global__ void __launch_bounds__(ResTile<MODE>::NT)
     k_residual(Mesh m, ResParams P, const float *__restrict__ x, const float *__restrict__ vp,
@@ -687,12 +751,33 @@ __global__ void __launch_bounds__(ResTile<MODE>::NT)
                float *__restrict__ xt_out) {
     if (flag && *flag == 0) return; // predicated launch (fallback path not taken)
     using T = ResTile<MODE>;
-    const int rt0 = (m.nf[0] + T::TX - 1) / T::TX, rt1 = (m.nf[1] + T::TY - 1) / T::TY;
-    const int rt2 = (m.nf[2] + T::TZ - 1) / T::TZ;
-    const int tl = (int)xcd_item(blockIdx.x, gridDim.x);
-    if (tl >= rt0 * rt1 * rt2) return;
-    residual_tile<MODE>(m, P, tl % rt0, (tl / rt0) % rt1, tl / (rt0 * rt1), x, vp, fmid, out, aux,
-                        MODE == MODE_RES ? tflag + tl : nullptr, xc, xt_out);
+    const int G[3] = {(m.nf[0] + T::TX - 1) / T::TX, (m.nf[1] + T::TY - 1) / T::TY, (m.nf[2] + T::TZ - 1) / T::TZ};
+    const int F[3] = {m.nf[0] / T::TX, m.nf[1] / T::TY, m.nf[2] / T::TZ};
+    const int64_t nfull = (int64_t)F[0] * F[1] * F[2];
+    const int64_t xf = NXCD * ((nfull + NXCD - 1) / NXCD);
+    int64_t t;
+    if (blockIdx.x < xf) {
+        t = xcd_item(blockIdx.x, xf);
+        if (t >= nfull) return;
+    } else {
+        t = nfull + (blockIdx.x - xf);
+        if (t >= (int64_t)G[0] * G[1] * G[2]) return;
+    }
+    int c[3];
+    tile_of(t, G, F, c);
+    const int tl = c[0] + G[0] * (c[1] + G[1] * c[2]);
+    residual_tile<MODE>(m, P, c[0], c[1], c[2], x, vp, fmid, out, aux, MODE == MODE_RES ? tflag + tl : nullptr, xc,
+                        xt_out);
+}
+
+// Launch size of a tile grid in the order of tile_of.
+template <int MODE>
+static unsigned tile_blocks(const Mesh &m) {
+    using T = ResTile<MODE>;
+    const int64_t g = (int64_t)((m.nf[0] + T::TX - 1) / T::TX) * ((m.nf[1] + T::TY - 1) / T::TY) *
+                      ((m.nf[2] + T::TZ - 1) / T::TZ);
+    const int64_t f = (int64_t)(m.nf[0] / T::TX) * (m.nf[1] / T::TY) * (m.nf[2] / T::TZ);
+    return (unsigned)(xcd_blocks(f) + (g - f));
 }
 
 // Batched: one flat grid over the tiles of all boxes.  x is a 4-component
@@ -700,20 +785,36 @@ __global__ void __launch_bounds__(ResTile<MODE>::NT)
 // part), vp has 3 components, out 4; aux holds 32 floats per patch.
 template <int MODE>
 __global__ void __launch_bounds__(ResTile<MODE>::NT)
-    k_residual_batch(const BoxDesc *__restrict__ D, int nbox, int64_t ntiles, const float *__restrict__ x,
-                     const float *__restrict__ vp, float *__restrict__ out, float *__restrict__ aux,
-                     int *__restrict__ tflag, const double *__restrict__ xc, float *__restrict__ xt_out) {
-    const int64_t blk = xcd_item(blockIdx.x, gridDim.x);
-    if (blk >= ntiles) return;
-    const int b = find_box(nbox, blk, [&](int i) { return D[i].blk_tile; });
+    k_residual_batch(const BoxDesc *__restrict__ D, int nbox, int64_t nfull, int64_t npart,
+                     const float *__restrict__ x, const float *__restrict__ vp, float *__restrict__ out,
+                     float *__restrict__ aux, int *__restrict__ tflag, const double *__restrict__ xc,
+                     float *__restrict__ xt_out) {
+    // full tiles of all boxes first (XCD-contiguous), then the partial ones
+    const int64_t xf = NXCD * ((nfull + NXCD - 1) / NXCD);
+    int b;
+    int64_t t;
+    if (blockIdx.x < xf) {
+        const int64_t f = xcd_item(blockIdx.x, xf);
+        if (f >= nfull) return;
+        b = find_box(nbox, f, [&](int i) { return D[i].blk_full; });
+        t = f - D[b].blk_full;
+    } else {
+        const int64_t q = blockIdx.x - xf;
+        if (q >= npart) return;
+        b = find_box(nbox, q, [&](int i) { return D[i].blk_part; });
+        t = (int64_t)D[b].rfull[0] * D[b].rfull[1] * D[b].rfull[2] + (q - D[b].blk_part);
+    }
     const BoxDesc &d = D[b];
     const Mesh m = d.m;
     const ResParams P = d.rp;
-    int t = (int)(blk - d.blk_tile);
-    int bx = t % d.rtiles[0], by = (t / d.rtiles[0]) % d.rtiles[1], bz = t / (d.rtiles[0] * d.rtiles[1]);
+    int c[3];
+    tile_of(t, d.rtiles, d.rfull, c);
+    const int tl = c[0] + d.rtiles[0] * (c[1] + d.rtiles[1] * c[2]);
+    (void)tl;
+    const int bx = c[0], by = c[1], bz = c[2];
     residual_tile<MODE>(m, P, bx, by, bz, MODE != MODE_PRES ? x + 4 * d.off_fine : nullptr,
                         MODE != MODE_RHS ? vp + 3 * d.off_fine : nullptr, nullptr, out + 4 * d.off_fine,
-                        MODE == MODE_RES ? aux + 32 * d.off_patch : nullptr, MODE == MODE_RES ? tflag + blk : nullptr,
+                        nullptr, nullptr,
                         MODE == MODE_PRES ? xc + 4 * d.off_coarse : nullptr,
                         MODE == MODE_PRES ? xt_out + 4 * d.off_fine : nullptr);
 }
@@ -821,30 +922,34 @@ int residual_launch(const Mesh &m, const dnnmg_ns *ns, const float *x, const flo
     ResParams P = make_params(m, ns);
     dim3 g = res_grid<MODE_RES>(m);
     int *tflag = (int *)((char *)aux + up256(sizeof(float) * 32 * m.n_patches));
-    k_residual<MODE_RES><<<xcd_blocks((int64_t)g.x * g.y * g.z), ResTile<MODE_RES>::NT, 0, s>>>(
-        m, P, x, vprev, fmid, r, aux, tflag, flag, nullptr, nullptr);
+    k_residual<MODE_RES><<<tile_blocks<MODE_RES>(m), ResTile<MODE_RES>::NT, 0, s>>>(m, P, x, vprev, fmid, r, aux,
+                                                                                 tflag, flag, nullptr, nullptr);
     k_lps_corners<<<blocks_for(m.n_coarse, 256), 256, 0, s>>>(m, aux, tflag, g.x, g.y, g.z, r, flag);
     return hip_check(hipGetLastError(), "dnnmg_residual launch");
 }
 
-void residual_tiles(const Mesh &m, int rt[3]) {
+// Tile grid of a box (rt) and its box of full tiles (rf).
+void residual_tiles(const Mesh &m, int rt[3], int rf[3]) {
+    using T = ResTile<MODE_RES>;
     dim3 g = res_grid<MODE_RES>(m);
     rt[0] = g.x;
     rt[1] = g.y;
     rt[2] = g.z;
+    rf[0] = m.nf[0] / T::TX;
+    rf[1] = m.nf[1] / T::TY;
+    rf[2] = m.nf[2] / T::TZ;
 }
 
-
-void rhs_batch_launch(const BoxDesc *D, int nbox, int64_t ntiles, const float *v, float *b, hipStream_t s) {
-    k_residual_batch<MODE_RHS><<<xcd_blocks(ntiles), ResTile<MODE_RHS>::NT, 0, s>>>(D, nbox, ntiles, v, nullptr, b,
-                                                                                   nullptr, nullptr, nullptr,
-                                                                                   nullptr);
+void rhs_batch_launch(const BoxDesc *D, int nbox, int64_t nfull, int64_t npart, const float *v, float *b,
+                      hipStream_t s) {
+    k_residual_batch<MODE_RHS><<<(unsigned)(xcd_blocks(nfull) + npart), ResTile<MODE_RHS>::NT, 0, s>>>(
+        D, nbox, nfull, npart, v, nullptr, b, nullptr, nullptr, nullptr, nullptr);
 }
 
-void prolong_residual_batch_launch(const BoxDesc *D, int nbox, int64_t ntiles, const double *xc, const float *vp,
-                                   float *xt, float *r, hipStream_t s) {
-    k_residual_batch<MODE_PRES><<<xcd_blocks(ntiles), ResTile<MODE_PRES>::NT, 0, s>>>(D, nbox, ntiles, nullptr, vp, r,
-                                                                                    nullptr, nullptr, xc, xt);
+void prolong_residual_batch_launch(const BoxDesc *D, int nbox, int64_t nfull, int64_t npart, const double *xc,
+                                   const float *vp, float *xt, float *r, hipStream_t s) {
+    k_residual_batch<MODE_PRES><<<(unsigned)(xcd_blocks(nfull) + npart), ResTile<MODE_PRES>::NT, 0, s>>>(
+        D, nbox, nfull, npart, nullptr, vp, r, nullptr, nullptr, xc, xt);
 }
 
 } // namespace dnnmg
@@ -879,8 +984,7 @@ extern "C" int dnnmg_rhs(const dnnmg_box *box, const dnnmg_ns *ns, const float *
     if ((rc = check_ns(ns))) return rc;
     if (!v || !b) return fail(DNNMG_ERR_ARG, "dnnmg_rhs: NULL pointer");
     ResParams P = make_params(m, ns);
-    dim3 g = res_grid<MODE_RHS>(m);
-    k_residual<MODE_RHS><<<xcd_blocks((int64_t)g.x * g.y * g.z), ResTile<MODE_RHS>::NT, 0, (hipStream_t)stream>>>(
+    k_residual<MODE_RHS><<<tile_blocks<MODE_RHS>(m), ResTile<MODE_RHS>::NT, 0, (hipStream_t)stream>>>(
         m, P, v, nullptr, fmid, b, nullptr, nullptr, nullptr, nullptr, nullptr);
     return hip_check(hipGetLastError(), "dnnmg_rhs launch");
 }
@@ -893,8 +997,7 @@ extern "C" int dnnmg_prolong_residual(const dnnmg_box *box, const dnnmg_ns *ns, 
     if ((rc = check_ns(ns))) return rc;
     if (!xc || !vprev || !xt || !r) return fail(DNNMG_ERR_ARG, "dnnmg_prolong_residual: NULL pointer");
     ResParams P = make_params(m, ns);
-    dim3 g = res_grid<MODE_PRES>(m);
-    k_residual<MODE_PRES><<<xcd_blocks((int64_t)g.x * g.y * g.z), ResTile<MODE_PRES>::NT, 0, (hipStream_t)stream>>>(
+    k_residual<MODE_PRES><<<tile_blocks<MODE_PRES>(m), ResTile<MODE_PRES>::NT, 0, (hipStream_t)stream>>>(
         m, P, nullptr, vprev, fmid, r, nullptr, nullptr, nullptr, xc, xt);
     return hip_check(hipGetLastError(), "dnnmg_prolong_residual launch");
 }

@@ -29,11 +29,10 @@ def residual_flops_per_cell(lps: bool = False) -> int:
     (no recomputation counted)."""
     values = 7 * EVAL_VAL                          # x~, vp, p~ at the Gauss points
     test = 4 * PI_VERTICES                         # patch interpolant of (x~, p~)
-    per_comp = (32                                 # vp - x~, (1/k)(.) + f, vp + x~
-                + EVAL_VG + EVAL_VAL               # grad(vp + x~)_a, (vp - x~)_a / k
-                + 24 + 8                           # -nu/2, pressure term
-                + EVAL_VG + 56                     # -1/2 vp . grad vp_a
-                + EVAL_VG + 56 + 8                 # -1/2 x~ . grad x~_a, divergence
+    per_comp = (16                                 # (1/k)(vp_a - v_a)
+                + EVAL_VG + 56                     # grad vp_a; -1/2 vp . grad vp_a
+                + EVAL_VG + 56 + 8                 # grad v_a; -1/2 v . grad v_a; divergence
+                + 48 + 8                           # -nu/2 grad(vp_a + v_a), + p d_a phi
                 + INTEGRATE)                       # vertex integrals
     cont = 8 + INTEGRATE_VAL                       # -(div x~, xi)
     sums = 32 + 32                                 # quadrature weight, LDS sums
