@@ -66,7 +66,7 @@ static int layout(dnnmg_plan *p, const dnnmg_box *boxes, int nbox) {
         oc += d.m.n_coarse;
         op += d.m.n_patches;
         bf += (d.m.n_fine + 255) / 256;
-        bc += (d.m.n_coarse + 255) / 256;
+        bc += (4 * d.m.n_coarse + 255) / 256; // restriction: one thread per component and node
         const int64_t nfull = (int64_t)rf[0] * rf[1] * rf[2];
         bt += nfull;
         bpart += (int64_t)rt[0] * rt[1] * rt[2] - nfull;

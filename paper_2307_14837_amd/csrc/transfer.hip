@@ -124,7 +124,11 @@ __global__ void __launch_bounds__(256) k_prolong(Mesh m, int ncomp, const double
 // issued together; FP64 accumulation.
 __device__ __forceinline__ void restrict_node(const Mesh &m, int64_t t, int ncomp, const float *__restrict__ bf,
                                               double *__restrict__ bc) {
-    if (t >= m.n_coarse) return;
+    // one thread per (component, coarse node): consecutive threads take
+    // consecutive nodes of one component
+    if (t >= (int64_t)ncomp * m.n_coarse) return;
+    const int comp = (int)(t / m.n_coarse);
+    t -= (int64_t)comp * m.n_coarse;
     uint32_t JK = fdiv((uint32_t)t, m.cx), I = (uint32_t)t - JK * m.nc[0];
     uint32_t K = fdiv(JK, m.cy), J = JK - K * m.nc[1];
     const int C[3] = {(int)I, (int)J, (int)K};
@@ -141,28 +145,24 @@ __device__ __forceinline__ void restrict_node(const Mesh &m, int64_t t, int ncom
             f[a][d] = fi;
             w[a][d] = ok ? (d == 1 ? 1.0 : 0.5) : 0.0;
         }
-    for (int comp = 0; comp < ncomp; ++comp) {
-        const float *b = bf + (int64_t)comp * m.n_fine;
-        float v[27];
+    const float *b = bf + (int64_t)comp * m.n_fine;
+    float v[27];
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
+    for (int c = 0; c < 3; ++c)
 #pragma unroll
-            for (int bb = 0; bb < 3; ++bb)
+        for (int bb = 0; bb < 3; ++bb)
 #pragma unroll
-                for (int a = 0; a < 3; ++a)
-                    v[a + 3 * bb + 9 * c] =
-                        b[f[0][a] + (int64_t)m.nf[0] * (f[1][bb] + (int64_t)m.nf[1] * f[2][c])];
-        double acc = 0.0;
+            for (int a = 0; a < 3; ++a)
+                v[a + 3 * bb + 9 * c] = b[f[0][a] + (int64_t)m.nf[0] * (f[1][bb] + (int64_t)m.nf[1] * f[2][c])];
+    double acc = 0.0;
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
+    for (int c = 0; c < 3; ++c)
 #pragma unroll
-            for (int bb = 0; bb < 3; ++bb) {
-                double row = w[0][0] * v[9 * c + 3 * bb] + w[0][1] * v[1 + 9 * c + 3 * bb] +
-                             w[0][2] * v[2 + 9 * c + 3 * bb];
-                acc += w[1][bb] * w[2][c] * row;
-            }
-        bc[(int64_t)comp * m.n_coarse + t] = acc;
-    }
+        for (int bb = 0; bb < 3; ++bb) {
+            double row = w[0][0] * v[9 * c + 3 * bb] + w[0][1] * v[1 + 9 * c + 3 * bb] + w[0][2] * v[2 + 9 * c + 3 * bb];
+            acc += w[1][bb] * w[2][c] * row;
+        }
+    bc[(int64_t)comp * m.n_coarse + t] = acc;
 }
 
 __global__ void __launch_bounds__(256) k_restrict(Mesh m, int ncomp, const float *__restrict__ bf,
@@ -352,7 +352,7 @@ extern "C" int dnnmg_restrict(const dnnmg_box *box, int ncomp, const float *bf, 
     if (rc) return rc;
     if (ncomp < 1 || ncomp > 4) return fail(DNNMG_ERR_ARG, "dnnmg_restrict: ncomp %d not in 1..4", ncomp);
     if (!bf || !bc) return fail(DNNMG_ERR_ARG, "dnnmg_restrict: NULL pointer");
-    k_restrict<<<blocks_for(m.n_coarse, 256), 256, 0, STREAM>>>(m, ncomp, bf, bc);
+    k_restrict<<<blocks_for((int64_t)ncomp * m.n_coarse, 256), 256, 0, STREAM>>>(m, ncomp, bf, bc);
     return hip_check(hipGetLastError(), "dnnmg_restrict launch");
 }
 
