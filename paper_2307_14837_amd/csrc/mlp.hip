@@ -154,8 +154,11 @@ __device__ __forceinline__ void layer(const typename Frag<K>::T *__restrict__ Wl
     for (int i = 0; i < OTW; ++i)
 #pragma unroll
         for (int t = 0; t < PT; ++t) acc[i][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // two K chunks per step: the weight loads of a step are issued together
-#pragma unroll 2
+    // UNROLL K chunks per step: the weight loads of a step are issued
+    // together (8-wave tiles have few output tiles per wave, so a whole
+    // layer's weight fragments fit in registers and are requested at once)
+    constexpr int UNROLL = (NW == 8 && H <= 256) ? NCH : 2;
+#pragma unroll UNROLL
     for (int kc = 0; kc < NCH; ++kc) {
         FA b[PT];
 #pragma unroll
