@@ -259,6 +259,50 @@ def run_training(steps):
             "ms_per_step": ms, "patches_per_s": n / (ms * 1e-3), "approx_tflops": fl / (ms * 1e-3) / 1e12}
 
 
+def kernels_at_scale():
+    """The hot-path kernels on the large channel (coarse 128x32x32: 131,072
+    patches, 1,085,825 fine nodes), each timed alone (50 graph-captured
+    launches): HBM-bound stencils as achieved GB/s of their algorithmic bytes,
+    VALU kernels as TFLOP/s, network forwards as TFLOP/s."""
+    import torch
+
+    import dnnmg_synth as syn
+    from paper_2307_14837_amd import _lib as L
+    from paper_2307_14837_amd import flops
+
+    w = syn.cfg5()
+    st, inp, params = build_step(w, "bf16")
+    st.step()
+    torch.cuda.synchronize()
+    nf, npch = st.nf, st.np
+    ncell = 8 * npch
+    reps = 50
+    out = {"workload": w.name, "fine_nodes": nf, "patches": npch}
+    B = flops.BYTES_PER_FINE_NODE
+    t = time_kernel(lambda: L.dnnmg_prolong(st.box, st.xc, st.xt), reps)
+    out["prolong"] = {"ms": t, "GB/s": B["prolong"] * nf / (t * 1e-3) / 1e9}
+    t = time_kernel(lambda: L.dnnmg_scatter_avg(st.box, st.Y, st.xcorr, vbase=st.xt), reps)
+    out["scatter"] = {"ms": t, "GB/s": B["scatter"] * nf / (t * 1e-3) / 1e9}
+    t = time_kernel(lambda: L.dnnmg_restrict(st.box, st.b, st.bc), reps)
+    out["restrict"] = {"ms": t, "GB/s": B["restrict"] * nf / (t * 1e-3) / 1e9}
+    gb = flops.gather_bytes_per_patch(2) * npch
+    t = time_kernel(lambda: L.dnnmg_patch_gather(st.box, st.xt, st.r, st.X, st.xdtype, 192, st.shift, st.inv_scale),
+                    reps)
+    out["gather_bf16"] = {"ms": t, "GB/s": gb / (t * 1e-3) / 1e9}
+    t = time_kernel(lambda: L.dnnmg_prolong_residual(st.box, st.ns, st.xc, st.vprev, st.xt, st.r), reps)
+    out["prolong_residual"] = {"ms": t, "TFLOP/s": flops.prolong_residual_flops_per_cell() * ncell / (t * 1e-3) / 1e12}
+    t = time_kernel(lambda: L.dnnmg_rhs(st.box, st.ns, st.xcorr, st.b), reps)
+    out["rhs"] = {"ms": t, "TFLOP/s": flops.rhs_flops_per_cell() * ncell / (t * 1e-3) / 1e12}
+    fl = flops.mlp_flops_per_patch(w.hidden) * npch
+    for dtype in ("bf16", "fp8"):
+        s2, _, _ = build_step(w, dtype)
+        L.dnnmg_patch_gather(s2.box, s2.xt, s2.r, s2.X, s2.xdtype, 192, s2.shift, s2.inv_scale)
+        for tp in (32, 64):
+            t = time_kernel(lambda: L.dnnmg_patch_forward_tiles(s2.net, npch, s2.X, 192, s2.Y, tp), reps)
+            out[f"forward_{dtype}_{tp}"] = {"ms": t, "TFLOP/s": fl / (t * 1e-3) / 1e12}
+    return out
+
+
 def accuracy(w, dtype):
     """rel-L2 of the corrected velocity correction d and of b^L against the
     FP64 oracle on the same inputs (test infrastructure)."""
@@ -376,6 +420,8 @@ def main():
             run_per_box_plain("fp32", max(args.steps // 4, 10), max(args.warmup // 4, 3)),
             run_training(20),
         ]
+        print("[bench] kernels on the large channel", file=sys.stderr, flush=True)
+        out["kernels_at_scale"] = kernels_at_scale()
         print("[bench] accuracy vs oracle", file=sys.stderr, flush=True)
         out["accuracy_rel_l2"] = {"bf16": accuracy(w, "bf16"), "fp32": accuracy(w, "fp32")}
     if not args.no_cpu:

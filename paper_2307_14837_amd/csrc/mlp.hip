@@ -130,10 +130,18 @@ __device__ __forceinline__ void put_act(unsigned char *out, int t, int ot, int l
         uint2 w = make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
         *(uint2 *)(out + ((t * NCHN + (ot >> 1)) * 64 + lane) * 16 + 8 * (ot & 1)) = w;
     } else {
-        uint32_t w = 0;
+        // hardware E4M3 conversion (round to nearest even; the same bits as
+        // f32_to_e4m3 for finite inputs within +-448); inputs are clamped to
+        // +-448 first, as the software encoder saturates, and NaN passes
+        float q[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) w |= (uint32_t)f32_to_e4m3(v[e] * qinv) << (8 * e);
-        *(uint32_t *)(out + ((t * NCHN + (ot >> 3)) * 64 + lane) * 32 + 4 * (ot & 7)) = w;
+        for (int e = 0; e < 4; ++e) {
+            const float x = v[e] * qinv;
+            q[e] = x != x ? x : fminf(fmaxf(x, -448.0f), 448.0f);
+        }
+        int w = __builtin_amdgcn_cvt_pk_fp8_f32(q[0], q[1], 0, false);
+        w = __builtin_amdgcn_cvt_pk_fp8_f32(q[2], q[3], w, true);
+        *(int *)(out + ((t * NCHN + (ot >> 3)) * 64 + lane) * 32 + 4 * (ot & 7)) = w;
     }
 }
 
