@@ -279,16 +279,23 @@ def kernels_at_scale():
     reps = 50
     out = {"workload": w.name, "fine_nodes": nf, "patches": npch}
     B = flops.BYTES_PER_FINE_NODE
-    t = time_kernel(lambda: L.dnnmg_prolong(st.box, st.xc, st.xt), reps)
-    out["prolong"] = {"ms": t, "GB/s": B["prolong"] * nf / (t * 1e-3) / 1e9}
-    t = time_kernel(lambda: L.dnnmg_scatter_avg(st.box, st.Y, st.xcorr, vbase=st.xt), reps)
-    out["scatter"] = {"ms": t, "GB/s": B["scatter"] * nf / (t * 1e-3) / 1e9}
-    t = time_kernel(lambda: L.dnnmg_restrict(st.box, st.b, st.bc), reps)
-    out["restrict"] = {"ms": t, "GB/s": B["restrict"] * nf / (t * 1e-3) / 1e9}
-    gb = flops.gather_bytes_per_patch(2) * npch
-    t = time_kernel(lambda: L.dnnmg_patch_gather(st.box, st.xt, st.r, st.X, st.xdtype, 192, st.shift, st.inv_scale),
-                    reps)
-    out["gather_bf16"] = {"ms": t, "GB/s": gb / (t * 1e-3) / 1e9}
+
+    def hbm(name, fn, nbytes):
+        # the kernel's algorithmic bytes per second, beside a plain device
+        # copy moving the same number of bytes (the practical ceiling at
+        # this size: launch and ramp included)
+        t = time_kernel(fn, reps)
+        a = torch.empty(int(nbytes) // 8, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        tc = time_kernel(lambda: b.copy_(a), reps)
+        out[name] = {"ms": t, "GB/s": nbytes / (t * 1e-3) / 1e9, "copy_same_bytes_GB/s": 8 * a.numel() / (tc * 1e-3) / 1e9}
+
+    hbm("prolong", lambda: L.dnnmg_prolong(st.box, st.xc, st.xt), B["prolong"] * nf)
+    for form, tag in ((L.SCATTER_NODES, "scatter_nodes"), (L.SCATTER_TILED, "scatter_tiled")):
+        hbm(tag, lambda: L.dnnmg_scatter_avg_form(st.box, st.Y, st.xcorr, form, vbase=st.xt), B["scatter"] * nf)
+    hbm("restrict", lambda: L.dnnmg_restrict(st.box, st.b, st.bc), B["restrict"] * nf)
+    hbm("gather_bf16", lambda: L.dnnmg_patch_gather(st.box, st.xt, st.r, st.X, st.xdtype, 192, st.shift,
+                                                    st.inv_scale), flops.gather_bytes_per_patch(2) * npch)
     t = time_kernel(lambda: L.dnnmg_prolong_residual(st.box, st.ns, st.xc, st.vprev, st.xt, st.r), reps)
     out["prolong_residual"] = {"ms": t, "TFLOP/s": flops.prolong_residual_flops_per_cell() * ncell / (t * 1e-3) / 1e12}
     t = time_kernel(lambda: L.dnnmg_rhs(st.box, st.ns, st.xcorr, st.b), reps)

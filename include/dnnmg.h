@@ -228,6 +228,22 @@ int dnnmg_adamw_step(int64_t n, float *theta, float *m, float *v, const float *g
 int dnnmg_scatter_avg(const dnnmg_box *box, const float *Y, const float *vbase, float *d,
                       void *stream);
 
+/* dnnmg_scatter_avg with the kernel form chosen by the caller (the results
+ * are bit for bit the same):
+ *   DNNMG_SCATTER_NODES  one thread per fine node reading the patch rows
+ *                        directly (fastest while the mesh gives each compute
+ *                        unit little work);
+ *   DNNMG_SCATTER_TILED  workgroups over 16 x 8 x 2 node tiles that first
+ *                        copy the patch rows they need into LDS with
+ *                        contiguous reads (fastest on large meshes);
+ *   DNNMG_SCATTER_AUTO   the choice dnnmg_scatter_avg makes: tiled once the
+ *                        fine mesh has at least 4 x (compute units) x 256
+ *                        nodes.
+ * Any other form is DNNMG_ERR_ARG. */
+enum { DNNMG_SCATTER_AUTO = 0, DNNMG_SCATTER_NODES = 1, DNNMG_SCATTER_TILED = 2 };
+int dnnmg_scatter_avg_form(const dnnmg_box *box, const float *Y, const float *vbase, float *d, int form,
+                           void *stream);
+
 /* Squared Euclidean norm in FP64 of a (or of a - b if b != NULL) over n
  * FP32 elements, written to *out (device).  Used for the residual indicator
  * eta = ||r(v~ + d)|| / ||r(v~)||.  Fixed-order two-level reduction

@@ -95,6 +95,7 @@ _sig("dnnmg_patch_forward", [_P(MLP), c_i64, c_vp, c_i64, c_vp, c_vp, c_vp])
 _sig("dnnmg_patch_forward_tiles", [_P(MLP), c_i64, c_vp, c_i64, c_vp, c_vp, ctypes.c_int, ctypes.c_int, c_vp])
 _sig("dnnmg_patch_saved_bytes", [_P(MLP), c_i64], c_sz)
 _sig("dnnmg_scatter_avg", [_P(Box), c_vp, c_vp, c_vp, c_vp])
+_sig("dnnmg_scatter_avg_form", [_P(Box), c_vp, c_vp, c_vp, ctypes.c_int, c_vp])
 _sig("dnnmg_norm2_workspace", [], c_sz)
 _sig("dnnmg_norm2_f64", [c_i64, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp])
 _sig("dnnmg_mse_grad", [c_i64, c_vp, c_vp, c_vp, c_vp])
@@ -123,7 +124,7 @@ EXPORTS = [
     "dnnmg_residual_workspace", "dnnmg_residual", "dnnmg_rhs", "dnnmg_restrict",
     "dnnmg_patch_gather", "dnnmg_mlp_packed_bytes", "dnnmg_mlp_pack", "dnnmg_patch_forward",
     "dnnmg_patch_forward_tiles", "dnnmg_prolong_residual",
-    "dnnmg_patch_saved_bytes", "dnnmg_scatter_avg", "dnnmg_norm2_workspace", "dnnmg_norm2_f64",
+    "dnnmg_patch_saved_bytes", "dnnmg_scatter_avg", "dnnmg_scatter_avg_form", "dnnmg_norm2_workspace", "dnnmg_norm2_f64",
     "dnnmg_mse_grad", "dnnmg_patch_backward_workspace", "dnnmg_patch_backward", "dnnmg_adamw_step",
     "dnnmg_vanka_workspace", "dnnmg_vanka_sweeps", "dnnmg_fallback_workspace", "dnnmg_fallback",
     "dnnmg_patch_gather_forward", "dnnmg_plan_workspace", "dnnmg_plan_create", "dnnmg_plan_destroy",
@@ -291,6 +292,17 @@ def dnnmg_scatter_avg(box, Y, d, vbase=None, stream=None):
     _check(_lib.dnnmg_scatter_avg(ctypes.byref(b), _ptr(Y, torch.float32, npch * N_OUT, "Y"),
                                   _ptr(vbase, torch.float32, 4 * nf, "vbase"),
                                   _ptr(d, torch.float32, nd * nf, "d"), _stream(stream)))
+
+SCATTER_AUTO, SCATTER_NODES, SCATTER_TILED = 0, 1, 2
+
+
+def dnnmg_scatter_avg_form(box, Y, d, form, vbase=None, stream=None):
+    b = Box.of(box)
+    nf, _, npch = box_sizes(b)
+    nd = 3 if vbase is None else 4
+    _check(_lib.dnnmg_scatter_avg_form(ctypes.byref(b), _ptr(Y, torch.float32, npch * N_OUT, "Y"),
+                                       _ptr(vbase, torch.float32, 4 * nf, "vbase"),
+                                       _ptr(d, torch.float32, nd * nf, "d"), int(form), _stream(stream)))
 
 
 def norm2_workspace_bytes() -> int:

@@ -8,6 +8,7 @@
 #include "common.hpp"
 #include "extension.hpp"
 #include "lowp.hpp"
+#include "mlp.hpp"
 
 namespace dnnmg {
 
@@ -273,6 +274,186 @@ __global__ void __launch_bounds__(256) k_scatter_batch(const BoxDesc *__restrict
                  vbase + 4 * dd.off_fine, xc + 4 * dd.off_fine);
 }
 
+// Tiled form of the same sums.  Patch outputs are stored patch by patch
+// (81 floats each), so node-order reads of them touch one cache line per
+// lane; a workgroup instead copies the patch rows its nodes need into LDS
+// with contiguous reads (rows of consecutive x patches are adjacent in
+// memory) and sums from there.  Tile = ST_X x ST_Y x ST_Z owned fine nodes;
+// on a non-periodic axis the last tile also owns the final node 2n, so no
+// tile is a one-node sliver.  Patch slot s along an axis holds patch
+// b + s, b = first owned node / 2 - 1 (wrapped on a periodic axis).
+constexpr int ST_X = 16, ST_Y = 8;
+constexpr int SS_X = ST_X / 2 + 1, SS_Y = ST_Y / 2 + 1;
+constexpr int SS_RUN = 81 * SS_X;                       // floats per run of x slots
+
+// tiles along an axis with nf nodes: ceil(nf / T), less one where that
+// would leave a single node to the last tile
+__host__ __device__ inline int stiles_axis(int nf, int T) {
+    int t = (nf + T - 1) / T;
+    if (t > 1 && nf % T == 1) --t;
+    return t;
+}
+
+// Holders of the node at local index l (global i) along one axis as
+// (slot, local node, weight) in the ascending patch order of holders(); an
+// absent second holder repeats the first with weight 0.
+struct SHold {
+    int s[2], loc[2];
+    float w[2];
+    int cnt;
+};
+
+__device__ __forceinline__ SHold stile_holders(int l, int i, int n, int per) {
+    SHold h;
+    const int lo_s = l >> 1, hi_s = lo_s + 1;
+    if (i & 1) {
+        h.s[0] = h.s[1] = hi_s;
+        h.loc[0] = h.loc[1] = 1;
+        h.w[0] = 1.f;
+        h.w[1] = 0.f;
+        h.cnt = 1;
+        return h;
+    }
+    // periodic: the wrapped lower patch n - 1 comes last at i = 0
+    const bool has_lo = per || i > 0, has_hi = per || i < 2 * n;
+    const bool lo_first = has_lo && !(per && i == 0);
+    h.s[0] = lo_first ? lo_s : hi_s;
+    h.loc[0] = lo_first ? 2 : 0;
+    h.s[1] = has_lo && has_hi ? (lo_first ? hi_s : lo_s) : h.s[0];
+    h.loc[1] = has_lo && has_hi ? (lo_first ? 0 : 2) : h.loc[0];
+    h.w[0] = 1.f;
+    h.w[1] = has_lo && has_hi ? 1.f : 0.f;
+    h.cnt = (int)has_lo + (int)has_hi;
+    return h;
+}
+
+template <int ST_Z, int ST_NT>
+__device__ __forceinline__ void scatter_tile(const Mesh &m, int tx, int ty, int tz, int gx, int gy, int gz,
+                                             const float *__restrict__ Y, const float *__restrict__ vbase,
+                                             float *__restrict__ d) {
+    constexpr int SS_Z = ST_Z / 2 + 1;
+    constexpr int SS_ITER = (SS_RUN + ST_NT - 1) / ST_NT;   // loads per thread per run
+    __shared__ float sY[SS_Z * SS_Y * SS_RUN];
+    const int tid = threadIdx.x;
+    const int x0 = tx * ST_X, y0 = ty * ST_Y, z0 = tz * ST_Z;
+    const int nx = (tx == gx - 1 ? m.nf[0] : x0 + ST_X) - x0;   // owned nodes per axis
+    const int ny = (ty == gy - 1 ? m.nf[1] : y0 + ST_Y) - y0;
+    const int nz = (tz == gz - 1 ? m.nf[2] : z0 + ST_Z) - z0;
+    const int nn = nx * ny * nz;
+    const bool full = nx == ST_X && ny == ST_Y && nz == ST_Z;
+    const int bI = x0 / 2 - 1, bJ = y0 / 2 - 1, bK = z0 / 2 - 1;
+    // node coordinates of this thread's passes, and their base field,
+    // requested with the patch rows so the tile waits for memory once
+    constexpr int NPASS = ((ST_X + 1) * (ST_Y + 1) * (ST_Z + 1) + ST_NT - 1) / ST_NT;
+    int lx[NPASS], ly[NPASS], lz[NPASS];
+    int64_t node[NPASS];
+    float vb[NPASS][4];
+#pragma unroll
+    for (int p = 0; p < NPASS; ++p) {
+        const int q = tid + p * ST_NT;
+        if (full) {
+            lx[p] = q % ST_X;
+            ly[p] = (q / ST_X) % ST_Y;
+            lz[p] = q / (ST_X * ST_Y);
+        } else {
+            lx[p] = q % nx;
+            ly[p] = (q / nx) % ny;
+            lz[p] = q / (nx * ny);
+        }
+        node[p] = x0 + lx[p] + (int64_t)m.nf[0] * (y0 + ly[p] + (int64_t)m.nf[1] * (z0 + lz[p]));
+#pragma unroll
+        for (int c = 0; c < 4; ++c) vb[p][c] = (vbase && q < nn) ? vbase[c * m.n_fine + node[p]] : 0.0f;
+    }
+    // stage: one run of SS_X consecutive x patches per (y, z) slot; patches
+    // outside the mesh are zero (read only with weight 0)
+    // (a run inside the mesh along x is one contiguous stretch of memory;
+    // the two forms are separate loops so each issues all its loads at once)
+    float t[SS_Z * SS_Y][SS_ITER];
+    auto run_ok = [&](int r, int64_t &row) {
+        const int J = wrap(bJ + r % SS_Y, m.n[1], m.per[1]);
+        const int K = wrap(bK + r / SS_Y, m.n[2], m.per[2]);
+        row = (int64_t)m.n[0] * (J + (int64_t)m.n[1] * K);
+        return J >= 0 && J < m.n[1] && K >= 0 && K < m.n[2];
+    };
+    if (bI >= 0 && bI + SS_X <= m.n[0]) {
+#pragma unroll
+        for (int r = 0; r < SS_Z * SS_Y; ++r) {
+            int64_t row;
+            const bool rok = run_ok(r, row);
+            const float *run = Y + (row + bI) * 81;
+#pragma unroll
+            for (int u = 0; u < SS_ITER; ++u) {
+                const int e = tid + u * ST_NT;
+                t[r][u] = rok && e < SS_RUN ? run[e] : 0.0f;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < SS_Z * SS_Y; ++r) {
+            int64_t row;
+            const bool rok = run_ok(r, row);
+#pragma unroll
+            for (int u = 0; u < SS_ITER; ++u) {
+                const int e = tid + u * ST_NT;
+                const int sx = e / 81;
+                const int I = wrap(bI + sx, m.n[0], m.per[0]);
+                t[r][u] = 0.0f;
+                if (rok && e < SS_RUN && I >= 0 && I < m.n[0]) t[r][u] = Y[(row + I) * 81 + (e - 81 * sx)];
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < SS_Z * SS_Y; ++r)
+#pragma unroll
+        for (int u = 0; u < SS_ITER; ++u) {
+            const int e = tid + u * ST_NT;
+            if (e < SS_RUN) sY[r * SS_RUN + e] = t[r][u];
+        }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < NPASS; ++p) {
+        if (tid + p * ST_NT >= nn) break;
+        const int i = x0 + lx[p], j = y0 + ly[p], k = z0 + lz[p];
+        const SHold hx = stile_holders(lx[p], i, m.n[0], m.per[0]);
+        const SHold hy = stile_holders(ly[p], j, m.n[1], m.per[1]);
+        const SHold hz = stile_holders(lz[p], k, m.n[2], m.per[2]);
+        // all 2 x 2 x 2 candidates, z, then y, then x, as extension_at
+        float acc[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int rb = (hz.s[c] * SS_Y + hy.s[b]) * SS_RUN + 3 * hy.loc[b] + 9 * hz.loc[c];
+                const float wbc = hy.w[b] * hz.w[c];
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const float *src = sY + rb + 81 * hx.s[a] + hx.loc[a];
+                    const float w = hx.w[a] * wbc;
+#pragma unroll
+                    for (int cc = 0; cc < 3; ++cc) acc[cc] = fmaf(w, src[27 * cc], acc[cc]);
+                }
+            }
+        const float inv = 1.0f / (float)(hx.cnt * hy.cnt * hz.cnt); // power of two: exact
+        const bool dir = on_dirichlet(m, i, j, k);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            float v = dir ? 0.0f : acc[c] * inv;
+            if (vbase) v += vb[p][c];
+            d[c * m.n_fine + node[p]] = v;
+        }
+        if (vbase) d[3 * m.n_fine + node[p]] = vb[p][3];
+    }
+}
+
+template <int ST_Z, int ST_NT>
+__global__ void __launch_bounds__(ST_NT) k_scatter_tiled(Mesh m, int gx, int gy, int gz, const float *__restrict__ Y,
+                                                         const float *__restrict__ vbase, float *__restrict__ d) {
+    const int64_t t = xcd_item(blockIdx.x, gridDim.x);
+    if (t >= (int64_t)gx * gy * gz) return;
+    scatter_tile<ST_Z, ST_NT>(m, (int)(t % gx), (int)((t / gx) % gy), (int)(t / ((int64_t)gx * gy)), gx, gy, gz, Y,
+                              vbase, d);
+}
+
 // -------------------------------------------------------------- norms -----
 constexpr int NORM_BLOCKS = 1024;
 
@@ -385,14 +566,37 @@ extern "C" int dnnmg_patch_gather(const dnnmg_box *box, const float *x, const fl
     return hip_check(hipGetLastError(), "dnnmg_patch_gather launch");
 }
 
-extern "C" int dnnmg_scatter_avg(const dnnmg_box *box, const float *Y, const float *vbase, float *d,
-                                 void *stream) {
+// The tiled form wins once every compute unit has several tiles; on smaller
+// meshes the per-node form (no staging round trip) is faster.
+constexpr int SCATTER_TZ = 2, SCATTER_NT = 256;
+
+static bool scatter_prefers_tiles(const Mesh &m) {
+    return m.n_fine >= (int64_t)4 * device_cus() * ST_X * ST_Y * SCATTER_TZ;
+}
+
+extern "C" int dnnmg_scatter_avg_form(const dnnmg_box *box, const float *Y, const float *vbase, float *d, int form,
+                                      void *stream) {
     Mesh m;
     int rc = make_mesh(box, &m);
     if (rc) return rc;
     if (!Y || !d) return fail(DNNMG_ERR_ARG, "dnnmg_scatter_avg: NULL pointer");
-    k_scatter<<<blocks_for(m.n_fine, 256), 256, 0, STREAM>>>(m, Y, vbase, d);
+    if (form < DNNMG_SCATTER_AUTO || form > DNNMG_SCATTER_TILED)
+        return fail(DNNMG_ERR_ARG, "dnnmg_scatter_avg_form: unknown form %d", form);
+    if (form == DNNMG_SCATTER_AUTO) form = scatter_prefers_tiles(m) ? DNNMG_SCATTER_TILED : DNNMG_SCATTER_NODES;
+    if (form == DNNMG_SCATTER_TILED) {
+        const int gx = stiles_axis(m.nf[0], ST_X), gy = stiles_axis(m.nf[1], ST_Y);
+        const int gz = stiles_axis(m.nf[2], SCATTER_TZ);
+        k_scatter_tiled<SCATTER_TZ, SCATTER_NT>
+            <<<xcd_blocks((int64_t)gx * gy * gz), SCATTER_NT, 0, STREAM>>>(m, gx, gy, gz, Y, vbase, d);
+    } else {
+        k_scatter<<<blocks_for(m.n_fine, 256), 256, 0, STREAM>>>(m, Y, vbase, d);
+    }
     return hip_check(hipGetLastError(), "dnnmg_scatter_avg launch");
+}
+
+extern "C" int dnnmg_scatter_avg(const dnnmg_box *box, const float *Y, const float *vbase, float *d,
+                                 void *stream) {
+    return dnnmg_scatter_avg_form(box, Y, vbase, d, DNNMG_SCATTER_AUTO, stream);
 }
 
 extern "C" size_t dnnmg_norm2_workspace(void) { return NORM_BLOCKS * sizeof(double); }

@@ -215,6 +215,40 @@ def test_gather_scatter(L, orc, name):
     assert np.array_equal(g4[3], x[3])
 
 
+SCATTER_BOXES = dict(BOXES, per_tiny=syn.BoxSpec((2, 2, 2), (1.0, 1.0, 1.0), 7, 0),
+                     per_x=syn.BoxSpec((4, 3, 5), (1.0, 0.6, 0.9), 1, syn.Y_LO | syn.Y_HI),
+                     cfg5=syn.cfg5().box)
+
+
+@pytest.mark.parametrize("name", list(SCATTER_BOXES))
+def test_scatter_forms(L, orc, name):
+    """The per-node and the tiled extension kernels give the same bits (same
+    candidates, same summation order), with and without the base iterate,
+    and match the oracle; the automatic choice is one of them."""
+    box = SCATTER_BOXES[name]
+    say("scatter forms", name)
+    rng = np.random.default_rng(11)
+    npch, nf = box.n_patches, box.n_fine
+    Y = to_gpu(f32(rng.standard_normal(npch * 81)))
+    x = to_gpu(f32(rng.standard_normal(4 * nf)))
+    dref = orc.scatter(box, Y.cpu().numpy().reshape(npch, 81).astype(np.float64))
+    for vbase, nd in ((None, 3), (x, 4)):
+        outs = {}
+        for form in (L.SCATTER_NODES, L.SCATTER_TILED, L.SCATTER_AUTO):
+            d = torch.full((nd * nf,), float("nan"), dtype=torch.float32, device=dev())
+            L.dnnmg_scatter_avg_form(box, Y, d, form, vbase=vbase)
+            outs[form] = d.cpu().numpy().reshape(nd, nf)
+        assert np.array_equal(outs[L.SCATTER_NODES], outs[L.SCATTER_TILED])
+        assert np.array_equal(outs[L.SCATTER_NODES], outs[L.SCATTER_AUTO])
+        g = outs[L.SCATTER_TILED]
+        base = 0.0 if vbase is None else x.cpu().numpy().reshape(4, nf)[:3]
+        assert rel_l2(g[:3], dref + base) <= 1e-6
+        if vbase is not None:
+            assert np.array_equal(g[3], x.cpu().numpy().reshape(4, nf)[3])
+    with pytest.raises(L.DnnmgError):
+        L.dnnmg_scatter_avg_form(box, Y, torch.empty(3 * nf, device=dev()), 3)
+
+
 def pack_net(L, dtype, params, w_scale=(1.0, 1.0, 1.0)):
     H = params[0].shape[1]
     Wp, bias = [], []
