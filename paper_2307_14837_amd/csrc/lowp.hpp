@@ -42,6 +42,16 @@ __host__ __device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
     return (uint32_t)f32_to_bf16(lo) | ((uint32_t)f32_to_bf16(hi) << 16);
 }
 
+// The same conversions with gfx950's packed f32 -> bf16 instruction (round to
+// nearest even; bit for bit equal to f32_to_bf16 for every non-NaN input, and
+// NaN stays NaN), for device code.
+typedef __bf16 dnnmg_bf16x2 __attribute__((ext_vector_type(2)));
+typedef float dnnmg_f32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf16x2_hw(float lo, float hi) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((dnnmg_f32x2){lo, hi}, dnnmg_bf16x2));
+}
+__device__ __forceinline__ uint16_t f32_to_bf16_hw(float f) { return (uint16_t)pack_bf16x2_hw(f, 0.0f); }
+
 // float -> E4M3FN bits.  Normal range 2^-6 .. 448 keeps 3 mantissa bits;
 // below 2^-6 the spacing is 2^-9 (subnormals).
 __host__ __device__ __forceinline__ uint8_t f32_to_e4m3(float f) {

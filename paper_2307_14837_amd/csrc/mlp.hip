@@ -106,18 +106,6 @@ __device__ __forceinline__ f32x4 mfma(typename Frag<K>::T a, typename Frag<K>::T
         return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 0, 0, 0, 127, 0, 127);
 }
 
-__device__ __forceinline__ float tanh_fast(float z) {
-    // tanh z = 1 - 2 / (exp(2z) + 1); saturates cleanly for large |z|
-    float t = __expf(2.0f * z);
-    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(t + 1.0f);
-}
-
-template <int K>
-__device__ __forceinline__ float act(float z) {
-    if constexpr (K == KF32) return tanhf(z);
-    else return tanh_fast(z);
-}
-
 // Activations v[0..3] of units 16 ot + 4 g + e of patch p (lane 16 g + p) of
 // patch tile t into the next layer's LDS fragments (kind KN, NCHN chunks);
 // see kslot_to_input for the slot order.
@@ -127,7 +115,7 @@ __device__ __forceinline__ void put_act(unsigned char *out, int t, int ot, int l
 #pragma unroll
         for (int e = 0; e < 4; ++e) ((float *)out)[(t * NCHN + 4 * ot + e) * 64 + lane] = v[e];
     } else if constexpr (KN == KBF16) {
-        uint2 w = make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
+        uint2 w = make_uint2(pack_bf16x2_hw(v[0], v[1]), pack_bf16x2_hw(v[2], v[3]));
         *(uint2 *)(out + ((t * NCHN + (ot >> 1)) * 64 + lane) * 16 + 8 * (ot & 1)) = w;
     } else {
         // hardware E4M3 conversion (round to nearest even; the same bits as
@@ -199,12 +187,21 @@ __device__ __forceinline__ void layer(const typename Frag<K>::T *__restrict__ Wl
             }
         } else {
             const float4 bb = *(const float4 *)(bias + 16 * ot + 4 * g);
-            const float bv[4] = {bb.x, bb.y, bb.z, bb.w};
+            // low precision: tanh z = 1 - 2 / (2^(2 z log2 e) + 1) with the
+            // factor 2 log2 e folded into the scale and the bias
+            constexpr float K2 = 2.8853900817779268f; // 2 log2(e)
+            const float sc = K == KF32 ? scale : scale * K2;
+            const float bv[4] = {K == KF32 ? bb.x : bb.x * K2, K == KF32 ? bb.y : bb.y * K2,
+                                 K == KF32 ? bb.z : bb.z * K2, K == KF32 ? bb.w : bb.w * K2};
 #pragma unroll
             for (int t = 0; t < PT; ++t) {
                 float v[4];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) v[e] = act<K>(acc[i][t][e] * scale + bv[e]);
+                for (int e = 0; e < 4; ++e) {
+                    const float z = acc[i][t][e] * sc + bv[e];
+                    if constexpr (K == KF32) v[e] = tanhf(z);
+                    else v[e] = 1.0f - 2.0f * __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(z) + 1.0f);
+                }
                 put_act<KN, NCHN>(out, t, ot, lane, v, qinv);
                 if (saved) {
                     int64_t row = base + 16 * t + p;
@@ -214,7 +211,7 @@ __device__ __forceinline__ void layer(const typename Frag<K>::T *__restrict__ Wl
                             *(float4 *)((float *)saved + idx) = make_float4(v[0], v[1], v[2], v[3]);
                         else
                             *(uint2 *)((uint16_t *)saved + idx) =
-                                make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
+                                make_uint2(pack_bf16x2_hw(v[0], v[1]), pack_bf16x2_hw(v[2], v[3]));
                     }
                 }
             }
@@ -274,7 +271,7 @@ __device__ __forceinline__ void put_input(unsigned char *buf, int pl, int col, f
         ((float *)buf)[(t * NCH0 + (col >> 2)) * 64 + 16 * (col & 3) + p] = v;
     } else {
         const int w = col & 31;
-        *(uint16_t *)(buf + ((t * NCH0 + (col >> 5)) * 64 + 16 * (w >> 3) + p) * 16 + 2 * (w & 7)) = f32_to_bf16(v);
+        *(uint16_t *)(buf + ((t * NCH0 + (col >> 5)) * 64 + 16 * (w >> 3) + p) * 16 + 2 * (w & 7)) = f32_to_bf16_hw(v);
     }
 }
 

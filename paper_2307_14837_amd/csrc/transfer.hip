@@ -225,8 +225,8 @@ __global__ void __launch_bounds__(256)
         *(float4 *)((float *)Xout + M * ldx + col0) = o;
     } else if (DT == DNNMG_BF16) {
         uint2 o;
-        o.x = pack_bf16x2(z[0], z[1]);
-        o.y = pack_bf16x2(z[2], z[3]);
+        o.x = pack_bf16x2_hw(z[0], z[1]);
+        o.y = pack_bf16x2_hw(z[2], z[3]);
         *(uint2 *)((uint16_t *)Xout + M * ldx + col0) = o;
     } else {
         uint32_t o = 0;
