@@ -47,16 +47,19 @@ __global__ void k_mult(Mesh m, uint8_t *__restrict__ mult) {
 
 // ------------------------------------------------------- prolongation -----
 // 1-D Q1 interpolation: even fine index = coarse node, odd = mean of the two
-// coarse neighbours (wrapping on periodic axes).  One thread per coarse node
-// C = (I, J, K) writes the fine nodes 2C + (a, b, c), a, b, c in {0, 1}, that
-// exist, from the 2x2x2 coarse block C .. C+1: all loads are issued at once
-// (one memory round trip per thread).  The FP64 coarse values are rounded to
-// FP32 and averaged axis by axis (x, then y, then z) in FP32, the same
-// operations the residual kernel uses for the patch interpolant, so a
+// coarse neighbours (wrapping on periodic axes).  One thread per (component,
+// coarse node) C = (I, J, K) writes the fine nodes 2C + (a, b, c), a, b, c in
+// {0, 1}, that exist, from the 2x2x2 coarse block C .. C+1: all loads are
+// issued at once (one memory round trip per thread); consecutive threads
+// take consecutive nodes of one component.  The FP64 coarse values are
+// rounded to FP32 and averaged axis by axis (x, then y, then z) in FP32, the
+// same operations the residual kernel uses for the patch interpolant, so a
 // prolongated field equals its own patch interpolant bit for bit.
 __device__ __forceinline__ void prolong_node(const Mesh &m, int64_t t, int ncomp, const double *__restrict__ xc,
                                              float *__restrict__ xf) {
-    if (t >= m.n_coarse) return;
+    if (t >= (int64_t)ncomp * m.n_coarse) return;
+    const int comp = (int)(t / m.n_coarse);
+    t -= (int64_t)comp * m.n_coarse;
     uint32_t JK = fdiv((uint32_t)t, m.cx), I = (uint32_t)t - JK * m.nc[0];
     uint32_t K = fdiv(JK, m.cy), J = JK - K * m.nc[1];
     const int C[3] = {(int)I, (int)J, (int)K};
@@ -69,45 +72,39 @@ __device__ __forceinline__ void prolong_node(const Mesh &m, int64_t t, int ncomp
         odd[a] = m.per[a] || C[a] + 1 < m.nc[a];
         hi[a] = odd[a] ? up : C[a];
     }
-    const int64_t ncn = m.n_coarse, nfn = m.n_fine;
-    int64_t cidx[8];
+    const double *x = xc + (int64_t)comp * m.n_coarse;
+    float v[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         int ii = (q & 1) ? hi[0] : C[0], jj = (q & 2) ? hi[1] : C[1], kk = (q & 4) ? hi[2] : C[2];
-        cidx[q] = ii + (int64_t)m.nc[0] * (jj + (int64_t)m.nc[1] * kk);
+        v[q] = (float)x[ii + (int64_t)m.nc[0] * (jj + (int64_t)m.nc[1] * kk)];
     }
+    // x pass, y pass, z pass: value at offset 0 = corner, at 1 = mean
+    float px[8];
+#pragma unroll
+    for (int q = 0; q < 8; q += 2) { px[q] = v[q]; px[q + 1] = 0.5f * (v[q] + v[q + 1]); }
+    float py[8];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            py[a + 4 * c] = px[a + 4 * c];
+            py[a + 2 + 4 * c] = 0.5f * (px[a + 4 * c] + px[a + 2 + 4 * c]);
+        }
+    float pz[8];
+#pragma unroll
+    for (int ab = 0; ab < 4; ++ab) { pz[ab] = py[ab]; pz[ab + 4] = 0.5f * (py[ab] + py[ab + 4]); }
     const int64_t f0 = 2 * (int64_t)I + (int64_t)m.nf[0] * (2 * (int64_t)J + (int64_t)m.nf[1] * 2 * K);
-    for (int comp = 0; comp < ncomp; ++comp) {
-        const double *x = xc + comp * ncn;
-        float v[8];
+    float *out = xf + (int64_t)comp * m.n_fine + f0;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = (float)x[cidx[q]];
-        // x pass, y pass, z pass: value at offset 0 = corner, at 1 = mean
-        float px[8];
+    for (int c = 0; c < 2; ++c) {
+        if (c && !odd[2]) break;
 #pragma unroll
-        for (int q = 0; q < 8; q += 2) { px[q] = v[q]; px[q + 1] = 0.5f * (v[q] + v[q + 1]); }
-        float py[8];
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-#pragma unroll
-            for (int a = 0; a < 2; ++a) {
-                py[a + 4 * c] = px[a + 4 * c];
-                py[a + 2 + 4 * c] = 0.5f * (px[a + 4 * c] + px[a + 2 + 4 * c]);
-            }
-        float pz[8];
-#pragma unroll
-        for (int ab = 0; ab < 4; ++ab) { pz[ab] = py[ab]; pz[ab + 4] = 0.5f * (py[ab] + py[ab + 4]); }
-        float *out = xf + comp * nfn + f0;
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            if (c && !odd[2]) break;
-#pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                if (b && !odd[1]) break;
-                float *row = out + (int64_t)m.nf[0] * (b + (int64_t)m.nf[1] * c);
-                row[0] = pz[2 * b + 4 * c];
-                if (odd[0]) row[1] = pz[1 + 2 * b + 4 * c];
-            }
+        for (int b = 0; b < 2; ++b) {
+            if (b && !odd[1]) break;
+            float *row = out + (int64_t)m.nf[0] * (b + (int64_t)m.nf[1] * c);
+            row[0] = pz[2 * b + 4 * c];
+            if (odd[0]) row[1] = pz[1 + 2 * b + 4 * c];
         }
     }
 }
@@ -522,7 +519,7 @@ extern "C" int dnnmg_prolong(const dnnmg_box *box, int ncomp, const double *xc, 
     if (rc) return rc;
     if (ncomp < 1 || ncomp > 4) return fail(DNNMG_ERR_ARG, "dnnmg_prolong: ncomp %d not in 1..4", ncomp);
     if (!xc || !xf) return fail(DNNMG_ERR_ARG, "dnnmg_prolong: NULL pointer");
-    k_prolong<<<blocks_for(m.n_coarse, 256), 256, 0, STREAM>>>(m, ncomp, xc, xf);
+    k_prolong<<<blocks_for((int64_t)ncomp * m.n_coarse, 256), 256, 0, STREAM>>>(m, ncomp, xc, xf);
     return hip_check(hipGetLastError(), "dnnmg_prolong launch");
 }
 
