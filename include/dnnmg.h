@@ -141,6 +141,23 @@ int dnnmg_residual(const dnnmg_box *box, const dnnmg_ns *ns, const float *x, con
 int dnnmg_prolong_residual(const dnnmg_box *box, const dnnmg_ns *ns, const double *xc, const float *vprev,
                            const float *fmid, float *xt, float *r, void *stream);
 
+/* The same fused pass against a given right-hand side (Algorithm 1: the fine
+ * Rhs of the previous step feeds the next step's residual):
+ *   xt = P xc (as dnnmg_prolong) and r = b - A(xt),
+ * where A(x) holds the terms of eq. (4cranknicholson3) that depend on the
+ * new iterate: (1/k) M v + 1/2 N(v) + nu/2 K v - (p, div phi) for the
+ * momentum rows and (div v, xi) for the continuity row.  With b =
+ * dnnmg_rhs(vprev, fmid) this is the residual dnnmg_prolong_residual
+ * computes (same terms, summed as b plus the new-iterate part, so equal up
+ * to FP32 rounding); in a time loop b is the previous step's Rhs output, so
+ * the terms of the previous velocity are not evaluated twice.
+ *   xc FP64 [4][n_coarse]; b FP32 [4][n_fine] (pressure row added as given,
+ *   0 from dnnmg_rhs); xt and r FP32 [4][n_fine] outputs, not overlapping
+ *   the inputs (r == b is DNNMG_ERR_ARG).  Velocity rows of r on Dirichlet
+ *   faces are 0. */
+int dnnmg_prolong_residual_b(const dnnmg_box *box, const dnnmg_ns *ns, const double *xc, const float *b, float *xt,
+                             float *r, void *stream);
+
 /* Right-hand side of (4cranknicholson3) for the next step (Algorithm 1,
  * "Rhs"): b_a = (1/k)(v_a, phi) - 1/2 (v.grad v_a, phi) - nu/2 (grad v_a,
  * grad phi) + (fmid_a, phi); pressure rows 0; Dirichlet velocity rows 0.
@@ -322,6 +339,20 @@ int dnnmg_plan_choice(const dnnmg_plan *plan, int *patches_per_tile, int *grid);
 int dnnmg_batch_step(const dnnmg_plan *plan, const dnnmg_mlp *net, const float *shift, const float *inv_scale,
                      const double *xc, const float *vprev, float *xt, float *r, float *Y, float *xcorr,
                      float *b, double *bc, void *stream);
+
+/* The batched step against the previous step's right-hand side (as
+ * dnnmg_prolong_residual_b): on entry b FP32 [4] (batch layout) holds the
+ * Rhs the previous step left; the step computes r = b - A(x~), ..., then
+ * overwrites b with the new Rhs and restricts it to bc.  b must not overlap
+ * xt, r, Y, xcorr or bc.  Same launches as dnnmg_batch_step. */
+int dnnmg_batch_step_b(const dnnmg_plan *plan, const dnnmg_mlp *net, const float *shift, const float *inv_scale,
+                       const double *xc, float *b, float *xt, float *r, float *Y, float *xcorr, double *bc,
+                       void *stream);
+
+/* Right-hand side (as dnnmg_rhs, no forcing) of every box of the plan, in one
+ * launch: v FP32 [3 or 4] and b FP32 [4] in the batch layout.  Starts a time
+ * loop run with dnnmg_batch_step_b from a given previous velocity. */
+int dnnmg_batch_rhs(const dnnmg_plan *plan, const float *v, float *b, void *stream);
 /* Autotuner (setup call, synchronises the stream): times the network stage
  * on the batch's own inputs for every candidate (16, 32 or 64 patches per
  * workgroup tile, as built for the network's type and width; one workgroup

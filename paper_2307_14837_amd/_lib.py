@@ -87,6 +87,7 @@ _sig("dnnmg_residual_workspace", [_P(Box)], c_sz)
 _sig("dnnmg_residual", [_P(Box), _P(NS), c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp])
 _sig("dnnmg_rhs", [_P(Box), _P(NS), c_vp, c_vp, c_vp, c_vp])
 _sig("dnnmg_prolong_residual", [_P(Box), _P(NS), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp])
+_sig("dnnmg_prolong_residual_b", [_P(Box), _P(NS), c_vp, c_vp, c_vp, c_vp, c_vp])
 _sig("dnnmg_restrict", [_P(Box), ctypes.c_int, c_vp, c_vp, c_vp])
 _sig("dnnmg_patch_gather", [_P(Box), c_vp, c_vp, _P(Feat), ctypes.c_int, c_f, c_vp, c_i64, c_vp])
 _sig("dnnmg_mlp_packed_bytes", [ctypes.c_int, ctypes.c_int, ctypes.c_int], c_sz)
@@ -115,6 +116,8 @@ _sig("dnnmg_plan_destroy", [c_vp])
 _sig("dnnmg_plan_sizes", [c_vp, _P(c_i64), _P(c_i64), _P(c_i64)])
 _sig("dnnmg_plan_choice", [c_vp, _P(ctypes.c_int), _P(ctypes.c_int)])
 _sig("dnnmg_batch_step", [c_vp, _P(MLP), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp])
+_sig("dnnmg_batch_step_b", [c_vp, _P(MLP), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp])
+_sig("dnnmg_batch_rhs", [c_vp, c_vp, c_vp, c_vp])
 _sig("dnnmg_plan_autotune", [c_vp, _P(MLP), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
                              ctypes.c_int, c_vp])
 _sig("dnnmg_adamw_step", [c_i64, c_vp, c_vp, c_vp, c_vp, c_f, c_f, c_f, c_f, c_f, c_i64, c_vp])
@@ -123,12 +126,13 @@ EXPORTS = [
     "dnnmg_version", "dnnmg_last_error", "dnnmg_box_sizes", "dnnmg_patch_dofmap", "dnnmg_prolong",
     "dnnmg_residual_workspace", "dnnmg_residual", "dnnmg_rhs", "dnnmg_restrict",
     "dnnmg_patch_gather", "dnnmg_mlp_packed_bytes", "dnnmg_mlp_pack", "dnnmg_patch_forward",
-    "dnnmg_patch_forward_tiles", "dnnmg_prolong_residual",
+    "dnnmg_patch_forward_tiles", "dnnmg_prolong_residual", "dnnmg_prolong_residual_b",
     "dnnmg_patch_saved_bytes", "dnnmg_scatter_avg", "dnnmg_scatter_avg_form", "dnnmg_norm2_workspace", "dnnmg_norm2_f64",
     "dnnmg_mse_grad", "dnnmg_patch_backward_workspace", "dnnmg_patch_backward", "dnnmg_adamw_step",
     "dnnmg_vanka_workspace", "dnnmg_vanka_sweeps", "dnnmg_fallback_workspace", "dnnmg_fallback",
     "dnnmg_patch_gather_forward", "dnnmg_plan_workspace", "dnnmg_plan_create", "dnnmg_plan_destroy",
     "dnnmg_plan_sizes", "dnnmg_plan_choice", "dnnmg_batch_step", "dnnmg_plan_autotune",
+    "dnnmg_batch_step_b", "dnnmg_batch_rhs",
 ]
 
 
@@ -222,6 +226,15 @@ def dnnmg_prolong_residual(box, ns, xc, vprev, xt, r, fmid=None, stream=None):
                                        _ptr(vprev, torch.float32, 3 * nf, "vprev"),
                                        _ptr(fmid, torch.float32, 3 * nf, "fmid"), _ptr(xt, torch.float32, 4 * nf, "xt"),
                                        _ptr(r, torch.float32, 4 * nf, "r"), _stream(stream)))
+
+
+def dnnmg_prolong_residual_b(box, ns, xc, b, xt, r, stream=None):
+    bx = Box.of(box)
+    nf, nc, _ = box_sizes(bx)
+    _check(_lib.dnnmg_prolong_residual_b(ctypes.byref(bx), ctypes.byref(NS.of(ns)),
+                                         _ptr(xc, torch.float64, 4 * nc, "xc"), _ptr(b, torch.float32, 4 * nf, "b"),
+                                         _ptr(xt, torch.float32, 4 * nf, "xt"), _ptr(r, torch.float32, 4 * nf, "r"),
+                                         _stream(stream)))
 
 
 def dnnmg_restrict(box, bf, bc, ncomp=4, stream=None):
@@ -423,6 +436,23 @@ class Plan:
 
     def step(self, net, bufs, shift=None, inv_scale=None, stream=None):
         _check(_lib.dnnmg_batch_step(self.handle, *self._args(net, shift, inv_scale, bufs), _stream(stream)))
+
+    def step_b(self, net, bufs, shift=None, inv_scale=None, stream=None):
+        nf, nc, npch = self.n_fine, self.n_coarse, self.n_patches
+        _check(_lib.dnnmg_batch_step_b(self.handle, ctypes.byref(net), _ptr(shift, torch.float32, 165, "shift"),
+                                       _ptr(inv_scale, torch.float32, 165, "inv_scale"),
+                                       _ptr(bufs["xc"], torch.float64, 4 * nc, "xc"),
+                                       _ptr(bufs["b"], torch.float32, 4 * nf, "b"),
+                                       _ptr(bufs["xt"], torch.float32, 4 * nf, "xt"),
+                                       _ptr(bufs["r"], torch.float32, 4 * nf, "r"),
+                                       _ptr(bufs["Y"], torch.float32, npch * N_OUT, "Y"),
+                                       _ptr(bufs["xcorr"], torch.float32, 4 * nf, "xcorr"),
+                                       _ptr(bufs["bc"], torch.float64, 4 * nc, "bc"), _stream(stream)))
+
+    def rhs(self, v4, b, stream=None):
+        nf = self.n_fine
+        _check(_lib.dnnmg_batch_rhs(self.handle, _ptr(v4, torch.float32, 4 * nf, "v"), _ptr(b, torch.float32, 4 * nf, "b"),
+                                    _stream(stream)))
 
     def autotune(self, net, bufs, shift=None, inv_scale=None, reps=5, stream=None):
         _check(_lib.dnnmg_plan_autotune(self.handle, *self._args(net, shift, inv_scale, bufs), int(reps),

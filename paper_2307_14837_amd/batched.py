@@ -1,6 +1,8 @@
 """Batched correction step over many independent boxes of uneven size (one
-plan, six launches per step whatever the number of boxes), with the
-autotuned network stage and HIP-graph capture."""
+plan, five launches per step whatever the number of boxes), with the
+autotuned network stage and HIP-graph capture.  By default the step carries
+the right-hand side: each step's residual is r = b - A(x~) with the b the
+previous step computed (load() computes the first one from vprev)."""
 from __future__ import annotations
 
 import numpy as np
@@ -11,8 +13,10 @@ from .stepper import DTYPES, TANH_SCALE
 
 
 class BatchedStep:
-    def __init__(self, boxes, ns, params, dtype="bf16", device="cuda:0", shift=None, inv_scale=None):
+    def __init__(self, boxes, ns, params, dtype="bf16", device="cuda:0", shift=None, inv_scale=None,
+                 carry_rhs=True):
         self.dev = torch.device(device)
+        self.carry_rhs = bool(carry_rhs)
         self.boxes = [L.Box.of(b) for b in boxes]
         self.sizes = [L.box_sizes(b) for b in self.boxes]
         self.plan = L.Plan(self.boxes, ns, device=device)
@@ -58,9 +62,19 @@ class BatchedStep:
         vp = np.concatenate([np.asarray(v, np.float32).reshape(3, -1).ravel() for v in vprevs])
         self.bufs["xc"].copy_(torch.as_tensor(xc))
         self.bufs["vprev"].copy_(torch.as_tensor(vp))
+        if self.carry_rhs:
+            # the previous velocity in the 4-component layout (xcorr is
+            # scratch until the step writes it), then its right-hand side
+            v4 = self.bufs["xcorr"]
+            for of, oc, op, nf, nc, npch in self._offsets():
+                v4[4 * of:4 * of + 3 * nf].copy_(self.bufs["vprev"][3 * of:3 * of + 3 * nf])
+            self.plan.rhs(v4, self.bufs["b"])
 
     def step(self, stream=None):
-        self.plan.step(self.net, self.bufs, self.shift, self.inv_scale, stream=stream)
+        if self.carry_rhs:
+            self.plan.step_b(self.net, self.bufs, self.shift, self.inv_scale, stream=stream)
+        else:
+            self.plan.step(self.net, self.bufs, self.shift, self.inv_scale, stream=stream)
 
     def autotune(self, reps=5):
         self.plan.autotune(self.net, self.bufs, self.shift, self.inv_scale, reps=reps)

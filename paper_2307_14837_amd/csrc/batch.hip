@@ -20,6 +20,8 @@ void prolong_residual_batch_launch(const BoxDesc *D, int nbox, int64_t nfull, in
 void restrict_batch_launch(const BoxDesc *D, int nbox, int64_t nblk, const float *bf, double *bc, hipStream_t s);
 void rhs_batch_launch(const BoxDesc *D, int nbox, int64_t nfull, int64_t npart, const float *v, float *b,
                       hipStream_t s);
+void prolong_residual_b_batch_launch(const BoxDesc *D, int nbox, int64_t nfull, int64_t npart, const double *xc,
+                                     const float *b, float *xt, float *r, hipStream_t s);
 void scatter_batch_launch(const BoxDesc *D, int nbox, int64_t nblk, const float *Y, const float *vbase, float *xc,
                           hipStream_t s);
 
@@ -143,11 +145,14 @@ extern "C" int dnnmg_plan_choice(const dnnmg_plan *p, int *patches_per_tile, int
     return DNNMG_OK;
 }
 
+// vprev == NULL: b holds the previous step's right-hand side on entry and
+// the residual is r = b - A(x~); b is then overwritten with the new one.
 static int step_impl(const dnnmg_plan *p, const dnnmg_mlp *net, const float *shift, const float *inv,
                      const double *xc, const float *vprev, float *xt, float *r, float *Y, float *xcorr, float *b,
                      double *bc, hipStream_t s) {
     const BoxDesc *D = p->d_desc;
-    prolong_residual_batch_launch(D, p->nbox, p->tiles_full, p->tiles_part, xc, vprev, xt, r, s);
+    if (vprev) prolong_residual_batch_launch(D, p->nbox, p->tiles_full, p->tiles_part, xc, vprev, xt, r, s);
+    else prolong_residual_b_batch_launch(D, p->nbox, p->tiles_full, p->tiles_part, xc, b, xt, r, s);
     BoxDesc none{};
     int rc = fwd_launch(net, p->pt, true, p->ptiles, p->grid, 0, nullptr, 0, D, p->nbox, none, xt, r, shift, inv,
                         Y, nullptr, s);
@@ -174,6 +179,22 @@ extern "C" int dnnmg_batch_step(const dnnmg_plan *p, const dnnmg_mlp *net, const
     int rc = check_step(p, net, xc, vprev, xt, r, Y, xcorr, b, bc);
     if (rc) return rc;
     return step_impl(p, net, shift, inv_scale, xc, vprev, xt, r, Y, xcorr, b, bc, (hipStream_t)stream);
+}
+
+extern "C" int dnnmg_batch_step_b(const dnnmg_plan *p, const dnnmg_mlp *net, const float *shift,
+                                  const float *inv_scale, const double *xc, float *b, float *xt, float *r, float *Y,
+                                  float *xcorr, double *bc, void *stream) {
+    if (!b) return fail(DNNMG_ERR_ARG, "batch step: NULL buffer");
+    int rc = check_step(p, net, xc, b, xt, r, Y, xcorr, b, bc);
+    if (rc) return rc;
+    if (b == r || b == xt || b == xcorr) return fail(DNNMG_ERR_ARG, "dnnmg_batch_step_b: b overlaps an output");
+    return step_impl(p, net, shift, inv_scale, xc, nullptr, xt, r, Y, xcorr, b, bc, (hipStream_t)stream);
+}
+
+extern "C" int dnnmg_batch_rhs(const dnnmg_plan *p, const float *v, float *b, void *stream) {
+    if (!p || !v || !b) return fail(DNNMG_ERR_ARG, "dnnmg_batch_rhs: NULL argument");
+    rhs_batch_launch(p->d_desc, p->nbox, p->tiles_full, p->tiles_part, v, b, (hipStream_t)stream);
+    return hip_check(hipGetLastError(), "dnnmg_batch_rhs launch");
 }
 
 extern "C" int dnnmg_plan_autotune(dnnmg_plan *p, const dnnmg_mlp *net, const float *shift, const float *inv_scale,

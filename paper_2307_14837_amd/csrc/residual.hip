@@ -208,6 +208,12 @@ constexpr int MODE_RHS = 1;
 // itself (and writes out): the iterate is patchwise Q1, so every local
 // projection term vanishes identically and none is evaluated
 constexpr int MODE_PRES = 2;
+// the same against a given right-hand side b (the Rhs of the previous step's
+// corrected velocity): r = b - A(x~); the tile evaluates only the terms of
+// the new iterate and adds b at its owned nodes
+constexpr int MODE_PRESB = 3;
+__host__ __device__ constexpr bool mode_prolongs(int mode) { return mode == MODE_PRES || mode == MODE_PRESB; }
+__host__ __device__ constexpr bool mode_has_vp(int mode) { return mode == MODE_RES || mode == MODE_PRES; }
 
 template <int MODE>
 struct ResTile {
@@ -221,7 +227,7 @@ struct ResTile {
     static constexpr int NPX = TX / 2, NPY = TY / 2, NPZ = TZ / 2, NP = NPX * NPY * NPZ;
     static constexpr int NT = 768; // one thread per cell (765 cells)
     static constexpr int NF_STAGE = MODE != MODE_RHS ? 4 : 0; // x, p on the wide range
-    static constexpr int NF_V = 3;                            // vp (res) or v (rhs)
+    static constexpr int NF_V = MODE == MODE_PRESB ? 0 : 3;   // vp (res) or v (rhs)
     static constexpr int NACC = MODE != MODE_RHS ? 4 : 3;
     // coarse nodes under the staged range (prolongating tiles)
     static constexpr int CX = TX / 2 + 2, CY = TY / 2 + 2, CZ = TZ / 2 + 2, CN = CX * CY * CZ;
@@ -243,11 +249,11 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
                                               float *__restrict__ xt_out = nullptr) {
     using T = ResTile<MODE>;
     __shared__ float sX[T::NF_STAGE > 0 ? T::NF_STAGE * T::SN : 1];
-    __shared__ float sV[T::NF_V * T::VN];
-    __shared__ float sF[3 * T::VN];      // forcing, when given
+    __shared__ float sV[T::NF_V > 0 ? T::NF_V * T::VN : 1];
+    __shared__ float sF[MODE == MODE_PRESB ? 1 : 3 * T::VN]; // forcing, when given
     __shared__ float sCell[8 * T::NCELL]; // [vertex j][cell]
     __shared__ float sCor[MODE == MODE_RES ? 8 * T::NCELL : 1];
-    __shared__ float sC[MODE == MODE_PRES ? 4 * T::CN : 1]; // coarse iterate, rounded to FP32
+    __shared__ float sC[mode_prolongs(MODE) ? 4 * T::CN : 1]; // coarse iterate, rounded to FP32
 
     const int x0 = bx * T::TX, y0 = by * T::TY, z0 = bz * T::TZ;
     const int tid = threadIdx.x;
@@ -263,7 +269,7 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
     };
     // all loads of a thread are issued before its LDS stores, so the staging
     // costs one memory round trip
-    if constexpr (MODE == MODE_PRES) {
+    if constexpr (mode_prolongs(MODE)) {
         // coarse nodes x0/2 - 1 .. of the staged range, then Q1 interpolation
         // axis by axis (x, y, z) in FP32: the operations of the prolongation
         // kernel, so x~ is the same to the bit
@@ -351,8 +357,10 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
                 for (int f = 0; f < 3; ++f) dst[f * T::VN + s] = tmp[it][f];
         }
     };
-    stage_v(MODE != MODE_RHS ? vp : x, sV);
-    if (fmid) stage_v(fmid, sF);
+    if constexpr (MODE != MODE_PRESB) {
+        stage_v(MODE != MODE_RHS ? vp : x, sV);
+        if (fmid) stage_v(fmid, sF);
+    }
     for (int s = tid; s < 8 * T::NCELL; s += T::NT) {
         sCell[s] = 0.0f;
         if constexpr (MODE == MODE_RES) sCor[s] = 0.0f;
@@ -484,9 +492,11 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
 #pragma unroll
                 for (int j = 0; j < 8; ++j) w[j] = sX[d * T::SN + xb + xoff(j)];
                 eval_val(w, xv[d]);
+                if constexpr (mode_has_vp(MODE)) {
 #pragma unroll
-                for (int j = 0; j < 8; ++j) w[j] = sV[d * T::VN + vb + voff(j)];
-                eval_val(w, pv[d]);
+                    for (int j = 0; j < 8; ++j) w[j] = sV[d * T::VN + vb + voff(j)];
+                    eval_val(w, pv[d]);
+                }
             }
             float w[8];
 #pragma unroll
@@ -500,24 +510,33 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
             float acc[8];
             if (live) {
                 float w[8], tmp[8], g0[8], g1[8], g2[8], G0[8], G1[8], G2[8], F[8];
-                // (1/k)(vp_a - v_a) (+ (f^{n-1} + f^n)/2) at the Gauss points
-                if (fmid) {
+                if constexpr (mode_has_vp(MODE)) {
+                    // (1/k)(vp_a - v_a) (+ (f^{n-1} + f^n)/2) at the Gauss points
+                    if (fmid) {
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) w[j] = sF[a * T::VN + vb + voff(j)];
-                    eval_val(w, F);
+                        for (int j = 0; j < 8; ++j) w[j] = sF[a * T::VN + vb + voff(j)];
+                        eval_val(w, F);
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) F[q] = 0.0f;
+                    }
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) F[q] += P.inv_dt * (pv[a][q] - xv[a][q]);
+                    // -1/2 vp . grad vp_a; the gradient also enters -nu/2 grad(vp_a + v_a)
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) w[j] = sV[a * T::VN + vb + voff(j)];
+                    eval_vg(w, ih0, ih1, ih2, tmp, G0, G1, G2);
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        F[q] -= 0.5f * (pv[0][q] * G0[q] + pv[1][q] * G1[q] + pv[2][q] * G2[q]);
                 } else {
+                    // the previous step's terms are in b: -(1/k) v_a only
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) F[q] = 0.0f;
+                    for (int q = 0; q < 8; ++q) {
+                        F[q] = -P.inv_dt * xv[a][q];
+                        G0[q] = G1[q] = G2[q] = 0.0f;
+                    }
                 }
-#pragma unroll
-                for (int q = 0; q < 8; ++q) F[q] += P.inv_dt * (pv[a][q] - xv[a][q]);
-                // -1/2 vp . grad vp_a; the gradient also enters -nu/2 grad(vp_a + v_a)
-#pragma unroll
-                for (int j = 0; j < 8; ++j) w[j] = sV[a * T::VN + vb + voff(j)];
-                eval_vg(w, ih0, ih1, ih2, tmp, G0, G1, G2);
-#pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    F[q] -= 0.5f * (pv[0][q] * G0[q] + pv[1][q] * G1[q] + pv[2][q] * G2[q]);
                 // -1/2 v . grad v_a, divergence
 #pragma unroll
                 for (int j = 0; j < 8; ++j) w[j] = sX[a * T::SN + xb + xoff(j)];
@@ -525,9 +544,15 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
                     F[q] -= 0.5f * (xv[0][q] * g0[q] + xv[1][q] * g1[q] + xv[2][q] * g2[q]);
-                    G0[q] = -P.half_nu * (G0[q] + g0[q]);
-                    G1[q] = -P.half_nu * (G1[q] + g1[q]);
-                    G2[q] = -P.half_nu * (G2[q] + g2[q]);
+                    if constexpr (mode_has_vp(MODE)) {
+                        G0[q] = -P.half_nu * (G0[q] + g0[q]);
+                        G1[q] = -P.half_nu * (G1[q] + g1[q]);
+                        G2[q] = -P.half_nu * (G2[q] + g2[q]);
+                    } else {
+                        G0[q] = -P.half_nu * g0[q];
+                        G1[q] = -P.half_nu * g1[q];
+                        G2[q] = -P.half_nu * g2[q];
+                    }
                 }
                 const float *ga = a == 0 ? g0 : (a == 1 ? g1 : g2);
                 float *Ga = a == 0 ? G0 : (a == 1 ? G1 : G2);
@@ -681,11 +706,18 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
         if (gi < m.nf[0] && gj < m.nf[1] && gk < m.nf[2]) {
             int64_t g = gi + (int64_t)m.nf[0] * (gj + (int64_t)m.nf[1] * gk);
             bool dir = on_dirichlet(m, gi, gj, gk);
+            if constexpr (MODE == MODE_PRESB) {
+                // r = b - A(x~): vp carries b [4][n_fine]
 #pragma unroll
-            for (int f = 0; f < 3; ++f) out[f * nfn + g] = dir ? 0.0f : res[f];
-            if constexpr (MODE != MODE_RHS) out[3 * nfn + g] = res[3];
-            else out[3 * nfn + g] = 0.0f;
-            if constexpr (MODE == MODE_PRES) {
+                for (int f = 0; f < 3; ++f) out[f * nfn + g] = dir ? 0.0f : vp[f * nfn + g] + res[f];
+                out[3 * nfn + g] = vp[3 * nfn + g] + res[3];
+            } else {
+#pragma unroll
+                for (int f = 0; f < 3; ++f) out[f * nfn + g] = dir ? 0.0f : res[f];
+                if constexpr (MODE != MODE_RHS) out[3 * nfn + g] = res[3];
+                else out[3 * nfn + g] = 0.0f;
+            }
+            if constexpr (mode_prolongs(MODE)) {
                 const int slot = (lx + 2) + T::SX * ((ly + 2) + T::SY * (lz + 2));
 #pragma unroll
                 for (int f = 0; f < 4; ++f) xt_out[f * nfn + g] = sX[f * T::SN + slot];
@@ -812,11 +844,11 @@ __global__ void __launch_bounds__(ResTile<MODE>::NT)
     const int tl = c[0] + d.rtiles[0] * (c[1] + d.rtiles[1] * c[2]);
     (void)tl;
     const int bx = c[0], by = c[1], bz = c[2];
-    residual_tile<MODE>(m, P, bx, by, bz, MODE != MODE_PRES ? x + 4 * d.off_fine : nullptr,
-                        MODE != MODE_RHS ? vp + 3 * d.off_fine : nullptr, nullptr, out + 4 * d.off_fine,
-                        nullptr, nullptr,
-                        MODE == MODE_PRES ? xc + 4 * d.off_coarse : nullptr,
-                        MODE == MODE_PRES ? xt_out + 4 * d.off_fine : nullptr);
+    residual_tile<MODE>(m, P, bx, by, bz, !mode_prolongs(MODE) ? x + 4 * d.off_fine : nullptr,
+                        MODE == MODE_RHS ? nullptr : vp + (MODE == MODE_PRESB ? 4 : 3) * d.off_fine, nullptr,
+                        out + 4 * d.off_fine, nullptr, nullptr,
+                        mode_prolongs(MODE) ? xc + 4 * d.off_coarse : nullptr,
+                        mode_prolongs(MODE) ? xt_out + 4 * d.off_fine : nullptr);
 }
 
 // Adds the corner (pi phi) parts of the LPS terms: a coarse vertex collects
@@ -952,6 +984,12 @@ void prolong_residual_batch_launch(const BoxDesc *D, int nbox, int64_t nfull, in
         D, nbox, nfull, npart, nullptr, vp, r, nullptr, nullptr, xc, xt);
 }
 
+void prolong_residual_b_batch_launch(const BoxDesc *D, int nbox, int64_t nfull, int64_t npart, const double *xc,
+                                     const float *b, float *xt, float *r, hipStream_t s) {
+    k_residual_batch<MODE_PRESB><<<(unsigned)(xcd_blocks(nfull) + npart), ResTile<MODE_PRESB>::NT, 0, s>>>(
+        D, nbox, nfull, npart, nullptr, b, r, nullptr, nullptr, xc, xt);
+}
+
 } // namespace dnnmg
 
 using namespace dnnmg;
@@ -987,6 +1025,20 @@ extern "C" int dnnmg_rhs(const dnnmg_box *box, const dnnmg_ns *ns, const float *
     k_residual<MODE_RHS><<<tile_blocks<MODE_RHS>(m), ResTile<MODE_RHS>::NT, 0, (hipStream_t)stream>>>(
         m, P, v, nullptr, fmid, b, nullptr, nullptr, nullptr, nullptr, nullptr);
     return hip_check(hipGetLastError(), "dnnmg_rhs launch");
+}
+
+extern "C" int dnnmg_prolong_residual_b(const dnnmg_box *box, const dnnmg_ns *ns, const double *xc,
+                                        const float *b, float *xt, float *r, void *stream) {
+    Mesh m;
+    int rc = make_mesh(box, &m);
+    if (rc) return rc;
+    if ((rc = check_ns(ns))) return rc;
+    if (!xc || !b || !xt || !r) return fail(DNNMG_ERR_ARG, "dnnmg_prolong_residual_b: NULL pointer");
+    if (b == r) return fail(DNNMG_ERR_ARG, "dnnmg_prolong_residual_b: b and r must not alias");
+    ResParams P = make_params(m, ns);
+    k_residual<MODE_PRESB><<<tile_blocks<MODE_PRESB>(m), ResTile<MODE_PRESB>::NT, 0, (hipStream_t)stream>>>(
+        m, P, nullptr, b, nullptr, r, nullptr, nullptr, nullptr, xc, xt);
+    return hip_check(hipGetLastError(), "dnnmg_prolong_residual_b launch");
 }
 
 extern "C" int dnnmg_prolong_residual(const dnnmg_box *box, const dnnmg_ns *ns, const double *xc,

@@ -56,6 +56,19 @@ def prolong_residual_flops_per_cell() -> int:
     return residual_flops_per_cell(lps=False) - 4 * PI_VERTICES + PROLONG_PER_NODE
 
 
+def prolong_residual_b_flops_per_cell() -> int:
+    """Prolongation fused with r = b - A(x~) against a given right-hand side,
+    per fine cell: only the terms of the new iterate, plus b at the node."""
+    values = 4 * EVAL_VAL                          # x~, p~ at the Gauss points
+    per_comp = (8                                  # -(1/k) v_a
+                + EVAL_VG + 56 + 8                 # grad v_a; -1/2 v . grad v_a; divergence
+                + 24 + 8                           # -nu/2 grad v_a, + p d_a phi
+                + INTEGRATE)                       # vertex integrals
+    cont = 8 + INTEGRATE_VAL                       # -(div x~, xi)
+    sums = 32 + 32 + 4                             # quadrature weight, LDS sums, + b
+    return values + 3 * per_comp + cont + sums + PROLONG_PER_NODE
+
+
 def rhs_flops_per_cell() -> int:
     """Right-hand side b = Rhs(v) per fine cell (no forcing)."""
     per_comp = EVAL_VG + 8 + 24 + 7 * 8 + INTEGRATE

@@ -24,12 +24,16 @@ class CorrectionStep:
 
     params: [W1, b1, W2, b2, W3, b3] (numpy or torch, W as [fan_in][fan_out]).
     shift / inv_scale: per-feature standardisation of the 165 inputs (None =
-    identity).  FP8 networks quantise W2 with amax / 448 and the tanh outputs
+    identity).  carry_rhs (default: without the indicator): the step's
+    residual is r = b - A(x~) with b the right-hand side the previous step
+    computed (load() computes the first one from vprev), so the terms of the
+    previous velocity are evaluated once per step, not twice; the indicator
+    path keeps vprev, which its residual and fallback need.  FP8 networks quantise W2 with amax / 448 and the tanh outputs
     entering layer 2 with the fixed scale 1 / 448.
     """
 
     def __init__(self, box, ns, params, dtype="bf16", device="cuda:0", shift=None, inv_scale=None,
-                 indicator=False, theta=1.0, fallback_sweeps=4, fused=True):
+                 indicator=False, theta=1.0, fallback_sweeps=4, fused=True, carry_rhs=None):
         self.box = L.Box.of(box)
         self.ns = L.NS.of(ns)
         self.dev = torch.device(device)
@@ -39,6 +43,9 @@ class CorrectionStep:
         self.indicator = indicator
         # fused: the gather runs inside the network kernel (no X round trip)
         self.fused = bool(fused)
+        self.carry_rhs = (not indicator) if carry_rhs is None else bool(carry_rhs)
+        if self.carry_rhs and indicator:
+            raise ValueError("carry_rhs: the indicator path needs vprev")
         f32 = dict(dtype=torch.float32, device=self.dev)
         f64 = dict(dtype=torch.float64, device=self.dev)
         self.xc = torch.zeros(4 * self.nc, **f64)
@@ -88,11 +95,18 @@ class CorrectionStep:
     def load(self, xc, vprev):
         self.xc.copy_(torch.as_tensor(np.asarray(xc, np.float64).ravel()))
         self.vprev.copy_(torch.as_tensor(np.asarray(vprev, np.float32).ravel()))
+        if self.carry_rhs:
+            # the right-hand side of the previous velocity, as the previous
+            # step would have left it
+            L.dnnmg_rhs(self.box, self.ns, self.vprev, self.b)
 
     def step(self, stream=None):
         box, ns = self.box, self.ns
         # x~ = P xc and r = F - A(x~) in one pass (no LPS terms on a prolongation)
-        L.dnnmg_prolong_residual(box, ns, self.xc, self.vprev, self.xt, self.r, stream=stream)
+        if self.carry_rhs:
+            L.dnnmg_prolong_residual_b(box, ns, self.xc, self.b, self.xt, self.r, stream=stream)
+        else:
+            L.dnnmg_prolong_residual(box, ns, self.xc, self.vprev, self.xt, self.r, stream=stream)
         if self.fused:
             L.dnnmg_patch_gather_forward(box, self.net, self.xt, self.r, self.Y, self.shift, self.inv_scale,
                                          stream=stream)

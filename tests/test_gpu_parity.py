@@ -138,6 +138,55 @@ def test_prolong_residual_fused(L, orc, name):
         assert rel_l2(r2.cpu().numpy().reshape(4, -1), ref) <= 1e-5
 
 
+@pytest.mark.parametrize("name", list(BOXES))
+def test_prolong_residual_b(L, orc, name):
+    """Prolongation + residual against a given right-hand side: x~ equals
+    dnnmg_prolong bit for bit; b is added at the nodes exactly (r(b) ==
+    fl(b + r(0)) element by element, Dirichlet velocity rows 0); with b =
+    Rhs(v_prev, f) the result is the Crank-Nicolson residual of the oracle."""
+    box = BOXES[name]
+    say("prolong+residual against b", name)
+    ns = syn.NSParams(1e-3, 0.01) if name != "cfg2" else syn.cfg2().ns
+    rng = np.random.default_rng(23)
+    xc = rng.standard_normal((4, box.n_coarse))
+    vp = f32(rng.standard_normal((3, box.n_fine)))
+    fm = f32(rng.standard_normal((3, box.n_fine)))
+    nf = box.n_fine
+    xcg, vpg = to_gpu(xc.ravel()), to_gpu(vp.ravel())
+    new = lambda: torch.full((4 * nf,), float("nan"), dtype=torch.float32, device=dev())
+    xt0 = new()
+    L.dnnmg_prolong(box, xcg, xt0)
+    # b = 0 gives -A(x~); an arbitrary b is added exactly
+    zero = torch.zeros(4 * nf, dtype=torch.float32, device=dev())
+    xt1, r0 = new(), new()
+    L.dnnmg_prolong_residual_b(box, ns, xcg, zero, xt1, r0)
+    braw = to_gpu(f32(rng.standard_normal(4 * nf)))
+    xt2, rb = new(), new()
+    L.dnnmg_prolong_residual_b(box, ns, xcg, braw, xt2, rb)
+    torch.cuda.synchronize()
+    assert torch.equal(xt0, xt1) and torch.equal(xt0, xt2)
+    r0n, rbn, bn = (t.cpu().numpy().reshape(4, -1) for t in (r0, rb, braw))
+    expect = (bn + r0n).astype(np.float32)
+    differ = rbn != expect
+    # only Dirichlet velocity rows, which are 0 whatever b is
+    assert not differ[3].any()
+    assert np.all((r0n[:3][differ[:3]] == 0) & (rbn[:3][differ[:3]] == 0))
+    for forcing in (None, fm):
+        fg = None if forcing is None else to_gpu(forcing.ravel())
+        b = new()
+        L.dnnmg_rhs(box, ns, vpg, b, fmid=fg)
+        xt3, r = new(), new()
+        L.dnnmg_prolong_residual_b(box, ns, xcg, b, xt3, r)
+        torch.cuda.synchronize()
+        ref = orc.residual(box, ns, xt3.cpu().numpy().reshape(4, -1).astype(np.float64), vp.astype(np.float64),
+                           None if forcing is None else forcing.astype(np.float64))
+        e = rel_l2(r.cpu().numpy().reshape(4, -1), ref)
+        say(f"  forcing={forcing is not None} rel-L2 {e:.2e}")
+        assert e <= 1e-5
+    with pytest.raises(L.DnnmgError):
+        L.dnnmg_prolong_residual_b(box, ns, xcg, rb, xt2, rb)
+
+
 def test_residual_forcing_and_lps_weights(L, orc):
     box = BOXES["mixed"]
     say("residual forcing + strong LPS")

@@ -75,6 +75,38 @@ def test_graph_replay_matches_eager(stepper):
         assert np.array_equal(st.xcorr.cpu().numpy().reshape(4, -1)[:3], eager["vcorr"].astype(np.float32))
 
 
+def test_carried_rhs_graph_and_vprev_form(stepper):
+    """A step that carries the right-hand side (r = b - A(x~), b from the
+    previous step) matches the step built from v_prev up to FP32 rounding,
+    and its graph replays match the eager step when b is reset in between."""
+    w = syn.cfg2()
+    say("carried rhs cfg2")
+    inp = syn.step_inputs(w, seed=3)
+    params = syn.mlp_params(165, w.hidden, 81, seed=3)
+    a = stepper.CorrectionStep(w.box, w.ns, params, dtype="fp32", carry_rhs=True)
+    b = stepper.CorrectionStep(w.box, w.ns, params, dtype="fp32", carry_rhs=False)
+    oa, ob = a.run_numpy(inp.xc, inp.vprev), b.run_numpy(inp.xc, inp.vprev)
+    assert np.array_equal(oa["xt"], ob["xt"])
+    for key in ("r", "d", "b", "bc"):
+        e = rel_l2(oa[key], ob[key])
+        say(f"  {key} rel-L2 {e:.2e}")
+        assert e <= 1e-5, key
+    st = stepper.CorrectionStep(w.box, w.ns, params, dtype="bf16")
+    assert st.carry_rhs
+    eager = st.run_numpy(inp.xc, inp.vprev)
+    st.load(inp.xc, inp.vprev)
+    b0 = st.b.clone()
+    st.capture()
+    for rep in range(3):
+        st.b.copy_(b0)
+        st.bc.zero_()
+        torch.cuda.synchronize()
+        st.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(st.bc.cpu().numpy().reshape(4, -1), eager["bc"]), rep
+        assert np.array_equal(st.r.cpu().numpy().reshape(4, -1), eager["r"].astype(np.float32)), rep
+
+
 @pytest.mark.parametrize("mode", ["never", "always", "nan_weights", "huge_weights"])
 def test_indicator_fallback(stepper, orc, mode):
     """Residual-indicator fallback forced from the host: theta = inf (never),
