@@ -226,6 +226,9 @@ struct ResTile {
     static constexpr int VX = TX + 2, VY = TY + 2, VZ = TZ + 2, VN = VX * VY * VZ;
     static constexpr int NPX = TX / 2, NPY = TY / 2, NPZ = TZ / 2, NP = NPX * NPY * NPZ;
     static constexpr int NT = 768; // one thread per cell (765 cells)
+    // the right-hand side and the residual against a given one fit in 85
+    // registers: two workgroups (six waves per SIMD) share a compute unit
+    static constexpr int WAVES_PER_SIMD = MODE == MODE_RHS || MODE == MODE_PRESB ? 6 : 3;
     static constexpr int NF_STAGE = MODE != MODE_RHS ? 4 : 0; // x, p on the wide range
     static constexpr int NF_V = MODE == MODE_PRESB ? 0 : 3;   // vp (res) or v (rhs)
     static constexpr int NACC = MODE != MODE_RHS ? 4 : 3;
@@ -776,7 +779,7 @@ __device__ __forceinline__ void tile_of(int64_t t, const int G[3], const int F[3
 }
 
 template <int MODE>
-__global__ void __launch_bounds__(ResTile<MODE>::NT)
+__global__ void __launch_bounds__(ResTile<MODE>::NT, ResTile<MODE>::WAVES_PER_SIMD)
     k_residual(Mesh m, ResParams P, const float *__restrict__ x, const float *__restrict__ vp,
                const float *__restrict__ fmid, float *__restrict__ out, float *__restrict__ aux,
                int *__restrict__ tflag, const int *__restrict__ flag, const double *__restrict__ xc,
@@ -816,7 +819,7 @@ static unsigned tile_blocks(const Mesh &m) {
 // iterate in the batch layout (the right-hand side reads its velocity
 // part), vp has 3 components, out 4; aux holds 32 floats per patch.
 template <int MODE>
-__global__ void __launch_bounds__(ResTile<MODE>::NT)
+__global__ void __launch_bounds__(ResTile<MODE>::NT, ResTile<MODE>::WAVES_PER_SIMD)
     k_residual_batch(const BoxDesc *__restrict__ D, int nbox, int64_t nfull, int64_t npart,
                      const float *__restrict__ x, const float *__restrict__ vp, float *__restrict__ out,
                      float *__restrict__ aux, int *__restrict__ tflag, const double *__restrict__ xc,
