@@ -129,6 +129,16 @@ size_t dnnmg_residual_workspace(const dnnmg_box *box);
 int dnnmg_residual(const dnnmg_box *box, const dnnmg_ns *ns, const float *x, const float *vprev,
                    const float *fmid, float *r, void *ws, size_t ws_bytes, void *stream);
 
+/* The same residual against a given right-hand side (Algorithm 1: the fine
+ * Rhs of the previous step): r = b - A(x), A holding the terms of eq.
+ * (4cranknicholson3) and the LPS terms of eq. (disc:ns) that depend on the
+ * iterate x (see dnnmg_prolong_residual_b).  With b = dnnmg_rhs(vprev, fmid)
+ * it equals dnnmg_residual up to FP32 rounding.
+ *   x FP32 [4][n_fine]; b FP32 [4][n_fine]; r FP32 [4][n_fine] output (r == b
+ *   is DNNMG_ERR_ARG); ws as for dnnmg_residual. */
+int dnnmg_residual_b(const dnnmg_box *box, const dnnmg_ns *ns, const float *x, const float *b, float *r, void *ws,
+                     size_t ws_bytes, void *stream);
+
 /* Prolongation and fine residual fused (Algorithm 1): xt = P xc exactly as
  * dnnmg_prolong computes it (ncomp 4), and r = F - A(xt) as dnnmg_residual
  * computes it, bit for bit, in one pass.  Since xt is patchwise Q1 (the Q1
@@ -300,6 +310,13 @@ size_t dnnmg_fallback_workspace(const dnnmg_box *box);
 int dnnmg_fallback(const dnnmg_box *box, const dnnmg_ns *ns, const float *xt, const float *vprev,
                    const float *fmid, const double *norms, double theta, int sweeps, float omega,
                    float *xcorr, int *flag_out, void *ws, size_t ws_bytes, void *stream);
+
+/* The fallback against a given right-hand side: as dnnmg_fallback with every
+ * residual of the sweeps computed as dnnmg_residual_b(x, b) (b: FP32
+ * [4][n_fine], the Rhs of the previous step; must not alias x_corr). */
+int dnnmg_fallback_b(const dnnmg_box *box, const dnnmg_ns *ns, const float *xt, const float *b, const double *norms,
+                     double theta, int sweeps, float omega, float *xcorr, int *flag_out, void *ws, size_t ws_bytes,
+                     void *stream);
 
 /* Operators Q and N fused (eqs. defQ and NN): the network's first-layer
  * inputs are built in on-chip memory from x~ (FP32 [4][n_fine]) and r (FP32

@@ -85,6 +85,9 @@ _sig("dnnmg_patch_dofmap", [_P(Box), c_vp, c_vp, c_vp])
 _sig("dnnmg_prolong", [_P(Box), ctypes.c_int, c_vp, c_vp, c_vp])
 _sig("dnnmg_residual_workspace", [_P(Box)], c_sz)
 _sig("dnnmg_residual", [_P(Box), _P(NS), c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp])
+_sig("dnnmg_residual_b", [_P(Box), _P(NS), c_vp, c_vp, c_vp, c_vp, c_sz, c_vp])
+_sig("dnnmg_fallback_b", [_P(Box), _P(NS), c_vp, c_vp, c_vp, ctypes.c_double, ctypes.c_int, c_f, c_vp, c_vp, c_vp,
+                          c_sz, c_vp])
 _sig("dnnmg_rhs", [_P(Box), _P(NS), c_vp, c_vp, c_vp, c_vp])
 _sig("dnnmg_prolong_residual", [_P(Box), _P(NS), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp])
 _sig("dnnmg_prolong_residual_b", [_P(Box), _P(NS), c_vp, c_vp, c_vp, c_vp, c_vp])
@@ -127,6 +130,7 @@ EXPORTS = [
     "dnnmg_residual_workspace", "dnnmg_residual", "dnnmg_rhs", "dnnmg_restrict",
     "dnnmg_patch_gather", "dnnmg_mlp_packed_bytes", "dnnmg_mlp_pack", "dnnmg_patch_forward",
     "dnnmg_patch_forward_tiles", "dnnmg_prolong_residual", "dnnmg_prolong_residual_b",
+    "dnnmg_residual_b", "dnnmg_fallback_b",
     "dnnmg_patch_saved_bytes", "dnnmg_scatter_avg", "dnnmg_scatter_avg_form", "dnnmg_norm2_workspace", "dnnmg_norm2_f64",
     "dnnmg_mse_grad", "dnnmg_patch_backward_workspace", "dnnmg_patch_backward", "dnnmg_adamw_step",
     "dnnmg_vanka_workspace", "dnnmg_vanka_sweeps", "dnnmg_fallback_workspace", "dnnmg_fallback",
@@ -197,6 +201,14 @@ def dnnmg_prolong(box, xc, xf, ncomp=4, stream=None):
 
 def residual_workspace_bytes(box) -> int:
     return int(_lib.dnnmg_residual_workspace(ctypes.byref(Box.of(box))))
+
+
+def dnnmg_residual_b(box, ns, x, b, r, ws, stream=None):
+    bx = Box.of(box)
+    nf, _, _ = box_sizes(bx)
+    _check(_lib.dnnmg_residual_b(ctypes.byref(bx), ctypes.byref(NS.of(ns)), _ptr(x, torch.float32, 4 * nf, "x"),
+                                 _ptr(b, torch.float32, 4 * nf, "b"), _ptr(r, torch.float32, 4 * nf, "r"),
+                                 _ptr(ws, None, None, "ws"), ws.numel() * ws.element_size(), _stream(stream)))
 
 
 def dnnmg_residual(box, ns, x, vprev, r, ws, fmid=None, stream=None):
@@ -377,6 +389,17 @@ def dnnmg_vanka_sweeps(box, ns, x, vprev, ws, sweeps=1, omega=1.0, coupled=False
 
 def fallback_workspace_bytes(box) -> int:
     return int(_lib.dnnmg_fallback_workspace(ctypes.byref(Box.of(box))))
+
+
+def dnnmg_fallback_b(box, ns, xt, b, norms, xcorr, ws, theta=1.0, sweeps=4, omega=1.0, flag_out=None,
+                     stream=None):
+    bx = Box.of(box)
+    nf, _, _ = box_sizes(bx)
+    _check(_lib.dnnmg_fallback_b(ctypes.byref(bx), ctypes.byref(NS.of(ns)), _ptr(xt, torch.float32, 4 * nf, "xt"),
+                                 _ptr(b, torch.float32, 4 * nf, "b"), _ptr(norms, torch.float64, 2, "norms"),
+                                 float(theta), int(sweeps), float(omega), _ptr(xcorr, torch.float32, 4 * nf, "xcorr"),
+                                 _ptr(flag_out, torch.int32, 1, "flag_out"), _ptr(ws, None, None, "ws"),
+                                 ws.numel() * ws.element_size(), _stream(stream)))
 
 
 def dnnmg_fallback(box, ns, xt, vprev, norms, xcorr, ws, theta=1.0, sweeps=4, omega=1.0, flag_out=None,

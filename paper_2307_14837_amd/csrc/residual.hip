@@ -212,7 +212,12 @@ constexpr int MODE_PRES = 2;
 // corrected velocity): r = b - A(x~); the tile evaluates only the terms of
 // the new iterate and adds b at its owned nodes
 constexpr int MODE_PRESB = 3;
+// the general residual (any iterate, LPS terms where they do not vanish)
+// against a given right-hand side: r = b - A(x)
+constexpr int MODE_RESB = 4;
 __host__ __device__ constexpr bool mode_prolongs(int mode) { return mode == MODE_PRES || mode == MODE_PRESB; }
+__host__ __device__ constexpr bool mode_general(int mode) { return mode == MODE_RES || mode == MODE_RESB; }
+__host__ __device__ constexpr bool mode_against_b(int mode) { return mode == MODE_PRESB || mode == MODE_RESB; }
 __host__ __device__ constexpr bool mode_has_vp(int mode) { return mode == MODE_RES || mode == MODE_PRES; }
 
 template <int MODE>
@@ -229,8 +234,9 @@ struct ResTile {
     // the right-hand side and the residual against a given one fit in 85
     // registers: two workgroups (six waves per SIMD) share a compute unit
     static constexpr int WAVES_PER_SIMD = MODE == MODE_RHS || MODE == MODE_PRESB ? 6 : 3;
+
     static constexpr int NF_STAGE = MODE != MODE_RHS ? 4 : 0; // x, p on the wide range
-    static constexpr int NF_V = MODE == MODE_PRESB ? 0 : 3;   // vp (res) or v (rhs)
+    static constexpr int NF_V = mode_against_b(MODE) ? 0 : 3; // vp (res) or v (rhs)
     static constexpr int NACC = MODE != MODE_RHS ? 4 : 3;
     // coarse nodes under the staged range (prolongating tiles)
     static constexpr int CX = TX / 2 + 2, CY = TY / 2 + 2, CZ = TZ / 2 + 2, CN = CX * CY * CZ;
@@ -253,9 +259,9 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
     using T = ResTile<MODE>;
     __shared__ float sX[T::NF_STAGE > 0 ? T::NF_STAGE * T::SN : 1];
     __shared__ float sV[T::NF_V > 0 ? T::NF_V * T::VN : 1];
-    __shared__ float sF[MODE == MODE_PRESB ? 1 : 3 * T::VN]; // forcing, when given
+    __shared__ float sF[mode_against_b(MODE) ? 1 : 3 * T::VN]; // forcing, when given
     __shared__ float sCell[8 * T::NCELL]; // [vertex j][cell]
-    __shared__ float sCor[MODE == MODE_RES ? 8 * T::NCELL : 1];
+    __shared__ float sCor[mode_general(MODE) ? 8 * T::NCELL : 1];
     __shared__ float sC[mode_prolongs(MODE) ? 4 * T::CN : 1]; // coarse iterate, rounded to FP32
 
     const int x0 = bx * T::TX, y0 = by * T::TY, z0 = bz * T::TZ;
@@ -318,7 +324,7 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
             }
         }
     }
-    if constexpr (MODE == MODE_RES) {
+    if constexpr (mode_general(MODE)) {
         constexpr int IT = (T::SN + T::NT - 1) / T::NT;
         float tmp[IT][4];
 #pragma unroll
@@ -360,13 +366,13 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
                 for (int f = 0; f < 3; ++f) dst[f * T::VN + s] = tmp[it][f];
         }
     };
-    if constexpr (MODE != MODE_PRESB) {
+    if constexpr (!mode_against_b(MODE)) {
         stage_v(MODE != MODE_RHS ? vp : x, sV);
         if (fmid) stage_v(fmid, sF);
     }
     for (int s = tid; s < 8 * T::NCELL; s += T::NT) {
         sCell[s] = 0.0f;
-        if constexpr (MODE == MODE_RES) sCor[s] = 0.0f;
+        if constexpr (mode_general(MODE)) sCor[s] = 0.0f;
     }
     __syncthreads();
 
@@ -475,7 +481,7 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
         // patch interpolant.  When the vertex values and the interpolant
         // computed here agree bit for bit every LPS contribution of the cell
         // is exactly zero; the other cells get them in a second pass.
-        if (MODE == MODE_RES && live) {
+        if (mode_general(MODE) && live) {
 #pragma unroll
             for (int d = 0; d < 4; ++d) {
                 float cv[8], pw[8];
@@ -579,15 +585,15 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
     }
 
     // ---- LPS terms of the cells that need them, one equation at a time ----
-    float corner[MODE == MODE_RES ? 4 : 1] = {};
+    float corner[mode_general(MODE) ? 4 : 1] = {};
     // owned patch P = tid / 8, corner j = tid % 8: its cells, in offset order
-    const bool pown = MODE == MODE_RES && tid < 8 * T::NP;
+    const bool pown = mode_general(MODE) && tid < 8 * T::NP;
     const int pslot = tid >> 3, pj = tid & 7;
     const int ppx = pslot % T::NPX, ppy = (pslot / T::NPX) % T::NPY, ppz = pslot / (T::NPX * T::NPY);
     // cell of offset o = ox + 2 oy + 4 oz in patch (ppx, ppy, ppz): ex = 2 ppx + 1 + ox
     const int pcb = (2 * ppx + 1) + T::EX * ((2 * ppy + 1) + T::EY * (2 * ppz + 1));
     bool any_lps = false;
-    if constexpr (MODE == MODE_RES) {
+    if constexpr (mode_general(MODE)) {
         any_lps = __syncthreads_or(need);
         if (any_lps) {
             for (int a = 0; a < 4; ++a) {
@@ -709,8 +715,8 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
         if (gi < m.nf[0] && gj < m.nf[1] && gk < m.nf[2]) {
             int64_t g = gi + (int64_t)m.nf[0] * (gj + (int64_t)m.nf[1] * gk);
             bool dir = on_dirichlet(m, gi, gj, gk);
-            if constexpr (MODE == MODE_PRESB) {
-                // r = b - A(x~): vp carries b [4][n_fine]
+            if constexpr (mode_against_b(MODE)) {
+                // r = b - A(x): vp carries b [4][n_fine]
 #pragma unroll
                 for (int f = 0; f < 3; ++f) out[f * nfn + g] = dir ? 0.0f : vp[f * nfn + g] + res[f];
                 out[3 * nfn + g] = vp[3 * nfn + g] + res[3];
@@ -727,7 +733,7 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
             }
         }
     }
-    if constexpr (MODE == MODE_RES) {
+    if constexpr (mode_general(MODE)) {
         // the tile's flag says whether its patches' corner sums were written
         if (tid == 0) *tflag = any_lps ? 1 : 0;
         if (pown && any_lps) {
@@ -801,7 +807,7 @@ __global__ void __launch_bounds__(ResTile<MODE>::NT, ResTile<MODE>::WAVES_PER_SI
     int c[3];
     tile_of(t, G, F, c);
     const int tl = c[0] + G[0] * (c[1] + G[1] * c[2]);
-    residual_tile<MODE>(m, P, c[0], c[1], c[2], x, vp, fmid, out, aux, MODE == MODE_RES ? tflag + tl : nullptr, xc,
+    residual_tile<MODE>(m, P, c[0], c[1], c[2], x, vp, fmid, out, aux, mode_general(MODE) ? tflag + tl : nullptr, xc,
                         xt_out);
 }
 
@@ -963,6 +969,17 @@ int residual_launch(const Mesh &m, const dnnmg_ns *ns, const float *x, const flo
     return hip_check(hipGetLastError(), "dnnmg_residual launch");
 }
 
+int residual_launch_b(const Mesh &m, const dnnmg_ns *ns, const float *x, const float *b, float *r, float *aux,
+                      const int *flag, hipStream_t s) {
+    ResParams P = make_params(m, ns);
+    dim3 g = res_grid<MODE_RES>(m);
+    int *tflag = (int *)((char *)aux + up256(sizeof(float) * 32 * m.n_patches));
+    k_residual<MODE_RESB><<<tile_blocks<MODE_RESB>(m), ResTile<MODE_RESB>::NT, 0, s>>>(m, P, x, b, nullptr, r, aux,
+                                                                                    tflag, flag, nullptr, nullptr);
+    k_lps_corners<<<blocks_for(m.n_coarse, 256), 256, 0, s>>>(m, aux, tflag, g.x, g.y, g.z, r, flag);
+    return hip_check(hipGetLastError(), "dnnmg_residual_b launch");
+}
+
 // Tile grid of a box (rt) and its box of full tiles (rf).
 void residual_tiles(const Mesh &m, int rt[3], int rf[3]) {
     using T = ResTile<MODE_RES>;
@@ -1015,6 +1032,20 @@ extern "C" int dnnmg_residual(const dnnmg_box *box, const dnnmg_ns *ns, const fl
     if (ws_bytes < lps_ws_bytes(m))
         return fail(DNNMG_ERR_SHAPE, "dnnmg_residual: workspace %zu < %zu bytes", ws_bytes, lps_ws_bytes(m));
     return residual_launch(m, ns, x, vprev, fmid, r, (float *)ws, nullptr, (hipStream_t)stream);
+}
+
+extern "C" int dnnmg_residual_b(const dnnmg_box *box, const dnnmg_ns *ns, const float *x, const float *b, float *r,
+                                void *ws, size_t ws_bytes, void *stream) {
+    Mesh m;
+    int rc = make_mesh(box, &m);
+    if (rc) return rc;
+    if ((rc = check_ns(ns))) return rc;
+    if (!x || !b || !r || !ws) return fail(DNNMG_ERR_ARG, "dnnmg_residual_b: NULL pointer");
+    if (b == r) return fail(DNNMG_ERR_ARG, "dnnmg_residual_b: b and r must not alias");
+    if (!aligned16(ws)) return fail(DNNMG_ERR_ARG, "dnnmg_residual_b: workspace not 16-byte aligned");
+    if (ws_bytes < lps_ws_bytes(m))
+        return fail(DNNMG_ERR_SHAPE, "dnnmg_residual_b: workspace %zu < %zu bytes", ws_bytes, lps_ws_bytes(m));
+    return residual_launch_b(m, ns, x, b, r, (float *)ws, nullptr, (hipStream_t)stream);
 }
 
 extern "C" int dnnmg_rhs(const dnnmg_box *box, const dnnmg_ns *ns, const float *v, const float *fmid,

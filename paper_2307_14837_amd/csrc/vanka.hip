@@ -433,11 +433,12 @@ static void make_tables(const Mesh &m, const dnnmg_ns *ns, VankaTables &T, Vanka
 }
 
 // Entry used by the public calls: `sweeps` sweeps on x (in place), each
-// preceded by a residual of the current iterate.  ws layout: r (4 n_fine
+// preceded by a residual of the current iterate (from vprev and fmid, or,
+// when b is given, against that right-hand side).  ws layout: r (4 n_fine
 // floats), residual workspace, D (n_patches * 108 floats).
 int vanka_sweeps(const dnnmg_box *box, const dnnmg_ns *ns, float *x, const float *vprev,
                  const float *fmid, int sweeps, float omega, int coupled, char *ws, const int *flag,
-                 hipStream_t s);
+                 hipStream_t s, const float *b = nullptr);
 
 } // namespace dnnmg
 
@@ -447,6 +448,8 @@ using namespace dnnmg;
 namespace dnnmg {
 int residual_launch(const Mesh &m, const dnnmg_ns *ns, const float *x, const float *vprev,
                     const float *fmid, float *r, float *aux, const int *flag, hipStream_t s);
+int residual_launch_b(const Mesh &m, const dnnmg_ns *ns, const float *x, const float *b, float *r, float *aux,
+                      const int *flag, hipStream_t s);
 size_t lps_ws_bytes(const Mesh &m);
 size_t vanka_ws_bytes(const Mesh &m) {
     auto up = [](size_t b) { return (b + 255) / 256 * 256; };
@@ -455,7 +458,7 @@ size_t vanka_ws_bytes(const Mesh &m) {
 
 int vanka_sweeps(const dnnmg_box *box, const dnnmg_ns *ns, float *x, const float *vprev,
                  const float *fmid, int sweeps, float omega, int coupled, char *ws, const int *flag,
-                 hipStream_t s) {
+                 hipStream_t s, const float *b) {
     Mesh m;
     int rc = make_mesh(box, &m);
     if (rc) return rc;
@@ -467,7 +470,9 @@ int vanka_sweeps(const dnnmg_box *box, const dnnmg_ns *ns, float *x, const float
     float *aux = (float *)(ws + up(sizeof(float) * 4 * m.n_fine));
     float *D = (float *)(ws + up(sizeof(float) * 4 * m.n_fine) + lps_ws_bytes(m));
     for (int it = 0; it < sweeps; ++it) {
-        if ((rc = residual_launch(m, ns, x, vprev, fmid, r, aux, flag, s))) return rc;
+        if ((rc = b ? residual_launch_b(m, ns, x, b, r, aux, flag, s)
+                    : residual_launch(m, ns, x, vprev, fmid, r, aux, flag, s)))
+            return rc;
         if (coupled)
             k_vanka_local<true><<<(unsigned)m.n_patches, 64, 0, s>>>(m, T, P, x, r, D, flag);
         else
@@ -521,6 +526,29 @@ extern "C" int dnnmg_fallback(const dnnmg_box *box, const dnnmg_ns *ns, const fl
     k_copy_pred<<<blocks_for(4 * m.n_fine, 256), 256, 0, s>>>(4 * m.n_fine, xt, xcorr, flag);
     if ((rc = hip_check(hipGetLastError(), "dnnmg_fallback launch"))) return rc;
     return vanka_sweeps(box, ns, xcorr, vprev, fmid, sweeps, omega, 0, w, flag, s);
+}
+
+extern "C" int dnnmg_fallback_b(const dnnmg_box *box, const dnnmg_ns *ns, const float *xt, const float *b,
+                                const double *norms, double theta, int sweeps, float omega, float *xcorr,
+                                int *flag_out, void *ws, size_t ws_bytes, void *stream) {
+    Mesh m;
+    int rc = make_mesh(box, &m);
+    if (rc) return rc;
+    if (!ns || !(ns->dt > 0.0)) return fail(DNNMG_ERR_ARG, "dnnmg_fallback_b: bad ns");
+    if (!xt || !b || !norms || !xcorr || !ws) return fail(DNNMG_ERR_ARG, "dnnmg_fallback_b: NULL pointer");
+    if (b == xcorr) return fail(DNNMG_ERR_ARG, "dnnmg_fallback_b: b and xcorr must not alias");
+    if (sweeps < 0 || !(omega > 0.0f) || !(theta >= 0.0))
+        return fail(DNNMG_ERR_ARG, "dnnmg_fallback_b: need sweeps >= 0, omega > 0, theta >= 0");
+    if (ws_bytes < dnnmg_fallback_workspace(box))
+        return fail(DNNMG_ERR_SHAPE, "dnnmg_fallback_b: workspace %zu < %zu bytes", ws_bytes,
+                    dnnmg_fallback_workspace(box));
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)ws;
+    int *flag = (int *)(w + vanka_ws_bytes(m));
+    k_indicator_flag<<<1, 64, 0, s>>>(norms, theta * theta, flag, flag_out);
+    k_copy_pred<<<blocks_for(4 * m.n_fine, 256), 256, 0, s>>>(4 * m.n_fine, xt, xcorr, flag);
+    if ((rc = hip_check(hipGetLastError(), "dnnmg_fallback_b launch"))) return rc;
+    return vanka_sweeps(box, ns, xcorr, nullptr, nullptr, sweeps, omega, 0, w, flag, s, b);
 }
 
 extern "C" size_t dnnmg_vanka_workspace(const dnnmg_box *box) {

@@ -24,11 +24,11 @@ class CorrectionStep:
 
     params: [W1, b1, W2, b2, W3, b3] (numpy or torch, W as [fan_in][fan_out]).
     shift / inv_scale: per-feature standardisation of the 165 inputs (None =
-    identity).  carry_rhs (default: without the indicator): the step's
-    residual is r = b - A(x~) with b the right-hand side the previous step
-    computed (load() computes the first one from vprev), so the terms of the
-    previous velocity are evaluated once per step, not twice; the indicator
-    path keeps vprev, which its residual and fallback need.  FP8 networks quantise W2 with amax / 448 and the tanh outputs
+    identity).  carry_rhs (default): the step's residuals are r = b - A(x)
+    with b the right-hand side the previous step computed (load() computes
+    the first one from vprev), so the terms of the previous velocity are
+    evaluated once per step, not again in every residual; carry_rhs=False
+    builds them from vprev in each residual instead.  FP8 networks quantise W2 with amax / 448 and the tanh outputs
     entering layer 2 with the fixed scale 1 / 448.
     """
 
@@ -43,9 +43,7 @@ class CorrectionStep:
         self.indicator = indicator
         # fused: the gather runs inside the network kernel (no X round trip)
         self.fused = bool(fused)
-        self.carry_rhs = (not indicator) if carry_rhs is None else bool(carry_rhs)
-        if self.carry_rhs and indicator:
-            raise ValueError("carry_rhs: the indicator path needs vprev")
+        self.carry_rhs = True if carry_rhs is None else bool(carry_rhs)
         f32 = dict(dtype=torch.float32, device=self.dev)
         f64 = dict(dtype=torch.float64, device=self.dev)
         self.xc = torch.zeros(4 * self.nc, **f64)
@@ -119,12 +117,20 @@ class CorrectionStep:
         if self.indicator:
             # eta = ||r(x_corr)|| / ||r(x~)||; above theta the plain fine
             # correction replaces the network's (decided on the device)
-            L.dnnmg_residual(box, ns, self.xcorr, self.vprev, self.r2, self.ws_res, stream=stream)
+            if self.carry_rhs:
+                L.dnnmg_residual_b(box, ns, self.xcorr, self.b, self.r2, self.ws_res, stream=stream)
+            else:
+                L.dnnmg_residual(box, ns, self.xcorr, self.vprev, self.r2, self.ws_res, stream=stream)
             L.dnnmg_norm2_f64(self.r, self.norms[0:1], self.ws_norm, stream=stream)
             L.dnnmg_norm2_f64(self.r2, self.norms[1:2], self.ws_norm, stream=stream)
-            L.dnnmg_fallback(box, ns, self.xt, self.vprev, self.norms, self.xcorr, self.ws_fb,
-                             theta=self.theta, sweeps=self.fallback_sweeps, flag_out=self.fell_back,
-                             stream=stream)
+            if self.carry_rhs:
+                L.dnnmg_fallback_b(box, ns, self.xt, self.b, self.norms, self.xcorr, self.ws_fb,
+                                   theta=self.theta, sweeps=self.fallback_sweeps, flag_out=self.fell_back,
+                                   stream=stream)
+            else:
+                L.dnnmg_fallback(box, ns, self.xt, self.vprev, self.norms, self.xcorr, self.ws_fb,
+                                 theta=self.theta, sweeps=self.fallback_sweeps, flag_out=self.fell_back,
+                                 stream=stream)
         L.dnnmg_rhs(box, ns, self.xcorr, self.b, stream=stream)
         L.dnnmg_restrict(box, self.b, self.bc, stream=stream)
 

@@ -187,6 +187,46 @@ def test_prolong_residual_b(L, orc, name):
         L.dnnmg_prolong_residual_b(box, ns, xcg, rb, xt2, rb)
 
 
+@pytest.mark.parametrize("name", ["cfg1", "chan_mid", "mixed"])
+def test_residual_b(L, orc, name):
+    """General residual against a given right-hand side, on a field with
+    active LPS terms: b is added exactly (r(b) == fl(b + r(0)) outside
+    Dirichlet velocity rows), and with b = Rhs(v_prev) it matches the oracle's
+    Crank-Nicolson residual."""
+    box = BOXES[name]
+    say("residual against b", name)
+    ns = syn.NSParams(0.05, 0.02, 0.5, 0.8)
+    x, vp = fields(box, 6, False, orc)
+    nf = box.n_fine
+    xg, vpg = to_gpu(x.ravel()), to_gpu(vp.ravel())
+    ws = torch.empty(L.residual_workspace_bytes(box), dtype=torch.uint8, device=dev())
+    new = lambda: torch.full((4 * nf,), float("nan"), dtype=torch.float32, device=dev())
+    r0, rb = new(), new()
+    L.dnnmg_residual_b(box, ns, xg, torch.zeros(4 * nf, dtype=torch.float32, device=dev()), r0, ws)
+    braw = to_gpu(f32(np.random.default_rng(8).standard_normal(4 * nf)))
+    L.dnnmg_residual_b(box, ns, xg, braw, rb, ws)
+    torch.cuda.synchronize()
+    r0n, rbn, bn = (t.cpu().numpy().reshape(4, -1) for t in (r0, rb, braw))
+    # b enters before the LPS corner parts are added (a second rounding):
+    # equal to b + r(0) within two roundings, Dirichlet velocity rows 0
+    dirr = (r0n[:3] == 0) & (rbn[:3] == 0)
+    ok = np.abs(rbn - (bn + r0n)) <= 2 * 2.0 ** -24 * (np.abs(bn) + 2 * np.abs(r0n))
+    ok[:3] |= dirr
+    assert ok.all()
+    b = new()
+    L.dnnmg_rhs(box, ns, vpg, b)
+    r = new()
+    L.dnnmg_residual_b(box, ns, xg, b, r, ws)
+    torch.cuda.synchronize()
+    ref = orc.residual(box, ns, x.astype(np.float64), vp.astype(np.float64))
+    got = r.cpu().numpy().reshape(4, -1)
+    e = rel_l2(got, ref)
+    say(f"  rel-L2 {e:.2e}")
+    assert e <= 1e-5
+    for f in range(4):
+        assert rel_l2(got[f], ref[f]) <= 1e-5, f
+
+
 def test_residual_forcing_and_lps_weights(L, orc):
     box = BOXES["mixed"]
     say("residual forcing + strong LPS")

@@ -59,3 +59,35 @@ def test_vanka_sweeps_match_oracle(L, orc, name, sweeps, coupled):
         r1 = np.linalg.norm(orc.residual(box, ns, got, vp.astype(np.float64))[:3])
         say(f"  momentum residual {r0:.3e} -> {r1:.3e}")
         assert r1 < r0 / 3.0 ** sweeps
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fallback_against_rhs_matches_oracle(L, orc, name):
+    """The fallback whose sweep residuals are r = b - A(x), b = Rhs(v_prev):
+    taken (theta = 0), it gives the oracle's pressure-held sweeps from x~; not
+    taken (theta = inf), x_corr is left as it is."""
+    box, ns = CASES[name]
+    say("fallback against b", name)
+    x, vp = inputs(box, orc, 5)
+    nf = box.n_fine
+    xt = to_gpu(x.ravel())
+    b = torch.empty(4 * nf, dtype=torch.float32, device=dev())
+    L.dnnmg_rhs(box, ns, to_gpu(vp.ravel()), b)
+    ws = torch.empty(L.fallback_workspace_bytes(box), dtype=torch.uint8, device=dev())
+    norms = torch.tensor([1.0, 1.0], dtype=torch.float64, device=dev())
+    flag = torch.zeros(1, dtype=torch.int32, device=dev())
+    keep = to_gpu(f32(np.full(4 * nf, 7.0)))
+    L.dnnmg_fallback_b(box, ns, xt, b, norms, keep, ws, theta=float("inf"), sweeps=2, flag_out=flag)
+    torch.cuda.synchronize()
+    assert flag.item() == 0 and torch.all(keep == 7.0)
+    xcorr = torch.empty(4 * nf, dtype=torch.float32, device=dev())
+    L.dnnmg_fallback_b(box, ns, xt, b, norms, xcorr, ws, theta=0.0, sweeps=2, flag_out=flag)
+    torch.cuda.synchronize()
+    assert flag.item() == 1
+    got = xcorr.cpu().numpy().reshape(4, -1).astype(np.float64)
+    ref = x.astype(np.float64)
+    for _ in range(2):
+        ref = orc.vanka_sweep(box, ns, ref, vp.astype(np.float64), omega=1.0, coupled=False)
+    e = rel_l2(got - x, ref - x)
+    say(f"  correction rel-L2 {e:.2e}")
+    assert e <= 1e-4
