@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--no-variants", action="store_true", help="only the default workload")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="run only the dominant kernel and a plain copy a few times (for rocprofv3 --pmc)")
+    ap.add_argument("--scale-only", action="store_true",
+                    help="run only the per-kernel measurements on the large channel (for rocprofv3)")
     return ap.parse_args()
 
 
@@ -350,6 +352,9 @@ def main():
     args = parse()
     if args.pmc_probe:
         pmc_probe()
+        return
+    if args.scale_only:
+        print(json.dumps({"kernels_at_scale": kernels_at_scale()}), flush=True)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
