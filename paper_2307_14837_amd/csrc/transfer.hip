@@ -280,6 +280,7 @@ __global__ void __launch_bounds__(256) k_scatter_batch(const BoxDesc *__restrict
 // tile is a one-node sliver.  Patch slot s along an axis holds patch
 // b + s, b = first owned node / 2 - 1 (wrapped on a periodic axis).
 constexpr int ST_X = 16, ST_Y = 8;
+constexpr int SCATTER_TZ = 2, SCATTER_NT = 256; // the built tile depth and workgroup size
 constexpr int SS_X = ST_X / 2 + 1, SS_Y = ST_Y / 2 + 1;
 constexpr int SS_RUN = 81 * SS_X;                       // floats per run of x slots
 
@@ -362,9 +363,12 @@ __device__ __forceinline__ void scatter_tile(const Mesh &m, int tx, int ty, int 
         for (int c = 0; c < 4; ++c) vb[p][c] = (vbase && q < nn) ? vbase[c * m.n_fine + node[p]] : 0.0f;
     }
     // stage: one run of SS_X consecutive x patches per (y, z) slot; patches
-    // outside the mesh are zero (read only with weight 0)
-    // (a run inside the mesh along x is one contiguous stretch of memory;
-    // the two forms are separate loops so each issues all its loads at once)
+    // outside the mesh are zero (read only with weight 0).  Along x a run is
+    // at most two contiguous stretches of patch rows: elements [e_lo, sp)
+    // at row offset offA + e and, where a periodic run wraps, [sp, e_hi) at
+    // offB + e.  Only a periodic axis of fewer than SS_X patches wraps more
+    // than once; it takes the per-element form.  The two forms are separate
+    // loops so each issues all its loads at once.
     float t[SS_Z * SS_Y][SS_ITER];
     auto run_ok = [&](int r, int64_t &row) {
         const int J = wrap(bJ + r % SS_Y, m.n[1], m.per[1]);
@@ -372,16 +376,33 @@ __device__ __forceinline__ void scatter_tile(const Mesh &m, int tx, int ty, int 
         row = (int64_t)m.n[0] * (J + (int64_t)m.n[1] * K);
         return J >= 0 && J < m.n[1] && K >= 0 && K < m.n[2];
     };
-    if (bI >= 0 && bI + SS_X <= m.n[0]) {
+    const int n0 = m.n[0];
+    int e_lo = 0, e_hi = SS_RUN, sp = SS_RUN;
+    int64_t offA = (int64_t)bI * 81, offB = 0;
+    const bool stretches = !m.per[0] || n0 >= SS_X;
+    if (m.per[0]) {
+        if (bI < 0) {                      // slot 0 is patch n0 - 1
+            sp = 81;
+            offA = (int64_t)(n0 - 1) * 81;
+            offB = -81;
+        } else if (bI + SS_X > n0) {       // slots from n0 - bI on are patches 0, 1, ..
+            sp = (n0 - bI) * 81;
+            offB = -(int64_t)sp;
+        }
+    } else {
+        e_lo = (bI < 0 ? -bI : 0) * 81;
+        e_hi = (n0 - bI < SS_X ? n0 - bI : SS_X) * 81;
+    }
+    if (stretches) {
 #pragma unroll
         for (int r = 0; r < SS_Z * SS_Y; ++r) {
             int64_t row;
             const bool rok = run_ok(r, row);
-            const float *run = Y + (row + bI) * 81;
+            const float *rb = Y + row * 81;
 #pragma unroll
             for (int u = 0; u < SS_ITER; ++u) {
                 const int e = tid + u * ST_NT;
-                t[r][u] = rok && e < SS_RUN ? run[e] : 0.0f;
+                t[r][u] = rok && e >= e_lo && e < e_hi ? rb[(e < sp ? offA : offB) + e] : 0.0f;
             }
         }
     } else {
@@ -487,6 +508,12 @@ __global__ void __launch_bounds__(256) k_norm_final(int nparts, const double *__
     if (threadIdx.x == 0) *out = red[0];
 }
 
+// The tiled form wins once every compute unit has several tiles; on smaller
+// meshes the per-node form (no staging round trip) is faster.
+static bool scatter_prefers_tiles(int64_t n_fine) {
+    return n_fine >= (int64_t)4 * device_cus() * ST_X * ST_Y * SCATTER_TZ;
+}
+
 void restrict_batch_launch(const BoxDesc *D, int nbox, int64_t nblk, const float *bf, double *bc, hipStream_t s) {
     k_restrict_batch<<<(unsigned)nblk, 256, 0, s>>>(D, nbox, bf, bc);
 }
@@ -565,11 +592,8 @@ extern "C" int dnnmg_patch_gather(const dnnmg_box *box, const float *x, const fl
 
 // The tiled form wins once every compute unit has several tiles; on smaller
 // meshes the per-node form (no staging round trip) is faster.
-constexpr int SCATTER_TZ = 2, SCATTER_NT = 256;
 
-static bool scatter_prefers_tiles(const Mesh &m) {
-    return m.n_fine >= (int64_t)4 * device_cus() * ST_X * ST_Y * SCATTER_TZ;
-}
+static bool scatter_prefers_tiles(const Mesh &m) { return scatter_prefers_tiles(m.n_fine); }
 
 extern "C" int dnnmg_scatter_avg_form(const dnnmg_box *box, const float *Y, const float *vbase, float *d, int form,
                                       void *stream) {

@@ -306,6 +306,8 @@ def test_gather_scatter(L, orc, name):
 
 SCATTER_BOXES = dict(BOXES, per_tiny=syn.BoxSpec((2, 2, 2), (1.0, 1.0, 1.0), 7, 0),
                      per_x=syn.BoxSpec((4, 3, 5), (1.0, 0.6, 0.9), 1, syn.Y_LO | syn.Y_HI),
+                     per_wide=syn.BoxSpec((20, 6, 4), (1.0, 0.5, 0.4), 7, 0),
+                     per_x_wide=syn.BoxSpec((18, 5, 3), (1.0, 0.5, 0.4), 1, syn.Z_LO | syn.Z_HI),
                      cfg5=syn.cfg5().box)
 
 
