@@ -23,11 +23,14 @@ template <> __device__ __forceinline__ float ld<uint16_t>(const uint16_t *p, int
     return bf16_to_f32(p[i]);
 }
 
-constexpr int BM = 64, BN = 64, BK = 16;
+constexpr int BM = 64, BN = 64, BK = 32;
+constexpr int STAGE = BM * BK / 256; // elements of each operand a thread stages per K step
 
 // C[M x N] (+= split) = op(A) op(B); op(A)[m][k] = TA ? A[k*lda + m] : A[m*lda + k],
 // op(B)[k][n] = TB ? B[n*ldb + k] : B[k*ldb + n].  EPI: C *= (1 - S[m][n]^2).
 // blockIdx.z = split index over K; C + z*M*N receives that split's partial.
+// The next K step's operands are loaded into registers while the current
+// step's products run (one memory round trip per step, overlapped).
 template <bool TA, bool TB, typename TAe, typename TBe, typename TSe, bool EPI>
 __global__ void __launch_bounds__(256)
     k_gemm(int64_t M, int64_t N, int64_t K, int64_t kchunk, const TAe *__restrict__ A, int64_t lda,
@@ -47,26 +50,37 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
-        // stage A tile (BM x BK) and B tile (BK x BN), 4 elements per thread each
+    float ra[STAGE], rb[STAGE];
+    auto load = [&](int64_t k0) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            int e = tid + 256 * r; // 0..1023
+        for (int r = 0; r < STAGE; ++r) {
+            const int e = tid + 256 * r;
             int mm, kk;
             if (TA) { mm = e % BM; kk = e / BM; } else { kk = e % BK; mm = e / BK; }
             int64_t gm = m0 + mm, gk = k0 + kk;
-            float v = 0.f;
-            if (gm < M && gk < kend) v = TA ? ld(A, gk * lda + gm) : ld(A, gm * lda + gk);
-            As[kk][mm] = v;
+            ra[r] = (gm < M && gk < kend) ? (TA ? ld(A, gk * lda + gm) : ld(A, gm * lda + gk)) : 0.f;
             int nn;
             if (TB) { kk = e % BK; nn = e / BK; } else { nn = e % BN; kk = e / BN; }
-            int64_t gn = n0 + nn;
+            const int64_t gn = n0 + nn;
             gk = k0 + kk;
-            v = 0.f;
-            if (gn < N && gk < kend) v = TB ? ld(B, gn * ldb + gk) : ld(B, gk * ldb + gn);
-            Bs[kk][nn] = v;
+            rb[r] = (gn < N && gk < kend) ? (TB ? ld(B, gn * ldb + gk) : ld(B, gk * ldb + gn)) : 0.f;
         }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int r = 0; r < STAGE; ++r) {
+            const int e = tid + 256 * r;
+            if (TA) As[e / BM][e % BM] = ra[r];
+            else As[e % BK][e / BK] = ra[r];
+            if (TB) Bs[e % BK][e / BK] = rb[r];
+            else Bs[e / BN][e % BN] = rb[r];
+        }
+    };
+    if (kbeg < kend) load(kbeg);
+    for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+        store();
         __syncthreads();
+        if (k0 + BK < kend) load(k0 + BK);
 #pragma unroll
         for (int ks = 0; ks < BK; ks += 4) {
             float af[2], bfv[2];
@@ -112,15 +126,22 @@ __global__ void k_sum_splits(int64_t len, int nz, const float *__restrict__ part
     out[i] = s;
 }
 
-// column sums of a row-major [rows][cols] FP32 matrix, split over row chunks
-__global__ void k_colsum(int64_t rows, int64_t cols, int64_t chunk, const float *__restrict__ A,
-                         float *__restrict__ part) {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= cols) return;
-    int64_t r0 = (int64_t)blockIdx.y * chunk, r1 = r0 + chunk < rows ? r0 + chunk : rows;
+// Column sums of a row-major [rows][cols] FP32 matrix over row chunks: a
+// block takes 64 columns (one row segment per wave and step) and `chunk`
+// rows, four row lanes summing every fourth row, combined in a fixed order;
+// part[chunk index][c].
+__global__ void __launch_bounds__(256) k_colsum(int64_t rows, int64_t cols, int64_t chunk,
+                                                const float *__restrict__ A, float *__restrict__ part) {
+    __shared__ float red[4][64];
+    const int cl = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int64_t c = (int64_t)blockIdx.x * 64 + cl;
+    const int64_t r0 = (int64_t)blockIdx.y * chunk, r1 = r0 + chunk < rows ? r0 + chunk : rows;
     float s = 0.f;
-    for (int64_t r = r0; r < r1; ++r) s += A[r * cols + c];
-    part[(int64_t)blockIdx.y * cols + c] = s;
+    if (c < cols)
+        for (int64_t r = r0 + g; r < r1; r += 4) s += A[r * cols + c];
+    red[g][cl] = s;
+    __syncthreads();
+    if (g == 0 && c < cols) part[(int64_t)blockIdx.y * cols + c] = (red[0][cl] + red[1][cl]) + (red[2][cl] + red[3][cl]);
 }
 
 __global__ void k_mse_grad(int64_t len, float scale, const float *__restrict__ Y,
@@ -157,7 +178,10 @@ static BwdPlan plan_bwd(int H, int64_t n) {
     if (p.splits > 64) p.splits = 64;
     if (p.splits < 1) p.splits = 1;
     p.kchunk = ((n + p.splits - 1) / p.splits + BK - 1) / BK * BK;
-    p.rsplits = p.splits;
+    // bias gradients: chunks of 256 rows (at most 1024 of them)
+    p.rsplits = (n + 255) / 256;
+    if (p.rsplits > 1024) p.rsplits = 1024;
+    if (p.rsplits < 1) p.rsplits = 1;
     p.rows_chunk = (n + p.rsplits - 1) / p.rsplits;
     if (p.rows_chunk < 1) p.rows_chunk = 1;
     size_t a = 256;
@@ -208,8 +232,8 @@ static void backward_impl(const BwdPlan &p, const TX *X, int64_t ldx, const TS *
     const float *srcs[3] = {dz1, dz2, dY};
     const int64_t cols[3] = {H, H, N_OUT};
     for (int l = 0; l < 3; ++l) {
-        dim3 grid(blocks_for(cols[l], 128), (unsigned)p.rsplits);
-        k_colsum<<<grid, 128, 0, s>>>(n, cols[l], p.rows_chunk, srcs[l], cpart);
+        dim3 grid(blocks_for(cols[l], 64), (unsigned)p.rsplits);
+        k_colsum<<<grid, 256, 0, s>>>(n, cols[l], p.rows_chunk, srcs[l], cpart);
         k_sum_splits<<<blocks_for(cols[l], 256), 256, 0, s>>>(cols[l], (int)p.rsplits, cpart, db[l]);
     }
 }
