@@ -4,7 +4,8 @@
 //
 // The backward pass is five products of the forward's shapes:
 //   dZ2 = (dY W3^T) (.) (1 - A2^2),   dZ1 = (dZ2 W2^T) (.) (1 - A1^2)
-//   dW3 = A2^T dY,  dW2 = A1^T dZ2,  dW1 = X^T dZ1,  db = column sums.
+//   dW3 = A2^T dY,  dW2 = A1^T dZ2,  dW1 = X^T dZ1,  db = column sums
+// (of dY, dZ2, dZ1, summed from the tiles the weight-gradient products stage).
 // They run on one tiled GEMM kernel (64x64 output tiles, LDS-staged operands,
 // v_mfma_f32_16x16x4f32 with FP32 accumulation).  The weight gradients reduce
 // over patches; they are split over K (patch ranges) and the partial tiles are
@@ -31,11 +32,14 @@ constexpr int STAGE = BM * BK / 256; // elements of each operand a thread stages
 // blockIdx.z = split index over K; C + z*M*N receives that split's partial.
 // The next K step's operands are loaded into registers while the current
 // step's products run (one memory round trip per step, overlapped).
+// colsum != NULL: the blocks of the first M tile also sum op(B) over their
+// K range from the staged tiles (colsum + z*N: the column sums of B over
+// split z, in K order), which gives the bias gradients without another pass.
 template <bool TA, bool TB, typename TAe, typename TBe, typename TSe, bool EPI>
 __global__ void __launch_bounds__(256)
     k_gemm(int64_t M, int64_t N, int64_t K, int64_t kchunk, const TAe *__restrict__ A, int64_t lda,
            const TBe *__restrict__ B, int64_t ldb, float *__restrict__ C, int64_t ldc,
-           const TSe *__restrict__ S, int64_t lds_) {
+           const TSe *__restrict__ S, int64_t lds_, float *__restrict__ colsum) {
     __shared__ float As[BK][BM + 4];
     __shared__ float Bs[BK][BN + 4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -76,11 +80,16 @@ __global__ void __launch_bounds__(256)
             else Bs[e / BN][e % BN] = rb[r];
         }
     };
+    const bool csum = colsum && blockIdx.x == 0 && tid < BN;
+    float cs = 0.f;
     if (kbeg < kend) load(kbeg);
     for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
         store();
         __syncthreads();
         if (k0 + BK < kend) load(k0 + BK);
+        if (csum)
+#pragma unroll
+            for (int kk = 0; kk < BK; ++kk) cs += Bs[kk][tid];
 #pragma unroll
         for (int ks = 0; ks < BK; ks += 4) {
             float af[2], bfv[2];
@@ -96,6 +105,7 @@ __global__ void __launch_bounds__(256)
         }
         __syncthreads();
     }
+    if (csum && n0 + tid < N) colsum[(int64_t)blockIdx.z * N + n0 + tid] = cs;
     float *Cz = C + (int64_t)blockIdx.z * M * N;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -126,24 +136,6 @@ __global__ void k_sum_splits(int64_t len, int nz, const float *__restrict__ part
     out[i] = s;
 }
 
-// Column sums of a row-major [rows][cols] FP32 matrix over row chunks: a
-// block takes 64 columns (one row segment per wave and step) and `chunk`
-// rows, four row lanes summing every fourth row, combined in a fixed order;
-// part[chunk index][c].
-__global__ void __launch_bounds__(256) k_colsum(int64_t rows, int64_t cols, int64_t chunk,
-                                                const float *__restrict__ A, float *__restrict__ part) {
-    __shared__ float red[4][64];
-    const int cl = threadIdx.x & 63, g = threadIdx.x >> 6;
-    const int64_t c = (int64_t)blockIdx.x * 64 + cl;
-    const int64_t r0 = (int64_t)blockIdx.y * chunk, r1 = r0 + chunk < rows ? r0 + chunk : rows;
-    float s = 0.f;
-    if (c < cols)
-        for (int64_t r = r0 + g; r < r1; r += 4) s += A[r * cols + c];
-    red[g][cl] = s;
-    __syncthreads();
-    if (g == 0 && c < cols) part[(int64_t)blockIdx.y * cols + c] = (red[0][cl] + red[1][cl]) + (red[2][cl] + red[3][cl]);
-}
-
 __global__ void k_mse_grad(int64_t len, float scale, const float *__restrict__ Y,
                            const float *__restrict__ T, float *__restrict__ dY) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -166,7 +158,7 @@ __global__ void k_adamw(int64_t n, float *__restrict__ th, float *__restrict__ m
 }
 
 struct BwdPlan {
-    int64_t n, H, splits, kchunk, rows_chunk, rsplits;
+    int64_t n, H, splits, kchunk, rsplits;
     size_t off_dz2, off_dz1, off_part, off_cpart, total;
 };
 
@@ -178,12 +170,7 @@ static BwdPlan plan_bwd(int H, int64_t n) {
     if (p.splits > 64) p.splits = 64;
     if (p.splits < 1) p.splits = 1;
     p.kchunk = ((n + p.splits - 1) / p.splits + BK - 1) / BK * BK;
-    // bias gradients: chunks of 256 rows (at most 1024 of them)
-    p.rsplits = (n + 255) / 256;
-    if (p.rsplits > 1024) p.rsplits = 1024;
-    if (p.rsplits < 1) p.rsplits = 1;
-    p.rows_chunk = (n + p.rsplits - 1) / p.rsplits;
-    if (p.rows_chunk < 1) p.rows_chunk = 1;
+    p.rsplits = p.splits; // bias gradients: one column-sum partial per split
     size_t a = 256;
     auto up = [&](size_t b) { return (b + a - 1) / a * a; };
     p.off_dz2 = 0;
@@ -198,11 +185,13 @@ static BwdPlan plan_bwd(int H, int64_t n) {
 template <bool TA, bool TB, typename TAe, typename TBe, typename TSe, bool EPI>
 static void gemm(int64_t M, int64_t N, int64_t K, int64_t splits, int64_t kchunk, const TAe *A,
                  int64_t lda, const TBe *B, int64_t ldb, float *C, int64_t ldc, float *part,
-                 const TSe *S, int64_t lds_, hipStream_t s) {
+                 const TSe *S, int64_t lds_, hipStream_t s, float *cpart = nullptr, float *colsum = nullptr) {
     dim3 grid((unsigned)((M + BM - 1) / BM), (unsigned)((N + BN - 1) / BN), (unsigned)splits);
     k_gemm<TA, TB, TAe, TBe, TSe, EPI><<<grid, 256, 0, s>>>(M, N, K, kchunk, A, lda, B, ldb,
-                                                            splits == 1 ? C : part, ldc, S, lds_);
+                                                            splits == 1 ? C : part, ldc, S, lds_,
+                                                            colsum ? cpart : nullptr);
     if (splits > 1) k_sum_splits<<<blocks_for(M * N, 256), 256, 0, s>>>(M * N, (int)splits, part, C);
+    if (colsum) k_sum_splits<<<blocks_for(N, 256), 256, 0, s>>>(N, (int)splits, cpart, colsum);
 }
 
 template <typename TX, typename TS>
@@ -221,21 +210,14 @@ static void backward_impl(const BwdPlan &p, const TX *X, int64_t ldx, const TS *
     // dZ1 = (dZ2 W2^T) (.) (1 - A1^2): W2 is [H_in][H_out] -> op(B)[k=j][n=h] = W2[h][j]
     gemm<false, true, float, float, TS, true>(n, H, H, 1, H + BK, dz2, H, W2, H, dz1, H, nullptr, A1, H,
                                               s);
-    // weight gradients, split over patches
+    // weight gradients, split over patches; the bias gradients (column sums
+    // of dY, dZ2, dZ1) come from the same staged tiles
     gemm<true, false, TS, float, float, false>(H, N_OUT, n, p.splits, p.kchunk, A2, H, dY, N_OUT, dW[2],
-                                               N_OUT, part, nullptr, 0, s);
+                                               N_OUT, part, nullptr, 0, s, cpart, db[2]);
     gemm<true, false, TS, float, float, false>(H, H, n, p.splits, p.kchunk, A1, H, dz2, H, dW[1], H,
-                                               part, nullptr, 0, s);
+                                               part, nullptr, 0, s, cpart, db[1]);
     gemm<true, false, TX, float, float, false>(N_IN, H, n, p.splits, p.kchunk, X, ldx, dz1, H, dW[0], H,
-                                               part, nullptr, 0, s);
-    // bias gradients
-    const float *srcs[3] = {dz1, dz2, dY};
-    const int64_t cols[3] = {H, H, N_OUT};
-    for (int l = 0; l < 3; ++l) {
-        dim3 grid(blocks_for(cols[l], 64), (unsigned)p.rsplits);
-        k_colsum<<<grid, 256, 0, s>>>(n, cols[l], p.rows_chunk, srcs[l], cpart);
-        k_sum_splits<<<blocks_for(cols[l], 256), 256, 0, s>>>(cols[l], (int)p.rsplits, cpart, db[l]);
-    }
+                                               part, nullptr, 0, s, cpart, db[0]);
 }
 
 } // namespace dnnmg
