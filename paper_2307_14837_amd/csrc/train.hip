@@ -127,6 +127,97 @@ __global__ void __launch_bounds__(256)
             }
 }
 
+// Weight gradient of a BF16 network on BF16 MFMA: C = sum_k A[k][m] B[k][n]
+// over split z's K range (C + z*M*N receives the partial; M, N <= any),
+// A [K][lda] BF16 (activations or network inputs), B [K][N] FP32 (dZ, rounded
+// to BF16 as it is staged), FP32 accumulation; the same BF16 operand
+// rounding as the forward pass.  Tiles of 128 x 128 outputs, 32 K per step
+// (one v_mfma_f32_16x16x32_bf16 deep), four waves of 64 x 64; operands are
+// staged K-minor in LDS so a fragment (8 consecutive K of one row) is one
+// 16-byte read; the next step's operands are loaded during the current
+// step's products.  colsum != NULL: the blocks of the first M tile also sum
+// B (in FP32, before rounding) over their K range, in a fixed order.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+constexpr int WB = 128, WK = 32, WKP = WK + 8; // tile, K step, padded LDS row (bf16)
+
+__global__ void __launch_bounds__(256)
+    k_wgrad_bf16(int64_t M, int64_t N, int64_t K, int64_t kchunk, const uint16_t *__restrict__ A, int64_t lda,
+                 const float *__restrict__ B, float *__restrict__ C, float *__restrict__ colsum) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[WB * WKP];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[WB * WKP];
+    __shared__ float cred[2][WB];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t m0 = (int64_t)blockIdx.x * WB, n0 = (int64_t)blockIdx.y * WB;
+    const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+    const int64_t kend = kbeg + kchunk < K ? kbeg + kchunk : K;
+    const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
+    const int g = lane >> 4, i16 = lane & 15;
+    // staging: thread covers column c = tid % 128 of both operand tiles and
+    // K rows kk = 2 (tid / 128) + 4 r + {0, 1}, r < 8
+    const int c = tid & 127, kh = (tid >> 7) * 2;
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    uint16_t ra[8][2];
+    float rb[8][2];
+    auto load = [&](int64_t k0) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int64_t gk = k0 + kh + 4 * r + h;
+                const bool kin = gk < kend;
+                ra[r][h] = (kin && m0 + c < M) ? A[gk * lda + m0 + c] : (uint16_t)0;
+                rb[r][h] = (kin && n0 + c < N) ? B[gk * N + n0 + c] : 0.0f;
+            }
+    };
+    const bool csum = colsum && blockIdx.x == 0;
+    float cs = 0.f;
+    if (kbeg < kend) load(kbeg);
+    for (int64_t k0 = kbeg; k0 < kend; k0 += WK) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int kk = kh + 4 * r;
+            *(uint32_t *)&As[c * WKP + kk] = (uint32_t)ra[r][0] | ((uint32_t)ra[r][1] << 16);
+            *(uint32_t *)&Bs[c * WKP + kk] = pack_bf16x2_hw(rb[r][0], rb[r][1]);
+            if (csum) cs += rb[r][0] + rb[r][1];
+        }
+        __syncthreads();
+        if (k0 + WK < kend) load(k0 + WK);
+        u32x4_t af[4], bf[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) af[a] = *(const u32x4_t *)&As[(wm + 16 * a + i16) * WKP + 8 * g];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) bf[b] = *(const u32x4_t *)&Bs[(wn + 16 * b + i16) * WKP + 8 * g];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, af[a]),
+                                                                    __builtin_bit_cast(bf16x8_t, bf[b]), acc[a][b],
+                                                                    0, 0, 0);
+        __syncthreads();
+    }
+    if (csum) {
+        cred[tid >> 7][c] = cs;
+        __syncthreads();
+        if (tid < 128 && n0 + c < N) colsum[(int64_t)blockIdx.z * N + n0 + c] = cred[0][c] + cred[1][c];
+    }
+    float *Cz = C + (int64_t)blockIdx.z * M * N;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t gm = m0 + wm + 16 * a + 4 * g + e, gn = n0 + wn + 16 * b + i16;
+                if (gm < M && gn < N) Cz[gm * N + gn] = acc[a][b][e];
+            }
+}
+
 // out[i] = sum_z part[z][i], fixed order
 __global__ void k_sum_splits(int64_t len, int nz, const float *__restrict__ part, float *__restrict__ out) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -159,6 +250,7 @@ __global__ void k_adamw(int64_t n, float *__restrict__ th, float *__restrict__ m
 
 struct BwdPlan {
     int64_t n, H, splits, kchunk, rsplits;
+    int64_t wsplits, wkchunk; // the BF16 weight-gradient products: more, shorter splits
     size_t off_dz2, off_dz1, off_part, off_cpart, total;
 };
 
@@ -171,14 +263,19 @@ static BwdPlan plan_bwd(int H, int64_t n) {
     if (p.splits < 1) p.splits = 1;
     p.kchunk = ((n + p.splits - 1) / p.splits + BK - 1) / BK * BK;
     p.rsplits = p.splits; // bias gradients: one column-sum partial per split
+    p.wsplits = (n + 511) / 512;
+    if (p.wsplits > 256) p.wsplits = 256;
+    if (p.wsplits < 1) p.wsplits = 1;
+    p.wkchunk = ((n + p.wsplits - 1) / p.wsplits + WK - 1) / WK * WK;
+    const int64_t ps = p.splits > p.wsplits ? p.splits : p.wsplits;
     size_t a = 256;
     auto up = [&](size_t b) { return (b + a - 1) / a * a; };
     p.off_dz2 = 0;
     p.off_dz1 = up(p.off_dz2 + sizeof(float) * n * H);
     p.off_part = up(p.off_dz1 + sizeof(float) * n * H);
-    size_t part = sizeof(float) * p.splits * (size_t)((size_t)N_IN * H + (size_t)H * H + (size_t)H * N_OUT);
+    size_t part = sizeof(float) * ps * (size_t)((size_t)N_IN * H + (size_t)H * H + (size_t)H * N_OUT);
     p.off_cpart = up(p.off_part + part);
-    p.total = up(p.off_cpart + sizeof(float) * p.rsplits * (size_t)(2 * H + N_OUT));
+    p.total = up(p.off_cpart + sizeof(float) * ps * (size_t)(2 * H + N_OUT));
     return p;
 }
 
@@ -192,6 +289,15 @@ static void gemm(int64_t M, int64_t N, int64_t K, int64_t splits, int64_t kchunk
                                                             colsum ? cpart : nullptr);
     if (splits > 1) k_sum_splits<<<blocks_for(M * N, 256), 256, 0, s>>>(M * N, (int)splits, part, C);
     if (colsum) k_sum_splits<<<blocks_for(N, 256), 256, 0, s>>>(N, (int)splits, cpart, colsum);
+}
+
+static void wgrad_bf16(int64_t M, int64_t N, int64_t K, int64_t splits, int64_t kchunk, const uint16_t *A,
+                       int64_t lda, const float *B, float *C, float *part, float *cpart, float *colsum,
+                       hipStream_t s) {
+    dim3 grid((unsigned)((M + WB - 1) / WB), (unsigned)((N + WB - 1) / WB), (unsigned)splits);
+    k_wgrad_bf16<<<grid, 256, 0, s>>>(M, N, K, kchunk, A, lda, B, part, cpart);
+    k_sum_splits<<<blocks_for(M * N, 256), 256, 0, s>>>(M * N, (int)splits, part, C);
+    k_sum_splits<<<blocks_for(N, 256), 256, 0, s>>>(N, (int)splits, cpart, colsum);
 }
 
 template <typename TX, typename TS>
@@ -212,12 +318,19 @@ static void backward_impl(const BwdPlan &p, const TX *X, int64_t ldx, const TS *
                                               s);
     // weight gradients, split over patches; the bias gradients (column sums
     // of dY, dZ2, dZ1) come from the same staged tiles
-    gemm<true, false, TS, float, float, false>(H, N_OUT, n, p.splits, p.kchunk, A2, H, dY, N_OUT, dW[2],
-                                               N_OUT, part, nullptr, 0, s, cpart, db[2]);
-    gemm<true, false, TS, float, float, false>(H, H, n, p.splits, p.kchunk, A1, H, dz2, H, dW[1], H,
-                                               part, nullptr, 0, s, cpart, db[1]);
-    gemm<true, false, TX, float, float, false>(N_IN, H, n, p.splits, p.kchunk, X, ldx, dz1, H, dW[0], H,
-                                               part, nullptr, 0, s, cpart, db[0]);
+    if constexpr (sizeof(TS) == 2 && sizeof(TX) == 2) {
+        // BF16 network: BF16 products with FP32 accumulation
+        wgrad_bf16(H, N_OUT, n, p.wsplits, p.wkchunk, A2, H, dY, dW[2], part, cpart, db[2], s);
+        wgrad_bf16(H, H, n, p.wsplits, p.wkchunk, A1, H, dz2, dW[1], part, cpart, db[1], s);
+        wgrad_bf16(N_IN, H, n, p.wsplits, p.wkchunk, X, ldx, dz1, dW[0], part, cpart, db[0], s);
+    } else {
+        gemm<true, false, TS, float, float, false>(H, N_OUT, n, p.splits, p.kchunk, A2, H, dY, N_OUT, dW[2],
+                                                   N_OUT, part, nullptr, 0, s, cpart, db[2]);
+        gemm<true, false, TS, float, float, false>(H, H, n, p.splits, p.kchunk, A1, H, dz2, H, dW[1], H,
+                                                   part, nullptr, 0, s, cpart, db[1]);
+        gemm<true, false, TX, float, float, false>(N_IN, H, n, p.splits, p.kchunk, X, ldx, dz1, H, dW[0], H,
+                                                   part, nullptr, 0, s, cpart, db[0]);
+    }
 }
 
 } // namespace dnnmg
