@@ -260,7 +260,8 @@ def run_training(steps):
     from paper_2307_14837_amd import flops
 
     fl = 3 * flops.mlp_flops_per_patch(H) * n  # forward + backward (about 2x forward)
-    return {"workload": "training_batch_65536_width256", "dtype": "bf16 forward, fp32 backward/master",
+    return {"workload": "training_batch_65536_width256",
+            "dtype": "bf16 forward and backward products, fp32 accumulation and master weights",
             "ms_per_step": ms, "patches_per_s": n / (ms * 1e-3), "approx_tflops": fl / (ms * 1e-3) / 1e12}
 
 

@@ -6,10 +6,12 @@
 //   dZ2 = (dY W3^T) (.) (1 - A2^2),   dZ1 = (dZ2 W2^T) (.) (1 - A1^2)
 //   dW3 = A2^T dY,  dW2 = A1^T dZ2,  dW1 = X^T dZ1,  db = column sums
 // (of dY, dZ2, dZ1, summed from the tiles the weight-gradient products stage).
-// They run on one tiled GEMM kernel (64x64 output tiles, LDS-staged operands,
-// v_mfma_f32_16x16x4f32 with FP32 accumulation).  The weight gradients reduce
-// over patches; they are split over K (patch ranges) and the partial tiles are
-// summed in a fixed order, so results are run-to-run identical.
+// For an FP32 network they run on one tiled GEMM kernel (64x64 output tiles,
+// LDS-staged operands, v_mfma_f32_16x16x4f32); for a BF16 network on BF16
+// MFMA kernels with the operands rounded to BF16 as in the forward pass.
+// All accumulate in FP32.  The weight gradients reduce over patches; they are
+// split over K (patch ranges) and the partial tiles are summed in a fixed
+// order, so results are run-to-run identical.
 #include "common.hpp"
 #include "lowp.hpp"
 #include "mlp.hpp"
@@ -218,13 +220,97 @@ __global__ void __launch_bounds__(256)
             }
 }
 
-// out[i] = sum_z part[z][i], fixed order
-__global__ void k_sum_splits(int64_t len, int nz, const float *__restrict__ part, float *__restrict__ out) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= len) return;
+// dZ of a BF16 network on BF16 MFMA: C[m][n] = (sum_k A[m][k] W[n][k])
+// (1 - S[m][n]^2), A FP32 [M][lda] (dY or dZ2), W FP32 [N][ldw] (the next
+// layer's master weights, so the product is by W^T), S BF16 [M][lds] (the
+// saved activations); A and W rounded to BF16 as they are staged, FP32
+// accumulation.  128 x 128 tiles, 32 K per step; both operands are K-minor
+// in memory already, so a thread stages 16 consecutive K of one row.
+__global__ void __launch_bounds__(256)
+    k_dz_bf16(int64_t M, int64_t N, int64_t K, const float *__restrict__ A, int64_t lda,
+              const float *__restrict__ W, int64_t ldw, const uint16_t *__restrict__ S, int64_t lds_,
+              float *__restrict__ C, int64_t ldc) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[WB * WKP];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[WB * WKP];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t m0 = (int64_t)blockIdx.x * WB, n0 = (int64_t)blockIdx.y * WB;
+    const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
+    const int g = lane >> 4, i16 = lane & 15;
+    const int row = tid >> 1, kq = (tid & 1) * 16; // staged row and its 16 K
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float ra[16], rw[16];
+    auto load = [&](int64_t k0) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int64_t k = k0 + kq + e;
+            ra[e] = (m0 + row < M && k < K) ? A[(m0 + row) * lda + k] : 0.0f;
+            rw[e] = (n0 + row < N && k < K) ? W[(n0 + row) * ldw + k] : 0.0f;
+        }
+    };
+    load(0);
+    for (int64_t k0 = 0; k0 < K; k0 += WK) {
+        u32x4_t pa[2], pw[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                pa[h][q] = pack_bf16x2_hw(ra[8 * h + 2 * q], ra[8 * h + 2 * q + 1]);
+                pw[h][q] = pack_bf16x2_hw(rw[8 * h + 2 * q], rw[8 * h + 2 * q + 1]);
+            }
+        *(u32x4_t *)&As[row * WKP + kq] = pa[0];
+        *(u32x4_t *)&As[row * WKP + kq + 8] = pa[1];
+        *(u32x4_t *)&Bs[row * WKP + kq] = pw[0];
+        *(u32x4_t *)&Bs[row * WKP + kq + 8] = pw[1];
+        __syncthreads();
+        if (k0 + WK < K) load(k0 + WK);
+        u32x4_t af[4], bf[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) af[a] = *(const u32x4_t *)&As[(wm + 16 * a + i16) * WKP + 8 * g];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) bf[b] = *(const u32x4_t *)&Bs[(wn + 16 * b + i16) * WKP + 8 * g];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, af[a]),
+                                                                    __builtin_bit_cast(bf16x8_t, bf[b]), acc[a][b],
+                                                                    0, 0, 0);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t gm = m0 + wm + 16 * a + 4 * g + e, gn = n0 + wn + 16 * b + i16;
+                if (gm < M && gn < N) {
+                    const float sv = bf16_to_f32(S[gm * lds_ + gn]);
+                    C[gm * ldc + gn] = acc[a][b][e] * (1.0f - sv * sv);
+                }
+            }
+}
+
+// out[i] = sum_z part[z][i] in a fixed order: a block takes 64 elements and
+// four split lanes (lane q sums z = q, q + 4, ..; the four are combined as
+// (s0 + s1) + (s2 + s3)), loads issued eight at a time.
+__global__ void __launch_bounds__(256) k_sum_splits(int64_t len, int nz, const float *__restrict__ part,
+                                                    float *__restrict__ out) {
+    __shared__ float red[4][64];
+    const int el = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int64_t i = (int64_t)blockIdx.x * 64 + el;
     float s = 0.f;
-    for (int z = 0; z < nz; ++z) s += part[(int64_t)z * len + i];
-    out[i] = s;
+    if (i < len) {
+#pragma unroll 8
+        for (int z = q; z < nz; z += 4) s += part[(int64_t)z * len + i];
+    }
+    red[q][el] = s;
+    __syncthreads();
+    if (q == 0 && i < len) out[i] = (red[0][el] + red[1][el]) + (red[2][el] + red[3][el]);
 }
 
 __global__ void k_mse_grad(int64_t len, float scale, const float *__restrict__ Y,
@@ -287,8 +373,8 @@ static void gemm(int64_t M, int64_t N, int64_t K, int64_t splits, int64_t kchunk
     k_gemm<TA, TB, TAe, TBe, TSe, EPI><<<grid, 256, 0, s>>>(M, N, K, kchunk, A, lda, B, ldb,
                                                             splits == 1 ? C : part, ldc, S, lds_,
                                                             colsum ? cpart : nullptr);
-    if (splits > 1) k_sum_splits<<<blocks_for(M * N, 256), 256, 0, s>>>(M * N, (int)splits, part, C);
-    if (colsum) k_sum_splits<<<blocks_for(N, 256), 256, 0, s>>>(N, (int)splits, cpart, colsum);
+    if (splits > 1) k_sum_splits<<<blocks_for(M * N, 64), 256, 0, s>>>(M * N, (int)splits, part, C);
+    if (colsum) k_sum_splits<<<blocks_for(N, 64), 256, 0, s>>>(N, (int)splits, cpart, colsum);
 }
 
 static void wgrad_bf16(int64_t M, int64_t N, int64_t K, int64_t splits, int64_t kchunk, const uint16_t *A,
@@ -296,8 +382,8 @@ static void wgrad_bf16(int64_t M, int64_t N, int64_t K, int64_t splits, int64_t 
                        hipStream_t s) {
     dim3 grid((unsigned)((M + WB - 1) / WB), (unsigned)((N + WB - 1) / WB), (unsigned)splits);
     k_wgrad_bf16<<<grid, 256, 0, s>>>(M, N, K, kchunk, A, lda, B, part, cpart);
-    k_sum_splits<<<blocks_for(M * N, 256), 256, 0, s>>>(M * N, (int)splits, part, C);
-    k_sum_splits<<<blocks_for(N, 256), 256, 0, s>>>(N, (int)splits, cpart, colsum);
+    k_sum_splits<<<blocks_for(M * N, 64), 256, 0, s>>>(M * N, (int)splits, part, C);
+    k_sum_splits<<<blocks_for(N, 64), 256, 0, s>>>(N, (int)splits, cpart, colsum);
 }
 
 template <typename TX, typename TS>
@@ -310,12 +396,19 @@ static void backward_impl(const BwdPlan &p, const TX *X, int64_t ldx, const TS *
     float *part = (float *)(ws + p.off_part);
     float *cpart = (float *)(ws + p.off_cpart);
     const TS *A1 = saved, *A2 = saved + n * H;
-    // dZ2 = (dY W3^T) (.) (1 - A2^2): W3 is [H][81] -> op(B)[k=o][n=h] = W3[h][o]
-    gemm<false, true, float, float, TS, true>(n, H, N_OUT, 1, N_OUT + BK, dY, N_OUT, W3, N_OUT, dz2, H,
-                                              nullptr, A2, H, s);
-    // dZ1 = (dZ2 W2^T) (.) (1 - A1^2): W2 is [H_in][H_out] -> op(B)[k=j][n=h] = W2[h][j]
-    gemm<false, true, float, float, TS, true>(n, H, H, 1, H + BK, dz2, H, W2, H, dz1, H, nullptr, A1, H,
-                                              s);
+    if constexpr (sizeof(TS) == 2) {
+        // BF16 network: dZ products on BF16 MFMA (W3 is [H][81], W2 [H][H])
+        dim3 grid((unsigned)((n + WB - 1) / WB), (unsigned)((H + WB - 1) / WB));
+        k_dz_bf16<<<grid, 256, 0, s>>>(n, H, N_OUT, dY, N_OUT, W3, N_OUT, (const uint16_t *)A2, H, dz2, H);
+        k_dz_bf16<<<grid, 256, 0, s>>>(n, H, H, dz2, H, W2, H, (const uint16_t *)A1, H, dz1, H);
+    } else {
+        // dZ2 = (dY W3^T) (.) (1 - A2^2): W3 is [H][81] -> op(B)[k=o][n=h] = W3[h][o]
+        gemm<false, true, float, float, TS, true>(n, H, N_OUT, 1, N_OUT + BK, dY, N_OUT, W3, N_OUT, dz2, H,
+                                                  nullptr, A2, H, s);
+        // dZ1 = (dZ2 W2^T) (.) (1 - A1^2): W2 is [H_in][H_out] -> op(B)[k=j][n=h] = W2[h][j]
+        gemm<false, true, float, float, TS, true>(n, H, H, 1, H + BK, dz2, H, W2, H, dz1, H, nullptr, A1, H,
+                                                  s);
+    }
     // weight gradients, split over patches; the bias gradients (column sums
     // of dY, dZ2, dZ1) come from the same staged tiles
     if constexpr (sizeof(TS) == 2 && sizeof(TX) == 2) {
