@@ -26,6 +26,7 @@
 // the 8 Gauss points from the 8 vertex values, and the transpose to vertex
 // integrals, each by three 1-D passes.
 #include "common.hpp"
+#include "mlp.hpp"
 
 // Floating-point contraction only within a source expression: every kernel
 // instance (single box, batched, with or without forcing) then rounds the
@@ -784,7 +785,10 @@ __device__ __forceinline__ void tile_of(int64_t t, const int G[3], const int F[3
     c[2] = (int)(p / ((int64_t)gx * F[1]));
 }
 
-template <int MODE>
+// STRIDED = false: one tile per block (the grid covers the tiles);
+// STRIDED = true: blocks walk the tiles with stride gridDim.x, for launches
+// that a device flag may skip on a small grid.
+template <int MODE, bool STRIDED = false>
 __global__ void __launch_bounds__(ResTile<MODE>::NT, ResTile<MODE>::WAVES_PER_SIMD)
     k_residual(Mesh m, ResParams P, const float *__restrict__ x, const float *__restrict__ vp,
                const float *__restrict__ fmid, float *__restrict__ out, float *__restrict__ aux,
@@ -796,19 +800,22 @@ __global__ void __launch_bounds__(ResTile<MODE>::NT, ResTile<MODE>::WAVES_PER_SI
     const int F[3] = {m.nf[0] / T::TX, m.nf[1] / T::TY, m.nf[2] / T::TZ};
     const int64_t nfull = (int64_t)F[0] * F[1] * F[2];
     const int64_t xf = NXCD * ((nfull + NXCD - 1) / NXCD);
-    int64_t t;
-    if (blockIdx.x < xf) {
-        t = xcd_item(blockIdx.x, xf);
-        if (t >= nfull) return;
-    } else {
-        t = nfull + (blockIdx.x - xf);
-        if (t >= (int64_t)G[0] * G[1] * G[2]) return;
+    const int64_t nblk = xf + ((int64_t)G[0] * G[1] * G[2] - nfull);
+    for (int64_t vb = blockIdx.x; vb < nblk; vb += STRIDED ? gridDim.x : nblk) {
+        int64_t t;
+        if (vb < xf) {
+            t = xcd_item(vb, xf);
+            if (t >= nfull) continue;
+        } else {
+            t = nfull + (vb - xf);
+        }
+        int c[3];
+        tile_of(t, G, F, c);
+        const int tl = c[0] + G[0] * (c[1] + G[1] * c[2]);
+        residual_tile<MODE>(m, P, c[0], c[1], c[2], x, vp, fmid, out, aux, mode_general(MODE) ? tflag + tl : nullptr,
+                            xc, xt_out);
+        if constexpr (STRIDED) __syncthreads(); // the tile's LDS reads are done before the next stages
     }
-    int c[3];
-    tile_of(t, G, F, c);
-    const int tl = c[0] + G[0] * (c[1] + G[1] * c[2]);
-    residual_tile<MODE>(m, P, c[0], c[1], c[2], x, vp, fmid, out, aux, mode_general(MODE) ? tflag + tl : nullptr, xc,
-                        xt_out);
 }
 
 // Launch size of a tile grid in the order of tile_of.
@@ -919,7 +926,17 @@ __global__ void __launch_bounds__(256) k_lps_corners(Mesh m, const float *__rest
                                                      float *__restrict__ r, const int *__restrict__ flag) {
     if (flag && *flag == 0) return;
     const int rt[3] = {rt0, rt1, rt2};
-    lps_corner_node(m, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, aux, tflag, rt, r);
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m.n_coarse;
+         t += (int64_t)gridDim.x * blockDim.x)
+        lps_corner_node(m, t, aux, tflag, rt, r);
+}
+
+// Grid of a launch that a device flag may skip: a few workgroups per compute
+// unit walk the work, so a launch that is not taken costs little.
+static unsigned predicated_grid(unsigned full, const int *flag, unsigned per_cu) {
+    if (!flag) return full;
+    const unsigned cap = per_cu * (unsigned)device_cus();
+    return full < cap ? full : cap;
 }
 
 
@@ -963,9 +980,14 @@ int residual_launch(const Mesh &m, const dnnmg_ns *ns, const float *x, const flo
     ResParams P = make_params(m, ns);
     dim3 g = res_grid<MODE_RES>(m);
     int *tflag = (int *)((char *)aux + up256(sizeof(float) * 32 * m.n_patches));
-    k_residual<MODE_RES><<<tile_blocks<MODE_RES>(m), ResTile<MODE_RES>::NT, 0, s>>>(m, P, x, vprev, fmid, r, aux,
-                                                                                 tflag, flag, nullptr, nullptr);
-    k_lps_corners<<<blocks_for(m.n_coarse, 256), 256, 0, s>>>(m, aux, tflag, g.x, g.y, g.z, r, flag);
+    if (flag)
+        k_residual<MODE_RES, true><<<predicated_grid(tile_blocks<MODE_RES>(m), flag, 2), ResTile<MODE_RES>::NT, 0,
+                                     s>>>(m, P, x, vprev, fmid, r, aux, tflag, flag, nullptr, nullptr);
+    else
+        k_residual<MODE_RES><<<tile_blocks<MODE_RES>(m), ResTile<MODE_RES>::NT, 0, s>>>(m, P, x, vprev, fmid, r, aux,
+                                                                                     tflag, nullptr, nullptr, nullptr);
+    k_lps_corners<<<predicated_grid(blocks_for(m.n_coarse, 256), flag, 4), 256, 0, s>>>(m, aux, tflag, g.x, g.y, g.z,
+                                                                                        r, flag);
     return hip_check(hipGetLastError(), "dnnmg_residual launch");
 }
 
@@ -974,9 +996,15 @@ int residual_launch_b(const Mesh &m, const dnnmg_ns *ns, const float *x, const f
     ResParams P = make_params(m, ns);
     dim3 g = res_grid<MODE_RES>(m);
     int *tflag = (int *)((char *)aux + up256(sizeof(float) * 32 * m.n_patches));
-    k_residual<MODE_RESB><<<tile_blocks<MODE_RESB>(m), ResTile<MODE_RESB>::NT, 0, s>>>(m, P, x, b, nullptr, r, aux,
-                                                                                    tflag, flag, nullptr, nullptr);
-    k_lps_corners<<<blocks_for(m.n_coarse, 256), 256, 0, s>>>(m, aux, tflag, g.x, g.y, g.z, r, flag);
+    if (flag)
+        k_residual<MODE_RESB, true><<<predicated_grid(tile_blocks<MODE_RESB>(m), flag, 2), ResTile<MODE_RESB>::NT, 0,
+                                      s>>>(m, P, x, b, nullptr, r, aux, tflag, flag, nullptr, nullptr);
+    else
+        k_residual<MODE_RESB><<<tile_blocks<MODE_RESB>(m), ResTile<MODE_RESB>::NT, 0, s>>>(m, P, x, b, nullptr, r, aux,
+                                                                                        tflag, nullptr, nullptr,
+                                                                                        nullptr);
+    k_lps_corners<<<predicated_grid(blocks_for(m.n_coarse, 256), flag, 4), 256, 0, s>>>(m, aux, tflag, g.x, g.y, g.z,
+                                                                                        r, flag);
     return hip_check(hipGetLastError(), "dnnmg_residual_b launch");
 }
 

@@ -16,6 +16,7 @@
 //   S = C + sum_a B_a K^-1 B_a^T,  S dp = r_p - sum_a B_a K^-1 r_a,
 //   du_a = K^-1 (r_a + B_a^T dp).
 #include "common.hpp"
+#include "mlp.hpp"
 
 namespace dnnmg {
 
@@ -44,16 +45,15 @@ __device__ __forceinline__ int iota_of(int a, int b, int c) { return a + 3 * b +
 
 // COUPLED: full velocity-pressure local systems; otherwise the momentum
 // equations with the pressure held (K delta_a = r_a per component, dp = 0).
+// The local problem of patch M (one 64-thread block).
 template <bool COUPLED>
-__global__ void __launch_bounds__(64)
-    k_vanka_local(Mesh m, VankaTables T, VankaParams P, const float *__restrict__ x,
-                  const float *__restrict__ r, float *__restrict__ D, const int *__restrict__ flag) {
+__device__ __forceinline__ void vanka_patch(const Mesh m, const VankaTables T, const VankaParams P,
+                                            const float *__restrict__ x, const float *__restrict__ r,
+                                            float *__restrict__ D, int64_t M) {
     constexpr int NB = COUPLED ? 3 : 1;   // divergence blocks kept
     constexpr int NO = COUPLED ? 8 : 1;   // own cells with LPS tables
     constexpr int NZ = COUPLED ? 84 : 3;  // right-hand sides of K
-    if (flag && *flag == 0) return;
     const int lane = threadIdx.x;
-    const int64_t M = blockIdx.x;
     uint32_t J_K = fdiv((uint32_t)M, m.px), I = (uint32_t)M - J_K * m.n[0];
     uint32_t K = fdiv(J_K, m.py), J = J_K - K * m.n[1];
     const int64_t nfn = m.n_fine;
@@ -335,14 +335,32 @@ __global__ void __launch_bounds__(64)
     }
 }
 
+// STRIDED = false: one patch per block (the grid covers the patches);
+// STRIDED = true: blocks walk the patches with stride gridDim.x, for launches
+// that a device flag may skip on a smaller grid.
+template <bool COUPLED, bool STRIDED = false>
+__global__ void __launch_bounds__(64)
+    k_vanka_local(Mesh m, VankaTables T, VankaParams P, const float *__restrict__ x,
+                  const float *__restrict__ r, float *__restrict__ D, const int *__restrict__ flag) {
+    if (flag && *flag == 0) return;
+    if constexpr (STRIDED) {
+        for (int64_t M = blockIdx.x; M < m.n_patches; M += gridDim.x) {
+            vanka_patch<COUPLED>(m, T, P, x, r, D, M);
+            __syncthreads(); // the patch's LDS reads are complete before the next one's writes
+        }
+    } else {
+        vanka_patch<COUPLED>(m, T, P, x, r, D, blockIdx.x);
+    }
+}
+
 // x_out = x + omega * mu (.) sum over patches holding the node of delta_P;
 // Dirichlet velocities unchanged.  Safe in place (x_out == x).
 __global__ void __launch_bounds__(256) k_vanka_apply(Mesh m, const float *__restrict__ D, float omega,
                                                      const float *x, float *xout,
                                                      const int *__restrict__ flag) {
     if (flag && *flag == 0) return;
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= m.n_fine) return;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m.n_fine;
+         t += (int64_t)gridDim.x * blockDim.x) {
     uint32_t jk = fdiv((uint32_t)t, m.fx), i = (uint32_t)t - jk * m.nf[0];
     uint32_t k = fdiv(jk, m.fy), j = jk - k * m.nf[1];
     int P[3][2], Lc[3][2], cnt[3];
@@ -385,6 +403,7 @@ __global__ void __launch_bounds__(256) k_vanka_apply(Mesh m, const float *__rest
     for (int f = 0; f < 4; ++f) {
         float dv = (f < 3 && dir) ? 0.0f : acc[f] * inv;
         xout[f * m.n_fine + t] = x[f * m.n_fine + t] + omega * dv;
+    }
     }
 }
 
@@ -469,15 +488,25 @@ int vanka_sweeps(const dnnmg_box *box, const dnnmg_ns *ns, float *x, const float
     float *r = (float *)ws;
     float *aux = (float *)(ws + up(sizeof(float) * 4 * m.n_fine));
     float *D = (float *)(ws + up(sizeof(float) * 4 * m.n_fine) + lps_ws_bytes(m));
+    // predicated sweeps (fallback): grid-stride grids of a few workgroups per
+    // compute unit, so sweeps that are not taken cost little
+    const int ncu = device_cus();
+    const unsigned strided_grid = (unsigned)(m.n_patches < 16 * (int64_t)ncu ? m.n_patches : 16 * (int64_t)ncu);
+    const unsigned apply_grid =
+        flag && blocks_for(m.n_fine, 256) > 4u * ncu ? 4u * ncu : blocks_for(m.n_fine, 256);
     for (int it = 0; it < sweeps; ++it) {
         if ((rc = b ? residual_launch_b(m, ns, x, b, r, aux, flag, s)
                     : residual_launch(m, ns, x, vprev, fmid, r, aux, flag, s)))
             return rc;
-        if (coupled)
-            k_vanka_local<true><<<(unsigned)m.n_patches, 64, 0, s>>>(m, T, P, x, r, D, flag);
+        if (flag && coupled)
+            k_vanka_local<true, true><<<strided_grid, 64, 0, s>>>(m, T, P, x, r, D, flag);
+        else if (flag)
+            k_vanka_local<false, true><<<strided_grid, 64, 0, s>>>(m, T, P, x, r, D, flag);
+        else if (coupled)
+            k_vanka_local<true><<<(unsigned)m.n_patches, 64, 0, s>>>(m, T, P, x, r, D, nullptr);
         else
-            k_vanka_local<false><<<(unsigned)m.n_patches, 64, 0, s>>>(m, T, P, x, r, D, flag);
-        k_vanka_apply<<<blocks_for(m.n_fine, 256), 256, 0, s>>>(m, D, omega, x, x, flag);
+            k_vanka_local<false><<<(unsigned)m.n_patches, 64, 0, s>>>(m, T, P, x, r, D, nullptr);
+        k_vanka_apply<<<apply_grid, 256, 0, s>>>(m, D, omega, x, x, flag);
     }
     return hip_check(hipGetLastError(), "dnnmg_vanka launch");
 }
@@ -496,8 +525,14 @@ __global__ void k_indicator_flag(const double *__restrict__ norms, double theta2
 __global__ void __launch_bounds__(256) k_copy_pred(int64_t n, const float *__restrict__ src,
                                                    float *__restrict__ dst, const int *__restrict__ flag) {
     if (*flag == 0) return;
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) dst[t] = src[t];
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+        dst[t] = src[t];
+}
+
+// grid of the predicated copy: a few workgroups per compute unit
+static unsigned copy_grid(const Mesh &m) {
+    const unsigned full = blocks_for(4 * m.n_fine, 256), cap = 4u * (unsigned)device_cus();
+    return full < cap ? full : cap;
 }
 
 extern "C" size_t dnnmg_fallback_workspace(const dnnmg_box *box) {
@@ -523,7 +558,7 @@ extern "C" int dnnmg_fallback(const dnnmg_box *box, const dnnmg_ns *ns, const fl
     char *w = (char *)ws;
     int *flag = (int *)(w + vanka_ws_bytes(m));
     k_indicator_flag<<<1, 64, 0, s>>>(norms, theta * theta, flag, flag_out);
-    k_copy_pred<<<blocks_for(4 * m.n_fine, 256), 256, 0, s>>>(4 * m.n_fine, xt, xcorr, flag);
+    k_copy_pred<<<copy_grid(m), 256, 0, s>>>(4 * m.n_fine, xt, xcorr, flag);
     if ((rc = hip_check(hipGetLastError(), "dnnmg_fallback launch"))) return rc;
     return vanka_sweeps(box, ns, xcorr, vprev, fmid, sweeps, omega, 0, w, flag, s);
 }
@@ -546,7 +581,7 @@ extern "C" int dnnmg_fallback_b(const dnnmg_box *box, const dnnmg_ns *ns, const 
     char *w = (char *)ws;
     int *flag = (int *)(w + vanka_ws_bytes(m));
     k_indicator_flag<<<1, 64, 0, s>>>(norms, theta * theta, flag, flag_out);
-    k_copy_pred<<<blocks_for(4 * m.n_fine, 256), 256, 0, s>>>(4 * m.n_fine, xt, xcorr, flag);
+    k_copy_pred<<<copy_grid(m), 256, 0, s>>>(4 * m.n_fine, xt, xcorr, flag);
     if ((rc = hip_check(hipGetLastError(), "dnnmg_fallback_b launch"))) return rc;
     return vanka_sweeps(box, ns, xcorr, nullptr, nullptr, sweeps, omega, 0, w, flag, s, b);
 }
