@@ -45,15 +45,21 @@ __device__ __forceinline__ int iota_of(int a, int b, int c) { return a + 3 * b +
 
 // COUPLED: full velocity-pressure local systems; otherwise the momentum
 // equations with the pressure held (K delta_a = r_a per component, dp = 0).
-// The local problem of patch M (one 64-thread block).
-template <bool COUPLED>
-__device__ __forceinline__ void vanka_patch(const Mesh m, const VankaTables T, const VankaParams P,
-                                            const float *__restrict__ x, const float *__restrict__ r,
-                                            float *__restrict__ D, int64_t M) {
+// STRIDED = false: one patch per block (the grid covers the patches);
+// STRIDED = true: blocks walk the patches with stride gridDim.x, for launches
+// that a device flag may skip on a smaller grid.
+template <bool COUPLED, bool STRIDED = false>
+__global__ void __launch_bounds__(64)
+    k_vanka_local(Mesh m, VankaTables T, VankaParams P, const float *__restrict__ x,
+                  const float *__restrict__ r, float *__restrict__ D, const int *__restrict__ flag) {
     constexpr int NB = COUPLED ? 3 : 1;   // divergence blocks kept
     constexpr int NO = COUPLED ? 8 : 1;   // own cells with LPS tables
     constexpr int NZ = COUPLED ? 84 : 3;  // right-hand sides of K
+    if (flag && *flag == 0) return;
     const int lane = threadIdx.x;
+    int64_t M = blockIdx.x;
+    do { // one patch; STRIDED: the next one gridDim.x on
+    if constexpr (STRIDED) __syncthreads(); // the previous patch's LDS reads are complete
     uint32_t J_K = fdiv((uint32_t)M, m.px), I = (uint32_t)M - J_K * m.n[0];
     uint32_t K = fdiv(J_K, m.py), J = J_K - K * m.n[1];
     const int64_t nfn = m.n_fine;
@@ -270,7 +276,7 @@ __device__ __forceinline__ void vanka_patch(const Mesh m, const VankaTables T, c
             int f = s2 / 27, i = s2 % 27;
             out[s2] = (f < 3 && !sDir[i]) ? sZ[f][i] : 0.0f;
         }
-        return;
+        continue;
     } else {
     // ---- Schur complement S = C + sum_a B_a K^-1 B_a^T, s = r_p - sum_a B_a K^-1 r_a ----
     for (int e = lane; e < 729; e += 64) {
@@ -333,24 +339,7 @@ __device__ __forceinline__ void vanka_patch(const Mesh m, const VankaTables T, c
     }
 
     }
-}
-
-// STRIDED = false: one patch per block (the grid covers the patches);
-// STRIDED = true: blocks walk the patches with stride gridDim.x, for launches
-// that a device flag may skip on a smaller grid.
-template <bool COUPLED, bool STRIDED = false>
-__global__ void __launch_bounds__(64)
-    k_vanka_local(Mesh m, VankaTables T, VankaParams P, const float *__restrict__ x,
-                  const float *__restrict__ r, float *__restrict__ D, const int *__restrict__ flag) {
-    if (flag && *flag == 0) return;
-    if constexpr (STRIDED) {
-        for (int64_t M = blockIdx.x; M < m.n_patches; M += gridDim.x) {
-            vanka_patch<COUPLED>(m, T, P, x, r, D, M);
-            __syncthreads(); // the patch's LDS reads are complete before the next one's writes
-        }
-    } else {
-        vanka_patch<COUPLED>(m, T, P, x, r, D, blockIdx.x);
-    }
+    } while (STRIDED && (M += gridDim.x) < m.n_patches);
 }
 
 // x_out = x + omega * mu (.) sum over patches holding the node of delta_P;
