@@ -202,6 +202,122 @@ __device__ __forceinline__ void pi_transpose(const float vals[8], int ox, int oy
         for (int C = 0; C < 2; ++C) cor[AB + 4 * C] = wz[0][C] * Yv[AB] + wz[1][C] * Yv[AB + 4];
 }
 
+// The patch interpolant evaluated directly at the Gauss points of one of its
+// cells.  Along an axis the cell with offset o covers the coarse coordinates
+// [o/2, (o+1)/2] of its patch, so its Gauss points sit at s = (o + xi) / 2.
+__device__ __forceinline__ void patch_coords(int o, float s[2]) {
+    s[0] = 0.5f * ((float)o + GLO);
+    s[1] = 0.5f * ((float)o + (1.0f - GLO));
+}
+// a patch-linear function with end values c0, c1 at the two coordinates s
+__device__ __forceinline__ void plin2(float c0, float c1, const float s[2], float &q0, float &q1) {
+    float d = c1 - c0;
+    q0 = fmaf(s[0], d, c0);
+    q1 = fmaf(s[1], d, c0);
+}
+// Values of the interpolant with corner values c at the cell's Gauss points
+// (what eval_val gives from pi_vertices, up to rounding).
+__device__ __forceinline__ void patch_val(const float c[8], const float sx[2], const float sy[2],
+                                          const float sz[2], float v[8]) {
+    float X[8]; // qa + 2B + 4C
+#pragma unroll
+    for (int BC = 0; BC < 4; ++BC) plin2(c[2 * BC], c[2 * BC + 1], sx, X[2 * BC], X[2 * BC + 1]);
+    float Y[8]; // qa + 2qb + 4C
+#pragma unroll
+    for (int C = 0; C < 2; ++C)
+#pragma unroll
+        for (int qa = 0; qa < 2; ++qa) plin2(X[qa + 4 * C], X[qa + 2 + 4 * C], sy, Y[qa + 4 * C], Y[qa + 2 + 4 * C]);
+#pragma unroll
+    for (int ab = 0; ab < 4; ++ab) plin2(Y[ab], Y[ab + 4], sz, v[ab], v[ab + 4]);
+}
+// Its physical gradient at the Gauss points (the patch is two cells wide, so
+// a corner difference is divided by 2h).  Each component is constant along
+// its own axis: GX[qb + 2qc], GY[qa + 2qc], GZ[qa + 2qb].
+__device__ __forceinline__ void patch_grad(const float c[8], const float sx[2], const float sy[2],
+                                           const float sz[2], float ih0, float ih1, float ih2, float GX[4],
+                                           float GY[4], float GZ[4]) {
+    float D[4], t[4];
+    // x: differences per (B, C), interpolated in y, then z
+#pragma unroll
+    for (int BC = 0; BC < 4; ++BC) D[BC] = c[2 * BC + 1] - c[2 * BC];
+#pragma unroll
+    for (int C = 0; C < 2; ++C) plin2(D[2 * C], D[2 * C + 1], sy, t[2 * C], t[2 * C + 1]); // qb + 2C
+#pragma unroll
+    for (int qb = 0; qb < 2; ++qb) plin2(t[qb], t[qb + 2], sz, GX[qb], GX[qb + 2]);
+    // y: differences per (A, C), interpolated in x, then z
+#pragma unroll
+    for (int C = 0; C < 2; ++C)
+#pragma unroll
+        for (int A = 0; A < 2; ++A) D[A + 2 * C] = c[A + 2 + 4 * C] - c[A + 4 * C];
+#pragma unroll
+    for (int C = 0; C < 2; ++C) plin2(D[2 * C], D[2 * C + 1], sx, t[2 * C], t[2 * C + 1]); // qa + 2C
+#pragma unroll
+    for (int qa = 0; qa < 2; ++qa) plin2(t[qa], t[qa + 2], sz, GY[qa], GY[qa + 2]);
+    // z: differences per (A, B), interpolated in x, then y
+#pragma unroll
+    for (int AB = 0; AB < 4; ++AB) D[AB] = c[AB + 4] - c[AB];
+#pragma unroll
+    for (int B = 0; B < 2; ++B) plin2(D[2 * B], D[2 * B + 1], sx, t[2 * B], t[2 * B + 1]); // qa + 2B
+#pragma unroll
+    for (int qa = 0; qa < 2; ++qa) plin2(t[qa], t[qa + 2], sy, GZ[qa], GZ[qa + 2]);
+    const float hx = 0.5f * ih0, hy = 0.5f * ih1, hz = 0.5f * ih2;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        GX[k] *= hx;
+        GY[k] *= hy;
+        GZ[k] *= hz;
+    }
+}
+// out[A + 2B + 4C] = sum over the cell's Gauss points of G . grad psi, psi
+// the patch's Q1 function of corner (A, B, C) (unit weights): what
+// pi_transpose gives from integrate with gradient terms only, up to rounding.
+// Along an axis psi is l_0(s) = 1 - s or l_1(s) = s, with derivative -+1/(2h).
+__device__ __forceinline__ void patch_integrate_grad(const float G0[8], const float G1[8], const float G2[8],
+                                                     const float sx[2], const float sy[2], const float sz[2],
+                                                     float ih0, float ih1, float ih2, float out[8]) {
+    const float hx = 0.5f * ih0, hy = 0.5f * ih1, hz = 0.5f * ih2;
+    // x pass per p = qb + 2qc: the x-derivative part summed over qa, the y
+    // and z parts weighted with l_A(sx[qa])
+    float SX[4], BY[8], BZ[8]; // BY, BZ: A + 2p
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int q0 = 2 * p, q1 = 2 * p + 1;
+        SX[p] = (G0[q0] + G0[q1]) * hx;
+        const float y1 = fmaf(sx[1], G1[q1], sx[0] * G1[q0]);
+        BY[1 + 2 * p] = y1;
+        BY[2 * p] = (G1[q0] + G1[q1]) - y1;
+        const float z1 = fmaf(sx[1], G2[q1], sx[0] * G2[q0]);
+        BZ[1 + 2 * p] = z1;
+        BZ[2 * p] = (G2[q0] + G2[q1]) - z1;
+    }
+    // y pass per qc: value parts weighted with l_B(sy[qb]), y part summed over qb
+    float Y[8], Z[8]; // A + 2B + 4qc
+#pragma unroll
+    for (int qc = 0; qc < 2; ++qc) {
+        const int p0 = 2 * qc, p1 = 1 + 2 * qc;
+        const float t1 = fmaf(sy[1], SX[p1], sy[0] * SX[p0]);
+        const float t0 = (SX[p0] + SX[p1]) - t1;
+#pragma unroll
+        for (int A = 0; A < 2; ++A) {
+            const float gy = (BY[A + 2 * p0] + BY[A + 2 * p1]) * hy;
+            Y[A + 4 * qc] = (A ? t0 : -t0) - gy;
+            Y[A + 2 + 4 * qc] = (A ? t1 : -t1) + gy;
+            const float z1 = fmaf(sy[1], BZ[A + 2 * p1], sy[0] * BZ[A + 2 * p0]);
+            Z[A + 2 + 4 * qc] = z1;
+            Z[A + 4 * qc] = (BZ[A + 2 * p0] + BZ[A + 2 * p1]) - z1;
+        }
+    }
+    // z pass per (A, B): value part weighted with l_C(sz[qc]), z part summed over qc
+#pragma unroll
+    for (int AB = 0; AB < 4; ++AB) {
+        const float v1 = fmaf(sz[1], Y[AB + 4], sz[0] * Y[AB]);
+        const float v0 = (Y[AB] + Y[AB + 4]) - v1;
+        const float gz = (Z[AB] + Z[AB + 4]) * hz;
+        out[AB] = v0 - gz;
+        out[AB + 4] = v1 + gz;
+    }
+}
+
 // ------------------------------------------------------------ kernel ------
 constexpr int MODE_RES = 0;
 constexpr int MODE_RHS = 1;
@@ -277,6 +393,16 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
         ok = gi >= 0 && gi < m.nf[0] && gj >= 0 && gj < m.nf[1] && gk >= 0 && gk < m.nf[2];
         return gi + (int64_t)m.nf[0] * (gj + (int64_t)m.nf[1] * gk);
     };
+    // b at the owned node is loaded first: its latency overlaps the staging
+    float bown[mode_against_b(MODE) ? 4 : 1] = {};
+    if constexpr (mode_against_b(MODE)) {
+        const int gi = x0 + tid % T::TX, gj = y0 + (tid / T::TX) % T::TY, gk = z0 + tid / (T::TX * T::TY);
+        if (tid < T::NOWN && gi < m.nf[0] && gj < m.nf[1] && gk < m.nf[2]) {
+            const int64_t g = gi + (int64_t)m.nf[0] * (gj + (int64_t)m.nf[1] * gk);
+#pragma unroll
+            for (int f = 0; f < 4; ++f) bown[f] = vp[f * nfn + g];
+        }
+    }
     // all loads of a thread are issued before its LDS stores, so the staging
     // costs one memory round trip
     if constexpr (mode_prolongs(MODE)) {
@@ -439,6 +565,7 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
     };
 
     bool need = false;
+    float xv[3][8]; // x~ at the Gauss points (both passes of the general residual)
     if constexpr (MODE == MODE_RHS) {
         float w[3][8], wv[3][8];
         if (live) {
@@ -494,7 +621,7 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
             }
         }
         // x~, vp and p~ at the Gauss points; divergence of x~
-        float xv[3][8], pv[3][8], pq[8], div[8];
+        float pv[3][8], pq[8], div[8];
         if (live) {
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
@@ -597,53 +724,56 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
     if constexpr (mode_general(MODE)) {
         any_lps = __syncthreads_or(need);
         if (any_lps) {
+            // the cell's stabilisation parameter (stabparams: |v|_inf over the
+            // vertices) and pi v at the Gauss points, shared by the equations
+            // (v there is the first pass's)
+            float den = 1.0f, piv[3][8], sx[2], sy[2], sz[2];
+            patch_coords(ox, sx);
+            patch_coords(oy, sy);
+            patch_coords(oz, sz);
+            if (live && need) {
+                float vmax2 = 0.0f;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    float u0 = sX[0 * T::SN + xb + xoff(j)], u1 = sX[1 * T::SN + xb + xoff(j)],
+                          u2 = sX[2 * T::SN + xb + xoff(j)];
+                    vmax2 = fmaxf(vmax2, u0 * u0 + u1 * u1 + u2 * u2);
+                }
+                den = P.nu * (1.0f / (P.hT * P.hT)) + sqrtf(vmax2) / P.hT + P.inv_dt;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    float w[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) w[j] = sX[d * T::SN + cb + coff(j)];
+                    patch_val(w, sx, sy, sz, piv[d]);
+                }
+            }
             for (int a = 0; a < 4; ++a) {
                 float acc[8], cor[8];
 #pragma unroll
                 for (int j = 0; j < 8; ++j) acc[j] = cor[j] = 0.0f;
                 if (live && need) {
-                    // stabilisation parameters (stabparams): |v|_inf over the vertices
-                    float vmax2 = 0.0f;
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        float u0 = sX[0 * T::SN + xb + xoff(j)], u1 = sX[1 * T::SN + xb + xoff(j)],
-                              u2 = sX[2 * T::SN + xb + xoff(j)];
-                        vmax2 = fmaxf(vmax2, u0 * u0 + u1 * u1 + u2 * u2);
-                    }
-                    float den = P.nu * (1.0f / (P.hT * P.hT)) + sqrtf(vmax2) / P.hT + P.inv_dt;
                     if (a < 3) {
                         // R_a = v.grad v_a - pi v . grad pi v_a, tested with
                         // v.grad phi (own vertices) and pi v . grad pi phi
                         // (patch corners)
                         const float deltaT = P.delta0 / den;
-                        float xv[3][8], piv[3][8], pa[8], va[8];
+                        float ca[8], va[8];
 #pragma unroll
-                        for (int d = 0; d < 3; ++d) {
-                            float w[8], pw[8];
-#pragma unroll
-                            for (int j = 0; j < 8; ++j) w[j] = sX[d * T::SN + xb + xoff(j)];
-                            eval_val(w, xv[d]);
-#pragma unroll
-                            for (int j = 0; j < 8; ++j) w[j] = sX[d * T::SN + cb + coff(j)];
-                            pi_vertices(w, ox, oy, oz, pw);
-                            eval_val(pw, piv[d]);
+                        for (int j = 0; j < 8; ++j) {
+                            ca[j] = sX[a * T::SN + cb + coff(j)];
+                            va[j] = sX[a * T::SN + xb + xoff(j)];
                         }
-                        {
-                            float w[8];
-#pragma unroll
-                            for (int j = 0; j < 8; ++j) w[j] = sX[a * T::SN + cb + coff(j)];
-                            pi_vertices(w, ox, oy, oz, pa);
-#pragma unroll
-                            for (int j = 0; j < 8; ++j) va[j] = sX[a * T::SN + xb + xoff(j)];
-                        }
-                        float tmp[8], g0[8], g1[8], g2[8], h0[8], h1[8], h2[8];
+                        float tmp[8], g0[8], g1[8], g2[8], HX[4], HY[4], HZ[4];
                         eval_vg(va, ih0, ih1, ih2, tmp, g0, g1, g2);
-                        eval_vg(pa, ih0, ih1, ih2, tmp, h0, h1, h2);
+                        patch_grad(ca, sx, sy, sz, ih0, ih1, ih2, HX, HY, HZ);
                         float C0[8], C1[8], C2[8];
 #pragma unroll
                         for (int q = 0; q < 8; ++q) {
+                            const int qa = q & 1, qb = (q >> 1) & 1, qc = q >> 2;
                             float R = (xv[0][q] * g0[q] + xv[1][q] * g1[q] + xv[2][q] * g2[q]) -
-                                      (piv[0][q] * h0[q] + piv[1][q] * h1[q] + piv[2][q] * h2[q]);
+                                      (piv[0][q] * HX[qb + 2 * qc] + piv[1][q] * HY[qa + 2 * qc] +
+                                       piv[2][q] * HZ[qa + 2 * qb]);
                             float dR = deltaT * R;
                             g0[q] = -dR * xv[0][q];
                             g1[q] = -dR * xv[1][q];
@@ -654,9 +784,7 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
                             tmp[q] = 0.0f;
                         }
                         integrate<true, true, true>(tmp, g0, g1, g2, ih0, ih1, ih2, acc);
-                        float cvals[8];
-                        integrate<true, true, true>(tmp, C0, C1, C2, ih0, ih1, ih2, cvals);
-                        pi_transpose(cvals, ox, oy, oz, cor);
+                        patch_integrate_grad(C0, C1, C2, sx, sy, sz, ih0, ih1, ih2, cor);
                     } else {
                         // -alpha_T (grad(p - pi p), grad(xi - pi xi))
                         const float alphaT = P.alpha0 / den;
@@ -719,8 +847,8 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
             if constexpr (mode_against_b(MODE)) {
                 // r = b - A(x): vp carries b [4][n_fine]
 #pragma unroll
-                for (int f = 0; f < 3; ++f) out[f * nfn + g] = dir ? 0.0f : vp[f * nfn + g] + res[f];
-                out[3 * nfn + g] = vp[3 * nfn + g] + res[3];
+                for (int f = 0; f < 3; ++f) out[f * nfn + g] = dir ? 0.0f : bown[f] + res[f];
+                out[3 * nfn + g] = bown[3] + res[3];
             } else {
 #pragma unroll
                 for (int f = 0; f < 3; ++f) out[f * nfn + g] = dir ? 0.0f : res[f];
