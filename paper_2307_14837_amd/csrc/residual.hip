@@ -882,35 +882,44 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
 // tiles fill in after instead of doubling the critical path.  t in [0, F):
 // full tile; t in [F, G): partial tiles, as the slabs bz >= Fz, then
 // by >= Fy (bz < Fz), then bx >= Fx (by < Fy, bz < Fz).
-__device__ __forceinline__ void tile_of(int64_t t, const int G[3], const int F[3], int c[3]) {
-    const int64_t nf = (int64_t)F[0] * F[1] * F[2];
+__device__ __forceinline__ void tile_of(int64_t t64, const int G[3], const int F[3], int c[3]) {
+    // tile counts fit 32 bits (a tile holds hundreds of the < 2^31 nodes), and
+    // 32-bit divisions are a fraction of the 64-bit sequences
+    const uint32_t t = (uint32_t)t64;
+    const uint32_t g0 = G[0], g1 = G[1], f0 = F[0], f1 = F[1];
+    const uint32_t nf = f0 * f1 * (uint32_t)F[2];
     if (t < nf) {
-        c[0] = (int)(t % F[0]);
-        c[1] = (int)((t / F[0]) % F[1]);
-        c[2] = (int)(t / ((int64_t)F[0] * F[1]));
+        const uint32_t q = t / f0;
+        c[0] = (int)(t - q * f0);
+        c[1] = (int)(q % f1);
+        c[2] = (int)(q / f1);
         return;
     }
-    int64_t p = t - nf;
-    const int64_t r1 = (int64_t)(G[2] - F[2]) * G[0] * G[1];
+    uint32_t p = t - nf;
+    const uint32_t r1 = (uint32_t)(G[2] - F[2]) * g0 * g1;
     if (p < r1) {
-        c[0] = (int)(p % G[0]);
-        c[1] = (int)((p / G[0]) % G[1]);
-        c[2] = F[2] + (int)(p / ((int64_t)G[0] * G[1]));
+        const uint32_t q = p / g0;
+        c[0] = (int)(p - q * g0);
+        c[1] = (int)(q % g1);
+        c[2] = F[2] + (int)(q / g1);
         return;
     }
     p -= r1;
-    const int64_t r2 = (int64_t)(G[1] - F[1]) * G[0] * F[2];
+    const uint32_t gy = g1 - f1;
+    const uint32_t r2 = gy * g0 * (uint32_t)F[2];
     if (p < r2) {
-        c[0] = (int)(p % G[0]);
-        c[1] = F[1] + (int)((p / G[0]) % (G[1] - F[1]));
-        c[2] = (int)(p / ((int64_t)G[0] * (G[1] - F[1])));
+        const uint32_t q = p / g0;
+        c[0] = (int)(p - q * g0);
+        c[1] = F[1] + (int)(q % gy);
+        c[2] = (int)(q / gy);
         return;
     }
     p -= r2;
-    const int gx = G[0] - F[0];
-    c[0] = F[0] + (int)(p % gx);
-    c[1] = (int)((p / gx) % F[1]);
-    c[2] = (int)(p / ((int64_t)gx * F[1]));
+    const uint32_t gx = g0 - f0;
+    const uint32_t q = p / gx;
+    c[0] = F[0] + (int)(p - q * gx);
+    c[1] = (int)(q % f1);
+    c[2] = (int)(q / f1);
 }
 
 // STRIDED = false: one tile per block (the grid covers the tiles);
