@@ -13,6 +13,8 @@
 // Element types: FP32 (v_mfma_f32_16x16x4f32), BF16 (v_mfma_f32_16x16x32_bf16)
 // and OCP FP8 E4M3 (v_mfma_scale_f32_16x16x128_f8f6f4) with per-tensor
 // scales; all accumulate in FP32 and apply bias and tanh in FP32.
+#include <type_traits>
+
 #include "common.hpp"
 #include "lowp.hpp"
 #include "mlp.hpp"
@@ -154,35 +156,47 @@ __device__ __forceinline__ void layer(const typename Frag<K>::T *__restrict__ Wl
     // together (8-wave tiles have few output tiles per wave, so a whole
     // layer's weight fragments fit in registers and are requested at once)
     constexpr int UNROLL = (NW == 8 && H <= 256) ? NCH : 2;
+    // products over the wave's first NT output tiles; the tile test sits
+    // outside the K loop, so a step's weight loads carry no branch and are
+    // requested together
+    auto products = [&](auto nt) {
+        constexpr int NT = decltype(nt)::value;
 #pragma unroll UNROLL
-    for (int kc = 0; kc < NCH; ++kc) {
-        FA b[PT];
+        for (int kc = 0; kc < NCH; ++kc) {
+            FA b[PT];
 #pragma unroll
-        for (int t = 0; t < PT; ++t) b[t] = ((const FA *)in)[(t * NCH + kc) * 64 + lane];
+            for (int t = 0; t < PT; ++t) b[t] = ((const FA *)in)[(t * NCH + kc) * 64 + lane];
 #pragma unroll
-        for (int i = 0; i < OTW; ++i) {
-            const int ot = wave + NW * i;
-            if (NTILES % NW == 0 || ot < NTILES) {
-                FA a = Wl[((int64_t)kc * NTILES + ot) * 64 + lane];
+            for (int i = 0; i < NT; ++i) {
+                FA a = Wl[((int64_t)kc * NTILES + wave + NW * i) * 64 + lane];
 #pragma unroll
                 for (int t = 0; t < PT; ++t) acc[i][t] = mfma<K>(a, b[t], acc[i][t]);
             }
         }
-    }
+    };
+    if (NTILES % NW == 0 || wave + NW * (OTW - 1) < NTILES) products(std::integral_constant<int, OTW>{});
+    else if constexpr (OTW > 1) products(std::integral_constant<int, OTW - 1>{});
 #pragma unroll
     for (int i = 0; i < OTW; ++i) {
         const int ot = wave + NW * i;
         if (!(NTILES % NW == 0 || ot < NTILES)) continue;
         if constexpr (LAST) {
             // outputs of the tile to LDS rows [16 t + p][81]; written out
-            // contiguously afterwards
+            // contiguously afterwards (the lane's four biases are loaded
+            // once, clamped to the last output, without a branch)
             float *ys = (float *)out;
+            float bl[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int o = 16 * ot + 4 * g + e;
+                bl[e] = bias[o < N_OUT ? o : N_OUT - 1];
+            }
 #pragma unroll
             for (int t = 0; t < PT; ++t) {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     int o = 16 * ot + 4 * g + e;
-                    if (o < N_OUT) ys[(16 * t + p) * N_OUT + o] = acc[i][t][e] * scale + bias[o];
+                    if (o < N_OUT) ys[(16 * t + p) * N_OUT + o] = acc[i][t][e] * scale + bl[e];
                 }
             }
         } else {

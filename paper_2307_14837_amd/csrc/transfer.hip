@@ -243,16 +243,18 @@ __device__ __forceinline__ void scatter_node(const Mesh &m, int64_t t, const flo
     if (t >= m.n_fine) return;
     uint32_t jk = fdiv((uint32_t)t, m.fx), i = (uint32_t)t - jk * m.nf[0];
     uint32_t k = fdiv(jk, m.fy), j = jk - k * m.nf[1];
+    // the base field is requested with the network outputs (one round trip)
+    float b[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (vbase)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) b[c] = vbase[c * m.n_fine + t];
     float v[3];
     extension_at(m, (int)i, (int)j, (int)k, Y, v);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        if (vbase) v[c] += vbase[c * m.n_fine + t];
-        d[c * m.n_fine + t] = v[c];
-    }
+    for (int c = 0; c < 3; ++c) d[c * m.n_fine + t] = vbase ? v[c] + b[c] : v[c];
     // the network predicts no pressure correction: the corrected iterate
     // keeps the prolongated pressure
-    if (vbase) d[3 * m.n_fine + t] = vbase[3 * m.n_fine + t];
+    if (vbase) d[3 * m.n_fine + t] = b[3];
 }
 
 __global__ void __launch_bounds__(256) k_scatter(Mesh m, const float *__restrict__ Y,
