@@ -316,11 +316,19 @@ __device__ __forceinline__ void stage_gather(const Mesh &m, const float *__restr
                 v[f] = xt[f * m.n_fine + node];
                 v[3 + f] = r[f * m.n_fine + node];
             }
+            // the standardisation constants are requested with the node
+            // values (a branch per field would wait for each load in turn)
+            float sh[6], sc[6];
+            if (shift)
+#pragma unroll
+                for (int f = 0; f < 6; ++f) sh[f] = shift[27 * f + iota];
+            if (inv)
+#pragma unroll
+                for (int f = 0; f < 6; ++f) sc[f] = inv[27 * f + iota];
 #pragma unroll
             for (int f = 0; f < 6; ++f) {
-                const int col = 27 * f + iota;
-                if (shift) v[f] -= shift[col];
-                if (inv) v[f] *= inv[col];
+                if (shift) v[f] -= sh[f];
+                if (inv) v[f] *= sc[f];
             }
         }
 #pragma unroll
@@ -328,11 +336,13 @@ __device__ __forceinline__ void stage_gather(const Mesh &m, const float *__restr
     }
     for (int it = tid; it < 16 * PT * (IN_PAD - 162); it += NTHR) {
         const int pl = it / (IN_PAD - 162), col = 162 + (it - pl * (IN_PAD - 162));
+        const int cc = col < N_IN ? col : N_IN - 1;
+        const float sh = shift ? shift[cc] : 0.0f, sc = inv ? inv[cc] : 1.0f;
         float v = 0.0f;
         if (col < N_IN && base + pl < n) {
             v = m.H[col - 162];
-            if (shift) v -= shift[col];
-            if (inv) v *= inv[col];
+            if (shift) v -= sh;
+            if (inv) v *= sc;
         }
         put_input<K1, NCH0>(buf, pl, col, v);
     }

@@ -416,10 +416,15 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
             cj = wrap(cj, m.nc[1], m.per[1]);
             ck = wrap(ck, m.nc[2], m.per[2]);
             const bool ok = ci >= 0 && ci < m.nc[0] && cj >= 0 && cj < m.nc[1] && ck >= 0 && ck < m.nc[2];
-            const int64_t g = ci + (int64_t)m.nc[0] * (cj + (int64_t)m.nc[1] * ck);
+            // absent nodes read node 0 and discard it: the loads carry no
+            // branch and go out together
+            const int64_t g = ok ? ci + (int64_t)m.nc[0] * (cj + (int64_t)m.nc[1] * ck) : 0;
+            double d[4];
+#pragma unroll
+            for (int f = 0; f < 4; ++f) d[f] = xc[f * ncn + g];
             float v[4];
 #pragma unroll
-            for (int f = 0; f < 4; ++f) v[f] = ok ? (float)xc[f * ncn + g] : 0.0f;
+            for (int f = 0; f < 4; ++f) v[f] = ok ? (float)d[f] : 0.0f;
 #pragma unroll
             for (int f = 0; f < 4; ++f) sC[f * T::CN + s] = v[f];
         }
@@ -461,8 +466,11 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
             bool ok;
             int64_t g = gnode(x0 - 2 + lx, y0 - 2 + ly, z0 - 2 + lz, ok);
             ok &= s < T::SN;
+            g = ok ? g : 0; // absent nodes read node 0 and discard it
 #pragma unroll
-            for (int f = 0; f < 4; ++f) tmp[it][f] = ok ? x[f * nfn + g] : 0.0f;
+            for (int f = 0; f < 4; ++f) tmp[it][f] = x[f * nfn + g];
+#pragma unroll
+            for (int f = 0; f < 4; ++f) tmp[it][f] = ok ? tmp[it][f] : 0.0f;
         }
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
@@ -482,8 +490,11 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
             bool ok;
             int64_t g = gnode(x0 - 1 + lx, y0 - 1 + ly, z0 - 1 + lz, ok);
             ok &= s < T::VN;
+            g = ok ? g : 0; // absent nodes read node 0 and discard it
 #pragma unroll
-            for (int f = 0; f < 3; ++f) tmp[it][f] = ok ? src[f * nfn + g] : 0.0f;
+            for (int f = 0; f < 3; ++f) tmp[it][f] = src[f * nfn + g];
+#pragma unroll
+            for (int f = 0; f < 3; ++f) tmp[it][f] = ok ? tmp[it][f] : 0.0f;
         }
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
@@ -1014,7 +1025,7 @@ __device__ __forceinline__ void lps_corner_node(const Mesh &m, int64_t t, const 
     uint32_t JK = fdiv((uint32_t)t, m.cx), I = (uint32_t)t - JK * m.nc[0];
     uint32_t K = fdiv(JK, m.cy), J = JK - K * m.nc[1];
     // patches with this vertex as a corner, per axis, ascending
-    int P[3][2], L[3][2], cnt[3];
+    int P[3][2] = {}, L[3][2] = {}, cnt[3];
     const int C[3] = {(int)I, (int)J, (int)K};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -1032,30 +1043,45 @@ __device__ __forceinline__ void lps_corner_node(const Mesh &m, int64_t t, const 
     }
     // a patch's corner sums exist when its residual tile had LPS work
     constexpr int PX = ResTile<MODE_RES>::NPX, PY = ResTile<MODE_RES>::NPY, PZ = ResTile<MODE_RES>::NPZ;
-    float s[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    bool any = false;
-    for (int c = 0; c < cnt[2]; ++c)
-        for (int b = 0; b < cnt[1]; ++b)
-            for (int a = 0; a < cnt[0]; ++a) {
-                const int tl = P[0][a] / PX + rt[0] * (P[1][b] / PY + rt[1] * (P[2][c] / PZ));
-                if (!tflag[tl]) continue;
-                any = true;
-                int64_t M = P[0][a] + (int64_t)m.n[0] * (P[1][b] + (int64_t)m.n[1] * P[2][c]);
-                int j = L[0][a] + 2 * L[1][b] + 4 * L[2][c];
-                const float4 v = *(const float4 *)(aux + M * 32 + 4 * j);
-                s[0] += v.x;
-                s[1] += v.y;
-                s[2] += v.z;
-                s[3] += v.w;
-            }
-    if (!any) return;
+    // all 2 x 2 x 2 candidates (a fastest), their tile flags, corner sums
+    // and the node's residual are requested at once; absent candidates read
+    // patch 0 and are skipped in the sums, which run in the same order
+    int fl[8];
+    float4 v[8];
+    bool valid[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int a = q & 1, b = (q >> 1) & 1, c = q >> 2;
+        valid[q] = a < cnt[0] && b < cnt[1] && c < cnt[2];
+        const int pa = valid[q] ? P[0][a] : 0, pb = valid[q] ? P[1][b] : 0, pc = valid[q] ? P[2][c] : 0;
+        const int tl = pa / PX + rt[0] * (pb / PY + rt[1] * (pc / PZ));
+        fl[q] = tflag[tl];
+        const int64_t M = pa + (int64_t)m.n[0] * (pb + (int64_t)m.n[1] * pc);
+        const int j = L[0][a] + 2 * L[1][b] + 4 * L[2][c];
+        v[q] = *(const float4 *)(aux + M * 32 + 4 * j);
+    }
     int gi = 2 * I, gj = 2 * J, gk = 2 * K;
     int64_t g = gi + (int64_t)m.nf[0] * (gj + (int64_t)m.nf[1] * gk);
+    float rv[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) rv[f] = r[f * m.n_fine + g];
+    float s[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        if (!valid[q] || !fl[q]) continue;
+        any = true;
+        s[0] += v[q].x;
+        s[1] += v[q].y;
+        s[2] += v[q].z;
+        s[3] += v[q].w;
+    }
+    if (!any) return;
     bool dir = on_dirichlet(m, gi, gj, gk);
 #pragma unroll
     for (int f = 0; f < 3; ++f)
-        if (!dir) r[f * m.n_fine + g] += s[f];
-    r[3 * m.n_fine + g] += s[3];
+        if (!dir) r[f * m.n_fine + g] = rv[f] + s[f];
+    r[3 * m.n_fine + g] = rv[3] + s[3];
 }
 
 __global__ void __launch_bounds__(256) k_lps_corners(Mesh m, const float *__restrict__ aux,

@@ -63,30 +63,42 @@ __global__ void __launch_bounds__(256)
             const int e = tid + 256 * r;
             int mm, kk;
             if (TA) { mm = e % BM; kk = e / BM; } else { kk = e % BK; mm = e / BK; }
+            // out-of-range elements read the last row / column (k0 < kend,
+            // M, N >= 1): the loads carry no branch and go out together;
+            // store() zeroes them
             int64_t gm = m0 + mm, gk = k0 + kk;
-            ra[r] = (gm < M && gk < kend) ? (TA ? ld(A, gk * lda + gm) : ld(A, gm * lda + gk)) : 0.f;
+            gm = gm < M ? gm : M - 1;
+            gk = gk < kend ? gk : kend - 1;
+            ra[r] = TA ? ld(A, gk * lda + gm) : ld(A, gm * lda + gk);
             int nn;
             if (TB) { kk = e % BK; nn = e / BK; } else { nn = e % BN; kk = e / BN; }
-            const int64_t gn = n0 + nn;
+            int64_t gn = n0 + nn;
+            gn = gn < N ? gn : N - 1;
             gk = k0 + kk;
-            rb[r] = (gn < N && gk < kend) ? (TB ? ld(B, gn * ldb + gk) : ld(B, gk * ldb + gn)) : 0.f;
+            gk = gk < kend ? gk : kend - 1;
+            rb[r] = TB ? ld(B, gn * ldb + gk) : ld(B, gk * ldb + gn);
         }
     };
-    auto store = [&]() {
+    auto store = [&](int64_t k0) {
 #pragma unroll
         for (int r = 0; r < STAGE; ++r) {
             const int e = tid + 256 * r;
-            if (TA) As[e / BM][e % BM] = ra[r];
-            else As[e % BK][e / BK] = ra[r];
-            if (TB) Bs[e % BK][e / BK] = rb[r];
-            else Bs[e / BN][e % BN] = rb[r];
+            int mm, kk, nn, kb;
+            if (TA) { mm = e % BM; kk = e / BM; } else { kk = e % BK; mm = e / BK; }
+            if (TB) { kb = e % BK; nn = e / BK; } else { nn = e % BN; kb = e / BN; }
+            const float va = (m0 + mm < M && k0 + kk < kend) ? ra[r] : 0.f;
+            const float vb = (n0 + nn < N && k0 + kb < kend) ? rb[r] : 0.f;
+            if (TA) As[e / BM][e % BM] = va;
+            else As[e % BK][e / BK] = va;
+            if (TB) Bs[e % BK][e / BK] = vb;
+            else Bs[e / BN][e % BN] = vb;
         }
     };
     const bool csum = colsum && blockIdx.x == 0 && tid < BN;
     float cs = 0.f;
     if (kbeg < kend) load(kbeg);
     for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
-        store();
+        store(k0);
         __syncthreads();
         if (k0 + BK < kend) load(k0 + BK);
         if (csum)
@@ -170,22 +182,29 @@ __global__ void __launch_bounds__(256)
         for (int r = 0; r < 8; ++r)
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                const int64_t gk = k0 + kh + 4 * r + h;
-                const bool kin = gk < kend;
-                ra[r][h] = (kin && m0 + c < M) ? A[gk * lda + m0 + c] : (uint16_t)0;
-                rb[r][h] = (kin && n0 + c < N) ? B[gk * N + n0 + c] : 0.0f;
+                // clamped reads with no branch (k0 < kend, M, N >= 1); the
+                // staging below zeroes the out-of-range ones
+                int64_t gk = k0 + kh + 4 * r + h;
+                gk = gk < kend ? gk : kend - 1;
+                const int64_t mc = m0 + c < M ? m0 + c : M - 1, nc = n0 + c < N ? n0 + c : N - 1;
+                ra[r][h] = A[gk * lda + mc];
+                rb[r][h] = B[gk * N + nc];
             }
     };
     const bool csum = colsum && blockIdx.x == 0;
     float cs = 0.f;
     if (kbeg < kend) load(kbeg);
+    const bool mok = m0 + c < M, nok = n0 + c < N;
     for (int64_t k0 = kbeg; k0 < kend; k0 += WK) {
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
             const int kk = kh + 4 * r;
-            *(uint32_t *)&As[c * WKP + kk] = (uint32_t)ra[r][0] | ((uint32_t)ra[r][1] << 16);
-            *(uint32_t *)&Bs[c * WKP + kk] = pack_bf16x2_hw(rb[r][0], rb[r][1]);
-            if (csum) cs += rb[r][0] + rb[r][1];
+            const bool k0ok = k0 + kk < kend, k1ok = k0 + kk + 1 < kend;
+            const uint16_t a0 = (k0ok && mok) ? ra[r][0] : (uint16_t)0, a1 = (k1ok && mok) ? ra[r][1] : (uint16_t)0;
+            const float b0 = (k0ok && nok) ? rb[r][0] : 0.0f, b1 = (k1ok && nok) ? rb[r][1] : 0.0f;
+            *(uint32_t *)&As[c * WKP + kk] = (uint32_t)a0 | ((uint32_t)a1 << 16);
+            *(uint32_t *)&Bs[c * WKP + kk] = pack_bf16x2_hw(b0, b1);
+            if (csum) cs += b0 + b1;
         }
         __syncthreads();
         if (k0 + WK < kend) load(k0 + WK);
@@ -246,11 +265,15 @@ __global__ void __launch_bounds__(256)
     auto load = [&](int64_t k0) {
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-            const int64_t k = k0 + kq + e;
-            ra[e] = (m0 + row < M && k < K) ? A[(m0 + row) * lda + k] : 0.0f;
-            rw[e] = (n0 + row < N && k < K) ? W[(n0 + row) * ldw + k] : 0.0f;
+            // clamped reads with no branch (K, M, N >= 1); the staging
+            // below zeroes the out-of-range ones
+            const int64_t k = k0 + kq + e < K ? k0 + kq + e : K - 1;
+            const int64_t mr = m0 + row < M ? m0 + row : M - 1, nr = n0 + row < N ? n0 + row : N - 1;
+            ra[e] = A[mr * lda + k];
+            rw[e] = W[nr * ldw + k];
         }
     };
+    const bool mok = m0 + row < M, nok = n0 + row < N;
     load(0);
     for (int64_t k0 = 0; k0 < K; k0 += WK) {
         u32x4_t pa[2], pw[2];
@@ -258,8 +281,10 @@ __global__ void __launch_bounds__(256)
         for (int h = 0; h < 2; ++h)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                pa[h][q] = pack_bf16x2_hw(ra[8 * h + 2 * q], ra[8 * h + 2 * q + 1]);
-                pw[h][q] = pack_bf16x2_hw(rw[8 * h + 2 * q], rw[8 * h + 2 * q + 1]);
+                const int e0 = 8 * h + 2 * q;
+                const bool k0ok = k0 + kq + e0 < K, k1ok = k0 + kq + e0 + 1 < K;
+                pa[h][q] = pack_bf16x2_hw((mok && k0ok) ? ra[e0] : 0.0f, (mok && k1ok) ? ra[e0 + 1] : 0.0f);
+                pw[h][q] = pack_bf16x2_hw((nok && k0ok) ? rw[e0] : 0.0f, (nok && k1ok) ? rw[e0 + 1] : 0.0f);
             }
         *(u32x4_t *)&As[row * WKP + kq] = pa[0];
         *(u32x4_t *)&As[row * WKP + kq + 8] = pa[1];

@@ -195,6 +195,15 @@ __global__ void __launch_bounds__(256)
     const int col0 = (int)(threadIdx.x - local * quads) * 4;
     uint32_t J_K = fdiv((uint32_t)M, m.px), I = (uint32_t)M - J_K * m.n[0];
     uint32_t K = fdiv(J_K, m.py), J = J_K - K * m.n[1];
+    // standardisation constants (clamped to the last input column) are
+    // requested with the node values
+    float sh[4], sc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int cc = col0 + q < 165 ? col0 + q : 164;
+        sh[q] = shift ? shift[cc] : 0.0f;
+        sc[q] = inv_scale ? inv_scale[cc] : 1.0f;
+    }
     float z[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -212,8 +221,8 @@ __global__ void __launch_bounds__(256)
             v = m.H[col - 162];
         }
         if (col < 165) {
-            if (shift) v -= shift[col];
-            if (inv_scale) v *= inv_scale[col];
+            if (shift) v -= sh[q];
+            if (inv_scale) v *= sc[q];
         }
         z[q] = v;
     }
