@@ -23,7 +23,8 @@ import csv
 import json
 from collections import defaultdict
 
-ENTRY_KERNELS = {"dnnmg_prolong_residual": ("k_residual<2>",), "dnnmg_prolong_residual_b": ("k_residual<3>",)}
+ENTRY_KERNELS = {"dnnmg_prolong_residual": ("k_residual<2, false>",),
+                 "dnnmg_prolong_residual_b": ("k_residual<3, false>",)}
 COPY_KERNEL = "neg"
 
 
