@@ -251,24 +251,66 @@ __global__ void __launch_bounds__(256)
               float *__restrict__ C, int64_t ldc) {
     __shared__ __attribute__((aligned(16))) uint16_t As[WB * WKP];
     __shared__ __attribute__((aligned(16))) uint16_t Bs[WB * WKP];
+    constexpr int SP = WB + 8; // row pitch of the S tile in LDS
+    __shared__ __attribute__((aligned(16))) uint16_t Ss[WB * SP];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t m0 = (int64_t)blockIdx.x * WB, n0 = (int64_t)blockIdx.y * WB;
     const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
     const int g = lane >> 4, i16 = lane & 15;
     const int row = tid >> 1, kq = (tid & 1) * 16; // staged row and its 16 K
+    // the tile's saved activations (row `row`, 64 columns per thread) are
+    // requested now and held through the K loop, then staged in LDS for the
+    // epilogue: one round trip, hidden behind the products (clamped reads;
+    // the epilogue writes only the elements inside the matrix)
+    u32x4_t sreg[8];
+    {
+        const int64_t sr = m0 + row < M ? m0 + row : M - 1;
+        const int64_t c0 = n0 + 64 * (tid & 1);
+        if (n0 + WB <= N && lds_ % 8 == 0 && ((uintptr_t)S & 15) == 0) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) sreg[j] = *(const u32x4_t *)(S + sr * lds_ + c0 + 8 * j);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                uint32_t w[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t ca = c0 + 8 * j + 2 * q, cb = ca + 1;
+                    const uint32_t lo = S[sr * lds_ + (ca < N ? ca : N - 1)];
+                    const uint32_t hi = S[sr * lds_ + (cb < N ? cb : N - 1)];
+                    w[q] = lo | (hi << 16);
+                }
+                sreg[j] = u32x4_t{w[0], w[1], w[2], w[3]};
+            }
+        }
+    }
     f32x4 acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
     float ra[16], rw[16];
+    // 16-byte loads when the rows allow them (K a multiple of the step and
+    // 16-byte aligned rows), else clamped element reads
+    const bool vec = K % WK == 0 && lda % 4 == 0 && ldw % 4 == 0 && ((uintptr_t)A & 15) == 0 &&
+                     ((uintptr_t)W & 15) == 0;
     auto load = [&](int64_t k0) {
+        const int64_t mr = m0 + row < M ? m0 + row : M - 1, nr = n0 + row < N ? n0 + row : N - 1;
+        if (vec) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float4 va = *(const float4 *)(A + mr * lda + k0 + kq + 4 * q);
+                const float4 vw = *(const float4 *)(W + nr * ldw + k0 + kq + 4 * q);
+                ra[4 * q] = va.x, ra[4 * q + 1] = va.y, ra[4 * q + 2] = va.z, ra[4 * q + 3] = va.w;
+                rw[4 * q] = vw.x, rw[4 * q + 1] = vw.y, rw[4 * q + 2] = vw.z, rw[4 * q + 3] = vw.w;
+            }
+            return;
+        }
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
             // clamped reads with no branch (K, M, N >= 1); the staging
             // below zeroes the out-of-range ones
             const int64_t k = k0 + kq + e < K ? k0 + kq + e : K - 1;
-            const int64_t mr = m0 + row < M ? m0 + row : M - 1, nr = n0 + row < N ? n0 + row : N - 1;
             ra[e] = A[mr * lda + k];
             rw[e] = W[nr * ldw + k];
         }
@@ -307,14 +349,18 @@ __global__ void __launch_bounds__(256)
         __syncthreads();
     }
 #pragma unroll
+    for (int j = 0; j < 8; ++j) *(u32x4_t *)&Ss[row * SP + 64 * (tid & 1) + 8 * j] = sreg[j];
+    __syncthreads();
+#pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int64_t gm = m0 + wm + 16 * a + 4 * g + e, gn = n0 + wn + 16 * b + i16;
+                const int lm = wm + 16 * a + 4 * g + e, ln = wn + 16 * b + i16;
+                const int64_t gm = m0 + lm, gn = n0 + ln;
                 if (gm < M && gn < N) {
-                    const float sv = bf16_to_f32(S[gm * lds_ + gn]);
+                    const float sv = bf16_to_f32(Ss[lm * SP + ln]);
                     C[gm * ldc + gn] = acc[a][b][e] * (1.0f - sv * sv);
                 }
             }
