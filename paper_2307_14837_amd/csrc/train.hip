@@ -177,7 +177,21 @@ __global__ void __launch_bounds__(256)
         for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
     uint16_t ra[8][2];
     float rb[8][2];
+    const int64_t mc = m0 + c < M ? m0 + c : M - 1, nc = n0 + c < N ? n0 + c : N - 1;
     auto load = [&](int64_t k0) {
+        if (k0 + WK <= kend) {
+            // a whole step inside the range: fixed offsets from the step's rows
+            const uint16_t *pa = A + (k0 + kh) * lda + mc;
+            const float *pb = B + (k0 + kh) * N + nc;
+#pragma unroll
+            for (int r = 0; r < 8; ++r)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    ra[r][h] = pa[(4 * r + h) * lda];
+                    rb[r][h] = pb[(4 * r + h) * N];
+                }
+            return;
+        }
 #pragma unroll
         for (int r = 0; r < 8; ++r)
 #pragma unroll
@@ -186,7 +200,6 @@ __global__ void __launch_bounds__(256)
                 // staging below zeroes the out-of-range ones
                 int64_t gk = k0 + kh + 4 * r + h;
                 gk = gk < kend ? gk : kend - 1;
-                const int64_t mc = m0 + c < M ? m0 + c : M - 1, nc = n0 + c < N ? n0 + c : N - 1;
                 ra[r][h] = A[gk * lda + mc];
                 rb[r][h] = B[gk * N + nc];
             }
