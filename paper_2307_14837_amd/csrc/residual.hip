@@ -621,8 +621,11 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
         // computed here agree bit for bit every LPS contribution of the cell
         // is exactly zero; the other cells get them in a second pass.
         if (mode_general(MODE) && live) {
+            // field by field until one differs (a wave whose cells all
+            // differ in the first field skips the other three)
 #pragma unroll
             for (int d = 0; d < 4; ++d) {
+                if (need) break;
                 float cv[8], pw[8];
 #pragma unroll
                 for (int j = 0; j < 8; ++j) cv[j] = sX[d * T::SN + cb + coff(j)];
