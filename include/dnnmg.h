@@ -279,6 +279,13 @@ size_t dnnmg_norm2_workspace(void);
 int dnnmg_norm2_f64(int64_t n, const float *a, const float *b, double *out, void *ws,
                     size_t ws_bytes, void *stream);
 
+/* Both squared norms of the residual indicator in one pass: out[0] =
+ * ||a0||^2, out[1] = ||a1||^2 (FP64, device), each bit for bit what
+ * dnnmg_norm2_f64 gives for that vector alone (same partition, same order).
+ * ws: device workspace of 2 * dnnmg_norm2_workspace() bytes. */
+int dnnmg_norm2_pair_f64(int64_t n, const float *a0, const float *a1, double *out, void *ws, size_t ws_bytes,
+                         void *stream);
+
 /* Plain fine-level correction used by the residual-indicator fallback:
  * `sweeps` additive patch sweeps with the local problems of the Vanka
  * smoother (Sec. 2.4) on the patches of Sec. 4.2, in place on x FP32

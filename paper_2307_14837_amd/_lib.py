@@ -102,6 +102,7 @@ _sig("dnnmg_scatter_avg", [_P(Box), c_vp, c_vp, c_vp, c_vp])
 _sig("dnnmg_scatter_avg_form", [_P(Box), c_vp, c_vp, c_vp, ctypes.c_int, c_vp])
 _sig("dnnmg_norm2_workspace", [], c_sz)
 _sig("dnnmg_norm2_f64", [c_i64, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp])
+_sig("dnnmg_norm2_pair_f64", [c_i64, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp])
 _sig("dnnmg_mse_grad", [c_i64, c_vp, c_vp, c_vp, c_vp])
 _sig("dnnmg_patch_backward_workspace", [_P(MLP), c_i64], c_sz)
 _sig("dnnmg_patch_backward", [_P(MLP), c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_vp, c_vp * 3, c_vp * 3,
@@ -136,7 +137,7 @@ EXPORTS = [
     "dnnmg_vanka_workspace", "dnnmg_vanka_sweeps", "dnnmg_fallback_workspace", "dnnmg_fallback",
     "dnnmg_patch_gather_forward", "dnnmg_plan_workspace", "dnnmg_plan_create", "dnnmg_plan_destroy",
     "dnnmg_plan_sizes", "dnnmg_plan_choice", "dnnmg_batch_step", "dnnmg_plan_autotune",
-    "dnnmg_batch_step_b", "dnnmg_batch_rhs",
+    "dnnmg_batch_step_b", "dnnmg_batch_rhs", "dnnmg_norm2_pair_f64",
 ]
 
 
@@ -339,6 +340,13 @@ def dnnmg_norm2_f64(a, out, ws, b=None, n=None, stream=None):
     _check(_lib.dnnmg_norm2_f64(int(n), _ptr(a, torch.float32, n, "a"), _ptr(b, torch.float32, n, "b"),
                                 _ptr(out, torch.float64, 1, "out"), _ptr(ws, None, None, "ws"),
                                 ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def dnnmg_norm2_pair_f64(a0, a1, out, ws, n=None, stream=None):
+    n = a0.numel() if n is None else n
+    _check(_lib.dnnmg_norm2_pair_f64(int(n), _ptr(a0, torch.float32, n, "a0"), _ptr(a1, torch.float32, n, "a1"),
+                                     _ptr(out, torch.float64, 2, "out"), _ptr(ws, None, None, "ws"),
+                                     ws.numel() * ws.element_size(), _stream(stream)))
 
 
 def dnnmg_mse_grad(Y, T, dY, n=None, stream=None):

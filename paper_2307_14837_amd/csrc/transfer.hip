@@ -486,9 +486,17 @@ __global__ void __launch_bounds__(ST_NT) k_scatter_tiled(Mesh m, int gx, int gy,
 // -------------------------------------------------------------- norms -----
 constexpr int NORM_BLOCKS = 1024;
 
+// Block (x, y) sums vector y (a, or a1 for y = 1) over the grid-stride
+// range of x; part[y][x].  Every vector is reduced over the same partition
+// in the same order, whichever launch it is in.
 __global__ void __launch_bounds__(256) k_norm_partial(int64_t n, const float *__restrict__ a,
                                                       const float *__restrict__ b,
+                                                      const float *__restrict__ a1,
                                                       double *__restrict__ part) {
+    if (blockIdx.y == 1) {
+        a = a1;
+        b = nullptr;
+    }
     double s = 0.0;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
          t += (int64_t)gridDim.x * blockDim.x) {
@@ -502,12 +510,15 @@ __global__ void __launch_bounds__(256) k_norm_partial(int64_t n, const float *__
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = red[0];
 }
 
+// Block y sums part[y][0 .. nparts) into out[y].
 __global__ void __launch_bounds__(256) k_norm_final(int nparts, const double *__restrict__ part,
                                                     double *__restrict__ out) {
     __shared__ double red[256];
+    part += (int64_t)blockIdx.x * nparts;
+    out += blockIdx.x;
     double s = 0.0;
     for (int t = threadIdx.x; t < nparts; t += 256) s += part[t];
     red[threadIdx.x] = s;
@@ -640,7 +651,19 @@ extern "C" int dnnmg_norm2_f64(int64_t n, const float *a, const float *b, double
     if (ws_bytes < dnnmg_norm2_workspace())
         return fail(DNNMG_ERR_SHAPE, "dnnmg_norm2_f64: workspace %zu < %zu bytes", ws_bytes,
                     dnnmg_norm2_workspace());
-    k_norm_partial<<<NORM_BLOCKS, 256, 0, STREAM>>>(n, a, b, (double *)ws);
+    k_norm_partial<<<NORM_BLOCKS, 256, 0, STREAM>>>(n, a, b, nullptr, (double *)ws);
     k_norm_final<<<1, 256, 0, STREAM>>>(NORM_BLOCKS, (const double *)ws, out);
     return hip_check(hipGetLastError(), "dnnmg_norm2_f64 launch");
+}
+
+extern "C" int dnnmg_norm2_pair_f64(int64_t n, const float *a0, const float *a1, double *out, void *ws,
+                                    size_t ws_bytes, void *stream) {
+    if (n < 0) return fail(DNNMG_ERR_SHAPE, "dnnmg_norm2_pair_f64: n < 0");
+    if (!a0 || !a1 || !out || !ws) return fail(DNNMG_ERR_ARG, "dnnmg_norm2_pair_f64: NULL pointer");
+    if (ws_bytes < 2 * dnnmg_norm2_workspace())
+        return fail(DNNMG_ERR_SHAPE, "dnnmg_norm2_pair_f64: workspace %zu < %zu bytes", ws_bytes,
+                    2 * dnnmg_norm2_workspace());
+    k_norm_partial<<<dim3(NORM_BLOCKS, 2), 256, 0, STREAM>>>(n, a0, nullptr, a1, (double *)ws);
+    k_norm_final<<<2, 256, 0, STREAM>>>(NORM_BLOCKS, (const double *)ws, out);
+    return hip_check(hipGetLastError(), "dnnmg_norm2_pair_f64 launch");
 }

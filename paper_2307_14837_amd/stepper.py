@@ -62,7 +62,7 @@ class CorrectionStep:
         if indicator:
             self.r2 = torch.zeros(4 * self.nf, **f32)
             self.norms = torch.zeros(2, **f64)
-            self.ws_norm = torch.zeros(L.norm2_workspace_bytes(), dtype=torch.uint8, device=self.dev)
+            self.ws_norm = torch.zeros(2 * L.norm2_workspace_bytes(), dtype=torch.uint8, device=self.dev)
             self.ws_fb = torch.zeros(L.fallback_workspace_bytes(self.box), dtype=torch.uint8, device=self.dev)
             self.fell_back = torch.zeros(1, dtype=torch.int32, device=self.dev)
         self.shift = None if shift is None else torch.as_tensor(np.asarray(shift, np.float32)).to(self.dev)
@@ -121,8 +121,7 @@ class CorrectionStep:
                 L.dnnmg_residual_b(box, ns, self.xcorr, self.b, self.r2, self.ws_res, stream=stream)
             else:
                 L.dnnmg_residual(box, ns, self.xcorr, self.vprev, self.r2, self.ws_res, stream=stream)
-            L.dnnmg_norm2_f64(self.r, self.norms[0:1], self.ws_norm, stream=stream)
-            L.dnnmg_norm2_f64(self.r2, self.norms[1:2], self.ws_norm, stream=stream)
+            L.dnnmg_norm2_pair_f64(self.r, self.r2, self.norms, self.ws_norm, stream=stream)
             if self.carry_rhs:
                 L.dnnmg_fallback_b(box, ns, self.xt, self.b, self.norms, self.xcorr, self.ws_fb,
                                    theta=self.theta, sweeps=self.fallback_sweeps, flag_out=self.fell_back,

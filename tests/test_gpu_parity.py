@@ -522,3 +522,13 @@ def test_norm2(L):
         np.testing.assert_allclose(out.item(), np.sum(a.astype(np.float64) ** 2), rtol=1e-12)
         L.dnnmg_norm2_f64(to_gpu(a), out, ws, b=to_gpu(b))
         np.testing.assert_allclose(out.item(), np.sum((a.astype(np.float64) - b) ** 2), rtol=1e-12)
+        # both vectors in one pass: each result equals its single-vector one
+        ws2 = torch.empty(2 * L.norm2_workspace_bytes(), dtype=torch.uint8, device=dev())
+        pair = torch.zeros(2, dtype=torch.float64, device=dev())
+        L.dnnmg_norm2_pair_f64(to_gpu(a), to_gpu(b), pair, ws2)
+        sa = torch.zeros(1, dtype=torch.float64, device=dev()); sb = torch.zeros(1, dtype=torch.float64, device=dev())
+        L.dnnmg_norm2_f64(to_gpu(a), sa, ws)
+        L.dnnmg_norm2_f64(to_gpu(b), sb, ws)
+        assert pair[0].item() == sa.item() and pair[1].item() == sb.item()
+    with pytest.raises(L.DnnmgError):
+        L.dnnmg_norm2_pair_f64(to_gpu(a), to_gpu(b), pair, ws)
