@@ -228,9 +228,11 @@ int dnnmg_mse_grad(int64_t n, const float *Y, const float *T, float *dY, void *s
  * for F32 or BF16 networks.  net gives dtype and width; W2 and W3 are the FP32
  * master weights of layers 2 and 3 (row-major [fan_in][fan_out]); X and ldx
  * are the forward's inputs and `saved` its activations.  dW[l] (FP32
- * row-major [fan_in][fan_out]) and db[l] are overwritten.  Products use
- * FP32 MFMA with FP32 accumulation; sums over patches are split into fixed
- * ranges and added in a fixed order (deterministic).  ws: device workspace of
+ * row-major [fan_in][fan_out]) and db[l] are overwritten.  Products run on
+ * the network's own element type (BF16 MFMA with operands rounded to BF16
+ * for a BF16 network, FP32 MFMA for an F32 network), always with FP32
+ * accumulation; sums over patches are split into fixed ranges and added in a
+ * fixed order (deterministic).  ws: device workspace of
  * dnnmg_patch_backward_workspace(net, n) bytes. */
 size_t dnnmg_patch_backward_workspace(const dnnmg_mlp *net, int64_t n);
 int dnnmg_patch_backward(const dnnmg_mlp *net, const float *W2, const float *W3, int64_t n,
@@ -310,7 +312,9 @@ int dnnmg_vanka_sweeps(const dnnmg_box *box, const dnnmg_ns *ns, float *x, const
  * If eta = ||r(x_corr)|| / ||r(x~)|| exceeds theta (or is NaN), x_corr FP32
  * [4][n_fine] is replaced by `sweeps` pressure-held sweeps of
  * dnnmg_vanka_sweeps started from x~; otherwise x_corr is left as it is and
- * the launched kernels exit at once.  flag_out (device int, optional)
+ * the launched kernels exit at once.  theta = +inf never falls back (only the
+ * indicator is evaluated); with ||r(x~)|| = 0 the fallback is taken only if
+ * ||r(x_corr)|| is not 0 as well (0/0 counts as eta = 0).  flag_out (device int, optional)
  * receives 1 when the fallback was taken.  ws: dnnmg_fallback_workspace(box)
  * bytes. */
 size_t dnnmg_fallback_workspace(const dnnmg_box *box);
@@ -352,11 +356,11 @@ int dnnmg_plan_sizes(const dnnmg_plan *plan, int64_t *n_fine, int64_t *n_coarse,
 int dnnmg_plan_choice(const dnnmg_plan *plan, int *patches_per_tile, int *grid);
 
 /* One correction step (Algorithm 1 after the coarse solve) for every box of
- * the plan in five kernel launches, independent of the number of boxes:
- * prolongation fused with the residual (as dnnmg_prolong_residual), fused
- * gather + network (persistent over the patch tiles of all boxes),
- * extension giving the corrected iterate (v~ + d, p~), right-hand side,
- * restriction (FP64).
+ * the plan in five kernel launches, independent of the number of boxes (not
+ * one fused launch): prolongation fused with the residual (as
+ * dnnmg_prolong_residual), gather + network in one persistent launch over
+ * the patch tiles of all boxes, extension giving the corrected iterate
+ * (v~ + d, p~), right-hand side, restriction (FP64).
  * Buffers (batch layout): xc FP64 [4 comps], vprev FP32 [3], xt, r, xcorr,
  * b FP32 [4], Y FP32 [patches][81], bc FP64 [4].  No forcing.  The step can
  * be captured in a HIP graph. */

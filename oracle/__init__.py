@@ -63,28 +63,34 @@ def lib():
     if _lib is None:
         if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
             build(force=True)
-        L = ctypes.CDLL(_LIB_PATH)
-        P = ctypes.POINTER
-        d = ctypes.c_double
-        i64 = ctypes.c_int64
-        dp = P(d)
-        L.or_fine_nodes.restype = i64
-        L.or_coarse_nodes.restype = i64
-        L.or_patches.restype = i64
-        L.or_mse.restype = d
-        L.or_norm2.restype = d
-        L.or_round_bf16.restype = d
-        L.or_round_bf16.argtypes = [d]
-        L.or_round_e4m3.restype = d
-        L.or_round_e4m3.argtypes = [d]
-        L.or_mlp_forward.argtypes = [i64, ctypes.c_int, ctypes.c_int, ctypes.c_int] + [dp] * 10
-        L.or_mlp_backward.argtypes = [i64, ctypes.c_int, ctypes.c_int, ctypes.c_int] + [dp] * 12
-        L.or_mse.argtypes = [i64, ctypes.c_int, dp, dp, dp]
-        L.or_adamw.argtypes = [i64, dp, dp, dp, dp, d, d, d, d, d, i64]
-        L.or_norm2.argtypes = [i64, dp, dp]
-        L.or_vanka_sweep.argtypes = [P(Box), P(NS), dp, dp, dp, d, ctypes.c_int, dp]
-        _lib = L
+        _lib = load(_LIB_PATH)
     return _lib
+
+
+def load(path):
+    """Open a compiled oracle library and declare its signatures (the tests
+    also load deliberately altered copies of the oracle this way)."""
+    L = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    d = ctypes.c_double
+    i64 = ctypes.c_int64
+    dp = P(d)
+    L.or_fine_nodes.restype = i64
+    L.or_coarse_nodes.restype = i64
+    L.or_patches.restype = i64
+    L.or_mse.restype = d
+    L.or_norm2.restype = d
+    L.or_round_bf16.restype = d
+    L.or_round_bf16.argtypes = [d]
+    L.or_round_e4m3.restype = d
+    L.or_round_e4m3.argtypes = [d]
+    L.or_mlp_forward.argtypes = [i64, ctypes.c_int, ctypes.c_int, ctypes.c_int] + [dp] * 10
+    L.or_mlp_backward.argtypes = [i64, ctypes.c_int, ctypes.c_int, ctypes.c_int] + [dp] * 12
+    L.or_mse.argtypes = [i64, ctypes.c_int, dp, dp, dp]
+    L.or_adamw.argtypes = [i64, dp, dp, dp, dp, d, d, d, d, d, i64]
+    L.or_norm2.argtypes = [i64, dp, dp]
+    L.or_vanka_sweep.argtypes = [P(Box), P(NS), dp, dp, dp, d, ctypes.c_int, dp]
+    return L
 
 
 def _box(b) -> Box:
@@ -268,6 +274,24 @@ def round_e4m3(x) -> np.ndarray:
     return np.vectorize(lambda t: f(float(t)), otypes=[np.float64])(np.asarray(x, dtype=np.float64))
 
 
+def eta_of(n0, n1) -> float:
+    """Indicator eta = ||r(x_corr)|| / ||r(x~)|| from the two squared norms;
+    0/0 (both residuals zero) reads as 0, a zero reference with a nonzero
+    corrected residual as +inf."""
+    if n0 > 0.0:
+        return float(np.sqrt(n1 / n0))
+    return 0.0 if n1 == 0.0 else float("inf") if n1 > 0.0 else float("nan")
+
+
+def fallback_taken(n0, n1, theta) -> int:
+    """Fallback decision of the residual indicator: eta > theta or eta NaN,
+    where theta = +inf disables the fallback."""
+    if np.isinf(theta):
+        return 0
+    eta = eta_of(n0, n1)
+    return int(not (eta <= theta))
+
+
 def correction_step(box, ns, params, xc, vprev, shift=None, inv_scale=None, indicator=False,
                     theta=1.0, fallback_sweeps=4, omega=1.0):
     """Algorithm 1 after the coarse solve, step by step in FP64:
@@ -287,8 +311,9 @@ def correction_step(box, ns, params, xc, vprev, shift=None, inv_scale=None, indi
         xcorr = np.concatenate([vcorr, xt[3:4]])
         r2 = residual(box, ns, xcorr, vprev)
         out["r2"] = r2
-        out["eta"] = float(np.sqrt(norm2(r2) / norm2(r)))
-        out["fell_back"] = int(not (norm2(r2) <= theta ** 2 * norm2(r)))
+        n0, n1 = norm2(r), norm2(r2)
+        out["eta"] = eta_of(n0, n1)
+        out["fell_back"] = fallback_taken(n0, n1, theta)
         if out["fell_back"]:
             xv = xt.copy()
             for _ in range(fallback_sweeps):

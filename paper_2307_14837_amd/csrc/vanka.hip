@@ -506,7 +506,18 @@ int vanka_sweeps(const dnnmg_box *box, const dnnmg_ns *ns, float *x, const float
 __global__ void k_indicator_flag(const double *__restrict__ norms, double theta2, int *flag,
                                  int *flag_out) {
     if (threadIdx.x != 0) return;
-    int f = (norms[1] <= theta2 * norms[0]) ? 0 : 1;
+    // eta^2 = norms[1] / norms[0] against theta^2.  An infinite threshold
+    // never falls back (the indicator is only evaluated); a zero reference
+    // residual falls back only if the corrected one is not zero too (0/0 is
+    // read as eta = 0); a NaN corrected residual falls back.
+    const double n0 = norms[0], n1 = norms[1];
+    int f;
+    if (isinf(theta2))
+        f = 0;
+    else if (n0 > 0.0)
+        f = (n1 <= theta2 * n0) ? 0 : 1;
+    else
+        f = (n1 <= 0.0) ? 0 : 1;
     *flag = f;
     if (flag_out) *flag_out = f;
 }

@@ -91,3 +91,29 @@ def test_fallback_against_rhs_matches_oracle(L, orc, name):
     e = rel_l2(got - x, ref - x)
     say(f"  correction rel-L2 {e:.2e}")
     assert e <= 1e-4
+
+
+NORM_CASES = [(0.0, 0.0), (0.0, 1.0), (1.0, 0.5), (1.0, 2.0), (1.0, float("nan")), (0.0, float("nan"))]
+
+
+@pytest.mark.parametrize("theta", [1.0, float("inf")])
+def test_indicator_flag_decisions(L, orc, theta):
+    """The device decision of the residual indicator equals the oracle's on
+    hand-set norms: a zero reference residual (0/0 reads as eta = 0), a NaN
+    corrected residual, and theta = inf, which never falls back."""
+    box, ns = CASES[list(CASES)[0]]
+    nf = box.n_fine
+    xt = to_gpu(f32(np.full(4 * nf, 3.0)))
+    b = torch.zeros(4 * nf, dtype=torch.float32, device=dev())
+    ws = torch.empty(L.fallback_workspace_bytes(box), dtype=torch.uint8, device=dev())
+    flag = torch.full((1,), -1, dtype=torch.int32, device=dev())
+    for n0, n1 in NORM_CASES:
+        say("indicator flag", theta, n0, n1)
+        norms = torch.tensor([n0, n1], dtype=torch.float64, device=dev())
+        xcorr = to_gpu(f32(np.full(4 * nf, 7.0)))
+        L.dnnmg_fallback_b(box, ns, xt, b, norms, xcorr, ws, theta=theta, sweeps=0, flag_out=flag)
+        torch.cuda.synchronize()
+        want = orc.fallback_taken(n0, n1, theta)
+        assert flag.item() == want, (n0, n1, theta)
+        # zero sweeps: a taken fallback leaves x~ itself, else x_corr is kept
+        assert torch.all(xcorr == (3.0 if want else 7.0))

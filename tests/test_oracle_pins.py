@@ -662,3 +662,46 @@ def test_vanka_velocity_sweeps_converge(orc, box):
     norms.append(np.linalg.norm(orc.residual(box, P, x, vp)[:3]))
     for a, b in zip(norms, norms[1:]):
         assert b < a / 3.0, norms
+
+
+def test_scatter_independent_of_summation_order(orc):
+    """Extension L (eq. defL) summed in a random order of the (patch, local
+    node) pairs with numpy, from the brute-force dof lists: the oracle's
+    fixed-order sums agree to roundoff; relabelling the patches by a
+    periodic translation of one coarse cell shifts d by two fine nodes."""
+    box = periodic_box((4, 2, 2), (1.0, 0.5, 0.5))
+    rng = np.random.default_rng(31)
+    Y = rng.standard_normal((box.n_patches, 81))
+    d = orc.scatter(box, Y)
+    Nf = box.fine_shape
+    acc = np.zeros((3, box.n_fine)); cnt = np.zeros(box.n_fine)
+    pairs = [(M, a, b, c) for M in range(box.n_patches) for c in range(3) for b in range(3) for a in range(3)]
+    for t in rng.permutation(len(pairs)):
+        M, a, b, c = pairs[t]
+        I = M % box.n[0]; J = (M // box.n[0]) % box.n[1]; K = M // (box.n[0] * box.n[1])
+        g = ((2 * I + a) % Nf[0]) + Nf[0] * (((2 * J + b) % Nf[1]) + Nf[1] * ((2 * K + c) % Nf[2]))
+        for comp in range(3):
+            acc[comp, g] += Y[M, 27 * comp + a + 3 * b + 9 * c]
+        cnt[g] += 1
+    np.testing.assert_allclose(d, acc / cnt[None, :], rtol=1e-14, atol=1e-15)
+    # translation: patch (I, J, K) -> (I+1, J, K)
+    Yr = Y.reshape(box.n[2], box.n[1], box.n[0], 81)
+    Ys = np.roll(Yr, 1, axis=2).reshape(-1, 81)
+    ds = orc.scatter(box, Ys)
+    shift = lambda a: np.roll(a.reshape(3, Nf[2], Nf[1], Nf[0]), 2, axis=3).reshape(3, -1)
+    np.testing.assert_allclose(ds, shift(d), rtol=1e-14, atol=1e-15)
+
+
+def test_mse_matches_torch(orc):
+    """Training loss (1/n) sum_M ||Y_M - T_M||^2 and its gradient against
+    torch's mse_loss and autograd."""
+    import torch
+
+    rng = np.random.default_rng(32)
+    Y = rng.standard_normal((37, 81)); T = rng.standard_normal((37, 81))
+    loss, dY = orc.mse(Y, T)
+    y = torch.tensor(Y, dtype=torch.float64, requires_grad=True)
+    ref = torch.nn.functional.mse_loss(y, torch.tensor(T, dtype=torch.float64), reduction="sum") / Y.shape[0]
+    ref.backward()
+    assert abs(loss - ref.item()) <= 1e-13 * ref.item()
+    np.testing.assert_allclose(dY, y.grad.numpy(), rtol=1e-13, atol=1e-16)
