@@ -139,6 +139,22 @@ int dnnmg_residual(const dnnmg_box *box, const dnnmg_ns *ns, const float *x, con
 int dnnmg_residual_b(const dnnmg_box *box, const dnnmg_ns *ns, const float *x, const float *b, float *r, void *ws,
                      size_t ws_bytes, void *stream);
 
+/* dnnmg_residual_b for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and the same results, bit for bit, with the LPS workspace taken
+ * from a device array of DNNMG_NOALLOC_SCRATCH_BYTES built into the library
+ * (one per GPU, held until the process ends) instead of a caller workspace.
+ * Makes no allocation of any kind.  A box needing more than the built-in
+ * size (dnnmg_residual_workspace(box) > DNNMG_NOALLOC_SCRATCH_BYTES, about
+ * 270,000 patches) is DNNMG_ERR_SHAPE.  All calls on one GPU share its
+ * array: calls that may overlap on one GPU (other streams, other threads)
+ * race and must be ordered by the caller.  The first call on a device looks
+ * up the array's address (a host-side query, no allocation); call it once
+ * outside capture before capturing it in a graph. */
+#define DNNMG_NOALLOC_SCRATCH_BYTES (33u << 20)
+int dnnmg_residual_b_noalloc(const dnnmg_box *box, const dnnmg_ns *ns, const float *x, const float *b, float *r,
+                             void *stream);
+
 /* Prolongation and fine residual fused (Algorithm 1): xt = P xc exactly as
  * dnnmg_prolong computes it (ncomp 4), and r = F - A(xt) as dnnmg_residual
  * computes it, bit for bit, in one pass.  Since xt is patchwise Q1 (the Q1

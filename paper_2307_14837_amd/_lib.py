@@ -86,6 +86,7 @@ _sig("dnnmg_prolong", [_P(Box), ctypes.c_int, c_vp, c_vp, c_vp])
 _sig("dnnmg_residual_workspace", [_P(Box)], c_sz)
 _sig("dnnmg_residual", [_P(Box), _P(NS), c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp])
 _sig("dnnmg_residual_b", [_P(Box), _P(NS), c_vp, c_vp, c_vp, c_vp, c_sz, c_vp])
+_sig("dnnmg_residual_b_noalloc", [_P(Box), _P(NS), c_vp, c_vp, c_vp, c_vp])
 _sig("dnnmg_fallback_b", [_P(Box), _P(NS), c_vp, c_vp, c_vp, ctypes.c_double, ctypes.c_int, c_f, c_vp, c_vp, c_vp,
                           c_sz, c_vp])
 _sig("dnnmg_rhs", [_P(Box), _P(NS), c_vp, c_vp, c_vp, c_vp])
@@ -131,7 +132,7 @@ EXPORTS = [
     "dnnmg_residual_workspace", "dnnmg_residual", "dnnmg_rhs", "dnnmg_restrict",
     "dnnmg_patch_gather", "dnnmg_mlp_packed_bytes", "dnnmg_mlp_pack", "dnnmg_patch_forward",
     "dnnmg_patch_forward_tiles", "dnnmg_prolong_residual", "dnnmg_prolong_residual_b",
-    "dnnmg_residual_b", "dnnmg_fallback_b",
+    "dnnmg_residual_b", "dnnmg_residual_b_noalloc", "dnnmg_fallback_b",
     "dnnmg_patch_saved_bytes", "dnnmg_scatter_avg", "dnnmg_scatter_avg_form", "dnnmg_norm2_workspace", "dnnmg_norm2_f64",
     "dnnmg_mse_grad", "dnnmg_patch_backward_workspace", "dnnmg_patch_backward", "dnnmg_adamw_step",
     "dnnmg_vanka_workspace", "dnnmg_vanka_sweeps", "dnnmg_fallback_workspace", "dnnmg_fallback",
@@ -210,6 +211,17 @@ def dnnmg_residual_b(box, ns, x, b, r, ws, stream=None):
     _check(_lib.dnnmg_residual_b(ctypes.byref(bx), ctypes.byref(NS.of(ns)), _ptr(x, torch.float32, 4 * nf, "x"),
                                  _ptr(b, torch.float32, 4 * nf, "b"), _ptr(r, torch.float32, 4 * nf, "r"),
                                  _ptr(ws, None, None, "ws"), ws.numel() * ws.element_size(), _stream(stream)))
+
+
+NOALLOC_SCRATCH_BYTES = 33 << 20  # DNNMG_NOALLOC_SCRATCH_BYTES of include/dnnmg.h
+
+
+def dnnmg_residual_b_noalloc(box, ns, x, b, r, stream=None):
+    bx = Box.of(box)
+    nf, _, _ = box_sizes(bx)
+    _check(_lib.dnnmg_residual_b_noalloc(ctypes.byref(bx), ctypes.byref(NS.of(ns)),
+                                         _ptr(x, torch.float32, 4 * nf, "x"), _ptr(b, torch.float32, 4 * nf, "b"),
+                                         _ptr(r, torch.float32, 4 * nf, "r"), _stream(stream)))
 
 
 def dnnmg_residual(box, ns, x, vprev, r, ws, fmid=None, stream=None):

@@ -25,6 +25,8 @@
 // Per cell the quadrature uses sum factorisation: values and gradients at
 // the 8 Gauss points from the 8 vertex values, and the transpose to vertex
 // integrals, each by three 1-D passes.
+#include <mutex>
+
 #include "common.hpp"
 #include "mlp.hpp"
 
@@ -1239,6 +1241,62 @@ extern "C" int dnnmg_residual_b(const dnnmg_box *box, const dnnmg_ns *ns, const 
     if (!aligned16(ws)) return fail(DNNMG_ERR_ARG, "dnnmg_residual_b: workspace not 16-byte aligned");
     if (ws_bytes < lps_ws_bytes(m))
         return fail(DNNMG_ERR_SHAPE, "dnnmg_residual_b: workspace %zu < %zu bytes", ws_bytes, lps_ws_bytes(m));
+    return residual_launch_b(m, ns, x, b, r, (float *)ws, nullptr, (hipStream_t)stream);
+}
+
+// ------------------------------------------- allocation-free residual_b --
+// Scratch of dnnmg_residual_b_noalloc: the LPS corner sums and tile flags of
+// one box, in a device array of fixed size that every GPU the library runs
+// on holds until the process ends.  Host code never passes the array's name
+// to a kernel (on the host it is a stand-in, not a device address): the
+// device address is looked up once per device and kept in g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[DNNMG_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of this device's scratch array (looked up on the first call
+// on the device, with the device current).
+int scratch_address(void **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_check(e, "dnnmg_residual_b_noalloc: hipGetDevice");
+    if (dev < 0 || dev >= MAX_DEVICES)
+        return fail(DNNMG_ERR_UNSUPPORTED, "dnnmg_residual_b_noalloc: device index %d >= %d", dev, MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_check(e, "dnnmg_residual_b_noalloc: hipGetSymbolAddress(scratch)");
+        if (!p) return fail(DNNMG_ERR_HIP, "dnnmg_residual_b_noalloc: scratch has no device address");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return DNNMG_OK;
+}
+} // namespace
+
+extern "C" int dnnmg_residual_b_noalloc(const dnnmg_box *box, const dnnmg_ns *ns, const float *x, const float *b,
+                                        float *r, void *stream) {
+    Mesh m;
+    int rc = make_mesh(box, &m);
+    if (rc) return rc;
+    if ((rc = check_ns(ns))) return rc;
+    if (!x || !b || !r) return fail(DNNMG_ERR_ARG, "dnnmg_residual_b_noalloc: NULL pointer");
+    if (b == r) return fail(DNNMG_ERR_ARG, "dnnmg_residual_b_noalloc: b and r must not alias");
+    const size_t need = lps_ws_bytes(m);
+    if (need > (size_t)DNNMG_NOALLOC_SCRATCH_BYTES)
+        return fail(DNNMG_ERR_SHAPE,
+                    "dnnmg_residual_b_noalloc: the box needs %zu bytes of scratch, more than the %zu built in "
+                    "(%lld patches; use dnnmg_residual_b with a workspace)",
+                    need, (size_t)DNNMG_NOALLOC_SCRATCH_BYTES, (long long)m.n_patches);
+    void *ws = nullptr;
+    if ((rc = scratch_address(&ws))) return rc;
+    // every tile of this box writes its flag before the corner kernel reads
+    // it, and corner sums are read only under a set flag, so nothing left by
+    // an earlier call is read: no clearing is needed
     return residual_launch_b(m, ns, x, b, r, (float *)ws, nullptr, (hipStream_t)stream);
 }
 
