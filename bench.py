@@ -192,6 +192,7 @@ def run_per_box_plain(dtype, steps, warmup):
     import torch
 
     import dnnmg_synth as syn
+    from paper_2307_14837_amd import _lib as L
     from paper_2307_14837_amd import stepper
 
     boxes = syn.cfg3_boxes(seed=0)
@@ -210,15 +211,7 @@ def run_per_box_plain(dtype, steps, warmup):
                 st.step()
 
         def capture(self):
-            s = torch.cuda.Stream()
-            s.wait_stream(torch.cuda.current_stream())
-            with torch.cuda.stream(s):
-                self.step()
-            torch.cuda.current_stream().wait_stream(s)
-            torch.cuda.synchronize()
-            self.g = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(self.g):
-                self.step()
+            self.g = L.capture_graph(self.step)
 
         def replay(self):
             self.g.replay()

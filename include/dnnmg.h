@@ -216,6 +216,21 @@ size_t dnnmg_mlp_packed_bytes(int dtype, int hidden, int layer);
 int dnnmg_mlp_pack(int dtype, int hidden, int layer, const float *W, float w_scale, void *Wp,
                    void *stream);
 
+/* Setup of a network for the kernels (Sec. 3 network; the per-tensor
+ * scaling of the FP8 precision scheme): packs the three FP32 layers W[l]
+ * (device, row-major [fan_in][fan_out]: 165 x H, H x H, H x 81) into Wp[l]
+ * (device, dnnmg_mlp_packed_bytes(dtype, hidden, l) bytes each, 16-byte
+ * aligned), chooses the scales and fills *net (n_in, hidden, n_out, dtype,
+ * W = Wp, b = b, w_scale, a_scale).  Scales: FP8 networks get w_scale[1] =
+ * max |W2| / 448 (the amax taken on the device, so W2 / w_scale spans the
+ * E4M3 range) and a_scale[1] = 1 / 448 for the tanh outputs entering the
+ * E4M3 product (|tanh| < 1); every other scale is 1.  b[l]: FP32 biases
+ * (device, H, H, 81).  ws: device workspace of at least 256 bytes.  A setup
+ * call: it synchronises `stream` (the FP8 scale is read back into *net).
+ * A non-finite or zero max |W2| of an FP8 network is DNNMG_ERR_ARG. */
+int dnnmg_mlp_prepare(int dtype, int hidden, const float *const W[3], const float *const b[3], void *const Wp[3],
+                      void *ws, size_t ws_bytes, dnnmg_mlp *net, void *stream);
+
 /* Patch network N applied to every row of X (Sec. 4.2, patch-wise
  * prediction): Y = W3^T tanh(W2^T tanh(W1^T x + b1) + b2) + b3, FP32
  * accumulation, FP32 outputs Y [n][81].  X has the network's dtype and
@@ -405,6 +420,25 @@ int dnnmg_batch_rhs(const dnnmg_plan *plan, const float *v, float *b, void *stre
 int dnnmg_plan_autotune(dnnmg_plan *plan, const dnnmg_mlp *net, const float *shift, const float *inv_scale,
                         const double *xc, const float *vprev, float *xt, float *r, float *Y, float *xcorr,
                         float *b, double *bc, int reps, void *stream);
+
+/* HIP-graph capture of library calls (Algorithm 1 as one replayable time
+ * step).  dnnmg_graph_capture_begin starts capturing `stream` (a non-default
+ * stream that is not already capturing; thread-local capture mode); every
+ * library call enqueued on it until dnnmg_graph_capture_end is recorded
+ * instead of run.  dnnmg_graph_capture_end stops the capture and
+ * instantiates the executable graph into *graph (owned by the caller, freed
+ * by dnnmg_graph_destroy); it must be called even when a call in between
+ * failed, and then returns that failure and no graph.  dnnmg_graph_replay
+ * launches the graph on `stream`: the recorded kernels run again on the
+ * buffers they were recorded with, whose current contents they read.  No
+ * recorded call allocates or sets memory with a runtime memset, so replays
+ * are repeatable.  Begin, end and destroy are setup calls (end allocates the
+ * graph's host-side description); replay does not synchronise. */
+typedef struct dnnmg_graph dnnmg_graph;
+int dnnmg_graph_capture_begin(void *stream);
+int dnnmg_graph_capture_end(void *stream, dnnmg_graph **graph);
+int dnnmg_graph_replay(const dnnmg_graph *graph, void *stream);
+int dnnmg_graph_destroy(dnnmg_graph *graph);
 
 #ifdef __cplusplus
 }

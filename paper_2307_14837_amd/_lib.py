@@ -125,6 +125,11 @@ _sig("dnnmg_batch_step_b", [c_vp, _P(MLP), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c
 _sig("dnnmg_batch_rhs", [c_vp, c_vp, c_vp, c_vp])
 _sig("dnnmg_plan_autotune", [c_vp, _P(MLP), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
                              ctypes.c_int, c_vp])
+_sig("dnnmg_mlp_prepare", [ctypes.c_int, ctypes.c_int, c_vp * 3, c_vp * 3, c_vp * 3, c_vp, c_sz, _P(MLP), c_vp])
+_sig("dnnmg_graph_capture_begin", [c_vp])
+_sig("dnnmg_graph_capture_end", [c_vp, _P(c_vp)])
+_sig("dnnmg_graph_replay", [c_vp, c_vp])
+_sig("dnnmg_graph_destroy", [c_vp])
 _sig("dnnmg_adamw_step", [c_i64, c_vp, c_vp, c_vp, c_vp, c_f, c_f, c_f, c_f, c_f, c_i64, c_vp])
 
 EXPORTS = [
@@ -138,7 +143,8 @@ EXPORTS = [
     "dnnmg_vanka_workspace", "dnnmg_vanka_sweeps", "dnnmg_fallback_workspace", "dnnmg_fallback",
     "dnnmg_patch_gather_forward", "dnnmg_plan_workspace", "dnnmg_plan_create", "dnnmg_plan_destroy",
     "dnnmg_plan_sizes", "dnnmg_plan_choice", "dnnmg_batch_step", "dnnmg_plan_autotune",
-    "dnnmg_batch_step_b", "dnnmg_batch_rhs", "dnnmg_norm2_pair_f64",
+    "dnnmg_batch_step_b", "dnnmg_batch_rhs", "dnnmg_norm2_pair_f64", "dnnmg_mlp_prepare",
+    "dnnmg_graph_capture_begin", "dnnmg_graph_capture_end", "dnnmg_graph_replay", "dnnmg_graph_destroy",
 ]
 
 
@@ -304,6 +310,82 @@ def make_mlp(dtype, hidden, Wp, bias, w_scale=(1.0, 1.0, 1.0), a_scale=(1.0, 1.0
         net.w_scale[l] = float(w_scale[l])
         net.a_scale[l] = float(a_scale[l])
     return net
+
+
+class PreparedMLP:
+    """A network packed for the kernels by dnnmg_mlp_prepare: owns the packed
+    weights and biases (device) and the filled dnnmg_mlp description."""
+
+    def __init__(self, dtype, hidden, W32, bias, device):
+        self.dtype, self.hidden = int(dtype), int(hidden)
+        self.W32 = [w.contiguous() for w in W32]
+        self.bias = [b.contiguous() for b in bias]
+        self.Wp = [torch.zeros(packed_bytes(dtype, hidden, l), dtype=torch.uint8, device=device) for l in range(3)]
+        self._ws = torch.zeros(256, dtype=torch.uint8, device=device)
+        self.net = MLP()
+        for l, (w, n) in enumerate(((N_IN, hidden), (hidden, hidden), (hidden, N_OUT))):
+            _ptr(self.W32[l], torch.float32, w * n, f"W{l + 1}")
+            _ptr(self.bias[l], torch.float32, n, f"b{l + 1}")
+        self.prepare()
+
+    def prepare(self, stream=None):
+        """(Re)packs from the FP32 weights (setup call: synchronises)."""
+        W = (c_vp * 3)(*[w.data_ptr() for w in self.W32])
+        B = (c_vp * 3)(*[b.data_ptr() for b in self.bias])
+        P = (c_vp * 3)(*[w.data_ptr() for w in self.Wp])
+        _check(_lib.dnnmg_mlp_prepare(self.dtype, self.hidden, W, B, P, _ptr(self._ws), self._ws.numel(),
+                                      ctypes.byref(self.net), _stream(stream)))
+        return self.net
+
+
+def mlp_prepare(dtype, hidden, W32, bias, device="cuda:0") -> PreparedMLP:
+    return PreparedMLP(dtype, hidden, W32, bias, torch.device(device))
+
+
+class Graph:
+    """Executable HIP graph of the library calls made inside `capture()`
+    (dnnmg_graph_capture_begin / _end); replay() launches it."""
+
+    def __init__(self):
+        self.handle = None
+
+    def begin(self, stream):
+        _check(_lib.dnnmg_graph_capture_begin(_stream(stream)))
+
+    def end(self, stream):
+        h = c_vp()
+        _check(_lib.dnnmg_graph_capture_end(_stream(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def replay(self, stream=None):
+        if self.handle is None:
+            raise RuntimeError("graph not captured")
+        _check(_lib.dnnmg_graph_replay(self.handle, _stream(stream)))
+
+    def __del__(self):
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            _lib.dnnmg_graph_destroy(self.handle)
+            self.handle = None
+
+
+def capture_graph(fn, device="cuda:0") -> Graph:
+    """Runs fn() once eagerly on a side stream (warm-up), then records the
+    library calls fn() makes into a HIP graph on that stream."""
+    dev = torch.device(device)
+    s = torch.cuda.Stream(device=dev)
+    s.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(s):
+        fn()
+    torch.cuda.current_stream(dev).wait_stream(s)
+    torch.cuda.synchronize(dev)
+    g = Graph()
+    with torch.cuda.stream(s):
+        g.begin(s)
+        try:
+            fn()
+        finally:
+            g.end(s)
+    return g
 
 
 def saved_bytes(net: MLP, n: int) -> int:

@@ -9,7 +9,7 @@ import numpy as np
 import torch
 
 from . import _lib as L
-from .stepper import DTYPES, TANH_SCALE
+from .stepper import DTYPES
 
 
 class BatchedStep:
@@ -34,18 +34,9 @@ class BatchedStep:
         self.inv_scale = None if inv_scale is None else torch.as_tensor(np.asarray(inv_scale, np.float32)).to(self.dev)
         H = int(np.shape(params[0])[1])
         W32 = [torch.as_tensor(np.asarray(params[2 * l], np.float32)).contiguous().to(self.dev) for l in range(3)]
-        self.bias = [torch.as_tensor(np.asarray(params[2 * l + 1], np.float32)).contiguous().to(self.dev) for l in range(3)]
-        ws = [1.0, 1.0, 1.0]
-        a = [1.0, 1.0, 1.0]
-        if self.dtype == L.FP8_E4M3:
-            ws = [1.0, max(float(W32[1].abs().max().item()), 1e-30) / 448.0, 1.0]
-            a = [1.0, TANH_SCALE, 1.0]
-        self.Wp = []
-        for l in range(3):
-            buf = torch.zeros(L.packed_bytes(self.dtype, H, l), dtype=torch.uint8, device=self.dev)
-            L.dnnmg_mlp_pack(self.dtype, H, l, W32[l], buf, w_scale=ws[l])
-            self.Wp.append(buf)
-        self.net = L.make_mlp(self.dtype, H, self.Wp, self.bias, ws, a)
+        bias = [torch.as_tensor(np.asarray(params[2 * l + 1], np.float32)).contiguous().to(self.dev) for l in range(3)]
+        self.prepared = L.mlp_prepare(self.dtype, H, W32, bias, device=self.dev)
+        self.net = self.prepared.net
         self.graph = None
 
     # per-box views of the batch layout
@@ -81,20 +72,11 @@ class BatchedStep:
         return self.plan.choice()
 
     def capture(self):
-        s = torch.cuda.Stream(device=self.dev)
-        s.wait_stream(torch.cuda.current_stream(self.dev))
-        with torch.cuda.stream(s):
-            self.step()
-        torch.cuda.current_stream(self.dev).wait_stream(s)
-        torch.cuda.synchronize(self.dev)
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g):
-            self.step()
-        self.graph = g
-        return g
+        self.graph = L.capture_graph(self.step, device=self.dev)
+        return self.graph
 
-    def replay(self):
-        self.graph.replay()
+    def replay(self, stream=None):
+        self.graph.replay(stream)
 
     def results(self):
         """Per-box numpy outputs: xt, xcorr, bc, Y."""

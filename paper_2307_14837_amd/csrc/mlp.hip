@@ -13,6 +13,9 @@
 // Element types: FP32 (v_mfma_f32_16x16x4f32), BF16 (v_mfma_f32_16x16x32_bf16)
 // and OCP FP8 E4M3 (v_mfma_scale_f32_16x16x128_f8f6f4) with per-tensor
 // scales; all accumulate in FP32 and apply bias and tanh in FP32.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
 #include <type_traits>
 
 #include "common.hpp"
@@ -552,6 +555,77 @@ extern "C" int dnnmg_mlp_pack(int dtype, int hidden, int layer, const float *W, 
         k_pack<uint8_t><<<grid, 256, 0, s>>>(kind, layer, fan_in, fan_out, ntiles, nchunks, W,
                                              1.f / w_scale, (uint8_t *)Wp);
     return hip_check(hipGetLastError(), "dnnmg_mlp_pack launch");
+}
+
+// max |w| over n weights as the bit pattern of a non-negative float (the
+// integer order of such patterns is their numeric order, and a NaN compares
+// above +inf), combined across workgroups with an atomic maximum, so the
+// result does not depend on the order of the workgroups.
+__global__ void __launch_bounds__(256) k_amax_init(unsigned *__restrict__ out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = 0u;
+}
+
+__global__ void __launch_bounds__(256) k_amax(int64_t n, const float *__restrict__ W, unsigned *__restrict__ out) {
+    unsigned m = 0u;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        m = max(m, __float_as_uint(W[i]) & 0x7fffffffu);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, o));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, m);
+}
+
+extern "C" int dnnmg_mlp_prepare(int dtype, int hidden, const float *const W[3], const float *const b[3],
+                                 void *const Wp[3], void *ws, size_t ws_bytes, dnnmg_mlp *net, void *stream) {
+    if (!W || !b || !Wp || !net) return fail(DNNMG_ERR_ARG, "dnnmg_mlp_prepare: NULL pointer");
+    if (hidden != 64 && hidden != 128 && hidden != 256 && hidden != 512)
+        return fail(DNNMG_ERR_UNSUPPORTED, "dnnmg_mlp_prepare: hidden %d", hidden);
+    if (dtype != DNNMG_F32 && dtype != DNNMG_BF16 && dtype != DNNMG_FP8_E4M3)
+        return fail(DNNMG_ERR_UNSUPPORTED, "dnnmg_mlp_prepare: dtype %d", dtype);
+    if (dtype == DNNMG_FP8_E4M3 && hidden < 128)
+        return fail(DNNMG_ERR_UNSUPPORTED, "dnnmg_mlp_prepare: FP8 needs hidden >= 128");
+    for (int l = 0; l < 3; ++l) {
+        if (!W[l] || !b[l] || !Wp[l]) return fail(DNNMG_ERR_ARG, "dnnmg_mlp_prepare: W/b/Wp[%d] is NULL", l);
+        if (!aligned16(Wp[l]) || !aligned16(b[l]))
+            return fail(DNNMG_ERR_ARG, "dnnmg_mlp_prepare: Wp/b[%d] not 16-byte aligned", l);
+    }
+    if (!ws || !aligned16(ws) || ws_bytes < 256)
+        return fail(DNNMG_ERR_ARG, "dnnmg_mlp_prepare: workspace must be >= 256 bytes, 16-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    float w_scale[3] = {1.f, 1.f, 1.f}, a_scale[3] = {1.f, 1.f, 1.f};
+    if (dtype == DNNMG_FP8_E4M3) {
+        const int64_t n = (int64_t)hidden * hidden;
+        unsigned *d = (unsigned *)ws;
+        k_amax_init<<<1, 64, 0, s>>>(d);
+        k_amax<<<(unsigned)std::min<int64_t>(blocks_for(n, 256), 1024), 256, 0, s>>>(n, W[1], d);
+        int rc = hip_check(hipGetLastError(), "dnnmg_mlp_prepare: amax launch");
+        if (rc) return rc;
+        unsigned bits = 0;
+        if ((rc = hip_check(hipMemcpyAsync(&bits, d, sizeof bits, hipMemcpyDeviceToHost, s),
+                            "dnnmg_mlp_prepare: amax read-back")))
+            return rc;
+        if ((rc = hip_check(hipStreamSynchronize(s), "dnnmg_mlp_prepare: synchronise"))) return rc;
+        float amax;
+        memcpy(&amax, &bits, sizeof amax);
+        if (!(amax > 0.f) || !std::isfinite(amax))
+            return fail(DNNMG_ERR_ARG, "dnnmg_mlp_prepare: max |W2| = %g (needs a finite value > 0)", (double)amax);
+        w_scale[1] = amax / 448.f;
+        a_scale[1] = 1.f / 448.f;
+    }
+    for (int l = 0; l < 3; ++l) {
+        int rc = dnnmg_mlp_pack(dtype, hidden, l, W[l], w_scale[l], Wp[l], stream);
+        if (rc) return rc;
+    }
+    net->n_in = N_IN;
+    net->hidden = hidden;
+    net->n_out = N_OUT;
+    net->dtype = dtype;
+    for (int l = 0; l < 3; ++l) {
+        net->W[l] = Wp[l];
+        net->b[l] = b[l];
+        net->w_scale[l] = w_scale[l];
+        net->a_scale[l] = a_scale[l];
+    }
+    return DNNMG_OK;
 }
 
 extern "C" size_t dnnmg_patch_saved_bytes(const dnnmg_mlp *net, int64_t n) {

@@ -16,7 +16,6 @@ from . import _lib as L
 DTYPES = {"fp32": L.F32, "bf16": L.BF16, "fp8": L.FP8_E4M3}
 _TORCH = {L.F32: torch.float32, L.BF16: torch.bfloat16, L.FP8_E4M3: torch.uint8}
 LDX = L.IN_PAD  # 192: K padded for the MFMA granule
-TANH_SCALE = 1.0 / 448.0  # FP8 scale of the tanh outputs (|tanh| < 1 maps inside +-448)
 
 
 class CorrectionStep:
@@ -28,8 +27,8 @@ class CorrectionStep:
     with b the right-hand side the previous step computed (load() computes
     the first one from vprev), so the terms of the previous velocity are
     evaluated once per step, not again in every residual; carry_rhs=False
-    builds them from vprev in each residual instead.  FP8 networks quantise W2 with amax / 448 and the tanh outputs
-    entering layer 2 with the fixed scale 1 / 448.
+    builds them from vprev in each residual instead.  The network is packed by
+    the library (dnnmg_mlp_prepare), which also picks the FP8 scales.
     """
 
     def __init__(self, box, ns, params, dtype="bf16", device="cuda:0", shift=None, inv_scale=None,
@@ -73,21 +72,14 @@ class CorrectionStep:
     # ------------------------------------------------------------- network --
     def set_params(self, params):
         H = self.hidden
-        self.W32 = [torch.as_tensor(np.asarray(params[2 * l], np.float32)).contiguous().to(self.dev) for l in range(3)]
-        self.bias = [torch.as_tensor(np.asarray(params[2 * l + 1], np.float32)).contiguous().to(self.dev) for l in range(3)]
-        self.w_scale = [1.0, 1.0, 1.0]
-        if self.dtype == L.FP8_E4M3:
-            self.w_scale = [1.0, max(float(self.W32[1].abs().max().item()), 1e-30) / 448.0, 1.0]
-        self.Wp = []
-        for l in range(3):
-            buf = torch.zeros(L.packed_bytes(self.dtype, H, l), dtype=torch.uint8, device=self.dev)
-            L.dnnmg_mlp_pack(self.dtype, H, l, self.W32[l], buf, w_scale=self.w_scale[l])
-            self.Wp.append(buf)
-        self._make_net()
-
-    def _make_net(self):
-        a = [1.0, TANH_SCALE, 1.0] if self.dtype == L.FP8_E4M3 else [1.0, 1.0, 1.0]
-        self.net = L.make_mlp(self.dtype, self.hidden, self.Wp, self.bias, self.w_scale, a)
+        W32 = [torch.as_tensor(np.asarray(params[2 * l], np.float32)).contiguous().to(self.dev) for l in range(3)]
+        bias = [torch.as_tensor(np.asarray(params[2 * l + 1], np.float32)).contiguous().to(self.dev) for l in range(3)]
+        # packing and the per-tensor scales of the precision scheme are the
+        # library's (dnnmg_mlp_prepare)
+        self.prepared = L.mlp_prepare(self.dtype, H, W32, bias, device=self.dev)
+        self.W32, self.bias, self.Wp = self.prepared.W32, self.prepared.bias, self.prepared.Wp
+        self.net = self.prepared.net
+        self.w_scale = [float(self.net.w_scale[l]) for l in range(3)]
 
     # ---------------------------------------------------------------- step --
     def load(self, xc, vprev):
@@ -134,21 +126,13 @@ class CorrectionStep:
         L.dnnmg_restrict(box, self.b, self.bc, stream=stream)
 
     def capture(self):
-        """Capture step() into a HIP graph (torch.cuda.CUDAGraph wraps hipGraph)."""
-        s = torch.cuda.Stream(device=self.dev)
-        s.wait_stream(torch.cuda.current_stream(self.dev))
-        with torch.cuda.stream(s):
-            self.step()  # warm-up outside the graph
-        torch.cuda.current_stream(self.dev).wait_stream(s)
-        torch.cuda.synchronize(self.dev)
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g):
-            self.step()
-        self.graph = g
-        return g
+        """Record step() into a HIP graph through the library's capture calls
+        (one eager warm-up step first)."""
+        self.graph = L.capture_graph(self.step, device=self.dev)
+        return self.graph
 
-    def replay(self):
-        self.graph.replay()
+    def replay(self, stream=None):
+        self.graph.replay(stream)
 
     def run_numpy(self, xc, vprev):
         self.load(xc, vprev)

@@ -22,6 +22,59 @@ from .stepper import DTYPES, LDX
 _XT = {L.F32: torch.float32, L.BF16: torch.bfloat16}
 
 
+class PatchMLPFunction(torch.autograd.Function):
+    """The patch network as a differentiable torch operation whose forward and
+    backward run on the library's kernels (dnnmg_patch_forward with saved
+    activations; dnnmg_patch_backward, the chain rule through both tanh
+    layers of Sec. 3's network).
+
+    apply(X, W1, b1, W2, b2, W3, b3, dtype) -> Y [n][81] FP32.  X [n][192]
+    holds the gathered inputs in the network's element type (FP32 or BF16;
+    no gradient flows to it); W are the FP32 master weights [fan_in][fan_out]
+    and b the FP32 biases.  The forward packs the weights (dnnmg_mlp_prepare)
+    and runs the network; the backward takes dL/dY and returns dL/dW and
+    dL/db, FP32.  The products of a BF16 network run on BF16 MFMA with FP32
+    accumulation (as the library documents); FP8 networks do not train.
+    """
+
+    @staticmethod
+    def forward(ctx, X, W1, b1, W2, b2, W3, b3, dtype):
+        dt = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+        if dt not in (L.F32, L.BF16):
+            raise ValueError("training runs in FP32 or BF16")
+        if X.dim() != 2 or X.shape[1] != LDX or X.dtype != _XT[dt]:
+            raise ValueError(f"X must be [n][{LDX}] {_XT[dt]}")
+        n, H = X.shape[0], W1.shape[1]
+        dev = X.device
+        Ws = [W1.detach().contiguous(), W2.detach().contiguous(), W3.detach().contiguous()]
+        bs = [b1.detach().contiguous(), b2.detach().contiguous(), b3.detach().contiguous()]
+        prep = L.mlp_prepare(dt, H, Ws, bs, device=dev)
+        Y = torch.empty(n * L.N_OUT, dtype=torch.float32, device=dev)
+        saved = torch.empty(max(L.saved_bytes(prep.net, n), 16), dtype=torch.uint8, device=dev)
+        X = X.contiguous()
+        L.dnnmg_patch_forward(prep.net, n, X, LDX, Y, saved=saved)
+        ctx.save_for_backward(X, Ws[1], Ws[2], saved)
+        ctx.prep, ctx.n, ctx.H = prep, n, H
+        return Y.view(n, L.N_OUT)
+
+    @staticmethod
+    def backward(ctx, dY):
+        X, W2, W3, saved = ctx.saved_tensors
+        n, H, net = ctx.n, ctx.H, ctx.prep.net
+        dev = X.device
+        f32 = dict(dtype=torch.float32, device=dev)
+        dW = [torch.empty(L.N_IN, H, **f32), torch.empty(H, H, **f32), torch.empty(H, L.N_OUT, **f32)]
+        db = [torch.empty(H, **f32), torch.empty(H, **f32), torch.empty(L.N_OUT, **f32)]
+        ws = torch.empty(max(L.backward_workspace_bytes(net, n), 16), dtype=torch.uint8, device=dev)
+        L.dnnmg_patch_backward(net, W2, W3, n, X, LDX, saved, dY.contiguous().view(-1).float(), dW, db, ws)
+        return None, dW[0], db[0], dW[1], db[1], dW[2], db[2], None
+
+
+def patch_mlp(X, W1, b1, W2, b2, W3, b3, dtype="fp32"):
+    """Y = N(X) on the library's kernels, differentiable in the parameters."""
+    return PatchMLPFunction.apply(X, W1, b1, W2, b2, W3, b3, dtype)
+
+
 class PatchTrainer:
     def __init__(self, params, dtype="bf16", lr=1e-3, weight_decay=1e-5, betas=(0.9, 0.999), eps=1e-8,
                  device="cuda:0", max_batch=65536):

@@ -67,3 +67,13 @@ def test_host_validation_without_gpu():
     rc = lib.dnnmg_patch_forward(ctypes.byref(net), 10, None, 192, None, None, None)
     assert rc == -3
     assert lib.dnnmg_version() >= 1
+
+
+def test_graph_calls_validate_on_host():
+    import paper_2307_14837_amd as L
+
+    lib = L._lib.lib()
+    # the legacy default stream cannot be captured; NULL handles are errors
+    assert lib.dnnmg_graph_capture_begin(None) == -1
+    assert lib.dnnmg_graph_replay(None, None) == -1
+    assert lib.dnnmg_graph_destroy(None) == 0

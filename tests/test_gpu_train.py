@@ -114,3 +114,31 @@ def test_adamw(L, orc):
     torch.cuda.synchronize()
     got = th.cpu().numpy()
     assert np.max(np.abs(got - tr)) <= 1e-6 * np.max(np.abs(tr))
+
+
+@pytest.mark.parametrize("dtype,H,n,tol", [("fp32", 64, 257, 1e-5), ("bf16", 128, 333, 2e-2)])
+def test_autograd_function_matches_oracle(L, orc, dtype, H, n, tol):
+    """The network as a torch.autograd.Function over the library's forward and
+    backward kernels: gradients of a torch-side MSE loss through
+    torch.autograd equal the oracle's chain-rule gradients (pinned by finite
+    differences), and the loss matches."""
+    from paper_2307_14837_amd import train
+
+    say("autograd function", dtype, "H", H, "n", n)
+    params = syn.mlp_params(165, H, 81, seed=21, bias_scale=0.1)
+    rng = np.random.default_rng(22)
+    X = f32(rng.standard_normal((n, 165)))
+    T = f32(rng.standard_normal((n, 81)) * 0.5)
+    xt = torch.float32 if dtype == "fp32" else torch.bfloat16
+    Xg = to_gpu(padded(X, 192)).to(xt).contiguous()
+    ps = [to_gpu(f32(p)).requires_grad_(True) for p in params]
+    Y = train.patch_mlp(Xg, *ps, dtype=dtype)
+    loss = ((Y - to_gpu(T)) ** 2).sum() / n
+    loss.backward()
+    torch.cuda.synchronize()
+    gr, lr_, _ = oracle_grads(orc, params, X, T)
+    assert abs(loss.item() - lr_) <= max(tol, 1e-6) * abs(lr_)
+    for i, (p, b) in enumerate(zip(ps, gr)):
+        e = rel_l2(p.grad.cpu().numpy().astype(np.float64).reshape(b.shape), b)
+        say(f"  grad {i} rel-L2 {e:.2e}")
+        assert e <= tol, i
