@@ -1,14 +1,21 @@
 """Benchmark of the DNN-MG fine-level correction step on one MI355X.
 
 One step = prolongation -> fine residual -> patch gather -> patch network ->
-multiplicity-averaged extension -> right-hand side -> restriction (the hot
-path after the coarse solve), captured in one HIP graph and replayed.
+multiplicity-averaged extension -> residual indicator (and, above its
+threshold, the plain fine correction) -> right-hand side -> restriction (the
+hot path after the coarse solve), captured in one HIP graph and replayed as a
+time loop (each step's right-hand side feeds the next step's residual).
 
-Default workload: the single-simulation channel, coarse 64x16x16 cells
-(16,384 patches), fine 128x32x32 cells (140,481 nodes), FP32 stencils and a
-BF16 network 165-256-256-81.  Prints one JSON line; `value` is patches/s.
-Also reported: the same step with an FP32 network, and the large channel
-(131,072 patches, FP8 network of width 512) with the residual indicator.
+Headline workload: the large single run, channel 2.5 x 0.41 x 0.41 with
+coarse 128x32x32 cells (131,072 patches) and fine 256x64x64 cells (1,085,825
+nodes); FP32 stencils, network 165-512-512-81 with the E4M3 hidden product,
+residual indicator with threshold 1 and the fallback to the plain fine
+correction.  Its network is trained on the GPU (library kernels) on the plain
+fine correction of four other seeded inputs of the same channel.  Prints one
+JSON line; `value` is patches/s.  Also reported: the same step with FP32 and
+BF16 networks, the 16,384-patch channel, the 32-box batch, a training step,
+per-kernel rates, accuracy against the FP64 oracle and the oracle's own CPU
+throughput.
 """
 from __future__ import annotations
 
@@ -16,6 +23,8 @@ import argparse
 import hashlib
 import json
 import os
+import platform
+import subprocess
 import sys
 import time
 
@@ -27,7 +36,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP32_VALU_PEAK_TFLOPS = 157.3  # published vector FP32 (packed FMA); non-packed issue is half
 BF16_MFMA_PEAK_TFLOPS = 2500.0
+FP8_MFMA_PEAK_TFLOPS = 5000.0
 PMC_COPY_MIB = 256  # plain copy of known size that calibrates the HBM byte counters
+CPU_WORKERS = 16    # host threads / processes of the CPU baseline (the machine's CPU share per GPU)
+DISTILL_SEEDS = (1, 2, 3, 4)
 
 
 def parse():
@@ -35,12 +47,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--no-variants", action="store_true", help="only the default workload")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline and accuracy leg")
+    ap.add_argument("--no-variants", action="store_true", help="only the headline workload")
+    ap.add_argument("--profile-step", action="store_true",
+                    help="run only the headline step's graph replays (for rocprofv3 --kernel-trace)")
     ap.add_argument("--pmc-probe", action="store_true",
-                    help="run only the dominant kernel and a plain copy a few times (for rocprofv3 --pmc)")
+                    help="run only the headline step's dominant kernel and a plain copy (for rocprofv3 --pmc)")
     ap.add_argument("--scale-only", action="store_true",
                     help="run only the per-kernel measurements on the large channel (for rocprofv3)")
+    ap.add_argument("--cpu-worker", type=int, default=None, help=argparse.SUPPRESS)
     return ap.parse_args()
 
 
@@ -67,50 +82,117 @@ def traffic_from_profile(entry, workload):
     return k.get("bytes_per_launch")
 
 
-def pmc_probe():
-    """The dominant entry point (prolongation + residual of the default
-    workload, in the form against the carried right-hand side, and in the
-    form that reads v_prev), then a plain device copy of PMC_COPY_MIB MiB,
-    three launches each, for counter runs."""
-    import torch
-
+# ------------------------------------------------------------ CPU leg -------
+def slab_workload():
+    """The CPU sample: a slab of the large channel (its first 8 coarse cells
+    along x, 8x32x32 coarse cells = 8,192 patches) at the same cell sizes,
+    with the same network width."""
     import dnnmg_synth as syn
-    from paper_2307_14837_amd import _lib as L
 
-    w = syn.cfg2()
-    st, _, _ = build_step(w, "bf16")
-    for _ in range(3):
-        L.dnnmg_prolong_residual(st.box, st.ns, st.xc, st.vprev, st.xt, st.r)
-    for _ in range(3):
-        L.dnnmg_prolong_residual_b(st.box, st.ns, st.xc, st.b, st.xt, st.r)
-    torch.cuda.synchronize()
-    n = PMC_COPY_MIB * 2**20 // 4
-    a = torch.ones(n, dtype=torch.float32, device="cuda")
-    b = torch.empty_like(a)
-    torch.cuda.synchronize()
-    for _ in range(3):
-        torch.neg(a, out=b)
-    torch.cuda.synchronize()
-    print(json.dumps({"pmc_probe": w.name, "copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n,
-                      "src_hash": src_hash(*RESIDUAL_SOURCES)}), flush=True)
+    w5 = syn.cfg5()
+    box = syn.BoxSpec((8, 32, 32), (w5.box.len[0] * 8 / w5.box.n[0], w5.box.len[1], w5.box.len[2]), 0,
+                      syn.CHANNEL_DIRICHLET)
+    return syn.Workload("channel_slab_8x32x32_of_128x32x32", box, w5.ns, w5.hidden, "fp8", "channel")
 
 
+def cpu_worker(seed):
+    """One process of the CPU baseline: the oracle's full correction step with
+    the indicator evaluated (the fallback not taken, as on the GPU), on the
+    slab sample; prints its wall time."""
+    import dnnmg_synth as syn
+    import oracle
+
+    w = slab_workload()
+    inp = syn.step_inputs(w, seed=seed)
+    params = [np.asarray(p, np.float32).astype(np.float64) for p in syn.mlp_params(165, w.hidden, 81, seed=seed)]
+    oracle.lib()
+    t0 = time.perf_counter()
+    oracle.correction_step(w.box, w.ns, params, inp.xc, inp.vprev, indicator=True, theta=float("inf"))
+    print(json.dumps({"seed": seed, "s": time.perf_counter() - t0}), flush=True)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def run_workers(n):
+    t0 = time.perf_counter()
+    procs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker", str(k)],
+                              stdout=subprocess.PIPE, text=True) for k in range(n)]
+    outs = [p.communicate()[0] for p in procs]
+    wall = time.perf_counter() - t0
+    for p in procs:
+        if p.returncode != 0:
+            raise RuntimeError("CPU baseline worker failed")
+    per = [json.loads(o.strip().splitlines()[-1])["s"] for o in outs]
+    return wall, per
+
+
+def cpu_baseline():
+    """The oracle as it stands (single-threaded C), timed on the host before
+    the GPU is touched: one process on the slab sample (one core), then
+    CPU_WORKERS processes on CPU_WORKERS seeded slabs at once (all cores of
+    the GPU's share)."""
+    w = slab_workload()
+    npch = w.box.n_patches
+    wall1, _ = run_workers(1)
+    wallN, per = run_workers(CPU_WORKERS)
+    return {"value": npch / wall1, "unit": "patches/s", "cores": 1, "kind": "oracle",
+            "sample": f"one full correction step (indicator evaluated, fallback not taken) of {w.name} "
+                      f"({npch} patches, fine {2 * w.box.n[0]}x64x64 cells of the large channel, network width "
+                      f"{w.hidden}) in FP64, {wall1:.1f} s on one core",
+            "all_cores": {"value": CPU_WORKERS * npch / wallN, "unit": "patches/s", "cores": CPU_WORKERS,
+                          "sample": f"{CPU_WORKERS} processes, each the same step on its own seeded slab, "
+                                    f"{wallN:.1f} s wall (per process {min(per):.1f}-{max(per):.1f} s)"},
+            "nproc": os.cpu_count(), "cpu_model": cpu_model()}
+
+
+def oracle_reference(w, seed=0, threads=CPU_WORKERS):
+    """FP64 oracle chain of one step (indicator evaluated, no fallback) on
+    seeded inputs and seeded network weights: the reference of the accuracy
+    figures (the network's rows on `threads` host threads)."""
+    import dnnmg_synth as syn
+    import oracle
+
+    inp = syn.step_inputs(w, seed=seed)
+    params = [np.asarray(p, np.float32).astype(np.float64) for p in syn.mlp_params(165, w.hidden, 81, seed=seed)]
+    vp32 = np.asarray(inp.vprev, np.float32).astype(np.float64)
+    t0 = time.perf_counter()
+    ref = oracle.correction_step(w.box, w.ns, params, inp.xc, vp32, indicator=True, theta=float("inf"),
+                                 threads=threads)
+    keep = {k: ref[k] for k in ("xt", "r", "d", "bc", "eta")}
+    keep["seconds"] = time.perf_counter() - t0
+    return keep
+
+
+# ------------------------------------------------------------ GPU leg -------
 def time_graph(st, steps, warmup):
+    """Graph replays of the step: `warmup` untimed, then `steps` timed with HIP
+    events on the replay stream (one event between consecutive steps, for the
+    median and minimum)."""
     import torch
 
     st.capture()
     for _ in range(warmup):
         st.replay()
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
-    e0.record()
-    for _ in range(steps):
+    ev[0].record()
+    for k in range(steps):
         st.replay()
-    e1.record()
+        ev[k + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return e0.elapsed_time(e1) / steps, wall
+    per = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])
+    return {"ms": ev[0].elapsed_time(ev[steps]) / steps, "median_ms": float(np.median(per)),
+            "min_ms": float(per.min()), "wall_s": wall}
 
 
 def time_kernel(fn, reps):
@@ -139,27 +221,133 @@ def time_kernel(fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
-def build_step(w, dtype, seed=0, indicator=False, theta=1.0):
+def distilled_network(w):
+    """The headline's network: trained on the GPU on the plain fine correction
+    of DISTILL_SEEDS inputs of the same workload (train.distill)."""
+    import dnnmg_synth as syn
+    from paper_2307_14837_amd import train
+
+    t0 = time.perf_counter()
+    inputs = []
+    for s in DISTILL_SEEDS:
+        inp = syn.step_inputs(w, seed=s)
+        inputs.append((inp.xc, inp.vprev))
+    params, shift, inv, info = train.distill(w.box, w.ns, inputs, w.hidden, steps=600)
+    info["seconds"] = time.perf_counter() - t0
+    info["seeds"] = list(DISTILL_SEEDS)
+    return params, shift, inv, info
+
+
+def build_step(w, dtype, params=None, shift=None, inv=None, seed=0, indicator=False, theta=1.0):
     import dnnmg_synth as syn
     from paper_2307_14837_amd import stepper
 
     inp = syn.step_inputs(w, seed=seed)
-    params = syn.mlp_params(165, w.hidden, 81, seed=seed)
-    st = stepper.CorrectionStep(w.box, w.ns, params, dtype=dtype, indicator=indicator, theta=theta)
+    if params is None:
+        params = syn.mlp_params(165, w.hidden, 81, seed=seed)
+    st = stepper.CorrectionStep(w.box, w.ns, params, dtype=dtype, indicator=indicator, theta=theta,
+                                shift=shift, inv_scale=inv)
     st.load(inp.xc, inp.vprev)
-    return st, inp, params
+    return st, inp
 
 
-def run_variant(w, dtype, steps, warmup, indicator=False, fallback="never"):
-    """indicator: the residual test runs every step; fallback "never"
-    (threshold infinite: test only) or "always" (threshold 0: the
-    fallback sweeps replace the correction every step)."""
-    theta = float("inf") if fallback == "never" else 0.0
-    st, inp, params = build_step(w, dtype, indicator=indicator, theta=theta)
-    ms, wall = time_graph(st, steps, warmup)
-    return {"workload": w.name, "dtype": dtype, "indicator": indicator,
-            "fallback": fallback if indicator else None, "ms_per_step": ms,
-            "patches_per_s": st.np / (ms * 1e-3), "fine_dof_per_s": 4 * st.nf / (ms * 1e-3)}
+def fallback_accounting(st, inp, steps):
+    """The timed time loop replayed again from the same start, synchronising
+    after each step to read the indicator: eta per step and how often the
+    fallback was taken."""
+    import torch
+
+    st.load(inp.xc, inp.vprev)
+    etas, taken = [], 0
+    for _ in range(steps):
+        st.replay()
+        torch.cuda.synchronize()
+        n = st.norms.cpu().numpy()
+        etas.append(float(np.sqrt(n[1] / n[0])) if n[0] > 0 else 0.0)
+        taken += int(st.fell_back.item())
+    e = np.array(etas)
+    return {"steps": steps, "fallback_rate": taken / steps, "eta_first": etas[0],
+            "eta_median": float(np.median(e)), "eta_max": float(e.max())}
+
+
+def run_step(w, dtype, steps, warmup, params=None, shift=None, inv=None, indicator=False, theta=1.0,
+             account=False):
+    st, inp = build_step(w, dtype, params, shift, inv, indicator=indicator, theta=theta)
+    t = time_graph(st, steps, warmup)
+    out = {"workload": w.name, "dtype": dtype, "indicator": indicator, "theta": theta if indicator else None,
+           "ms_per_step": t["ms"], "median_ms": t["median_ms"], "min_ms": t["min_ms"],
+           "patches_per_s": st.np / (t["ms"] * 1e-3), "fine_dof_per_s": 4 * st.nf / (t["ms"] * 1e-3)}
+    if indicator and account:
+        out["indicator_stats"] = fallback_accounting(st, inp, steps)
+    return out, st, t
+
+
+def step_kernel_times(st, reps=20):
+    """Each launch of the headline step timed alone on the step's own buffers
+    (after one step, so every input holds step data): ms per launch."""
+    from paper_2307_14837_amd import _lib as L
+
+    box, ns = st.box, st.ns
+    st.step()
+    k = {
+        "prolong_residual_b": lambda: L.dnnmg_prolong_residual_b(box, ns, st.xc, st.b, st.xt, st.r),
+        "gather_forward": lambda: L.dnnmg_patch_gather_forward(box, st.net, st.xt, st.r, st.Y, st.shift,
+                                                              st.inv_scale),
+        "scatter": lambda: L.dnnmg_scatter_avg(box, st.Y, st.xcorr, vbase=st.xt),
+        "residual_b_indicator": lambda: L.dnnmg_residual_b(box, ns, st.xcorr, st.b, st.r2, st.ws_res),
+        "norm2_pair": lambda: L.dnnmg_norm2_pair_f64(st.r, st.r2, st.norms, st.ws_norm),
+        "fallback_skipped": lambda: L.dnnmg_fallback_b(box, ns, st.xt, st.b, st.norms, st.xcorr, st.ws_fb,
+                                                       theta=st.theta, sweeps=st.fallback_sweeps,
+                                                       flag_out=st.fell_back),
+        "rhs": lambda: L.dnnmg_rhs(box, ns, st.xcorr, st.b),
+        "restrict": lambda: L.dnnmg_restrict(box, st.b, st.bc),
+    }
+    return {name: time_kernel(fn, reps) for name, fn in k.items()}
+
+
+def roofline_of(kernel_ms, st, w):
+    """Roofline object of the step's dominant launch (the largest of
+    step_kernel_times), from the algorithmic counts per fine node of
+    flops.ALG_*."""
+    from paper_2307_14837_amd import flops
+
+    name = max(kernel_ms, key=kernel_ms.get)
+    t = kernel_ms[name]
+    nf, npch = st.nf, st.np
+    if name == "gather_forward":
+        flop = flops.mlp_flops_per_patch(w.hidden) * npch
+        peak = FP8_MFMA_PEAK_TFLOPS if st.dtype == 2 else BF16_MFMA_PEAK_TFLOPS
+        return {"kernel": "dnnmg_patch_gather_forward", "bound": "mfma", "achieved": flop / (t * 1e-3) / 1e12,
+                "peak": peak, "unit": "TFLOP/s", "frac": flop / (t * 1e-3) / 1e12 / peak, "traffic": None,
+                "avg_launch_ms": t, "flop_per_launch": flop}
+    per_node = {"residual_b_indicator": flops.ALG_RESIDUAL_B_GENERAL_PER_NODE,
+                "prolong_residual_b": flops.ALG_PROLONG_RESIDUAL_B_PER_NODE,
+                "rhs": flops.ALG_RHS_PER_NODE}
+    if name in per_node:
+        flop = per_node[name] * nf
+        entry = {"residual_b_indicator": "dnnmg_residual_b", "prolong_residual_b": "dnnmg_prolong_residual_b",
+                 "rhs": "dnnmg_rhs"}[name]
+        ach = flop / (t * 1e-3) / 1e12
+        return {"kernel": entry, "bound": "alu", "achieved": ach, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / FP32_VALU_PEAK_TFLOPS, "traffic": traffic_from_profile(entry, w.name),
+                "avg_launch_ms": t, "flop_per_launch": flop}
+    nbytes = flops.BYTES_PER_FINE_NODE.get(name, 0) * nf
+    ach = nbytes / (t * 1e-3) / 1e9
+    return {"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": None, "avg_launch_ms": t}
+
+
+def accuracy(w, dtype, ref):
+    """rel-L2 of one GPU step (seeded inputs and weights, indicator evaluated,
+    fallback not taken) against the FP64 oracle reference of the same step."""
+    st, inp = build_step(w, dtype, indicator=True, theta=float("inf"))
+    out = st.run_numpy(inp.xc, inp.vprev)
+    rel = lambda a, b: float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+    tol = {"fp32": 1e-5, "bf16": 2e-2, "fp8": 5e-2}[dtype]
+    res = {"xt": rel(out["xt"], ref["xt"]), "r": rel(out["r"], ref["r"]), "d": rel(out["d"], ref["d"]),
+           "bc": rel(out["bc"], ref["bc"]), "eta_gpu": out["eta"], "eta_oracle": ref["eta"], "tol_d_bc": tol}
+    res["within_tol"] = bool(res["r"] <= 1e-5 and res["d"] <= tol and res["bc"] <= tol)
+    return res
 
 
 def run_batched(dtype, steps, warmup):
@@ -179,18 +367,17 @@ def run_batched(dtype, steps, warmup):
     bs = batched.BatchedStep(boxes, ns, params, dtype=dtype)
     bs.load(xcs, vps)
     ppt, grid = bs.autotune(reps=5)
-    ms, _ = time_graph(bs, steps, warmup)
+    t = time_graph(bs, steps, warmup)
     npch, nf = bs.plan.n_patches, bs.plan.n_fine
     return {"workload": "cfg3_32_periodic_boxes", "boxes": len(boxes), "patches": npch, "fine_nodes": nf,
             "dtype": dtype, "fused_batched": True, "autotuned": {"patches_per_tile": ppt, "grid": grid},
-            "ms_per_step": ms, "patches_per_s": npch / (ms * 1e-3), "fine_dof_per_s": 4 * nf / (ms * 1e-3)}
+            "ms_per_step": t["ms"], "median_ms": t["median_ms"], "patches_per_s": npch / (t["ms"] * 1e-3),
+            "fine_dof_per_s": 4 * nf / (t["ms"] * 1e-3)}
 
 
 def run_per_box_plain(dtype, steps, warmup):
     """The same 32 boxes as separate plain steps (unfused gather, FP32 network),
     all 32 captured in one HIP graph."""
-    import torch
-
     import dnnmg_synth as syn
     from paper_2307_14837_amd import _lib as L
     from paper_2307_14837_amd import stepper
@@ -216,12 +403,12 @@ def run_per_box_plain(dtype, steps, warmup):
         def replay(self):
             self.g.replay()
 
-    ms, _ = time_graph(All(), steps, warmup)
+    t = time_graph(All(), steps, warmup)
     npch = sum(b.n_patches for b in boxes)
     nf = sum(b.n_fine for b in boxes)
     return {"workload": "cfg3_32_periodic_boxes", "boxes": len(boxes), "patches": npch, "dtype": dtype,
-            "fused_batched": False, "ms_per_step": ms, "patches_per_s": npch / (ms * 1e-3),
-            "fine_dof_per_s": 4 * nf / (ms * 1e-3)}
+            "fused_batched": False, "ms_per_step": t["ms"], "patches_per_s": npch / (t["ms"] * 1e-3),
+            "fine_dof_per_s": 4 * nf / (t["ms"] * 1e-3)}
 
 
 def run_training(steps):
@@ -230,7 +417,7 @@ def run_training(steps):
     import torch
 
     import dnnmg_synth as syn
-    from paper_2307_14837_amd import train
+    from paper_2307_14837_amd import flops, train
 
     n, H = 65536, 256
     params = syn.mlp_params(165, H, 81, seed=0)
@@ -250,8 +437,6 @@ def run_training(steps):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
-    from paper_2307_14837_amd import flops
-
     fl = 3 * flops.mlp_flops_per_patch(H) * n  # forward + backward (about 2x forward)
     return {"workload": "training_batch_65536_width256",
             "dtype": "bf16 forward and backward products, fp32 accumulation and master weights",
@@ -270,11 +455,10 @@ def kernels_at_scale():
     from paper_2307_14837_amd import flops
 
     w = syn.cfg5()
-    st, inp, params = build_step(w, "bf16")
+    st, inp = build_step(w, "bf16")
     st.step()
     torch.cuda.synchronize()
     nf, npch = st.nf, st.np
-    ncell = 8 * npch
     reps = 50
     out = {"workload": w.name, "fine_nodes": nf, "patches": npch}
     B = flops.BYTES_PER_FINE_NODE
@@ -295,16 +479,13 @@ def kernels_at_scale():
     hbm("restrict", lambda: L.dnnmg_restrict(st.box, st.b, st.bc), B["restrict"] * nf)
     hbm("gather_bf16", lambda: L.dnnmg_patch_gather(st.box, st.xt, st.r, st.X, st.xdtype, 192, st.shift,
                                                     st.inv_scale), flops.gather_bytes_per_patch(2) * npch)
-    t = time_kernel(lambda: L.dnnmg_prolong_residual(st.box, st.ns, st.xc, st.vprev, st.xt, st.r), reps)
-    out["prolong_residual"] = {"ms": t, "TFLOP/s": flops.prolong_residual_flops_per_cell() * ncell / (t * 1e-3) / 1e12}
     t = time_kernel(lambda: L.dnnmg_prolong_residual_b(st.box, st.ns, st.xc, st.b, st.xt, st.r), reps)
-    out["prolong_residual_b"] = {"ms": t,
-                                 "TFLOP/s": flops.prolong_residual_b_flops_per_cell() * ncell / (t * 1e-3) / 1e12}
+    out["prolong_residual_b"] = {"ms": t, "TFLOP/s": flops.ALG_PROLONG_RESIDUAL_B_PER_NODE * nf / (t * 1e-3) / 1e12}
     t = time_kernel(lambda: L.dnnmg_rhs(st.box, st.ns, st.xcorr, st.b), reps)
-    out["rhs"] = {"ms": t, "TFLOP/s": flops.rhs_flops_per_cell() * ncell / (t * 1e-3) / 1e12}
+    out["rhs"] = {"ms": t, "TFLOP/s": flops.ALG_RHS_PER_NODE * nf / (t * 1e-3) / 1e12}
     fl = flops.mlp_flops_per_patch(w.hidden) * npch
     for dtype in ("bf16", "fp8"):
-        s2, _, _ = build_step(w, dtype)
+        s2, _ = build_step(w, dtype)
         L.dnnmg_patch_gather(s2.box, s2.xt, s2.r, s2.X, s2.xdtype, 192, s2.shift, s2.inv_scale)
         for tp in (32, 64):
             t = time_kernel(lambda: L.dnnmg_patch_forward_tiles(s2.net, npch, s2.X, 192, s2.Y, tp), reps)
@@ -312,136 +493,159 @@ def kernels_at_scale():
     return out
 
 
-def accuracy(w, dtype):
-    """rel-L2 of the corrected velocity correction d and of b^L against the
-    FP64 oracle on the same inputs (test infrastructure)."""
-    import oracle
-
-    st, inp, params = build_step(w, dtype)
-    out = st.run_numpy(inp.xc, inp.vprev)
-    p32 = [np.asarray(p, np.float32).astype(np.float64) for p in params]
-    ref = oracle.correction_step(w.box, w.ns, p32, inp.xc, out["vprev32"])
-    rel = lambda a, b: float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
-    return {"d": rel(out["d"], ref["d"]), "r": rel(out["r"], ref["r"]), "bc": rel(out["bc"], ref["bc"])}
-
-
-def cpu_baseline(w):
-    """The oracle as it stands, one full correction step of the same workload
-    on one host core (the oracle is single-threaded C)."""
-    import dnnmg_synth as syn
-    import oracle
-
-    inp = syn.step_inputs(w, seed=0)
-    params = [np.asarray(p, np.float32).astype(np.float64) for p in syn.mlp_params(165, w.hidden, 81, seed=0)]
-    oracle.lib()
-    t0 = time.perf_counter()
-    oracle.correction_step(w.box, w.ns, params, inp.xc, inp.vprev)
-    dt = time.perf_counter() - t0
-    return {"value": w.box.n_patches / dt, "unit": "patches/s", "cores": 1, "kind": "oracle",
-            "sample": f"one full correction step of {w.name} ({w.box.n_patches} patches) in FP64, "
-                      f"{dt:.2f} s"}
-
-
-def main():
-    args = parse()
-    if args.pmc_probe:
-        pmc_probe()
-        return
-    if args.scale_only:
-        print(json.dumps({"kernels_at_scale": kernels_at_scale()}), flush=True)
-        return
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
-                          "n_gpus": args.gpus}))
-        sys.exit(2)
+def pmc_probe():
+    """The headline step's indicator residual (general iterate against the
+    carried right-hand side) and prolongation + residual, three launches each
+    on step data, then a plain device copy of PMC_COPY_MIB MiB, for counter
+    runs.  The network has seeded weights (no training in this run): its
+    correction is nonzero on every patch, as the trained network's is, so
+    the residual kernels do the same work."""
     import torch
 
     import dnnmg_synth as syn
     from paper_2307_14837_amd import _lib as L
-    from paper_2307_14837_amd import flops
+
+    w = syn.cfg5()
+    # the step without the indicator fills every buffer the indicator's
+    # residual reads, and launches none of the kernels counted below
+    st, _ = build_step(w, "bf16")
+    st.step()
+    r2 = torch.empty_like(st.r)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        L.dnnmg_residual_b(st.box, st.ns, st.xcorr, st.b, r2, st.ws_res)
+    for _ in range(3):
+        L.dnnmg_prolong_residual_b(st.box, st.ns, st.xc, st.b, st.xt, st.r)
+    torch.cuda.synchronize()
+    n = PMC_COPY_MIB * 2**20 // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    print(json.dumps({"pmc_probe": w.name, "copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n,
+                      "src_hash": src_hash(*RESIDUAL_SOURCES)}), flush=True)
+
+
+def profile_step(steps):
+    """The headline step alone: distilled FP8 network, indicator at threshold
+    1, `steps` graph replays (for rocprofv3 --kernel-trace --stats)."""
+    import torch
+
+    import dnnmg_synth as syn
+
+    w = syn.cfg5()
+    params, shift, inv, _ = distilled_network(w)
+    st, _ = build_step(w, "fp8", params, shift, inv, indicator=True, theta=1.0)
+    st.capture()
+    for _ in range(steps):
+        st.replay()
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_step": w.name, "replays": steps, "fell_back_last": int(st.fell_back.item())}),
+          flush=True)
+
+
+def main():
+    args = parse()
+    if args.cpu_worker is not None:
+        cpu_worker(args.cpu_worker)
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1", "n_gpus": args.gpus}))
+        sys.exit(2)
+    if args.pmc_probe:
+        pmc_probe()
+        return
+    if args.profile_step:
+        profile_step(args.steps)
+        return
+    if args.scale_only:
+        print(json.dumps({"kernels_at_scale": kernels_at_scale()}), flush=True)
+        return
+
+    import dnnmg_synth as syn
+
+    # CPU leg first, before the GPU is touched: the oracle's throughput on the
+    # host cores, and the FP64 references of the accuracy figures
+    cpu, refs = None, {}
+    if not args.no_cpu:
+        print("[bench] CPU oracle baseline (1 core, then all cores)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline()
+        print("[bench] FP64 oracle references (large channel, 16,384-patch channel)", file=sys.stderr, flush=True)
+        refs["cfg5"] = oracle_reference(syn.cfg5())
+        refs["cfg2"] = oracle_reference(syn.cfg2())
+
+    import torch
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
-    w = syn.cfg2()
-    st, inp, params = build_step(w, "bf16")
-    print(f"[bench] {w.name}: {st.np} patches, {st.nf} fine nodes; timing {args.steps} graph replays",
-          file=sys.stderr, flush=True)
-    ms, wall = time_graph(st, args.steps, args.warmup)
-
-    # dominant kernel: prolongation + fine residual against the carried
-    # right-hand side (VALU bound), timed live with HIP events on the stream
-    # it runs on
-    reps = 50
-    res_ms = time_kernel(lambda: L.dnnmg_prolong_residual_b(st.box, st.ns, st.xc, st.b, st.xt, st.r), reps)
-    ncells = 8 * st.np
-    flop = flops.prolong_residual_b_flops_per_cell() * ncells
-    achieved = flop / (res_ms * 1e-3) / 1e12
-    traffic = traffic_from_profile("dnnmg_prolong_residual_b", w.name)
-    L.dnnmg_patch_gather(st.box, st.xt, st.r, st.X, st.xdtype, 192, st.shift, st.inv_scale)
-    kernel_ms = {
-        "prolong_residual_b": res_ms,
-        "prolong_residual": time_kernel(lambda: L.dnnmg_prolong_residual(st.box, st.ns, st.xc, st.vprev, st.xt,
-                                                                         st.r), reps),
-        "residual": time_kernel(lambda: L.dnnmg_residual(st.box, st.ns, st.xt, st.vprev, st.r, st.ws_res), reps),
-        "prolong": time_kernel(lambda: L.dnnmg_prolong(st.box, st.xc, st.xt), reps),
-        "gather_forward_fused": time_kernel(lambda: L.dnnmg_patch_gather_forward(st.box, st.net, st.xt, st.r, st.Y,
-                                                                                st.shift, st.inv_scale), reps),
-        "gather": time_kernel(lambda: L.dnnmg_patch_gather(st.box, st.xt, st.r, st.X, st.xdtype, 192,
-                                                          st.shift, st.inv_scale), reps),
-        "forward": time_kernel(lambda: L.dnnmg_patch_forward(st.net, st.np, st.X, 192, st.Y), reps),
-        "scatter": time_kernel(lambda: L.dnnmg_scatter_avg(st.box, st.Y, st.xcorr, vbase=st.xt), reps),
-        "rhs": time_kernel(lambda: L.dnnmg_rhs(st.box, st.ns, st.xcorr, st.b), reps),
-        "restrict": time_kernel(lambda: L.dnnmg_restrict(st.box, st.b, st.bc), reps),
-    }
-    fwd_tiles = {}
-    for tp in (16, 32, 64):
-        fwd_tiles[tp] = time_kernel(lambda: L.dnnmg_patch_forward_tiles(st.net, st.np, st.X, 192, st.Y, tp), reps)
-    kernel_ms["forward_by_tile"] = fwd_tiles
-    mlp_flop = flops.mlp_flops_per_patch(256) * st.np
+    w = syn.cfg5()
+    print(f"[bench] {w.name}: training the network on the plain fine correction", file=sys.stderr, flush=True)
+    params, shift, inv, dinfo = distilled_network(w)
+    print(f"[bench] headline: FP8 network + indicator (theta 1), {args.steps} graph replays", file=sys.stderr,
+          flush=True)
+    head, st, t = run_step(w, "fp8", args.steps, args.warmup, params, shift, inv, indicator=True, theta=1.0,
+                           account=True)
+    kernel_ms = step_kernel_times(st)
+    roof = roofline_of(kernel_ms, st, w)
     out = {
         "metric": "DNN-MG correction step throughput (patches/s; fine DOF/s also given)",
-        "value": st.np / (ms * 1e-3),
+        "value": head["patches_per_s"],
         "unit": "patches/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": head["ms_per_step"],
+        "median_ms_per_step": head["median_ms"],
+        "min_ms_per_step": head["min_ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16",
+        "dtype": "fp8",
         "data": "synthetic",
         "config": {"workload": w.name, "patches": st.np, "fine_nodes": st.nf, "fine_dofs": 4 * st.nf,
-                   "network": "165-256-256-81 tanh, BF16 MFMA, FP32 accumulate",
+                   "network": "165-512-512-81 tanh; E4M3 hidden product (per-tensor scales), BF16 input and "
+                              "output layers, FP32 accumulation",
+                   "network_weights": "trained on the GPU on the plain fine correction of 4 other seeded inputs",
                    "stencils": "FP32 (prolongation from FP64, restriction to FP64)",
+                   "indicator": "eta = ||r(x_corr)|| / ||r(x~)|| in FP64, theta = 1, fallback = 4 "
+                                "pressure-held patch-Vanka sweeps",
+                   "time_loop": "each replay's right-hand side feeds the next replay's residual",
                    "parallelism": "1 GPU", "graph": "hipGraph replay of the whole step"},
-        "fine_dof_per_s": 4 * st.nf / (ms * 1e-3),
-        "roofline": {"kernel": "dnnmg_prolong_residual_b", "bound": "alu", "achieved": achieved,
-                     "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": traffic,
-                     "avg_launch_ms": res_ms, "flop_per_launch": flop},
-        "kernel_ms": kernel_ms,
-        "mlp_tflops": mlp_flop / (kernel_ms["forward"] * 1e-3) / 1e12,
-        "wall_s_timed": wall,
+        "fine_dof_per_s": head["fine_dof_per_s"],
+        "indicator": head["indicator_stats"],
+        "network_training": dinfo,
+        "roofline": roof,
+        "step_kernel_ms": kernel_ms,
+        "wall_s_timed": t["wall_s"],
     }
     if not args.no_variants:
-        print("[bench] variants: fp32 network, indicator, large FP8 channel", file=sys.stderr, flush=True)
-        out["variants"] = [
-            run_variant(w, "fp32", args.steps, args.warmup),
-            run_variant(w, "bf16", args.steps, args.warmup, indicator=True, fallback="never"),
-            run_variant(w, "bf16", args.steps, args.warmup, indicator=True, fallback="always"),
-            run_variant(syn.cfg5(), "fp8", max(args.steps // 4, 10), max(args.warmup // 4, 3), indicator=True),
-            run_variant(syn.cfg5(), "bf16", max(args.steps // 4, 10), max(args.warmup // 4, 3)),
-            run_batched("bf16", max(args.steps // 4, 10), max(args.warmup // 4, 3)),
-            run_per_box_plain("fp32", max(args.steps // 4, 10), max(args.warmup // 4, 3)),
+        print("[bench] variants", file=sys.stderr, flush=True)
+        sv, wv = max(args.steps // 4, 10), max(args.warmup // 4, 3)
+        c2 = syn.cfg2()
+        variants = [
+            run_step(w, "fp32", sv, wv, params, shift, inv, indicator=True, theta=1.0, account=True)[0],
+            run_step(w, "bf16", sv, wv, params, shift, inv, indicator=True, theta=1.0, account=True)[0],
+            run_step(w, "fp8", sv, wv, params, shift, inv)[0],
+            run_step(c2, "bf16", args.steps, args.warmup)[0],
+            run_step(c2, "fp32", args.steps, args.warmup)[0],
+            run_batched("bf16", sv, wv),
+            run_per_box_plain("fp32", sv, wv),
             run_training(20),
         ]
+        out["variants"] = variants
         print("[bench] kernels on the large channel", file=sys.stderr, flush=True)
         out["kernels_at_scale"] = kernels_at_scale()
-        print("[bench] accuracy vs oracle", file=sys.stderr, flush=True)
-        out["accuracy_rel_l2"] = {"bf16": accuracy(w, "bf16"), "fp32": accuracy(w, "fp32")}
-    if not args.no_cpu:
-        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w)
+    if refs:
+        print("[bench] accuracy against the FP64 oracle", file=sys.stderr, flush=True)
+        out["accuracy_rel_l2"] = {
+            "note": "one step on seeded inputs and seeded N(0, 1/fan_in) weights, indicator evaluated",
+            "cfg5_channel_128x32x32": {dt: accuracy(w, dt, refs["cfg5"]) for dt in ("fp32", "bf16", "fp8")},
+            "cfg2_channel_64x16x16": {dt: accuracy(syn.cfg2(), dt, refs["cfg2"]) for dt in ("fp32", "bf16")},
+            "oracle_seconds": {k: v["seconds"] for k, v in refs.items()},
+        }
+    if cpu:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

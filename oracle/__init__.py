@@ -292,16 +292,31 @@ def fallback_taken(n0, n1, theta) -> int:
     return int(not (eta <= theta))
 
 
+def mlp_forward_rows(X, params, threads=1):
+    """mlp_forward over row ranges on `threads` host threads (the network acts
+    on each patch row alone, so every row's arithmetic is unchanged)."""
+    if threads <= 1 or X.shape[0] < 2 * threads:
+        return mlp_forward(X, *params)
+    from concurrent.futures import ThreadPoolExecutor
+
+    X = _f64(X)
+    parts = np.array_split(np.arange(X.shape[0]), threads)
+    with ThreadPoolExecutor(threads) as ex:
+        Ys = list(ex.map(lambda idx: mlp_forward(X[idx[0]:idx[-1] + 1], *params), parts))
+    return np.concatenate(Ys)
+
+
 def correction_step(box, ns, params, xc, vprev, shift=None, inv_scale=None, indicator=False,
-                    theta=1.0, fallback_sweeps=4, omega=1.0):
+                    theta=1.0, fallback_sweeps=4, omega=1.0, threads=1):
     """Algorithm 1 after the coarse solve, step by step in FP64:
     x~ = P x^L; r = F - A(x~); X = Q(x~, r, geometry); Y = N(X);
     x_corr = (v~ + L(Y), p~); b = Rhs(v~ + d); b^L = R b.
-    With indicator, also r(x_corr) and eta = ||r(x_corr)|| / ||r(x~)||."""
+    With indicator, also r(x_corr) and eta = ||r(x_corr)|| / ||r(x~)||.
+    threads > 1 evaluates the network's rows on that many host threads."""
     xt = prolong(box, xc)
     r = residual(box, ns, xt, vprev)
     X = gather(box, xt, r, shift, inv_scale)
-    Y = mlp_forward(X, *params)
+    Y = mlp_forward_rows(X, params, threads)
     d = scatter(box, Y)
     vcorr = xt[:3] + d
     out = dict(xt=xt, r=r, X=X, Y=Y, d=d)

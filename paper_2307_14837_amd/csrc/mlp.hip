@@ -429,7 +429,7 @@ static void fp8_scales(const dnnmg_mlp *net, float &s1, float &q1) {
 // Instantiated (dtype, width, PT) forward variants.
 #define DNNMG_FWD_VARIANTS(X)                                                                           \
     X(DNNMG_F32, 64, 1) X(DNNMG_F32, 64, 2) X(DNNMG_F32, 128, 1) X(DNNMG_F32, 128, 2)                   \
-    X(DNNMG_F32, 256, 1) X(DNNMG_F32, 256, 2)                                                            \
+    X(DNNMG_F32, 256, 1) X(DNNMG_F32, 256, 2) X(DNNMG_F32, 512, 1) X(DNNMG_F32, 512, 2)                  \
     X(DNNMG_BF16, 64, 1) X(DNNMG_BF16, 64, 2) X(DNNMG_BF16, 64, 4)                                       \
     X(DNNMG_BF16, 128, 1) X(DNNMG_BF16, 128, 2) X(DNNMG_BF16, 128, 4)                                    \
     X(DNNMG_BF16, 256, 1) X(DNNMG_BF16, 256, 2) X(DNNMG_BF16, 256, 4)                                    \

@@ -99,3 +99,33 @@ def gather_bytes_per_patch(x_bytes: int, ldx: int = 192) -> float:
     """Read 6 fine fields at the patch's nodes (about 8 fine nodes own one patch),
     write one padded row of the network input."""
     return 8 * 6 * 4 + ldx * x_bytes
+
+
+# ---- algorithmic counts per fine node used for the roofline figures --------
+# Per-node estimates of the steps of the correction, lower than the itemised
+# counts above (they leave out the sum-factorisation bookkeeping): the fine
+# residual about 1.3 k flop at a prolongated iterate (Galerkin terms; its
+# local projection terms vanish there) and 2.9 k with active LPS terms; the
+# right-hand side about 1.2 k; the prolongation under 10.  A kernel that
+# evaluates only part of a step (the forms against the carried right-hand
+# side leave the previous velocity's terms to the Rhs of the previous step)
+# is credited with the step's estimate times the share of the itemised count
+# that it evaluates.
+ALG_RESIDUAL_AT_PROLONGATION_PER_NODE = 1300
+ALG_RESIDUAL_GENERAL_PER_NODE = 2900
+ALG_RHS_PER_NODE = 1200
+ALG_PROLONG_PER_NODE = 10
+
+
+def _share_prolong_residual_b() -> float:
+    return prolong_residual_b_flops_per_cell() / prolong_residual_flops_per_cell()
+
+
+def _share_residual_b_general() -> float:
+    full = residual_flops_per_cell(lps=True)
+    return (full - rhs_flops_per_cell()) / full
+
+
+ALG_PROLONG_RESIDUAL_B_PER_NODE = round(
+    (ALG_PROLONG_PER_NODE + ALG_RESIDUAL_AT_PROLONGATION_PER_NODE) * _share_prolong_residual_b())
+ALG_RESIDUAL_B_GENERAL_PER_NODE = round(ALG_RESIDUAL_GENERAL_PER_NODE * _share_residual_b_general())

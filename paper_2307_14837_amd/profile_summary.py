@@ -11,10 +11,13 @@ probe runs in the same process:
 F.csv / W.csv are rocprofv3 `*_counter_collection.csv` files; probe.log is
 what `bench.py --pmc-probe` printed (its last JSON line is used).
 
-stats: a Markdown table of a `--kernel-trace --stats` run's kernel_stats.csv:
+stats: a Markdown table of a `--kernel-trace --stats` run's kernel_stats.csv,
+or of its kernel_trace.csv restricted to the dispatches after the last one
+matching --after:
 
     python -m paper_2307_14837_amd.profile_summary stats --csv K.csv --out profiles/<name>.md \\
         --command "<the rocprofv3 command>"
+    python -m paper_2307_14837_amd.profile_summary stats --trace T.csv --after k_adamw ...
 """
 from __future__ import annotations
 
@@ -23,7 +26,7 @@ import csv
 import json
 from collections import defaultdict
 
-ENTRY_KERNELS = {"dnnmg_prolong_residual": ("k_residual<2, false>",),
+ENTRY_KERNELS = {"dnnmg_residual_b": ("k_residual<4, false>", "k_lps_corners"),
                  "dnnmg_prolong_residual_b": ("k_residual<3, false>",)}
 COPY_KERNEL = "neg"
 
@@ -47,8 +50,27 @@ def find(avgs, needle):
     return hits[0]
 
 
+def trace_stats(path, after):
+    """kernel_stats-like rows from a kernel_trace.csv, over the dispatches
+    after the last one whose name contains `after` (the setup before the
+    measured section, e.g. network training, is left out)."""
+    rows = list(csv.DictReader(open(path)))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    last = max((i for i, r in enumerate(rows) if after in r["Kernel_Name"]), default=-1)
+    rows = rows[last + 1:]
+    per = defaultdict(list)
+    for r in rows:
+        per[r["Kernel_Name"]].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    total = sum(sum(v) for v in per.values()) or 1
+    out = []
+    for name, d in per.items():
+        out.append({"Name": name, "Calls": len(d), "TotalDurationNs": sum(d), "AverageNs": sum(d) / len(d),
+                    "MinNs": min(d), "MaxNs": max(d), "Percentage": 100.0 * sum(d) / total})
+    return out
+
+
 def stats(a):
-    rows = list(csv.DictReader(open(a.csv)))
+    rows = trace_stats(a.trace, a.after) if a.trace else list(csv.DictReader(open(a.csv)))
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     lines = [f"# {a.title}", "", "Command:", "", "```", a.command, "```", "",
              "| kernel | calls | avg us | min us | max us | share % |", "|---|---:|---:|---:|---:|---:|"]
@@ -66,7 +88,9 @@ def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="mode", required=True)
     sp = sub.add_parser("stats")
-    sp.add_argument("--csv", required=True)
+    sp.add_argument("--csv", default=None, help="kernel_stats.csv of a --stats run")
+    sp.add_argument("--trace", default=None, help="kernel_trace.csv (with --after)")
+    sp.add_argument("--after", default="", help="count only dispatches after the last kernel matching this")
     sp.add_argument("--out", required=True)
     sp.add_argument("--command", default="")
     sp.add_argument("--title", default="rocprofv3 kernel statistics")

@@ -166,3 +166,97 @@ def feature_stats(X32, n_rows):
     sd = A.std(axis=0)
     inv = np.where(sd > 1e-12 * np.maximum(1.0, np.abs(mu)), 1.0 / np.where(sd > 0, sd, 1.0), 1.0)
     return mu.astype(np.float32), inv.astype(np.float32)
+
+
+def plain_correction_pairs(box, ns, inputs, sweeps=4, device="cuda:0"):
+    """Training pairs from the plain fine-level method on one box (the
+    learned part is trained on data the plain method generates).  For every
+    (x^L, v_prev) of `inputs`: b = Rhs(v_prev); x~ = P x^L and r = b - A(x~);
+    the plain correction x_V = `sweeps` pressure-held patch-Vanka sweeps from
+    x~ (the fallback's correction, taken unconditionally); the network input
+    Q(x~, r) and the target Q(x_V - x~) (velocity part, 81 per patch).
+    Every step runs in the library's kernels.  Returns FP32 inputs [rows][192]
+    (not standardised), targets [rows][81] and the indicator of the plain
+    correction eta_V = ||r(x_V)|| / ||r(x~)|| per input."""
+    dev = torch.device(device)
+    bx, nsp = L.Box.of(box), L.NS.of(ns)
+    nf, nc, npch = L.box_sizes(bx)
+    f32 = dict(dtype=torch.float32, device=dev)
+    xc = torch.zeros(4 * nc, dtype=torch.float64, device=dev)
+    vp = torch.zeros(3 * nf, **f32)
+    xt, r, b, xv, rv = (torch.zeros(4 * nf, **f32) for _ in range(5))
+    ws_fb = torch.zeros(L.fallback_workspace_bytes(bx), dtype=torch.uint8, device=dev)
+    ws_res = torch.zeros(L.residual_workspace_bytes(bx), dtype=torch.uint8, device=dev)
+    ws_n = torch.zeros(2 * L.norm2_workspace_bytes(), dtype=torch.uint8, device=dev)
+    norms = torch.ones(2, dtype=torch.float64, device=dev)
+    Tpad = torch.zeros(npch * LDX, **f32)
+    X = torch.zeros(len(inputs) * npch, LDX, **f32)
+    T = torch.zeros(len(inputs) * npch, L.N_OUT, **f32)
+    etas = []
+    for s, (c, v) in enumerate(inputs):
+        xc.copy_(torch.as_tensor(np.asarray(c, np.float64).ravel()))
+        vp.copy_(torch.as_tensor(np.asarray(v, np.float32).ravel()))
+        L.dnnmg_rhs(bx, nsp, vp, b)
+        L.dnnmg_prolong_residual_b(bx, nsp, xc, b, xt, r)
+        L.dnnmg_patch_gather(bx, xt, r, X[s * npch:(s + 1) * npch], L.F32, LDX)
+        norms.fill_(1.0)  # eta = 1 > theta = 0: the plain correction is taken
+        L.dnnmg_fallback_b(bx, nsp, xt, b, norms, xv, ws_fb, theta=0.0, sweeps=sweeps)
+        L.dnnmg_residual_b(bx, nsp, xv, b, rv, ws_res)
+        L.dnnmg_norm2_pair_f64(r, rv, norms, ws_n)
+        dv = xv - xt
+        L.dnnmg_patch_gather(bx, dv, dv, Tpad, L.F32, LDX)
+        T[s * npch:(s + 1) * npch] = Tpad.view(npch, LDX)[:, :L.N_OUT]
+        n = norms.cpu().numpy()
+        etas.append(float(np.sqrt(n[1] / n[0])) if n[0] > 0 else 0.0)
+    return X, T, etas
+
+
+def standardisation(X32):
+    """Per-feature shift and inverse scale (R9 standardisation) of FP32
+    inputs [rows][192]: mean and 1/std over the rows (constant features keep
+    scale 1)."""
+    A = X32[:, :L.N_IN].double()
+    mu, sd = A.mean(0), A.std(0)
+    ok = sd > 1e-12 * torch.clamp(mu.abs(), min=1.0)
+    inv = torch.where(ok, 1.0 / torch.where(ok, sd, torch.ones_like(sd)), torch.ones_like(sd))
+    return mu.float(), inv.float()
+
+
+def distill(box, ns, inputs, hidden, steps=600, batch=65536, lr=1e-3, seed=0, sweeps=4, device="cuda:0"):
+    """Trains the patch network on the plain fine-level correction of `box`
+    (plain_correction_pairs on `inputs`), BF16 compute with FP32 master
+    weights and AdamW, batches of `batch` rows drawn uniformly.  Inputs are
+    standardised per feature and the targets by one scalar, folded into the
+    output layer of the returned parameters.  Returns (params [W1, b1, W2,
+    b2, W3, b3] numpy, shift, inv_scale (numpy FP32 [165]), info)."""
+    dev = torch.device(device)
+    X, T, etas = plain_correction_pairs(box, ns, inputs, sweeps=sweeps, device=device)
+    shift, inv = standardisation(X)
+    rows = X.shape[0]
+    Z = torch.zeros(rows, LDX, dtype=torch.bfloat16, device=dev)
+    Z[:, :L.N_IN] = ((X[:, :L.N_IN] - shift) * inv).to(torch.bfloat16)
+    del X
+    t_scale = float(T.double().std().item())
+    Tn = T / t_scale
+    params = [np.asarray(p) for p in _init_params(hidden, seed)]
+    tr = PatchTrainer(params, dtype="bf16", lr=lr, weight_decay=1e-5, max_batch=batch, device=device)
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    bsz = min(batch, rows)
+    for _ in range(steps):
+        idx = torch.randint(0, rows, (bsz,), device=dev, generator=g)
+        tr.step(Z[idx].contiguous().view(-1), Tn[idx].contiguous().view(-1), bsz)
+    info = {"rows": rows, "steps": steps, "batch": bsz, "final_loss": tr.loss(bsz), "target_scale": t_scale,
+            "plain_correction_eta": etas}
+    return tr.params(target_scale=t_scale), shift.cpu().numpy(), inv.cpu().numpy(), info
+
+
+def _init_params(hidden, seed):
+    """N(0, 1/fan_in) weights, zero biases, the output layer scaled by 0.1
+    (a small initial correction)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for fi, fo in ((L.N_IN, hidden), (hidden, hidden), (hidden, L.N_OUT)):
+        out += [rng.standard_normal((fi, fo)) / np.sqrt(fi), np.zeros(fo)]
+    out[4] *= 0.1
+    return out

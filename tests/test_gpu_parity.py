@@ -372,10 +372,10 @@ def padded(X, ldx):
     return out
 
 
-@pytest.mark.parametrize("n", [1, 33, 64, 1000, 4099])
-def test_mlp_fp32(L, orc, n):
-    say("mlp fp32 n", n)
-    params = syn.mlp_params(165, 128, 81, seed=1, bias_scale=0.1)
+@pytest.mark.parametrize("H,n", [(128, 1), (128, 33), (128, 64), (128, 1000), (128, 4099), (512, 33), (512, 4099)])
+def test_mlp_fp32(L, orc, H, n):
+    say("mlp fp32 H", H, "n", n)
+    params = syn.mlp_params(165, H, 81, seed=1, bias_scale=0.1)
     X = f32(np.random.default_rng(2).standard_normal((n, 165)))
     Y, _ = run_forward(L, L.F32, params, to_gpu(padded(X, 192).ravel()), 192)
     p32 = [f32(p).astype(np.float64) for p in params]

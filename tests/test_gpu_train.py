@@ -56,7 +56,7 @@ def oracle_grads(orc, params, X, T):
     return [dW1, db1, dW2, db2, dW3, db3], loss, dY
 
 
-@pytest.mark.parametrize("H,n", [(64, 1), (64, 257), (128, 4099), (256, 2048)])
+@pytest.mark.parametrize("H,n", [(64, 1), (64, 257), (128, 4099), (256, 2048), (512, 700)])
 def test_backward_fp32(L, orc, H, n):
     say("backward fp32 H", H, "n", n)
     params = syn.mlp_params(165, H, 81, seed=11, bias_scale=0.1)
@@ -73,7 +73,7 @@ def test_backward_fp32(L, orc, H, n):
         assert e <= 1e-5, i
 
 
-@pytest.mark.parametrize("H,n", [(128, 333), (256, 4096)])
+@pytest.mark.parametrize("H,n", [(128, 333), (256, 4096), (512, 1500)])
 def test_backward_bf16(L, orc, H, n):
     say("backward bf16 H", H, "n", n)
     params = syn.mlp_params(165, H, 81, seed=13, bias_scale=0.1)

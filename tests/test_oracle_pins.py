@@ -705,3 +705,15 @@ def test_mse_matches_torch(orc):
     ref.backward()
     assert abs(loss - ref.item()) <= 1e-13 * ref.item()
     np.testing.assert_allclose(dY, y.grad.numpy(), rtol=1e-13, atol=1e-16)
+
+
+def test_mlp_rows_on_threads_equal_one_call(orc):
+    """The network evaluated over row ranges on host threads gives the one-call
+    result bit for bit (each row's arithmetic is the same)."""
+    import dnnmg_synth as syn
+
+    params = syn.mlp_params(165, 64, 81, seed=3, bias_scale=0.1)
+    X = np.random.default_rng(4).standard_normal((1001, 165))
+    a = orc.mlp_forward(X, *params)
+    b = orc.mlp_forward_rows(X, params, threads=7)
+    assert np.array_equal(a, b)
