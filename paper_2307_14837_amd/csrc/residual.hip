@@ -577,7 +577,7 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
         return s;
     };
 
-    bool need = false;
+    bool need = false, need_p = false;
     float xv[3][8]; // x~ at the Gauss points (both passes of the general residual)
     if constexpr (MODE == MODE_RHS) {
         float w[3][8], wv[3][8];
@@ -622,18 +622,25 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
         // patch interpolant.  When the vertex values and the interpolant
         // computed here agree bit for bit every LPS contribution of the cell
         // is exactly zero; the other cells get them in a second pass.
+        // The delta terms depend on the velocity only and the alpha term on
+        // the pressure only, so the two are decided separately: `need` for
+        // the velocity (field by field until one differs; a wave whose cells
+        // all differ in the first field skips the other two), `need_p` for
+        // the pressure (the network corrects only the velocity, so on the
+        // indicator's and the fallback's iterates the alpha term vanishes).
         if (mode_general(MODE) && live) {
-            // field by field until one differs (a wave whose cells all
-            // differ in the first field skips the other three)
 #pragma unroll
             for (int d = 0; d < 4; ++d) {
-                if (need) break;
+                if (d < 3 && need) continue;
                 float cv[8], pw[8];
 #pragma unroll
                 for (int j = 0; j < 8; ++j) cv[j] = sX[d * T::SN + cb + coff(j)];
                 pi_vertices(cv, ox, oy, oz, pw);
+                bool differs = false;
 #pragma unroll
-                for (int j = 0; j < 8; ++j) need |= pw[j] != sX[d * T::SN + xb + xoff(j)];
+                for (int j = 0; j < 8; ++j) differs |= pw[j] != sX[d * T::SN + xb + xoff(j)];
+                if (d < 3) need |= differs;
+                else need_p = differs;
             }
         }
         // x~, vp and p~ at the Gauss points; divergence of x~
@@ -738,7 +745,8 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
     const int pcb = (2 * ppx + 1) + T::EX * ((2 * ppy + 1) + T::EY * (2 * ppz + 1));
     bool any_lps = false;
     if constexpr (mode_general(MODE)) {
-        any_lps = __syncthreads_or(need);
+        const bool any_v = __syncthreads_or(need), any_p = __syncthreads_or(need_p);
+        any_lps = any_v || any_p;
         if (any_lps) {
             // the cell's stabilisation parameter (stabparams: |v|_inf over the
             // vertices) and pi v at the Gauss points, shared by the equations
@@ -747,7 +755,7 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
             patch_coords(ox, sx);
             patch_coords(oy, sy);
             patch_coords(oz, sz);
-            if (live && need) {
+            if (live && (need || need_p)) {
                 float vmax2 = 0.0f;
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
@@ -756,6 +764,8 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
                     vmax2 = fmaxf(vmax2, u0 * u0 + u1 * u1 + u2 * u2);
                 }
                 den = P.nu * (1.0f / (P.hT * P.hT)) + sqrtf(vmax2) / P.hT + P.inv_dt;
+            }
+            if (live && need) {
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
                     float w[8];
@@ -765,10 +775,13 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
                 }
             }
             for (int a = 0; a < 4; ++a) {
+                // equations whose terms vanish on every cell of the tile are
+                // skipped (the decision is uniform over the workgroup)
+                if ((a < 3 && !any_v) || (a == 3 && !any_p)) continue;
                 float acc[8], cor[8];
 #pragma unroll
                 for (int j = 0; j < 8; ++j) acc[j] = cor[j] = 0.0f;
-                if (live && need) {
+                if (live && (a < 3 ? need : need_p)) {
                     if (a < 3) {
                         // R_a = v.grad v_a - pi v . grad pi v_a, tested with
                         // v.grad phi (own vertices) and pi v . grad pi phi
