@@ -212,6 +212,74 @@ def scatter(box, Y) -> np.ndarray:
     return out
 
 
+# ------------------------------------------- J-level prediction (Sec. 4.2) --
+
+def level_box(box, J) -> Box:
+    """The box whose fine lattice is the prediction lattice J levels above the
+    coarse mesh of `box` (n * 2^(J-1) cells per axis)."""
+    bx = _box(box)
+    out = Box()
+    for a in range(3):
+        out.n[a] = int(bx.n[a]) << (J - 1)
+        out.len[a] = bx.len[a]
+    out.periodic_mask, out.dirichlet_mask = bx.periodic_mask, bx.dirichlet_mask
+    return out
+
+
+def patch_nodes(J) -> int:
+    return ((1 << J) + 1) ** 3
+
+
+def dofmap_levels(box, J):
+    """dof(P_M, iota) [N_p, (2^J+1)^3] and valence on the J-level lattice."""
+    bx = _box(box)
+    m = np.zeros((patches(bx), patch_nodes(J)), dtype=np.int32)
+    mult = np.zeros(fine_nodes(level_box(bx, J)), dtype=np.uint8)
+    lib().or_dofmap_levels(ctypes.byref(bx), ctypes.c_int(J), m.ctypes.data_as(ctypes.c_void_p),
+                           mult.ctypes.data_as(ctypes.c_void_p))
+    return m, mult
+
+
+def prolong_levels(box, J, xc) -> np.ndarray:
+    """P^J: the prolongation of Algorithm 1 applied J times (coarse mesh of
+    `box` to the J-level lattice)."""
+    x = _f64(xc)
+    for lev in range(1, J + 1):
+        x = prolong(level_box(box, lev), x)
+    return x
+
+
+def restrict_levels(box, J, bf) -> np.ndarray:
+    """(P^J)^T: the restriction applied J times (J-level lattice to the coarse
+    mesh of `box`)."""
+    b = _f64(bf)
+    for lev in range(J, 0, -1):
+        b = restrict(level_box(box, lev), b)
+    return b
+
+
+def gather_levels(box, J, x, r, shift=None, inv_scale=None) -> np.ndarray:
+    """Network input batch of the J-level prediction [N_p, 6 (2^J+1)^3 + 3]."""
+    bx = _box(box)
+    nf = fine_nodes(level_box(bx, J))
+    x = _f64(x).reshape(-1, nf)
+    r = _f64(r).reshape(-1, nf)
+    out = np.zeros((patches(bx), 6 * patch_nodes(J) + 3))
+    lib().or_gather_levels(ctypes.byref(bx), ctypes.c_int(J), _dp(x), _dp(r), _dp(_f64(shift)),
+                           _dp(_f64(inv_scale)), _dp(out))
+    return out
+
+
+def scatter_levels(box, J, Y) -> np.ndarray:
+    """Extension L of eq. (defL) on the J-level patches: [3][N_f]."""
+    bx = _box(box)
+    nf = fine_nodes(level_box(bx, J))
+    Y = _f64(Y).reshape(patches(bx), 3 * patch_nodes(J))
+    out = np.zeros((3, nf))
+    lib().or_scatter_levels(ctypes.byref(bx), ctypes.c_int(J), _dp(Y), _dp(out))
+    return out
+
+
 def mlp_forward(X, W1, b1, W2, b2, W3, b3, want_hidden=False):
     """Y = W3^T tanh(W2^T tanh(W1^T x + b1) + b2) + b3 per row (Sec. 3, tanh MLP)."""
     X = _f64(X)
@@ -307,17 +375,29 @@ def mlp_forward_rows(X, params, threads=1):
 
 
 def correction_step(box, ns, params, xc, vprev, shift=None, inv_scale=None, indicator=False,
-                    theta=1.0, fallback_sweeps=4, omega=1.0, threads=1):
+                    theta=1.0, fallback_sweeps=4, omega=1.0, threads=1, levels=1):
     """Algorithm 1 after the coarse solve, step by step in FP64:
     x~ = P x^L; r = F - A(x~); X = Q(x~, r, geometry); Y = N(X);
     x_corr = (v~ + L(Y), p~); b = Rhs(v~ + d); b^L = R b.
     With indicator, also r(x_corr) and eta = ||r(x_corr)|| / ||r(x~)||.
-    threads > 1 evaluates the network's rows on that many host threads."""
-    xt = prolong(box, xc)
+    threads > 1 evaluates the network's rows on that many host threads.
+    levels = J: the prediction J levels above the coarse mesh (Sec. 4.2):
+    P and R are applied J times, the residual, Rhs and fallback live on the
+    J-level lattice (the fine mesh of level_box(box, J)), the patches are
+    the coarse cells with (2^J + 1)^3 nodes."""
+    if levels == 1:
+        xt = prolong(box, xc)
+    else:
+        xt = prolong_levels(box, levels, xc)
+        fine_box = level_box(box, levels)
+        box, coarse_box = fine_box, box
     r = residual(box, ns, xt, vprev)
-    X = gather(box, xt, r, shift, inv_scale)
+    if levels == 1:
+        X = gather(box, xt, r, shift, inv_scale)
+    else:
+        X = gather_levels(coarse_box, levels, xt, r, shift, inv_scale)
     Y = mlp_forward_rows(X, params, threads)
-    d = scatter(box, Y)
+    d = scatter(box, Y) if levels == 1 else scatter_levels(coarse_box, levels, Y)
     vcorr = xt[:3] + d
     out = dict(xt=xt, r=r, X=X, Y=Y, d=d)
     if indicator:
@@ -335,7 +415,7 @@ def correction_step(box, ns, params, xc, vprev, shift=None, inv_scale=None, indi
                 xv = vanka_sweep(box, ns, xv, vprev, omega=omega, coupled=False)
             vcorr = xv[:3]
     b = rhs(box, ns, vcorr)
-    bc = restrict(box, b)
+    bc = restrict(box, b) if levels == 1 else restrict_levels(coarse_box, levels, b)
     out.update(vcorr=vcorr, b=b, bc=bc)
     return out
 

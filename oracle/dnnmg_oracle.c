@@ -475,6 +475,92 @@ void or_scatter(const or_box *b, const double *Y, double *d) {
     free(dir);
 }
 
+/* ---------------------- patches of the two-level prediction (Sec. 4.2) -- */
+
+/* Prediction J levels above the coarse mesh of b (J = 1 or 2): the fine
+ * lattice is that of the box bJ with n * 2^(J-1) cells per axis (its own
+ * fine mesh has n * 2^J cells); patch M = cell (I,J,K) of b covers P^3 fine
+ * cells, P = 2^J, and its (P+1)^3 local nodes iota = a + (P+1) b + (P+1)^2 c,
+ * a,b,c in 0..P, are the fine nodes (P I + a, P J + b, P K + c) of bJ.
+ * J = 1 is the single-level patch of or_dofmap. */
+static or_box level_box(const or_box *b, int J) {
+    or_box c = *b;
+    for (int a = 0; a < 3; ++a) c.n[a] = b->n[a] << (J - 1);
+    return c;
+}
+
+/* dof map [np][(P+1)^3] and valence (counted over all patches). */
+void or_dofmap_levels(const or_box *b, int J, int32_t *map, uint8_t *mult) {
+    const int P = 1 << J, S = P + 1, NL = S * S * S;
+    const or_box f = level_box(b, J);
+    const int64_t nf = or_fine_nodes(&f);
+    for (int64_t n = 0; n < nf; ++n) mult[n] = 0;
+    for (int64_t K = 0; K < b->n[2]; ++K)
+        for (int64_t Jj = 0; Jj < b->n[1]; ++Jj)
+            for (int64_t I = 0; I < b->n[0]; ++I) {
+                int64_t M = I + b->n[0] * (Jj + b->n[1] * K);
+                for (int c = 0; c < S; ++c)
+                    for (int bb = 0; bb < S; ++bb)
+                        for (int a = 0; a < S; ++a) {
+                            int64_t g = fine_node(&f, P * I + a, P * Jj + bb, P * K + c);
+                            map[M * NL + a + S * bb + S * S * c] = (int32_t)g;
+                            mult[g] += 1;
+                        }
+            }
+}
+
+/* Q of eq. (defQ) on the patches of the J-level prediction: row M =
+ * [u(nodes), v(..), w(..), r_u(..), r_v(..), r_w(..), H0, H1, H2] with the
+ * coarse cell sizes H of b, then z = (X - shift) * inv_scale.
+ * x, r on the fine lattice of level_box(b, J); X [np][6 (P+1)^3 + 3]. */
+void or_gather_levels(const or_box *b, int J, const double *x, const double *r, const double *shift,
+                      const double *inv_scale, double *X) {
+    const int P = 1 << J, S = P + 1, NL = S * S * S, NC = 6 * NL + 3;
+    const or_box f = level_box(b, J);
+    const int64_t nfn = or_fine_nodes(&f), np = or_patches(b);
+    int32_t *map = (int32_t *)malloc(sizeof(int32_t) * NL * np);
+    uint8_t *mult = (uint8_t *)malloc(nfn);
+    or_dofmap_levels(b, J, map, mult);
+    for (int64_t M = 0; M < np; ++M) {
+        double *row = X + M * NC;
+        for (int c = 0; c < 3; ++c)
+            for (int i = 0; i < NL; ++i) {
+                row[NL * c + i] = x[c * nfn + map[M * NL + i]];
+                row[3 * NL + NL * c + i] = r[c * nfn + map[M * NL + i]];
+            }
+        for (int a = 0; a < 3; ++a) row[6 * NL + a] = b->len[a] / b->n[a];
+        for (int q = 0; q < NC; ++q) {
+            double sh = shift ? shift[q] : 0.0, g = inv_scale ? inv_scale[q] : 1.0;
+            row[q] = (row[q] - sh) * g;
+        }
+    }
+    free(map);
+    free(mult);
+}
+
+/* L of eq. (defL) on the patches of the J-level prediction: Y [np][3 (P+1)^3]
+ * (component-major per patch) averaged by valence into d [3][N_f] on the
+ * fine lattice of level_box(b, J); Dirichlet velocity nodes get 0. */
+void or_scatter_levels(const or_box *b, int J, const double *Y, double *d) {
+    const int P = 1 << J, S = P + 1, NL = S * S * S;
+    const or_box f = level_box(b, J);
+    const int64_t nfn = or_fine_nodes(&f), np = or_patches(b);
+    int32_t *map = (int32_t *)malloc(sizeof(int32_t) * NL * np);
+    uint8_t *mult = (uint8_t *)malloc(nfn);
+    uint8_t *dir = (uint8_t *)malloc(nfn);
+    or_dofmap_levels(b, J, map, mult);
+    or_dirichlet_flags(&f, dir);
+    for (int64_t t = 0; t < 3 * nfn; ++t) d[t] = 0.0;
+    for (int64_t M = 0; M < np; ++M)
+        for (int c = 0; c < 3; ++c)
+            for (int i = 0; i < NL; ++i) d[c * nfn + map[M * NL + i]] += Y[M * 3 * NL + NL * c + i];
+    for (int64_t n = 0; n < nfn; ++n)
+        for (int c = 0; c < 3; ++c) d[c * nfn + n] = dir[n] ? 0.0 : d[c * nfn + n] / mult[n];
+    free(map);
+    free(mult);
+    free(dir);
+}
+
 /* ------------------------------------------------ network (Sec. 3) ------ */
 
 /* Y = W3^T tanh(W2^T tanh(W1^T x + b1) + b2) + b3 for every row x of X.
