@@ -68,7 +68,8 @@ typedef struct dnnmg_ns {
 #define DNNMG_FP8_E4M3 2 /* OCP E4M3FN, max 448, saturating */
 
 /* Patch network 165 -> H -> H -> 81 with tanh (Sec. 3; width H in
- * {64,128,256,512}).  W[l] are packed by dnnmg_mlp_pack; b[l] are FP32
+ * {64,128,256,512}; 753 -> H -> H -> 375 for the two-level prediction, see
+ * dnnmg_mlp_prepare_io).  W[l] are packed by dnnmg_mlp_pack; b[l] are FP32
  * biases (length H, H, 81).  Products accumulate in FP32 and bias and tanh are
  * applied in FP32.  Element types per layer (1, 2, 3):
  *   DNNMG_F32       FP32, FP32, FP32   (inputs X FP32)
@@ -78,9 +79,9 @@ typedef struct dnnmg_ns {
  *                   W2q * w_scale[1] and layer-2 inputs a = aq * a_scale[1];
  *                   the other scales are ignored. */
 typedef struct dnnmg_mlp {
-    int32_t n_in;  /* must be 165 */
+    int32_t n_in;  /* 165 (or 753, two-level prediction) */
     int32_t hidden;
-    int32_t n_out; /* must be 81 */
+    int32_t n_out; /* 81 (or 375) */
     int32_t dtype; /* DNNMG_F32 | DNNMG_BF16 | DNNMG_FP8_E4M3 */
     const void *W[3];
     const float *b[3];
@@ -420,6 +421,52 @@ int dnnmg_batch_rhs(const dnnmg_plan *plan, const float *v, float *b, void *stre
 int dnnmg_plan_autotune(dnnmg_plan *plan, const dnnmg_mlp *net, const float *shift, const float *inv_scale,
                         const double *xc, const float *vprev, float *xt, float *r, float *Y, float *xcorr,
                         float *b, double *bc, int reps, void *stream);
+
+/* Prediction J levels above the coarse mesh (Sec. 4.2; J = `levels`, 1 or 2):
+ * the network corrects the solution on level L + J, whose mesh has 2^J n
+ * cells per axis; a patch is one coarse cell with 2^J x 2^J x 2^J fine cells
+ * and (2^J + 1)^3 nodes, local node iota = a + (2^J+1) b + (2^J+1)^2 c, fine
+ * node (2^J I + a, 2^J J + b, 2^J K + c).  `box` is always the coarse box (n
+ * cells); the fine fields live on the level-(L + J) lattice (node counts
+ * from dnnmg_level_sizes).  The residual, Rhs, norms and fallback of level
+ * L + J are the one-level calls on the box with 2^(J-1) n cells (their local
+ * projection is onto the next-coarser level, independent of J).  levels = 1
+ * is the same as the one-level calls.  J = 2: 125 nodes, network inputs 753
+ * = 375 velocities + 375 momentum residuals + 3 cell sizes (ldx >= 753), 375
+ * outputs. */
+int dnnmg_level_sizes(const dnnmg_box *box, int levels, int64_t *n_fine, int64_t *n_coarse, int64_t *n_patches);
+/* map int32 [n_patches][(2^J+1)^3]; mult uint8 [n_fine(L+J)] (1, 2, 4 or 8). */
+int dnnmg_patch_dofmap_levels(const dnnmg_box *box, int levels, int32_t *map, uint8_t *mult, void *stream);
+/* Prolongation L -> L + J (Algorithm 1), J times the one-level prolongation:
+ * xc FP64 [ncomp][n_coarse] -> xf FP32 [ncomp][n_fine(L+J)].  The values are
+ * those of dnnmg_prolong applied level by level in FP32, bit for bit, so the
+ * result equals its own patch interpolant on level L + J - 1 exactly. */
+int dnnmg_prolong_levels(const dnnmg_box *box, int levels, int ncomp, const double *xc, float *xf, void *stream);
+/* Its transpose (restriction of the rhs, Algorithm 1), FP64 accumulation:
+ * bf FP32 [ncomp][n_fine(L+J)] -> bc FP64 [ncomp][n_coarse]. */
+int dnnmg_restrict_levels(const dnnmg_box *box, int levels, int ncomp, const float *bf, double *bc, void *stream);
+/* Operator Q of eq. (defQ) on the J-level patches: row M = [u(nodes), v, w,
+ * r_u, r_v, r_w, H0, H1, H2] standardised by `feat` (device arrays of
+ * 6 (2^J+1)^3 + 3 floats or NULL), FP32 or BF16, X [n_patches][ldx]
+ * (padding columns zero). */
+int dnnmg_patch_gather_levels(const dnnmg_box *box, int levels, const float *x, const float *r,
+                              const dnnmg_feat *feat, int dtype, void *X, int64_t ldx, void *stream);
+/* Extension L of eq. (defL) on the J-level patches: Y FP32 [n_patches][3
+ * (2^J+1)^3]; vbase / d as for dnnmg_scatter_avg, on the level-(L + J)
+ * lattice. */
+int dnnmg_scatter_avg_levels(const dnnmg_box *box, int levels, const float *Y, const float *vbase, float *d,
+                             void *stream);
+/* Packing and setup of networks of either width pair (n_in, n_out) = (165,
+ * 81) or (753, 375) (J = 1 or 2); dnnmg_mlp_packed_bytes / _pack / _prepare
+ * are these with (165, 81).  dnnmg_patch_forward takes either network (the
+ * J = 2 one as FP32, BF16 or FP8 rows, widths 256 and 512 as built);
+ * dnnmg_patch_gather_forward and the backward are built for J = 1. */
+size_t dnnmg_mlp_packed_bytes_io(int dtype, int n_in, int hidden, int n_out, int layer);
+int dnnmg_mlp_pack_io(int dtype, int n_in, int hidden, int n_out, int layer, const float *W, float w_scale,
+                      void *Wp, void *stream);
+int dnnmg_mlp_prepare_io(int dtype, int n_in, int hidden, int n_out, const float *const W[3],
+                         const float *const b[3], void *const Wp[3], void *ws, size_t ws_bytes, dnnmg_mlp *net,
+                         void *stream);
 
 /* HIP-graph capture of library calls (Algorithm 1 as one replayable time
  * step).  dnnmg_graph_capture_begin starts capturing `stream` (a non-default

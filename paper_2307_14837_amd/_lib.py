@@ -126,6 +126,15 @@ _sig("dnnmg_batch_rhs", [c_vp, c_vp, c_vp, c_vp])
 _sig("dnnmg_plan_autotune", [c_vp, _P(MLP), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
                              ctypes.c_int, c_vp])
 _sig("dnnmg_mlp_prepare", [ctypes.c_int, ctypes.c_int, c_vp * 3, c_vp * 3, c_vp * 3, c_vp, c_sz, _P(MLP), c_vp])
+_sig("dnnmg_mlp_packed_bytes_io", [ctypes.c_int] * 5, c_sz)
+_sig("dnnmg_mlp_pack_io", [ctypes.c_int] * 5 + [c_vp, c_f, c_vp, c_vp])
+_sig("dnnmg_mlp_prepare_io", [ctypes.c_int] * 4 + [c_vp * 3, c_vp * 3, c_vp * 3, c_vp, c_sz, _P(MLP), c_vp])
+_sig("dnnmg_level_sizes", [_P(Box), ctypes.c_int, _P(c_i64), _P(c_i64), _P(c_i64)])
+_sig("dnnmg_patch_dofmap_levels", [_P(Box), ctypes.c_int, c_vp, c_vp, c_vp])
+_sig("dnnmg_prolong_levels", [_P(Box), ctypes.c_int, ctypes.c_int, c_vp, c_vp, c_vp])
+_sig("dnnmg_restrict_levels", [_P(Box), ctypes.c_int, ctypes.c_int, c_vp, c_vp, c_vp])
+_sig("dnnmg_patch_gather_levels", [_P(Box), ctypes.c_int, c_vp, c_vp, _P(Feat), ctypes.c_int, c_vp, c_i64, c_vp])
+_sig("dnnmg_scatter_avg_levels", [_P(Box), ctypes.c_int, c_vp, c_vp, c_vp, c_vp])
 _sig("dnnmg_graph_capture_begin", [c_vp])
 _sig("dnnmg_graph_capture_end", [c_vp, _P(c_vp)])
 _sig("dnnmg_graph_replay", [c_vp, c_vp])
@@ -145,7 +154,13 @@ EXPORTS = [
     "dnnmg_plan_sizes", "dnnmg_plan_choice", "dnnmg_batch_step", "dnnmg_plan_autotune",
     "dnnmg_batch_step_b", "dnnmg_batch_rhs", "dnnmg_norm2_pair_f64", "dnnmg_mlp_prepare",
     "dnnmg_graph_capture_begin", "dnnmg_graph_capture_end", "dnnmg_graph_replay", "dnnmg_graph_destroy",
+    "dnnmg_mlp_packed_bytes_io", "dnnmg_mlp_pack_io", "dnnmg_mlp_prepare_io", "dnnmg_level_sizes",
+    "dnnmg_patch_dofmap_levels", "dnnmg_prolong_levels", "dnnmg_restrict_levels", "dnnmg_patch_gather_levels",
+    "dnnmg_scatter_avg_levels",
 ]
+
+# network widths per prediction depth J (levels): inputs, outputs, padded input row
+LEVEL_IO = {1: (165, 81, 192), 2: (753, 375, 768)}
 
 
 class DnnmgError(RuntimeError):
@@ -290,8 +305,8 @@ def dnnmg_patch_gather(box, x, r, X, dtype, ldx, shift=None, inv_scale=None, x_s
                                    float(x_scale), _ptr(X, None, None, "X"), ldx, _stream(stream)))
 
 
-def packed_bytes(dtype, hidden, layer) -> int:
-    return int(_lib.dnnmg_mlp_packed_bytes(dtype, hidden, layer))
+def packed_bytes(dtype, hidden, layer, n_in=N_IN, n_out=N_OUT) -> int:
+    return int(_lib.dnnmg_mlp_packed_bytes_io(dtype, n_in, hidden, n_out, layer))
 
 
 def dnnmg_mlp_pack(dtype, hidden, layer, W, Wp, w_scale=1.0, stream=None):
@@ -312,18 +327,83 @@ def make_mlp(dtype, hidden, Wp, bias, w_scale=(1.0, 1.0, 1.0), a_scale=(1.0, 1.0
     return net
 
 
+def level_sizes(box, levels):
+    """(n_fine on level L + J, n_coarse, n_patches) of the J-level prediction."""
+    b = Box.of(box)
+    nf, nc, np_ = c_i64(), c_i64(), c_i64()
+    _check(_lib.dnnmg_level_sizes(ctypes.byref(b), int(levels), ctypes.byref(nf), ctypes.byref(nc),
+                                  ctypes.byref(np_)))
+    return nf.value, nc.value, np_.value
+
+
+def level_box(box, levels) -> Box:
+    """The box whose own fine mesh is level L + J (n doubled J - 1 times)."""
+    b = Box.of(box)
+    out = Box()
+    for a in range(3):
+        out.n[a] = int(b.n[a]) << (int(levels) - 1)
+        out.len[a] = b.len[a]
+    out.periodic_mask, out.dirichlet_mask = b.periodic_mask, b.dirichlet_mask
+    return out
+
+
+def dnnmg_patch_dofmap_levels(box, levels, dofmap=None, mult=None, stream=None):
+    b = Box.of(box)
+    nf, _, npch = level_sizes(b, levels)
+    nodes = ((1 << int(levels)) + 1) ** 3
+    _check(_lib.dnnmg_patch_dofmap_levels(ctypes.byref(b), int(levels), _ptr(dofmap, torch.int32, npch * nodes, "map"),
+                                          _ptr(mult, torch.uint8, nf, "mult"), _stream(stream)))
+
+
+def dnnmg_prolong_levels(box, levels, xc, xf, ncomp=4, stream=None):
+    b = Box.of(box)
+    nf, nc, _ = level_sizes(b, levels)
+    _check(_lib.dnnmg_prolong_levels(ctypes.byref(b), int(levels), ncomp, _ptr(xc, torch.float64, ncomp * nc, "xc"),
+                                     _ptr(xf, torch.float32, ncomp * nf, "xf"), _stream(stream)))
+
+
+def dnnmg_restrict_levels(box, levels, bf, bc, ncomp=4, stream=None):
+    b = Box.of(box)
+    nf, nc, _ = level_sizes(b, levels)
+    _check(_lib.dnnmg_restrict_levels(ctypes.byref(b), int(levels), ncomp, _ptr(bf, torch.float32, ncomp * nf, "bf"),
+                                      _ptr(bc, torch.float64, ncomp * nc, "bc"), _stream(stream)))
+
+
+def dnnmg_patch_gather_levels(box, levels, x, r, X, dtype, ldx, shift=None, inv_scale=None, stream=None):
+    b = Box.of(box)
+    nf, _, npch = level_sizes(b, levels)
+    nin = LEVEL_IO[int(levels)][0]
+    feat = Feat(_ptr(shift, torch.float32, nin, "shift"), _ptr(inv_scale, torch.float32, nin, "inv_scale"))
+    if X.numel() * X.element_size() < npch * ldx * {F32: 4, BF16: 2}[dtype]:
+        raise ValueError("X too small")
+    _check(_lib.dnnmg_patch_gather_levels(ctypes.byref(b), int(levels), _ptr(x, torch.float32, 3 * nf, "x"),
+                                          _ptr(r, torch.float32, 3 * nf, "r"), ctypes.byref(feat), int(dtype),
+                                          _ptr(X, None, None, "X"), int(ldx), _stream(stream)))
+
+
+def dnnmg_scatter_avg_levels(box, levels, Y, d, vbase=None, stream=None):
+    b = Box.of(box)
+    nf, _, npch = level_sizes(b, levels)
+    nout = 3 * ((1 << int(levels)) + 1) ** 3
+    _check(_lib.dnnmg_scatter_avg_levels(ctypes.byref(b), int(levels), _ptr(Y, torch.float32, npch * nout, "Y"),
+                                         _ptr(vbase, torch.float32, 4 * nf, "vbase"),
+                                         _ptr(d, torch.float32, (4 if vbase is not None else 3) * nf, "d"),
+                                         _stream(stream)))
+
+
 class PreparedMLP:
     """A network packed for the kernels by dnnmg_mlp_prepare: owns the packed
     weights and biases (device) and the filled dnnmg_mlp description."""
 
-    def __init__(self, dtype, hidden, W32, bias, device):
-        self.dtype, self.hidden = int(dtype), int(hidden)
+    def __init__(self, dtype, hidden, W32, bias, device, n_in=N_IN, n_out=N_OUT):
+        self.dtype, self.hidden, self.n_in, self.n_out = int(dtype), int(hidden), int(n_in), int(n_out)
         self.W32 = [w.contiguous() for w in W32]
         self.bias = [b.contiguous() for b in bias]
-        self.Wp = [torch.zeros(packed_bytes(dtype, hidden, l), dtype=torch.uint8, device=device) for l in range(3)]
+        self.Wp = [torch.zeros(packed_bytes(dtype, hidden, l, n_in, n_out), dtype=torch.uint8, device=device)
+                   for l in range(3)]
         self._ws = torch.zeros(256, dtype=torch.uint8, device=device)
         self.net = MLP()
-        for l, (w, n) in enumerate(((N_IN, hidden), (hidden, hidden), (hidden, N_OUT))):
+        for l, (w, n) in enumerate(((n_in, hidden), (hidden, hidden), (hidden, n_out))):
             _ptr(self.W32[l], torch.float32, w * n, f"W{l + 1}")
             _ptr(self.bias[l], torch.float32, n, f"b{l + 1}")
         self.prepare()
@@ -333,13 +413,13 @@ class PreparedMLP:
         W = (c_vp * 3)(*[w.data_ptr() for w in self.W32])
         B = (c_vp * 3)(*[b.data_ptr() for b in self.bias])
         P = (c_vp * 3)(*[w.data_ptr() for w in self.Wp])
-        _check(_lib.dnnmg_mlp_prepare(self.dtype, self.hidden, W, B, P, _ptr(self._ws), self._ws.numel(),
-                                      ctypes.byref(self.net), _stream(stream)))
+        _check(_lib.dnnmg_mlp_prepare_io(self.dtype, self.n_in, self.hidden, self.n_out, W, B, P, _ptr(self._ws),
+                                         self._ws.numel(), ctypes.byref(self.net), _stream(stream)))
         return self.net
 
 
-def mlp_prepare(dtype, hidden, W32, bias, device="cuda:0") -> PreparedMLP:
-    return PreparedMLP(dtype, hidden, W32, bias, torch.device(device))
+def mlp_prepare(dtype, hidden, W32, bias, device="cuda:0", n_in=N_IN, n_out=N_OUT) -> PreparedMLP:
+    return PreparedMLP(dtype, hidden, W32, bias, torch.device(device), n_in, n_out)
 
 
 class Graph:
@@ -394,13 +474,13 @@ def saved_bytes(net: MLP, n: int) -> int:
 
 def dnnmg_patch_forward(net: MLP, n, X, ldx, Y, saved=None, stream=None):
     _check(_lib.dnnmg_patch_forward(ctypes.byref(net), int(n), _ptr(X, None, None, "X"), int(ldx),
-                                    _ptr(Y, torch.float32, n * N_OUT, "Y"),
+                                    _ptr(Y, torch.float32, n * net.n_out, "Y"),
                                     _ptr(saved, None, None, "saved"), _stream(stream)))
 
 
 def dnnmg_patch_forward_tiles(net: MLP, n, X, ldx, Y, tile_patches, grid=0, saved=None, stream=None):
     _check(_lib.dnnmg_patch_forward_tiles(ctypes.byref(net), int(n), _ptr(X, None, None, "X"), int(ldx),
-                                          _ptr(Y, torch.float32, n * N_OUT, "Y"),
+                                          _ptr(Y, torch.float32, n * net.n_out, "Y"),
                                           _ptr(saved, None, None, "saved"), int(tile_patches), int(grid),
                                           _stream(stream)))
 

@@ -141,7 +141,7 @@ __device__ __forceinline__ void put_act(unsigned char *out, int t, int ot, int l
 // One dense layer for the tile: acc = W^T B over the wave's output tiles,
 // then bias and (unless LAST) tanh into the next layer's fragments, or (LAST)
 // the output rows.
-template <int K, int KN, int NTILES, int NCH, int PT, bool LAST, int H, int NW>
+template <int K, int KN, int NTILES, int NCH, int PT, bool LAST, int H, int NW, int NO = N_OUT>
 __device__ __forceinline__ void layer(const typename Frag<K>::T *__restrict__ Wl, const float *__restrict__ bias,
                                       const unsigned char *in, unsigned char *out, float scale, float qinv,
                                       int wave, int lane, int64_t base, int64_t n, float *__restrict__ Y,
@@ -192,14 +192,14 @@ __device__ __forceinline__ void layer(const typename Frag<K>::T *__restrict__ Wl
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int o = 16 * ot + 4 * g + e;
-                bl[e] = bias[o < N_OUT ? o : N_OUT - 1];
+                bl[e] = bias[o < NO ? o : NO - 1];
             }
 #pragma unroll
             for (int t = 0; t < PT; ++t) {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     int o = 16 * ot + 4 * g + e;
-                    if (o < N_OUT) ys[(16 * t + p) * N_OUT + o] = acc[i][t][e] * scale + bl[e];
+                    if (o < NO) ys[(16 * t + p) * NO + o] = acc[i][t][e] * scale + bl[e];
                 }
             }
         } else {
@@ -238,16 +238,17 @@ __device__ __forceinline__ void layer(const typename Frag<K>::T *__restrict__ Wl
 
 // LDS sizes of the forward kernels: buffer 0 holds the network input, then
 // the layer-3 input; buffer 1 the layer-2 input.
-template <int DT, int H, int PT>
+template <int DT, int H, int PT, int J = 1>
 struct FwdShape {
+    using IO = NetIo<J>;
     static constexpr int K1 = layer_kind(DT, 0), K2 = layer_kind(DT, 1), K3 = layer_kind(DT, 2);
-    static constexpr int NCH0 = IN_PAD / (4 * kind_E(K1));
+    static constexpr int NCH0 = IO::INP / (4 * kind_E(K1));
     static constexpr int NCH1 = H / (4 * kind_E(K2));
     static constexpr int NCH2 = H / (4 * kind_E(K3));
     static constexpr int IN0 = PT * NCH0 * 64 * frag_bytes(K1);
     static constexpr int IN1 = PT * NCH1 * 64 * frag_bytes(K2);
     static constexpr int IN2 = PT * NCH2 * 64 * frag_bytes(K3);
-    static constexpr int YB = 16 * PT * N_OUT * 4; // output rows of the tile
+    static constexpr int YB = 16 * PT * IO::NOUT * 4; // output rows of the tile
     static constexpr int BUF0 = IN0 > IN2 ? IN0 : IN2;
     static constexpr int BUF1 = IN1 > YB ? IN1 : YB;
     // waves per workgroup: 64-patch tiles take 8 waves (two output tiles of
@@ -259,10 +260,10 @@ struct FwdShape {
 // Network input rows X [n][ldx] (FP32 or BF16) of patches base .. base + 16 PT
 // into the layer-1 fragments: one thread per 16-byte piece of a row, so the
 // rows are read contiguously.
-template <int K1, int NCH0, int PT, int NTHR>
+template <int K1, int NCH0, int PT, int NTHR, int INP = IN_PAD>
 __device__ __forceinline__ void stage_rows(const void *__restrict__ Xv, int64_t ldx, int64_t base, int64_t n,
                                            unsigned char *buf, int tid) {
-    constexpr int PIECES = IN_PAD * kind_bytes(K1) / 16; // 16-byte pieces per row
+    constexpr int PIECES = INP * kind_bytes(K1) / 16; // 16-byte pieces per row
     for (int it = tid; it < 16 * PT * PIECES; it += NTHR) {
         const int pl = it / PIECES, pc = it - pl * PIECES;
         const int64_t row = base + pl;
@@ -357,15 +358,17 @@ __device__ __forceinline__ void stage_gather(const Mesh &m, const float *__restr
 // when D is null), and tile -> box by the prefix sums blk_ptile.  Workgroups
 // walk the tiles with stride gridDim.x; every thread of a workgroup takes the
 // same tiles, so the barriers inside the loop are uniform.
-template <int DT, int H, int PT, bool GATHER>
-__global__ void __launch_bounds__((FwdShape<DT, H, PT>::NTHR))
+template <int DT, int H, int PT, bool GATHER, int J = 1>
+__global__ void __launch_bounds__((FwdShape<DT, H, PT, J>::NTHR))
     k_mlp_fwd(int64_t ntiles, int64_t n_rows, const void *__restrict__ Xv, int64_t ldx,
               const BoxDesc *__restrict__ D, int nbox, BoxDesc one, const float *__restrict__ xt_all,
               const float *__restrict__ r_all, const float *__restrict__ shift, const float *__restrict__ inv,
               const void *__restrict__ W0, const void *__restrict__ W1, const void *__restrict__ W2,
               const float *__restrict__ b0, const float *__restrict__ b1, const float *__restrict__ b2,
               float *__restrict__ Y_all, void *__restrict__ saved, float s1, float q1inv) {
-    using S = FwdShape<DT, H, PT>;
+    static_assert(!GATHER || J == 1, "the fused gather is built for one-level patches");
+    using S = FwdShape<DT, H, PT, J>;
+    constexpr int NO = S::IO::NOUT;
     using F1 = typename Frag<S::K1>::T;
     using F2 = typename Frag<S::K2>::T;
     using F3 = typename Frag<S::K3>::T;
@@ -381,13 +384,13 @@ __global__ void __launch_bounds__((FwdShape<DT, H, PT>::NTHR))
             const BoxDesc &d = D ? D[b] : one;
             n = d.m.n_patches;
             base = (tile - d.blk_ptile) * 16 * PT;
-            Y = Y_all + 81 * d.off_patch;
+            Y = Y_all + NO * d.off_patch;
             stage_gather<S::K1, S::NCH0, PT, S::NTHR>(d.m, xt_all + 4 * d.off_fine, r_all + 4 * d.off_fine, shift, inv,
                                              base, n, buf0, tid);
         } else {
             n = n_rows;
             base = tile * 16 * PT;
-            stage_rows<S::K1, S::NCH0, PT, S::NTHR>(Xv, ldx, base, n, buf0, tid);
+            stage_rows<S::K1, S::NCH0, PT, S::NTHR, S::IO::INP>(Xv, ldx, base, n, buf0, tid);
         }
         __syncthreads();
         layer<S::K1, S::K2, H / 16, S::NCH0, PT, false, H, S::NW>((const F1 *)W0, b0, buf0, buf1, 1.0f, q1inv, wave,
@@ -396,14 +399,15 @@ __global__ void __launch_bounds__((FwdShape<DT, H, PT>::NTHR))
         layer<S::K2, S::K3, H / 16, S::NCH1, PT, false, H, S::NW>((const F2 *)W1, b1, buf1, buf0, s1, 1.0f, wave, lane,
                                                           base, n, Y, saved, n * H, sbytes);
         __syncthreads();
-        layer<S::K3, S::K3, OUT_PAD / 16, S::NCH2, PT, true, H, S::NW>((const F3 *)W2, b2, buf0, buf1, 1.0f, 1.0f,
-                                                                        wave, lane, base, n, Y, nullptr, 0, sbytes);
+        layer<S::K3, S::K3, S::IO::OUTP / 16, S::NCH2, PT, true, H, S::NW, NO>((const F3 *)W2, b2, buf0, buf1, 1.0f,
+                                                                                1.0f, wave, lane, base, n, Y, nullptr,
+                                                                                0, sbytes);
         __syncthreads();
         {
             // the tile's rows are contiguous in Y
-            const int cnt = (int)((n - base < 16 * PT ? n - base : 16 * PT) * N_OUT);
+            const int cnt = (int)((n - base < 16 * PT ? n - base : 16 * PT) * NO);
             const float *ys = (const float *)buf1;
-            float *yd = Y + base * N_OUT;
+            float *yd = Y + base * NO;
             int q0 = 0;
             if ((((uintptr_t)yd) & 15) == 0) {
                 for (int q = tid; q < cnt / 4; q += S::NTHR) ((float4 *)yd)[q] = ((const float4 *)ys)[q];
@@ -438,10 +442,21 @@ static void fp8_scales(const dnnmg_mlp *net, float &s1, float &q1) {
     X(DNNMG_FP8_E4M3, 256, 1) X(DNNMG_FP8_E4M3, 256, 2) X(DNNMG_FP8_E4M3, 256, 4)                        \
     X(DNNMG_FP8_E4M3, 512, 1) X(DNNMG_FP8_E4M3, 512, 2) X(DNNMG_FP8_E4M3, 512, 4)
 
+// Variants of the two-level prediction (753 inputs, 375 outputs): tiles of
+// 16 or 32 patches (the 768-wide input rows of 64 patches would not fit LDS).
+#define DNNMG_FWD_VARIANTS2(X)                                                                          \
+    X(DNNMG_F32, 256, 1) X(DNNMG_BF16, 256, 1) X(DNNMG_BF16, 256, 2) X(DNNMG_BF16, 512, 1)              \
+    X(DNNMG_BF16, 512, 2) X(DNNMG_FP8_E4M3, 512, 1) X(DNNMG_FP8_E4M3, 512, 2)
+
 bool fwd_has_pt(const dnnmg_mlp *net, int pt) {
+    const int J = net_levels(net->n_in, net->n_out);
 #define HAS(DT, HH, P)                                                                                  \
     if (net->dtype == DT && net->hidden == HH && pt == P) return true;
-    DNNMG_FWD_VARIANTS(HAS)
+    if (J == 1) {
+        DNNMG_FWD_VARIANTS(HAS)
+    } else if (J == 2) {
+        DNNMG_FWD_VARIANTS2(HAS)
+    }
 #undef HAS
     return false;
 }
@@ -475,8 +490,22 @@ int fwd_launch(const dnnmg_mlp *net, int pt, bool gather, int64_t ntiles, int gr
                                                              net->b[1], net->b[2], Y, saved, s1, q1);    \
         return hip_check(hipGetLastError(), "patch network forward launch");                            \
     }
-    DNNMG_FWD_VARIANTS(LAUNCH)
+    if (net_levels(net->n_in, net->n_out) == 1) {
+        DNNMG_FWD_VARIANTS(LAUNCH)
+    }
 #undef LAUNCH
+#define LAUNCH2(DT, HH, P)                                                                              \
+    if (net->dtype == DT && net->hidden == HH && pt == P) {                                             \
+        if (gather) return fail(DNNMG_ERR_UNSUPPORTED, "patch network forward: no fused gather for J = 2"); \
+        k_mlp_fwd<DT, HH, P, false, 2><<<grid, FwdShape<DT, HH, P, 2>::NTHR, 0, s>>>(                    \
+            ntiles, n_rows, X, ldx, nullptr, 0, one, nullptr, nullptr, nullptr, nullptr, net->W[0], net->W[1], \
+            net->W[2], net->b[0], net->b[1], net->b[2], Y, saved, s1, q1);                               \
+        return hip_check(hipGetLastError(), "patch network forward launch");                            \
+    }
+    if (net_levels(net->n_in, net->n_out) == 2) {
+        DNNMG_FWD_VARIANTS2(LAUNCH2)
+    }
+#undef LAUNCH2
     return fail(DNNMG_ERR_UNSUPPORTED, "patch network forward: dtype %d width %d tile %d", net->dtype,
                 net->hidden, pt);
 }
@@ -496,9 +525,9 @@ int device_cus() {
 
 int check_net(const dnnmg_mlp *net) {
     if (!net) return fail(DNNMG_ERR_ARG, "net is NULL");
-    if (net->n_in != N_IN || net->n_out != N_OUT)
-        return fail(DNNMG_ERR_SHAPE, "network must be %d -> H -> H -> %d (got %d, %d)", N_IN, N_OUT,
-                    net->n_in, net->n_out);
+    if (!net_levels(net->n_in, net->n_out))
+        return fail(DNNMG_ERR_SHAPE, "network must be %d -> H -> H -> %d or %d -> H -> H -> %d (got %d, %d)",
+                    NetIo<1>::NIN, NetIo<1>::NOUT, NetIo<2>::NIN, NetIo<2>::NOUT, net->n_in, net->n_out);
     if (net->hidden != 64 && net->hidden != 128 && net->hidden != 256 && net->hidden != 512)
         return fail(DNNMG_ERR_UNSUPPORTED, "hidden width %d not in {64,128,256,512}", net->hidden);
     if (net->dtype != DNNMG_F32 && net->dtype != DNNMG_BF16 && net->dtype != DNNMG_FP8_E4M3)
@@ -517,16 +546,23 @@ int check_net(const dnnmg_mlp *net) {
 
 using namespace dnnmg;
 
-extern "C" size_t dnnmg_mlp_packed_bytes(int dtype, int hidden, int layer) {
-    if (layer < 0 || layer > 2) return 0;
+extern "C" size_t dnnmg_mlp_packed_bytes_io(int dtype, int n_in, int hidden, int n_out, int layer) {
+    const int J = net_levels(n_in, n_out);
+    if (!J || layer < 0 || layer > 2) return 0;
     if (dtype != DNNMG_F32 && dtype != DNNMG_BF16 && dtype != DNNMG_FP8_E4M3) return 0;
-    int kp = layer == 0 ? IN_PAD : hidden;
-    int np = layer == 2 ? OUT_PAD : hidden;
+    int kp = layer == 0 ? io_in_pad(J) : hidden;
+    int np = layer == 2 ? io_out_pad(J) : hidden;
     return (size_t)kp * np * kind_bytes(layer_kind(dtype, layer));
 }
 
-extern "C" int dnnmg_mlp_pack(int dtype, int hidden, int layer, const float *W, float w_scale,
-                              void *Wp, void *stream) {
+extern "C" size_t dnnmg_mlp_packed_bytes(int dtype, int hidden, int layer) {
+    return dnnmg_mlp_packed_bytes_io(dtype, N_IN, hidden, N_OUT, layer);
+}
+
+extern "C" int dnnmg_mlp_pack_io(int dtype, int n_in, int hidden, int n_out, int layer, const float *W,
+                                 float w_scale, void *Wp, void *stream) {
+    const int J = net_levels(n_in, n_out);
+    if (!J) return fail(DNNMG_ERR_SHAPE, "dnnmg_mlp_pack: widths %d -> %d not supported", n_in, n_out);
     if (hidden != 64 && hidden != 128 && hidden != 256 && hidden != 512)
         return fail(DNNMG_ERR_UNSUPPORTED, "dnnmg_mlp_pack: hidden %d", hidden);
     if (layer < 0 || layer > 2) return fail(DNNMG_ERR_ARG, "dnnmg_mlp_pack: layer %d", layer);
@@ -537,10 +573,10 @@ extern "C" int dnnmg_mlp_pack(int dtype, int hidden, int layer, const float *W, 
     if (kind == KFP8 && !(w_scale > 0.f)) return fail(DNNMG_ERR_ARG, "dnnmg_mlp_pack: w_scale must be > 0");
     if (kind == KFP8 && hidden < 128)
         return fail(DNNMG_ERR_UNSUPPORTED, "dnnmg_mlp_pack: FP8 needs hidden >= 128");
-    int fan_in = layer == 0 ? N_IN : hidden;
-    int fan_out = layer == 2 ? N_OUT : hidden;
-    int kp = layer == 0 ? IN_PAD : hidden;
-    int np = layer == 2 ? OUT_PAD : hidden;
+    int fan_in = layer == 0 ? n_in : hidden;
+    int fan_out = layer == 2 ? n_out : hidden;
+    int kp = layer == 0 ? io_in_pad(J) : hidden;
+    int np = layer == 2 ? io_out_pad(J) : hidden;
     int E = kind_E(kind);
     int ntiles = np / 16, nchunks = kp / (4 * E);
     int64_t total = (int64_t)ntiles * nchunks * 64 * E;
@@ -555,6 +591,11 @@ extern "C" int dnnmg_mlp_pack(int dtype, int hidden, int layer, const float *W, 
         k_pack<uint8_t><<<grid, 256, 0, s>>>(kind, layer, fan_in, fan_out, ntiles, nchunks, W,
                                              1.f / w_scale, (uint8_t *)Wp);
     return hip_check(hipGetLastError(), "dnnmg_mlp_pack launch");
+}
+
+extern "C" int dnnmg_mlp_pack(int dtype, int hidden, int layer, const float *W, float w_scale,
+                              void *Wp, void *stream) {
+    return dnnmg_mlp_pack_io(dtype, N_IN, hidden, N_OUT, layer, W, w_scale, Wp, stream);
 }
 
 // max |w| over n weights as the bit pattern of a non-negative float (the
@@ -574,9 +615,12 @@ __global__ void __launch_bounds__(256) k_amax(int64_t n, const float *__restrict
     if ((threadIdx.x & 63) == 0) atomicMax(out, m);
 }
 
-extern "C" int dnnmg_mlp_prepare(int dtype, int hidden, const float *const W[3], const float *const b[3],
-                                 void *const Wp[3], void *ws, size_t ws_bytes, dnnmg_mlp *net, void *stream) {
+extern "C" int dnnmg_mlp_prepare_io(int dtype, int n_in, int hidden, int n_out, const float *const W[3],
+                                    const float *const b[3], void *const Wp[3], void *ws, size_t ws_bytes,
+                                    dnnmg_mlp *net, void *stream) {
     if (!W || !b || !Wp || !net) return fail(DNNMG_ERR_ARG, "dnnmg_mlp_prepare: NULL pointer");
+    if (!net_levels(n_in, n_out))
+        return fail(DNNMG_ERR_SHAPE, "dnnmg_mlp_prepare: widths %d -> %d not supported", n_in, n_out);
     if (hidden != 64 && hidden != 128 && hidden != 256 && hidden != 512)
         return fail(DNNMG_ERR_UNSUPPORTED, "dnnmg_mlp_prepare: hidden %d", hidden);
     if (dtype != DNNMG_F32 && dtype != DNNMG_BF16 && dtype != DNNMG_FP8_E4M3)
@@ -612,12 +656,12 @@ extern "C" int dnnmg_mlp_prepare(int dtype, int hidden, const float *const W[3],
         a_scale[1] = 1.f / 448.f;
     }
     for (int l = 0; l < 3; ++l) {
-        int rc = dnnmg_mlp_pack(dtype, hidden, l, W[l], w_scale[l], Wp[l], stream);
+        int rc = dnnmg_mlp_pack_io(dtype, n_in, hidden, n_out, l, W[l], w_scale[l], Wp[l], stream);
         if (rc) return rc;
     }
-    net->n_in = N_IN;
+    net->n_in = n_in;
     net->hidden = hidden;
-    net->n_out = N_OUT;
+    net->n_out = n_out;
     net->dtype = dtype;
     for (int l = 0; l < 3; ++l) {
         net->W[l] = Wp[l];
@@ -626,6 +670,11 @@ extern "C" int dnnmg_mlp_prepare(int dtype, int hidden, const float *const W[3],
         net->a_scale[l] = a_scale[l];
     }
     return DNNMG_OK;
+}
+
+extern "C" int dnnmg_mlp_prepare(int dtype, int hidden, const float *const W[3], const float *const b[3],
+                                 void *const Wp[3], void *ws, size_t ws_bytes, dnnmg_mlp *net, void *stream) {
+    return dnnmg_mlp_prepare_io(dtype, N_IN, hidden, N_OUT, W, b, Wp, ws, ws_bytes, net, stream);
 }
 
 extern "C" size_t dnnmg_patch_saved_bytes(const dnnmg_mlp *net, int64_t n) {
@@ -651,9 +700,10 @@ extern "C" int dnnmg_patch_forward_tiles(const dnnmg_mlp *net, int64_t n, const 
     if (!X || !Y) return fail(DNNMG_ERR_ARG, "dnnmg_patch_forward: NULL pointer");
     if (!aligned16(X)) return fail(DNNMG_ERR_ARG, "dnnmg_patch_forward: X not 16-byte aligned");
     int align = net->dtype == DNNMG_F32 ? 4 : 8;
-    if (ldx < IN_PAD || ldx % align)
+    const int inp = io_in_pad(net_levels(net->n_in, net->n_out));
+    if (ldx < inp || ldx % align)
         return fail(DNNMG_ERR_SHAPE, "dnnmg_patch_forward: ldx %lld must be >= %d and a multiple of %d",
-                    (long long)ldx, IN_PAD, align);
+                    (long long)ldx, inp, align);
     if (saved && net->dtype == DNNMG_FP8_E4M3)
         return fail(DNNMG_ERR_UNSUPPORTED, "dnnmg_patch_forward: FP8 networks do not save activations");
     if (saved && !aligned16(saved)) return fail(DNNMG_ERR_ARG, "dnnmg_patch_forward: saved not aligned");
@@ -675,6 +725,8 @@ extern "C" int dnnmg_patch_gather_forward(const dnnmg_box *box, const dnnmg_mlp 
                                           const float *r, const dnnmg_feat *feat, float *Y, void *stream) {
     int rc = check_net(net);
     if (rc) return rc;
+    if (net->n_in != N_IN)
+        return fail(DNNMG_ERR_UNSUPPORTED, "dnnmg_patch_gather_forward: one-level patches only (%d inputs)", N_IN);
     BoxDesc one{};
     if ((rc = make_mesh(box, &one.m))) return rc;
     if (!xt || !r || !Y) return fail(DNNMG_ERR_ARG, "dnnmg_patch_gather_forward: NULL pointer");

@@ -32,16 +32,23 @@ class CorrectionStep:
     """
 
     def __init__(self, box, ns, params, dtype="bf16", device="cuda:0", shift=None, inv_scale=None,
-                 indicator=False, theta=1.0, fallback_sweeps=4, fused=True, carry_rhs=None):
+                 indicator=False, theta=1.0, fallback_sweeps=4, fused=True, carry_rhs=None, levels=1):
         self.box = L.Box.of(box)
         self.ns = L.NS.of(ns)
         self.dev = torch.device(device)
         self.dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
-        self.nf, self.nc, self.np = L.box_sizes(self.box)
+        # levels = J: the prediction J levels above the coarse mesh (Sec. 4.2);
+        # fbox is the box whose own fine mesh is level L + J (the residual,
+        # Rhs and fallback run on it)
+        self.levels = int(levels)
+        self.fbox = L.level_box(self.box, self.levels)
+        self.nf, self.nc, self.np = L.level_sizes(self.box, self.levels)
+        self.n_in, self.n_out, self.ldx = L.LEVEL_IO[self.levels]
         self.hidden = int(np.shape(params[0])[1])
         self.indicator = indicator
-        # fused: the gather runs inside the network kernel (no X round trip)
-        self.fused = bool(fused)
+        # fused: the gather runs inside the network kernel (no X round trip;
+        # built for one-level patches)
+        self.fused = bool(fused) and self.levels == 1
         self.carry_rhs = True if carry_rhs is None else bool(carry_rhs)
         f32 = dict(dtype=torch.float32, device=self.dev)
         f64 = dict(dtype=torch.float64, device=self.dev)
@@ -49,11 +56,11 @@ class CorrectionStep:
         self.xt = torch.zeros(4 * self.nf, **f32)       # prolongated (u, v, w, p)
         self.vprev = torch.zeros(3 * self.nf, **f32)
         self.r = torch.zeros(4 * self.nf, **f32)
-        self.ws_res = torch.zeros(L.residual_workspace_bytes(self.box), dtype=torch.uint8, device=self.dev)
+        self.ws_res = torch.zeros(L.residual_workspace_bytes(self.fbox), dtype=torch.uint8, device=self.dev)
         # FP8 networks take BF16 inputs (their first layer is BF16)
         self.xdtype = L.F32 if self.dtype == L.F32 else L.BF16
-        self.X = torch.zeros(self.np * LDX, dtype=_TORCH[self.xdtype], device=self.dev)
-        self.Y = torch.zeros(self.np * L.N_OUT, **f32)
+        self.X = torch.zeros(self.np * self.ldx, dtype=_TORCH[self.xdtype], device=self.dev)
+        self.Y = torch.zeros(self.np * self.n_out, **f32)
         self.xcorr = torch.zeros(4 * self.nf, **f32)    # (v~ + d, p~)
         self.b = torch.zeros(4 * self.nf, **f32)
         self.bc = torch.zeros(4 * self.nc, **f64)
@@ -62,7 +69,7 @@ class CorrectionStep:
             self.r2 = torch.zeros(4 * self.nf, **f32)
             self.norms = torch.zeros(2, **f64)
             self.ws_norm = torch.zeros(2 * L.norm2_workspace_bytes(), dtype=torch.uint8, device=self.dev)
-            self.ws_fb = torch.zeros(L.fallback_workspace_bytes(self.box), dtype=torch.uint8, device=self.dev)
+            self.ws_fb = torch.zeros(L.fallback_workspace_bytes(self.fbox), dtype=torch.uint8, device=self.dev)
             self.fell_back = torch.zeros(1, dtype=torch.int32, device=self.dev)
         self.shift = None if shift is None else torch.as_tensor(np.asarray(shift, np.float32)).to(self.dev)
         self.inv_scale = None if inv_scale is None else torch.as_tensor(np.asarray(inv_scale, np.float32)).to(self.dev)
@@ -76,7 +83,7 @@ class CorrectionStep:
         bias = [torch.as_tensor(np.asarray(params[2 * l + 1], np.float32)).contiguous().to(self.dev) for l in range(3)]
         # packing and the per-tensor scales of the precision scheme are the
         # library's (dnnmg_mlp_prepare)
-        self.prepared = L.mlp_prepare(self.dtype, H, W32, bias, device=self.dev)
+        self.prepared = L.mlp_prepare(self.dtype, H, W32, bias, device=self.dev, n_in=self.n_in, n_out=self.n_out)
         self.W32, self.bias, self.Wp = self.prepared.W32, self.prepared.bias, self.prepared.Wp
         self.net = self.prepared.net
         self.w_scale = [float(self.net.w_scale[l]) for l in range(3)]
@@ -88,9 +95,11 @@ class CorrectionStep:
         if self.carry_rhs:
             # the right-hand side of the previous velocity, as the previous
             # step would have left it
-            L.dnnmg_rhs(self.box, self.ns, self.vprev, self.b)
+            L.dnnmg_rhs(self.fbox, self.ns, self.vprev, self.b)
 
     def step(self, stream=None):
+        if self.levels != 1:
+            return self._step_levels(stream)
         box, ns = self.box, self.ns
         # x~ = P xc and r = F - A(x~) in one pass (no LPS terms on a prolongation)
         if self.carry_rhs:
@@ -125,6 +134,37 @@ class CorrectionStep:
         L.dnnmg_rhs(box, ns, self.xcorr, self.b, stream=stream)
         L.dnnmg_restrict(box, self.b, self.bc, stream=stream)
 
+    def _step_levels(self, stream=None):
+        """The step with the prediction J levels above the coarse mesh: x~ =
+        P^J x^L, the residual of level L + J (on fbox, against the carried
+        right-hand side or from v_prev), Q and the network on the J-level
+        patches, L back to level L + J, [indicator], Rhs on fbox, b^L =
+        (P^J)^T b."""
+        box, fb, ns, J = self.box, self.fbox, self.ns, self.levels
+        L.dnnmg_prolong_levels(box, J, self.xc, self.xt, stream=stream)
+        if self.carry_rhs:
+            L.dnnmg_residual_b(fb, ns, self.xt, self.b, self.r, self.ws_res, stream=stream)
+        else:
+            L.dnnmg_residual(fb, ns, self.xt, self.vprev, self.r, self.ws_res, stream=stream)
+        L.dnnmg_patch_gather_levels(box, J, self.xt, self.r, self.X, self.xdtype, self.ldx, self.shift,
+                                    self.inv_scale, stream=stream)
+        L.dnnmg_patch_forward(self.net, self.np, self.X, self.ldx, self.Y, stream=stream)
+        L.dnnmg_scatter_avg_levels(box, J, self.Y, self.xcorr, vbase=self.xt, stream=stream)
+        if self.indicator:
+            if self.carry_rhs:
+                L.dnnmg_residual_b(fb, ns, self.xcorr, self.b, self.r2, self.ws_res, stream=stream)
+            else:
+                L.dnnmg_residual(fb, ns, self.xcorr, self.vprev, self.r2, self.ws_res, stream=stream)
+            L.dnnmg_norm2_pair_f64(self.r, self.r2, self.norms, self.ws_norm, stream=stream)
+            if self.carry_rhs:
+                L.dnnmg_fallback_b(fb, ns, self.xt, self.b, self.norms, self.xcorr, self.ws_fb, theta=self.theta,
+                                   sweeps=self.fallback_sweeps, flag_out=self.fell_back, stream=stream)
+            else:
+                L.dnnmg_fallback(fb, ns, self.xt, self.vprev, self.norms, self.xcorr, self.ws_fb, theta=self.theta,
+                                 sweeps=self.fallback_sweeps, flag_out=self.fell_back, stream=stream)
+        L.dnnmg_rhs(fb, ns, self.xcorr, self.b, stream=stream)
+        L.dnnmg_restrict_levels(box, J, self.b, self.bc, stream=stream)
+
     def capture(self):
         """Record step() into a HIP graph through the library's capture calls
         (one eager warm-up step first)."""
@@ -143,7 +183,7 @@ class CorrectionStep:
         out = {
             "xt": xt,
             "r": self.r.cpu().numpy().reshape(4, -1).astype(np.float64),
-            "Y": self.Y.cpu().numpy().reshape(-1, 81).astype(np.float64),
+            "Y": self.Y.cpu().numpy().reshape(-1, self.n_out).astype(np.float64),
             "vcorr": xcorr[:3],
             "d": xcorr[:3] - xt[:3],
             "b": self.b.cpu().numpy().reshape(4, -1).astype(np.float64),
