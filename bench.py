@@ -282,6 +282,29 @@ def run_step(w, dtype, steps, warmup, params=None, shift=None, inv=None, indicat
     return out, st, t
 
 
+def run_levels(dtype, steps, warmup):
+    """The two-level prediction on the large channel's fine mesh: coarse
+    64x16x16 cells (16,384 patches of 4x4x4 fine cells), fine 256x64x64,
+    network 753-512-512-375, indicator evaluated (threshold infinite: no
+    fallback), seeded weights."""
+    import dnnmg_synth as syn
+    from paper_2307_14837_amd import stepper
+
+    w5 = syn.cfg5()
+    wc = syn.Workload("channel_64x16x16_two_levels", syn.channel_box((64, 16, 16)), w5.ns, 512, dtype, "channel")
+    xc = syn.step_inputs(wc, seed=0).xc
+    vprev = syn.step_inputs(w5, seed=0).vprev  # on the 256x64x64 fine lattice
+    params = syn.mlp_params(753, 512, 375, seed=0)
+    params[4] = params[4] * 0.05
+    st = stepper.CorrectionStep(wc.box, wc.ns, params, dtype=dtype, levels=2, indicator=True, theta=float("inf"))
+    st.load(xc, vprev)
+    t = time_graph(st, steps, warmup)
+    return {"workload": wc.name, "levels": 2, "dtype": dtype, "patches": st.np, "fine_nodes": st.nf,
+            "network": "753-512-512-375", "indicator": True, "theta": None, "ms_per_step": t["ms"],
+            "median_ms": t["median_ms"], "patches_per_s": st.np / (t["ms"] * 1e-3),
+            "fine_dof_per_s": 4 * st.nf / (t["ms"] * 1e-3)}
+
+
 def step_kernel_times(st, reps=20):
     """Each launch of the headline step timed alone on the step's own buffers
     (after one step, so every input holds step data): ms per launch."""
@@ -627,6 +650,7 @@ def main():
             run_step(w, "fp32", sv, wv, params, shift, inv, indicator=True, theta=1.0, account=True)[0],
             run_step(w, "bf16", sv, wv, params, shift, inv, indicator=True, theta=1.0, account=True)[0],
             run_step(w, "fp8", sv, wv, params, shift, inv)[0],
+            run_levels("fp8", sv, wv),
             run_step(c2, "bf16", args.steps, args.warmup)[0],
             run_step(c2, "fp32", args.steps, args.warmup)[0],
             run_batched("bf16", sv, wv),
