@@ -468,6 +468,53 @@ int dnnmg_mlp_prepare_io(int dtype, int n_in, int hidden, int n_out, const float
                          const float *const b[3], void *const Wp[3], void *ws, size_t ws_bytes, dnnmg_mlp *net,
                          void *stream);
 
+/* The paper's network form (Sec. 3; widths and depth of Sec. 5.3): D hidden
+ * layers of width H (512 or 750) without biases, batch normalisation
+ * N_i(z) = (z - mu_i) / s_i * gamma_i + beta_i before each tanh, and skip
+ * connections where the widths match:
+ *   f_1(x) = tanh(N_1(W_1 x)),  f_i(x) = tanh(N_i(W_i x)) + x (i = 2..D),
+ *   Y = W_{D+1} f_D(...),
+ * on the inputs of Sec. 4.2 (dnnmg_patch_gather_paper): 240 -> 81 for
+ * one-level patches, 1024 -> 375 for the two-level ones.  Inference only:
+ * mu_i and s_i are the statistics of a trained network, and the setup folds
+ * each normalisation into its layer (weights times gamma / s per output
+ * unit, bias beta - gamma mu / s), the widths padded for the matrix cores
+ * (dnnmg_deepnet_widths: inputs 256 / 1024, hidden 512 / 768, outputs 96 /
+ * 384; padding units have zero weights and biases, so their activations are
+ * exactly 0).  FP32 or BF16 (BF16 operands and activations, FP32
+ * accumulation, bias, tanh and skip additions). */
+#define DNNMG_DEEP_MAX_DEPTH 16
+typedef struct dnnmg_deepnet {
+    int32_t n_in, hidden, n_out, depth, dtype;
+    const void *W[DNNMG_DEEP_MAX_DEPTH + 1];  /* packed layers 0..depth (device) */
+    const float *b[DNNMG_DEEP_MAX_DEPTH + 1]; /* folded biases (device; the last is zero) */
+} dnnmg_deepnet;
+/* Padded widths of a (n_in, hidden, n_out) network; any output may be NULL. */
+int dnnmg_deepnet_widths(int n_in, int hidden, int n_out, int *in_pad, int *hidden_pad, int *out_pad);
+/* Bytes of packed layer `layer` (0..depth). */
+size_t dnnmg_deepnet_packed_bytes(int dtype, int n_in, int hidden, int n_out, int depth, int layer);
+/* Setup (enqueued on `stream`, no synchronisation): W[l] FP32 row-major
+ * [fan_in][fan_out] for l = 0..depth; gamma[l], beta[l], mean[l], sd[l] FP32
+ * [hidden] for l = 0..depth-1 (sd > 0); Wp[l] (dnnmg_deepnet_packed_bytes)
+ * and bias[l] (hidden_pad floats, out_pad for l = depth) receive the folded
+ * layers; ws: device workspace of hidden_pad floats; *net is filled. */
+int dnnmg_deepnet_prepare(int dtype, int n_in, int hidden, int n_out, int depth, const float *const W[],
+                          const float *const gamma[], const float *const beta[], const float *const mean[],
+                          const float *const sd[], void *const Wp[], float *const bias[], void *ws, size_t ws_bytes,
+                          dnnmg_deepnet *net, void *stream);
+/* Y FP32 [n][n_out] = the network on the rows of X [n][ldx] (FP32 for FP32
+ * networks, BF16 otherwise; ldx >= in_pad, padding columns zero). */
+int dnnmg_deepnet_forward(const dnnmg_deepnet *net, int64_t n, const void *X, int64_t ldx, float *Y, void *stream);
+/* The inputs of the paper's form (Sec. 4.2) on the J-level patches: row M =
+ * [u, v, w, p at the (2^J+1)^3 patch nodes, r_u, r_v, r_w, r_p there, the 12
+ * edge lengths of the coarse cell (x-directed, then y, then z), its 4
+ * diagonals, and at its 8 vertices the mean of the 3 angles between the
+ * faces meeting there (pi/2 on these axis-parallel cells)], standardised by
+ * `feat` (8 (2^J+1)^3 + 24 floats or NULL), FP32 or BF16, X [n_patches][ldx]
+ * (ldx >= 240 / 1024; padding columns zero).  x, r: FP32 [4][n_fine(L+J)]. */
+int dnnmg_patch_gather_paper(const dnnmg_box *box, int levels, const float *x, const float *r,
+                             const dnnmg_feat *feat, int dtype, void *X, int64_t ldx, void *stream);
+
 /* HIP-graph capture of library calls (Algorithm 1 as one replayable time
  * step).  dnnmg_graph_capture_begin starts capturing `stream` (a non-default
  * stream that is not already capturing; thread-local capture mode); every

@@ -10,6 +10,7 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -68,6 +69,15 @@ class MLP(ctypes.Structure):
 
 class Feat(ctypes.Structure):
     _fields_ = [("shift", c_vp), ("inv_scale", c_vp)]
+
+
+DEEP_MAX_DEPTH = 16  # DNNMG_DEEP_MAX_DEPTH of include/dnnmg.h
+
+
+class DeepNetDesc(ctypes.Structure):
+    _fields_ = [("n_in", ctypes.c_int32), ("hidden", ctypes.c_int32), ("n_out", ctypes.c_int32),
+                ("depth", ctypes.c_int32), ("dtype", ctypes.c_int32), ("W", c_vp * (DEEP_MAX_DEPTH + 1)),
+                ("b", c_vp * (DEEP_MAX_DEPTH + 1))]
 
 
 def _sig(name, argtypes, restype=ctypes.c_int):
@@ -135,6 +145,11 @@ _sig("dnnmg_prolong_levels", [_P(Box), ctypes.c_int, ctypes.c_int, c_vp, c_vp, c
 _sig("dnnmg_restrict_levels", [_P(Box), ctypes.c_int, ctypes.c_int, c_vp, c_vp, c_vp])
 _sig("dnnmg_patch_gather_levels", [_P(Box), ctypes.c_int, c_vp, c_vp, _P(Feat), ctypes.c_int, c_vp, c_i64, c_vp])
 _sig("dnnmg_scatter_avg_levels", [_P(Box), ctypes.c_int, c_vp, c_vp, c_vp, c_vp])
+_sig("dnnmg_deepnet_widths", [ctypes.c_int] * 3 + [_P(ctypes.c_int)] * 3)
+_sig("dnnmg_deepnet_packed_bytes", [ctypes.c_int] * 6, c_sz)
+_sig("dnnmg_deepnet_prepare", [ctypes.c_int] * 5 + [c_vp] * 8 + [c_sz, _P(DeepNetDesc), c_vp])
+_sig("dnnmg_deepnet_forward", [_P(DeepNetDesc), c_i64, c_vp, c_i64, c_vp, c_vp])
+_sig("dnnmg_patch_gather_paper", [_P(Box), ctypes.c_int, c_vp, c_vp, _P(Feat), ctypes.c_int, c_vp, c_i64, c_vp])
 _sig("dnnmg_graph_capture_begin", [c_vp])
 _sig("dnnmg_graph_capture_end", [c_vp, _P(c_vp)])
 _sig("dnnmg_graph_replay", [c_vp, c_vp])
@@ -156,7 +171,8 @@ EXPORTS = [
     "dnnmg_graph_capture_begin", "dnnmg_graph_capture_end", "dnnmg_graph_replay", "dnnmg_graph_destroy",
     "dnnmg_mlp_packed_bytes_io", "dnnmg_mlp_pack_io", "dnnmg_mlp_prepare_io", "dnnmg_level_sizes",
     "dnnmg_patch_dofmap_levels", "dnnmg_prolong_levels", "dnnmg_restrict_levels", "dnnmg_patch_gather_levels",
-    "dnnmg_scatter_avg_levels",
+    "dnnmg_scatter_avg_levels", "dnnmg_deepnet_widths", "dnnmg_deepnet_packed_bytes", "dnnmg_deepnet_prepare",
+    "dnnmg_deepnet_forward", "dnnmg_patch_gather_paper",
 ]
 
 # network widths per prediction depth J (levels): inputs, outputs, padded input row
@@ -389,6 +405,57 @@ def dnnmg_scatter_avg_levels(box, levels, Y, d, vbase=None, stream=None):
                                          _ptr(vbase, torch.float32, 4 * nf, "vbase"),
                                          _ptr(d, torch.float32, (4 if vbase is not None else 3) * nf, "d"),
                                          _stream(stream)))
+
+
+def deepnet_widths(n_in, hidden, n_out):
+    ip, hp, op = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(_lib.dnnmg_deepnet_widths(n_in, hidden, n_out, ctypes.byref(ip), ctypes.byref(hp), ctypes.byref(op)))
+    return ip.value, hp.value, op.value
+
+
+class DeepNet:
+    """The paper's network packed for the kernels (dnnmg_deepnet_prepare): owns
+    the FP32 parameters, the packed layers and folded biases (device)."""
+
+    def __init__(self, dtype, Ws, gammas, betas, means, stds, device="cuda:0"):
+        dev = torch.device(device)
+        t = lambda a: torch.as_tensor(np.asarray(a, np.float32)).contiguous().to(dev)
+        self.dtype = int(dtype)
+        self.depth = len(Ws) - 1
+        self.n_in, self.hidden = np.shape(Ws[0])
+        self.n_out = np.shape(Ws[-1])[1]
+        self.in_pad, self.hidden_pad, self.out_pad = deepnet_widths(self.n_in, self.hidden, self.n_out)
+        self.W = [t(w) for w in Ws]
+        self.stats = [[t(x) for x in xs] for xs in (gammas, betas, means, stds)]
+        self.Wp = [torch.zeros(int(_lib.dnnmg_deepnet_packed_bytes(self.dtype, self.n_in, self.hidden, self.n_out,
+                                                                    self.depth, l)), dtype=torch.uint8, device=dev)
+                   for l in range(self.depth + 1)]
+        self.bias = [torch.zeros(self.hidden_pad if l < self.depth else self.out_pad, dtype=torch.float32, device=dev)
+                     for l in range(self.depth + 1)]
+        self._ws = torch.zeros(4 * self.hidden_pad, dtype=torch.uint8, device=dev)
+        self.net = DeepNetDesc()
+        arr = lambda xs: (c_vp * (self.depth + 1))(*[x.data_ptr() for x in xs])
+        st = [(c_vp * self.depth)(*[x.data_ptr() for x in xs]) for xs in self.stats]
+        _check(_lib.dnnmg_deepnet_prepare(self.dtype, self.n_in, self.hidden, self.n_out, self.depth, arr(self.W),
+                                          st[0], st[1], st[2], st[3], arr(self.Wp), arr(self.bias), _ptr(self._ws),
+                                          self._ws.numel(), ctypes.byref(self.net), _stream(None)))
+
+
+def dnnmg_deepnet_forward(net: DeepNet, n, X, ldx, Y, stream=None):
+    _check(_lib.dnnmg_deepnet_forward(ctypes.byref(net.net), int(n), _ptr(X, None, None, "X"), int(ldx),
+                                      _ptr(Y, torch.float32, n * net.n_out, "Y"), _stream(stream)))
+
+
+def dnnmg_patch_gather_paper(box, levels, x, r, X, dtype, ldx, shift=None, inv_scale=None, stream=None):
+    b = Box.of(box)
+    nf, _, npch = level_sizes(b, levels)
+    nin = 240 if int(levels) == 1 else 1024
+    feat = Feat(_ptr(shift, torch.float32, nin, "shift"), _ptr(inv_scale, torch.float32, nin, "inv_scale"))
+    if X.numel() * X.element_size() < npch * ldx * {F32: 4, BF16: 2}[dtype]:
+        raise ValueError("X too small")
+    _check(_lib.dnnmg_patch_gather_paper(ctypes.byref(b), int(levels), _ptr(x, torch.float32, 4 * nf, "x"),
+                                         _ptr(r, torch.float32, 4 * nf, "r"), ctypes.byref(feat), int(dtype),
+                                         _ptr(X, None, None, "X"), int(ldx), _stream(stream)))
 
 
 class PreparedMLP:

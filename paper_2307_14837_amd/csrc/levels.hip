@@ -12,6 +12,8 @@
 // level L), `m2` the mesh of the doubled box (its coarse nodes are level
 // L + 1, its fine nodes level L + 2).  Patch M = coarse cell (I, J, K), local
 // node iota = a + 5 b + 25 c, fine node (4I + a, 4J + b, 4K + c).
+#include <math.h>
+
 #include "common.hpp"
 #include "lowp.hpp"
 
@@ -293,6 +295,81 @@ __global__ void __launch_bounds__(256) k_scatter2(Mesh m, Mesh m2, const float *
     if (vbase) d[3 * m2.n_fine + t] = b[3];
 }
 
+// ----------------------------------------- inputs of the paper's network --
+// Row M = [x~ (4 fields) at the S^3 patch nodes, r (4 fields) there, 24
+// geometry features]: one thread per four consecutive columns.  The fine
+// lattice is mf (m itself for one-level patches), S = 2^J + 1.
+struct Geo24 {
+    float f[24];
+};
+
+template <int DT, int J>
+__global__ void __launch_bounds__(256)
+    k_gather_paper(Mesh m, Mesh mf, const float *__restrict__ x, const float *__restrict__ r,
+                   const float *__restrict__ shift, const float *__restrict__ inv_scale, Geo24 geo,
+                   void *__restrict__ Xout, int64_t ldx) {
+    constexpr int P = 1 << J, S = P + 1, NL = S * S * S, NIN = 8 * NL + 24;
+    const int quads = (int)(ldx / 4);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t M = t / quads;
+    if (M >= m.n_patches) return;
+    const int col0 = (int)(t - M * quads) * 4;
+    const uint32_t JK = fdiv((uint32_t)M, m.px), I = (uint32_t)M - JK * m.n[0];
+    const uint32_t K = fdiv(JK, m.py), Jj = JK - K * m.n[1];
+    float sh[4], sc[4], v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int col = col0 + q;
+        const int cc = col < NIN ? col : NIN - 1;
+        sh[q] = shift ? shift[cc] : 0.0f;
+        sc[q] = inv_scale ? inv_scale[cc] : 1.0f;
+        const int cn = col < 8 * NL ? col : 0; // node columns read a valid address
+        const int f = cn / NL, iota = cn - NL * f;
+        const int a = iota % S, b = (iota / S) % S, c = iota / (S * S);
+        const int i = wrap(P * (int)I + a, mf.nf[0], mf.per[0]);
+        const int j = wrap(P * (int)Jj + b, mf.nf[1], mf.per[1]);
+        const int k = wrap(P * (int)K + c, mf.nf[2], mf.per[2]);
+        const int64_t node = i + (int64_t)mf.nf[0] * (j + (int64_t)mf.nf[1] * k);
+        v[q] = f < 4 ? x[f * mf.n_fine + node] : r[(f - 4) * mf.n_fine + node];
+    }
+    float z[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int col = col0 + q;
+        float val = col < 8 * NL ? v[q] : (col < NIN ? geo.f[col - 8 * NL] : 0.0f);
+        if (col < NIN) {
+            if (shift) val -= sh[q];
+            if (inv_scale) val *= sc[q];
+        }
+        z[q] = val;
+    }
+    if (DT == DNNMG_F32) {
+        *(float4 *)((float *)Xout + M * ldx + col0) = make_float4(z[0], z[1], z[2], z[3]);
+    } else {
+        uint2 o;
+        o.x = pack_bf16x2_hw(z[0], z[1]);
+        o.y = pack_bf16x2_hw(z[2], z[3]);
+        *(uint2 *)((uint16_t *)Xout + M * ldx + col0) = o;
+    }
+}
+
+// The 24 geometry features of a coarse cell of the box (all cells are the
+// same axis-parallel brick): edges H0 x4, H1 x4, H2 x4; the 4 diagonals
+// |H|; the mean dihedral angle at each vertex, pi/2.
+static Geo24 brick_features(const dnnmg_box *box) {
+    Geo24 g;
+    double H[3], d2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        H[a] = box->len[a] / box->n[a];
+        d2 += H[a] * H[a];
+    }
+    for (int a = 0; a < 3; ++a)
+        for (int e = 0; e < 4; ++e) g.f[4 * a + e] = (float)H[a];
+    for (int e = 0; e < 4; ++e) g.f[12 + e] = (float)sqrt(d2);
+    for (int e = 0; e < 8; ++e) g.f[16 + e] = (float)(0.5 * 3.14159265358979323846);
+    return g;
+}
+
 // the doubled box (its fine mesh is level L + 2)
 static int level2_meshes(const dnnmg_box *box, Mesh *m, Mesh *m2) {
     int rc = make_mesh(box, m);
@@ -400,4 +477,36 @@ extern "C" int dnnmg_scatter_avg_levels(const dnnmg_box *box, int levels, const 
     if (!Y || !d) return fail(DNNMG_ERR_ARG, "dnnmg_scatter_avg_levels: NULL pointer");
     k_scatter2<<<blocks_for(m2.n_fine, 256), 256, 0, STREAM>>>(m, m2, Y, vbase, d);
     return hip_check(hipGetLastError(), "dnnmg_scatter_avg_levels launch");
+}
+
+extern "C" int dnnmg_patch_gather_paper(const dnnmg_box *box, int levels, const float *x, const float *r,
+                                        const dnnmg_feat *feat, int dtype, void *X, int64_t ldx, void *stream) {
+    int rc = check_levels(levels, "dnnmg_patch_gather_paper");
+    if (rc) return rc;
+    Mesh m, m2;
+    if (levels == 1) {
+        if ((rc = make_mesh(box, &m))) return rc;
+        m2 = m;
+    } else if ((rc = level2_meshes(box, &m, &m2))) {
+        return rc;
+    }
+    if (!x || !r || !X) return fail(DNNMG_ERR_ARG, "dnnmg_patch_gather_paper: NULL pointer");
+    if (!aligned16(X)) return fail(DNNMG_ERR_ARG, "dnnmg_patch_gather_paper: X not 16-byte aligned");
+    const int nin = levels == 1 ? 240 : 1024;
+    const int align = dtype == DNNMG_F32 ? 4 : 8;
+    if (ldx < nin || ldx % align)
+        return fail(DNNMG_ERR_SHAPE, "dnnmg_patch_gather_paper: ldx %lld must be >= %d and a multiple of %d",
+                    (long long)ldx, nin, align);
+    const float *sh = feat ? feat->shift : nullptr;
+    const float *sc = feat ? feat->inv_scale : nullptr;
+    const Geo24 geo = brick_features(box);
+    const unsigned g = blocks_for(m.n_patches * (ldx / 4), 256);
+#define GP(DT, JJ) k_gather_paper<DT, JJ><<<g, 256, 0, STREAM>>>(m, m2, x, r, sh, sc, geo, X, ldx)
+    if (dtype == DNNMG_F32 && levels == 1) GP(DNNMG_F32, 1);
+    else if (dtype == DNNMG_F32) GP(DNNMG_F32, 2);
+    else if (dtype == DNNMG_BF16 && levels == 1) GP(DNNMG_BF16, 1);
+    else if (dtype == DNNMG_BF16) GP(DNNMG_BF16, 2);
+    else return fail(DNNMG_ERR_UNSUPPORTED, "dnnmg_patch_gather_paper: dtype %d (FP32 or BF16)", dtype);
+#undef GP
+    return hip_check(hipGetLastError(), "dnnmg_patch_gather_paper launch");
 }

@@ -58,9 +58,12 @@ __host__ __device__ inline int kslot_to_input(int kind, int layer, int kc, int g
     return 16 * (kc * (E / 4) + (e >> 2)) + 4 * g + (e & 3);
 }
 
+// colscale (optional): every weight of output column o is multiplied by
+// colscale[o] first (a batch normalisation folded into the layer).
 template <typename OUT>
 __global__ void k_pack(int kind, int layer, int fan_in, int fan_out, int ntiles, int nchunks,
-                       const float *__restrict__ W, float inv_wscale, OUT *__restrict__ Wp) {
+                       const float *__restrict__ W, float inv_wscale, OUT *__restrict__ Wp,
+                       const float *__restrict__ colscale) {
     const int E = kind_E(kind);
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t total = (int64_t)ntiles * nchunks * 64 * E;
@@ -73,6 +76,7 @@ __global__ void k_pack(int kind, int layer, int fan_in, int fan_out, int ntiles,
     int o = 16 * ot + i;
     int k = kslot_to_input(kind, layer, kc, g, e);
     float w = (o < fan_out && k < fan_in) ? W[(int64_t)k * fan_out + o] : 0.0f;
+    if (colscale && o < fan_out) w *= colscale[o];
     if constexpr (sizeof(OUT) == 4) Wp[t] = w;
     else if constexpr (sizeof(OUT) == 2) Wp[t] = f32_to_bf16(w);
     else Wp[t] = f32_to_e4m3(w * inv_wscale);
@@ -141,7 +145,7 @@ __device__ __forceinline__ void put_act(unsigned char *out, int t, int ot, int l
 // One dense layer for the tile: acc = W^T B over the wave's output tiles,
 // then bias and (unless LAST) tanh into the next layer's fragments, or (LAST)
 // the output rows.
-template <int K, int KN, int NTILES, int NCH, int PT, bool LAST, int H, int NW, int NO = N_OUT>
+template <int K, int KN, int NTILES, int NCH, int PT, bool LAST, int H, int NW, int NO = N_OUT, bool SKIP = false>
 __device__ __forceinline__ void layer(const typename Frag<K>::T *__restrict__ Wl, const float *__restrict__ bias,
                                       const unsigned char *in, unsigned char *out, float scale, float qinv,
                                       int wave, int lane, int64_t base, int64_t n, float *__restrict__ Y,
@@ -218,6 +222,21 @@ __device__ __forceinline__ void layer(const typename Frag<K>::T *__restrict__ Wl
                     const float z = acc[i][t][e] * sc + bv[e];
                     if constexpr (K == KF32) v[e] = tanhf(z);
                     else v[e] = 1.0f - 2.0f * __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(z) + 1.0f);
+                }
+                if constexpr (SKIP) {
+                    // skip connection: + the layer's own input at these units
+                    // (an H-wide input of the same kind has the output's layout)
+                    static_assert(K == KN && (K == KF32 || K == KBF16), "skip needs equal FP32/BF16 layouts");
+                    if constexpr (KN == KF32) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) v[e] += ((const float *)in)[(t * NCHN + 4 * ot + e) * 64 + lane];
+                    } else {
+                        const uint2 w = *(const uint2 *)(in + ((t * NCHN + (ot >> 1)) * 64 + lane) * 16 + 8 * (ot & 1));
+                        v[0] += bf16_to_f32((uint16_t)(w.x & 0xffffu));
+                        v[1] += bf16_to_f32((uint16_t)(w.x >> 16));
+                        v[2] += bf16_to_f32((uint16_t)(w.y & 0xffffu));
+                        v[3] += bf16_to_f32((uint16_t)(w.y >> 16));
+                    }
                 }
                 put_act<KN, NCHN>(out, t, ot, lane, v, qinv);
                 if (saved) {
@@ -419,6 +438,109 @@ __global__ void __launch_bounds__((FwdShape<DT, H, PT, J>::NTHR))
     }
 }
 
+// ------------------------------------------------- the paper's network ----
+// Sec. 3: f_1 = tanh(N_1(W_1 x)), f_i = tanh(N_i(W_i x)) + x (i = 2 .. D),
+// f_L = W_L x, with the batch normalisations N_i folded into the packed
+// weights (column scale gamma / s) and a bias (beta - gamma mu / s).  Widths:
+// inputs INP (240 -> 256 or 1024), hidden HP (512, or 750 -> 768: the padded
+// units have zero weights and bias, so their activations stay exactly 0),
+// outputs NO (81 or 375).  Activations ping-pong between two LDS buffers.
+struct DeepArgs {
+    const void *W[DNNMG_DEEP_MAX_DEPTH + 1];
+    const float *b[DNNMG_DEEP_MAX_DEPTH + 1];
+};
+
+template <int DT, int HP, int PT, int J>
+struct DeepShape {
+    static constexpr int INP = J == 1 ? 256 : 1024;
+    static constexpr int NO = J == 1 ? 81 : 375, OUTP = J == 1 ? 96 : 384;
+    static constexpr int K = DT == DNNMG_F32 ? KF32 : KBF16;
+    static constexpr int NCH0 = INP / (4 * kind_E(K)), NCHH = HP / (4 * kind_E(K));
+    static constexpr int IN0 = PT * NCH0 * 64 * frag_bytes(K), INH = PT * NCHH * 64 * frag_bytes(K);
+    static constexpr int YB = 16 * PT * NO * 4;
+    static constexpr int BUF = IN0 > INH ? (IN0 > YB ? IN0 : YB) : (INH > YB ? INH : YB);
+    static constexpr int NW = (PT == 4 || HP > 512) ? 8 : 4;
+    static constexpr int NTHR = 64 * NW;
+};
+
+template <int DT, int HP, int PT, int J>
+__global__ void __launch_bounds__((DeepShape<DT, HP, PT, J>::NTHR))
+    k_deep_fwd(int64_t ntiles, int64_t n, const void *__restrict__ Xv, int64_t ldx, DeepArgs a, int depth,
+               float *__restrict__ Y) {
+    using S = DeepShape<DT, HP, PT, J>;
+    using F = typename Frag<S::K>::T;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[2 * S::BUF];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t base = tile * 16 * PT;
+        unsigned char *cur = smem, *nxt = smem + S::BUF;
+        stage_rows<S::K, S::NCH0, PT, S::NTHR, S::INP>(Xv, ldx, base, n, cur, tid);
+        __syncthreads();
+        layer<S::K, S::K, HP / 16, S::NCH0, PT, false, HP, S::NW>((const F *)a.W[0], a.b[0], cur, nxt, 1.0f, 1.0f,
+                                                                  wave, lane, base, n, Y, nullptr, 0, 0);
+        __syncthreads();
+        for (int l = 1; l < depth; ++l) {
+            unsigned char *t = cur;
+            cur = nxt;
+            nxt = t;
+            layer<S::K, S::K, HP / 16, S::NCHH, PT, false, HP, S::NW, S::NO, true>(
+                (const F *)a.W[l], a.b[l], cur, nxt, 1.0f, 1.0f, wave, lane, base, n, Y, nullptr, 0, 0);
+            __syncthreads();
+        }
+        layer<S::K, S::K, S::OUTP / 16, S::NCHH, PT, true, HP, S::NW, S::NO>(
+            (const F *)a.W[depth], a.b[depth], nxt, cur, 1.0f, 1.0f, wave, lane, base, n, Y, nullptr, 0, 0);
+        __syncthreads();
+        {
+            const int cnt = (int)((n - base < 16 * PT ? n - base : 16 * PT) * S::NO);
+            const float *ys = (const float *)cur;
+            float *yd = Y + base * S::NO;
+            int q0 = 0;
+            if ((((uintptr_t)yd) & 15) == 0) {
+                for (int q = tid; q < cnt / 4; q += S::NTHR) ((float4 *)yd)[q] = ((const float4 *)ys)[q];
+                q0 = cnt / 4 * 4;
+            }
+            for (int q = q0 + tid; q < cnt; q += S::NTHR) yd[q] = ys[q];
+        }
+        __syncthreads();
+    }
+}
+
+// batch normalisation folded into a layer: colscale = gamma / s, bias =
+// beta - gamma mu / s for the H real units, 0 for the padding up to HP
+__global__ void __launch_bounds__(256) k_bn_fold(int H, int HP, const float *__restrict__ gamma,
+                                                 const float *__restrict__ beta, const float *__restrict__ mean,
+                                                 const float *__restrict__ sd, float *__restrict__ colscale,
+                                                 float *__restrict__ bias) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= HP) return;
+    if (u >= H) {
+        bias[u] = 0.0f;
+        return;
+    }
+    const float c = gamma[u] / sd[u];
+    colscale[u] = c;
+    bias[u] = beta[u] - c * mean[u];
+}
+
+__global__ void __launch_bounds__(256) k_zero_f32(int n, float *__restrict__ p) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u < n) p[u] = 0.0f;
+}
+
+// Instantiated (dtype, padded width, PT, J) variants of the paper's network.
+#define DNNMG_DEEP_VARIANTS(X)                                                                          \
+    X(DNNMG_F32, 512, 1, 1) X(DNNMG_F32, 768, 1, 1) X(DNNMG_BF16, 512, 2, 1) X(DNNMG_BF16, 512, 4, 1)     \
+    X(DNNMG_BF16, 768, 1, 1) X(DNNMG_BF16, 768, 2, 1)                                                     \
+    X(DNNMG_F32, 512, 1, 2) X(DNNMG_F32, 768, 1, 2) X(DNNMG_BF16, 512, 1, 2) X(DNNMG_BF16, 512, 2, 2)     \
+    X(DNNMG_BF16, 768, 1, 2) X(DNNMG_BF16, 768, 2, 2)
+
+static int deep_levels(int n_in, int n_out) {
+    if (n_in == 240 && n_out == 81) return 1;
+    if (n_in == 1024 && n_out == 375) return 2;
+    return 0;
+}
+static int deep_hpad(int hidden) { return (hidden + 255) / 256 * 256; }
+
 static void fp8_scales(const dnnmg_mlp *net, float &s1, float &q1) {
     s1 = 1.f;
     q1 = 1.f;
@@ -583,13 +705,14 @@ extern "C" int dnnmg_mlp_pack_io(int dtype, int n_in, int hidden, int n_out, int
     hipStream_t s = (hipStream_t)stream;
     unsigned grid = blocks_for(total, 256);
     if (kind == KF32)
-        k_pack<float><<<grid, 256, 0, s>>>(kind, layer, fan_in, fan_out, ntiles, nchunks, W, 1.f, (float *)Wp);
+        k_pack<float><<<grid, 256, 0, s>>>(kind, layer, fan_in, fan_out, ntiles, nchunks, W, 1.f, (float *)Wp,
+                                           nullptr);
     else if (kind == KBF16)
         k_pack<uint16_t><<<grid, 256, 0, s>>>(kind, layer, fan_in, fan_out, ntiles, nchunks, W, 1.f,
-                                              (uint16_t *)Wp);
+                                              (uint16_t *)Wp, nullptr);
     else
         k_pack<uint8_t><<<grid, 256, 0, s>>>(kind, layer, fan_in, fan_out, ntiles, nchunks, W,
-                                             1.f / w_scale, (uint8_t *)Wp);
+                                             1.f / w_scale, (uint8_t *)Wp, nullptr);
     return hip_check(hipGetLastError(), "dnnmg_mlp_pack launch");
 }
 
@@ -736,4 +859,127 @@ extern "C" int dnnmg_patch_gather_forward(const dnnmg_box *box, const dnnmg_mlp 
     const int64_t ntiles = (one.m.n_patches + 16 * pt - 1) / (16 * pt);
     return fwd_launch(net, pt, true, ntiles, 0, 0, nullptr, 0, nullptr, 1, one, xt, r, sh, sc, Y, nullptr,
                       (hipStream_t)stream);
+}
+
+// ------------------------------------------------- the paper's network ----
+extern "C" int dnnmg_deepnet_widths(int n_in, int hidden, int n_out, int *in_pad, int *hidden_pad, int *out_pad) {
+    const int J = deep_levels(n_in, n_out);
+    if (!J) return fail(DNNMG_ERR_SHAPE, "paper network widths %d -> %d (240 -> 81 or 1024 -> 375)", n_in, n_out);
+    if (hidden != 512 && hidden != 750)
+        return fail(DNNMG_ERR_UNSUPPORTED, "paper network hidden width %d (512 or 750)", hidden);
+    if (in_pad) *in_pad = J == 1 ? 256 : 1024;
+    if (hidden_pad) *hidden_pad = deep_hpad(hidden);
+    if (out_pad) *out_pad = J == 1 ? 96 : 384;
+    return DNNMG_OK;
+}
+
+extern "C" size_t dnnmg_deepnet_packed_bytes(int dtype, int n_in, int hidden, int n_out, int depth, int layer) {
+    int ip, hp, op;
+    if (dnnmg_deepnet_widths(n_in, hidden, n_out, &ip, &hp, &op)) return 0;
+    if (dtype != DNNMG_F32 && dtype != DNNMG_BF16) return 0;
+    if (depth < 2 || depth > DNNMG_DEEP_MAX_DEPTH || layer < 0 || layer > depth) return 0;
+    const int kp = layer == 0 ? ip : hp, np = layer == depth ? op : hp;
+    return (size_t)kp * np * (dtype == DNNMG_F32 ? 4 : 2);
+}
+
+extern "C" int dnnmg_deepnet_prepare(int dtype, int n_in, int hidden, int n_out, int depth, const float *const W[],
+                                     const float *const gamma[], const float *const beta[],
+                                     const float *const mean[], const float *const sd[], void *const Wp[],
+                                     float *const bias[], void *ws, size_t ws_bytes, dnnmg_deepnet *net,
+                                     void *stream) {
+    int ip, hp, op, rc;
+    if ((rc = dnnmg_deepnet_widths(n_in, hidden, n_out, &ip, &hp, &op))) return rc;
+    if (dtype != DNNMG_F32 && dtype != DNNMG_BF16)
+        return fail(DNNMG_ERR_UNSUPPORTED, "dnnmg_deepnet_prepare: dtype %d (FP32 or BF16)", dtype);
+    if (depth < 2 || depth > DNNMG_DEEP_MAX_DEPTH)
+        return fail(DNNMG_ERR_ARG, "dnnmg_deepnet_prepare: depth %d not in 2..%d", depth, DNNMG_DEEP_MAX_DEPTH);
+    if (!W || !gamma || !beta || !mean || !sd || !Wp || !bias || !net || !ws)
+        return fail(DNNMG_ERR_ARG, "dnnmg_deepnet_prepare: NULL pointer");
+    if (ws_bytes < sizeof(float) * (size_t)hp || !aligned16(ws))
+        return fail(DNNMG_ERR_ARG, "dnnmg_deepnet_prepare: workspace needs %zu bytes, 16-byte aligned",
+                    sizeof(float) * (size_t)hp);
+    for (int l = 0; l <= depth; ++l) {
+        if (!W[l] || !Wp[l] || !bias[l] || !aligned16(Wp[l]) || !aligned16(bias[l]))
+            return fail(DNNMG_ERR_ARG, "dnnmg_deepnet_prepare: layer %d pointers NULL or misaligned", l);
+        if (l < depth && (!gamma[l] || !beta[l] || !mean[l] || !sd[l]))
+            return fail(DNNMG_ERR_ARG, "dnnmg_deepnet_prepare: normalisation %d NULL", l);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    float *colscale = (float *)ws;
+    const int kind = dtype == DNNMG_F32 ? KF32 : KBF16, E = kind_E(kind);
+    for (int l = 0; l <= depth; ++l) {
+        const bool last = l == depth;
+        const int fan_in = l == 0 ? n_in : hidden, fan_out = last ? n_out : hidden;
+        const int kp = l == 0 ? ip : hp, np = last ? op : hp;
+        // packing slot order: direct input columns for the first layer, the
+        // accumulator layout of the previous layer for the others
+        const int lk = l == 0 ? 0 : 1;
+        if (!last)
+            k_bn_fold<<<blocks_for(hp, 256), 256, 0, s>>>(hidden, hp, gamma[l], beta[l], mean[l], sd[l], colscale,
+                                                        bias[l]);
+        else
+            k_zero_f32<<<blocks_for(op, 256), 256, 0, s>>>(op, bias[l]);
+        const int ntiles = np / 16, nchunks = kp / (4 * E);
+        const int64_t total = (int64_t)ntiles * nchunks * 64 * E;
+        if (kind == KF32)
+            k_pack<float><<<blocks_for(total, 256), 256, 0, s>>>(kind, lk, fan_in, fan_out, ntiles, nchunks, W[l],
+                                                                 1.f, (float *)Wp[l], last ? nullptr : colscale);
+        else
+            k_pack<uint16_t><<<blocks_for(total, 256), 256, 0, s>>>(kind, lk, fan_in, fan_out, ntiles, nchunks, W[l],
+                                                                    1.f, (uint16_t *)Wp[l],
+                                                                    last ? nullptr : colscale);
+    }
+    if ((rc = hip_check(hipGetLastError(), "dnnmg_deepnet_prepare launch"))) return rc;
+    net->n_in = n_in;
+    net->hidden = hidden;
+    net->n_out = n_out;
+    net->depth = depth;
+    net->dtype = dtype;
+    for (int l = 0; l <= DNNMG_DEEP_MAX_DEPTH; ++l) {
+        net->W[l] = l <= depth ? Wp[l] : nullptr;
+        net->b[l] = l <= depth ? bias[l] : nullptr;
+    }
+    return DNNMG_OK;
+}
+
+extern "C" int dnnmg_deepnet_forward(const dnnmg_deepnet *net, int64_t n, const void *X, int64_t ldx, float *Y,
+                                     void *stream) {
+    if (!net) return fail(DNNMG_ERR_ARG, "dnnmg_deepnet_forward: net is NULL");
+    int ip, hp, op, rc;
+    if ((rc = dnnmg_deepnet_widths(net->n_in, net->hidden, net->n_out, &ip, &hp, &op))) return rc;
+    if (net->depth < 2 || net->depth > DNNMG_DEEP_MAX_DEPTH)
+        return fail(DNNMG_ERR_ARG, "dnnmg_deepnet_forward: depth %d", net->depth);
+    if (n < 0) return fail(DNNMG_ERR_SHAPE, "dnnmg_deepnet_forward: n < 0");
+    if (n == 0) return DNNMG_OK;
+    if (!X || !Y || !aligned16(X)) return fail(DNNMG_ERR_ARG, "dnnmg_deepnet_forward: X/Y NULL or X misaligned");
+    const int align = net->dtype == DNNMG_F32 ? 4 : 8;
+    if (ldx < ip || ldx % align)
+        return fail(DNNMG_ERR_SHAPE, "dnnmg_deepnet_forward: ldx %lld must be >= %d and a multiple of %d",
+                    (long long)ldx, ip, align);
+    DeepArgs a{};
+    for (int l = 0; l <= net->depth; ++l) {
+        if (!net->W[l] || !net->b[l]) return fail(DNNMG_ERR_ARG, "dnnmg_deepnet_forward: layer %d NULL", l);
+        a.W[l] = net->W[l];
+        a.b[l] = net->b[l];
+    }
+    const int J = deep_levels(net->n_in, net->n_out);
+    const int ncu = device_cus();
+    // the largest built tile that still gives every compute unit work
+    int pt = 0;
+#define PICK(DT, H, P, JJ)                                                                              \
+    if (net->dtype == DT && hp == H && J == JJ && (pt == 0 || (P > pt && n >= (int64_t)ncu * 16 * P))) pt = P;
+    DNNMG_DEEP_VARIANTS(PICK)
+#undef PICK
+    if (!pt) return fail(DNNMG_ERR_UNSUPPORTED, "dnnmg_deepnet_forward: dtype %d width %d not built", net->dtype, hp);
+    const int64_t ntiles = (n + 16 * pt - 1) / (16 * pt);
+    hipStream_t s = (hipStream_t)stream;
+#define LAUNCH(DT, H, P, JJ)                                                                            \
+    if (net->dtype == DT && hp == H && J == JJ && pt == P) {                                            \
+        k_deep_fwd<DT, H, P, JJ><<<(unsigned)ntiles, DeepShape<DT, H, P, JJ>::NTHR, 0, s>>>(ntiles, n, X, ldx, a, \
+                                                                                          net->depth, Y); \
+        return hip_check(hipGetLastError(), "dnnmg_deepnet_forward launch");                            \
+    }
+    DNNMG_DEEP_VARIANTS(LAUNCH)
+#undef LAUNCH
+    return fail(DNNMG_ERR_UNSUPPORTED, "dnnmg_deepnet_forward: no variant");
 }

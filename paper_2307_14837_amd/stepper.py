@@ -32,7 +32,8 @@ class CorrectionStep:
     """
 
     def __init__(self, box, ns, params, dtype="bf16", device="cuda:0", shift=None, inv_scale=None,
-                 indicator=False, theta=1.0, fallback_sweeps=4, fused=True, carry_rhs=None, levels=1):
+                 indicator=False, theta=1.0, fallback_sweeps=4, fused=True, carry_rhs=None, levels=1,
+                 network="mlp"):
         self.box = L.Box.of(box)
         self.ns = L.NS.of(ns)
         self.dev = torch.device(device)
@@ -43,12 +44,23 @@ class CorrectionStep:
         self.levels = int(levels)
         self.fbox = L.level_box(self.box, self.levels)
         self.nf, self.nc, self.np = L.level_sizes(self.box, self.levels)
-        self.n_in, self.n_out, self.ldx = L.LEVEL_IO[self.levels]
-        self.hidden = int(np.shape(params[0])[1])
+        # network "mlp": the 3-layer tanh network of the configurations;
+        # "paper": the paper's form (Sec. 3: batch normalisation, skip
+        # connections, D hidden layers) on its inputs (Sec. 4.2), params =
+        # (Ws, gammas, betas, means, stds)
+        self.network = network
+        if network == "paper":
+            Ws = params[0]
+            self.n_in, self.n_out = int(np.shape(Ws[0])[0]), int(np.shape(Ws[-1])[1])
+            self.ldx = L.deepnet_widths(self.n_in, int(np.shape(Ws[0])[1]), self.n_out)[0]
+            self.hidden = int(np.shape(Ws[0])[1])
+        else:
+            self.n_in, self.n_out, self.ldx = L.LEVEL_IO[self.levels]
+            self.hidden = int(np.shape(params[0])[1])
         self.indicator = indicator
         # fused: the gather runs inside the network kernel (no X round trip;
         # built for one-level patches)
-        self.fused = bool(fused) and self.levels == 1
+        self.fused = bool(fused) and self.levels == 1 and network == "mlp"
         self.carry_rhs = True if carry_rhs is None else bool(carry_rhs)
         f32 = dict(dtype=torch.float32, device=self.dev)
         f64 = dict(dtype=torch.float64, device=self.dev)
@@ -79,6 +91,10 @@ class CorrectionStep:
     # ------------------------------------------------------------- network --
     def set_params(self, params):
         H = self.hidden
+        if self.network == "paper":
+            # batch normalisations folded into the packed layers by the library
+            self.deep = L.DeepNet(self.dtype, *params, device=self.dev)
+            return
         W32 = [torch.as_tensor(np.asarray(params[2 * l], np.float32)).contiguous().to(self.dev) for l in range(3)]
         bias = [torch.as_tensor(np.asarray(params[2 * l + 1], np.float32)).contiguous().to(self.dev) for l in range(3)]
         # packing and the per-tensor scales of the precision scheme are the
@@ -98,7 +114,7 @@ class CorrectionStep:
             L.dnnmg_rhs(self.fbox, self.ns, self.vprev, self.b)
 
     def step(self, stream=None):
-        if self.levels != 1:
+        if self.levels != 1 or self.network != "mlp":
             return self._step_levels(stream)
         box, ns = self.box, self.ns
         # x~ = P xc and r = F - A(x~) in one pass (no LPS terms on a prolongation)
@@ -135,20 +151,25 @@ class CorrectionStep:
         L.dnnmg_restrict(box, self.b, self.bc, stream=stream)
 
     def _step_levels(self, stream=None):
-        """The step with the prediction J levels above the coarse mesh: x~ =
-        P^J x^L, the residual of level L + J (on fbox, against the carried
-        right-hand side or from v_prev), Q and the network on the J-level
-        patches, L back to level L + J, [indicator], Rhs on fbox, b^L =
-        (P^J)^T b."""
+        """The step with the prediction J levels above the coarse mesh (and
+        the step with the paper's network at any J): x~ = P^J x^L, the
+        residual of level L + J (on fbox, against the carried right-hand
+        side or from v_prev), Q and the network on the J-level patches, L
+        back to level L + J, [indicator], Rhs on fbox, b^L = (P^J)^T b."""
         box, fb, ns, J = self.box, self.fbox, self.ns, self.levels
         L.dnnmg_prolong_levels(box, J, self.xc, self.xt, stream=stream)
         if self.carry_rhs:
             L.dnnmg_residual_b(fb, ns, self.xt, self.b, self.r, self.ws_res, stream=stream)
         else:
             L.dnnmg_residual(fb, ns, self.xt, self.vprev, self.r, self.ws_res, stream=stream)
-        L.dnnmg_patch_gather_levels(box, J, self.xt, self.r, self.X, self.xdtype, self.ldx, self.shift,
-                                    self.inv_scale, stream=stream)
-        L.dnnmg_patch_forward(self.net, self.np, self.X, self.ldx, self.Y, stream=stream)
+        if self.network == "paper":
+            L.dnnmg_patch_gather_paper(box, J, self.xt, self.r, self.X, self.xdtype, self.ldx, self.shift,
+                                       self.inv_scale, stream=stream)
+            L.dnnmg_deepnet_forward(self.deep, self.np, self.X, self.ldx, self.Y, stream=stream)
+        else:
+            L.dnnmg_patch_gather_levels(box, J, self.xt, self.r, self.X, self.xdtype, self.ldx, self.shift,
+                                        self.inv_scale, stream=stream)
+            L.dnnmg_patch_forward(self.net, self.np, self.X, self.ldx, self.Y, stream=stream)
         L.dnnmg_scatter_avg_levels(box, J, self.Y, self.xcorr, vbase=self.xt, stream=stream)
         if self.indicator:
             if self.carry_rhs:

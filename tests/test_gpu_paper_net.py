@@ -1,0 +1,135 @@
+"""The paper's network form on the GPU (Sec. 3: batch normalisation folded
+into the layers, skip connections, 8 hidden layers of width 512 or 750; Sec.
+4.2 inputs with pressure, continuity residual and 24 geometry features)
+against the FP64 oracle, which evaluates the normalisation explicitly."""
+import numpy as np
+import pytest
+import torch
+
+import dnnmg_synth as syn
+from gpu_util import dev, f32, rel_l2, say, to_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_2307_14837_amd as L
+
+    assert torch.cuda.is_available()
+    return L
+
+
+@pytest.fixture(scope="module")
+def dn(orc):
+    from oracle import deepnet
+
+    return deepnet
+
+
+def r32(ps):
+    """Parameters rounded to FP32 once (the values both sides see)."""
+    return [[f32(x).astype(np.float64) for x in group] for group in ps]
+
+
+@pytest.mark.parametrize("levels", [1, 2])
+@pytest.mark.parametrize("dtype", ["fp32", "bf16"])
+def test_gather_paper(L, dn, levels, dtype):
+    box = syn.BoxSpec((4, 2, 2), (1.0, 0.6, 0.5), 1, syn.Y_LO | syn.Z_HI)
+    nf, _, npch = L.level_sizes(box, levels)
+    nin = 240 if levels == 1 else 1024
+    ldx = 256 if levels == 1 else 1024
+    rng = np.random.default_rng(1)
+    x = f32(rng.standard_normal((4, nf)))
+    r = f32(rng.standard_normal((4, nf)) * 1e-2)
+    sh = f32(rng.standard_normal(nin) * 0.1)
+    inv = f32(rng.uniform(0.5, 2.0, nin))
+    dt = {"fp32": L.F32, "bf16": L.BF16}[dtype]
+    X = torch.zeros(npch * ldx, dtype=torch.float32 if dtype == "fp32" else torch.bfloat16, device=dev())
+    L.dnnmg_patch_gather_paper(box, levels, to_gpu(x.ravel()), to_gpu(r.ravel()), X, dt, ldx, to_gpu(sh), to_gpu(inv))
+    torch.cuda.synchronize()
+    got = X.float().cpu().numpy().reshape(npch, ldx)
+    ref = dn.paper_inputs(box, levels, x.astype(np.float64), r.astype(np.float64), sh.astype(np.float64),
+                          inv.astype(np.float64))
+    assert np.all(got[:, nin:] == 0.0)
+    # the GPU sees the inputs rounded to FP32 (the geometry features are
+    # computed in FP64 and rounded once) and rounds (X - shift) * inv_scale
+    # twice: the bound scales with |X| + |shift|, not with the standardised
+    # value, which can cancel; BF16 adds its own rounding of the result
+    raw = dn.paper_inputs(box, levels, x.astype(np.float64), r.astype(np.float64))
+    bound = 4 * 2.0 ** -24 * (np.abs(raw) + np.abs(sh)) * inv
+    if dtype == "bf16":
+        bound = bound + 2.0 ** -8 * np.abs(ref)
+    err = np.abs(got[:, :nin] - ref)
+    worst = np.unravel_index(np.argmax(err - bound), err.shape)
+    say(f"  worst column {worst[1]}: err {err[worst]:.3e} bound {bound[worst]:.3e} ref {ref[worst]:.4e}")
+    assert np.all(err <= bound)
+
+
+CASES = [(240, 512, 81, "fp32", 1e-5), (240, 750, 81, "fp32", 1e-5), (1024, 512, 375, "fp32", 1e-5),
+         (1024, 750, 375, "fp32", 1e-5), (240, 512, 81, "bf16", 2e-2), (240, 750, 81, "bf16", 2e-2),
+         (1024, 512, 375, "bf16", 2e-2), (1024, 750, 375, "bf16", 2e-2)]
+
+
+@pytest.mark.parametrize("n_in,H,n_out,dtype,tol", CASES)
+@pytest.mark.parametrize("n", [37, 2000])
+def test_paper_network_forward(L, dn, n_in, H, n_out, dtype, tol, n):
+    say("paper network", n_in, H, n_out, dtype, n)
+    ps = r32(dn.random_params(n_in, H, n_out, 8, seed=2))
+    net = L.DeepNet({"fp32": L.F32, "bf16": L.BF16}[dtype], *ps)
+    ip = net.in_pad
+    X = f32(np.random.default_rng(3).standard_normal((n, n_in)))
+    Xp = np.zeros((n, ip), np.float32)
+    Xp[:, :n_in] = X
+    Xg = to_gpu(Xp.ravel())
+    if dtype == "bf16":
+        Xg = Xg.to(torch.bfloat16)
+    Y = torch.full((n * n_out,), float("nan"), dtype=torch.float32, device=dev())
+    L.dnnmg_deepnet_forward(net, n, Xg, ip, Y)
+    torch.cuda.synchronize()
+    ref = dn.forward(X.astype(np.float64), *ps)
+    e = rel_l2(Y.cpu().numpy().reshape(n, n_out), ref)
+    say(f"  rel-L2 {e:.2e}")
+    assert e <= tol
+
+
+@pytest.mark.parametrize("levels,dtype,tol", [(1, "fp32", 1e-4), (2, "fp32", 1e-4), (1, "bf16", 2e-2),
+                                              (2, "bf16", 2e-2)])
+def test_step_with_paper_network(orc, dn, levels, dtype, tol):
+    """One correction step with the paper's network (indicator evaluated, no
+    fallback) against the oracle's chain: P^J, the residual of level L + J,
+    the paper's inputs, the network with explicit normalisation, L, Rhs, R."""
+    from paper_2307_14837_amd import stepper
+
+    box = syn.channel_box((8, 4, 4)) if levels == 1 else syn.channel_box((4, 2, 2))
+    ns = syn.NSParams(1e-3, 0.005)
+    say("step with the paper's network", levels, dtype)
+    fb = orc.level_box(box, levels)
+    nf = orc.fine_nodes(fb)
+    inp = syn.step_inputs(syn.Workload("w", box, ns, 512, dtype, "channel"), seed=4)
+    xt0 = orc.prolong_levels(box, levels, inp.xc)
+    rng = np.random.default_rng(5)
+    vprev = xt0[:3] + 0.05 * rng.standard_normal((3, nf))
+    dmask = orc.dirichlet_flags(fb).astype(bool)
+    vprev[:, dmask] = xt0[:3][:, dmask]
+    n_in, n_out = (240, 81) if levels == 1 else (1024, 375)
+    ps = dn.random_params(n_in, 512, n_out, 8, seed=6)
+    ps[0][-1] = ps[0][-1] * 0.05
+    ps = r32(ps)
+    st = stepper.CorrectionStep(box, ns, ps, dtype=dtype, levels=levels, network="paper", indicator=True,
+                                theta=float("inf"))
+    out = st.run_numpy(inp.xc, vprev)
+    vp = out["vprev32"]
+    xt = orc.prolong_levels(box, levels, inp.xc)
+    r = orc.residual(fb, ns, xt, vp)
+    X = dn.paper_inputs(box, levels, xt, r)
+    Y = dn.forward(X, *ps)
+    d = orc.scatter_levels(box, levels, Y)
+    vcorr = xt[:3] + d
+    b = orc.rhs(fb, ns, vcorr)
+    bc = orc.restrict_levels(box, levels, b)
+    assert rel_l2(out["r"], r) <= 1e-5
+    for key, ref in (("Y", Y), ("d", d), ("bc", bc)):
+        e = rel_l2(out[key], ref)
+        say(f"  {key} rel-L2 {e:.2e}")
+        assert e <= tol, key
