@@ -305,6 +305,47 @@ def run_levels(dtype, steps, warmup):
             "fine_dof_per_s": 4 * st.nf / (t["ms"] * 1e-3)}
 
 
+def paper_network_params(n_in, hidden, n_out, depth=8, seed=0):
+    """Seeded parameters of the paper's network form: N(0, 1/fan_in) weights,
+    batch-normalisation gamma, beta and statistics near identity, the output
+    layer scaled down (a small correction)."""
+    rng = np.random.default_rng(seed)
+    dims = [n_in] + [hidden] * depth + [n_out]
+    Ws = [rng.standard_normal((dims[i], dims[i + 1])) / np.sqrt(dims[i]) for i in range(depth + 1)]
+    Ws[-1] *= 0.05
+    ga = [1.0 + 0.1 * rng.standard_normal(hidden) for _ in range(depth)]
+    be = [0.05 * rng.standard_normal(hidden) for _ in range(depth)]
+    mu = [0.05 * rng.standard_normal(hidden) for _ in range(depth)]
+    sd = [np.exp(0.1 * rng.standard_normal(hidden)) for _ in range(depth)]
+    return Ws, ga, be, mu, sd
+
+
+def run_paper_network(steps, warmup):
+    """The large channel's step with the paper's network form (240 inputs, 8
+    hidden layers of width 750 with folded batch normalisation and skip
+    connections, 81 outputs; BF16), indicator evaluated (threshold infinite),
+    seeded parameters; and the network's forward alone in TFLOP/s."""
+    import dnnmg_synth as syn
+    from paper_2307_14837_amd import _lib as L
+    from paper_2307_14837_amd import stepper
+
+    w = syn.cfg5()
+    inp = syn.step_inputs(w, seed=0)
+    ps = paper_network_params(240, 750, 81)
+    st = stepper.CorrectionStep(w.box, w.ns, ps, dtype="bf16", network="paper", indicator=True,
+                                theta=float("inf"))
+    st.load(inp.xc, inp.vprev)
+    t = time_graph(st, steps, warmup)
+    st.step()
+    tf = time_kernel(lambda: L.dnnmg_deepnet_forward(st.deep, st.np, st.X, st.ldx, st.Y), 10)
+    useful = 2 * (240 * 750 + 7 * 750 * 750 + 750 * 81) * st.np
+    return {"workload": w.name, "network": "paper form 240-750x8-81 (batch norm folded, skip connections)",
+            "dtype": "bf16", "indicator": True, "theta": None, "ms_per_step": t["ms"], "median_ms": t["median_ms"],
+            "patches_per_s": st.np / (t["ms"] * 1e-3), "forward_ms": tf,
+            "forward_tflops": useful / (tf * 1e-3) / 1e12,
+            "forward_frac_of_bf16_peak": useful / (tf * 1e-3) / 1e12 / BF16_MFMA_PEAK_TFLOPS}
+
+
 def step_kernel_times(st, reps=20):
     """Each launch of the headline step timed alone on the step's own buffers
     (after one step, so every input holds step data): ms per launch."""
@@ -651,6 +692,7 @@ def main():
             run_step(w, "bf16", sv, wv, params, shift, inv, indicator=True, theta=1.0, account=True)[0],
             run_step(w, "fp8", sv, wv, params, shift, inv)[0],
             run_levels("fp8", sv, wv),
+            run_paper_network(sv, wv),
             run_step(c2, "bf16", args.steps, args.warmup)[0],
             run_step(c2, "fp32", args.steps, args.warmup)[0],
             run_batched("bf16", sv, wv),
