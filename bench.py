@@ -60,6 +60,11 @@ def parse():
 
 
 RESIDUAL_SOURCES = ("residual.hip", "common.hpp", "common.hip")
+NETWORK_SOURCES = ("mlp.hip", "mlp.hpp", "lowp.hpp", "common.hpp", "common.hip")
+# the sources each counted entry point is built from (a PMC summary holds
+# for the sources it was taken on)
+ENTRY_SOURCES = {"dnnmg_residual_b": RESIDUAL_SOURCES, "dnnmg_prolong_residual_b": RESIDUAL_SOURCES,
+                 "dnnmg_patch_gather_forward": NETWORK_SOURCES}
 
 
 def src_hash(*names):
@@ -77,7 +82,7 @@ def traffic_from_profile(entry, workload):
         return None
     rec = json.load(open(path))
     k = rec.get("entries", {}).get(entry)
-    if not k or k.get("src_hash") != src_hash(*RESIDUAL_SOURCES):
+    if not k or k.get("src_hash") != src_hash(*ENTRY_SOURCES[entry]):
         return None
     return k.get("bytes_per_launch")
 
@@ -382,7 +387,8 @@ def roofline_of(kernel_ms, st, w):
         flop = flops.mlp_flops_per_patch(w.hidden) * npch
         peak = FP8_MFMA_PEAK_TFLOPS if st.dtype == 2 else BF16_MFMA_PEAK_TFLOPS
         return {"kernel": "dnnmg_patch_gather_forward", "bound": "mfma", "achieved": flop / (t * 1e-3) / 1e12,
-                "peak": peak, "unit": "TFLOP/s", "frac": flop / (t * 1e-3) / 1e12 / peak, "traffic": None,
+                "peak": peak, "unit": "TFLOP/s", "frac": flop / (t * 1e-3) / 1e12 / peak,
+                "traffic": traffic_from_profile("dnnmg_patch_gather_forward", w.name),
                 "avg_launch_ms": t, "flop_per_launch": flop}
     per_node = {"residual_b_indicator": flops.ALG_RESIDUAL_B_GENERAL_PER_NODE,
                 "prolong_residual_b": flops.ALG_PROLONG_RESIDUAL_B_PER_NODE,
@@ -559,11 +565,12 @@ def kernels_at_scale():
 
 def pmc_probe():
     """The headline step's indicator residual (general iterate against the
-    carried right-hand side) and prolongation + residual, three launches each
-    on step data, then a plain device copy of PMC_COPY_MIB MiB, for counter
-    runs.  The network has seeded weights (no training in this run): its
-    correction is nonzero on every patch, as the trained network's is, so
-    the residual kernels do the same work."""
+    carried right-hand side), prolongation + residual and fused gather + FP8
+    network, three launches each on step data, then a plain device copy of
+    PMC_COPY_MIB MiB, for counter runs.  The network has seeded weights (no
+    training in this run): its correction is nonzero on every patch, as the
+    trained network's is, so the residual kernels do the same work, and the
+    network's work does not depend on its weights."""
     import torch
 
     import dnnmg_synth as syn
@@ -572,7 +579,7 @@ def pmc_probe():
     w = syn.cfg5()
     # the step without the indicator fills every buffer the indicator's
     # residual reads, and launches none of the kernels counted below
-    st, _ = build_step(w, "bf16")
+    st, _ = build_step(w, "fp8")
     st.step()
     r2 = torch.empty_like(st.r)
     torch.cuda.synchronize()
@@ -580,6 +587,8 @@ def pmc_probe():
         L.dnnmg_residual_b(st.box, st.ns, st.xcorr, st.b, r2, st.ws_res)
     for _ in range(3):
         L.dnnmg_prolong_residual_b(st.box, st.ns, st.xc, st.b, st.xt, st.r)
+    for _ in range(3):
+        L.dnnmg_patch_gather_forward(st.box, st.net, st.xt, st.r, st.Y, st.shift, st.inv_scale)
     torch.cuda.synchronize()
     n = PMC_COPY_MIB * 2**20 // 4
     a = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -589,7 +598,7 @@ def pmc_probe():
         torch.neg(a, out=b)
     torch.cuda.synchronize()
     print(json.dumps({"pmc_probe": w.name, "copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n,
-                      "src_hash": src_hash(*RESIDUAL_SOURCES)}), flush=True)
+                      "src_hash": {e: src_hash(*f) for e, f in ENTRY_SOURCES.items()}}), flush=True)
 
 
 def profile_step(steps):

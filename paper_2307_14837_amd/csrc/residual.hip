@@ -368,7 +368,7 @@ struct ResTile {
 // in a fixed order (and, for the LPS corner terms, thread 8 P + j the 8
 // cells of owned patch P at corner j), so the sums need no atomics and the
 // result does not depend on scheduling.
-template <int MODE>
+template <int MODE, bool DELTA_MERGED = false>
 __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P, int bx, int by, int bz,
                                               const float *__restrict__ x, const float *__restrict__ vp,
                                               const float *__restrict__ fmid, float *__restrict__ out,
@@ -579,6 +579,71 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
 
     bool need = false, need_p = false;
     float xv[3][8]; // x~ at the Gauss points (both passes of the general residual)
+    // tile-wide LPS decisions, the cell's LPS denominator (stabparams) and
+    // pi v at its Gauss points (general residual)
+    bool any_v = false, any_p = false;
+    float den = 1.0f, piv[3][8], sx[2], sy[2], sz[2];
+    // LPS corner sums of the owned patches: owned patch P = tid / 8, corner
+    // j = tid % 8; cell of offset o = ox + 2 oy + 4 oz in patch (ppx, ppy,
+    // ppz) is ex = 2 ppx + 1 + ox
+    float corner[mode_general(MODE) ? 4 : 1] = {};
+    const bool pown = mode_general(MODE) && tid < 8 * T::NP;
+    const int pslot = tid >> 3, pj = tid & 7;
+    const int ppx = pslot % T::NPX, ppy = (pslot / T::NPX) % T::NPY, ppz = pslot / (T::NPX * T::NPY);
+    const int pcb = (2 * ppx + 1) + T::EX * ((2 * ppy + 1) + T::EY * (2 * ppz + 1));
+    // halo cells (ex == 0 etc.) belong to a neighbour's patch
+    const bool own_patch = ex >= 1 && ey >= 1 && ez >= 1;
+    // equation a's cell integrals (own vertices c, patch corners cr) -> LDS;
+    // the owners sum their 8 cells, the patch-corner threads the 8 cells of
+    // their patch, after one barrier
+    auto reduce_c = [&](const float c[8], const float cr[8], float wq, float &corner_out) -> float {
+        if (live)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                sCell[j * T::NCELL + ce] = c[j] * wq;
+                sCor[j * T::NCELL + ce] = own_patch ? cr[j] * wq : 0.0f;
+            }
+        __syncthreads();
+        float s = 0.0f;
+        if (owner)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) s += sCell[j * T::NCELL + nb + ncell(j)];
+        if (pown) {
+            float t = 0.0f;
+#pragma unroll
+            for (int o = 0; o < 8; ++o)
+                t += sCor[pj * T::NCELL + pcb + (o & 1) + T::EX * (((o >> 1) & 1) + T::EY * (o >> 2))];
+            corner_out = t;
+        }
+        __syncthreads();
+        return s;
+    };
+    // the cell's LPS denominator (stabparams: |v|_inf over its vertices), its
+    // offsets in the patch and pi v at its Gauss points
+    auto lps_setup = [&]() {
+        patch_coords(ox, sx);
+        patch_coords(oy, sy);
+        patch_coords(oz, sz);
+        if (live && (need || need_p)) {
+            float vmax2 = 0.0f;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                float u0 = sX[0 * T::SN + xb + xoff(j)], u1 = sX[1 * T::SN + xb + xoff(j)],
+                      u2 = sX[2 * T::SN + xb + xoff(j)];
+                vmax2 = fmaxf(vmax2, u0 * u0 + u1 * u1 + u2 * u2);
+            }
+            den = P.nu * (1.0f / (P.hT * P.hT)) + sqrtf(vmax2) / P.hT + P.inv_dt;
+        }
+        if (live && need) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                float w[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) w[j] = sX[d * T::SN + cb + coff(j)];
+                patch_val(w, sx, sy, sz, piv[d]);
+            }
+        }
+    };
     if constexpr (MODE == MODE_RHS) {
         float w[3][8], wv[3][8];
         if (live) {
@@ -665,9 +730,24 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
         }
 #pragma unroll
         for (int q = 0; q < 8; ++q) div[q] = 0.0f;
+        // Against a given right-hand side on one box (the indicator's and the
+        // fallback's form) the velocity LPS terms (delta) of a momentum
+        // equation are evaluated with its Galerkin terms: the own-vertex part
+        // is a flux -delta_T R v added to the viscous flux before the one
+        // transpose to vertex integrals, the patch-corner part is reduced in
+        // the same barrier phase.  The other forms, whose Galerkin pass holds
+        // more values, evaluate them in a pass of their own below (merged,
+        // they would spill registers).
+        if constexpr (mode_general(MODE)) {
+            any_v = __syncthreads_or(need);
+            any_p = __syncthreads_or(need_p);
+            if constexpr (DELTA_MERGED) lps_setup();
+        }
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            float acc[8];
+            float acc[8], cor[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) cor[j] = 0.0f;
             if (live) {
                 float w[8], tmp[8], g0[8], g1[8], g2[8], G0[8], G1[8], G2[8], F[8];
                 if constexpr (mode_has_vp(MODE)) {
@@ -721,9 +801,36 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
                     div[q] += ga[q];
                     Ga[q] += pq[q]; // + (p, d_a phi)
                 }
+                if constexpr (DELTA_MERGED) {
+                    if (need) {
+                        // -delta_T (R_a, v.grad phi - pi v.grad pi phi) with
+                        // R_a = v.grad v_a - pi v.grad pi v_a
+                        const float deltaT = P.delta0 / den;
+                        float ca[8], HX[4], HY[4], HZ[4], C0[8], C1[8], C2[8];
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) ca[j] = sX[a * T::SN + cb + coff(j)];
+                        patch_grad(ca, sx, sy, sz, ih0, ih1, ih2, HX, HY, HZ);
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) {
+                            const int qa = q & 1, qb = (q >> 1) & 1, qc = q >> 2;
+                            const float R = (xv[0][q] * g0[q] + xv[1][q] * g1[q] + xv[2][q] * g2[q]) -
+                                            (piv[0][q] * HX[qb + 2 * qc] + piv[1][q] * HY[qa + 2 * qc] +
+                                             piv[2][q] * HZ[qa + 2 * qb]);
+                            const float dR = deltaT * R;
+                            G0[q] -= dR * xv[0][q];
+                            G1[q] -= dR * xv[1][q];
+                            G2[q] -= dR * xv[2][q];
+                            C0[q] = dR * piv[0][q];
+                            C1[q] = dR * piv[1][q];
+                            C2[q] = dR * piv[2][q];
+                        }
+                        patch_integrate_grad(C0, C1, C2, sx, sy, sz, ih0, ih1, ih2, cor);
+                    }
+                }
                 integrate<true, true, true>(F, G0, G1, G2, ih0, ih1, ih2, acc);
             }
-            res[a] = reduce(acc, P.wq);
+            if (DELTA_MERGED && any_v) res[a] = reduce_c(acc, cor, P.wq, corner[a]);
+            else res[a] = reduce(acc, P.wq);
         }
         // continuity: -(div v, xi)
         {
@@ -735,135 +842,83 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
         }
     }
 
-    // ---- LPS terms of the cells that need them, one equation at a time ----
-    float corner[mode_general(MODE) ? 4 : 1] = {};
-    // owned patch P = tid / 8, corner j = tid % 8: its cells, in offset order
-    const bool pown = mode_general(MODE) && tid < 8 * T::NP;
-    const int pslot = tid >> 3, pj = tid & 7;
-    const int ppx = pslot % T::NPX, ppy = (pslot / T::NPX) % T::NPY, ppz = pslot / (T::NPX * T::NPY);
-    // cell of offset o = ox + 2 oy + 4 oz in patch (ppx, ppy, ppz): ex = 2 ppx + 1 + ox
-    const int pcb = (2 * ppx + 1) + T::EX * ((2 * ppy + 1) + T::EY * (2 * ppz + 1));
+    // ---- LPS terms not taken with the Galerkin pass ----
     bool any_lps = false;
     if constexpr (mode_general(MODE)) {
-        const bool any_v = __syncthreads_or(need), any_p = __syncthreads_or(need_p);
         any_lps = any_v || any_p;
-        if (any_lps) {
-            // the cell's stabilisation parameter (stabparams: |v|_inf over the
-            // vertices) and pi v at the Gauss points, shared by the equations
-            // (v there is the first pass's)
-            float den = 1.0f, piv[3][8], sx[2], sy[2], sz[2];
-            patch_coords(ox, sx);
-            patch_coords(oy, sy);
-            patch_coords(oz, sz);
-            if (live && (need || need_p)) {
-                float vmax2 = 0.0f;
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    float u0 = sX[0 * T::SN + xb + xoff(j)], u1 = sX[1 * T::SN + xb + xoff(j)],
-                          u2 = sX[2 * T::SN + xb + xoff(j)];
-                    vmax2 = fmaxf(vmax2, u0 * u0 + u1 * u1 + u2 * u2);
-                }
-                den = P.nu * (1.0f / (P.hT * P.hT)) + sqrtf(vmax2) / P.hT + P.inv_dt;
-            }
-            if (live && need) {
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    float w[8];
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) w[j] = sX[d * T::SN + cb + coff(j)];
-                    patch_val(w, sx, sy, sz, piv[d]);
-                }
-            }
-            for (int a = 0; a < 4; ++a) {
-                // equations whose terms vanish on every cell of the tile are
-                // skipped (the decision is uniform over the workgroup)
-                if ((a < 3 && !any_v) || (a == 3 && !any_p)) continue;
+        if constexpr (!DELTA_MERGED)
+            if (any_lps) lps_setup();
+        if (!DELTA_MERGED && any_v) {
+            for (int a = 0; a < 3; ++a) {
+                // R_a = v.grad v_a - pi v . grad pi v_a, tested with
+                // v.grad phi (own vertices) and pi v . grad pi phi (patch
+                // corners)
                 float acc[8], cor[8];
 #pragma unroll
                 for (int j = 0; j < 8; ++j) acc[j] = cor[j] = 0.0f;
-                if (live && (a < 3 ? need : need_p)) {
-                    if (a < 3) {
-                        // R_a = v.grad v_a - pi v . grad pi v_a, tested with
-                        // v.grad phi (own vertices) and pi v . grad pi phi
-                        // (patch corners)
-                        const float deltaT = P.delta0 / den;
-                        float ca[8], va[8];
-#pragma unroll
-                        for (int j = 0; j < 8; ++j) {
-                            ca[j] = sX[a * T::SN + cb + coff(j)];
-                            va[j] = sX[a * T::SN + xb + xoff(j)];
-                        }
-                        float tmp[8], g0[8], g1[8], g2[8], HX[4], HY[4], HZ[4];
-                        eval_vg(va, ih0, ih1, ih2, tmp, g0, g1, g2);
-                        patch_grad(ca, sx, sy, sz, ih0, ih1, ih2, HX, HY, HZ);
-                        float C0[8], C1[8], C2[8];
-#pragma unroll
-                        for (int q = 0; q < 8; ++q) {
-                            const int qa = q & 1, qb = (q >> 1) & 1, qc = q >> 2;
-                            float R = (xv[0][q] * g0[q] + xv[1][q] * g1[q] + xv[2][q] * g2[q]) -
-                                      (piv[0][q] * HX[qb + 2 * qc] + piv[1][q] * HY[qa + 2 * qc] +
-                                       piv[2][q] * HZ[qa + 2 * qb]);
-                            float dR = deltaT * R;
-                            g0[q] = -dR * xv[0][q];
-                            g1[q] = -dR * xv[1][q];
-                            g2[q] = -dR * xv[2][q];
-                            C0[q] = dR * piv[0][q];
-                            C1[q] = dR * piv[1][q];
-                            C2[q] = dR * piv[2][q];
-                            tmp[q] = 0.0f;
-                        }
-                        integrate<true, true, true>(tmp, g0, g1, g2, ih0, ih1, ih2, acc);
-                        patch_integrate_grad(C0, C1, C2, sx, sy, sz, ih0, ih1, ih2, cor);
-                    } else {
-                        // -alpha_T (grad(p - pi p), grad(xi - pi xi))
-                        const float alphaT = P.alpha0 / den;
-                        float w[8], pw[8];
-#pragma unroll
-                        for (int j = 0; j < 8; ++j) w[j] = sX[3 * T::SN + cb + coff(j)];
-                        pi_vertices(w, ox, oy, oz, pw);
-#pragma unroll
-                        for (int j = 0; j < 8; ++j) w[j] = sX[3 * T::SN + xb + xoff(j)] - pw[j];
-                        float tmp[8], g0[8], g1[8], g2[8];
-                        eval_vg(w, ih0, ih1, ih2, tmp, g0, g1, g2);
-#pragma unroll
-                        for (int q = 0; q < 8; ++q) {
-                            g0[q] *= -alphaT;
-                            g1[q] *= -alphaT;
-                            g2[q] *= -alphaT;
-                            tmp[q] = 0.0f;
-                        }
-                        integrate<true, true, true>(tmp, g0, g1, g2, ih0, ih1, ih2, acc);
-                        float dv[8];
-#pragma unroll
-                        for (int j = 0; j < 8; ++j) dv[j] = -acc[j];
-                        pi_transpose(dv, ox, oy, oz, cor);
-                    }
-                }
-                // own-vertex parts to the nodes, corner parts to the owned
-                // patches (halo cells ex == 0 etc. belong to a neighbour's patch)
-                const bool own_patch = ex >= 1 && ey >= 1 && ez >= 1;
-                if (live)
+                if (live && need) {
+                    const float deltaT = P.delta0 / den;
+                    float ca[8], va[8];
 #pragma unroll
                     for (int j = 0; j < 8; ++j) {
-                        sCell[j * T::NCELL + ce] = acc[j] * P.wq;
-                        sCor[j * T::NCELL + ce] = own_patch ? cor[j] * P.wq : 0.0f;
+                        ca[j] = sX[a * T::SN + cb + coff(j)];
+                        va[j] = sX[a * T::SN + xb + xoff(j)];
                     }
-                __syncthreads();
-                if (owner) {
-                    float s = 0.0f;
+                    float tmp[8], g0[8], g1[8], g2[8], HX[4], HY[4], HZ[4];
+                    eval_vg(va, ih0, ih1, ih2, tmp, g0, g1, g2);
+                    patch_grad(ca, sx, sy, sz, ih0, ih1, ih2, HX, HY, HZ);
+                    float C0[8], C1[8], C2[8];
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) s += sCell[j * T::NCELL + nb + ncell(j)];
-                    res[a] += s;
+                    for (int q = 0; q < 8; ++q) {
+                        const int qa = q & 1, qb = (q >> 1) & 1, qc = q >> 2;
+                        float R = (xv[0][q] * g0[q] + xv[1][q] * g1[q] + xv[2][q] * g2[q]) -
+                                  (piv[0][q] * HX[qb + 2 * qc] + piv[1][q] * HY[qa + 2 * qc] +
+                                   piv[2][q] * HZ[qa + 2 * qb]);
+                        float dR = deltaT * R;
+                        g0[q] = -dR * xv[0][q];
+                        g1[q] = -dR * xv[1][q];
+                        g2[q] = -dR * xv[2][q];
+                        C0[q] = dR * piv[0][q];
+                        C1[q] = dR * piv[1][q];
+                        C2[q] = dR * piv[2][q];
+                        tmp[q] = 0.0f;
+                    }
+                    integrate<true, true, true>(tmp, g0, g1, g2, ih0, ih1, ih2, acc);
+                    patch_integrate_grad(C0, C1, C2, sx, sy, sz, ih0, ih1, ih2, cor);
                 }
-                if (pown) {
-                    float s = 0.0f;
-#pragma unroll
-                    for (int o = 0; o < 8; ++o)
-                        s += sCor[pj * T::NCELL + pcb + (o & 1) + T::EX * (((o >> 1) & 1) + T::EY * (o >> 2))];
-                    corner[a] = s;
-                }
-                __syncthreads();
+                res[a] += reduce_c(acc, cor, P.wq, corner[a]);
             }
+        }
+        if (any_p) {
+            // -alpha_T (grad(p - pi p), grad(xi - pi xi)): own-vertex and
+            // patch-corner parts
+            float acc[8], cor[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc[j] = cor[j] = 0.0f;
+            if (live && need_p) {
+                const float alphaT = P.alpha0 / den;
+                float w[8], pw[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) w[j] = sX[3 * T::SN + cb + coff(j)];
+                pi_vertices(w, ox, oy, oz, pw);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) w[j] = sX[3 * T::SN + xb + xoff(j)] - pw[j];
+                float tmp[8], g0[8], g1[8], g2[8];
+                eval_vg(w, ih0, ih1, ih2, tmp, g0, g1, g2);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    g0[q] *= -alphaT;
+                    g1[q] *= -alphaT;
+                    g2[q] *= -alphaT;
+                    tmp[q] = 0.0f;
+                }
+                integrate<true, true, true>(tmp, g0, g1, g2, ih0, ih1, ih2, acc);
+                float dv[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) dv[j] = -acc[j];
+                pi_transpose(dv, ox, oy, oz, cor);
+            }
+            res[3] += reduce_c(acc, cor, P.wq, corner[3]);
         }
     }
 
@@ -978,8 +1033,8 @@ __global__ void __launch_bounds__(ResTile<MODE>::NT, ResTile<MODE>::WAVES_PER_SI
         int c[3];
         tile_of(t, G, F, c);
         const int tl = c[0] + G[0] * (c[1] + G[1] * c[2]);
-        residual_tile<MODE>(m, P, c[0], c[1], c[2], x, vp, fmid, out, aux, mode_general(MODE) ? tflag + tl : nullptr,
-                            xc, xt_out);
+        residual_tile<MODE, MODE == MODE_RESB && !STRIDED>(m, P, c[0], c[1], c[2], x, vp, fmid, out, aux,
+                                                            mode_general(MODE) ? tflag + tl : nullptr, xc, xt_out);
         if constexpr (STRIDED) __syncthreads(); // the tile's LDS reads are done before the next stages
     }
 }

@@ -27,7 +27,8 @@ import json
 from collections import defaultdict
 
 ENTRY_KERNELS = {"dnnmg_residual_b": ("k_residual<4, false>", "k_lps_corners"),
-                 "dnnmg_prolong_residual_b": ("k_residual<3, false>",)}
+                 "dnnmg_prolong_residual_b": ("k_residual<3, false>",),
+                 "dnnmg_patch_gather_forward": ("k_mlp_fwd<2, 512",)}
 COPY_KERNEL = "neg"
 
 
@@ -119,7 +120,8 @@ def main():
             ks[kname] = {"fetch_kib": fk, "write_kib": wk}
             fb += fk * 1024.0 * f_scale
             wb += wk * 1024.0 * w_scale
-        entries[entry] = {"src_hash": probe["src_hash"], "kernels": ks, "fetch_bytes": fb, "write_bytes": wb,
+        h = probe["src_hash"]
+        entries[entry] = {"src_hash": h[entry] if isinstance(h, dict) else h, "kernels": ks, "fetch_bytes": fb, "write_bytes": wb,
                           "bytes_per_launch": fb + wb}
     out = {"workload": probe["pmc_probe"], "command": a.command,
            "copy": {"bytes_read": probe["copy_bytes_read"], "bytes_written": probe["copy_bytes_written"],
