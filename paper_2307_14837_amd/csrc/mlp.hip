@@ -103,6 +103,12 @@ template <> struct Frag<KF32> { using T = float; };
 template <> struct Frag<KBF16> { using T = u32x4; };  // 8 bf16
 template <> struct Frag<KFP8> { using T = i32x8; };   // 32 fp8
 
+// largest divisor of n that is at most cap
+__host__ __device__ constexpr int unroll_divisor(int n, int cap) {
+    int d = cap;
+    while (d > 1 && n % d != 0) --d;
+    return d;
+}
 __host__ __device__ constexpr int frag_bytes(int k) { return k == KF32 ? 4 : (k == KBF16 ? 16 : 32); }
 
 template <int K>
@@ -115,32 +121,62 @@ __device__ __forceinline__ f32x4 mfma(typename Frag<K>::T a, typename Frag<K>::T
         return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 0, 0, 0, 127, 0, 127);
 }
 
+// A weight fragment through a buffer resource: byte offset voff (the lane's
+// term, one VGPR) plus soff (wave-uniform, an SGPR), so the addresses of a
+// layer's fragments take no vector registers of their own.  Reads past the
+// resource's size return zero.
+template <int K>
+__device__ __forceinline__ typename Frag<K>::T load_frag(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    if constexpr (K == KF32) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    } else if constexpr (K == KBF16) {
+        return __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+    } else {
+        const u32x4 lo = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+        const u32x4 hi = __builtin_amdgcn_raw_buffer_load_b128(r, voff + 16, soff, 0);
+        return i32x8{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
+    }
+}
+
 // Activations v[0..3] of units 16 ot + 4 g + e of patch p (lane 16 g + p) of
-// patch tile t into the next layer's LDS fragments (kind KN, NCHN chunks);
-// see kslot_to_input for the slot order.
+// patch tile t into the next layer's LDS fragments (kind KN: FP32 or BF16,
+// NCHN chunks); see kslot_to_input for the slot order.
 template <int KN, int NCHN>
-__device__ __forceinline__ void put_act(unsigned char *out, int t, int ot, int lane, const float v[4], float qinv) {
+__device__ __forceinline__ void put_act(unsigned char *out, int t, int ot, int lane, const float v[4]) {
+    static_assert(KN == KF32 || KN == KBF16, "FP8 activations go through put_fp8");
     if constexpr (KN == KF32) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) ((float *)out)[(t * NCHN + 4 * ot + e) * 64 + lane] = v[e];
-    } else if constexpr (KN == KBF16) {
+    } else {
         uint2 w = make_uint2(pack_bf16x2_hw(v[0], v[1]), pack_bf16x2_hw(v[2], v[3]));
         *(uint2 *)(out + ((t * NCHN + (ot >> 1)) * 64 + lane) * 16 + 8 * (ot & 1)) = w;
-    } else {
-        // hardware E4M3 conversion (round to nearest even; the same bits as
-        // f32_to_e4m3 for finite inputs within +-448); inputs are clamped to
-        // +-448 first, as the software encoder saturates, and NaN passes
-        float q[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const float x = v[e] * qinv;
-            q[e] = x != x ? x : fminf(fmaxf(x, -448.0f), 448.0f);
-        }
-        int w = __builtin_amdgcn_cvt_pk_fp8_f32(q[0], q[1], 0, false);
-        w = __builtin_amdgcn_cvt_pk_fp8_f32(q[2], q[3], w, true);
-        *(int *)(out + ((t * NCHN + (ot >> 3)) * 64 + lane) * 32 + 4 * (ot & 7)) = w;
     }
 }
+
+// FP8 codes of qinv tanh z = qinv (1 - 2 r) for units 16 ot + 4 g + e of
+// patch p (lane 16 g + p) of patch tile t, from r = 1 / (exp(2 z) + 1), into
+// the next layer's LDS fragments (NCHN chunks), with the hardware E4M3
+// conversion (round to nearest even).  Since 0 <= r <= 1 the codes lie in
+// [-qinv, qinv]; SAT (qinv above 448, the largest E4M3 value) clamps them to
+// +-448 first, as the software encoder saturates.  NaN passes either way.
+template <int NCHN, bool SAT>
+__device__ __forceinline__ void put_fp8(unsigned char *out, int t, int ot, int lane, const float r[4], float qinv) {
+    float q[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const float x = fmaf(-2.0f * qinv, r[e], qinv);
+        q[e] = SAT ? (x != x ? x : fminf(fmaxf(x, -448.0f), 448.0f)) : x;
+    }
+    int w = __builtin_amdgcn_cvt_pk_fp8_f32(q[0], q[1], 0, false);
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(q[2], q[3], w, true);
+    *(int *)(out + ((t * NCHN + (ot >> 3)) * 64 + lane) * 32 + 4 * (ot & 7)) = w;
+}
+
+// Barrier for the LDS hand-offs between the layers of a tile: it waits for
+// this wave's LDS operations only, so weight loads and output stores stay in
+// flight across it (a full __syncthreads also drains the vector memory
+// counter).
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 // One dense layer for the tile: acc = W^T B over the wave's output tiles,
 // then bias and (unless LAST) tanh into the next layer's fragments, or (LAST)
@@ -155,31 +191,44 @@ __device__ __forceinline__ void layer(const typename Frag<K>::T *__restrict__ Wl
     constexpr int NCHN = LAST ? 1 : H / (4 * kind_E(KN));
     const int g = lane >> 4, p = lane & 15;
     f32x4 acc[OTW][PT];
-#pragma unroll
-    for (int i = 0; i < OTW; ++i)
-#pragma unroll
-        for (int t = 0; t < PT; ++t) acc[i][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // UNROLL K chunks per step: the weight loads of a step are issued
-    // together (8-wave tiles have few output tiles per wave, so a whole
-    // layer's weight fragments fit in registers and are requested at once)
-    constexpr int UNROLL = (NW == 8 && H <= 256) ? NCH : 2;
+    // UNROLL K chunks per step: the weight and activation fragments of a
+    // step are requested together.  A step holds OTW + PT fragments per K
+    // chunk; UNROLL is the largest divisor of NCH (at most 8) whose fragments
+    // fit in what the accumulators leave of a 192-register budget, and at
+    // least 2 where NCH is even.
+    constexpr int FRAG_REGS = frag_bytes(K) / 4;
+    constexpr int STEP_REGS = (OTW + PT) * FRAG_REGS;
+    constexpr int FIT = (192 - 4 * OTW * PT) / STEP_REGS;
+    constexpr int U0 = unroll_divisor(NCH, FIT < 1 ? 1 : (FIT > 8 ? 8 : FIT));
+    constexpr int UNROLL = (U0 < 2 && NCH % 2 == 0) ? 2 : U0;
+    constexpr int FB = frag_bytes(K);
+    const __amdgpu_buffer_rsrc_t wr =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<FA *>(Wl), (short)0, NCH * NTILES * 64 * FB, 0x00020000);
+    const int wave_u = __builtin_amdgcn_readfirstlane(wave);
     // products over the wave's first NT output tiles; the tile test sits
     // outside the K loop, so a step's weight loads carry no branch and are
     // requested together
     auto products = [&](auto nt) {
         constexpr int NT = decltype(nt)::value;
-#pragma unroll UNROLL
-        for (int kc = 0; kc < NCH; ++kc) {
+        auto chunk = [&](int kc, auto first) {
             FA b[PT];
 #pragma unroll
             for (int t = 0; t < PT; ++t) b[t] = ((const FA *)in)[(t * NCH + kc) * 64 + lane];
 #pragma unroll
             for (int i = 0; i < NT; ++i) {
-                FA a = Wl[((int64_t)kc * NTILES + wave + NW * i) * 64 + lane];
+                FA a = load_frag<K>(wr, lane * FB, (kc * NTILES + wave_u + NW * i) * 64 * FB);
 #pragma unroll
-                for (int t = 0; t < PT; ++t) acc[i][t] = mfma<K>(a, b[t], acc[i][t]);
+                for (int t = 0; t < PT; ++t)
+                    acc[i][t] = mfma<K>(a, b[t], decltype(first)::value ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[i][t]);
             }
-        }
+        };
+        // the accumulators start from zero
+#pragma unroll
+        for (int i = 0; i < OTW; ++i)
+#pragma unroll
+            for (int t = 0; t < PT; ++t) acc[i][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll UNROLL
+        for (int kc = 0; kc < NCH; ++kc) chunk(kc, std::false_type{});
     };
     if (NTILES % NW == 0 || wave + NW * (OTW - 1) < NTILES) products(std::integral_constant<int, OTW>{});
     else if constexpr (OTW > 1) products(std::integral_constant<int, OTW - 1>{});
@@ -214,42 +263,63 @@ __device__ __forceinline__ void layer(const typename Frag<K>::T *__restrict__ Wl
             const float sc = K == KF32 ? scale : scale * K2;
             const float bv[4] = {K == KF32 ? bb.x : bb.x * K2, K == KF32 ? bb.y : bb.y * K2,
                                  K == KF32 ? bb.z : bb.z * K2, K == KF32 ? bb.w : bb.w * K2};
+            auto tail = [&](auto satc) {
+                // SAT: the FP8 codes are clamped (activation scale above 448)
 #pragma unroll
-            for (int t = 0; t < PT; ++t) {
-                float v[4];
+                for (int t = 0; t < PT; ++t) {
+                    float v[4];
+                    if constexpr (KN == KFP8) {
+                        // FP8 next layer: its codes straight from r (one FMA)
+                        float r[4];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const float z = acc[i][t][e] * sc + bv[e];
-                    if constexpr (K == KF32) v[e] = tanhf(z);
-                    else v[e] = 1.0f - 2.0f * __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(z) + 1.0f);
-                }
-                if constexpr (SKIP) {
-                    // skip connection: + the layer's own input at these units
-                    // (an H-wide input of the same kind has the output's layout)
-                    static_assert(K == KN && (K == KF32 || K == KBF16), "skip needs equal FP32/BF16 layouts");
-                    if constexpr (KN == KF32) {
+                        for (int e = 0; e < 4; ++e)
+                            r[e] = __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(acc[i][t][e] * sc + bv[e]) + 1.0f);
+                        put_fp8<NCHN, decltype(satc)::value>(out, t, ot, lane, r, qinv);
+                        if (saved)
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) v[e] += ((const float *)in)[(t * NCHN + 4 * ot + e) * 64 + lane];
+                            for (int e = 0; e < 4; ++e) v[e] = 1.0f - 2.0f * r[e];
                     } else {
-                        const uint2 w = *(const uint2 *)(in + ((t * NCHN + (ot >> 1)) * 64 + lane) * 16 + 8 * (ot & 1));
-                        v[0] += bf16_to_f32((uint16_t)(w.x & 0xffffu));
-                        v[1] += bf16_to_f32((uint16_t)(w.x >> 16));
-                        v[2] += bf16_to_f32((uint16_t)(w.y & 0xffffu));
-                        v[3] += bf16_to_f32((uint16_t)(w.y >> 16));
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const float z = acc[i][t][e] * sc + bv[e];
+                            if constexpr (K == KF32) v[e] = tanhf(z);
+                            else v[e] = 1.0f - 2.0f * __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(z) + 1.0f);
+                        }
+                        if constexpr (SKIP) {
+                            // skip connection: + the layer's own input at these units
+                            // (an H-wide input of the same kind has the output's layout)
+                            static_assert(K == KN && (K == KF32 || K == KBF16), "skip needs equal FP32/BF16 layouts");
+                            if constexpr (KN == KF32) {
+#pragma unroll
+                                for (int e = 0; e < 4; ++e) v[e] += ((const float *)in)[(t * NCHN + 4 * ot + e) * 64 + lane];
+                            } else {
+                                const uint2 w = *(const uint2 *)(in + ((t * NCHN + (ot >> 1)) * 64 + lane) * 16 + 8 * (ot & 1));
+                                v[0] += bf16_to_f32((uint16_t)(w.x & 0xffffu));
+                                v[1] += bf16_to_f32((uint16_t)(w.x >> 16));
+                                v[2] += bf16_to_f32((uint16_t)(w.y & 0xffffu));
+                                v[3] += bf16_to_f32((uint16_t)(w.y >> 16));
+                            }
+                        }
+                        put_act<KN, NCHN>(out, t, ot, lane, v);
+                    }
+                    if (saved) {
+                        int64_t row = base + 16 * t + p;
+                        if (row < n) {
+                            int64_t idx = save_off + row * H + 16 * ot + 4 * g;
+                            if (save_bytes == 4)
+                                *(float4 *)((float *)saved + idx) = make_float4(v[0], v[1], v[2], v[3]);
+                            else
+                                *(uint2 *)((uint16_t *)saved + idx) =
+                                    make_uint2(pack_bf16x2_hw(v[0], v[1]), pack_bf16x2_hw(v[2], v[3]));
+                        }
                     }
                 }
-                put_act<KN, NCHN>(out, t, ot, lane, v, qinv);
-                if (saved) {
-                    int64_t row = base + 16 * t + p;
-                    if (row < n) {
-                        int64_t idx = save_off + row * H + 16 * ot + 4 * g;
-                        if (save_bytes == 4)
-                            *(float4 *)((float *)saved + idx) = make_float4(v[0], v[1], v[2], v[3]);
-                        else
-                            *(uint2 *)((uint16_t *)saved + idx) =
-                                make_uint2(pack_bf16x2_hw(v[0], v[1]), pack_bf16x2_hw(v[2], v[3]));
-                    }
-                }
+            };
+            if constexpr (KN == KFP8) {
+                if (qinv > 448.0f) tail(std::true_type{});
+                else tail(std::false_type{});
+            } else {
+                tail(std::false_type{});
             }
         }
     }
@@ -315,20 +385,35 @@ __device__ __forceinline__ void put_input(unsigned char *buf, int pl, int col, f
 // Operator Q of eq. (defQ) with the standardisation, straight into the
 // layer-1 fragments: input column 27 c + iota of patch (I,J,K) is field c of
 // [u, v, w, r_u, r_v, r_w] at local node iota = a + 3 b + 9 c'; columns
-// 162..164 are the coarse cell sizes, 165..191 zero.
+// 162..164 are the coarse cell sizes, 165..191 zero.  Lanes run over the
+// patches of the tile and waves over the local nodes: consecutive patches
+// of a row of the coarse mesh read fine nodes two apart, so a wave's load of
+// one field touches a few cache lines, and the standardisation constants of
+// a wave's node are the same for all its lanes.
 template <int K1, int NCH0, int PT, int NTHR>
 __device__ __forceinline__ void stage_gather(const Mesh &m, const float *__restrict__ xt, const float *__restrict__ r,
                                              const float *__restrict__ shift, const float *__restrict__ inv,
                                              int64_t base, int64_t n, unsigned char *buf, int tid) {
-    for (int it = tid; it < 16 * PT * 27; it += NTHR) {
-        const int pl = it / 27, iota = it - 27 * pl;
-        const int64_t row = base + pl;
+    constexpr int NPL = 16 * PT, STEP = NTHR / NPL;
+    static_assert(NTHR % NPL == 0, "a thread keeps one patch of the tile");
+    const int pl = tid % NPL;
+    const int64_t row = base + pl;
+    const bool ok = row < n;
+    int I = 0, J = 0, K = 0;
+    if (ok) {
+        const uint32_t JK = fdiv((uint32_t)row, m.px);
+        I = (int)((uint32_t)row - JK * m.n[0]);
+        K = (int)fdiv(JK, m.py);
+        J = (int)(JK - (uint32_t)K * m.n[1]);
+    }
+    // two of a thread's nodes are requested together (all of them would
+    // spill registers in the widest kernels)
+#pragma unroll 2
+    for (int q = 0; q < (27 + STEP - 1) / STEP; ++q) {
+        const int iota = tid / NPL + STEP * q;
+        if (iota >= 27) break;
         float v[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        if (row < n) {
-            uint32_t JK = fdiv((uint32_t)row, m.px);
-            const int I = (int)((uint32_t)row - JK * m.n[0]);
-            const int K = (int)fdiv(JK, m.py);
-            const int J = (int)(JK - (uint32_t)K * m.n[1]);
+        if (ok) {
             const int a = iota % 3, b = (iota / 3) % 3, c = iota / 9;
             const int i = wrap(2 * I + a, m.nf[0], m.per[0]);
             const int j = wrap(2 * J + b, m.nf[1], m.per[1]);
@@ -393,9 +478,15 @@ __global__ void __launch_bounds__((FwdShape<DT, H, PT, J>::NTHR))
     using F3 = typename Frag<S::K3>::T;
     __shared__ __attribute__((aligned(16))) unsigned char smem[S::BUF0 + S::BUF1];
     unsigned char *buf0 = smem, *buf1 = smem + S::BUF0;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int sbytes = DT == DNNMG_F32 ? 4 : 2;
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        // the thread index is read anew for each tile (the empty asm hides
+        // that it does not change), so the per-lane addresses of the layers
+        // are formed where they are used rather than held in registers
+        // across the whole loop
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        const int lane = tid & 63, wave = tid >> 6;
         int64_t base, n;
         float *Y = Y_all;
         if constexpr (GATHER) {
@@ -411,17 +502,17 @@ __global__ void __launch_bounds__((FwdShape<DT, H, PT, J>::NTHR))
             base = tile * 16 * PT;
             stage_rows<S::K1, S::NCH0, PT, S::NTHR, S::IO::INP>(Xv, ldx, base, n, buf0, tid);
         }
-        __syncthreads();
+        lds_barrier();
         layer<S::K1, S::K2, H / 16, S::NCH0, PT, false, H, S::NW>((const F1 *)W0, b0, buf0, buf1, 1.0f, q1inv, wave,
                                                           lane, base, n, Y, saved, 0, sbytes);
-        __syncthreads();
+        lds_barrier();
         layer<S::K2, S::K3, H / 16, S::NCH1, PT, false, H, S::NW>((const F2 *)W1, b1, buf1, buf0, s1, 1.0f, wave, lane,
                                                           base, n, Y, saved, n * H, sbytes);
-        __syncthreads();
+        lds_barrier();
         layer<S::K3, S::K3, S::IO::OUTP / 16, S::NCH2, PT, true, H, S::NW, NO>((const F3 *)W2, b2, buf0, buf1, 1.0f,
                                                                                 1.0f, wave, lane, base, n, Y, nullptr,
                                                                                 0, sbytes);
-        __syncthreads();
+        lds_barrier();
         {
             // the tile's rows are contiguous in Y
             const int cnt = (int)((n - base < 16 * PT ? n - base : 16 * PT) * NO);
@@ -434,7 +525,7 @@ __global__ void __launch_bounds__((FwdShape<DT, H, PT, J>::NTHR))
             }
             for (int q = q0 + tid; q < cnt; q += S::NTHR) yd[q] = ys[q];
         }
-        __syncthreads();
+        lds_barrier();
     }
 }
 
@@ -475,21 +566,21 @@ __global__ void __launch_bounds__((DeepShape<DT, HP, PT, J>::NTHR))
         const int64_t base = tile * 16 * PT;
         unsigned char *cur = smem, *nxt = smem + S::BUF;
         stage_rows<S::K, S::NCH0, PT, S::NTHR, S::INP>(Xv, ldx, base, n, cur, tid);
-        __syncthreads();
+        lds_barrier();
         layer<S::K, S::K, HP / 16, S::NCH0, PT, false, HP, S::NW>((const F *)a.W[0], a.b[0], cur, nxt, 1.0f, 1.0f,
                                                                   wave, lane, base, n, Y, nullptr, 0, 0);
-        __syncthreads();
+        lds_barrier();
         for (int l = 1; l < depth; ++l) {
             unsigned char *t = cur;
             cur = nxt;
             nxt = t;
             layer<S::K, S::K, HP / 16, S::NCHH, PT, false, HP, S::NW, S::NO, true>(
                 (const F *)a.W[l], a.b[l], cur, nxt, 1.0f, 1.0f, wave, lane, base, n, Y, nullptr, 0, 0);
-            __syncthreads();
+            lds_barrier();
         }
         layer<S::K, S::K, S::OUTP / 16, S::NCHH, PT, true, HP, S::NW, S::NO>(
             (const F *)a.W[depth], a.b[depth], nxt, cur, 1.0f, 1.0f, wave, lane, base, n, Y, nullptr, 0, 0);
-        __syncthreads();
+        lds_barrier();
         {
             const int cnt = (int)((n - base < 16 * PT ? n - base : 16 * PT) * S::NO);
             const float *ys = (const float *)cur;
@@ -501,7 +592,7 @@ __global__ void __launch_bounds__((DeepShape<DT, HP, PT, J>::NTHR))
             }
             for (int q = q0 + tid; q < cnt; q += S::NTHR) yd[q] = ys[q];
         }
-        __syncthreads();
+        lds_barrier();
     }
 }
 
