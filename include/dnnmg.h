@@ -534,6 +534,56 @@ int dnnmg_graph_capture_end(void *stream, dnnmg_graph **graph);
 int dnnmg_graph_replay(const dnnmg_graph *graph, void *stream);
 int dnnmg_graph_destroy(dnnmg_graph *graph);
 
+/* GPU-resident coarse step (Alg. 1, the coarse problem of a time step;
+ * Sec. 2.4): A(x^L) = b^L on the coarse mesh of `box` (box->n cells per
+ * axis, all even and >= 4), the Crank-Nicolson operator of eq. (disc:ns) with its
+ * LPS terms, solved by `newton_its` inexact Newton steps.  Each Newton
+ * correction is one cycle of FGMRES(krylov_dim) on J dx = b - A(x),
+ * right-preconditioned by one geometric multigrid V-cycle over `levels`
+ * meshes (the coarse mesh and its halvings while every axis keeps an even
+ * count of at least 4 cells; 0: all of them) whose smoother is the coupled patch-Vanka step (the 108 x 108
+ * velocity-pressure systems of the 2 x 2 x 2-cell patches, linearised at
+ * the Newton iterate, damped by omega, pre_sweeps before and post_sweeps
+ * after the coarse-grid correction, coarsest_sweeps on the last mesh).
+ * J is applied matrix-free: J z = (A(x + eps z) - A(x)) / eps with
+ * eps = fd_eta (rms(x) + fd_eta) / rms(z) on each mesh.  The residual and
+ * the smoother run in FP32, the iterate, norms and FGMRES's Hessenberg
+ * system in FP64.  Every count is fixed, so a solve can be recorded into a
+ * graph. */
+typedef struct dnnmg_coarse_opts {
+    int32_t newton_its;      /* >= 1 */
+    int32_t krylov_dim;      /* 1 .. DNNMG_COARSE_MAX_KRYLOV */
+    int32_t levels;          /* 0 or >= 1 */
+    int32_t pre_sweeps;      /* >= 1 */
+    int32_t post_sweeps;     /* >= 0 */
+    int32_t coarsest_sweeps; /* >= 1 */
+    double omega;            /* Vanka damping, (0, 2) */
+    double fd_eta;           /* > 0 */
+} dnnmg_coarse_opts;
+#define DNNMG_COARSE_MAX_KRYLOV 16
+
+/* Multigrid levels a solve on `box` with `opts` uses (>= 1), or a negative
+ * error code (an odd or too small cell count, invalid options). */
+int dnnmg_coarse_levels(const dnnmg_box *box, const dnnmg_coarse_opts *opts);
+/* Bytes of device workspace of dnnmg_coarse_solve, _jv and _vcycle. */
+size_t dnnmg_coarse_workspace(const dnnmg_box *box, const dnnmg_coarse_opts *opts);
+/* x (FP64 [4][n_coarse], in/out: start and result; its Dirichlet velocity
+ * entries are kept), b (FP64 [4][n_coarse], the right-hand side, e.g.
+ * dnnmg_restrict of the fine Rhs with its Dirichlet velocity rows zero).
+ * res_norms (device FP64 [newton_its + 1], or NULL) receives ||b - A(x_k)||_2
+ * before each Newton step and after the last.  b and x must not alias. */
+int dnnmg_coarse_solve(const dnnmg_box *box, const dnnmg_ns *ns, const double *b, double *x,
+                       const dnnmg_coarse_opts *opts, double *res_norms, void *ws, size_t ws_bytes, void *stream);
+/* The solve's Jacobian-vector product on the coarse mesh: w = J(x) z
+ * (FP32 [4][n_coarse] each; w must not alias x or z), with the solve's
+ * finite-difference step (opts->fd_eta). */
+int dnnmg_coarse_jv(const dnnmg_box *box, const dnnmg_ns *ns, const float *x, const float *z, float *w,
+                    const dnnmg_coarse_opts *opts, void *ws, size_t ws_bytes, void *stream);
+/* The solve's preconditioner: z = one V-cycle applied to s (FP32
+ * [4][n_coarse] each, not aliased), linearised at x. */
+int dnnmg_coarse_vcycle(const dnnmg_box *box, const dnnmg_ns *ns, const float *x, const float *s, float *z,
+                        const dnnmg_coarse_opts *opts, void *ws, size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -80,6 +80,15 @@ class DeepNetDesc(ctypes.Structure):
                 ("b", c_vp * (DEEP_MAX_DEPTH + 1))]
 
 
+class CoarseOpts(ctypes.Structure):
+    _fields_ = [("newton_its", ctypes.c_int32), ("krylov_dim", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("pre_sweeps", ctypes.c_int32), ("post_sweeps", ctypes.c_int32),
+                ("coarsest_sweeps", ctypes.c_int32), ("omega", ctypes.c_double), ("fd_eta", ctypes.c_double)]
+
+
+COARSE_MAX_KRYLOV = 16  # DNNMG_COARSE_MAX_KRYLOV of include/dnnmg.h
+
+
 def _sig(name, argtypes, restype=ctypes.c_int):
     f = getattr(_lib, name)
     f.argtypes = argtypes
@@ -155,6 +164,11 @@ _sig("dnnmg_graph_capture_end", [c_vp, _P(c_vp)])
 _sig("dnnmg_graph_replay", [c_vp, c_vp])
 _sig("dnnmg_graph_destroy", [c_vp])
 _sig("dnnmg_adamw_step", [c_i64, c_vp, c_vp, c_vp, c_vp, c_f, c_f, c_f, c_f, c_f, c_i64, c_vp])
+_sig("dnnmg_coarse_levels", [_P(Box), _P(CoarseOpts)])
+_sig("dnnmg_coarse_workspace", [_P(Box), _P(CoarseOpts)], c_sz)
+_sig("dnnmg_coarse_solve", [_P(Box), _P(NS), c_vp, c_vp, _P(CoarseOpts), c_vp, c_vp, c_sz, c_vp])
+_sig("dnnmg_coarse_jv", [_P(Box), _P(NS), c_vp, c_vp, c_vp, _P(CoarseOpts), c_vp, c_sz, c_vp])
+_sig("dnnmg_coarse_vcycle", [_P(Box), _P(NS), c_vp, c_vp, c_vp, _P(CoarseOpts), c_vp, c_sz, c_vp])
 
 EXPORTS = [
     "dnnmg_version", "dnnmg_last_error", "dnnmg_box_sizes", "dnnmg_patch_dofmap", "dnnmg_prolong",
@@ -172,7 +186,8 @@ EXPORTS = [
     "dnnmg_mlp_packed_bytes_io", "dnnmg_mlp_pack_io", "dnnmg_mlp_prepare_io", "dnnmg_level_sizes",
     "dnnmg_patch_dofmap_levels", "dnnmg_prolong_levels", "dnnmg_restrict_levels", "dnnmg_patch_gather_levels",
     "dnnmg_scatter_avg_levels", "dnnmg_deepnet_widths", "dnnmg_deepnet_packed_bytes", "dnnmg_deepnet_prepare",
-    "dnnmg_deepnet_forward", "dnnmg_patch_gather_paper",
+    "dnnmg_deepnet_forward", "dnnmg_patch_gather_paper", "dnnmg_coarse_levels", "dnnmg_coarse_workspace",
+    "dnnmg_coarse_solve", "dnnmg_coarse_jv", "dnnmg_coarse_vcycle",
 ]
 
 # network widths per prediction depth J (levels): inputs, outputs, padded input row
@@ -735,3 +750,54 @@ class Plan:
         if h is not None and h.value:
             _lib.dnnmg_plan_destroy(h)
             self.handle = None
+
+
+# ---------------------------------------------------------- coarse step ----
+def coarse_opts(newton_its=8, krylov_dim=16, levels=1, pre_sweeps=1, post_sweeps=0, coarsest_sweeps=1, omega=1.0,
+                fd_eta=1e-3) -> CoarseOpts:
+    """Defaults: the preconditioner is one coupled patch-Vanka sweep on the
+    coarse mesh itself (levels=1); see dnnmg_coarse_solve for why the
+    multigrid correction is off by default."""
+    return CoarseOpts(int(newton_its), int(krylov_dim), int(levels), int(pre_sweeps), int(post_sweeps),
+                      int(coarsest_sweeps), float(omega), float(fd_eta))
+
+
+def coarse_levels(box, opts: CoarseOpts) -> int:
+    n = int(_lib.dnnmg_coarse_levels(ctypes.byref(Box.of(box)), ctypes.byref(opts)))
+    if n < 0:
+        _check(n)
+    return n
+
+
+def coarse_workspace_bytes(box, opts: CoarseOpts) -> int:
+    n = int(_lib.dnnmg_coarse_workspace(ctypes.byref(Box.of(box)), ctypes.byref(opts)))
+    if n == 0:
+        coarse_levels(box, opts)  # raises with the reason
+    return n
+
+
+def dnnmg_coarse_solve(box, ns, b, x, opts: CoarseOpts, ws, res_norms=None, stream=None):
+    bx = Box.of(box)
+    _, nc, _ = box_sizes(bx)
+    _check(_lib.dnnmg_coarse_solve(ctypes.byref(bx), ctypes.byref(NS.of(ns)), _ptr(b, torch.float64, 4 * nc, "b"),
+                                   _ptr(x, torch.float64, 4 * nc, "x"), ctypes.byref(opts),
+                                   _ptr(res_norms, torch.float64, opts.newton_its + 1, "res_norms"),
+                                   _ptr(ws, None, None, "ws"), ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def dnnmg_coarse_jv(box, ns, x, z, w, opts: CoarseOpts, ws, stream=None):
+    bx = Box.of(box)
+    _, nc, _ = box_sizes(bx)
+    _check(_lib.dnnmg_coarse_jv(ctypes.byref(bx), ctypes.byref(NS.of(ns)), _ptr(x, torch.float32, 4 * nc, "x"),
+                                _ptr(z, torch.float32, 4 * nc, "z"), _ptr(w, torch.float32, 4 * nc, "w"),
+                                ctypes.byref(opts), _ptr(ws, None, None, "ws"), ws.numel() * ws.element_size(),
+                                _stream(stream)))
+
+
+def dnnmg_coarse_vcycle(box, ns, x, s, z, opts: CoarseOpts, ws, stream=None):
+    bx = Box.of(box)
+    _, nc, _ = box_sizes(bx)
+    _check(_lib.dnnmg_coarse_vcycle(ctypes.byref(bx), ctypes.byref(NS.of(ns)), _ptr(x, torch.float32, 4 * nc, "x"),
+                                    _ptr(s, torch.float32, 4 * nc, "s"), _ptr(z, torch.float32, 4 * nc, "z"),
+                                    ctypes.byref(opts), _ptr(ws, None, None, "ws"), ws.numel() * ws.element_size(),
+                                    _stream(stream)))

@@ -501,6 +501,25 @@ int vanka_sweeps(const dnnmg_box *box, const dnnmg_ns *ns, float *x, const float
 }
 } // namespace dnnmg
 
+namespace dnnmg {
+size_t vanka_local_bytes(const Mesh &m) { return sizeof(float) * 108 * (size_t)m.n_patches; }
+
+// One linear coupled patch-Vanka step (the multigrid smoother of the coarse
+// solve, Sec. 2.4): D_P = A_P^-1 d_P on every patch, A_P the local
+// Crank-Nicolson operator linearised at x (frozen convection), then
+// z <- z + omega * mu (.) sum_P L(D_P) with Dirichlet velocities unchanged.
+// D: vanka_local_bytes(m).
+int vanka_linear_step(const Mesh &m, const dnnmg_ns *ns, const float *x, const float *d, float *D, float omega,
+                      float *z, hipStream_t s) {
+    VankaTables T;
+    VankaParams P;
+    make_tables(m, ns, T, P);
+    k_vanka_local<true><<<(unsigned)m.n_patches, 64, 0, s>>>(m, T, P, x, d, D, nullptr);
+    k_vanka_apply<<<blocks_for(m.n_fine, 256), 256, 0, s>>>(m, D, omega, z, z, nullptr);
+    return hip_check(hipGetLastError(), "vanka step launch");
+}
+} // namespace dnnmg
+
 // Indicator decision on the device: fall back unless ||r(x_corr)||^2 <=
 // theta^2 ||r(x~)||^2 (a NaN in the corrected residual also falls back).
 __global__ void k_indicator_flag(const double *__restrict__ norms, double theta2, int *flag,

@@ -77,3 +77,39 @@ def test_graph_calls_validate_on_host():
     assert lib.dnnmg_graph_capture_begin(None) == -1
     assert lib.dnnmg_graph_replay(None, None) == -1
     assert lib.dnnmg_graph_destroy(None) == 0
+
+
+def test_coarse_step_host_logic():
+    """Levels and workspace of the GPU coarse solve are host computations:
+    the meshes are the coarse mesh and its halvings while every axis keeps
+    an even cell count; invalid options fail before any launch."""
+    import dnnmg_synth as syn
+    import paper_2307_14837_amd as L
+
+    lib = L._lib.lib()
+    o = L.coarse_opts(levels=0)  # every mesh of the hierarchy
+    big = syn.cfg5().box  # coarse mesh 128 x 32 x 32 cells
+    assert L.coarse_levels(big, o) == 4  # down to 16 x 4 x 4
+    assert L.coarse_levels(big, L.coarse_opts(levels=3)) == 3
+    assert L.coarse_levels(big, L.coarse_opts()) == 1  # the default: one mesh
+    assert L.coarse_levels(syn.channel_box((16, 8, 8)), o) == 2
+    # 6 x 4 x 4: the 3 x 2 x 2 mesh is not a level
+    assert L.coarse_levels(syn.channel_box((6, 4, 4)), o) == 1
+    # a periodic axis keeps an even cell count of at least 2 per box
+    per = syn.BoxSpec((8, 8, 8), (1, 1, 1), 7, 0)
+    assert L.coarse_levels(per, o) == 2
+    for bad in (L.coarse_opts(krylov_dim=0), L.coarse_opts(newton_its=0), L.coarse_opts(omega=2.0),
+                L.coarse_opts(fd_eta=0.0), L.coarse_opts(pre_sweeps=0)):
+        assert lib.dnnmg_coarse_levels(ctypes.byref(L.Box.of(big)), ctypes.byref(bad)) == -1
+    odd = L.Box.of(syn.channel_box((8, 2, 4)))
+    assert lib.dnnmg_coarse_levels(ctypes.byref(odd), ctypes.byref(o)) == -2
+    assert lib.dnnmg_coarse_workspace(ctypes.byref(odd), ctypes.byref(o)) == 0
+    # the workspace holds every level's vectors and the FGMRES basis
+    ws = L.coarse_workspace_bytes(big, o)
+    n0 = 4 * 129 * 33 * 33
+    assert ws > 4 * n0 * (7 + 5 + 2 * o.krylov_dim + 1)
+    assert ws < 4 * n0 * 60
+    # NULL workspace is an error before any launch
+    rc = lib.dnnmg_coarse_solve(ctypes.byref(L.Box.of(big)), ctypes.byref(L.NS.of(syn.cfg5().ns)), None, None,
+                                ctypes.byref(o), None, None, 0, None)
+    assert rc == -1
