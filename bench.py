@@ -513,6 +513,131 @@ def run_training(steps):
             "ms_per_step": ms, "patches_per_s": n / (ms * 1e-3), "approx_tflops": fl / (ms * 1e-3) / 1e12}
 
 
+def run_coarse_step():
+    """The GPU coarse step (Newton, FGMRES(16), one coupled patch-Vanka step
+    as preconditioner) on the large channel's coarse mesh (128x32x32 cells,
+    562 k unknowns): b^L = R Rhs(v0) of the channel start velocity, from the
+    coarse start with its Dirichlet data; eager and graph-replayed times and
+    the residual norms of the four Newton steps."""
+    import time
+
+    import torch
+
+    import dnnmg_synth as syn
+    from paper_2307_14837_amd import _lib as L
+
+    w = syn.cfg5()
+    box, ns = w.box, w.ns
+    vf, vc = syn.channel_initial(box, seed=0)
+    mask, vals = syn.channel_dirichlet(box, fine=False)
+    F = torch.zeros(4 * box.n_fine, dtype=torch.float32, device="cuda")
+    L.dnnmg_rhs(box, ns, torch.as_tensor(vf.astype(np.float32).ravel()).cuda(), F)
+    b = torch.zeros(4 * box.n_coarse, dtype=torch.float64, device="cuda")
+    L.dnnmg_restrict(box, F, b)
+    b.masked_fill_(torch.as_tensor(mask.ravel()).cuda(), 0.0)
+    x0 = np.zeros((4, box.n_coarse))
+    x0[:3] = vc
+    start = torch.as_tensor(np.where(mask, vals, x0).ravel()).cuda()
+    o = L.coarse_opts(newton_its=4)
+    ws = torch.empty(L.coarse_workspace_bytes(box, o), dtype=torch.uint8, device="cuda")
+    res = torch.zeros(o.newton_its + 1, dtype=torch.float64, device="cuda")
+    x = start.clone()
+    L.dnnmg_coarse_solve(box, ns, b, x, o, ws, res)
+    torch.cuda.synchronize()
+    x.copy_(start)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L.dnnmg_coarse_solve(box, ns, b, x, o, ws, res)
+    torch.cuda.synchronize()
+    eager = time.perf_counter() - t0
+    g = L.capture_graph(lambda: L.dnnmg_coarse_solve(box, ns, b, x, o, ws, res,
+                                                     stream=torch.cuda.current_stream()))
+    times = []
+    for _ in range(3):
+        x.copy_(start)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.replay(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    return {"workload": "coarse_step_channel_128x32x32", "unknowns": 4 * box.n_coarse,
+            "method": "4 Newton steps, FGMRES(16) each, one coupled patch-Vanka step as preconditioner, "
+                      "matrix-free Jacobian products",
+            "ms_eager": eager * 1e3, "ms_graph": min(times) * 1e3,
+            "residual_norms": [float(v) for v in res.cpu().numpy()]}
+
+
+def run_config4(steps=200, train_steps=150, hidden=256, batch=65536, opt_steps=600):
+    """The learned workload at its size: the channel of 48x12x12 coarse
+    cells (fine 96x24x24), `steps` teacher-forced steps of the plain method
+    generated on the GPU (coarse and fine solves by the GPU coarse step),
+    BF16 training at width 256 and batch 65,536 on steps 1..150 with the
+    library's kernels, and the relative velocity error of eq. (relerrors) on
+    the held-out steps 151..200: DNN-MG against the prolongated coarse
+    solution."""
+    import time
+
+    import torch
+
+    import dnnmg_synth as syn
+    from paper_2307_14837_amd import _lib as L
+    from paper_2307_14837_amd import stepper, train
+
+    w = syn.cfg4()
+    box, ns = w.box, w.ns
+    vf, vc = syn.channel_initial(box, amp=0.3, seed=0)
+    cb = syn.BoxSpec(tuple(n // 2 for n in box.n), box.len, box.periodic_mask, box.dirichlet_mask)
+    fbc, cbc = syn.channel_dirichlet(box, True), syn.channel_dirichlet(cb, True)
+    xc0 = np.zeros((4, box.n_coarse))
+    xc0[:3] = vc
+    log = lambda m: print("[bench]   " + m, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    xcs, vbar, _, norms = train.teacher_forced(box, ns, vf, xc0, steps, fbc, cbc, log=log)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    npch = box.n_patches
+    t0 = time.perf_counter()
+    X = train.gather_inputs(box, ns, [xcs[n].cpu().numpy() for n in range(train_steps)],
+                            [vbar[n].cpu().numpy() for n in range(train_steps)], L.F32).view(train_steps * npch, -1)
+    T = train.gather_targets(box, xcs[:train_steps], vbar[1:train_steps + 1])
+    shift, inv = train.standardisation(X)
+    Z = torch.zeros_like(X, dtype=torch.bfloat16)
+    Z[:, :L.N_IN] = ((X[:, :L.N_IN] - shift) * inv).to(torch.bfloat16)
+    del X
+    t_scale = float(T.double().std().item())
+    Tn = T / t_scale
+    tr = train.PatchTrainer(train._init_params(hidden, 0), dtype="bf16", lr=1e-3, max_batch=batch)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    rows = train_steps * npch
+    losses = []
+    for it in range(opt_steps):
+        idx = torch.randint(0, rows, (batch,), device="cuda", generator=g)
+        tr.step(Z[idx].contiguous().view(-1), Tn[idx].contiguous().view(-1), batch)
+        if it % 100 == 0 or it == opt_steps - 1:
+            losses.append(tr.loss(batch))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    st = stepper.CorrectionStep(box, ns, tr.params(target_scale=t_scale), dtype="bf16",
+                                shift=shift.cpu().numpy(), inv_scale=inv.cpu().numpy())
+    e_plain, e_net = [], []
+    for n in range(train_steps + 1, steps + 1):
+        out = st.run_numpy(xcs[n - 1].cpu().numpy(), vbar[n - 1].cpu().numpy())
+        ref = vbar[n].cpu().numpy().astype(np.float64)
+        nrm = np.linalg.norm(ref)
+        e_plain.append(np.linalg.norm(out["xt"][:3] - ref) / nrm)
+        e_net.append(np.linalg.norm(out["vcorr"] - ref) / nrm)
+    fine_red = [float(f[-1] / f[0]) for _, f in norms if f[0] > 0]
+    return {"workload": "cfg4_channel_48x12x12_learned", "steps": steps, "train_steps": train_steps,
+            "held_out": [train_steps + 1, steps], "hidden": hidden, "batch": batch, "optimizer_steps": opt_steps,
+            "data": "teacher-forced plain-method steps generated on the GPU (coarse and fine solves by the "
+                    "GPU coarse step, 10 Newton steps each)",
+            "fine_solve_residual_reduction_median": float(np.median(fine_red)),
+            "seconds_data": t_data, "seconds_training": t_train,
+            "training_loss": losses, "e_v_prolongation": float(np.mean(e_plain)),
+            "e_v_dnnmg": float(np.mean(e_net)), "e_v_ratio": float(np.mean(e_net) / np.mean(e_plain))}
+
+
 def kernels_at_scale():
     """The hot-path kernels on the large channel (coarse 128x32x32: 131,072
     patches, 1,085,825 fine nodes), each timed alone (50 graph-captured
@@ -707,6 +832,8 @@ def main():
             run_batched("bf16", sv, wv),
             run_per_box_plain("fp32", sv, wv),
             run_training(20),
+            run_coarse_step(),
+            run_config4(),
         ]
         out["variants"] = variants
         print("[bench] kernels on the large channel", file=sys.stderr, flush=True)

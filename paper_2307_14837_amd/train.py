@@ -260,3 +260,85 @@ def _init_params(hidden, seed):
         out += [rng.standard_normal((fi, fo)) / np.sqrt(fi), np.zeros(fo)]
     out[4] *= 0.1
     return out
+
+
+def _doubled(box):
+    """The box with twice the cells per axis: its coarse mesh is the fine
+    mesh of `box`, so the coarse-step solver solves on that mesh."""
+    b = L.Box.of(box)
+    out = L.Box()
+    for a in range(3):
+        out.n[a] = 2 * b.n[a]
+        out.len[a] = b.len[a]
+    out.periodic_mask, out.dirichlet_mask = b.periodic_mask, b.dirichlet_mask
+    return out
+
+
+def teacher_forced(box, ns, v0, xc0, steps, fine_bc, coarse_bc, opts=None, device="cuda:0", log=None):
+    """Teacher-forced data of the plain method on the GPU (the reading of
+    Sec. 4.2 that the oracle's CPU solver follows):
+      F_n   = Rhs_fine(vbar_{n-1})
+      x^L_n : A_coarse(x^L_n) = R F_n   (Dirichlet velocity rows zero)
+      xbar_n: A_fine(xbar_n) = F_n      (ground truth)
+    Both solves are dnnmg_coarse_solve (the fine one on the box with twice
+    the cells, whose coarse mesh is this box's fine mesh), each started from
+    the previous step's solution with the Dirichlet data (fine_bc /
+    coarse_bc: (mask [4][N] bool, values [4][N]) on the fine / coarse nodes).
+    Returns xc (list of FP64 [4][n_coarse] GPU tensors, steps 1..n), vbar
+    (list of FP32 [3][n_fine], vbar[0] = v0), pbar (FP32 [n_fine], steps
+    1..n) and the residual norms of each solve."""
+    dev = torch.device(device)
+    bx, nsp = L.Box.of(box), L.NS.of(ns)
+    fbx = _doubled(bx)
+    nf, nc, _ = L.box_sizes(bx)
+    opts = opts or L.coarse_opts(newton_its=10)
+    ws_c = torch.empty(L.coarse_workspace_bytes(bx, opts), dtype=torch.uint8, device=dev)
+    ws_f = torch.empty(L.coarse_workspace_bytes(fbx, opts), dtype=torch.uint8, device=dev)
+    fm = torch.as_tensor(np.asarray(fine_bc[0], bool).reshape(-1), device=dev)
+    fv = torch.as_tensor(np.asarray(fine_bc[1], np.float64).reshape(-1), device=dev)
+    cm = torch.as_tensor(np.asarray(coarse_bc[0], bool).reshape(-1), device=dev)
+    cv = torch.as_tensor(np.asarray(coarse_bc[1], np.float64).reshape(-1), device=dev)
+    F = torch.zeros(4 * nf, dtype=torch.float32, device=dev)
+    bL = torch.zeros(4 * nc, dtype=torch.float64, device=dev)
+    xc = torch.as_tensor(np.asarray(xc0, np.float64).reshape(-1)).to(dev)
+    xf = torch.zeros(4 * nf, dtype=torch.float64, device=dev)
+    xf[:3 * nf] = torch.as_tensor(np.asarray(v0, np.float64).reshape(-1)).to(dev)
+    vbar = [xf[:3 * nf].float().view(3, nf).clone()]
+    xcs, pbar, norms = [], [], []
+    res_c = torch.zeros(opts.newton_its + 1, dtype=torch.float64, device=dev)
+    res_f = torch.zeros_like(res_c)
+    for n in range(1, steps + 1):
+        L.dnnmg_rhs(bx, nsp, vbar[-1].reshape(-1).contiguous(), F)
+        L.dnnmg_restrict(bx, F, bL)
+        bL.masked_fill_(cm & (torch.arange(4 * nc, device=dev) < 3 * nc), 0.0)
+        xc = torch.where(cm, cv, xc)
+        L.dnnmg_coarse_solve(bx, nsp, bL, xc, opts, ws_c, res_c)
+        bF = F.double()
+        bF.masked_fill_(fm & (torch.arange(4 * nf, device=dev) < 3 * nf), 0.0)
+        xf = torch.where(fm, fv, xf)
+        L.dnnmg_coarse_solve(fbx, nsp, bF, xf, opts, ws_f, res_f)
+        xcs.append(xc.clone())
+        vbar.append(xf[:3 * nf].float().view(3, nf).clone())
+        pbar.append(xf[3 * nf:].float().clone())
+        norms.append((res_c.cpu().numpy(), res_f.cpu().numpy()))
+        if log and (n == 1 or n % 25 == 0 or n == steps):
+            log(f"teacher-forced step {n}/{steps}: coarse |r| {norms[-1][0][0]:.2e} -> {norms[-1][0][-1]:.2e}, "
+                f"fine |r| {norms[-1][1][0]:.2e} -> {norms[-1][1][-1]:.2e}")
+    return xcs, vbar, pbar, norms
+
+
+def gather_targets(box, xc_list, vnext_list, device="cuda:0"):
+    """Training targets of many steps: Q(vbar_n - P x^L_n) on each patch (the
+    81 velocity unknowns; Sec. 4.2 training objective), FP32 [steps * N_p][81]."""
+    dev = torch.device(device)
+    nf, nc, npch = L.box_sizes(box)
+    xt = torch.zeros(4 * nf, dtype=torch.float32, device=dev)
+    dv = torch.zeros(4 * nf, dtype=torch.float32, device=dev)
+    Tpad = torch.zeros(npch * LDX, dtype=torch.float32, device=dev)
+    T = torch.zeros(len(xc_list) * npch, L.N_OUT, dtype=torch.float32, device=dev)
+    for s, (c, v) in enumerate(zip(xc_list, vnext_list)):
+        L.dnnmg_prolong(box, torch.as_tensor(c).to(dev, torch.float64).contiguous().view(-1), xt)
+        dv[:3 * nf] = torch.as_tensor(v).to(dev, torch.float32).reshape(-1) - xt[:3 * nf]
+        L.dnnmg_patch_gather(box, dv, dv, Tpad, L.F32, LDX)
+        T[s * npch:(s + 1) * npch] = Tpad.view(npch, LDX)[:, :L.N_OUT]
+    return T
