@@ -13,7 +13,9 @@
 // kernel (matrix-free; eps scaled by rms(x) / rms(z)).  The V-cycle smooths
 // J_l z = s_l with linear coupled patch-Vanka steps linearised at x_l (the
 // Newton iterate injected to mesh l), restricts defects with the transpose
-// of the Q1 prolongation and prolongates corrections with it.
+// of the Q1 prolongation and prolongates corrections with it.  The local
+// Vanka systems depend on x_l only: they are inverted once per Newton step
+// (108 x 108 per patch) and each smoothing step is a local mat-vec.
 // Inner products and norms accumulate in FP64; the Hessenberg system is
 // FP64 and solved with Givens rotations on the device, so nothing returns
 // to the host and the whole solve can be recorded into a graph.
@@ -28,8 +30,10 @@ int residual_launch_b(const Mesh &m, const dnnmg_ns *ns, const float *x, const f
                       const int *flag, hipStream_t s);
 size_t lps_ws_bytes(const Mesh &m);
 size_t vanka_local_bytes(const Mesh &m);
-int vanka_linear_step(const Mesh &m, const dnnmg_ns *ns, const float *x, const float *d, float *D, float omega,
-                      float *z, hipStream_t s);
+size_t vanka_inverse_bytes(const Mesh &m);
+int vanka_factor(const Mesh &m, const dnnmg_ns *ns, const float *x, float *Ainv, hipStream_t s);
+int vanka_apply_factored(const Mesh &m, const float *Ainv, const float *d, float *D, float omega, float *z,
+                         hipStream_t s);
 int device_cus();
 
 namespace {
@@ -337,7 +341,7 @@ struct Level {
     dnnmg_box box; // n / 2^(l+1) cells: its fine mesh is mesh l
     Mesh m;
     int64_t n4;    // 4 * nodes of mesh l
-    float *x, *a0, *s, *z, *d, *y, *ra, *D;
+    float *x, *a0, *s, *z, *d, *y, *ra, *D, *Ainv;
     char *aux;
     double *xnorm, *eps, *znorm;
 };
@@ -422,6 +426,7 @@ int make_layout(const dnnmg_box *box, const dnnmg_coarse_opts *o, char *base, La
         v.y = (float *)take(vb);
         v.ra = (float *)take(vb);
         v.D = (float *)take(vanka_local_bytes(v.m));
+        v.Ainv = (float *)take(vanka_inverse_bytes(v.m));
         v.aux = take(lps_ws_bytes(v.m));
         v.xnorm = (double *)take(sizeof(double));
         v.eps = (double *)take(sizeof(double));
@@ -502,13 +507,14 @@ int linearise(const Ctx &c) {
         }
         TRY(residual_launch_b(v.m, c.ns, v.x, c.Y->zeros, v.a0, (float *)v.aux, nullptr, c.s));
         TRY(dots(c, v.n4, v.x, nullptr, 0, 1, v.xnorm));
+        TRY(vanka_factor(v.m, c.ns, v.x, v.Ainv, c.s));
     }
     return hip_check(hipGetLastError(), "coarse linearisation");
 }
 
 int smooth(const Ctx &c, Level &v, const float *s, float *z) {
     TRY(defect(c, v, s, z, v.d));
-    return vanka_linear_step(v.m, c.ns, v.x, v.d, v.D, (float)c.o->omega, z, c.s);
+    return vanka_apply_factored(v.m, v.Ainv, v.d, v.D, (float)c.o->omega, z, c.s);
 }
 
 // z0 = V s0: one V-cycle over the levels.  Level 0 reads s0 and writes z0;
@@ -523,7 +529,7 @@ int vcycle(const Ctx &c, const float *s0, float *z0) {
         float *z = Zp(l);
         TRY(zero(c, v.n4, z));
         // the first sweep's defect is s itself (z = 0)
-        TRY(vanka_linear_step(v.m, c.ns, v.x, S(l), v.D, (float)c.o->omega, z, c.s));
+        TRY(vanka_apply_factored(v.m, v.Ainv, S(l), v.D, (float)c.o->omega, z, c.s));
         const int sweeps = l == nl - 1 ? c.o->coarsest_sweeps : c.o->pre_sweeps;
         for (int it = 1; it < sweeps; ++it) TRY(smooth(c, v, S(l), z));
         if (l == nl - 1) break;

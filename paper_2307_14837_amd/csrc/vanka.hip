@@ -48,10 +48,14 @@ __device__ __forceinline__ int iota_of(int a, int b, int c) { return a + 3 * b +
 // STRIDED = false: one patch per block (the grid covers the patches);
 // STRIDED = true: blocks walk the patches with stride gridDim.x, for launches
 // that a device flag may skip on a smaller grid.
-template <bool COUPLED, bool STRIDED = false>
+// INVERSE (coupled only): r is not read; D receives the local inverse
+// A_P^-1 of every patch instead, column-major (D[M][j][row], 108 x 108),
+// each column the local solve of a unit right-hand side.
+template <bool COUPLED, bool STRIDED = false, bool INVERSE = false>
 __global__ void __launch_bounds__(64)
     k_vanka_local(Mesh m, VankaTables T, VankaParams P, const float *__restrict__ x,
                   const float *__restrict__ r, float *__restrict__ D, const int *__restrict__ flag) {
+    static_assert(!INVERSE || (COUPLED && !STRIDED), "local inverses are built for the coupled systems");
     constexpr int NB = COUPLED ? 3 : 1;   // divergence blocks kept
     constexpr int NO = COUPLED ? 8 : 1;   // own cells with LPS tables
     constexpr int NZ = COUPLED ? 84 : 3;  // right-hand sides of K
@@ -93,7 +97,7 @@ __global__ void __launch_bounds__(64)
         int gi = wrap(2 * (int)I + a, m.nf[0], m.per[0]);
         int gj = wrap(2 * (int)J + b, m.nf[1], m.per[1]);
         int gk = wrap(2 * (int)K + c, m.nf[2], m.per[2]);
-        sR[s] = r[f * nfn + gi + (int64_t)m.nf[0] * (gj + (int64_t)m.nf[1] * gk)];
+        sR[s] = INVERSE ? 0.0f : r[f * nfn + gi + (int64_t)m.nf[0] * (gj + (int64_t)m.nf[1] * gk)];
         if (f == 0) sDir[t] = on_dirichlet(m, gi, gj, gk) ? 1 : 0;
     }
     for (int s = lane; s < 27 * 28; s += 64) {
@@ -308,6 +312,72 @@ __global__ void __launch_bounds__(64)
         for (int i = k + 1 + lane; i < 27; i += 64) sC[i][k] /= piv;
         __syncthreads();
     }
+    if constexpr (INVERSE) {
+        // column j of A_P^-1: the local solve of e_j.  A velocity unit
+        // vector (f, jj): y = K^-1 e_jj, dp = S^-1 (-B_f y), du_a = [a = f] y
+        // + K^-1 B_a^T dp; a pressure one (jj): dp = S^-1 e_jj, du_a =
+        // K^-1 B_a^T dp.  Dirichlet velocities: zero rows and columns.
+        float *Ai = D + M * (108 * 108);
+        for (int j = lane; j < 108; j += 64) {
+            const int f = j / 27, jj = j % 27;
+            const bool vel = f < 3;
+            float y[27], v[27];
+#pragma unroll
+            for (int i = 0; i < 27; ++i) y[i] = (vel && i == jj && !sDir[jj]) ? 1.0f : 0.0f;
+            if (vel) {
+#pragma unroll
+                for (int i = 0; i < 27; ++i) {
+                    float t = y[i];
+#pragma unroll
+                    for (int k = 0; k < i; ++k) t -= sK[i][k] * y[k];
+                    y[i] = t;
+                }
+#pragma unroll
+                for (int i = 26; i >= 0; --i) {
+                    float t = y[i];
+#pragma unroll
+                    for (int k = i + 1; k < 27; ++k) t -= sK[i][k] * y[k];
+                    y[i] = t / sK[i][i];
+                }
+#pragma unroll
+                for (int i = 0; i < 27; ++i) {
+                    float t = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < 27; ++k) t = fmaf(sB[f][i][k], y[k], t);
+                    v[i] = -t;
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 27; ++i) v[i] = i == jj ? 1.0f : 0.0f;
+            }
+#pragma unroll
+            for (int i = 0; i < 27; ++i) {
+                float t = v[i];
+#pragma unroll
+                for (int k = 0; k < i; ++k) t -= sC[i][k] * v[k];
+                v[i] = t;
+            }
+#pragma unroll
+            for (int i = 26; i >= 0; --i) {
+                float t = v[i];
+#pragma unroll
+                for (int k = i + 1; k < 27; ++k) t -= sC[i][k] * v[k];
+                v[i] = t / sC[i][i];
+            }
+            float *col = Ai + j * 108;
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int i = 0; i < 27; ++i) {
+                    float t = a == f ? y[i] : 0.0f;
+#pragma unroll
+                    for (int k = 0; k < 27; ++k) t = fmaf(sZ[27 * a + k][i], v[k], t);
+                    col[27 * a + i] = sDir[i] ? 0.0f : t;
+                }
+#pragma unroll
+            for (int i = 0; i < 27; ++i) col[81 + i] = v[i];
+        }
+        continue;
+    }
     __shared__ float sDp[27];
     if (lane == 0) {
         float v[27];
@@ -502,21 +572,62 @@ int vanka_sweeps(const dnnmg_box *box, const dnnmg_ns *ns, float *x, const float
 } // namespace dnnmg
 
 namespace dnnmg {
-size_t vanka_local_bytes(const Mesh &m) { return sizeof(float) * 108 * (size_t)m.n_patches; }
+// D_P = A_P^-1 d_P on every patch from the column-major local inverses of
+// k_vanka_local<true, false, true>: two patches per block, lane = row.
+__global__ void __launch_bounds__(128) k_vanka_apply_inverse(Mesh m, const float *__restrict__ Ainv,
+                                                             const float *__restrict__ d, float *__restrict__ D) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t M = 2 * (int64_t)blockIdx.x + w;
+    __shared__ float sd[2][108];
+    if (M < m.n_patches) {
+        const uint32_t JK = fdiv((uint32_t)M, m.px), I = (uint32_t)M - JK * m.n[0];
+        const uint32_t K = fdiv(JK, m.py), J = JK - K * m.n[1];
+        for (int s = lane; s < 108; s += 64) {
+            const int f = s / 27, t = s % 27, a = t % 3, b = (t / 3) % 3, c = t / 9;
+            const int gi = wrap(2 * (int)I + a, m.nf[0], m.per[0]);
+            const int gj = wrap(2 * (int)J + b, m.nf[1], m.per[1]);
+            const int gk = wrap(2 * (int)K + c, m.nf[2], m.per[2]);
+            sd[w][s] = d[f * m.n_fine + gi + (int64_t)m.nf[0] * (gj + (int64_t)m.nf[1] * gk)];
+        }
+    }
+    __syncthreads();
+    if (M >= m.n_patches) return;
+    const float *A = Ainv + M * (108 * 108);
+    const bool two = lane + 64 < 108;
+    float a0 = 0.0f, a1 = 0.0f;
+    for (int j = 0; j < 108; ++j) {
+        const float dj = sd[w][j];
+        a0 = fmaf(A[j * 108 + lane], dj, a0);
+        if (two) a1 = fmaf(A[j * 108 + 64 + lane], dj, a1);
+    }
+    D[M * 108 + lane] = a0;
+    if (two) D[M * 108 + 64 + lane] = a1;
+}
 
-// One linear coupled patch-Vanka step (the multigrid smoother of the coarse
-// solve, Sec. 2.4): D_P = A_P^-1 d_P on every patch, A_P the local
-// Crank-Nicolson operator linearised at x (frozen convection), then
-// z <- z + omega * mu (.) sum_P L(D_P) with Dirichlet velocities unchanged.
-// D: vanka_local_bytes(m).
-int vanka_linear_step(const Mesh &m, const dnnmg_ns *ns, const float *x, const float *d, float *D, float omega,
-                      float *z, hipStream_t s) {
+size_t vanka_local_bytes(const Mesh &m) { return sizeof(float) * 108 * (size_t)m.n_patches; }
+size_t vanka_inverse_bytes(const Mesh &m) { return sizeof(float) * 108 * 108 * (size_t)m.n_patches; }
+
+// The local inverses of the coupled patch-Vanka systems (the multigrid
+// smoother of the coarse solve, Sec. 2.4): A_P, the local Crank-Nicolson
+// operator linearised at x (frozen convection), inverted on every patch.
+// They depend on x only, so one factorisation serves every application at
+// that linearisation.  Ainv: vanka_inverse_bytes(m).
+int vanka_factor(const Mesh &m, const dnnmg_ns *ns, const float *x, float *Ainv, hipStream_t s) {
     VankaTables T;
     VankaParams P;
     make_tables(m, ns, T, P);
-    k_vanka_local<true><<<(unsigned)m.n_patches, 64, 0, s>>>(m, T, P, x, d, D, nullptr);
+    k_vanka_local<true, false, true><<<(unsigned)m.n_patches, 64, 0, s>>>(m, T, P, x, nullptr, Ainv, nullptr);
+    return hip_check(hipGetLastError(), "vanka factor launch");
+}
+
+// One linear coupled patch-Vanka step with factored local systems:
+// D_P = A_P^-1 d_P, then z <- z + omega * mu (.) sum_P L(D_P) with Dirichlet
+// velocities unchanged.  D: vanka_local_bytes(m).
+int vanka_apply_factored(const Mesh &m, const float *Ainv, const float *d, float *D, float omega, float *z,
+                         hipStream_t s) {
+    k_vanka_apply_inverse<<<(unsigned)((m.n_patches + 1) / 2), 128, 0, s>>>(m, Ainv, d, D);
     k_vanka_apply<<<blocks_for(m.n_fine, 256), 256, 0, s>>>(m, D, omega, z, z, nullptr);
-    return hip_check(hipGetLastError(), "vanka step launch");
+    return hip_check(hipGetLastError(), "vanka apply launch");
 }
 } // namespace dnnmg
 
