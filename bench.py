@@ -567,6 +567,41 @@ def run_coarse_step():
             "residual_norms": [float(v) for v in res.cpu().numpy()]}
 
 
+def run_time_loop(w, params, shift, inv, steps=5):
+    """Whole time steps of Algorithm 1 on the GPU, one graph each: the coarse
+    problem (b^L the restriction of the previous step's fine Rhs) by the GPU
+    coarse step (4 Newton steps), then the configured correction (FP8
+    network, indicator at threshold 1, fallback), on the large channel."""
+    import time
+
+    import torch
+
+    import dnnmg_synth as syn
+    from paper_2307_14837_amd import _lib as L
+
+    st, inp = build_step(w, "fp8", params, shift, inv, indicator=True, theta=1.0)
+    mask, vals = syn.channel_dirichlet(w.box, fine=False)
+    st.attach_coarse(L.coarse_opts(newton_its=4), (mask, vals))
+    g = st.capture(full=True)
+    torch.cuda.synchronize()
+    ms, etas, fell, red = [], [], 0, []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        g.replay(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        ms.append((time.perf_counter() - t0) * 1e3)
+        n = st.norms.cpu().numpy()
+        etas.append(float(np.sqrt(n[1] / n[0])) if n[0] > 0 else 0.0)
+        fell += int(st.fell_back.item())
+        rc = st.c_res.cpu().numpy()
+        red.append(float(rc[-1] / rc[0]) if rc[0] > 0 else 0.0)
+    return {"workload": w.name + "_time_loop", "dtype": "fp8", "indicator": True, "theta": 1.0,
+            "method": "coarse step on the GPU (4 Newton steps, FGMRES(16), one Vanka step as preconditioner) "
+                      "+ the correction step, one graph per time step",
+            "steps": steps, "ms_per_time_step_median": float(np.median(ms)), "eta": etas,
+            "fallback_rate": fell / steps, "coarse_residual_reduction": red}
+
+
 def run_config4(steps=200, train_steps=150, hidden=256, batch=65536, opt_steps=600):
     """The learned workload at its size: the channel of 48x12x12 coarse
     cells (fine 96x24x24), `steps` teacher-forced steps of the plain method
@@ -833,6 +868,7 @@ def main():
             run_per_box_plain("fp32", sv, wv),
             run_training(20),
             run_coarse_step(),
+            run_time_loop(w, params, shift, inv),
             run_config4(),
         ]
         out["variants"] = variants

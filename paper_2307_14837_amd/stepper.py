@@ -186,10 +186,44 @@ class CorrectionStep:
         L.dnnmg_rhs(fb, ns, self.xcorr, self.b, stream=stream)
         L.dnnmg_restrict_levels(box, J, self.b, self.bc, stream=stream)
 
-    def capture(self):
-        """Record step() into a HIP graph through the library's capture calls
-        (one eager warm-up step first)."""
-        self.graph = L.capture_graph(self.step, device=self.dev)
+    def attach_coarse(self, opts, coarse_bc):
+        """Makes time_step() a whole time step of Algorithm 1 on the GPU: the
+        coarse problem A(x^L) = b^L (b^L the restriction of the previous
+        step's fine Rhs, left in bc, with its Dirichlet velocity rows zero)
+        solved by dnnmg_coarse_solve from the previous x^L with the Dirichlet
+        data coarse_bc = (mask [4][n_coarse] bool, values [4][n_coarse]),
+        then step().  One-level prediction with the carried right-hand side
+        only."""
+        if self.levels != 1 or not self.carry_rhs:
+            raise ValueError("the GPU time step is built for J = 1 with the carried right-hand side")
+        mask = torch.as_tensor(np.asarray(coarse_bc[0], bool).reshape(-1), device=self.dev)
+        vals = torch.as_tensor(np.asarray(coarse_bc[1], np.float64).reshape(-1), device=self.dev)
+        self.c_opts = opts
+        self.c_keep = (~mask).double()            # 0 on Dirichlet entries
+        self.c_dir = torch.where(mask, vals, torch.zeros_like(vals))
+        self.c_keep_rows = self.c_keep.clone()    # b^L: Dirichlet velocity rows zero
+        self.bL = torch.zeros_like(self.bc)
+        self.c_ws = torch.empty(L.coarse_workspace_bytes(self.box, opts), dtype=torch.uint8, device=self.dev)
+        self.c_res = torch.zeros(opts.newton_its + 1, dtype=torch.float64, device=self.dev)
+        # the restriction of the loaded Rhs, as the previous step leaves it
+        L.dnnmg_restrict(self.box, self.b, self.bc)
+
+    def time_step(self, stream=None):
+        """Coarse solve, then the correction step (attach_coarse first).  The
+        Dirichlet handling uses in-place elementwise products only, so the
+        whole time step can be recorded into one graph."""
+        s = torch.cuda.current_stream(self.dev) if stream is None else stream
+        with torch.cuda.stream(s):
+            self.bL.copy_(self.bc).mul_(self.c_keep_rows)
+            self.xc.mul_(self.c_keep).add_(self.c_dir)
+        L.dnnmg_coarse_solve(self.box, self.ns, self.bL, self.xc, self.c_opts, self.c_ws, self.c_res, stream=s)
+        self.step(s)
+
+    def capture(self, full=False):
+        """Record step() (full: time_step()) into a HIP graph through the
+        library's capture calls (one eager warm-up run first)."""
+        fn = (lambda: self.time_step(torch.cuda.current_stream(self.dev))) if full else self.step
+        self.graph = L.capture_graph(fn, device=self.dev)
         return self.graph
 
     def replay(self, stream=None):

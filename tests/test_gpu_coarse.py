@@ -258,3 +258,44 @@ def test_coarse_solve_graph_replays(L, orc):
         g.replay(torch.cuda.current_stream())
         torch.cuda.synchronize()
         assert np.array_equal(xg.cpu().numpy(), eager)
+
+
+def test_gpu_time_step_matches_oracle(L, orc):
+    """A whole time step of Algorithm 1 on the GPU (stepper.time_step: coarse
+    problem b^L = R Rhs(v_prev) solved by the GPU coarse step, then the
+    correction with an FP32 network), recorded into one graph and replayed
+    for two steps, against the oracle: its Newton solve of the same coarse
+    problem and its FP64 correction step, chained."""
+    from oracle.solve import NewtonSolver
+
+    from paper_2307_14837_amd import stepper
+
+    box = syn.channel_box((8, 4, 4))
+    ob = obox(box)
+    vf, vc = syn.channel_initial(box, seed=11)
+    mask, vals = syn.channel_dirichlet(box, fine=False)
+    xc0 = np.where(mask, vals, np.concatenate([vc, np.zeros((1, box.n_coarse))]))
+    params = syn.mlp_params(165, 64, 81, seed=3, bias_scale=0.1)
+    params[4] = params[4] * 0.01  # a small correction, as a trained network gives
+    st = stepper.CorrectionStep(box, NS, params, dtype="fp32")
+    st.load(xc0, vf)
+    st.attach_coarse(L.coarse_opts(newton_its=10), (mask, vals))
+    g = st.capture(full=True)  # the eager warm-up is time step 1
+    torch.cuda.synchronize()
+    got1 = st.xcorr.cpu().numpy().reshape(4, -1)[:3].astype(np.float64)
+    g.replay(torch.cuda.current_stream())  # time step 2
+    torch.cuda.synchronize()
+    got2 = st.xcorr.cpu().numpy().reshape(4, -1)[:3].astype(np.float64)
+    p64 = [np.asarray(p, np.float32).astype(np.float64) for p in params]
+    zero = np.zeros((3, ob.n_fine))
+    x, vprev = xc0, vf
+    for n, got in ((1, got1), (2, got2)):
+        bL = orc.restrict(box, orc.rhs(box, NS, vprev))
+        bL[:3][mask[:3]] = 0.0
+        x = np.where(mask, vals, x)
+        x, _ = NewtonSolver(ob, NS).solve(lambda z: bL + orc.residual(ob, NS, z, zero), x)
+        ref = orc.correction_step(box, NS, p64, x, vprev)
+        err = rel_l2(got, ref["vcorr"])
+        say(f"time step {n}: corrected velocity rel-L2 {err:.2e}")
+        assert err <= 1e-4
+        vprev = ref["vcorr"]
