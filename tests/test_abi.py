@@ -104,11 +104,14 @@ def test_coarse_step_host_logic():
     odd = L.Box.of(syn.channel_box((8, 2, 4)))
     assert lib.dnnmg_coarse_levels(ctypes.byref(odd), ctypes.byref(o)) == -2
     assert lib.dnnmg_coarse_workspace(ctypes.byref(odd), ctypes.byref(o)) == 0
-    # the workspace holds every level's vectors and the FGMRES basis
+    # the workspace holds every level's vectors, the local Vanka inverses
+    # (108 x 108 FP32 per patch of meshes 128, 64, 32, 16 x ...) and the
+    # FGMRES basis
     ws = L.coarse_workspace_bytes(big, o)
     n0 = 4 * 129 * 33 * 33
-    assert ws > 4 * n0 * (7 + 5 + 2 * o.krylov_dim + 1)
-    assert ws < 4 * n0 * 60
+    inv = 108 * 108 * 4 * (16384 + 2048 + 256 + 32)
+    assert ws > inv + 4 * n0 * (7 + 5 + 2 * o.krylov_dim + 1)
+    assert ws < inv + 4 * n0 * 60
     # NULL workspace is an error before any launch
     rc = lib.dnnmg_coarse_solve(ctypes.byref(L.Box.of(big)), ctypes.byref(L.NS.of(syn.cfg5().ns)), None, None,
                                 ctypes.byref(o), None, None, 0, None)
