@@ -662,6 +662,25 @@ def run_config4(steps=200, train_steps=150, hidden=256, batch=65536, opt_steps=6
         nrm = np.linalg.norm(ref)
         e_plain.append(np.linalg.norm(out["xt"][:3] - ref) / nrm)
         e_net.append(np.linalg.norm(out["vcorr"] - ref) / nrm)
+    # the paper's network form (8 hidden layers of width 512, batch
+    # normalisation with batch statistics, skip connections; its Sec. 4.2
+    # inputs) on the same data, trained with torch autograd in FP32 and run
+    # folded in the library's deep forward (BF16) inside the correction step
+    t1 = time.perf_counter()
+    Xp = train.paper_inputs(box, ns, xcs[:train_steps], vbar[:train_steps])
+    p_shift, p_inv = train.standardisation(Xp, 240)
+    Xp[:, :240] = (Xp[:, :240] - p_shift) * p_inv
+    pparams, _, _, ploss = train.train_paper_network(Xp, T, hidden=512, depth=8, steps=400, batch=16384)
+    del Xp
+    torch.cuda.synchronize()
+    t_paper = time.perf_counter() - t1
+    stp = stepper.CorrectionStep(box, ns, pparams, dtype="bf16", network="paper", shift=p_shift.cpu().numpy(),
+                                 inv_scale=p_inv.cpu().numpy())
+    e_paper = []
+    for n in range(train_steps + 1, steps + 1):
+        out = stp.run_numpy(xcs[n - 1].cpu().numpy(), vbar[n - 1].cpu().numpy())
+        ref = vbar[n].cpu().numpy().astype(np.float64)
+        e_paper.append(np.linalg.norm(out["vcorr"] - ref) / np.linalg.norm(ref))
     fine_red = [float(f[-1] / f[0]) for _, f in norms if f[0] > 0]
     return {"workload": "cfg4_channel_48x12x12_learned", "steps": steps, "train_steps": train_steps,
             "held_out": [train_steps + 1, steps], "hidden": hidden, "batch": batch, "optimizer_steps": opt_steps,
@@ -670,7 +689,13 @@ def run_config4(steps=200, train_steps=150, hidden=256, batch=65536, opt_steps=6
             "fine_solve_residual_reduction_median": float(np.median(fine_red)),
             "seconds_data": t_data, "seconds_training": t_train,
             "training_loss": losses, "e_v_prolongation": float(np.mean(e_plain)),
-            "e_v_dnnmg": float(np.mean(e_net)), "e_v_ratio": float(np.mean(e_net) / np.mean(e_plain))}
+            "e_v_dnnmg": float(np.mean(e_net)), "e_v_ratio": float(np.mean(e_net) / np.mean(e_plain)),
+            "paper_network": {"form": "240-512x8-81, batch normalisation (batch statistics in training, folded "
+                                      "for inference), skip connections; torch autograd FP32 training, 400 AdamW "
+                                      "steps at batch 16,384; BF16 library forward",
+                              "seconds_training": t_paper, "final_loss": ploss,
+                              "e_v_dnnmg": float(np.mean(e_paper)),
+                              "e_v_ratio": float(np.mean(e_paper) / np.mean(e_plain))}}
 
 
 def kernels_at_scale():

@@ -211,11 +211,11 @@ def plain_correction_pairs(box, ns, inputs, sweeps=4, device="cuda:0"):
     return X, T, etas
 
 
-def standardisation(X32):
+def standardisation(X32, n_in=L.N_IN):
     """Per-feature shift and inverse scale (R9 standardisation) of FP32
-    inputs [rows][192]: mean and 1/std over the rows (constant features keep
-    scale 1)."""
-    A = X32[:, :L.N_IN].double()
+    inputs [rows][ld]: mean and 1/std over the rows of the first n_in
+    columns (constant features keep scale 1)."""
+    A = X32[:, :n_in].double()
     mu, sd = A.mean(0), A.std(0)
     ok = sd > 1e-12 * torch.clamp(mu.abs(), min=1.0)
     inv = torch.where(ok, 1.0 / torch.where(ok, sd, torch.ones_like(sd)), torch.ones_like(sd))
@@ -342,3 +342,90 @@ def gather_targets(box, xc_list, vnext_list, device="cuda:0"):
         L.dnnmg_patch_gather(box, dv, dv, Tpad, L.F32, LDX)
         T[s * npch:(s + 1) * npch] = Tpad.view(npch, LDX)[:, :L.N_OUT]
     return T
+
+
+def paper_inputs(box, ns, xc_list, vprev_list, hidden=512, device="cuda:0"):
+    """The paper's network inputs of many steps (Sec. 4.2: velocities,
+    pressure, the four residuals and 24 geometry features per patch) through
+    the library's prolongation, residual and dnnmg_patch_gather_paper, not
+    standardised: FP32 [steps * N_p][ldx]."""
+    dev = torch.device(device)
+    nf, nc, npch = L.box_sizes(box)
+    ldx = L.deepnet_widths(240, hidden, L.N_OUT)[0]
+    xc = torch.zeros(4 * nc, dtype=torch.float64, device=dev)
+    vp = torch.zeros(3 * nf, dtype=torch.float32, device=dev)
+    xt = torch.zeros(4 * nf, dtype=torch.float32, device=dev)
+    r = torch.zeros(4 * nf, dtype=torch.float32, device=dev)
+    ws = torch.zeros(L.residual_workspace_bytes(box), dtype=torch.uint8, device=dev)
+    X = torch.zeros(len(xc_list) * npch, ldx, dtype=torch.float32, device=dev)
+    for s, (c, v) in enumerate(zip(xc_list, vprev_list)):
+        xc.copy_(torch.as_tensor(c).to(dev, torch.float64).reshape(-1))
+        vp.copy_(torch.as_tensor(v).to(dev, torch.float32).reshape(-1))
+        L.dnnmg_prolong(box, xc, xt)
+        L.dnnmg_residual(box, ns, xt, vp, r, ws)
+        L.dnnmg_patch_gather_paper(box, 1, xt, r, X[s * npch:(s + 1) * npch], L.F32, ldx)
+    return X
+
+
+class PaperNet(torch.nn.Module):
+    """The paper's network form for training (Sec. 3): no biases, batch
+    normalisation before each tanh (batch statistics in training), skip
+    connections on the hidden layers after the first."""
+
+    def __init__(self, n_in, hidden, n_out, depth=8):
+        super().__init__()
+        self.lin = torch.nn.ModuleList([torch.nn.Linear(n_in, hidden, bias=False)] +
+                                       [torch.nn.Linear(hidden, hidden, bias=False) for _ in range(depth - 1)])
+        self.bn = torch.nn.ModuleList([torch.nn.BatchNorm1d(hidden, eps=1e-5) for _ in range(depth)])
+        self.out = torch.nn.Linear(hidden, n_out, bias=False)
+
+    def forward(self, x):
+        a = x
+        for i, (lin, bn) in enumerate(zip(self.lin, self.bn)):
+            h = torch.tanh(bn(lin(a)))
+            a = h if i == 0 else h + a
+        return self.out(a)
+
+
+def train_paper_network(X, T, n_in=240, hidden=512, depth=8, steps=400, batch=65536, lr=1e-3, seed=0,
+                        device="cuda:0"):
+    """Trains the paper's network form with torch autograd (FP32, AdamW) on
+    standardised inputs X [rows][>= n_in] and targets T [rows][81] (scaled
+    by one scalar, folded back into the output layer).  The batch
+    normalisations' statistics are then taken over all rows (their running
+    averages at the final weights), for the folded inference of
+    dnnmg_deepnet_prepare.  Returns ((Ws, gammas, betas, means, stds),
+    module, target scale, final loss)."""
+    dev = torch.device(device)
+    torch.manual_seed(seed)
+    net = PaperNet(n_in, hidden, L.N_OUT, depth).to(dev)
+    t_scale = float(T.double().std().item())
+    Tn = T / t_scale
+    Xi = X[:, :n_in].contiguous()
+    opt = torch.optim.AdamW(net.parameters(), lr=lr, weight_decay=1e-5)
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    rows = Xi.shape[0]
+    bsz = min(batch, rows)
+    loss = None
+    for _ in range(steps):
+        idx = torch.randint(0, rows, (bsz,), device=dev, generator=g)
+        opt.zero_grad(set_to_none=True)
+        loss = torch.mean(torch.sum((net(Xi[idx]) - Tn[idx]) ** 2, dim=1))
+        loss.backward()
+        opt.step()
+    # population statistics of every normalisation at the final weights
+    for bn in net.bn:
+        bn.reset_running_stats()
+        bn.momentum = None
+    with torch.no_grad():
+        for b0 in range(0, rows, bsz):
+            net(Xi[b0:b0 + bsz])
+    net.eval()
+    Ws = [lin.weight.detach().t().double().cpu().numpy() for lin in net.lin]
+    Ws.append(net.out.weight.detach().t().double().cpu().numpy() * t_scale)
+    gammas = [bn.weight.detach().double().cpu().numpy() for bn in net.bn]
+    betas = [bn.bias.detach().double().cpu().numpy() for bn in net.bn]
+    means = [bn.running_mean.detach().double().cpu().numpy() for bn in net.bn]
+    stds = [np.sqrt(bn.running_var.detach().double().cpu().numpy() + bn.eps) for bn in net.bn]
+    return (Ws, gammas, betas, means, stds), net, t_scale, float(loss.item())

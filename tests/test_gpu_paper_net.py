@@ -133,3 +133,52 @@ def test_step_with_paper_network(orc, dn, levels, dtype, tol):
         e = rel_l2(out[key], ref)
         say(f"  {key} rel-L2 {e:.2e}")
         assert e <= tol, key
+
+
+def test_paper_network_trained_with_batch_statistics(L):
+    """The paper's network form trained with batch statistics (Sec. 3; torch
+    autograd, FP32) on GPU-generated teacher-forced data of a small channel
+    (inputs of Sec. 4.2 from the library's gather), then folded into the
+    library's deep forward: the folded forward equals the module in
+    evaluation mode, and the network, run inside the correction step, lowers
+    the held-out velocity error (eq. (relerrors))."""
+    from paper_2307_14837_amd import stepper, train
+
+    box = syn.channel_box((16, 4, 4))
+    ns = syn.NSParams(1e-3, 0.005)
+    vf, vc = syn.channel_initial(box, amp=0.3, seed=2)
+    cb = syn.BoxSpec(tuple(n // 2 for n in box.n), box.len, box.periodic_mask, box.dirichlet_mask)
+    fbc, cbc = syn.channel_dirichlet(box, True), syn.channel_dirichlet(cb, True)
+    xc0 = np.zeros((4, box.n_coarse))
+    xc0[:3] = vc
+    steps, ntr = 40, 30
+    xcs, vbar, _, _ = train.teacher_forced(box, ns, vf, xc0, steps, fbc, cbc)
+    X = train.paper_inputs(box, ns, xcs[:ntr], vbar[:ntr])
+    shift, inv = train.standardisation(X, 240)
+    Xs = torch.zeros_like(X)
+    Xs[:, :240] = (X[:, :240] - shift) * inv
+    T = train.gather_targets(box, xcs[:ntr], vbar[1:ntr + 1])
+    params, net, t_scale, loss = train.train_paper_network(Xs, T, hidden=512, depth=8, steps=300, batch=4096)
+    say("paper network: final training loss", loss)
+    n = 2048
+    deep = L.DeepNet(L.F32, *params)
+    Y = torch.zeros(n * 81, dtype=torch.float32, device=dev())
+    L.dnnmg_deepnet_forward(deep, n, Xs[:n].contiguous().view(-1), Xs.shape[1], Y)
+    with torch.no_grad():
+        ref = (net(Xs[:n, :240]) * t_scale).double().cpu().numpy()
+    torch.cuda.synchronize()
+    err = rel_l2(Y.cpu().numpy().reshape(n, 81), ref)
+    say("  folded forward vs module (eval mode): rel-L2", err)
+    assert err <= 1e-4
+    st = stepper.CorrectionStep(box, ns, params, dtype="fp32", network="paper", shift=shift.cpu().numpy(),
+                                inv_scale=inv.cpu().numpy())
+    e_plain, e_net = [], []
+    for k in range(ntr + 1, steps + 1):
+        out = st.run_numpy(xcs[k - 1].cpu().numpy(), vbar[k - 1].cpu().numpy())
+        refv = vbar[k].cpu().numpy().astype(np.float64)
+        nrm = np.linalg.norm(refv)
+        e_plain.append(np.linalg.norm(out["xt"][:3] - refv) / nrm)
+        e_net.append(np.linalg.norm(out["vcorr"] - refv) / nrm)
+    ratio = float(np.mean(e_net) / np.mean(e_plain))
+    say(f"  held-out e_v: prolongation {np.mean(e_plain):.4e}, paper network {np.mean(e_net):.4e}, ratio {ratio:.3f}")
+    assert ratio < 0.9
