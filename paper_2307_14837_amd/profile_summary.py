@@ -11,6 +11,13 @@ probe runs in the same process:
 F.csv / W.csv are rocprofv3 `*_counter_collection.csv` files; probe.log is
 what `bench.py --pmc-probe` printed (its last JSON line is used).
 
+sq: a Markdown table of SQ counters (one or more `--pmc` passes, each its own
+csv) for the one kernel whose name contains --kernel, averaged over its
+dispatches, with per-wave values:
+
+    python -m paper_2307_14837_amd.profile_summary sq --kernel "k_residual<4, false>" \
+        --csv P1.csv --csv P2.csv --out profiles/sq_<kernel>_<workload>.md --command "..." --command "..."
+
 stats: a Markdown table of a `--kernel-trace --stats` run's kernel_stats.csv,
 or of its kernel_trace.csv restricted to the dispatches after the last one
 matching --after:
@@ -85,6 +92,24 @@ def stats(a):
     print("\n".join(lines))
 
 
+def sq(a):
+    vals = {}
+    for path in a.csv:
+        names = {r["Counter_Name"] for r in csv.DictReader(open(path))}
+        for c in names:
+            vals[c] = find(per_kernel(path, c), a.kernel)
+    waves = vals.get("SQ_WAVES", 0.0) or 1.0
+    lines = [f"# {a.title}", "", "Commands (one counter pass each; values averaged over the dispatches of the kernel):",
+             "", "```", *a.command, "```", "", "| counter | total | per wave |", "|---|---:|---:|"]
+    for c in sorted(vals):
+        lines.append(f"| {c} | {vals[c]:.4g} | {vals[c] / waves:.1f} |")
+    if a.note:
+        lines += ["", *a.note]
+    with open(a.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="mode", required=True)
@@ -96,6 +121,13 @@ def main():
     sp.add_argument("--command", default="")
     sp.add_argument("--title", default="rocprofv3 kernel statistics")
     sp.add_argument("--top", type=int, default=20)
+    sq_p = sub.add_parser("sq")
+    sq_p.add_argument("--csv", action="append", required=True, help="counter_collection.csv of one --pmc pass")
+    sq_p.add_argument("--kernel", required=True, help="substring naming exactly one kernel")
+    sq_p.add_argument("--out", required=True)
+    sq_p.add_argument("--command", action="append", default=[])
+    sq_p.add_argument("--note", action="append", default=[], help="a line of text appended after the table")
+    sq_p.add_argument("--title", default="SQ counters")
     ap_p = sub.add_parser("pmc")
     ap_p.add_argument("--fetch", required=True)
     ap_p.add_argument("--write", required=True)
@@ -105,6 +137,8 @@ def main():
     a = ap.parse_args()
     if a.mode == "stats":
         return stats(a)
+    if a.mode == "sq":
+        return sq(a)
     probe = [json.loads(l) for l in open(a.probe) if l.startswith('{"pmc_probe"')][-1]
     fetch = per_kernel(a.fetch, "FETCH_SIZE")
     write = per_kernel(a.write, "WRITE_SIZE")
