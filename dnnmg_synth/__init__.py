@@ -284,3 +284,34 @@ def channel_dirichlet(box: BoxSpec, fine: bool):
     vals[0, inflow] = channel_profile(p[1, inflow], p[2, inflow], box.len[1])
     vals[:3, walls] = 0.0
     return mask, vals
+
+
+# ------------------------------------------------- distorted hexahedral mesh --
+
+def distorted_coords(box: BoxSpec, amp: float = 0.15, seed: int = 0, modes: int = 2) -> np.ndarray:
+    """Fine node positions [3][N_f] of a smoothly distorted box (the synthetic
+    stand-in for the paper's curved hexahedral meshes): the lattice positions
+    plus, per component a, amp * H_a * sum_m s_m sin(pi k_a X_a / L_a)
+    cos(2 pi k_b X_b / L_b + phi) cos(2 pi k_c X_c / L_c + psi), H_a the
+    element size L_a / n_a, wavenumbers of about a quarter of the element
+    count and random phases.  The displacement normal to each face vanishes
+    on it, so the domain stays the box and boundary nodes slide along their
+    faces.  Non-periodic boxes only."""
+    if box.periodic_mask:
+        raise ValueError("distorted meshes have no periodic axes")
+    rng = np.random.default_rng(seed)
+    P = node_coords(box, fine=True)
+    H = [box.len[a] / box.n[a] for a in range(3)]
+    out = P.copy()
+    for a in range(3):
+        b, c = (a + 1) % 3, (a + 2) % 3
+        for _ in range(modes):
+            ka = max(1, box.n[a] // 4) * int(rng.integers(1, 3))
+            kb = int(rng.integers(0, max(1, box.n[b] // 4) + 1))
+            kc = int(rng.integers(0, max(1, box.n[c] // 4) + 1))
+            s = rng.uniform(0.5, 1.0) * (1 if rng.random() < 0.5 else -1) / modes
+            phi, psi = rng.uniform(0, 2 * np.pi, 2)
+            out[a] += (amp * H[a] * s * np.sin(np.pi * ka * P[a] / box.len[a])
+                       * np.cos(2 * np.pi * kb * P[b] / box.len[b] + phi)
+                       * np.cos(2 * np.pi * kc * P[c] / box.len[c] + psi))
+    return out
