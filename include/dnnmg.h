@@ -584,6 +584,55 @@ int dnnmg_coarse_jv(const dnnmg_box *box, const dnnmg_ns *ns, const float *x, co
 int dnnmg_coarse_vcycle(const dnnmg_box *box, const dnnmg_ns *ns, const float *x, const float *s, float *z,
                         const dnnmg_coarse_opts *opts, void *ws, size_t ws_bytes, void *stream);
 
+
+/* The paper's discretisation (Sec. 2.2): equal-order Q2 elements for
+ * velocity and pressure on hexahedral meshes with curved (isoparametric)
+ * cells, local projection stabilisation of eq. (disc:ns) with pi_h the
+ * interpolation Q2 -> Q1 on each element, the Crank-Nicolson system of eq.
+ * (4cranknicholson3) with the parameters of eq. (stabparams).
+ *   Mesh: the topology of `box` (no periodic axes; box->len is not used):
+ *   n[a] fine Q2 elements per axis, 2 n[a] + 1 nodes per axis, node index as
+ *   above; element (I, J, K) holds the 27 nodes (2I + a, 2J + b, 2K + c)
+ *   and maps the reference cube by the Q2 interpolation of their positions
+ *   coords (device FP64 [3][n_fine], every element with a positive Jacobian
+ *   determinant).  The elements are the patches of Sec. 4.2 (one per cell
+ *   of level L), so the dof map, dnnmg_scatter_avg and the patch network
+ *   apply unchanged.  The coarse Q2 mesh (level L) has the elements of
+ *   2 x 2 x 2 fine elements (n[a] even) and the nodes with even indices.
+ *   pi_h: Q1 interpolation of the element's 8 vertex values; h_T: the
+ *   largest distance between two vertices of T; |v|_inf,T: the largest |v|
+ *   over T's 27 nodes; 3 x 3 x 3 Gauss points per element; FP32 arithmetic.
+ *   Element vectors are summed colour by colour (elements with equal index
+ *   parities share no node), so results are reproducible bit for bit.
+ * dnnmg_q2_residual_b: r = b - A(x), A holding the iterate's terms of eq.
+ *   (4cranknicholson3) and the LPS terms; x FP32 [4][n_fine], b FP32
+ *   [4][n_fine], r FP32 [4][n_fine] output (not aliasing x or b), velocity
+ *   rows on Dirichlet faces 0.
+ * dnnmg_q2_rhs: b = (1/k)(v_a, phi) - 1/2 (v.grad v_a, phi) - nu/2 (grad v_a,
+ *   grad phi) + (fmid_a, phi) (Algorithm 1, "Rhs"); v FP32 [3][n_fine],
+ *   fmid FP32 [3][n_fine] or NULL, b FP32 [4][n_fine] (pressure and Dirichlet
+ *   velocity rows 0). */
+int dnnmg_q2_residual_b(const dnnmg_box *box, const dnnmg_ns *ns, const double *coords, const float *x,
+                        const float *b, float *r, void *stream);
+int dnnmg_q2_rhs(const dnnmg_box *box, const dnnmg_ns *ns, const double *coords, const float *v,
+                 const float *fmid, float *b, void *stream);
+/* Prolongation of Algorithm 1 between the Q2 spaces: each fine node takes the
+ * Q2 interpolant of its coarse element (reference coordinates) in FP64,
+ * rounded to FP32.  xc FP64 [ncomp][n_coarse] -> xf FP32 [ncomp][n_fine],
+ * 1 <= ncomp <= 4, n[a] even.  dnnmg_q2_restrict is its transpose applied to
+ * a fine dual vector, accumulated in FP64: bf FP32 [ncomp][n_fine] -> bc FP64
+ * [ncomp][n_coarse]. */
+int dnnmg_q2_prolong(const dnnmg_box *box, int ncomp, const double *xc, float *xf, void *stream);
+int dnnmg_q2_restrict(const dnnmg_box *box, int ncomp, const float *bf, double *bc, void *stream);
+/* Operator Q of eq. (defQ) on the fine Q2 elements with geometry inputs for
+ * curved cells (Sec. 4.2): row M = [u, v, w at the 27 nodes, r_u, r_v, r_w
+ * there, g0, g1, g2], g_a the mean length of the element's 4
+ * vertex-to-vertex edges along axis a (the cell sizes on axis-parallel
+ * cells), standardised by `feat` (165 floats each or NULL), stored as FP32
+ * or BF16 in X [n_patches][ldx], ldx >= 165, padding columns zero. */
+int dnnmg_q2_patch_gather(const dnnmg_box *box, const double *coords, const float *x, const float *r,
+                          const dnnmg_feat *feat, int dtype, void *X, int64_t ldx, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

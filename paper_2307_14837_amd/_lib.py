@@ -169,6 +169,11 @@ _sig("dnnmg_coarse_workspace", [_P(Box), _P(CoarseOpts)], c_sz)
 _sig("dnnmg_coarse_solve", [_P(Box), _P(NS), c_vp, c_vp, _P(CoarseOpts), c_vp, c_vp, c_sz, c_vp])
 _sig("dnnmg_coarse_jv", [_P(Box), _P(NS), c_vp, c_vp, c_vp, _P(CoarseOpts), c_vp, c_sz, c_vp])
 _sig("dnnmg_coarse_vcycle", [_P(Box), _P(NS), c_vp, c_vp, c_vp, _P(CoarseOpts), c_vp, c_sz, c_vp])
+_sig("dnnmg_q2_residual_b", [_P(Box), _P(NS), c_vp, c_vp, c_vp, c_vp, c_vp])
+_sig("dnnmg_q2_rhs", [_P(Box), _P(NS), c_vp, c_vp, c_vp, c_vp, c_vp])
+_sig("dnnmg_q2_prolong", [_P(Box), ctypes.c_int, c_vp, c_vp, c_vp])
+_sig("dnnmg_q2_restrict", [_P(Box), ctypes.c_int, c_vp, c_vp, c_vp])
+_sig("dnnmg_q2_patch_gather", [_P(Box), c_vp, c_vp, c_vp, _P(Feat), ctypes.c_int, c_vp, c_i64, c_vp])
 
 EXPORTS = [
     "dnnmg_version", "dnnmg_last_error", "dnnmg_box_sizes", "dnnmg_patch_dofmap", "dnnmg_prolong",
@@ -187,7 +192,8 @@ EXPORTS = [
     "dnnmg_patch_dofmap_levels", "dnnmg_prolong_levels", "dnnmg_restrict_levels", "dnnmg_patch_gather_levels",
     "dnnmg_scatter_avg_levels", "dnnmg_deepnet_widths", "dnnmg_deepnet_packed_bytes", "dnnmg_deepnet_prepare",
     "dnnmg_deepnet_forward", "dnnmg_patch_gather_paper", "dnnmg_coarse_levels", "dnnmg_coarse_workspace",
-    "dnnmg_coarse_solve", "dnnmg_coarse_jv", "dnnmg_coarse_vcycle",
+    "dnnmg_coarse_solve", "dnnmg_coarse_jv", "dnnmg_coarse_vcycle", "dnnmg_q2_residual_b", "dnnmg_q2_rhs",
+    "dnnmg_q2_prolong", "dnnmg_q2_restrict", "dnnmg_q2_patch_gather",
 ]
 
 # network widths per prediction depth J (levels): inputs, outputs, padded input row
@@ -801,3 +807,47 @@ def dnnmg_coarse_vcycle(box, ns, x, s, z, opts: CoarseOpts, ws, stream=None):
                                     _ptr(s, torch.float32, 4 * nc, "s"), _ptr(z, torch.float32, 4 * nc, "z"),
                                     ctypes.byref(opts), _ptr(ws, None, None, "ws"), ws.numel() * ws.element_size(),
                                     _stream(stream)))
+
+
+# ---------------------------------------- Q2/Q2 elements on curved hexahedra --
+
+def dnnmg_q2_residual_b(box, ns, coords, x, b, r, stream=None):
+    bx = Box.of(box)
+    nf, _, _ = box_sizes(bx)
+    _check(_lib.dnnmg_q2_residual_b(ctypes.byref(bx), ctypes.byref(NS.of(ns)),
+                                    _ptr(coords, torch.float64, 3 * nf, "coords"),
+                                    _ptr(x, torch.float32, 4 * nf, "x"), _ptr(b, torch.float32, 4 * nf, "b"),
+                                    _ptr(r, torch.float32, 4 * nf, "r"), _stream(stream)))
+
+
+def dnnmg_q2_rhs(box, ns, coords, v, b_out, fmid=None, stream=None):
+    bx = Box.of(box)
+    nf, _, _ = box_sizes(bx)
+    _check(_lib.dnnmg_q2_rhs(ctypes.byref(bx), ctypes.byref(NS.of(ns)), _ptr(coords, torch.float64, 3 * nf, "coords"),
+                             _ptr(v, torch.float32, 3 * nf, "v"), _ptr(fmid, torch.float32, 3 * nf, "fmid"),
+                             _ptr(b_out, torch.float32, 4 * nf, "b"), _stream(stream)))
+
+
+def dnnmg_q2_prolong(box, xc, xf, ncomp=4, stream=None):
+    bx = Box.of(box)
+    nf, nc, _ = box_sizes(bx)
+    _check(_lib.dnnmg_q2_prolong(ctypes.byref(bx), ncomp, _ptr(xc, torch.float64, ncomp * nc, "xc"),
+                                 _ptr(xf, torch.float32, ncomp * nf, "xf"), _stream(stream)))
+
+
+def dnnmg_q2_restrict(box, bf, bc, ncomp=4, stream=None):
+    bx = Box.of(box)
+    nf, nc, _ = box_sizes(bx)
+    _check(_lib.dnnmg_q2_restrict(ctypes.byref(bx), ncomp, _ptr(bf, torch.float32, ncomp * nf, "bf"),
+                                  _ptr(bc, torch.float64, ncomp * nc, "bc"), _stream(stream)))
+
+
+def dnnmg_q2_patch_gather(box, coords, x, r, X, dtype, ldx, shift=None, inv_scale=None, stream=None):
+    bx = Box.of(box)
+    nf, _, npch = box_sizes(bx)
+    feat = Feat(_ptr(shift, torch.float32, 165, "shift"), _ptr(inv_scale, torch.float32, 165, "inv_scale"))
+    if X.numel() * X.element_size() < npch * ldx * {F32: 4, BF16: 2}[dtype]:
+        raise ValueError("X too small")
+    _check(_lib.dnnmg_q2_patch_gather(ctypes.byref(bx), _ptr(coords, torch.float64, 3 * nf, "coords"),
+                                      _ptr(x, torch.float32, 3 * nf, "x"), _ptr(r, torch.float32, 3 * nf, "r"),
+                                      ctypes.byref(feat), dtype, _ptr(X, None, None, "X"), ldx, _stream(stream)))

@@ -250,3 +250,102 @@ class CorrectionStep:
             out["eta"] = float(np.sqrt(n[1] / n[0])) if n[0] > 0 else float("inf")
             out["fell_back"] = int(self.fell_back.item())
         return out
+
+
+class Q2CorrectionStep:
+    """One correction step of Algorithm 1 on the paper's discretisation
+    (Sec. 2.2: Q2/Q2 elements on curved hexahedra, LPS with pi_h: Q2 -> Q1):
+    x~ = P xc (Q2 interpolation); r = b - A(x~); X = Q(x~, r, geometry);
+    Y = N(X); x_corr = (v~ + L(Y), p~); optionally the indicator's residual
+    r(x_corr) and the two FP64 norms; b = Rhs(v_corr); bc = R b.
+
+    The fine Q2 elements are the patches (27 nodes each), so the network,
+    the dof map and the extension are those of the Q1 step.  coords: node
+    positions [3][n_fine] (FP64).  b is carried from step to step as in the
+    Q1 step (load() computes the first one from vprev).  The fallback of the
+    Q1 step (its patch-Vanka sweeps are built for Q1) is not part of this
+    step: with indicator=True, eta is computed and reported only."""
+
+    def __init__(self, box, ns, coords, params, dtype="bf16", device="cuda:0", shift=None, inv_scale=None,
+                 indicator=False):
+        self.box = L.Box.of(box)
+        self.ns = L.NS.of(ns)
+        self.dev = torch.device(device)
+        self.dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+        self.nf, self.nc, self.np = L.box_sizes(self.box)
+        self.n_in, self.n_out, self.ldx = L.LEVEL_IO[1]
+        self.hidden = int(np.shape(params[0])[1])
+        self.indicator = indicator
+        f32 = dict(dtype=torch.float32, device=self.dev)
+        f64 = dict(dtype=torch.float64, device=self.dev)
+        self.coords = torch.as_tensor(np.ascontiguousarray(coords, np.float64).ravel()).to(self.dev)
+        self.xc = torch.zeros(4 * self.nc, **f64)
+        self.xt = torch.zeros(4 * self.nf, **f32)
+        self.vprev = torch.zeros(3 * self.nf, **f32)
+        self.r = torch.zeros(4 * self.nf, **f32)
+        self.xdtype = L.F32 if self.dtype == L.F32 else L.BF16
+        self.X = torch.zeros(self.np * self.ldx, dtype=_TORCH[self.xdtype], device=self.dev)
+        self.Y = torch.zeros(self.np * self.n_out, **f32)
+        self.xcorr = torch.zeros(4 * self.nf, **f32)
+        self.b = torch.zeros(4 * self.nf, **f32)
+        self.bc = torch.zeros(4 * self.nc, **f64)
+        if indicator:
+            self.r2 = torch.zeros(4 * self.nf, **f32)
+            self.norms = torch.zeros(2, **f64)
+            self.ws_norm = torch.zeros(2 * L.norm2_workspace_bytes(), dtype=torch.uint8, device=self.dev)
+        self.shift = None if shift is None else torch.as_tensor(np.asarray(shift, np.float32)).to(self.dev)
+        self.inv_scale = None if inv_scale is None else torch.as_tensor(np.asarray(inv_scale, np.float32)).to(self.dev)
+        W32 = [torch.as_tensor(np.asarray(params[2 * l], np.float32)).contiguous().to(self.dev) for l in range(3)]
+        bias = [torch.as_tensor(np.asarray(params[2 * l + 1], np.float32)).contiguous().to(self.dev) for l in range(3)]
+        self.prepared = L.mlp_prepare(self.dtype, self.hidden, W32, bias, device=self.dev)
+        self.net = self.prepared.net
+        self.graph = None
+
+    def load(self, xc, vprev):
+        self.xc.copy_(torch.as_tensor(np.asarray(xc, np.float64).ravel()))
+        self.vprev.copy_(torch.as_tensor(np.asarray(vprev, np.float32).ravel()))
+        L.dnnmg_q2_rhs(self.box, self.ns, self.coords, self.vprev, self.b)
+
+    def step(self, stream=None):
+        box, ns = self.box, self.ns
+        L.dnnmg_q2_prolong(box, self.xc, self.xt, stream=stream)
+        L.dnnmg_q2_residual_b(box, ns, self.coords, self.xt, self.b, self.r, stream=stream)
+        L.dnnmg_q2_patch_gather(box, self.coords, self.xt, self.r, self.X, self.xdtype, self.ldx, self.shift,
+                                self.inv_scale, stream=stream)
+        L.dnnmg_patch_forward(self.net, self.np, self.X, self.ldx, self.Y, stream=stream)
+        L.dnnmg_scatter_avg(box, self.Y, self.xcorr, vbase=self.xt, stream=stream)
+        if self.indicator:
+            L.dnnmg_q2_residual_b(box, ns, self.coords, self.xcorr, self.b, self.r2, stream=stream)
+            L.dnnmg_norm2_pair_f64(self.r, self.r2, self.norms, self.ws_norm, stream=stream)
+        L.dnnmg_q2_rhs(box, ns, self.coords, self.xcorr, self.b, stream=stream)
+        L.dnnmg_q2_restrict(box, self.b, self.bc, stream=stream)
+
+    def capture(self):
+        self.graph = L.capture_graph(self.step, device=self.dev)
+        return self.graph
+
+    def replay(self, stream=None):
+        self.graph.replay(stream)
+
+    def run_numpy(self, xc, vprev):
+        self.load(xc, vprev)
+        b_in = self.b.cpu().numpy().reshape(4, -1).astype(np.float64)
+        self.step()
+        torch.cuda.synchronize(self.dev)
+        xt = self.xt.cpu().numpy().reshape(4, -1).astype(np.float64)
+        xcorr = self.xcorr.cpu().numpy().reshape(4, -1).astype(np.float64)
+        out = {
+            "b_in": b_in,
+            "xt": xt,
+            "r": self.r.cpu().numpy().reshape(4, -1).astype(np.float64),
+            "Y": self.Y.cpu().numpy().reshape(-1, self.n_out).astype(np.float64),
+            "vcorr": xcorr[:3],
+            "d": xcorr[:3] - xt[:3],
+            "b": self.b.cpu().numpy().reshape(4, -1).astype(np.float64),
+            "bc": self.bc.cpu().numpy().reshape(4, -1),
+        }
+        if self.indicator:
+            n = self.norms.cpu().numpy()
+            out["r2"] = self.r2.cpu().numpy().reshape(4, -1).astype(np.float64)
+            out["eta"] = float(np.sqrt(n[1] / n[0])) if n[0] > 0 else float("inf")
+        return out

@@ -116,3 +116,34 @@ def test_coarse_step_host_logic():
     rc = lib.dnnmg_coarse_solve(ctypes.byref(L.Box.of(big)), ctypes.byref(L.NS.of(syn.cfg5().ns)), None, None,
                                 ctypes.byref(o), None, None, 0, None)
     assert rc == -1
+
+
+def test_q2_host_validation_without_gpu():
+    """The Q2 entry points check the mesh, the parameters and the pointers
+    before anything is enqueued."""
+    import dnnmg_synth as syn
+    import paper_2307_14837_amd as L
+
+    lib = L._lib.lib()
+    ns = L.NS.of(syn.cfg2().ns)
+    per = L.Box.of(syn.BoxSpec((4, 4, 4), (1, 1, 1), 1, 0))
+    rc = lib.dnnmg_q2_residual_b(ctypes.byref(per), ctypes.byref(ns), None, None, None, None, None)
+    assert rc == -2 and b"periodic" in lib.dnnmg_last_error()
+    box = L.Box.of(syn.channel_box((5, 2, 2)))
+    rc = lib.dnnmg_q2_residual_b(ctypes.byref(box), ctypes.byref(ns), None, None, None, None, None)
+    assert rc == -1 and b"NULL" in lib.dnnmg_last_error()
+    bad = L.NS(1e-3, 0.0, 0.02, 0.1)
+    rc = lib.dnnmg_q2_rhs(ctypes.byref(box), ctypes.byref(bad), None, None, None, None, None)
+    assert rc == -1 and b"dt" in lib.dnnmg_last_error()
+    # the coarse Q2 mesh needs even element counts
+    rc = lib.dnnmg_q2_prolong(ctypes.byref(box), 4, None, None, None)
+    assert rc == -2 and b"even" in lib.dnnmg_last_error()
+    even = L.Box.of(syn.channel_box((4, 2, 2)))
+    assert lib.dnnmg_q2_restrict(ctypes.byref(even), 0, None, None, None) == -1
+    assert lib.dnnmg_q2_prolong(ctypes.byref(even), 4, None, None, None) == -1
+    p = ctypes.c_void_p(16)
+    feat = L.Feat(None, None)
+    rc = lib.dnnmg_q2_patch_gather(ctypes.byref(even), p, p, p, ctypes.byref(feat), L.FP8_E4M3, p, 192, None)
+    assert rc == -3
+    rc = lib.dnnmg_q2_patch_gather(ctypes.byref(even), p, p, p, ctypes.byref(feat), L.F32, p, 100, None)
+    assert rc == -2
