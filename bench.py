@@ -55,6 +55,8 @@ def parse():
                     help="run only the headline step's dominant kernel and a plain copy (for rocprofv3 --pmc)")
     ap.add_argument("--scale-only", action="store_true",
                     help="run only the per-kernel measurements on the large channel (for rocprofv3)")
+    ap.add_argument("--q2-step", action="store_true",
+                    help="run only the Q2 step's graph replays on the large channel (for rocprofv3)")
     ap.add_argument("--cpu-worker", type=int, default=None, help=argparse.SUPPRESS)
     return ap.parse_args()
 
@@ -567,6 +569,75 @@ def run_coarse_step():
             "residual_norms": [float(v) for v in res.cpu().numpy()]}
 
 
+def q2_step(dtype="fp8", hidden=512, seed=0):
+    """The correction step on the paper's discretisation (Q2/Q2 elements on
+    curved hexahedra) for the large channel's mesh: 128 x 32 x 32 fine Q2
+    elements (the patches), 1,085,825 nodes, interior nodes displaced
+    smoothly by up to 0.15 element sizes; seeded network weights; indicator
+    evaluated."""
+    import dnnmg_synth as syn
+    from paper_2307_14837_amd import stepper
+
+    w = syn.cfg5()
+    X = syn.distorted_coords(w.box, amp=0.15, seed=seed)
+    inp = syn.step_inputs(w, seed=seed)
+    params = syn.mlp_params(165, hidden, 81, seed=seed)
+    st = stepper.Q2CorrectionStep(w.box, w.ns, X, params, dtype=dtype, indicator=True)
+    st.load(inp.xc, inp.vprev)
+    return w, st
+
+
+def run_q2_step(steps, warmup):
+    """Graph replays of the Q2 correction step (each replay's right-hand side
+    feeds the next one's residual) and each launch timed alone."""
+    from paper_2307_14837_amd import _lib as L
+    from paper_2307_14837_amd import flops
+
+    w, st = q2_step()
+    t = time_graph(st, steps, warmup)
+    box, ns = st.box, st.ns
+    k = {
+        "q2_prolong": lambda: L.dnnmg_q2_prolong(box, st.xc, st.xt),
+        "q2_residual_b": lambda: L.dnnmg_q2_residual_b(box, ns, st.coords, st.xt, st.b, st.r),
+        "gather_forward": lambda: L.dnnmg_patch_gather_forward_geom(box, st.net, st.geom, st.xt, st.r, st.Y),
+        "scatter": lambda: L.dnnmg_scatter_avg(box, st.Y, st.xcorr, vbase=st.xt),
+        "q2_residual_b_indicator": lambda: L.dnnmg_q2_residual_b(box, ns, st.coords, st.xcorr, st.b, st.r2),
+        "norm2_pair": lambda: L.dnnmg_norm2_pair_f64(st.r, st.r2, st.norms, st.ws_norm),
+        "q2_rhs": lambda: L.dnnmg_q2_rhs(box, ns, st.coords, st.xcorr, st.b),
+        "q2_restrict": lambda: L.dnnmg_q2_restrict(box, st.b, st.bc),
+    }
+    st.step()
+    kms = {name: time_kernel(fn, 10) for name, fn in k.items()}
+    ne = st.np
+    res_flop = flops.q2_residual_flops_per_element() * ne
+    rhs_flop = flops.q2_rhs_flops_per_element() * ne
+    n = st.norms.cpu().numpy()
+    return {"workload": "cfg5_channel_128x32x32_q2_curved", "elements": ne, "fine_nodes": st.nf,
+            "discretisation": "Q2/Q2 on curved hexahedra (isoparametric), LPS with pi_h: Q2 -> Q1, "
+                              "3x3x3 Gauss points, FP32",
+            "network": "165-512-512-81 FP8 (seeded weights)", "dtype": "fp8", "indicator": True,
+            "ms_per_step": t["ms"], "median_ms": t["median_ms"], "min_ms": t["min_ms"],
+            "patches_per_s": ne / (t["ms"] * 1e-3), "kernel_ms": kms,
+            "q2_residual": {"flop_per_element": flops.q2_residual_flops_per_element(),
+                            "tflops": res_flop / (kms["q2_residual_b"] * 1e-3) / 1e12,
+                            "frac_of_fp32_vector_peak": res_flop / (kms["q2_residual_b"] * 1e-3) / 1e12
+                            / FP32_VALU_PEAK_TFLOPS},
+            "q2_rhs_tflops": rhs_flop / (kms["q2_rhs"] * 1e-3) / 1e12,
+            "eta_last": float(np.sqrt(n[1] / n[0])) if n[0] > 0 else None}
+
+
+def q2_profile(steps):
+    """Only the Q2 step's graph replays (for rocprofv3 --kernel-trace)."""
+    w, st = q2_step()
+    st.capture()
+    for _ in range(steps):
+        st.replay()
+    import torch
+
+    torch.cuda.synchronize()
+    print(json.dumps({"q2_profile": "cfg5_channel_128x32x32_q2_curved", "replays": steps}), flush=True)
+
+
 def run_time_loop(w, params, shift, inv, steps=5):
     """Whole time steps of Algorithm 1 on the GPU, one graph each: the coarse
     problem (b^L the restriction of the previous step's fine Rhs) by the GPU
@@ -815,6 +886,9 @@ def main():
     if args.pmc_probe:
         pmc_probe()
         return
+    if args.q2_step:
+        q2_profile(args.steps)
+        return
     if args.profile_step:
         profile_step(args.steps)
         return
@@ -895,6 +969,7 @@ def main():
             run_coarse_step(),
             run_time_loop(w, params, shift, inv),
             run_config4(),
+            run_q2_step(sv, wv),
         ]
         out["variants"] = variants
         print("[bench] kernels on the large channel", file=sys.stderr, flush=True)

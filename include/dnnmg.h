@@ -624,14 +624,20 @@ int dnnmg_q2_rhs(const dnnmg_box *box, const dnnmg_ns *ns, const double *coords,
  * [ncomp][n_coarse]. */
 int dnnmg_q2_prolong(const dnnmg_box *box, int ncomp, const double *xc, float *xf, void *stream);
 int dnnmg_q2_restrict(const dnnmg_box *box, int ncomp, const float *bf, double *bc, void *stream);
-/* Operator Q of eq. (defQ) on the fine Q2 elements with geometry inputs for
- * curved cells (Sec. 4.2): row M = [u, v, w at the 27 nodes, r_u, r_v, r_w
- * there, g0, g1, g2], g_a the mean length of the element's 4
- * vertex-to-vertex edges along axis a (the cell sizes on axis-parallel
- * cells), standardised by `feat` (165 floats each or NULL), stored as FP32
- * or BF16 in X [n_patches][ldx], ldx >= 165, padding columns zero. */
-int dnnmg_q2_patch_gather(const dnnmg_box *box, const double *coords, const float *x, const float *r,
-                          const dnnmg_feat *feat, int dtype, void *X, int64_t ldx, void *stream);
+/* Geometry inputs of Sec. 4.2 for curved cells, a setup call (the mesh is
+ * fixed): geom FP32 [n_patches][3], g_a of element M = the mean length of its
+ * 4 vertex-to-vertex edges along axis a (the cell sizes on axis-parallel
+ * cells), from coords as for dnnmg_q2_residual_b.  The rows feed
+ * dnnmg_patch_gather_geom / dnnmg_patch_gather_forward_geom. */
+int dnnmg_q2_patch_features(const dnnmg_box *box, const double *coords, float *geom, void *stream);
+/* dnnmg_patch_gather and dnnmg_patch_gather_forward with geometry inputs per
+ * patch: columns 162..164 of row M are geom[3M .. 3M+2] (device FP32
+ * [n_patches][3], not NULL; standardised by `feat` like every column)
+ * instead of the box's cell sizes; everything else as there. */
+int dnnmg_patch_gather_geom(const dnnmg_box *box, const float *geom, const float *x, const float *r,
+                            const dnnmg_feat *feat, int dtype, float x_scale, void *X, int64_t ldx, void *stream);
+int dnnmg_patch_gather_forward_geom(const dnnmg_box *box, const dnnmg_mlp *net, const float *geom, const float *xt,
+                                    const float *r, const dnnmg_feat *feat, float *Y, void *stream);
 
 #ifdef __cplusplus
 }

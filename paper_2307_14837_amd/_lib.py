@@ -173,7 +173,9 @@ _sig("dnnmg_q2_residual_b", [_P(Box), _P(NS), c_vp, c_vp, c_vp, c_vp, c_vp])
 _sig("dnnmg_q2_rhs", [_P(Box), _P(NS), c_vp, c_vp, c_vp, c_vp, c_vp])
 _sig("dnnmg_q2_prolong", [_P(Box), ctypes.c_int, c_vp, c_vp, c_vp])
 _sig("dnnmg_q2_restrict", [_P(Box), ctypes.c_int, c_vp, c_vp, c_vp])
-_sig("dnnmg_q2_patch_gather", [_P(Box), c_vp, c_vp, c_vp, _P(Feat), ctypes.c_int, c_vp, c_i64, c_vp])
+_sig("dnnmg_q2_patch_features", [_P(Box), c_vp, c_vp, c_vp])
+_sig("dnnmg_patch_gather_geom", [_P(Box), c_vp, c_vp, c_vp, _P(Feat), ctypes.c_int, c_f, c_vp, c_i64, c_vp])
+_sig("dnnmg_patch_gather_forward_geom", [_P(Box), _P(MLP), c_vp, c_vp, c_vp, _P(Feat), c_vp, c_vp])
 
 EXPORTS = [
     "dnnmg_version", "dnnmg_last_error", "dnnmg_box_sizes", "dnnmg_patch_dofmap", "dnnmg_prolong",
@@ -193,7 +195,8 @@ EXPORTS = [
     "dnnmg_scatter_avg_levels", "dnnmg_deepnet_widths", "dnnmg_deepnet_packed_bytes", "dnnmg_deepnet_prepare",
     "dnnmg_deepnet_forward", "dnnmg_patch_gather_paper", "dnnmg_coarse_levels", "dnnmg_coarse_workspace",
     "dnnmg_coarse_solve", "dnnmg_coarse_jv", "dnnmg_coarse_vcycle", "dnnmg_q2_residual_b", "dnnmg_q2_rhs",
-    "dnnmg_q2_prolong", "dnnmg_q2_restrict", "dnnmg_q2_patch_gather",
+    "dnnmg_q2_prolong", "dnnmg_q2_restrict", "dnnmg_q2_patch_features", "dnnmg_patch_gather_geom",
+    "dnnmg_patch_gather_forward_geom",
 ]
 
 # network widths per prediction depth J (levels): inputs, outputs, padded input row
@@ -842,12 +845,31 @@ def dnnmg_q2_restrict(box, bf, bc, ncomp=4, stream=None):
                                   _ptr(bc, torch.float64, ncomp * nc, "bc"), _stream(stream)))
 
 
-def dnnmg_q2_patch_gather(box, coords, x, r, X, dtype, ldx, shift=None, inv_scale=None, stream=None):
+def dnnmg_q2_patch_features(box, coords, geom, stream=None):
+    bx = Box.of(box)
+    nf, _, npch = box_sizes(bx)
+    _check(_lib.dnnmg_q2_patch_features(ctypes.byref(bx), _ptr(coords, torch.float64, 3 * nf, "coords"),
+                                        _ptr(geom, torch.float32, 3 * npch, "geom"), _stream(stream)))
+
+
+def dnnmg_patch_gather_geom(box, geom, x, r, X, dtype, ldx, shift=None, inv_scale=None, x_scale=1.0, stream=None):
     bx = Box.of(box)
     nf, _, npch = box_sizes(bx)
     feat = Feat(_ptr(shift, torch.float32, 165, "shift"), _ptr(inv_scale, torch.float32, 165, "inv_scale"))
-    if X.numel() * X.element_size() < npch * ldx * {F32: 4, BF16: 2}[dtype]:
+    if X.numel() * X.element_size() < npch * ldx * {F32: 4, BF16: 2, FP8_E4M3: 1}[dtype]:
         raise ValueError("X too small")
-    _check(_lib.dnnmg_q2_patch_gather(ctypes.byref(bx), _ptr(coords, torch.float64, 3 * nf, "coords"),
-                                      _ptr(x, torch.float32, 3 * nf, "x"), _ptr(r, torch.float32, 3 * nf, "r"),
-                                      ctypes.byref(feat), dtype, _ptr(X, None, None, "X"), ldx, _stream(stream)))
+    _check(_lib.dnnmg_patch_gather_geom(ctypes.byref(bx), _ptr(geom, torch.float32, 3 * npch, "geom"),
+                                        _ptr(x, torch.float32, 3 * nf, "x"), _ptr(r, torch.float32, 3 * nf, "r"),
+                                        ctypes.byref(feat), dtype, float(x_scale), _ptr(X, None, None, "X"), ldx,
+                                        _stream(stream)))
+
+
+def dnnmg_patch_gather_forward_geom(box, net, geom, xt, r, Y, shift=None, inv_scale=None, stream=None):
+    bx = Box.of(box)
+    nf, _, npch = box_sizes(bx)
+    feat = Feat(_ptr(shift, torch.float32, 165, "shift"), _ptr(inv_scale, torch.float32, 165, "inv_scale"))
+    _check(_lib.dnnmg_patch_gather_forward_geom(ctypes.byref(bx), ctypes.byref(net),
+                                                _ptr(geom, torch.float32, 3 * npch, "geom"),
+                                                _ptr(xt, torch.float32, 3 * nf, "xt"),
+                                                _ptr(r, torch.float32, 3 * nf, "r"), ctypes.byref(feat),
+                                                _ptr(Y, torch.float32, npch * N_OUT, "Y"), _stream(stream)))

@@ -101,6 +101,7 @@ struct BoxDesc {
     int64_t blk_full, blk_part; // residual tiles: prefix sums of full / partial tiles
     int32_t rtiles[3];          // residual tile grid of the box
     int32_t rfull[3];           // its box of full tiles (no node beyond the mesh)
+    const float *geom;          // geometry inputs per patch [n_patches][3], or null: the box's cell sizes
 };
 
 // Box holding block `blk` of a batched launch: the last b with first[b] <= blk.

@@ -385,7 +385,8 @@ __device__ __forceinline__ void put_input(unsigned char *buf, int pl, int col, f
 // Operator Q of eq. (defQ) with the standardisation, straight into the
 // layer-1 fragments: input column 27 c + iota of patch (I,J,K) is field c of
 // [u, v, w, r_u, r_v, r_w] at local node iota = a + 3 b + 9 c'; columns
-// 162..164 are the coarse cell sizes, 165..191 zero.  Lanes run over the
+// 162..164 are the geometry inputs (the patch's row of geom, or the coarse
+// cell sizes of the box when geom is null), 165..191 zero.  Lanes run over the
 // patches of the tile and waves over the local nodes: consecutive patches
 // of a row of the coarse mesh read fine nodes two apart, so a wave's load of
 // one field touches a few cache lines, and the standardisation constants of
@@ -393,7 +394,8 @@ __device__ __forceinline__ void put_input(unsigned char *buf, int pl, int col, f
 template <int K1, int NCH0, int PT, int NTHR>
 __device__ __forceinline__ void stage_gather(const Mesh &m, const float *__restrict__ xt, const float *__restrict__ r,
                                              const float *__restrict__ shift, const float *__restrict__ inv,
-                                             int64_t base, int64_t n, unsigned char *buf, int tid) {
+                                             const float *__restrict__ geom, int64_t base, int64_t n,
+                                             unsigned char *buf, int tid) {
     constexpr int NPL = 16 * PT, STEP = NTHR / NPL;
     static_assert(NTHR % NPL == 0, "a thread keeps one patch of the tile");
     const int pl = tid % NPL;
@@ -448,7 +450,7 @@ __device__ __forceinline__ void stage_gather(const Mesh &m, const float *__restr
         const float sh = shift ? shift[cc] : 0.0f, sc = inv ? inv[cc] : 1.0f;
         float v = 0.0f;
         if (col < N_IN && base + pl < n) {
-            v = m.H[col - 162];
+            v = geom ? geom[3 * (base + pl) + (col - 162)] : m.H[col - 162];
             if (shift) v -= sh;
             if (inv) v *= sc;
         }
@@ -496,7 +498,7 @@ __global__ void __launch_bounds__((FwdShape<DT, H, PT, J>::NTHR))
             base = (tile - d.blk_ptile) * 16 * PT;
             Y = Y_all + NO * d.off_patch;
             stage_gather<S::K1, S::NCH0, PT, S::NTHR>(d.m, xt_all + 4 * d.off_fine, r_all + 4 * d.off_fine, shift, inv,
-                                             base, n, buf0, tid);
+                                                      d.geom, base, n, buf0, tid);
         } else {
             n = n_rows;
             base = tile * 16 * PT;
@@ -935,8 +937,8 @@ extern "C" int dnnmg_patch_forward_tiles(const dnnmg_mlp *net, int64_t n, const 
                       Y, saved, (hipStream_t)stream);
 }
 
-extern "C" int dnnmg_patch_gather_forward(const dnnmg_box *box, const dnnmg_mlp *net, const float *xt,
-                                          const float *r, const dnnmg_feat *feat, float *Y, void *stream) {
+static int gather_forward(const dnnmg_box *box, const dnnmg_mlp *net, const float *geom, const float *xt,
+                          const float *r, const dnnmg_feat *feat, float *Y, void *stream) {
     int rc = check_net(net);
     if (rc) return rc;
     if (net->n_in != N_IN)
@@ -944,12 +946,25 @@ extern "C" int dnnmg_patch_gather_forward(const dnnmg_box *box, const dnnmg_mlp 
     BoxDesc one{};
     if ((rc = make_mesh(box, &one.m))) return rc;
     if (!xt || !r || !Y) return fail(DNNMG_ERR_ARG, "dnnmg_patch_gather_forward: NULL pointer");
+    one.geom = geom;
     const float *sh = feat ? feat->shift : nullptr;
     const float *sc = feat ? feat->inv_scale : nullptr;
     const int pt = fwd_default_pt(net, one.m.n_patches, device_cus());
     const int64_t ntiles = (one.m.n_patches + 16 * pt - 1) / (16 * pt);
     return fwd_launch(net, pt, true, ntiles, 0, 0, nullptr, 0, nullptr, 1, one, xt, r, sh, sc, Y, nullptr,
                       (hipStream_t)stream);
+}
+
+extern "C" int dnnmg_patch_gather_forward(const dnnmg_box *box, const dnnmg_mlp *net, const float *xt,
+                                          const float *r, const dnnmg_feat *feat, float *Y, void *stream) {
+    return gather_forward(box, net, nullptr, xt, r, feat, Y, stream);
+}
+
+extern "C" int dnnmg_patch_gather_forward_geom(const dnnmg_box *box, const dnnmg_mlp *net, const float *geom,
+                                               const float *xt, const float *r, const dnnmg_feat *feat, float *Y,
+                                               void *stream) {
+    if (!geom) return fail(DNNMG_ERR_ARG, "dnnmg_patch_gather_forward_geom: geom is NULL");
+    return gather_forward(box, net, geom, xt, r, feat, Y, stream);
 }
 
 // ------------------------------------------------- the paper's network ----

@@ -391,148 +391,142 @@ __device__ __forceinline__ void q2_pw(int i, int n, int idx[3], double w[3]) {
     w[2] = 2.0 * t * (t - 0.5);
 }
 
-__global__ void k_q2_prolong(Mesh m, int ncomp, const double *__restrict__ xc, float *__restrict__ xf) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= m.n_fine) return;
-    const int64_t jk = t / m.nf[0];
-    const int i = (int)(t - jk * m.nf[0]), j = (int)(jk % m.nf[1]), k = (int)(jk / m.nf[1]);
-    int ix[3], iy[3], iz[3];
-    double wx[3], wy[3], wz[3];
-    q2_pw(i, m.n[0], ix, wx);
+// Nonzero entries of column I of the 1-D prolongation (coarse node I on an
+// axis with n fine elements), padded to 5 with zero weights: a coarse vertex
+// (I even) reaches the fine nodes 2I + {-3, -1, 0, 1, 3} with weights
+// {-1/8, 3/8, 1, 3/8, -1/8}, a coarse mid node (I odd) the fine nodes
+// 2I + {-1, 0, 1} with {3/4, 1, 3/4} (the quadratic functions at the quarter
+// points); the offsets +-2 fall on coarse nodes, where the other functions
+// vanish.  Padding and out-of-range entries point at fine node 2I.
+__device__ __forceinline__ void q2_rcol(int I, int n, int fi[5], double w[5]) {
+    const int c = 2 * I;
+    const bool mid = I & 1;
+    const int off[5] = {-3, -1, 0, 1, 3};
+    const double wv[5] = {-0.125, 0.375, 1.0, 0.375, -0.125};
+    const double wm[5] = {0.0, 0.75, 1.0, 0.75, 0.0};
+#pragma unroll
+    for (int s = 0; s < 5; ++s) {
+        const int f = c + off[s];
+        const bool ok = f >= 0 && f <= 2 * n;
+        fi[s] = ok ? f : c;
+        w[s] = ok ? (mid ? wm[s] : wv[s]) : 0.0;
+    }
+}
+
+// Prolongation, one workgroup per fine lattice row (j, k): the (y, z)
+// weights are the same for the whole row, so each coarse x node is first
+// combined over its (y, z) stencil (into LDS), then every fine node of the
+// row takes its three x terms from there.  Coarse reads are coalesced along
+// x and each is made once per row.
+__global__ void __launch_bounds__(256) k_q2_prolong_rows(Mesh m, int ncomp, const double *__restrict__ xc,
+                                                         float *__restrict__ xf) {
+    extern __shared__ double sU[]; // [ncomp][nc0]
+    const int64_t row = blockIdx.x;
+    const int j = (int)(row % m.nf[1]), k = (int)(row / m.nf[1]);
+    int iy[3], iz[3];
+    double wy[3], wz[3];
     q2_pw(j, m.n[1], iy, wy);
     q2_pw(k, m.n[2], iz, wz);
-    for (int c = 0; c < ncomp; ++c) {
-        const double *src = xc + c * m.n_coarse;
+    const int nc0 = m.nc[0];
+    for (int t = threadIdx.x; t < ncomp * nc0; t += blockDim.x) {
+        const int c = t / nc0, I = t - c * nc0;
+        const double *src = xc + c * m.n_coarse + I;
         double s = 0.0;
 #pragma unroll
-        for (int z = 0; z < 3; ++z) {
-            if (wz[z] == 0.0) continue;
+        for (int z = 0; z < 3; ++z)
 #pragma unroll
             for (int y = 0; y < 3; ++y) {
-                if (wy[y] == 0.0) continue;
-                double sx = 0.0;
-#pragma unroll
-                for (int xx = 0; xx < 3; ++xx)
-                    if (wx[xx] != 0.0)
-                        sx += wx[xx] * src[ix[xx] + (int64_t)m.nc[0] * (iy[y] + (int64_t)m.nc[1] * iz[z])];
-                s += wz[z] * wy[y] * sx;
+                const double w = wz[z] * wy[y];
+                if (w != 0.0) s += w * src[(int64_t)m.nc[0] * (iy[y] + (int64_t)m.nc[1] * iz[z])];
             }
+        sU[t] = s;
+    }
+    __syncthreads();
+    const int64_t base = (int64_t)m.nf[0] * (j + (int64_t)m.nf[1] * k);
+    for (int i = threadIdx.x; i < m.nf[0]; i += blockDim.x) {
+        int ix[3];
+        double wx[3];
+        q2_pw(i, m.n[0], ix, wx);
+        for (int c = 0; c < ncomp; ++c) {
+            const double *u = sU + c * nc0;
+            xf[c * m.n_fine + base + i] = (float)(wx[0] * u[ix[0]] + wx[1] * u[ix[1]] + wx[2] * u[ix[2]]);
         }
-        xf[c * m.n_fine + t] = (float)s;
     }
 }
 
-// Nonzero entries of column I of the 1-D prolongation (coarse node I on an
-// axis with n fine elements): a coarse vertex (I even) reaches the fine
-// nodes 2I + {-3, -1, 0, 1, 3} with weights {-1/8, 3/8, 1, 3/8, -1/8}, a
-// coarse mid node (I odd) the fine nodes 2I + {-1, 0, 1} with {3/4, 1, 3/4}
-// (the quadratic functions at the quarter points); the offsets +-2 fall on
-// coarse nodes, where the other functions vanish.
-__device__ __forceinline__ int q2_rcol(int I, int n, int fi[5], double w[5]) {
-    const int c = 2 * I;
-    int k = 0;
-    if (I & 1) {
-        const int off[3] = {-1, 0, 1};
-        const double wt[3] = {0.75, 1.0, 0.75};
-        for (int s = 0; s < 3; ++s) {
-            fi[k] = c + off[s];
-            w[k++] = wt[s];
-        }
-    } else {
-        const int off[5] = {-3, -1, 0, 1, 3};
-        const double wt[5] = {-0.125, 0.375, 1.0, 0.375, -0.125};
-        for (int s = 0; s < 5; ++s) {
-            const int f = c + off[s];
-            if (f < 0 || f > 2 * n) continue;
-            fi[k] = f;
-            w[k++] = wt[s];
-        }
-    }
-    return k;
-}
-
-__global__ void k_q2_restrict(Mesh m, int ncomp, const float *__restrict__ bf, double *__restrict__ bc) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= m.n_coarse) return;
-    const int64_t JK = t / m.nc[0];
-    const int I = (int)(t - JK * m.nc[0]), J = (int)(JK % m.nc[1]), K = (int)(JK / m.nc[1]);
-    int fx[5], fy[5], fz[5];
-    double wx[5], wy[5], wz[5];
-    const int nx = q2_rcol(I, m.n[0], fx, wx), ny = q2_rcol(J, m.n[1], fy, wy), nz = q2_rcol(K, m.n[2], fz, wz);
-    for (int c = 0; c < ncomp; ++c) {
-        const float *src = bf + c * m.n_fine;
+// Restriction (the transpose), one workgroup per coarse lattice row (J, K):
+// every fine x node is first summed over the row's (y, z) stencil (at most
+// 5 x 5 fine values, read coalesced along x, into LDS in FP64), then each
+// coarse node of the row takes its at most 5 x terms from there.
+__global__ void __launch_bounds__(256) k_q2_restrict_rows(Mesh m, int ncomp, const float *__restrict__ bf,
+                                                          double *__restrict__ bc) {
+    extern __shared__ double sT[]; // [ncomp][nf0]
+    const int64_t row = blockIdx.x;
+    const int J = (int)(row % m.nc[1]), K = (int)(row / m.nc[1]);
+    int fy[5], fz[5];
+    double wy[5], wz[5];
+    q2_rcol(J, m.n[1], fy, wy);
+    q2_rcol(K, m.n[2], fz, wz);
+    const int nf0 = m.nf[0];
+    for (int t = threadIdx.x; t < ncomp * nf0; t += blockDim.x) {
+        const int c = t / nf0, i = t - c * nf0;
+        const float *src = bf + c * m.n_fine + i;
         double s = 0.0;
-        for (int z = 0; z < nz; ++z)
-            for (int y = 0; y < ny; ++y) {
-                const int64_t row = (int64_t)m.nf[0] * (fy[y] + (int64_t)m.nf[1] * fz[z]);
-                double sx = 0.0;
-                for (int xx = 0; xx < nx; ++xx) sx += wx[xx] * (double)src[row + fx[xx]];
-                s += wz[z] * wy[y] * sx;
-            }
-        bc[c * m.n_coarse + t] = s;
+#pragma unroll
+        for (int z = 0; z < 5; ++z) {
+            if (wz[z] == 0.0) continue;
+            double sy = 0.0;
+#pragma unroll
+            for (int y = 0; y < 5; ++y)
+                if (wy[y] != 0.0) sy += wy[y] * (double)src[(int64_t)m.nf[0] * (fy[y] + (int64_t)m.nf[1] * fz[z])];
+            s += wz[z] * sy;
+        }
+        sT[t] = s;
+    }
+    __syncthreads();
+    const int64_t base = (int64_t)m.nc[0] * (J + (int64_t)m.nc[1] * K);
+    for (int I = threadIdx.x; I < m.nc[0]; I += blockDim.x) {
+        int fx[5];
+        double wx[5];
+        q2_rcol(I, m.n[0], fx, wx);
+        for (int c = 0; c < ncomp; ++c) {
+            const double *t = sT + c * nf0;
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) s += wx[q] * t[fx[q]];
+            bc[c * m.n_coarse + base + I] = s;
+        }
     }
 }
 
-// Patch inputs of Sec. 4.2 on the fine Q2 elements: row M = [u, v, w at the
-// 27 nodes, r_u, r_v, r_w there, g0, g1, g2], g_a the mean length of the
-// element's 4 vertex-to-vertex edges along axis a, standardised and stored
-// as FP32 or BF16; padding columns zero.  Thread (M, node) writes the node's
-// six columns; the element's first thread also writes the geometry columns.
-template <int DT>
-__global__ void k_q2_gather(Mesh m, const double *__restrict__ X, const float *__restrict__ x,
-                            const float *__restrict__ r, const float *__restrict__ shift,
-                            const float *__restrict__ inv, void *__restrict__ out, int64_t ldx) {
+// Geometry inputs of Sec. 4.2 for curved cells, once per mesh: g_a of
+// element M = the mean length of its 4 vertex-to-vertex edges along axis a
+// (the cell sizes on axis-parallel cells), from the FP64 node positions.
+__global__ void k_q2_features(Mesh m, const double *__restrict__ X, float *__restrict__ geom) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= m.n_patches * 27) return;
-    const int64_t M = t / 27;
-    const int l = (int)(t - 27 * M);
+    if (t >= 3 * m.n_patches) return;
+    const int64_t M = t / 3;
+    const int a = (int)(t - 3 * M);
     const int I = (int)(M % m.n[0]), J = (int)((M / m.n[0]) % m.n[1]), K = (int)(M / ((int64_t)m.n[0] * m.n[1]));
-    const int gi = 2 * I + l % 3, gj = 2 * J + (l / 3) % 3, gk = 2 * K + l / 9;
     const int64_t nf = m.n_fine;
-    const int64_t g = gi + (int64_t)m.nf[0] * (gj + (int64_t)m.nf[1] * gk);
-    auto put = [&](int col, float v) {
-        if (shift) v -= shift[col];
-        if (inv) v *= inv[col];
-        if (DT == DNNMG_F32)
-            static_cast<float *>(out)[M * ldx + col] = v;
-        else
-            static_cast<uint16_t *>(out)[M * ldx + col] = f32_to_bf16(v);
-    };
+    double sum = 0.0;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        put(27 * a + l, x[a * nf + g]);
-        put(81 + 27 * a + l, r[a * nf + g]);
-    }
-    if (l == 0) {
-        int64_t vn[8];
+    for (int v = 0; v < 8; ++v) {
+        if ((v >> a) & 1) continue;
+        const int w = v | (1 << a);
+        const int64_t p0 = (2 * I + 2 * (v & 1)) +
+                           (int64_t)m.nf[0] * ((2 * J + 2 * ((v >> 1) & 1)) + (int64_t)m.nf[1] * (2 * K + 2 * ((v >> 2) & 1)));
+        const int64_t p1 = (2 * I + 2 * (w & 1)) +
+                           (int64_t)m.nf[0] * ((2 * J + 2 * ((w >> 1) & 1)) + (int64_t)m.nf[1] * (2 * K + 2 * ((w >> 2) & 1)));
+        double d2 = 0.0;
 #pragma unroll
-        for (int v = 0; v < 8; ++v)
-            vn[v] = (2 * I + 2 * (v & 1)) + (int64_t)m.nf[0] * ((2 * J + 2 * ((v >> 1) & 1)) +
-                                                                 (int64_t)m.nf[1] * (2 * K + 2 * ((v >> 2) & 1)));
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            double sum = 0.0;
-#pragma unroll
-            for (int v = 0; v < 8; ++v) {
-                if ((v >> a) & 1) continue;
-                const int w = v | (1 << a);
-                double d2 = 0.0;
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    const double e = X[d * nf + vn[w]] - X[d * nf + vn[v]];
-                    d2 += e * e;
-                }
-                sum += sqrt(d2);
-            }
-            put(162 + a, (float)(0.25 * sum));
+        for (int d = 0; d < 3; ++d) {
+            const double e = X[d * nf + p1] - X[d * nf + p0];
+            d2 += e * e;
         }
+        sum += sqrt(d2);
     }
-    for (int64_t col = 165 + l; col < ldx; col += 27) {
-        if (DT == DNNMG_F32)
-            static_cast<float *>(out)[M * ldx + col] = 0.0f;
-        else
-            static_cast<uint16_t *>(out)[M * ldx + col] = 0;
-    }
+    geom[t] = (float)(0.25 * sum);
 }
 
 static int q2_mesh(const char *who, const dnnmg_box *box, Mesh *m, bool even) {
@@ -609,7 +603,10 @@ extern "C" int dnnmg_q2_prolong(const dnnmg_box *box, int ncomp, const double *x
     if (rc) return rc;
     if (ncomp < 1 || ncomp > 4) return fail(DNNMG_ERR_ARG, "dnnmg_q2_prolong: ncomp %d not in 1..4", ncomp);
     if (!xc || !xf) return fail(DNNMG_ERR_ARG, "dnnmg_q2_prolong: NULL pointer");
-    k_q2_prolong<<<blocks_for(m.n_fine, 256), 256, 0, STREAM>>>(m, ncomp, xc, xf);
+    if ((size_t)ncomp * m.nc[0] * sizeof(double) > 64 * 1024)
+        return fail(DNNMG_ERR_SHAPE, "dnnmg_q2_prolong: %d nodes per x row exceed the row buffer", m.nc[0]);
+    k_q2_prolong_rows<<<(unsigned)((int64_t)m.nf[1] * m.nf[2]), 256, (size_t)ncomp * m.nc[0] * sizeof(double),
+                        STREAM>>>(m, ncomp, xc, xf);
     return hip_check(hipGetLastError(), "dnnmg_q2_prolong launch");
 }
 
@@ -619,25 +616,18 @@ extern "C" int dnnmg_q2_restrict(const dnnmg_box *box, int ncomp, const float *b
     if (rc) return rc;
     if (ncomp < 1 || ncomp > 4) return fail(DNNMG_ERR_ARG, "dnnmg_q2_restrict: ncomp %d not in 1..4", ncomp);
     if (!bf || !bc) return fail(DNNMG_ERR_ARG, "dnnmg_q2_restrict: NULL pointer");
-    k_q2_restrict<<<blocks_for(m.n_coarse, 256), 256, 0, STREAM>>>(m, ncomp, bf, bc);
+    if ((size_t)ncomp * m.nf[0] * sizeof(double) > 64 * 1024)
+        return fail(DNNMG_ERR_SHAPE, "dnnmg_q2_restrict: %d nodes per x row exceed the row buffer", m.nf[0]);
+    k_q2_restrict_rows<<<(unsigned)((int64_t)m.nc[1] * m.nc[2]), 256, (size_t)ncomp * m.nf[0] * sizeof(double),
+                         STREAM>>>(m, ncomp, bf, bc);
     return hip_check(hipGetLastError(), "dnnmg_q2_restrict launch");
 }
 
-extern "C" int dnnmg_q2_patch_gather(const dnnmg_box *box, const double *coords, const float *x, const float *r,
-                                     const dnnmg_feat *feat, int dtype, void *X, int64_t ldx, void *stream) {
+extern "C" int dnnmg_q2_patch_features(const dnnmg_box *box, const double *coords, float *geom, void *stream) {
     Mesh m;
-    int rc = q2_mesh("dnnmg_q2_patch_gather", box, &m, false);
+    int rc = q2_mesh("dnnmg_q2_patch_features", box, &m, false);
     if (rc) return rc;
-    if (!coords || !x || !r || !X) return fail(DNNMG_ERR_ARG, "dnnmg_q2_patch_gather: NULL pointer");
-    if (ldx < 165) return fail(DNNMG_ERR_SHAPE, "dnnmg_q2_patch_gather: ldx %lld < 165", (long long)ldx);
-    const float *sh = feat ? feat->shift : nullptr;
-    const float *sc = feat ? feat->inv_scale : nullptr;
-    const unsigned g = blocks_for(m.n_patches * 27, 27 * 9);
-    if (dtype == DNNMG_F32)
-        k_q2_gather<DNNMG_F32><<<g, 27 * 9, 0, STREAM>>>(m, coords, x, r, sh, sc, X, ldx);
-    else if (dtype == DNNMG_BF16)
-        k_q2_gather<DNNMG_BF16><<<g, 27 * 9, 0, STREAM>>>(m, coords, x, r, sh, sc, X, ldx);
-    else
-        return fail(DNNMG_ERR_UNSUPPORTED, "dnnmg_q2_patch_gather: dtype %d (FP32 or BF16 rows)", dtype);
-    return hip_check(hipGetLastError(), "dnnmg_q2_patch_gather launch");
+    if (!coords || !geom) return fail(DNNMG_ERR_ARG, "dnnmg_q2_patch_features: NULL pointer");
+    k_q2_features<<<blocks_for(3 * m.n_patches, 256), 256, 0, STREAM>>>(m, coords, geom);
+    return hip_check(hipGetLastError(), "dnnmg_q2_patch_features launch");
 }

@@ -181,12 +181,13 @@ __global__ void __launch_bounds__(256) k_restrict_batch(const BoxDesc *__restric
 // ----------------------------------------------------------- gather Q -----
 // One thread writes 4 consecutive columns of a patch row.  Columns
 // 27 c + iota (c < 6) read field c of [u, v, w, r_u, r_v, r_w] at
-// dof(M, iota); 162..164 are the coarse cell sizes; the rest is zero padding.
+// dof(M, iota); 162..164 are the geometry inputs (row M of geom, or the
+// coarse cell sizes when geom is null); the rest is zero padding.
 template <int DT>
 __global__ void __launch_bounds__(256)
     k_gather(Mesh m, const float *__restrict__ x, const float *__restrict__ r,
              const float *__restrict__ shift, const float *__restrict__ inv_scale, float qinv,
-             void *__restrict__ Xout, int64_t ldx) {
+             void *__restrict__ Xout, int64_t ldx, const float *__restrict__ geom) {
     // block = GP patches x (ldx / 4) column quads
     const int quads = (int)(ldx / 4);
     const int local = threadIdx.x / quads;
@@ -218,7 +219,7 @@ __global__ void __launch_bounds__(256)
             int64_t node = i + (int64_t)m.nf[0] * (j + (int64_t)m.nf[1] * k);
             v = c < 3 ? x[c * m.n_fine + node] : r[(c - 3) * m.n_fine + node];
         } else if (col < 165) {
-            v = m.H[col - 162];
+            v = geom ? geom[3 * M + (col - 162)] : m.H[col - 162];
         }
         if (col < 165) {
             if (shift) v -= sh[q];
@@ -583,9 +584,8 @@ extern "C" int dnnmg_restrict(const dnnmg_box *box, int ncomp, const float *bf, 
     return hip_check(hipGetLastError(), "dnnmg_restrict launch");
 }
 
-extern "C" int dnnmg_patch_gather(const dnnmg_box *box, const float *x, const float *r,
-                                  const dnnmg_feat *feat, int dtype, float x_scale, void *X,
-                                  int64_t ldx, void *stream) {
+static int gather_launch(const dnnmg_box *box, const float *geom, const float *x, const float *r,
+                         const dnnmg_feat *feat, int dtype, float x_scale, void *X, int64_t ldx, void *stream) {
     Mesh m;
     int rc = make_mesh(box, &m);
     if (rc) return rc;
@@ -601,15 +601,28 @@ extern "C" int dnnmg_patch_gather(const dnnmg_box *box, const float *x, const fl
     int per_block = (int)(256 / (ldx / 4));
     unsigned g = blocks_for(m.n_patches, per_block);
     if (dtype == DNNMG_F32)
-        k_gather<DNNMG_F32><<<g, 256, 0, STREAM>>>(m, x, r, sh, sc, 1.0f, X, ldx);
+        k_gather<DNNMG_F32><<<g, 256, 0, STREAM>>>(m, x, r, sh, sc, 1.0f, X, ldx, geom);
     else if (dtype == DNNMG_BF16)
-        k_gather<DNNMG_BF16><<<g, 256, 0, STREAM>>>(m, x, r, sh, sc, 1.0f, X, ldx);
+        k_gather<DNNMG_BF16><<<g, 256, 0, STREAM>>>(m, x, r, sh, sc, 1.0f, X, ldx, geom);
     else if (dtype == DNNMG_FP8_E4M3) {
         if (!(x_scale > 0.0f)) return fail(DNNMG_ERR_ARG, "dnnmg_patch_gather: x_scale must be > 0 for FP8");
-        k_gather<DNNMG_FP8_E4M3><<<g, 256, 0, STREAM>>>(m, x, r, sh, sc, 1.0f / x_scale, X, ldx);
+        k_gather<DNNMG_FP8_E4M3><<<g, 256, 0, STREAM>>>(m, x, r, sh, sc, 1.0f / x_scale, X, ldx, geom);
     } else
         return fail(DNNMG_ERR_UNSUPPORTED, "dnnmg_patch_gather: dtype %d", dtype);
     return hip_check(hipGetLastError(), "dnnmg_patch_gather launch");
+}
+
+extern "C" int dnnmg_patch_gather(const dnnmg_box *box, const float *x, const float *r,
+                                  const dnnmg_feat *feat, int dtype, float x_scale, void *X,
+                                  int64_t ldx, void *stream) {
+    return gather_launch(box, nullptr, x, r, feat, dtype, x_scale, X, ldx, stream);
+}
+
+extern "C" int dnnmg_patch_gather_geom(const dnnmg_box *box, const float *geom, const float *x, const float *r,
+                                       const dnnmg_feat *feat, int dtype, float x_scale, void *X, int64_t ldx,
+                                       void *stream) {
+    if (!geom) return fail(DNNMG_ERR_ARG, "dnnmg_patch_gather_geom: geom is NULL");
+    return gather_launch(box, geom, x, r, feat, dtype, x_scale, X, ldx, stream);
 }
 
 // The tiled form wins once every compute unit has several tiles; on smaller

@@ -129,3 +129,33 @@ def _share_residual_b_general() -> float:
 ALG_PROLONG_RESIDUAL_B_PER_NODE = round(
     (ALG_PROLONG_PER_NODE + ALG_RESIDUAL_AT_PROLONGATION_PER_NODE) * _share_prolong_residual_b())
 ALG_RESIDUAL_B_GENERAL_PER_NODE = round(ALG_RESIDUAL_GENERAL_PER_NODE * _share_residual_b_general())
+
+
+# ---- Q2/Q2 elements on curved hexahedra (27 Gauss points per element) -----
+# Counted as the element kernel evaluates them: phase 1 per quadrature
+# point (shape functions, Jacobian, fields, Q1 interpolants, inverse, the 28
+# integrand coefficients), phase 2 per (test node, point) pair.
+Q2_SHAPE_PER_POINT = 27 * 4 + 9 * 3             # N and 3 derivatives of 27 functions
+Q2_JACOBIAN_PER_POINT = 27 * 9 * 2 + 14 + 9 * 3 + 1  # 9 FMA per node, det, cofactor inverse
+
+
+def q2_residual_flops_per_element() -> int:
+    """r = b - A(x) on one Q2 element (momentum and continuity rows with both
+    LPS terms), as issued by the element kernel."""
+    fields = 27 * 16 * 2                          # v, grad v, p, grad p: 16 FMA per node
+    interp = 8 * (8 + 15 * 2)                     # Q1 functions of 8 vertices, pi v, grad pi v, grad pi p
+    grads = (9 + 9 + 3 + 3) * 5                   # physical gradients of v, pi v, p, pi p
+    pointwise = 3 * 5 + 3 * 6 + 3                 # convection, R_a, weight
+    coeff = 3 * (15 + 6 + 4 + 30) + (9 + 3 + 15 + 3)  # momentum and continuity coefficients
+    phase1 = 27 * (Q2_SHAPE_PER_POINT + Q2_JACOBIAN_PER_POINT + fields + interp + grads + pointwise + coeff)
+    phase2 = 27 * 27 * (9 + 4 * 14 + 4)           # shape values, 4 equations x 7 FMA, sums
+    stab = 28 * 8 + 27 * 6 + 10                   # h_T, |v|_inf, alpha_T, delta_T
+    return phase1 + phase2 + stab + 27 * 4        # + the read-modify-write of 108 values
+
+
+def q2_rhs_flops_per_element() -> int:
+    """b = Rhs(v) on one Q2 element (momentum rows), as issued."""
+    fields = 27 * 12 * 2 + 27 * 3 * 2             # v, grad v; forcing values
+    phase1 = 27 * (Q2_SHAPE_PER_POINT + Q2_JACOBIAN_PER_POINT + fields + 9 * 5 + 15 + 3 * (6 + 15))
+    phase2 = 27 * 27 * (9 + 3 * 8 + 3)
+    return phase1 + phase2 + 27 * 3

@@ -267,7 +267,7 @@ class Q2CorrectionStep:
     step: with indicator=True, eta is computed and reported only."""
 
     def __init__(self, box, ns, coords, params, dtype="bf16", device="cuda:0", shift=None, inv_scale=None,
-                 indicator=False):
+                 indicator=False, fused=True):
         self.box = L.Box.of(box)
         self.ns = L.NS.of(ns)
         self.dev = torch.device(device)
@@ -276,9 +276,14 @@ class Q2CorrectionStep:
         self.n_in, self.n_out, self.ldx = L.LEVEL_IO[1]
         self.hidden = int(np.shape(params[0])[1])
         self.indicator = indicator
+        # fused: the gather runs inside the network kernel
+        self.fused = bool(fused)
         f32 = dict(dtype=torch.float32, device=self.dev)
         f64 = dict(dtype=torch.float64, device=self.dev)
         self.coords = torch.as_tensor(np.ascontiguousarray(coords, np.float64).ravel()).to(self.dev)
+        # geometry inputs of the curved cells, fixed with the mesh
+        self.geom = torch.zeros(3 * self.np, **f32)
+        L.dnnmg_q2_patch_features(self.box, self.coords, self.geom)
         self.xc = torch.zeros(4 * self.nc, **f64)
         self.xt = torch.zeros(4 * self.nf, **f32)
         self.vprev = torch.zeros(3 * self.nf, **f32)
@@ -310,9 +315,13 @@ class Q2CorrectionStep:
         box, ns = self.box, self.ns
         L.dnnmg_q2_prolong(box, self.xc, self.xt, stream=stream)
         L.dnnmg_q2_residual_b(box, ns, self.coords, self.xt, self.b, self.r, stream=stream)
-        L.dnnmg_q2_patch_gather(box, self.coords, self.xt, self.r, self.X, self.xdtype, self.ldx, self.shift,
-                                self.inv_scale, stream=stream)
-        L.dnnmg_patch_forward(self.net, self.np, self.X, self.ldx, self.Y, stream=stream)
+        if self.fused:
+            L.dnnmg_patch_gather_forward_geom(box, self.net, self.geom, self.xt, self.r, self.Y, self.shift,
+                                              self.inv_scale, stream=stream)
+        else:
+            L.dnnmg_patch_gather_geom(box, self.geom, self.xt, self.r, self.X, self.xdtype, self.ldx, self.shift,
+                                      self.inv_scale, stream=stream)
+            L.dnnmg_patch_forward(self.net, self.np, self.X, self.ldx, self.Y, stream=stream)
         L.dnnmg_scatter_avg(box, self.Y, self.xcorr, vbase=self.xt, stream=stream)
         if self.indicator:
             L.dnnmg_q2_residual_b(box, ns, self.coords, self.xcorr, self.b, self.r2, stream=stream)

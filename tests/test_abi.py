@@ -141,9 +141,16 @@ def test_q2_host_validation_without_gpu():
     even = L.Box.of(syn.channel_box((4, 2, 2)))
     assert lib.dnnmg_q2_restrict(ctypes.byref(even), 0, None, None, None) == -1
     assert lib.dnnmg_q2_prolong(ctypes.byref(even), 4, None, None, None) == -1
+    assert lib.dnnmg_q2_patch_features(ctypes.byref(even), None, None, None) == -1
+    assert lib.dnnmg_q2_patch_features(ctypes.byref(per), None, None, None) == -2
     p = ctypes.c_void_p(16)
     feat = L.Feat(None, None)
-    rc = lib.dnnmg_q2_patch_gather(ctypes.byref(even), p, p, p, ctypes.byref(feat), L.FP8_E4M3, p, 192, None)
-    assert rc == -3
-    rc = lib.dnnmg_q2_patch_gather(ctypes.byref(even), p, p, p, ctypes.byref(feat), L.F32, p, 100, None)
+    rc = lib.dnnmg_patch_gather_geom(ctypes.byref(even), None, p, p, ctypes.byref(feat), L.F32, 1.0, p, 192, None)
+    assert rc == -1 and b"geom" in lib.dnnmg_last_error()
+    rc = lib.dnnmg_patch_gather_geom(ctypes.byref(even), p, p, p, ctypes.byref(feat), L.F32, 1.0, p, 100, None)
     assert rc == -2
+    net = L.MLP()
+    net.n_in, net.hidden, net.n_out, net.dtype = 165, 128, 81, L.BF16
+    rc = lib.dnnmg_patch_gather_forward_geom(ctypes.byref(even), ctypes.byref(net), None, p, p, ctypes.byref(feat),
+                                             p, None)
+    assert rc < 0

@@ -124,6 +124,8 @@ def test_q2_transfer_matches_oracle(L, q2, n):
 
 @pytest.mark.parametrize("dtype", ["fp32", "bf16"])
 def test_q2_gather_matches_oracle(L, q2, dtype):
+    """Geometry inputs of the curved cells (once per mesh) and the gather with
+    per-patch geometry against the oracle's element gather."""
     box, X, base, x = channel_case((4, 2, 2), 5)
     say("q2 gather", dtype)
     rng = np.random.default_rng(9)
@@ -131,12 +133,16 @@ def test_q2_gather_matches_oracle(L, q2, dtype):
     x32 = f32(x)
     shift = f32(rng.standard_normal(165))
     inv = f32(rng.uniform(0.5, 2.0, 165))
+    geom = torch.zeros(3 * box.n_patches, dtype=torch.float32, device="cuda")
+    L.dnnmg_q2_patch_features(box, to_gpu(X.ravel()), geom)
     ldx = 192
     tdt = torch.float32 if dtype == "fp32" else torch.bfloat16
     Xg = torch.full((box.n_patches * ldx,), 7.0, dtype=tdt, device="cuda")
-    L.dnnmg_q2_patch_gather(box, to_gpu(X.ravel()), to_gpu(x32.ravel()), to_gpu(r.ravel()), Xg,
-                            L.F32 if dtype == "fp32" else L.BF16, ldx, to_gpu(shift), to_gpu(inv))
+    L.dnnmg_patch_gather_geom(box, geom, to_gpu(x32.ravel()), to_gpu(r.ravel()), Xg,
+                              L.F32 if dtype == "fp32" else L.BF16, ldx, to_gpu(shift), to_gpu(inv))
     torch.cuda.synchronize()
+    feat = q2.features(box, X)
+    assert np.abs(geom.cpu().numpy().reshape(-1, 3) - feat).max() <= 1e-7 * np.abs(feat).max()
     G = Xg.float().cpu().numpy().reshape(box.n_patches, ldx).astype(np.float64)
     ref = q2.gather(box, X, x32.astype(np.float64), r.astype(np.float64), shift.astype(np.float64),
                     inv.astype(np.float64))
@@ -145,11 +151,29 @@ def test_q2_gather_matches_oracle(L, q2, dtype):
     assert np.all(G[:, 165:] == 0.0)
 
 
+def test_fused_gather_forward_geom_equals_separate(L):
+    """The fused gather + network with per-patch geometry equals the
+    separate gather and forward bit for bit (FP8 network, BF16 rows)."""
+    from paper_2307_14837_amd import stepper
+
+    box, X, base, x = channel_case((8, 4, 4), 6)
+    params = syn.mlp_params(165, 256, 81, seed=4)
+    st = stepper.Q2CorrectionStep(box, NS, X, params, dtype="fp8")
+    st.load(base.xc, base.vprev)
+    st.step()
+    torch.cuda.synchronize()
+    Y_fused = st.Y.clone()
+    L.dnnmg_patch_gather_geom(box, st.geom, st.xt, st.r, st.X, L.BF16, st.ldx)
+    L.dnnmg_patch_forward(st.net, st.np, st.X, st.ldx, st.Y)
+    torch.cuda.synchronize()
+    assert torch.equal(st.Y, Y_fused)
+
+
 def p32(params):
     return [np.asarray(p, np.float32).astype(np.float64) for p in params]
 
 
-@pytest.mark.parametrize("dtype,tol", [("fp32", 1e-5), ("bf16", 2e-2)])
+@pytest.mark.parametrize("dtype,tol", [("fp32", 1e-5), ("bf16", 2e-2), ("fp8", 5e-2)])
 def test_q2_step_matches_oracle(q2, dtype, tol):
     from paper_2307_14837_amd import stepper
 
@@ -157,7 +181,7 @@ def test_q2_step_matches_oracle(q2, dtype, tol):
     X = syn.distorted_coords(box, amp=0.15, seed=11)
     w = syn.Workload("q2", box, NS, 64, dtype, "channel")
     inp = syn.step_inputs(w, seed=11)
-    params = syn.mlp_params(165, 64, 81, seed=2)
+    params = syn.mlp_params(165, 128 if dtype == "fp8" else 64, 81, seed=2)
     say("q2 step", dtype)
     st = stepper.Q2CorrectionStep(box, NS, X, params, dtype=dtype, indicator=True)
     out = st.run_numpy(inp.xc, inp.vprev)
