@@ -602,8 +602,9 @@ int dnnmg_coarse_vcycle(const dnnmg_box *box, const dnnmg_ns *ns, const float *x
  *   pi_h: Q1 interpolation of the element's 8 vertex values; h_T: the
  *   largest distance between two vertices of T; |v|_inf,T: the largest |v|
  *   over T's 27 nodes; 3 x 3 x 3 Gauss points per element; FP32 arithmetic.
- *   Element vectors are summed colour by colour (elements with equal index
- *   parities share no node), so results are reproducible bit for bit.
+ *   Element vectors go to the workspace ws (at least dnnmg_q2_workspace(box)
+ *   bytes, 16-byte aligned: 108 floats per element) and are summed per node
+ *   in a fixed order, so results are reproducible bit for bit.
  * dnnmg_q2_residual_b: r = b - A(x), A holding the iterate's terms of eq.
  *   (4cranknicholson3) and the LPS terms; x FP32 [4][n_fine], b FP32
  *   [4][n_fine], r FP32 [4][n_fine] output (not aliasing x or b), velocity
@@ -612,10 +613,11 @@ int dnnmg_coarse_vcycle(const dnnmg_box *box, const dnnmg_ns *ns, const float *x
  *   grad phi) + (fmid_a, phi) (Algorithm 1, "Rhs"); v FP32 [3][n_fine],
  *   fmid FP32 [3][n_fine] or NULL, b FP32 [4][n_fine] (pressure and Dirichlet
  *   velocity rows 0). */
+size_t dnnmg_q2_workspace(const dnnmg_box *box);
 int dnnmg_q2_residual_b(const dnnmg_box *box, const dnnmg_ns *ns, const double *coords, const float *x,
-                        const float *b, float *r, void *stream);
+                        const float *b, float *r, void *ws, size_t ws_bytes, void *stream);
 int dnnmg_q2_rhs(const dnnmg_box *box, const dnnmg_ns *ns, const double *coords, const float *v,
-                 const float *fmid, float *b, void *stream);
+                 const float *fmid, float *b, void *ws, size_t ws_bytes, void *stream);
 /* Prolongation of Algorithm 1 between the Q2 spaces: each fine node takes the
  * Q2 interpolant of its coarse element (reference coordinates) in FP64,
  * rounded to FP32.  xc FP64 [ncomp][n_coarse] -> xf FP32 [ncomp][n_fine],

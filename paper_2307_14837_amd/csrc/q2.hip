@@ -12,19 +12,24 @@
 // interpolation of their positions (FP64 [3][n_nodes], read as offsets from
 // the element's first vertex so the Jacobian keeps FP32 accuracy).
 //
-// Element integrals (3 x 3 x 3 Gauss points) run in two phases per element
-// inside one workgroup of 9 elements x 27 threads:
-//   1. one thread per quadrature point evaluates the Jacobian, the fields,
-//      their gradients and the Q1 interpolants there and reduces every term
+// Element integrals (3 x 3 x 3 Gauss points) run inside one workgroup of 9
+// elements x 27 threads, with the tensor-product structure of the element
+// used in both directions (sum factorisation):
+//   1. the node values of the coordinates and fields are taken to values and
+//      reference gradients at the 27 points by three 1-D passes (z, y, x),
+//      each a thread per (node or point) index triple and 3 terms;
+//   2. one thread per quadrature point evaluates the Jacobian, its inverse,
+//      the physical gradients and the Q1 interpolants and reduces every term
 //      of the weak form to 7 coefficients per equation: the factor of the
 //      test function, of its reference gradient and of the reference
 //      gradient of its Q1 interpolant (nonzero for vertex nodes only);
-//   2. one thread per test node sums those coefficients against its shape
-//      functions over the 27 points.
-// Element vectors are added into the global vector colour by colour: the 8
-// classes of elements with equal index parities share no node, so each of
-// the 8 launches updates its nodes without atomics and the sum order is
-// fixed (results are reproducible bit for bit).
+//   3. three 1-D passes (x, y, z) sum those coefficients against the shape
+//      functions (and, for the vertices, against the linear functions of the
+//      Q1 space) into the 27 test nodes.
+// Element vectors go to a workspace (108 floats per element, stored by local
+// node, from one launch over all elements); a second launch sums each
+// node's at most 8 entries in a fixed order, without atomics, so results
+// are reproducible bit for bit.
 #include "common.hpp"
 #include "lowp.hpp"
 
@@ -60,61 +65,74 @@ constexpr int Q2_CSTR = 28;  // per point: 4 equations x 7 coefficients
 
 enum { Q2_APPLY = 0, Q2_RHS = 1 };
 
-// Element (I, J, K) of colour `col` from its index within the colour.
-__device__ __forceinline__ bool colour_element(const Mesh &m, int col, int64_t e, int &I, int &J, int &K) {
-    const int cx = col & 1, cy = (col >> 1) & 1, cz = (col >> 2) & 1;
-    const int mx = (m.n[0] - cx + 1) >> 1, my = (m.n[1] - cy + 1) >> 1, mz = (m.n[2] - cz + 1) >> 1;
-    if (e >= (int64_t)mx * my * mz) return false;
-    const int ex = (int)(e % mx);
-    const int64_t r = e / mx;
-    const int ey = (int)(r % my), ez = (int)(r / my);
-    I = 2 * ex + cx;
-    J = 2 * ey + cy;
-    K = 2 * ez + cz;
-    return true;
-}
+// Per-element LDS arena (floats): the interpolation passes keep 2 and then 3
+// arrays of 27 per quantity (945 for 7 quantities); the test contraction
+// keeps the 28 coefficients of each point (0..755), the x-pass sums
+// (756..1079) and the vertex x-pass sums (1080..1403), then the y-pass sums
+// over the coefficients' region.
+constexpr int Q2_ARENA = 1404;
+constexpr int Q2_P = 756, Q2_A = 1080;
+// element vectors of one workgroup in the workspace: [27 e + node][slot]
+constexpr int Q2_GROUP = 108 * Q2_EPB;
 
-// MODE Q2_APPLY: out -= A(x) (x = u, v, w, p); MODE Q2_RHS: out += Rhs(x =
-// velocity, fmid).  Dirichlet velocity rows are left untouched.
+// MODE Q2_APPLY: the element vector of A(x) (x = u, v, w, p); MODE Q2_RHS:
+// that of Rhs(x = velocity, fmid).  The element vectors of workgroup g
+// (elements 9g .. 9g + 8) are stored as one block of 972 floats,
+// E[972 g + 9 (27 e + node) + slot], so the stores are contiguous and the
+// per-node sum reads neighbouring elements at neighbouring addresses.  Thread
+// l = (l0, l1, l2) (l0 + 3 l1 + 9 l2) of an element plays node (a, b, c) or
+// quadrature point (q0, q1, q2) or a mix of both in the 1-D passes below.
 template <int MODE>
-__global__ void __launch_bounds__(Q2_NT, 4) k_q2_element(Mesh m, Q2Params P, int col, const double *__restrict__ X,
-                                                      const float *__restrict__ x,
-                                                      const float *__restrict__ fmid, float *__restrict__ out) {
-    __shared__ __align__(16) float sN[Q2_EPB][27][Q2_NSTR];
-    __shared__ float sF[Q2_EPB][27][4]; // fmid (RHS mode)
-    __shared__ __align__(16) float sC[Q2_EPB][27][Q2_CSTR];
-    __shared__ float sV[Q2_EPB][27];    // |v|^2 per node
-    __shared__ float sH[Q2_EPB][8];     // largest squared vertex distance per vertex
+__global__ void __launch_bounds__(Q2_NT, 2) k_q2_element(Mesh m, Q2Params P, const double *__restrict__ X,
+                                                      const float *__restrict__ x, const float *__restrict__ fmid,
+                                                      float *__restrict__ E) {
+    // quantities interpolated to the points: 3 coordinates (gradients only),
+    // u, v, w (values and gradients), then p (APPLY) or the 3 forcing
+    // components (RHS, values only)
+    constexpr int NQ = MODE == Q2_APPLY ? 7 : 9;
+    constexpr int NE = MODE == Q2_APPLY ? 4 : 3; // equations tested
+    __shared__ __align__(16) float sQ[Q2_EPB][NQ][27];
+    constexpr int ARENA = Q2_ARENA; // >= 5 * 9 * 27 for the RHS mode's interpolation
+    __shared__ __align__(16) float sW[Q2_EPB][ARENA];
+    __shared__ float sV[Q2_EPB][27]; // |v|^2 per node
+    __shared__ float sH[Q2_EPB][8];  // largest squared vertex distance per vertex
 
     const int tid = threadIdx.x;
     const int s = tid / 27, l = tid - 27 * (tid / 27);
     const bool active_t = tid < 27 * Q2_EPB;
+    const int64_t el = (int64_t)blockIdx.x * Q2_EPB + s;
+    const bool valid = active_t && el < m.n_patches;
     int I = 0, J = 0, K = 0;
-    const bool valid =
-        active_t && colour_element(m, col, (int64_t)blockIdx.x * Q2_EPB + s, I, J, K);
+    if (valid) {
+        I = (int)(el % m.n[0]);
+        J = (int)((el / m.n[0]) % m.n[1]);
+        K = (int)(el / ((int64_t)m.n[0] * m.n[1]));
+    }
     const int64_t nf = m.n_fine;
-    const int la = l % 3, lb = (l / 3) % 3, lc = l / 9;
-    const int gi = 2 * I + la, gj = 2 * J + lb, gk = 2 * K + lc;
+    const int l0 = l % 3, l1 = (l / 3) % 3, l2 = l / 9;
+    const int gi = 2 * I + l0, gj = 2 * J + l1, gk = 2 * K + l2;
     const int64_t g = gi + (int64_t)m.nf[0] * (gj + (int64_t)m.nf[1] * gk);
+    float *W = sW[s < Q2_EPB ? s : 0];
 
     // ---- stage the element's node positions (relative to its first vertex) and fields
     if (valid) {
         const int64_t g0 = 2 * I + (int64_t)m.nf[0] * (2 * J + (int64_t)m.nf[1] * (2 * K));
+#pragma unroll
+        for (int d = 0; d < 3; ++d) sQ[s][d][l] = (float)(X[d * nf + g] - X[d * nf + g0]);
         float v2 = 0.0f;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) sN[s][l][d] = (float)(X[d * nf + g] - X[d * nf + g0]);
-        sN[s][l][3] = 0.0f;
+        for (int f = 0; f < 3; ++f) {
+            const float val = x[f * nf + g];
+            sQ[s][3 + f][l] = val;
+            v2 += val * val;
+        }
+        if (MODE == Q2_APPLY) {
+            sQ[s][6][l] = x[3 * nf + g];
+        } else {
 #pragma unroll
-        for (int f = 0; f < 4; ++f) {
-            float val = (MODE == Q2_RHS && f == 3) ? 0.0f : x[f * nf + g];
-            sN[s][l][4 + f] = val;
-            if (f < 3) v2 += val * val;
+            for (int f = 0; f < 3; ++f) sQ[s][6 + f][l] = fmid ? fmid[f * nf + g] : 0.0f;
         }
         sV[s][l] = v2;
-        if (MODE == Q2_RHS) {
-#pragma unroll
-            for (int f = 0; f < 3; ++f) sF[s][l][f] = fmid ? fmid[f * nf + g] : 0.0f;
-        }
     }
     __syncthreads();
 
@@ -129,72 +147,91 @@ __global__ void __launch_bounds__(Q2_NT, 4) k_q2_element(Mesh m, Q2Params P, int
                 float d2 = 0.0f;
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    float e = sN[s][wi][d] - sN[s][vi][d];
+                    const float e = sQ[s][d][wi] - sQ[s][d][vi];
                     d2 += e * e;
                 }
                 best = fmaxf(best, d2);
             }
             sH[s][l] = best;
         }
-        __syncthreads();
-        if (valid) {
-            float h2 = 0.0f, v2 = 0.0f;
-#pragma unroll
-            for (int v = 0; v < 8; ++v) h2 = fmaxf(h2, sH[s][v]);
-#pragma unroll
-            for (int n = 0; n < 27; ++n) v2 = fmaxf(v2, sV[s][n]);
-            const float hT = sqrtf(h2);
-            const float den = P.nu / h2 + sqrtf(v2) / hT + P.inv_dt;
-            alphaT = P.alpha0 / den;
-            deltaT = P.delta0 / den;
-        }
     }
 
-    // ---- phase 1: thread l is quadrature point (q0, q1, q2) = (la, lb, lc)
+    // ---- interpolation, pass z: thread (a, b, q2): values and z-derivatives
     if (valid) {
-        float Qx[3], Dx[3], Qy[3], Dy[3];
-        const float t0 = gauss_pt(la), t1 = gauss_pt(lb), t2 = gauss_pt(lc);
+        const float t = gauss_pt(l2);
+        const float Q0 = quad_fn(0, t), Q1 = quad_fn(1, t), Q2 = quad_fn(2, t);
+        const float D0 = quad_dfn(0, t), D1 = quad_dfn(1, t), D2 = quad_dfn(2, t);
+        const int n0 = l0 + 3 * l1;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            Qx[a] = quad_fn(a, t0);
-            Dx[a] = quad_dfn(a, t0);
-            Qy[a] = quad_fn(a, t1);
-            Dy[a] = quad_dfn(a, t1);
+        for (int q = 0; q < NQ; ++q) {
+            const float u0 = sQ[s][q][n0], u1 = sQ[s][q][n0 + 9], u2 = sQ[s][q][n0 + 18];
+            W[(2 * q) * 27 + l] = u0 * Q0 + u1 * Q1 + u2 * Q2;
+            if (MODE == Q2_APPLY || q < 6) W[(2 * q + 1) * 27 + l] = u0 * D0 + u1 * D1 + u2 * D2;
         }
-        float Jm[3][3] = {}, v[3] = {}, gv[3][3] = {}, p = 0.0f, gp[3] = {}, f[3] = {};
-#pragma unroll 1
-        for (int c = 0; c < 3; ++c) {
-            const float qz = quad_fn(c, t2), dqz = quad_dfn(c, t2);
+    }
+    __syncthreads();
+    if (MODE == Q2_APPLY && valid) {
+        float h2 = 0.0f, v2 = 0.0f;
 #pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                const float yz = Qy[b] * qz, dy = Dy[b] * qz, dz = Qy[b] * dqz;
+        for (int v = 0; v < 8; ++v) h2 = fmaxf(h2, sH[s][v]);
 #pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const int n = a + 3 * b + 9 * c;
-                    const float N = Qx[a] * yz;
-                    const float dN[3] = {Dx[a] * yz, Qx[a] * dy, Qx[a] * dz};
-                    const float4 pos = *reinterpret_cast<const float4 *>(&sN[s][n][0]);
-                    const float4 fld = *reinterpret_cast<const float4 *>(&sN[s][n][4]);
-                    const float pv[3] = {pos.x, pos.y, pos.z};
-                    const float fv[4] = {fld.x, fld.y, fld.z, fld.w};
+        for (int n = 0; n < 27; ++n) v2 = fmaxf(v2, sV[s][n]);
+        const float hT = sqrtf(h2);
+        const float den = P.nu / h2 + sqrtf(v2) / hT + P.inv_dt;
+        alphaT = P.alpha0 / den;
+        deltaT = P.delta0 / den;
+    }
+    // ---- pass y: thread (a, q1, q2): value, y-derivative, and the z-derivative carried
+    constexpr int YOFF = 2 * NQ * 27;
+    if (valid) {
+        const float t = gauss_pt(l1);
+        const float Q0 = quad_fn(0, t), Q1 = quad_fn(1, t), Q2 = quad_fn(2, t);
+        const float D0 = quad_dfn(0, t), D1 = quad_dfn(1, t), D2 = quad_dfn(2, t);
+        const int n0 = l0 + 9 * l2;
 #pragma unroll
-                    for (int e = 0; e < 3; ++e) {
-#pragma unroll
-                        for (int d = 0; d < 3; ++d) Jm[d][e] += pv[d] * dN[e];
-#pragma unroll
-                        for (int q = 0; q < 3; ++q) gv[q][e] += fv[q] * dN[e];
-                        if (MODE == Q2_APPLY) gp[e] += fv[3] * dN[e];
-                    }
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) v[q] += fv[q] * N;
-                    if (MODE == Q2_APPLY) p += fv[3] * N;
-                    if (MODE == Q2_RHS) {
-#pragma unroll
-                        for (int q = 0; q < 3; ++q) f[q] += sF[s][n][q] * N;
-                    }
-                }
+        for (int q = 0; q < NQ; ++q) {
+            const float *z = W + (2 * q) * 27 + n0;
+            const float z0 = z[0], z1 = z[3], z2 = z[6];
+            W[YOFF + (3 * q) * 27 + l] = z0 * Q0 + z1 * Q1 + z2 * Q2;
+            if (MODE == Q2_APPLY || q < 6) {
+                const float *w = W + (2 * q + 1) * 27 + n0;
+                W[YOFF + (3 * q + 1) * 27 + l] = z0 * D0 + z1 * D1 + z2 * D2;
+                W[YOFF + (3 * q + 2) * 27 + l] = w[0] * Q0 + w[3] * Q1 + w[6] * Q2;
             }
         }
+    }
+    __syncthreads();
+
+    // ---- pass x: thread (q0, q1, q2) = its quadrature point
+    float co[4][7];
+    if (valid) {
+        const float t0 = gauss_pt(l0), t1 = gauss_pt(l1), t2 = gauss_pt(l2);
+        const float Q0 = quad_fn(0, t0), Q1 = quad_fn(1, t0), Q2 = quad_fn(2, t0);
+        const float D0 = quad_dfn(0, t0), D1 = quad_dfn(1, t0), D2 = quad_dfn(2, t0);
+        const int n0 = 3 * l1 + 9 * l2;
+        float val[NQ], grd[NQ][3];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const float *y0 = W + YOFF + (3 * q) * 27 + n0;
+            val[q] = y0[0] * Q0 + y0[1] * Q1 + y0[2] * Q2;
+            if (MODE == Q2_APPLY || q < 6) {
+                const float *y1 = W + YOFF + (3 * q + 1) * 27 + n0;
+                const float *y2 = W + YOFF + (3 * q + 2) * 27 + n0;
+                grd[q][0] = y0[0] * D0 + y0[1] * D1 + y0[2] * D2;
+                grd[q][1] = y1[0] * Q0 + y1[1] * Q1 + y1[2] * Q2;
+                grd[q][2] = y2[0] * Q0 + y2[1] * Q1 + y2[2] * Q2;
+            }
+        }
+        float Jm[3][3], v[3], gv[3][3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                Jm[d][e] = grd[d][e];
+                gv[d][e] = grd[3 + d][e];
+            }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) v[d] = val[3 + d];
         const float det = Jm[0][0] * (Jm[1][1] * Jm[2][2] - Jm[1][2] * Jm[2][1]) -
                           Jm[0][1] * (Jm[1][0] * Jm[2][2] - Jm[1][2] * Jm[2][0]) +
                           Jm[0][2] * (Jm[1][0] * Jm[2][1] - Jm[1][1] * Jm[2][0]);
@@ -209,7 +246,7 @@ __global__ void __launch_bounds__(Q2_NT, 4) k_q2_element(Mesh m, Q2Params P, int
         Ji[2][0] = (Jm[1][0] * Jm[2][1] - Jm[1][1] * Jm[2][0]) * id;
         Ji[2][1] = (Jm[0][1] * Jm[2][0] - Jm[0][0] * Jm[2][1]) * id;
         Ji[2][2] = (Jm[0][0] * Jm[1][1] - Jm[0][1] * Jm[1][0]) * id;
-        const float w = gauss_wt(la) * gauss_wt(lb) * gauss_wt(lc) * det;
+        const float w = gauss_wt(l0) * gauss_wt(l1) * gauss_wt(l2) * det;
 
         // physical gradients: grad f = Ji^T (reference gradient)
         float G[3][3];
@@ -221,27 +258,28 @@ __global__ void __launch_bounds__(Q2_NT, 4) k_q2_element(Mesh m, Q2Params P, int
 #pragma unroll
         for (int q = 0; q < 3; ++q) conv[q] = v[0] * G[q][0] + v[1] * G[q][1] + v[2] * G[q][2];
 
-        float co[4][7];
         if (MODE == Q2_APPLY) {
+            const float p = val[6];
             // Q1 interpolants from the 8 vertices (local nodes 2va + 6vb + 18vc)
             const float Lx[2] = {1.0f - t0, t0}, Ly[2] = {1.0f - t1, t1}, Lz[2] = {1.0f - t2, t2};
             float pv[3] = {}, gpv[3][3] = {}, gpp[3] = {};
 #pragma unroll
             for (int vtx = 0; vtx < 8; ++vtx) {
                 const int va = vtx & 1, vb = (vtx >> 1) & 1, vc = (vtx >> 2) & 1;
+                const int vn = 2 * va + 6 * vb + 18 * vc;
                 const float sx = va ? 1.0f : -1.0f, sy = vb ? 1.0f : -1.0f, sz = vc ? 1.0f : -1.0f;
                 const float L = Lx[va] * Ly[vb] * Lz[vc];
                 const float dL[3] = {sx * Ly[vb] * Lz[vc], Lx[va] * sy * Lz[vc], Lx[va] * Ly[vb] * sz};
-                const float4 fld = *reinterpret_cast<const float4 *>(&sN[s][2 * va + 6 * vb + 18 * vc][4]);
-                const float fv[4] = {fld.x, fld.y, fld.z, fld.w};
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
-                    pv[q] += fv[q] * L;
+                    const float fq = sQ[s][3 + q][vn];
+                    pv[q] += fq * L;
 #pragma unroll
-                    for (int e = 0; e < 3; ++e) gpv[q][e] += fv[q] * dL[e];
+                    for (int e = 0; e < 3; ++e) gpv[q][e] += fq * dL[e];
                 }
+                const float fp = sQ[s][6][vn];
 #pragma unroll
-                for (int e = 0; e < 3; ++e) gpp[e] += fv[3] * dL[e];
+                for (int e = 0; e < 3; ++e) gpp[e] += fp * dL[e];
             }
             float gpi[3][3], gpp_phys[3], gp_phys[3];
 #pragma unroll
@@ -250,9 +288,9 @@ __global__ void __launch_bounds__(Q2_NT, 4) k_q2_element(Mesh m, Q2Params P, int
                 for (int q = 0; q < 3; ++q)
                     gpi[q][d] = gpv[q][0] * Ji[0][d] + gpv[q][1] * Ji[1][d] + gpv[q][2] * Ji[2][d];
                 gpp_phys[d] = gpp[0] * Ji[0][d] + gpp[1] * Ji[1][d] + gpp[2] * Ji[2][d];
-                gp_phys[d] = gp[0] * Ji[0][d] + gp[1] * Ji[1][d] + gp[2] * Ji[2][d];
+                gp_phys[d] = grd[6][0] * Ji[0][d] + grd[6][1] * Ji[1][d] + grd[6][2] * Ji[2][d];
             }
-            // momentum rows: factor of phi, of grad phi and of grad pi phi (physical)
+            // momentum rows: factor of phi, of grad phi and of grad pi phi (reference)
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
                 const float R = conv[q] - (pv[0] * gpi[q][0] + pv[1] * gpi[q][1] + pv[2] * gpi[q][2]);
@@ -283,7 +321,7 @@ __global__ void __launch_bounds__(Q2_NT, 4) k_q2_element(Mesh m, Q2Params P, int
         } else {
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
-                co[q][0] = w * (P.inv_dt * v[q] - 0.5f * conv[q] + f[q]);
+                co[q][0] = w * (P.inv_dt * v[q] - 0.5f * conv[q] + val[6 + q]);
 #pragma unroll
                 for (int e = 0; e < 3; ++e) {
                     co[q][1 + e] = -w * P.half_nu * (Ji[e][0] * G[q][0] + Ji[e][1] * G[q][1] + Ji[e][2] * G[q][2]);
@@ -293,86 +331,197 @@ __global__ void __launch_bounds__(Q2_NT, 4) k_q2_element(Mesh m, Q2Params P, int
 #pragma unroll
             for (int k = 0; k < 7; ++k) co[3][k] = 0.0f;
         }
+    }
+    __syncthreads(); // every pass-x read of the arena is done
+    if (valid) {
+        // the 28 coefficients of the point, equation-major (7 per equation)
+        float4 *c4 = reinterpret_cast<float4 *>(W + 28 * l);
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
+        for (int k = 0; k < 7; ++k) {
+            float t4[4];
 #pragma unroll
-            for (int k = 0; k < 7; ++k) sC[s][l][7 * e + k] = co[e][k];
+            for (int u = 0; u < 4; ++u) t4[u] = co[(4 * k + u) / 7][(4 * k + u) % 7];
+            c4[k] = make_float4(t4[0], t4[1], t4[2], t4[3]);
+        }
     }
     __syncthreads();
 
-    // ---- phase 2: thread l is test node (a, b, c) = (la, lb, lc)
-    if (!valid) return;
-    float Qa[3], Da[3], La[3];
-    const bool vert = !(la & 1) && !(lb & 1) && !(lc & 1);
-    const float vm = vert ? 1.0f : 0.0f;
-    const float sa = la ? 1.0f : -1.0f, sb = lb ? 1.0f : -1.0f, sc = lc ? 1.0f : -1.0f;
+    // ---- test contraction, pass x: thread (a, q1, q2) sums over q0
+    float P0[NE] = {}, P1[NE] = {}, P2[NE] = {}, A0[NE] = {}, A1[NE] = {}, A2[NE] = {};
+    if (valid) {
+        const int a = l0;
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        const float t = gauss_pt(q);
-        Qa[q] = quad_fn(la, t);
-        Da[q] = quad_dfn(la, t);
-        La[q] = la ? t : 1.0f - t; // the vertex's linear function (used when vert)
-    }
-    float acc[4] = {};
-#pragma unroll 1
-    for (int q12 = 0; q12 < 9; ++q12) {
-        const int q1 = q12 % 3, q2 = q12 / 3;
-        const float t1 = gauss_pt(q1), t2 = gauss_pt(q2);
-        const float qb1 = quad_fn(lb, t1), db1 = quad_dfn(lb, t1), qc2 = quad_fn(lc, t2), dc2 = quad_dfn(lc, t2);
-        const float lb1 = lb ? t1 : 1.0f - t1, lc2 = lc ? t2 : 1.0f - t2;
-        {
-            const float yz = qb1 * qc2, dy = db1 * qc2, dz = qb1 * dc2;
-            const float lyz = vm * lb1 * lc2, ly = vm * sb * lc2, lz = vm * lb1 * sc;
+        for (int q0 = 0; q0 < 3; ++q0) {
+            const float t = gauss_pt(q0);
+            const float Qa = quad_fn(a, t), Da = quad_dfn(a, t), la = a ? t : 1.0f - t;
+            const float4 *c4 = reinterpret_cast<const float4 *>(W + 28 * (q0 + 3 * l1 + 9 * l2));
+            float cf[28];
 #pragma unroll
-            for (int q0 = 0; q0 < 3; ++q0) {
-                const int qi = q0 + 3 * q1 + 9 * q2;
-                const float N = Qa[q0] * yz;
-                const float dN0 = Da[q0] * yz, dN1 = Qa[q0] * dy, dN2 = Qa[q0] * dz;
-                const float dL0 = sa * lyz, dL1 = La[q0] * ly, dL2 = La[q0] * lz;
-                const float4 *cq = reinterpret_cast<const float4 *>(&sC[s][qi][0]);
-                float cf[28];
+            for (int k = 0; k < 7; ++k) {
+                const float4 t4 = c4[k];
+                cf[4 * k] = t4.x;
+                cf[4 * k + 1] = t4.y;
+                cf[4 * k + 2] = t4.z;
+                cf[4 * k + 3] = t4.w;
+            }
 #pragma unroll
-                for (int k = 0; k < 7; ++k) {
-                    const float4 t4 = cq[k];
-                    cf[4 * k] = t4.x;
-                    cf[4 * k + 1] = t4.y;
-                    cf[4 * k + 2] = t4.z;
-                    cf[4 * k + 3] = t4.w;
-                }
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    if (MODE == Q2_RHS && e == 3) continue;
-                    const float *c = cf + 7 * e;
-                    float a = c[0] * N + c[1] * dN0 + c[2] * dN1 + c[3] * dN2;
-                    if (MODE == Q2_APPLY) a += c[4] * dL0 + c[5] * dL1 + c[6] * dL2;
-                    acc[e] += a;
+            for (int e = 0; e < NE; ++e) {
+                const float *c = cf + 7 * e;
+                P0[e] += c[0] * Qa + c[1] * Da;
+                P1[e] += c[2] * Qa;
+                P2[e] += c[3] * Qa;
+                if (MODE == Q2_APPLY) {
+                    A0[e] += c[4];
+                    A1[e] += c[5] * la;
+                    A2[e] += c[6] * la;
                 }
             }
         }
     }
-    const bool dir = on_dirichlet(m, gi, gj, gk);
+    if (valid) {
+        const float dla = l0 ? 1.0f : -1.0f;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        if (e < 3 && dir) continue;
-        if (MODE == Q2_RHS && e == 3) continue;
-        float *o = out + e * nf + g;
-        *o = MODE == Q2_APPLY ? *o - acc[e] : *o + acc[e];
+        for (int e = 0; e < NE; ++e) {
+            W[Q2_P + (3 * e) * 27 + l] = P0[e];
+            W[Q2_P + (3 * e + 1) * 27 + l] = P1[e];
+            W[Q2_P + (3 * e + 2) * 27 + l] = P2[e];
+            if (MODE == Q2_APPLY && l0 < 2) {
+                W[Q2_A + (3 * e) * 27 + l] = dla * A0[e];
+                W[Q2_A + (3 * e + 1) * 27 + l] = A1[e];
+                W[Q2_A + (3 * e + 2) * 27 + l] = A2[e];
+            }
+        }
+    }
+    __syncthreads();
+    // ---- pass y: thread (a, b, q2) sums over q1
+    const bool vtx = MODE == Q2_APPLY && l0 < 2 && l1 < 2;
+    float S0[NE] = {}, S2[NE] = {}, B01[NE] = {}, B2[NE] = {};
+    if (valid) {
+        const int a = l0, b = l1;
+        const float dlb = b ? 1.0f : -1.0f;
+#pragma unroll
+        for (int q1 = 0; q1 < 3; ++q1) {
+            const float t = gauss_pt(q1);
+            const float Qb = quad_fn(b, t), Db = quad_dfn(b, t), lb = b ? t : 1.0f - t;
+            const int idx = a + 3 * q1 + 9 * l2;
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                S0[e] += W[Q2_P + (3 * e) * 27 + idx] * Qb + W[Q2_P + (3 * e + 1) * 27 + idx] * Db;
+                S2[e] += W[Q2_P + (3 * e + 2) * 27 + idx] * Qb;
+                if (vtx) {
+                    B01[e] += W[Q2_A + (3 * e) * 27 + idx] * lb + W[Q2_A + (3 * e + 1) * 27 + idx] * dlb;
+                    B2[e] += W[Q2_A + (3 * e + 2) * 27 + idx] * lb;
+                }
+            }
+        }
+    }
+    if (valid) {
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            W[(2 * e) * 27 + l] = S0[e];
+            W[(2 * e + 1) * 27 + l] = S2[e];
+            if (vtx) {
+                W[216 + (2 * e) * 27 + l] = B01[e];
+                W[216 + (2 * e + 1) * 27 + l] = B2[e];
+            }
+        }
+    }
+    __syncthreads();
+    // ---- pass z: thread (a, b, c) = its test node
+    const bool vert = MODE == Q2_APPLY && !(l0 & 1) && !(l1 & 1) && !(l2 & 1);
+    const int vidx = (l0 >> 1) + 3 * (l1 >> 1);
+    const float dlc = (l2 >> 1) ? 1.0f : -1.0f;
+    float acc[4] = {};
+    if (valid) {
+#pragma unroll
+        for (int q2 = 0; q2 < 3; ++q2) {
+            const float t = gauss_pt(q2);
+            const float Qc = quad_fn(l2, t), Dc = quad_dfn(l2, t), lc = (l2 >> 1) ? t : 1.0f - t;
+            const int idx = l0 + 3 * l1 + 9 * q2;
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                acc[e] += W[(2 * e) * 27 + idx] * Qc + W[(2 * e + 1) * 27 + idx] * Dc;
+                if (vert)
+                    acc[e] += W[216 + (2 * e) * 27 + vidx + 9 * q2] * lc + W[216 + (2 * e + 1) * 27 + vidx + 9 * q2] * dlc;
+            }
+        }
+    }
+    // the workgroup's 9 element vectors as one block [27 e + node][slot]
+    if (valid) {
+        float *dst = E + (int64_t)blockIdx.x * Q2_GROUP + (int64_t)l * Q2_EPB + s;
+#pragma unroll
+        for (int e = 0; e < NE; ++e) dst[27 * Q2_EPB * e] = acc[e];
     }
 }
 
-// r = b with Dirichlet velocity rows 0 (APPLY), or out = 0 (RHS).
-__global__ void k_q2_init(Mesh m, const float *__restrict__ b, float *__restrict__ out) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 4 * m.n_fine) return;
-    const int64_t n = t % m.n_fine;
-    const int f = (int)(t / m.n_fine);
-    float val = b ? b[t] : 0.0f;
-    if (f < 3 && b) {
-        const int64_t jk = n / m.nf[0];
-        const int i = (int)(n - jk * m.nf[0]), j = (int)(jk % m.nf[1]), k = (int)(jk / m.nf[1]);
-        if (on_dirichlet(m, i, j, k)) val = 0.0f;
+// Elements holding node i on an axis with n elements (nodes 0..2n), in
+// ascending order, with the node's local index in each: an odd i lies in
+// element (i - 1) / 2 only (local 1); an even i is the last node of element
+// i/2 - 1 (local 2) and the first of element i/2 (local 0) where they exist.
+__device__ __forceinline__ int q2_owners(int i, int n, int el[2], int loc[2]) {
+    if (i & 1) {
+        el[0] = (i - 1) >> 1;
+        loc[0] = 1;
+        el[1] = el[0];
+        loc[1] = 1;
+        return 1;
     }
-    out[t] = val;
+    int c = 0;
+    el[0] = el[1] = i >> 1;
+    loc[0] = loc[1] = 0;
+    if (i >= 2) {
+        el[c] = (i >> 1) - 1;
+        loc[c++] = 2;
+    }
+    if ((i >> 1) < n) {
+        el[c] = i >> 1;
+        loc[c++] = 0;
+    }
+    return c;
+}
+
+// Per-node sum of the element vectors in a fixed order (elements ascending
+// in z, then y, then x): APPLY out = b - sum with Dirichlet velocity rows 0;
+// RHS out = sum for the momentum rows (pressure and Dirichlet velocity rows
+// 0).  Threads run over consecutive x nodes.
+template <int MODE>
+__global__ void __launch_bounds__(256) k_q2_sum_nodes(Mesh m, const float *__restrict__ E, const float *__restrict__ b,
+                                                      float *__restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m.n_fine) return;
+    const int64_t jk = t / m.nf[0];
+    const int i = (int)(t - jk * m.nf[0]), j = (int)(jk % m.nf[1]), k = (int)(jk / m.nf[1]);
+    int ex[2], ey[2], ez[2], lx[2], ly[2], lz[2];
+    const int cx = q2_owners(i, m.n[0], ex, lx), cy = q2_owners(j, m.n[1], ey, ly), cz = q2_owners(k, m.n[2], ez, lz);
+    float sum[4] = {};
+#pragma unroll
+    for (int uz = 0; uz < 2; ++uz) {
+        if (uz >= cz) break;
+#pragma unroll
+        for (int uy = 0; uy < 2; ++uy) {
+            if (uy >= cy) break;
+#pragma unroll
+            for (int ux = 0; ux < 2; ++ux) {
+                if (ux >= cx) break;
+                const int64_t M = ex[ux] + (int64_t)m.n[0] * (ey[uy] + (int64_t)m.n[1] * ez[uz]);
+                const int64_t grp = M / Q2_EPB;
+                const float *e = E + grp * Q2_GROUP + (lx[ux] + 3 * ly[uy] + 9 * lz[uz]) * Q2_EPB + (M - grp * Q2_EPB);
+#pragma unroll
+                for (int f = 0; f < 4; ++f)
+                    if (MODE == Q2_APPLY || f < 3) sum[f] += e[27 * Q2_EPB * f];
+            }
+        }
+    }
+    const bool dir = on_dirichlet(m, i, j, k);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        float v;
+        if (MODE == Q2_APPLY)
+            v = (f < 3 && dir) ? 0.0f : b[f * m.n_fine + t] - sum[f];
+        else
+            v = (f == 3 || dir) ? 0.0f : sum[f];
+        out[f * m.n_fine + t] = v;
+    }
 }
 
 // 1-D Q2 prolongation weights from the coarse nodes of level L (n / 2
@@ -551,21 +700,20 @@ static int q2_params(const char *who, const dnnmg_ns *ns, Q2Params *P) {
     return DNNMG_OK;
 }
 
-static int64_t colour_count(const Mesh &m, int col) {
-    int64_t c = 1;
-    for (int a = 0; a < 3; ++a) c *= (m.n[a] - ((col >> a) & 1) + 1) >> 1;
-    return c;
+static size_t q2_ws_bytes(const Mesh &m) {
+    const int64_t groups = (m.n_patches + Q2_EPB - 1) / Q2_EPB;
+    return (size_t)((groups * Q2_GROUP * 4 + 255) / 256 * 256);
 }
 
 template <int MODE>
 static int q2_assemble(const Mesh &m, const Q2Params &P, const double *X, const float *x, const float *fmid,
-                       const float *b, float *out, void *stream) {
-    k_q2_init<<<blocks_for(4 * m.n_fine, 256), 256, 0, STREAM>>>(m, MODE == Q2_APPLY ? b : nullptr, out);
-    for (int col = 0; col < 8; ++col) {
-        const int64_t ne = colour_count(m, col);
-        if (ne == 0) continue;
-        k_q2_element<MODE><<<blocks_for(ne, Q2_EPB), Q2_NT, 0, STREAM>>>(m, P, col, X, x, fmid, out);
-    }
+                       const float *b, float *out, void *ws, size_t ws_bytes, void *stream) {
+    if (!ws || !aligned16(ws) || ws_bytes < q2_ws_bytes(m))
+        return fail(DNNMG_ERR_ARG, "Q2 assembly: workspace of %zu bytes (16-byte aligned) needed, %zu given",
+                    q2_ws_bytes(m), ws_bytes);
+    float *E = static_cast<float *>(ws);
+    k_q2_element<MODE><<<blocks_for(m.n_patches, Q2_EPB), Q2_NT, 0, STREAM>>>(m, P, X, x, fmid, E);
+    k_q2_sum_nodes<MODE><<<blocks_for(m.n_fine, 256), 256, 0, STREAM>>>(m, E, b, out);
     return hip_check(hipGetLastError(), "Q2 element launch");
 }
 
@@ -573,8 +721,14 @@ static int q2_assemble(const Mesh &m, const Q2Params &P, const double *X, const 
 
 using namespace dnnmg;
 
+extern "C" size_t dnnmg_q2_workspace(const dnnmg_box *box) {
+    Mesh m;
+    if (q2_mesh("dnnmg_q2_workspace", box, &m, false)) return 0;
+    return q2_ws_bytes(m);
+}
+
 extern "C" int dnnmg_q2_residual_b(const dnnmg_box *box, const dnnmg_ns *ns, const double *coords, const float *x,
-                                   const float *b, float *r, void *stream) {
+                                   const float *b, float *r, void *ws, size_t ws_bytes, void *stream) {
     Mesh m;
     Q2Params P;
     int rc = q2_mesh("dnnmg_q2_residual_b", box, &m, false);
@@ -582,11 +736,11 @@ extern "C" int dnnmg_q2_residual_b(const dnnmg_box *box, const dnnmg_ns *ns, con
     if ((rc = q2_params("dnnmg_q2_residual_b", ns, &P))) return rc;
     if (!coords || !x || !b || !r) return fail(DNNMG_ERR_ARG, "dnnmg_q2_residual_b: NULL pointer");
     if (r == b || r == x) return fail(DNNMG_ERR_ARG, "dnnmg_q2_residual_b: r must not alias x or b");
-    return q2_assemble<Q2_APPLY>(m, P, coords, x, nullptr, b, r, stream);
+    return q2_assemble<Q2_APPLY>(m, P, coords, x, nullptr, b, r, ws, ws_bytes, stream);
 }
 
 extern "C" int dnnmg_q2_rhs(const dnnmg_box *box, const dnnmg_ns *ns, const double *coords, const float *v,
-                            const float *fmid, float *b, void *stream) {
+                            const float *fmid, float *b, void *ws, size_t ws_bytes, void *stream) {
     Mesh m;
     Q2Params P;
     int rc = q2_mesh("dnnmg_q2_rhs", box, &m, false);
@@ -594,7 +748,7 @@ extern "C" int dnnmg_q2_rhs(const dnnmg_box *box, const dnnmg_ns *ns, const doub
     if ((rc = q2_params("dnnmg_q2_rhs", ns, &P))) return rc;
     if (!coords || !v || !b) return fail(DNNMG_ERR_ARG, "dnnmg_q2_rhs: NULL pointer");
     if (b == v || (fmid && b == fmid)) return fail(DNNMG_ERR_ARG, "dnnmg_q2_rhs: b must not alias v or fmid");
-    return q2_assemble<Q2_RHS>(m, P, coords, v, fmid, nullptr, b, stream);
+    return q2_assemble<Q2_RHS>(m, P, coords, v, fmid, nullptr, b, ws, ws_bytes, stream);
 }
 
 extern "C" int dnnmg_q2_prolong(const dnnmg_box *box, int ncomp, const double *xc, float *xf, void *stream) {

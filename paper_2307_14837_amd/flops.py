@@ -132,30 +132,37 @@ ALG_RESIDUAL_B_GENERAL_PER_NODE = round(ALG_RESIDUAL_GENERAL_PER_NODE * _share_r
 
 
 # ---- Q2/Q2 elements on curved hexahedra (27 Gauss points per element) -----
-# Counted as the element kernel evaluates them: phase 1 per quadrature
-# point (shape functions, Jacobian, fields, Q1 interpolants, inverse, the 28
-# integrand coefficients), phase 2 per (test node, point) pair.
-Q2_SHAPE_PER_POINT = 27 * 4 + 9 * 3             # N and 3 derivatives of 27 functions
-Q2_JACOBIAN_PER_POINT = 27 * 9 * 2 + 14 + 9 * 3 + 1  # 9 FMA per node, det, cofactor inverse
+# Counted as the element kernel evaluates them, with sum factorisation: the
+# node values go to the points by three 1-D passes of 3 terms, the weak-form
+# coefficients back to the nodes likewise; the per-point work (Jacobian
+# inverse, physical gradients, the 8 vertex Q1 interpolants, the 28
+# coefficients) is counted once per point.
 
 
 def q2_residual_flops_per_element() -> int:
     """r = b - A(x) on one Q2 element (momentum and continuity rows with both
     LPS terms), as issued by the element kernel."""
-    fields = 27 * 16 * 2                          # v, grad v, p, grad p: 16 FMA per node
-    interp = 8 * (8 + 15 * 2)                     # Q1 functions of 8 vertices, pi v, grad pi v, grad pi p
-    grads = (9 + 9 + 3 + 3) * 5                   # physical gradients of v, pi v, p, pi p
-    pointwise = 3 * 5 + 3 * 6 + 3                 # convection, R_a, weight
-    coeff = 3 * (15 + 6 + 4 + 30) + (9 + 3 + 15 + 3)  # momentum and continuity coefficients
-    phase1 = 27 * (Q2_SHAPE_PER_POINT + Q2_JACOBIAN_PER_POINT + fields + interp + grads + pointwise + coeff)
-    phase2 = 27 * 27 * (9 + 4 * 14 + 4)           # shape values, 4 equations x 7 FMA, sums
+    interp = 7 * (27 * 2 * 6 + 27 * 3 * 6 + 27 * 4 * 6) - 3 * 27 * 6  # 7 quantities, coordinates without values
+    pi_interp = 8 * (8 + 15 * 2)                  # Q1 functions of 8 vertices, pi v, grad pi v, grad pi p
+    point = (14 + 9 * 3 + 1 + 3                   # det, inverse, weight
+             + (9 + 9 + 3 + 3) * 5                # physical gradients of v, pi v, p, pi p
+             + 3 * 5 + 3 * 6                      # convection, R_a
+             + 3 * (15 + 6 + 4 + 30) + 30)        # momentum and continuity coefficients
+    test = 4 * (27 * (12 + 6 + 6) + 27 * 6 + 27 * 6) + 4 * (18 * 12 + 12 * 9 + 8 * 6)  # x, y, z passes; vertices
     stab = 28 * 8 + 27 * 6 + 10                   # h_T, |v|_inf, alpha_T, delta_T
-    return phase1 + phase2 + stab + 27 * 4        # + the read-modify-write of 108 values
+    return interp + 27 * (pi_interp + point) + test + stab
 
 
 def q2_rhs_flops_per_element() -> int:
     """b = Rhs(v) on one Q2 element (momentum rows), as issued."""
-    fields = 27 * 12 * 2 + 27 * 3 * 2             # v, grad v; forcing values
-    phase1 = 27 * (Q2_SHAPE_PER_POINT + Q2_JACOBIAN_PER_POINT + fields + 9 * 5 + 15 + 3 * (6 + 15))
-    phase2 = 27 * 27 * (9 + 3 * 8 + 3)
-    return phase1 + phase2 + 27 * 3
+    interp = 6 * (27 * 2 * 6 + 27 * 3 * 6 + 27 * 4 * 6) - 3 * 27 * 6 + 3 * 3 * 27 * 6
+    point = 14 + 9 * 3 + 4 + 9 * 5 + 15 + 3 * (6 + 15)
+    test = 3 * (27 * (12 + 6 + 6) + 27 * 6 + 27 * 6)
+    return interp + 27 * point + test
+
+
+def q2_sum_nodes_bytes_per_node() -> float:
+    """Per-node sum of the element vectors: 108 floats per element read once
+    (one element per 8 nodes of the lattice), b read and r written (4
+    fields each)."""
+    return 108 * 4 / 8 + 4 * 4 + 4 * 4

@@ -283,6 +283,7 @@ class Q2CorrectionStep:
         self.coords = torch.as_tensor(np.ascontiguousarray(coords, np.float64).ravel()).to(self.dev)
         # geometry inputs of the curved cells, fixed with the mesh
         self.geom = torch.zeros(3 * self.np, **f32)
+        self.ws_q2 = torch.zeros(L.q2_workspace_bytes(self.box), dtype=torch.uint8, device=self.dev)
         L.dnnmg_q2_patch_features(self.box, self.coords, self.geom)
         self.xc = torch.zeros(4 * self.nc, **f64)
         self.xt = torch.zeros(4 * self.nf, **f32)
@@ -309,12 +310,12 @@ class Q2CorrectionStep:
     def load(self, xc, vprev):
         self.xc.copy_(torch.as_tensor(np.asarray(xc, np.float64).ravel()))
         self.vprev.copy_(torch.as_tensor(np.asarray(vprev, np.float32).ravel()))
-        L.dnnmg_q2_rhs(self.box, self.ns, self.coords, self.vprev, self.b)
+        L.dnnmg_q2_rhs(self.box, self.ns, self.coords, self.vprev, self.b, ws=self.ws_q2)
 
     def step(self, stream=None):
         box, ns = self.box, self.ns
         L.dnnmg_q2_prolong(box, self.xc, self.xt, stream=stream)
-        L.dnnmg_q2_residual_b(box, ns, self.coords, self.xt, self.b, self.r, stream=stream)
+        L.dnnmg_q2_residual_b(box, ns, self.coords, self.xt, self.b, self.r, ws=self.ws_q2, stream=stream)
         if self.fused:
             L.dnnmg_patch_gather_forward_geom(box, self.net, self.geom, self.xt, self.r, self.Y, self.shift,
                                               self.inv_scale, stream=stream)
@@ -324,9 +325,9 @@ class Q2CorrectionStep:
             L.dnnmg_patch_forward(self.net, self.np, self.X, self.ldx, self.Y, stream=stream)
         L.dnnmg_scatter_avg(box, self.Y, self.xcorr, vbase=self.xt, stream=stream)
         if self.indicator:
-            L.dnnmg_q2_residual_b(box, ns, self.coords, self.xcorr, self.b, self.r2, stream=stream)
+            L.dnnmg_q2_residual_b(box, ns, self.coords, self.xcorr, self.b, self.r2, ws=self.ws_q2, stream=stream)
             L.dnnmg_norm2_pair_f64(self.r, self.r2, self.norms, self.ws_norm, stream=stream)
-        L.dnnmg_q2_rhs(box, ns, self.coords, self.xcorr, self.b, stream=stream)
+        L.dnnmg_q2_rhs(box, ns, self.coords, self.xcorr, self.b, ws=self.ws_q2, stream=stream)
         L.dnnmg_q2_restrict(box, self.b, self.bc, stream=stream)
 
     def capture(self):
