@@ -640,6 +640,19 @@ int dnnmg_patch_gather_geom(const dnnmg_box *box, const float *geom, const float
                             const dnnmg_feat *feat, int dtype, float x_scale, void *X, int64_t ldx, void *stream);
 int dnnmg_patch_gather_forward_geom(const dnnmg_box *box, const dnnmg_mlp *net, const float *geom, const float *xt,
                                     const float *r, const dnnmg_feat *feat, float *Y, void *stream);
+/* The 24 geometry features of the paper's network inputs (Sec. 4.2) for
+ * curved cells, a setup call: geo24 FP32 [n_patches][24], for element M from
+ * the positions of its 8 vertices: the 12 vertex-to-vertex edge lengths
+ * (x-directed edges first, then y, then z, each ordered by the other two
+ * corner bits), the 4 diagonals between vertices sharing no face (vertex j
+ * to 7 - j, j = 0..3, vertex j = a + 2b + 4c), and per vertex the mean of the
+ * 3 dihedral angles between the faces meeting there. */
+int dnnmg_q2_patch_features24(const dnnmg_box *box, const double *coords, float *geo24, void *stream);
+/* dnnmg_patch_gather_paper (one-level patches) with the 24 geometry columns
+ * of row M taken from geo24[24 M ..] (device FP32 [n_patches][24], not NULL)
+ * instead of the box's brick features. */
+int dnnmg_patch_gather_paper_geom(const dnnmg_box *box, const float *geo24, const float *x, const float *r,
+                                  const dnnmg_feat *feat, int dtype, void *X, int64_t ldx, void *stream);
 
 #ifdef __cplusplus
 }

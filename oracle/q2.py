@@ -184,7 +184,42 @@ def gather(box, X, x, r, shift=None, inv_scale=None) -> np.ndarray:
     return out
 
 
-def correction_step(box, ns, X, params, xc, b, shift=None, inv_scale=None, indicator=False, threads=1):
+def paper_inputs(box, X, x, r, shift=None, inv_scale=None):
+    """Inputs of the paper's network (Sec. 4.2) on the fine Q2 elements:
+    row M = [u, v, w, p at the 27 nodes, r_u, r_v, r_w, r_p there, the 24
+    geometry features of the element's 8 vertices (general form)],
+    standardised by shift / inv_scale.  x, r [4][N]."""
+    from .deepnet import geometry_features
+
+    bx = _check(box)
+    nn = fine_nodes(bx)
+    X = _f64(X).reshape(3, nn)
+    x = _f64(x).reshape(4, nn)
+    r = _f64(r).reshape(4, nn)
+    nx, ny = 2 * bx.n[0] + 1, 2 * bx.n[1] + 1
+    ne = elements(bx)
+    out = np.zeros((ne, 8 * 27 + 24))
+    for K in range(bx.n[2]):
+        for J in range(bx.n[1]):
+            for I in range(bx.n[0]):
+                M = I + bx.n[0] * (J + bx.n[1] * K)
+                nodes = [(2 * I + a) + nx * ((2 * J + b) + ny * (2 * K + c))
+                         for c in range(3) for b in range(3) for a in range(3)]
+                verts = [(2 * I + 2 * (j & 1)) + nx * ((2 * J + 2 * ((j >> 1) & 1)) + ny * (2 * K + 2 * (j >> 2)))
+                         for j in range(8)]
+                for c in range(4):
+                    out[M, 27 * c:27 * (c + 1)] = x[c, nodes]
+                    out[M, 108 + 27 * c:108 + 27 * (c + 1)] = r[c, nodes]
+                out[M, 216:] = geometry_features(X[:, verts].T)
+    if shift is not None:
+        out -= np.asarray(shift, np.float64)
+    if inv_scale is not None:
+        out *= np.asarray(inv_scale, np.float64)
+    return out
+
+
+def correction_step(box, ns, X, params, xc, b, shift=None, inv_scale=None, indicator=False, threads=1,
+                    network="mlp"):
     """Algorithm 1 after the coarse solve on the Q2 levels, in FP64:
     x~ = P x^L; r = b - A(x~); X = Q(x~, r, geometry); Y = N(X);
     x_corr = (v~ + L(Y), p~); b' = Rhs(v_corr); b'^L = R b'.
@@ -192,8 +227,14 @@ def correction_step(box, ns, X, params, xc, b, shift=None, inv_scale=None, indic
     With indicator, also r(x_corr) and eta = ||r(x_corr)|| / ||r(x~)||."""
     xt = prolong(box, xc)
     r = residual_b(box, ns, X, xt, b)
-    Xin = gather(box, X, xt, r, shift, inv_scale)
-    Y = mlp_forward_rows(Xin, params, threads)
+    if network == "paper":
+        from .deepnet import forward as deep_forward
+
+        Xin = paper_inputs(box, X, xt, r, shift, inv_scale)
+        Y = deep_forward(Xin, *params)
+    else:
+        Xin = gather(box, X, xt, r, shift, inv_scale)
+        Y = mlp_forward_rows(Xin, params, threads)
     d = scatter(box, Y)
     vcorr = xt[:3] + d
     out = dict(xt=xt, r=r, X=Xin, Y=Y, d=d)

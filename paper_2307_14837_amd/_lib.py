@@ -177,6 +177,8 @@ _sig("dnnmg_q2_restrict", [_P(Box), ctypes.c_int, c_vp, c_vp, c_vp])
 _sig("dnnmg_q2_patch_features", [_P(Box), c_vp, c_vp, c_vp])
 _sig("dnnmg_patch_gather_geom", [_P(Box), c_vp, c_vp, c_vp, _P(Feat), ctypes.c_int, c_f, c_vp, c_i64, c_vp])
 _sig("dnnmg_patch_gather_forward_geom", [_P(Box), _P(MLP), c_vp, c_vp, c_vp, _P(Feat), c_vp, c_vp])
+_sig("dnnmg_q2_patch_features24", [_P(Box), c_vp, c_vp, c_vp])
+_sig("dnnmg_patch_gather_paper_geom", [_P(Box), c_vp, c_vp, c_vp, _P(Feat), ctypes.c_int, c_vp, c_i64, c_vp])
 
 EXPORTS = [
     "dnnmg_version", "dnnmg_last_error", "dnnmg_box_sizes", "dnnmg_patch_dofmap", "dnnmg_prolong",
@@ -197,7 +199,7 @@ EXPORTS = [
     "dnnmg_deepnet_forward", "dnnmg_patch_gather_paper", "dnnmg_coarse_levels", "dnnmg_coarse_workspace",
     "dnnmg_coarse_solve", "dnnmg_coarse_jv", "dnnmg_coarse_vcycle", "dnnmg_q2_residual_b", "dnnmg_q2_rhs", "dnnmg_q2_workspace",
     "dnnmg_q2_prolong", "dnnmg_q2_restrict", "dnnmg_q2_patch_features", "dnnmg_patch_gather_geom",
-    "dnnmg_patch_gather_forward_geom",
+    "dnnmg_patch_gather_forward_geom", "dnnmg_q2_patch_features24", "dnnmg_patch_gather_paper_geom",
 ]
 
 # network widths per prediction depth J (levels): inputs, outputs, padded input row
@@ -889,3 +891,22 @@ def dnnmg_patch_gather_forward_geom(box, net, geom, xt, r, Y, shift=None, inv_sc
                                                 _ptr(xt, torch.float32, 3 * nf, "xt"),
                                                 _ptr(r, torch.float32, 3 * nf, "r"), ctypes.byref(feat),
                                                 _ptr(Y, torch.float32, npch * N_OUT, "Y"), _stream(stream)))
+
+
+def dnnmg_q2_patch_features24(box, coords, geo24, stream=None):
+    bx = Box.of(box)
+    nf, _, npch = box_sizes(bx)
+    _check(_lib.dnnmg_q2_patch_features24(ctypes.byref(bx), _ptr(coords, torch.float64, 3 * nf, "coords"),
+                                          _ptr(geo24, torch.float32, 24 * npch, "geo24"), _stream(stream)))
+
+
+def dnnmg_patch_gather_paper_geom(box, geo24, x, r, X, dtype, ldx, shift=None, inv_scale=None, stream=None):
+    bx = Box.of(box)
+    nf, _, npch = box_sizes(bx)
+    feat = Feat(_ptr(shift, torch.float32, 240, "shift"), _ptr(inv_scale, torch.float32, 240, "inv_scale"))
+    if X.numel() * X.element_size() < npch * ldx * {F32: 4, BF16: 2}[dtype]:
+        raise ValueError("X too small")
+    _check(_lib.dnnmg_patch_gather_paper_geom(ctypes.byref(bx), _ptr(geo24, torch.float32, 24 * npch, "geo24"),
+                                              _ptr(x, torch.float32, 4 * nf, "x"), _ptr(r, torch.float32, 4 * nf, "r"),
+                                              ctypes.byref(feat), dtype, _ptr(X, None, None, "X"), ldx,
+                                              _stream(stream)))

@@ -297,7 +297,8 @@ __global__ void __launch_bounds__(256) k_scatter2(Mesh m, Mesh m2, const float *
 
 // ----------------------------------------- inputs of the paper's network --
 // Row M = [x~ (4 fields) at the S^3 patch nodes, r (4 fields) there, 24
-// geometry features]: one thread per four consecutive columns.  The fine
+// geometry features (row M of geo_rows, or the box's brick features when
+// geo_rows is null)]: one thread per four consecutive columns.  The fine
 // lattice is mf (m itself for one-level patches), S = 2^J + 1.
 struct Geo24 {
     float f[24];
@@ -307,7 +308,7 @@ template <int DT, int J>
 __global__ void __launch_bounds__(256)
     k_gather_paper(Mesh m, Mesh mf, const float *__restrict__ x, const float *__restrict__ r,
                    const float *__restrict__ shift, const float *__restrict__ inv_scale, Geo24 geo,
-                   void *__restrict__ Xout, int64_t ldx) {
+                   const float *__restrict__ geo_rows, void *__restrict__ Xout, int64_t ldx) {
     constexpr int P = 1 << J, S = P + 1, NL = S * S * S, NIN = 8 * NL + 24;
     const int quads = (int)(ldx / 4);
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -336,7 +337,8 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int col = col0 + q;
-        float val = col < 8 * NL ? v[q] : (col < NIN ? geo.f[col - 8 * NL] : 0.0f);
+        float val = col < 8 * NL ? v[q]
+                    : (col < NIN ? (geo_rows ? geo_rows[24 * M + (col - 8 * NL)] : geo.f[col - 8 * NL]) : 0.0f);
         if (col < NIN) {
             if (shift) val -= sh[q];
             if (inv_scale) val *= sc[q];
@@ -479,8 +481,8 @@ extern "C" int dnnmg_scatter_avg_levels(const dnnmg_box *box, int levels, const 
     return hip_check(hipGetLastError(), "dnnmg_scatter_avg_levels launch");
 }
 
-extern "C" int dnnmg_patch_gather_paper(const dnnmg_box *box, int levels, const float *x, const float *r,
-                                        const dnnmg_feat *feat, int dtype, void *X, int64_t ldx, void *stream) {
+static int gather_paper(const dnnmg_box *box, int levels, const float *geo_rows, const float *x, const float *r,
+                        const dnnmg_feat *feat, int dtype, void *X, int64_t ldx, void *stream) {
     int rc = check_levels(levels, "dnnmg_patch_gather_paper");
     if (rc) return rc;
     Mesh m, m2;
@@ -501,7 +503,7 @@ extern "C" int dnnmg_patch_gather_paper(const dnnmg_box *box, int levels, const 
     const float *sc = feat ? feat->inv_scale : nullptr;
     const Geo24 geo = brick_features(box);
     const unsigned g = blocks_for(m.n_patches * (ldx / 4), 256);
-#define GP(DT, JJ) k_gather_paper<DT, JJ><<<g, 256, 0, STREAM>>>(m, m2, x, r, sh, sc, geo, X, ldx)
+#define GP(DT, JJ) k_gather_paper<DT, JJ><<<g, 256, 0, STREAM>>>(m, m2, x, r, sh, sc, geo, geo_rows, X, ldx)
     if (dtype == DNNMG_F32 && levels == 1) GP(DNNMG_F32, 1);
     else if (dtype == DNNMG_F32) GP(DNNMG_F32, 2);
     else if (dtype == DNNMG_BF16 && levels == 1) GP(DNNMG_BF16, 1);
@@ -509,4 +511,16 @@ extern "C" int dnnmg_patch_gather_paper(const dnnmg_box *box, int levels, const 
     else return fail(DNNMG_ERR_UNSUPPORTED, "dnnmg_patch_gather_paper: dtype %d (FP32 or BF16)", dtype);
 #undef GP
     return hip_check(hipGetLastError(), "dnnmg_patch_gather_paper launch");
+}
+
+extern "C" int dnnmg_patch_gather_paper(const dnnmg_box *box, int levels, const float *x, const float *r,
+                                        const dnnmg_feat *feat, int dtype, void *X, int64_t ldx, void *stream) {
+    return gather_paper(box, levels, nullptr, x, r, feat, dtype, X, ldx, stream);
+}
+
+extern "C" int dnnmg_patch_gather_paper_geom(const dnnmg_box *box, const float *geo24, const float *x,
+                                             const float *r, const dnnmg_feat *feat, int dtype, void *X,
+                                             int64_t ldx, void *stream) {
+    if (!geo24) return fail(DNNMG_ERR_ARG, "dnnmg_patch_gather_paper_geom: geo24 is NULL");
+    return gather_paper(box, 1, geo24, x, r, feat, dtype, X, ldx, stream);
 }

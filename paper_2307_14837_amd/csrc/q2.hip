@@ -678,6 +678,76 @@ __global__ void k_q2_features(Mesh m, const double *__restrict__ X, float *__res
     geom[t] = (float)(0.25 * sum);
 }
 
+// The 24 geometry features of Sec. 4.2 of element M, from the positions of
+// its 8 vertices P_j (j = a + 2b + 4c at node (2I + 2a, 2J + 2b, 2K + 2c)):
+// the 12 edge lengths (edges along x, then y, then z, each group ordered by
+// the two other corner bits, lower axis first), the 4 diagonals |P_{7-j} -
+// P_j| (j = 0..3), and at each vertex the mean of the three dihedral angles
+// of the faces meeting there (along edge e_a the angle between the
+// components of the other two edges normal to e_a).  FP64, once per mesh.
+__global__ void k_q2_features24(Mesh m, const double *__restrict__ X, float *__restrict__ geo) {
+    const int64_t M = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (M >= m.n_patches) return;
+    const int I = (int)(M % m.n[0]), J = (int)((M / m.n[0]) % m.n[1]), K = (int)(M / ((int64_t)m.n[0] * m.n[1]));
+    const int64_t nf = m.n_fine;
+    double P[8][3];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int64_t n = (2 * I + 2 * (j & 1)) +
+                          (int64_t)m.nf[0] * ((2 * J + 2 * ((j >> 1) & 1)) + (int64_t)m.nf[1] * (2 * K + 2 * (j >> 2)));
+#pragma unroll
+        for (int d = 0; d < 3; ++d) P[j][d] = X[d * nf + n];
+    }
+    auto dist = [&](int i, int j) {
+        double s = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) s += (P[j][d] - P[i][d]) * (P[j][d] - P[i][d]);
+        return sqrt(s);
+    };
+    float *out = geo + 24 * M;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const int o0 = ax == 0 ? 1 : 0, o1 = ax == 2 ? 1 : 2;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int j0 = ((t & 1) << o0) | ((t >> 1) << o1);
+            out[4 * ax + t] = (float)dist(j0, j0 + (1 << ax));
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) out[12 + j] = (float)dist(j, 7 - j);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        double e[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) e[a][d] = P[j ^ (1 << a)][d] - P[j][d];
+        double sum = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
+            const double na = sqrt(e[a][0] * e[a][0] + e[a][1] * e[a][1] + e[a][2] * e[a][2]);
+            double u[3], pb[3], pc[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) u[d] = e[a][d] / na;
+            const double db = e[b][0] * u[0] + e[b][1] * u[1] + e[b][2] * u[2];
+            const double dc = e[c][0] * u[0] + e[c][1] * u[1] + e[c][2] * u[2];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                pb[d] = e[b][d] - db * u[d];
+                pc[d] = e[c][d] - dc * u[d];
+            }
+            const double nb = sqrt(pb[0] * pb[0] + pb[1] * pb[1] + pb[2] * pb[2]);
+            const double nc = sqrt(pc[0] * pc[0] + pc[1] * pc[1] + pc[2] * pc[2]);
+            double cv = (pb[0] * pc[0] + pb[1] * pc[1] + pb[2] * pc[2]) / (nb * nc);
+            cv = cv > 1.0 ? 1.0 : (cv < -1.0 ? -1.0 : cv);
+            sum += acos(cv);
+        }
+        out[16 + j] = (float)(sum / 3.0);
+    }
+}
+
 static int q2_mesh(const char *who, const dnnmg_box *box, Mesh *m, bool even) {
     int rc = make_mesh(box, m);
     if (rc) return rc;
@@ -775,6 +845,15 @@ extern "C" int dnnmg_q2_restrict(const dnnmg_box *box, int ncomp, const float *b
     k_q2_restrict_rows<<<(unsigned)((int64_t)m.nc[1] * m.nc[2]), 256, (size_t)ncomp * m.nf[0] * sizeof(double),
                          STREAM>>>(m, ncomp, bf, bc);
     return hip_check(hipGetLastError(), "dnnmg_q2_restrict launch");
+}
+
+extern "C" int dnnmg_q2_patch_features24(const dnnmg_box *box, const double *coords, float *geo24, void *stream) {
+    Mesh m;
+    int rc = q2_mesh("dnnmg_q2_patch_features24", box, &m, false);
+    if (rc) return rc;
+    if (!coords || !geo24) return fail(DNNMG_ERR_ARG, "dnnmg_q2_patch_features24: NULL pointer");
+    k_q2_features24<<<blocks_for(m.n_patches, 128), 128, 0, STREAM>>>(m, coords, geo24);
+    return hip_check(hipGetLastError(), "dnnmg_q2_patch_features24 launch");
 }
 
 extern "C" int dnnmg_q2_patch_features(const dnnmg_box *box, const double *coords, float *geom, void *stream) {

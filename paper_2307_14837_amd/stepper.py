@@ -264,20 +264,31 @@ class Q2CorrectionStep:
     positions [3][n_fine] (FP64).  b is carried from step to step as in the
     Q1 step (load() computes the first one from vprev).  The fallback of the
     Q1 step (its patch-Vanka sweeps are built for Q1) is not part of this
-    step: with indicator=True, eta is computed and reported only."""
+    step: with indicator=True, eta is computed and reported only.
+    network "mlp": the 165-H-H-81 network (geometry inputs: mean edge
+    lengths); "paper": the paper's form on its 240 inputs (Sec. 3, Sec. 4.2;
+    the 24 geometry features of each curved cell from its vertices), params
+    = (Ws, gammas, betas, means, stds), FP32 or BF16."""
 
     def __init__(self, box, ns, coords, params, dtype="bf16", device="cuda:0", shift=None, inv_scale=None,
-                 indicator=False, fused=True):
+                 indicator=False, fused=True, network="mlp"):
         self.box = L.Box.of(box)
         self.ns = L.NS.of(ns)
         self.dev = torch.device(device)
         self.dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
         self.nf, self.nc, self.np = L.box_sizes(self.box)
-        self.n_in, self.n_out, self.ldx = L.LEVEL_IO[1]
-        self.hidden = int(np.shape(params[0])[1])
+        self.network = network
+        if network == "paper":
+            Ws = params[0]
+            self.n_in, self.n_out = int(np.shape(Ws[0])[0]), int(np.shape(Ws[-1])[1])
+            self.hidden = int(np.shape(Ws[0])[1])
+            self.ldx = L.deepnet_widths(self.n_in, self.hidden, self.n_out)[0]
+        else:
+            self.n_in, self.n_out, self.ldx = L.LEVEL_IO[1]
+            self.hidden = int(np.shape(params[0])[1])
         self.indicator = indicator
         # fused: the gather runs inside the network kernel
-        self.fused = bool(fused)
+        self.fused = bool(fused) and network == "mlp"
         f32 = dict(dtype=torch.float32, device=self.dev)
         f64 = dict(dtype=torch.float64, device=self.dev)
         self.coords = torch.as_tensor(np.ascontiguousarray(coords, np.float64).ravel()).to(self.dev)
@@ -285,6 +296,9 @@ class Q2CorrectionStep:
         self.geom = torch.zeros(3 * self.np, **f32)
         self.ws_q2 = torch.zeros(L.q2_workspace_bytes(self.box), dtype=torch.uint8, device=self.dev)
         L.dnnmg_q2_patch_features(self.box, self.coords, self.geom)
+        if network == "paper":
+            self.geo24 = torch.zeros(24 * self.np, **f32)
+            L.dnnmg_q2_patch_features24(self.box, self.coords, self.geo24)
         self.xc = torch.zeros(4 * self.nc, **f64)
         self.xt = torch.zeros(4 * self.nf, **f32)
         self.vprev = torch.zeros(3 * self.nf, **f32)
@@ -301,10 +315,14 @@ class Q2CorrectionStep:
             self.ws_norm = torch.zeros(2 * L.norm2_workspace_bytes(), dtype=torch.uint8, device=self.dev)
         self.shift = None if shift is None else torch.as_tensor(np.asarray(shift, np.float32)).to(self.dev)
         self.inv_scale = None if inv_scale is None else torch.as_tensor(np.asarray(inv_scale, np.float32)).to(self.dev)
-        W32 = [torch.as_tensor(np.asarray(params[2 * l], np.float32)).contiguous().to(self.dev) for l in range(3)]
-        bias = [torch.as_tensor(np.asarray(params[2 * l + 1], np.float32)).contiguous().to(self.dev) for l in range(3)]
-        self.prepared = L.mlp_prepare(self.dtype, self.hidden, W32, bias, device=self.dev)
-        self.net = self.prepared.net
+        if network == "paper":
+            self.deep = L.DeepNet(self.dtype, *params, device=self.dev)
+        else:
+            W32 = [torch.as_tensor(np.asarray(params[2 * l], np.float32)).contiguous().to(self.dev) for l in range(3)]
+            bias = [torch.as_tensor(np.asarray(params[2 * l + 1], np.float32)).contiguous().to(self.dev)
+                    for l in range(3)]
+            self.prepared = L.mlp_prepare(self.dtype, self.hidden, W32, bias, device=self.dev)
+            self.net = self.prepared.net
         self.graph = None
 
     def load(self, xc, vprev):
@@ -316,7 +334,11 @@ class Q2CorrectionStep:
         box, ns = self.box, self.ns
         L.dnnmg_q2_prolong(box, self.xc, self.xt, stream=stream)
         L.dnnmg_q2_residual_b(box, ns, self.coords, self.xt, self.b, self.r, ws=self.ws_q2, stream=stream)
-        if self.fused:
+        if self.network == "paper":
+            L.dnnmg_patch_gather_paper_geom(box, self.geo24, self.xt, self.r, self.X, self.xdtype, self.ldx,
+                                            self.shift, self.inv_scale, stream=stream)
+            L.dnnmg_deepnet_forward(self.deep, self.np, self.X, self.ldx, self.Y, stream=stream)
+        elif self.fused:
             L.dnnmg_patch_gather_forward_geom(box, self.net, self.geom, self.xt, self.r, self.Y, self.shift,
                                               self.inv_scale, stream=stream)
         else:

@@ -253,3 +253,68 @@ def test_q2_residual_at_scale_matches_oracle(L, q2):
     err = field_err(rg, ro, scale)
     say(f"  per-field error / (|b| + |r|) {['%.1e' % e for e in err]}")
     assert max(err) <= 1e-5
+
+
+@pytest.fixture(scope="module")
+def dn():
+    from oracle import deepnet
+
+    return deepnet
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "bf16"])
+def test_q2_paper_inputs_match_oracle(L, q2, dtype):
+    """The 24 geometry features of curved cells (general form, from the 8
+    vertices) and the paper-form gather on the Q2 elements against the
+    oracle."""
+    box, X, base, x = channel_case((4, 2, 2), 7, amp=0.2)
+    say("q2 paper inputs", dtype)
+    rng = np.random.default_rng(19)
+    r = f32(rng.standard_normal((4, box.n_fine)))
+    x32 = f32(x)
+    shift = f32(rng.standard_normal(240))
+    inv = f32(rng.uniform(0.5, 2.0, 240))
+    geo = torch.zeros(24 * box.n_patches, dtype=torch.float32, device="cuda")
+    L.dnnmg_q2_patch_features24(box, to_gpu(X.ravel()), geo)
+    ldx = 256
+    tdt = torch.float32 if dtype == "fp32" else torch.bfloat16
+    Xg = torch.full((box.n_patches * ldx,), 7.0, dtype=tdt, device="cuda")
+    L.dnnmg_patch_gather_paper_geom(box, geo, to_gpu(x32.ravel()), to_gpu(r.ravel()), Xg,
+                                    L.F32 if dtype == "fp32" else L.BF16, ldx, to_gpu(shift), to_gpu(inv))
+    torch.cuda.synchronize()
+    ref = q2.paper_inputs(box, X, x32.astype(np.float64), r.astype(np.float64))
+    g = geo.cpu().numpy().reshape(-1, 24)
+    assert np.abs(g - ref[:, 216:]).max() <= 1e-6 * np.abs(ref[:, 216:]).max()
+    # the curved cells' angles differ from the brick's pi/2
+    assert np.abs(ref[:, 232:] - np.pi / 2).max() > 1e-3
+    G = Xg.float().cpu().numpy().reshape(box.n_patches, ldx).astype(np.float64)
+    z = (ref - shift.astype(np.float64)) * inv.astype(np.float64)
+    tol = 2e-6 if dtype == "fp32" else 2 ** -8
+    assert np.all(np.abs(G[:, :240] - z) <= tol * np.maximum(np.abs(z), 1.0))
+    assert np.all(G[:, 240:] == 0.0)
+
+
+@pytest.mark.parametrize("dtype,tol", [("fp32", 1e-4), ("bf16", 2e-2)])
+def test_q2_step_paper_network_matches_oracle(q2, dn, dtype, tol):
+    """The correction step on the paper's discretisation with the paper's
+    network form (240-512x8-81, batch normalisation folded, skip
+    connections) against the oracle's step."""
+    from paper_2307_14837_amd import stepper
+
+    box = syn.channel_box((8, 4, 4))
+    X = syn.distorted_coords(box, amp=0.15, seed=13)
+    w = syn.Workload("q2", box, NS, 64, dtype, "channel")
+    inp = syn.step_inputs(w, seed=13)
+    ps = dn.random_params(240, 512, 81, 8, seed=7)
+    ps[0][-1] = ps[0][-1] * 0.05  # a modest correction
+    say("q2 step, paper network", dtype)
+    st = stepper.Q2CorrectionStep(box, NS, X, ps, dtype=dtype, indicator=True, network="paper")
+    out = st.run_numpy(inp.xc, inp.vprev)
+    b = q2.rhs(box, NS, X, f32(inp.vprev).astype(np.float64))
+    r32 = [[np.asarray(a, np.float32).astype(np.float64) for a in group] for group in ps]
+    ref = q2.correction_step(box, NS, X, r32, inp.xc, b, indicator=True, network="paper")
+    for key in ("Y", "d", "b", "bc"):
+        e = rel_l2(out[key], ref[key])
+        say(f"  {key} rel-L2 {e:.2e}")
+        assert e <= tol, key
+    assert abs(out["eta"] - ref["eta"]) <= max(tol, 1e-5) * ref["eta"]
