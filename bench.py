@@ -965,6 +965,7 @@ def main():
             run_step(c2, "bf16", args.steps, args.warmup)[0],
             run_step(c2, "fp32", args.steps, args.warmup)[0],
             run_batched("bf16", sv, wv),
+            run_batched("fp32", sv, wv),
             run_per_box_plain("fp32", sv, wv),
             run_training(20),
             run_coarse_step(),

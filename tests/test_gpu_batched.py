@@ -33,7 +33,7 @@ BOXES = [syn.BoxSpec(n, (1.0, 1.0, 1.0), 7, 0) for n in [(8, 8, 8), (12, 8, 10),
                                                           (6, 4, 2), (16, 8, 12)]]
 
 
-@pytest.mark.parametrize("dtype", ["bf16", "fp8"])
+@pytest.mark.parametrize("dtype", ["fp32", "bf16", "fp8"])
 def test_batched_matches_single(mods, dtype):
     L, batched, stepper = mods
     say("batched vs single", dtype)
