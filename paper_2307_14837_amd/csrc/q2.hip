@@ -58,12 +58,23 @@ __device__ __forceinline__ float quad_dfn(int a, float t) {
     return a == 0 ? 4.0f * t - 3.0f : (a == 1 ? 4.0f - 8.0f * t : 4.0f * t - 1.0f);
 }
 
-constexpr int Q2_EPB = 9;    // elements per workgroup
-constexpr int Q2_NT = 256;   // threads per workgroup (243 active)
+constexpr int Q2_EPB = 8;    // elements per workgroup: one per 32-lane half of each of its 4 waves
+constexpr int Q2_NT = 256;   // threads per workgroup (27 active per half wave)
 constexpr int Q2_NSTR = 8;   // per node: 3 offsets, pad, 4 fields
 constexpr int Q2_CSTR = 28;  // per point: 4 equations x 7 coefficients
 
 enum { Q2_APPLY = 0, Q2_RHS = 1 };
+
+// An element's 27 threads lie in one 32-lane half of a wave and exchange
+// data only among themselves through LDS, so the phases of the element
+// kernel are ordered within the wave: LDS instructions of a wave execute in
+// order, and the fences keep the compiler from moving LDS accesses across
+// the point (no workgroup barrier; the waves of a workgroup run freely).
+__device__ __forceinline__ void q2_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // Per-element LDS arena (floats): the interpolation passes keep 2 and then 3
 // arrays of 27 per quantity (945 for 7 quantities); the test contraction
@@ -83,7 +94,7 @@ constexpr int Q2_GROUP = 108 * Q2_EPB;
 // l = (l0, l1, l2) (l0 + 3 l1 + 9 l2) of an element plays node (a, b, c) or
 // quadrature point (q0, q1, q2) or a mix of both in the 1-D passes below.
 template <int MODE>
-__global__ void __launch_bounds__(Q2_NT, 2) k_q2_element(Mesh m, Q2Params P, const double *__restrict__ X,
+__global__ void __launch_bounds__(Q2_NT, 3) k_q2_element(Mesh m, Q2Params P, const double *__restrict__ X,
                                                       const float *__restrict__ x, const float *__restrict__ fmid,
                                                       float *__restrict__ E) {
     // quantities interpolated to the points: 3 coordinates (gradients only),
@@ -92,14 +103,14 @@ __global__ void __launch_bounds__(Q2_NT, 2) k_q2_element(Mesh m, Q2Params P, con
     constexpr int NQ = MODE == Q2_APPLY ? 7 : 9;
     constexpr int NE = MODE == Q2_APPLY ? 4 : 3; // equations tested
     __shared__ __align__(16) float sQ[Q2_EPB][NQ][27];
-    constexpr int ARENA = Q2_ARENA; // >= 5 * 9 * 27 for the RHS mode's interpolation
+    constexpr int ARENA = MODE == Q2_APPLY ? Q2_ARENA : 5 * NQ * 27; // RHS: interpolation of 9 quantities
     __shared__ __align__(16) float sW[Q2_EPB][ARENA];
     __shared__ float sV[Q2_EPB][27]; // |v|^2 per node
     __shared__ float sH[Q2_EPB][8];  // largest squared vertex distance per vertex
 
     const int tid = threadIdx.x;
-    const int s = tid / 27, l = tid - 27 * (tid / 27);
-    const bool active_t = tid < 27 * Q2_EPB;
+    const int s = tid >> 5, l = tid & 31;
+    const bool active_t = l < 27;
     const int64_t el = (int64_t)blockIdx.x * Q2_EPB + s;
     const bool valid = active_t && el < m.n_patches;
     int I = 0, J = 0, K = 0;
@@ -112,7 +123,7 @@ __global__ void __launch_bounds__(Q2_NT, 2) k_q2_element(Mesh m, Q2Params P, con
     const int l0 = l % 3, l1 = (l / 3) % 3, l2 = l / 9;
     const int gi = 2 * I + l0, gj = 2 * J + l1, gk = 2 * K + l2;
     const int64_t g = gi + (int64_t)m.nf[0] * (gj + (int64_t)m.nf[1] * gk);
-    float *W = sW[s < Q2_EPB ? s : 0];
+    float *W = sW[s];
 
     // ---- stage the element's node positions (relative to its first vertex) and fields
     if (valid) {
@@ -134,7 +145,7 @@ __global__ void __launch_bounds__(Q2_NT, 2) k_q2_element(Mesh m, Q2Params P, con
         }
         sV[s][l] = v2;
     }
-    __syncthreads();
+    q2_wave_sync();
 
     float alphaT = 0.0f, deltaT = 0.0f;
     if (MODE == Q2_APPLY) {
@@ -169,7 +180,7 @@ __global__ void __launch_bounds__(Q2_NT, 2) k_q2_element(Mesh m, Q2Params P, con
             if (MODE == Q2_APPLY || q < 6) W[(2 * q + 1) * 27 + l] = u0 * D0 + u1 * D1 + u2 * D2;
         }
     }
-    __syncthreads();
+    q2_wave_sync();
     if (MODE == Q2_APPLY && valid) {
         float h2 = 0.0f, v2 = 0.0f;
 #pragma unroll
@@ -200,7 +211,7 @@ __global__ void __launch_bounds__(Q2_NT, 2) k_q2_element(Mesh m, Q2Params P, con
             }
         }
     }
-    __syncthreads();
+    q2_wave_sync();
 
     // ---- pass x: thread (q0, q1, q2) = its quadrature point
     float co[4][7];
@@ -332,7 +343,7 @@ __global__ void __launch_bounds__(Q2_NT, 2) k_q2_element(Mesh m, Q2Params P, con
             for (int k = 0; k < 7; ++k) co[3][k] = 0.0f;
         }
     }
-    __syncthreads(); // every pass-x read of the arena is done
+    q2_wave_sync(); // every pass-x read of the arena is done
     if (valid) {
         // the 28 coefficients of the point, equation-major (7 per equation)
         float4 *c4 = reinterpret_cast<float4 *>(W + 28 * l);
@@ -344,7 +355,7 @@ __global__ void __launch_bounds__(Q2_NT, 2) k_q2_element(Mesh m, Q2Params P, con
             c4[k] = make_float4(t4[0], t4[1], t4[2], t4[3]);
         }
     }
-    __syncthreads();
+    q2_wave_sync();
 
     // ---- test contraction, pass x: thread (a, q1, q2) sums over q0
     float P0[NE] = {}, P1[NE] = {}, P2[NE] = {}, A0[NE] = {}, A1[NE] = {}, A2[NE] = {};
@@ -392,7 +403,7 @@ __global__ void __launch_bounds__(Q2_NT, 2) k_q2_element(Mesh m, Q2Params P, con
             }
         }
     }
-    __syncthreads();
+    q2_wave_sync();
     // ---- pass y: thread (a, b, q2) sums over q1
     const bool vtx = MODE == Q2_APPLY && l0 < 2 && l1 < 2;
     float S0[NE] = {}, S2[NE] = {}, B01[NE] = {}, B2[NE] = {};
@@ -426,7 +437,7 @@ __global__ void __launch_bounds__(Q2_NT, 2) k_q2_element(Mesh m, Q2Params P, con
             }
         }
     }
-    __syncthreads();
+    q2_wave_sync();
     // ---- pass z: thread (a, b, c) = its test node
     const bool vert = MODE == Q2_APPLY && !(l0 & 1) && !(l1 & 1) && !(l2 & 1);
     const int vidx = (l0 >> 1) + 3 * (l1 >> 1);
