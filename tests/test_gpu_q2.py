@@ -318,3 +318,32 @@ def test_q2_step_paper_network_matches_oracle(q2, dn, dtype, tol):
         say(f"  {key} rel-L2 {e:.2e}")
         assert e <= tol, key
     assert abs(out["eta"] - ref["eta"]) <= max(tol, 1e-5) * ref["eta"]
+
+
+def test_q2_three_chained_steps_match_oracle_chain(q2):
+    """Three Q2 steps in a row, each residual against the Rhs the previous
+    step left (Algorithm 1's carried right-hand side), against the oracle's
+    chain; the coarse solution is fixed, so the chain exercises the carried b
+    and the network's dependence on it."""
+    from paper_2307_14837_amd import stepper
+
+    box = syn.channel_box((8, 4, 4))
+    X = syn.distorted_coords(box, amp=0.15, seed=17)
+    w = syn.Workload("q2", box, NS, 64, "fp32", "channel")
+    inp = syn.step_inputs(w, seed=17)
+    params = syn.mlp_params(165, 64, 81, seed=8)
+    params[4] = params[4] * 0.1  # a modest correction
+    st = stepper.Q2CorrectionStep(box, NS, X, params, dtype="fp32", indicator=True)
+    st.load(inp.xc, inp.vprev)
+    b = q2.rhs(box, NS, X, f32(inp.vprev).astype(np.float64))
+    p64 = [np.asarray(p, np.float32).astype(np.float64) for p in params]
+    for k in range(3):
+        st.step()
+        torch.cuda.synchronize()
+        ref = q2.correction_step(box, NS, X, p64, inp.xc, b, indicator=True)
+        bg = st.b.cpu().numpy().reshape(4, -1).astype(np.float64)
+        bcg = st.bc.cpu().numpy().reshape(4, -1)
+        e_b, e_bc = rel_l2(bg, ref["b"]), rel_l2(bcg, ref["bc"])
+        say(f"  step {k}: b rel-L2 {e_b:.2e}, bc {e_bc:.2e}")
+        assert e_b <= 1e-5 and e_bc <= 1e-5, k
+        b = ref["b"]
