@@ -610,6 +610,7 @@ def run_q2_step(steps, warmup):
     st.step()
     kms = {name: time_kernel(fn, 10) for name, fn in k.items()}
     ne = st.np
+    acc = q2_accuracy() if not args.no_cpu else None
     res_flop = flops.q2_residual_flops_per_element() * ne
     rhs_flop = flops.q2_rhs_flops_per_element() * ne
     n = st.norms.cpu().numpy()
@@ -624,7 +625,37 @@ def run_q2_step(steps, warmup):
                             "frac_of_fp32_vector_peak": res_flop / (kms["q2_residual_b"] * 1e-3) / 1e12
                             / FP32_VALU_PEAK_TFLOPS},
             "q2_rhs_tflops": rhs_flop / (kms["q2_rhs"] * 1e-3) / 1e12,
-            "eta_last": float(np.sqrt(n[1] / n[0])) if n[0] > 0 else None}
+            "eta_last": float(np.sqrt(n[1] / n[0])) if n[0] > 0 else None,
+            "accuracy_rel_l2": acc}
+
+
+def q2_accuracy():
+    """One Q2 step against the FP64 Q2 oracle on a curved channel of 64 x 16 x
+    16 fine Q2 elements (the same mesh recipe; the oracle takes seconds there),
+    seeded weights of width 512, indicator evaluated: rel-L2 of r, d, b^L and
+    eta for the FP8 and BF16 networks."""
+    import dnnmg_synth as syn
+    from oracle import q2 as oq2
+    from paper_2307_14837_amd import stepper
+
+    w = syn.cfg2()
+    X = syn.distorted_coords(w.box, amp=0.15, seed=0)
+    inp = syn.step_inputs(w, seed=0)
+    params = syn.mlp_params(165, 512, 81, seed=0)
+    b = oq2.rhs(w.box, w.ns, X, np.asarray(inp.vprev, np.float32).astype(np.float64))
+    p64 = [np.asarray(p, np.float32).astype(np.float64) for p in params]
+    ref = oq2.correction_step(w.box, w.ns, X, p64, inp.xc, b, indicator=True, threads=CPU_WORKERS)
+    out = {"workload": "channel_64x16x16_q2_curved", "elements": w.box.n_patches}
+    for dt in ("fp8", "bf16"):
+        st = stepper.Q2CorrectionStep(w.box, w.ns, X, params, dtype=dt, indicator=True)
+        g = st.run_numpy(inp.xc, inp.vprev)
+        out[dt] = {"r": rel(g["r"], ref["r"]), "d": rel(g["d"], ref["d"]), "bc": rel(g["bc"], ref["bc"]),
+                   "eta_gpu": g["eta"], "eta_oracle": ref["eta"]}
+    return out
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
 
 
 def q2_profile(steps):
