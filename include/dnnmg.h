@@ -603,7 +603,7 @@ int dnnmg_coarse_vcycle(const dnnmg_box *box, const dnnmg_ns *ns, const float *x
  *   largest distance between two vertices of T; |v|_inf,T: the largest |v|
  *   over T's 27 nodes; 3 x 3 x 3 Gauss points per element; FP32 arithmetic.
  *   Element vectors go to the workspace ws (at least dnnmg_q2_workspace(box)
- *   bytes, 16-byte aligned: 108 floats per element) and are summed per node
+ *   bytes, 16-byte aligned: 189 floats per element) and are summed per node
  *   in a fixed order, so results are reproducible bit for bit.
  * dnnmg_q2_residual_b: r = b - A(x), A holding the iterate's terms of eq.
  *   (4cranknicholson3) and the LPS terms; x FP32 [4][n_fine], b FP32
@@ -618,6 +618,14 @@ int dnnmg_q2_residual_b(const dnnmg_box *box, const dnnmg_ns *ns, const double *
                         const float *b, float *r, void *ws, size_t ws_bytes, void *stream);
 int dnnmg_q2_rhs(const dnnmg_box *box, const dnnmg_ns *ns, const double *coords, const float *v,
                  const float *fmid, float *b, void *ws, size_t ws_bytes, void *stream);
+/* Both at one iterate (Algorithm 1 after the correction: the indicator's
+ * residual and the next step's right-hand side at x_corr): r = b - A(x) as
+ * dnnmg_q2_residual_b and bnext = Rhs(velocity of x) as dnnmg_q2_rhs without
+ * forcing, in one pass that shares the element work.  bnext may be b itself
+ * (each node's b is read before it is replaced); r must not alias x, b or
+ * bnext.  ws as for dnnmg_q2_residual_b. */
+int dnnmg_q2_residual_rhs(const dnnmg_box *box, const dnnmg_ns *ns, const double *coords, const float *x,
+                          const float *b, float *r, float *bnext, void *ws, size_t ws_bytes, void *stream);
 /* Prolongation of Algorithm 1 between the Q2 spaces: each fine node takes the
  * Q2 interpolant of its coarse element (reference coordinates) in FP64,
  * rounded to FP32.  xc FP64 [ncomp][n_coarse] -> xf FP32 [ncomp][n_fine],

@@ -172,6 +172,7 @@ _sig("dnnmg_coarse_vcycle", [_P(Box), _P(NS), c_vp, c_vp, c_vp, _P(CoarseOpts), 
 _sig("dnnmg_q2_workspace", [_P(Box)], c_sz)
 _sig("dnnmg_q2_residual_b", [_P(Box), _P(NS), c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp])
 _sig("dnnmg_q2_rhs", [_P(Box), _P(NS), c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp])
+_sig("dnnmg_q2_residual_rhs", [_P(Box), _P(NS), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp])
 _sig("dnnmg_q2_prolong", [_P(Box), ctypes.c_int, c_vp, c_vp, c_vp])
 _sig("dnnmg_q2_restrict", [_P(Box), ctypes.c_int, c_vp, c_vp, c_vp])
 _sig("dnnmg_q2_patch_features", [_P(Box), c_vp, c_vp, c_vp])
@@ -197,7 +198,7 @@ EXPORTS = [
     "dnnmg_patch_dofmap_levels", "dnnmg_prolong_levels", "dnnmg_restrict_levels", "dnnmg_patch_gather_levels",
     "dnnmg_scatter_avg_levels", "dnnmg_deepnet_widths", "dnnmg_deepnet_packed_bytes", "dnnmg_deepnet_prepare",
     "dnnmg_deepnet_forward", "dnnmg_patch_gather_paper", "dnnmg_coarse_levels", "dnnmg_coarse_workspace",
-    "dnnmg_coarse_solve", "dnnmg_coarse_jv", "dnnmg_coarse_vcycle", "dnnmg_q2_residual_b", "dnnmg_q2_rhs", "dnnmg_q2_workspace",
+    "dnnmg_coarse_solve", "dnnmg_coarse_jv", "dnnmg_coarse_vcycle", "dnnmg_q2_residual_b", "dnnmg_q2_rhs", "dnnmg_q2_workspace", "dnnmg_q2_residual_rhs",
     "dnnmg_q2_prolong", "dnnmg_q2_restrict", "dnnmg_q2_patch_features", "dnnmg_patch_gather_geom",
     "dnnmg_patch_gather_forward_geom", "dnnmg_q2_patch_features24", "dnnmg_patch_gather_paper_geom",
 ]
@@ -837,6 +838,18 @@ def dnnmg_q2_residual_b(box, ns, coords, x, b, r, ws=None, stream=None):
                                     _ptr(x, torch.float32, 4 * nf, "x"), _ptr(b, torch.float32, 4 * nf, "b"),
                                     _ptr(r, torch.float32, 4 * nf, "r"), _ptr(ws, None, None, "ws"),
                                     ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def dnnmg_q2_residual_rhs(box, ns, coords, x, b, r, bnext, ws=None, stream=None):
+    """r = b - A(x) and bnext = Rhs(x[:3]) in one pass (bnext may be b)."""
+    bx = Box.of(box)
+    nf, _, _ = box_sizes(bx)
+    ws = _q2_ws(bx, ws)
+    _check(_lib.dnnmg_q2_residual_rhs(ctypes.byref(bx), ctypes.byref(NS.of(ns)),
+                                      _ptr(coords, torch.float64, 3 * nf, "coords"),
+                                      _ptr(x, torch.float32, 4 * nf, "x"), _ptr(b, torch.float32, 4 * nf, "b"),
+                                      _ptr(r, torch.float32, 4 * nf, "r"), _ptr(bnext, torch.float32, 4 * nf, "bnext"),
+                                      _ptr(ws, None, None, "ws"), ws.numel() * ws.element_size(), _stream(stream)))
 
 
 def dnnmg_q2_rhs(box, ns, coords, v, b_out, fmid=None, ws=None, stream=None):

@@ -63,7 +63,9 @@ constexpr int Q2_NT = 256;   // threads per workgroup (27 active per half wave)
 constexpr int Q2_NSTR = 8;   // per node: 3 offsets, pad, 4 fields
 constexpr int Q2_CSTR = 28;  // per point: 4 equations x 7 coefficients
 
-enum { Q2_APPLY = 0, Q2_RHS = 1 };
+// APPLY: A(x); RHS: Rhs(v, fmid); BOTH: A(x) and Rhs(v) (no forcing) at the
+// same iterate, sharing the staging, the interpolation and the point terms.
+enum { Q2_APPLY = 0, Q2_RHS = 1, Q2_BOTH = 2 };
 
 // An element's 27 threads lie in one 32-lane half of a wave and exchange
 // data only among themselves through LDS, so the phases of the element
@@ -85,6 +87,7 @@ constexpr int Q2_ARENA = 1404;
 constexpr int Q2_P = 756, Q2_A = 1080;
 // element vectors of one workgroup in the workspace: [27 e + node][slot]
 constexpr int Q2_GROUP = 108 * Q2_EPB;
+constexpr int Q2_GROUP_BOTH = 189 * Q2_EPB; // 4 + 3 equations
 
 // MODE Q2_APPLY: the element vector of A(x) (x = u, v, w, p); MODE Q2_RHS:
 // that of Rhs(x = velocity, fmid).  The element vectors of workgroup g
@@ -100,10 +103,11 @@ __global__ void __launch_bounds__(Q2_NT, 3) k_q2_element(Mesh m, Q2Params P, con
     // quantities interpolated to the points: 3 coordinates (gradients only),
     // u, v, w (values and gradients), then p (APPLY) or the 3 forcing
     // components (RHS, values only)
-    constexpr int NQ = MODE == Q2_APPLY ? 7 : 9;
-    constexpr int NE = MODE == Q2_APPLY ? 4 : 3; // equations tested
+    constexpr bool HAS_A = MODE != Q2_RHS; // the iterate's terms (and p, the LPS terms)
+    constexpr int NQ = HAS_A ? 7 : 9;
+    constexpr int NE = HAS_A ? 4 : 3; // equations of the first test contraction
     __shared__ __align__(16) float sQ[Q2_EPB][NQ][27];
-    constexpr int ARENA = MODE == Q2_APPLY ? Q2_ARENA : 5 * NQ * 27; // RHS: interpolation of 9 quantities
+    constexpr int ARENA = HAS_A ? Q2_ARENA : 5 * NQ * 27; // RHS: interpolation of 9 quantities
     __shared__ __align__(16) float sW[Q2_EPB][ARENA];
     __shared__ float sV[Q2_EPB][27]; // |v|^2 per node
     __shared__ float sH[Q2_EPB][8];  // largest squared vertex distance per vertex
@@ -137,7 +141,7 @@ __global__ void __launch_bounds__(Q2_NT, 3) k_q2_element(Mesh m, Q2Params P, con
             sQ[s][3 + f][l] = val;
             v2 += val * val;
         }
-        if (MODE == Q2_APPLY) {
+        if (HAS_A) {
             sQ[s][6][l] = x[3 * nf + g];
         } else {
 #pragma unroll
@@ -148,7 +152,7 @@ __global__ void __launch_bounds__(Q2_NT, 3) k_q2_element(Mesh m, Q2Params P, con
     q2_wave_sync();
 
     float alphaT = 0.0f, deltaT = 0.0f;
-    if (MODE == Q2_APPLY) {
+    if (HAS_A) {
         // h_T = the largest vertex distance; |v|_inf = the largest |v| over the 27 nodes
         if (valid && l < 8) {
             const int vi = 2 * (l & 1) + 6 * ((l >> 1) & 1) + 18 * ((l >> 2) & 1);
@@ -177,11 +181,11 @@ __global__ void __launch_bounds__(Q2_NT, 3) k_q2_element(Mesh m, Q2Params P, con
         for (int q = 0; q < NQ; ++q) {
             const float u0 = sQ[s][q][n0], u1 = sQ[s][q][n0 + 9], u2 = sQ[s][q][n0 + 18];
             W[(2 * q) * 27 + l] = u0 * Q0 + u1 * Q1 + u2 * Q2;
-            if (MODE == Q2_APPLY || q < 6) W[(2 * q + 1) * 27 + l] = u0 * D0 + u1 * D1 + u2 * D2;
+            if (HAS_A || q < 6) W[(2 * q + 1) * 27 + l] = u0 * D0 + u1 * D1 + u2 * D2;
         }
     }
     q2_wave_sync();
-    if (MODE == Q2_APPLY && valid) {
+    if (HAS_A && valid) {
         float h2 = 0.0f, v2 = 0.0f;
 #pragma unroll
         for (int v = 0; v < 8; ++v) h2 = fmaxf(h2, sH[s][v]);
@@ -204,7 +208,7 @@ __global__ void __launch_bounds__(Q2_NT, 3) k_q2_element(Mesh m, Q2Params P, con
             const float *z = W + (2 * q) * 27 + n0;
             const float z0 = z[0], z1 = z[3], z2 = z[6];
             W[YOFF + (3 * q) * 27 + l] = z0 * Q0 + z1 * Q1 + z2 * Q2;
-            if (MODE == Q2_APPLY || q < 6) {
+            if (HAS_A || q < 6) {
                 const float *w = W + (2 * q + 1) * 27 + n0;
                 W[YOFF + (3 * q + 1) * 27 + l] = z0 * D0 + z1 * D1 + z2 * D2;
                 W[YOFF + (3 * q + 2) * 27 + l] = w[0] * Q0 + w[3] * Q1 + w[6] * Q2;
@@ -215,6 +219,7 @@ __global__ void __launch_bounds__(Q2_NT, 3) k_q2_element(Mesh m, Q2Params P, con
 
     // ---- pass x: thread (q0, q1, q2) = its quadrature point
     float co[4][7];
+    float coR[3][4]; // BOTH: the Rhs's factors of phi and of its reference gradient
     if (valid) {
         const float t0 = gauss_pt(l0), t1 = gauss_pt(l1), t2 = gauss_pt(l2);
         const float Q0 = quad_fn(0, t0), Q1 = quad_fn(1, t0), Q2 = quad_fn(2, t0);
@@ -225,7 +230,7 @@ __global__ void __launch_bounds__(Q2_NT, 3) k_q2_element(Mesh m, Q2Params P, con
         for (int q = 0; q < NQ; ++q) {
             const float *y0 = W + YOFF + (3 * q) * 27 + n0;
             val[q] = y0[0] * Q0 + y0[1] * Q1 + y0[2] * Q2;
-            if (MODE == Q2_APPLY || q < 6) {
+            if (HAS_A || q < 6) {
                 const float *y1 = W + YOFF + (3 * q + 1) * 27 + n0;
                 const float *y2 = W + YOFF + (3 * q + 2) * 27 + n0;
                 grd[q][0] = y0[0] * D0 + y0[1] * D1 + y0[2] * D2;
@@ -269,7 +274,16 @@ __global__ void __launch_bounds__(Q2_NT, 3) k_q2_element(Mesh m, Q2Params P, con
 #pragma unroll
         for (int q = 0; q < 3; ++q) conv[q] = v[0] * G[q][0] + v[1] * G[q][1] + v[2] * G[q][2];
 
-        if (MODE == Q2_APPLY) {
+        if (HAS_A) {
+            if (MODE == Q2_BOTH) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    coR[q][0] = w * (P.inv_dt * v[q] - 0.5f * conv[q]);
+#pragma unroll
+                    for (int e = 0; e < 3; ++e)
+                        coR[q][1 + e] = -w * P.half_nu * (Ji[e][0] * G[q][0] + Ji[e][1] * G[q][1] + Ji[e][2] * G[q][2]);
+                }
+            }
             const float p = val[6];
             // Q1 interpolants from the 8 vertices (local nodes 2va + 6vb + 18vc)
             const float Lx[2] = {1.0f - t0, t0}, Ly[2] = {1.0f - t1, t1}, Lz[2] = {1.0f - t2, t2};
@@ -381,7 +395,7 @@ __global__ void __launch_bounds__(Q2_NT, 3) k_q2_element(Mesh m, Q2Params P, con
                 P0[e] += c[0] * Qa + c[1] * Da;
                 P1[e] += c[2] * Qa;
                 P2[e] += c[3] * Qa;
-                if (MODE == Q2_APPLY) {
+                if (HAS_A) {
                     A0[e] += c[4];
                     A1[e] += c[5] * la;
                     A2[e] += c[6] * la;
@@ -396,7 +410,7 @@ __global__ void __launch_bounds__(Q2_NT, 3) k_q2_element(Mesh m, Q2Params P, con
             W[Q2_P + (3 * e) * 27 + l] = P0[e];
             W[Q2_P + (3 * e + 1) * 27 + l] = P1[e];
             W[Q2_P + (3 * e + 2) * 27 + l] = P2[e];
-            if (MODE == Q2_APPLY && l0 < 2) {
+            if (HAS_A && l0 < 2) {
                 W[Q2_A + (3 * e) * 27 + l] = dla * A0[e];
                 W[Q2_A + (3 * e + 1) * 27 + l] = A1[e];
                 W[Q2_A + (3 * e + 2) * 27 + l] = A2[e];
@@ -405,7 +419,7 @@ __global__ void __launch_bounds__(Q2_NT, 3) k_q2_element(Mesh m, Q2Params P, con
     }
     q2_wave_sync();
     // ---- pass y: thread (a, b, q2) sums over q1
-    const bool vtx = MODE == Q2_APPLY && l0 < 2 && l1 < 2;
+    const bool vtx = HAS_A && l0 < 2 && l1 < 2;
     float S0[NE] = {}, S2[NE] = {}, B01[NE] = {}, B2[NE] = {};
     if (valid) {
         const int a = l0, b = l1;
@@ -439,7 +453,7 @@ __global__ void __launch_bounds__(Q2_NT, 3) k_q2_element(Mesh m, Q2Params P, con
     }
     q2_wave_sync();
     // ---- pass z: thread (a, b, c) = its test node
-    const bool vert = MODE == Q2_APPLY && !(l0 & 1) && !(l1 & 1) && !(l2 & 1);
+    const bool vert = HAS_A && !(l0 & 1) && !(l1 & 1) && !(l2 & 1);
     const int vidx = (l0 >> 1) + 3 * (l1 >> 1);
     const float dlc = (l2 >> 1) ? 1.0f : -1.0f;
     float acc[4] = {};
@@ -457,11 +471,84 @@ __global__ void __launch_bounds__(Q2_NT, 3) k_q2_element(Mesh m, Q2Params P, con
             }
         }
     }
-    // the workgroup's 9 element vectors as one block [27 e + node][slot]
+    // BOTH: a second test contraction for the Rhs's 3 equations (factors of
+    // phi and of its reference gradient only), through the same arena: the
+    // coefficients at 0..323, the x-pass sums at 324..566, the y-pass sums at
+    // 567..728
+    float accR[3] = {};
+    if constexpr (MODE == Q2_BOTH) {
+        q2_wave_sync(); // the first contraction's reads are done
+        if (valid) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) W[(4 * q + k) * 27 + l] = coR[q][k];
+        }
+        q2_wave_sync();
+        if (valid) {
+            float R0[3] = {}, R1[3] = {}, R2[3] = {};
+#pragma unroll
+            for (int q0 = 0; q0 < 3; ++q0) {
+                const float t = gauss_pt(q0);
+                const float Qa = quad_fn(l0, t), Da = quad_dfn(l0, t);
+                const int idx = q0 + 3 * l1 + 9 * l2;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    R0[q] += W[(4 * q) * 27 + idx] * Qa + W[(4 * q + 1) * 27 + idx] * Da;
+                    R1[q] += W[(4 * q + 2) * 27 + idx] * Qa;
+                    R2[q] += W[(4 * q + 3) * 27 + idx] * Qa;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                W[324 + (3 * q) * 27 + l] = R0[q];
+                W[324 + (3 * q + 1) * 27 + l] = R1[q];
+                W[324 + (3 * q + 2) * 27 + l] = R2[q];
+            }
+        }
+        q2_wave_sync();
+        if (valid) {
+            float T0[3] = {}, T2[3] = {};
+#pragma unroll
+            for (int q1 = 0; q1 < 3; ++q1) {
+                const float t = gauss_pt(q1);
+                const float Qb = quad_fn(l1, t), Db = quad_dfn(l1, t);
+                const int idx = l0 + 3 * q1 + 9 * l2;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    T0[q] += W[324 + (3 * q) * 27 + idx] * Qb + W[324 + (3 * q + 1) * 27 + idx] * Db;
+                    T2[q] += W[324 + (3 * q + 2) * 27 + idx] * Qb;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                W[567 + (2 * q) * 27 + l] = T0[q];
+                W[567 + (2 * q + 1) * 27 + l] = T2[q];
+            }
+        }
+        q2_wave_sync();
+        if (valid) {
+#pragma unroll
+            for (int q2 = 0; q2 < 3; ++q2) {
+                const float t = gauss_pt(q2);
+                const float Qc = quad_fn(l2, t), Dc = quad_dfn(l2, t);
+                const int idx = l0 + 3 * l1 + 9 * q2;
+#pragma unroll
+                for (int q = 0; q < 3; ++q)
+                    accR[q] += W[567 + (2 * q) * 27 + idx] * Qc + W[567 + (2 * q + 1) * 27 + idx] * Dc;
+            }
+        }
+    }
+    // the workgroup's 8 element vectors as one block [27 e + node][slot]
     if (valid) {
-        float *dst = E + (int64_t)blockIdx.x * Q2_GROUP + (int64_t)l * Q2_EPB + s;
+        constexpr int GROUPW = MODE == Q2_BOTH ? Q2_GROUP_BOTH : Q2_GROUP;
+        float *dst = E + (int64_t)blockIdx.x * GROUPW + (int64_t)l * Q2_EPB + s;
 #pragma unroll
         for (int e = 0; e < NE; ++e) dst[27 * Q2_EPB * e] = acc[e];
+        if constexpr (MODE == Q2_BOTH) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) dst[27 * Q2_EPB * (4 + q)] = accR[q];
+        }
     }
 }
 
@@ -496,15 +583,17 @@ __device__ __forceinline__ int q2_owners(int i, int n, int el[2], int loc[2]) {
 // RHS out = sum for the momentum rows (pressure and Dirichlet velocity rows
 // 0).  Threads run over consecutive x nodes.
 template <int MODE>
-__global__ void __launch_bounds__(256) k_q2_sum_nodes(Mesh m, const float *__restrict__ E, const float *__restrict__ b,
-                                                      float *__restrict__ out) {
+__global__ void __launch_bounds__(256) k_q2_sum_nodes(Mesh m, const float *__restrict__ E, const float *b, float *out,
+                                                      float *bnext) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= m.n_fine) return;
     const int64_t jk = t / m.nf[0];
     const int i = (int)(t - jk * m.nf[0]), j = (int)(jk % m.nf[1]), k = (int)(jk / m.nf[1]);
     int ex[2], ey[2], ez[2], lx[2], ly[2], lz[2];
     const int cx = q2_owners(i, m.n[0], ex, lx), cy = q2_owners(j, m.n[1], ey, ly), cz = q2_owners(k, m.n[2], ez, lz);
-    float sum[4] = {};
+    constexpr int NF = MODE == Q2_BOTH ? 7 : 4;
+    constexpr int GROUPW = MODE == Q2_BOTH ? Q2_GROUP_BOTH : Q2_GROUP;
+    float sum[NF] = {};
 #pragma unroll
     for (int uz = 0; uz < 2; ++uz) {
         if (uz >= cz) break;
@@ -516,22 +605,28 @@ __global__ void __launch_bounds__(256) k_q2_sum_nodes(Mesh m, const float *__res
                 if (ux >= cx) break;
                 const int64_t M = ex[ux] + (int64_t)m.n[0] * (ey[uy] + (int64_t)m.n[1] * ez[uz]);
                 const int64_t grp = M / Q2_EPB;
-                const float *e = E + grp * Q2_GROUP + (lx[ux] + 3 * ly[uy] + 9 * lz[uz]) * Q2_EPB + (M - grp * Q2_EPB);
+                const float *e = E + grp * GROUPW + (lx[ux] + 3 * ly[uy] + 9 * lz[uz]) * Q2_EPB + (M - grp * Q2_EPB);
 #pragma unroll
-                for (int f = 0; f < 4; ++f)
-                    if (MODE == Q2_APPLY || f < 3) sum[f] += e[27 * Q2_EPB * f];
+                for (int f = 0; f < NF; ++f)
+                    if (MODE != Q2_RHS || f < 3) sum[f] += e[27 * Q2_EPB * f];
             }
         }
     }
     const bool dir = on_dirichlet(m, i, j, k);
+    // b is read before bnext (which may be b itself) is written
+    float r[4];
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-        float v;
-        if (MODE == Q2_APPLY)
-            v = (f < 3 && dir) ? 0.0f : b[f * m.n_fine + t] - sum[f];
+        if (MODE != Q2_RHS)
+            r[f] = (f < 3 && dir) ? 0.0f : b[f * m.n_fine + t] - sum[f];
         else
-            v = (f == 3 || dir) ? 0.0f : sum[f];
-        out[f * m.n_fine + t] = v;
+            r[f] = (f == 3 || dir) ? 0.0f : sum[f];
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f) out[f * m.n_fine + t] = r[f];
+    if constexpr (MODE == Q2_BOTH) {
+#pragma unroll
+        for (int f = 0; f < 4; ++f) bnext[f * m.n_fine + t] = (f == 3 || dir) ? 0.0f : sum[4 + f];
     }
 }
 
@@ -783,18 +878,18 @@ static int q2_params(const char *who, const dnnmg_ns *ns, Q2Params *P) {
 
 static size_t q2_ws_bytes(const Mesh &m) {
     const int64_t groups = (m.n_patches + Q2_EPB - 1) / Q2_EPB;
-    return (size_t)((groups * Q2_GROUP * 4 + 255) / 256 * 256);
+    return (size_t)((groups * Q2_GROUP_BOTH * 4 + 255) / 256 * 256);
 }
 
 template <int MODE>
 static int q2_assemble(const Mesh &m, const Q2Params &P, const double *X, const float *x, const float *fmid,
-                       const float *b, float *out, void *ws, size_t ws_bytes, void *stream) {
+                       const float *b, float *out, void *ws, size_t ws_bytes, void *stream, float *bnext = nullptr) {
     if (!ws || !aligned16(ws) || ws_bytes < q2_ws_bytes(m))
         return fail(DNNMG_ERR_ARG, "Q2 assembly: workspace of %zu bytes (16-byte aligned) needed, %zu given",
                     q2_ws_bytes(m), ws_bytes);
     float *E = static_cast<float *>(ws);
     k_q2_element<MODE><<<blocks_for(m.n_patches, Q2_EPB), Q2_NT, 0, STREAM>>>(m, P, X, x, fmid, E);
-    k_q2_sum_nodes<MODE><<<blocks_for(m.n_fine, 256), 256, 0, STREAM>>>(m, E, b, out);
+    k_q2_sum_nodes<MODE><<<blocks_for(m.n_fine, 256), 256, 0, STREAM>>>(m, E, b, out, bnext);
     return hip_check(hipGetLastError(), "Q2 element launch");
 }
 
@@ -818,6 +913,19 @@ extern "C" int dnnmg_q2_residual_b(const dnnmg_box *box, const dnnmg_ns *ns, con
     if (!coords || !x || !b || !r) return fail(DNNMG_ERR_ARG, "dnnmg_q2_residual_b: NULL pointer");
     if (r == b || r == x) return fail(DNNMG_ERR_ARG, "dnnmg_q2_residual_b: r must not alias x or b");
     return q2_assemble<Q2_APPLY>(m, P, coords, x, nullptr, b, r, ws, ws_bytes, stream);
+}
+
+extern "C" int dnnmg_q2_residual_rhs(const dnnmg_box *box, const dnnmg_ns *ns, const double *coords, const float *x,
+                                     const float *b, float *r, float *bnext, void *ws, size_t ws_bytes, void *stream) {
+    Mesh m;
+    Q2Params P;
+    int rc = q2_mesh("dnnmg_q2_residual_rhs", box, &m, false);
+    if (rc) return rc;
+    if ((rc = q2_params("dnnmg_q2_residual_rhs", ns, &P))) return rc;
+    if (!coords || !x || !b || !r || !bnext) return fail(DNNMG_ERR_ARG, "dnnmg_q2_residual_rhs: NULL pointer");
+    if (r == b || r == x || r == bnext || bnext == x)
+        return fail(DNNMG_ERR_ARG, "dnnmg_q2_residual_rhs: r and bnext must not alias x, and r not b or bnext");
+    return q2_assemble<Q2_BOTH>(m, P, coords, x, nullptr, b, r, ws, ws_bytes, stream, bnext);
 }
 
 extern "C" int dnnmg_q2_rhs(const dnnmg_box *box, const dnnmg_ns *ns, const double *coords, const float *v,

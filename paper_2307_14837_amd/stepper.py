@@ -347,9 +347,12 @@ class Q2CorrectionStep:
             L.dnnmg_patch_forward(self.net, self.np, self.X, self.ldx, self.Y, stream=stream)
         L.dnnmg_scatter_avg(box, self.Y, self.xcorr, vbase=self.xt, stream=stream)
         if self.indicator:
-            L.dnnmg_q2_residual_b(box, ns, self.coords, self.xcorr, self.b, self.r2, ws=self.ws_q2, stream=stream)
+            # the indicator's residual and the next right-hand side at x_corr in one pass
+            L.dnnmg_q2_residual_rhs(box, ns, self.coords, self.xcorr, self.b, self.r2, self.b, ws=self.ws_q2,
+                                    stream=stream)
             L.dnnmg_norm2_pair_f64(self.r, self.r2, self.norms, self.ws_norm, stream=stream)
-        L.dnnmg_q2_rhs(box, ns, self.coords, self.xcorr, self.b, ws=self.ws_q2, stream=stream)
+        else:
+            L.dnnmg_q2_rhs(box, ns, self.coords, self.xcorr, self.b, ws=self.ws_q2, stream=stream)
         L.dnnmg_q2_restrict(box, self.b, self.bc, stream=stream)
 
     def capture(self):

@@ -135,8 +135,8 @@ def test_q2_host_validation_without_gpu():
     bad = L.NS(1e-3, 0.0, 0.02, 0.1)
     rc = lib.dnnmg_q2_rhs(ctypes.byref(box), ctypes.byref(bad), None, None, None, None, None, 0, None)
     assert rc == -1 and b"dt" in lib.dnnmg_last_error()
-    # 108 floats per element in groups of 8, rounded up to 256 bytes; too small a workspace is rejected
-    assert L.q2_workspace_bytes(box) == (3 * 8 * 108 * 4 + 255) // 256 * 256
+    # 189 floats per element (4 + 3 equations) in groups of 8, rounded up to 256 bytes; too small a workspace is rejected
+    assert L.q2_workspace_bytes(box) == (3 * 8 * 189 * 4 + 255) // 256 * 256
     p = ctypes.c_void_p(16)
     rc = lib.dnnmg_q2_residual_b(ctypes.byref(box), ctypes.byref(ns), p, p, p, ctypes.c_void_p(32), p, 100, None)
     assert rc == -1 and b"workspace" in lib.dnnmg_last_error()

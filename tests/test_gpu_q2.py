@@ -347,3 +347,31 @@ def test_q2_three_chained_steps_match_oracle_chain(q2):
         say(f"  step {k}: b rel-L2 {e_b:.2e}, bc {e_bc:.2e}")
         assert e_b <= 1e-5 and e_bc <= 1e-5, k
         b = ref["b"]
+
+
+def test_q2_residual_rhs_fused_matches_separate_and_oracle(L, q2):
+    """The fused indicator residual + next right-hand side equals the two
+    separate entry points (and the oracle), also in place (bnext = b)."""
+    box, X, base, x = channel_case((5, 3, 2), 9)
+    say("q2 fused residual + rhs")
+    rng = np.random.default_rng(23)
+    x32 = f32(x)
+    b32 = f32(rng.standard_normal((4, box.n_fine)))
+    Xg, xg, bg = to_gpu(X.ravel()), to_gpu(x32.ravel()), to_gpu(b32.ravel())
+    nf4 = 4 * box.n_fine
+    r_sep, b_sep = (torch.zeros(nf4, dtype=torch.float32, device="cuda") for _ in range(2))
+    L.dnnmg_q2_residual_b(box, NS, Xg, xg, bg, r_sep)
+    L.dnnmg_q2_rhs(box, NS, Xg, xg[:3 * box.n_fine].contiguous(), b_sep)
+    r_f, bn_f = (torch.zeros(nf4, dtype=torch.float32, device="cuda") for _ in range(2))
+    L.dnnmg_q2_residual_rhs(box, NS, Xg, xg, bg, r_f, bn_f)
+    b_in = bg.clone()
+    r_i = torch.zeros(nf4, dtype=torch.float32, device="cuda")
+    L.dnnmg_q2_residual_rhs(box, NS, Xg, xg, b_in, r_i, b_in)  # in place
+    torch.cuda.synchronize()
+    assert torch.equal(r_f, r_sep)
+    assert torch.equal(r_i, r_f) and torch.equal(b_in, bn_f)
+    e = rel_l2(bn_f.cpu().numpy(), b_sep.cpu().numpy())
+    say(f"  Rhs fused vs separate rel-L2 {e:.1e}")
+    assert e <= 1e-6
+    ref = q2.rhs(box, NS, X, x32[:3].astype(np.float64))
+    assert rel_l2(bn_f.cpu().numpy().reshape(4, -1), ref) <= 1e-6
