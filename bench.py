@@ -66,7 +66,8 @@ NETWORK_SOURCES = ("mlp.hip", "mlp.hpp", "lowp.hpp", "common.hpp", "common.hip")
 # the sources each counted entry point is built from (a PMC summary holds
 # for the sources it was taken on)
 ENTRY_SOURCES = {"dnnmg_residual_b": RESIDUAL_SOURCES, "dnnmg_prolong_residual_b": RESIDUAL_SOURCES,
-                 "dnnmg_patch_gather_forward": NETWORK_SOURCES}
+                 "dnnmg_patch_gather_forward": NETWORK_SOURCES,
+                 "dnnmg_q2_residual_b": ("q2.hip", "common.hpp", "common.hip")}
 
 
 def src_hash(*names):
@@ -624,7 +625,9 @@ def run_q2_step(steps, warmup):
             "q2_residual": {"flop_per_element": flops.q2_residual_flops_per_element(),
                             "tflops": res_flop / (kms["q2_residual_b"] * 1e-3) / 1e12,
                             "frac_of_fp32_vector_peak": res_flop / (kms["q2_residual_b"] * 1e-3) / 1e12
-                            / FP32_VALU_PEAK_TFLOPS},
+                            / FP32_VALU_PEAK_TFLOPS,
+                            "bytes_algorithmic_per_launch": flops.Q2_RESIDUAL_BYTES_PER_NODE * st.nf,
+                            "traffic": traffic_from_profile("dnnmg_q2_residual_b", w.name)},
             "q2_rhs_tflops": rhs_flop / (kms["q2_rhs"] * 1e-3) / 1e12,
             "eta_last": float(np.sqrt(n[1] / n[0])) if n[0] > 0 else None,
             "accuracy_rel_l2": acc}
@@ -645,8 +648,12 @@ def q2_accuracy():
     params = syn.mlp_params(165, 512, 81, seed=0)
     b = oq2.rhs(w.box, w.ns, X, np.asarray(inp.vprev, np.float32).astype(np.float64))
     p64 = [np.asarray(p, np.float32).astype(np.float64) for p in params]
+    t0 = time.perf_counter()
     ref = oq2.correction_step(w.box, w.ns, X, p64, inp.xc, b, indicator=True, threads=CPU_WORKERS)
-    out = {"workload": "channel_64x16x16_q2_curved", "elements": w.box.n_patches}
+    t_oracle = time.perf_counter() - t0
+    out = {"workload": "channel_64x16x16_q2_curved", "elements": w.box.n_patches,
+           "oracle_step_s": t_oracle, "oracle_threads": CPU_WORKERS,
+           "oracle_patches_per_s": w.box.n_patches / t_oracle}
     for dt in ("fp8", "bf16"):
         st = stepper.Q2CorrectionStep(w.box, w.ns, X, params, dtype=dt, indicator=True)
         g = st.run_numpy(inp.xc, inp.vprev)
@@ -879,6 +886,15 @@ def pmc_probe():
     for _ in range(3):
         L.dnnmg_patch_gather_forward(st.box, st.net, st.xt, st.r, st.Y, st.shift, st.inv_scale)
     torch.cuda.synchronize()
+    del st
+    # the Q2 residual (element kernel + per-node sum) on the curved channel mesh
+    _, q = q2_step()
+    q.step()
+    torch.cuda.synchronize()
+    for _ in range(3):
+        L.dnnmg_q2_residual_b(q.box, q.ns, q.coords, q.xt, q.b, q.r, ws=q.ws_q2)
+    torch.cuda.synchronize()
+    del q
     n = PMC_COPY_MIB * 2**20 // 4
     a = torch.ones(n, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)

@@ -166,3 +166,9 @@ def q2_sum_nodes_bytes_per_node() -> float:
     (one element per 8 nodes of the lattice), b read and r written (4
     fields each)."""
     return 108 * 4 / 8 + 4 * 4 + 4 * 4
+
+
+# r = b - A(x) on the Q2 mesh: x (4 FP32 fields) and b read, r written, the
+# FP64 node positions read, once per node (the element vectors' round trip
+# through the workspace is not counted)
+Q2_RESIDUAL_BYTES_PER_NODE = 4 * 4 + 4 * 4 + 4 * 4 + 3 * 8
