@@ -66,6 +66,7 @@ NETWORK_SOURCES = ("mlp.hip", "mlp.hpp", "lowp.hpp", "common.hpp", "common.hip")
 # the sources each counted entry point is built from (a PMC summary holds
 # for the sources it was taken on)
 ENTRY_SOURCES = {"dnnmg_residual_b": RESIDUAL_SOURCES, "dnnmg_prolong_residual_b": RESIDUAL_SOURCES,
+                 "dnnmg_residual_rhs_b": RESIDUAL_SOURCES,
                  "dnnmg_patch_gather_forward": NETWORK_SOURCES,
                  "dnnmg_q2_residual_b": ("q2.hip", "common.hpp", "common.hip")}
 
@@ -366,12 +367,15 @@ def step_kernel_times(st, reps=20):
         "gather_forward": lambda: L.dnnmg_patch_gather_forward(box, st.net, st.xt, st.r, st.Y, st.shift,
                                                               st.inv_scale),
         "scatter": lambda: L.dnnmg_scatter_avg(box, st.Y, st.xcorr, vbase=st.xt),
-        "residual_b_indicator": lambda: L.dnnmg_residual_b(box, ns, st.xcorr, st.b, st.r2, st.ws_res),
+        # the indicator's residual with the next right-hand side (b in place:
+        # repeated calls leave the same b and r)
+        "residual_rhs_b_indicator": lambda: L.dnnmg_residual_rhs_b(box, ns, st.xcorr, st.b, st.r2, st.ws_res,
+                                                                   b_save=st.b_prev),
         "norm2_pair": lambda: L.dnnmg_norm2_pair_f64(st.r, st.r2, st.norms, st.ws_norm),
-        "fallback_skipped": lambda: L.dnnmg_fallback_b(box, ns, st.xt, st.b, st.norms, st.xcorr, st.ws_fb,
+        "fallback_skipped": lambda: L.dnnmg_fallback_b(box, ns, st.xt, st.b_prev, st.norms, st.xcorr, st.ws_fb,
                                                        theta=st.theta, sweeps=st.fallback_sweeps,
                                                        flag_out=st.fell_back),
-        "rhs": lambda: L.dnnmg_rhs(box, ns, st.xcorr, st.b),
+        "rhs_if_skipped": lambda: L.dnnmg_rhs_if(box, ns, st.xcorr, st.b, st.fell_back),
         "restrict": lambda: L.dnnmg_restrict(box, st.b, st.bc),
     }
     return {name: time_kernel(fn, reps) for name, fn in k.items()}
@@ -393,13 +397,12 @@ def roofline_of(kernel_ms, st, w):
                 "peak": peak, "unit": "TFLOP/s", "frac": flop / (t * 1e-3) / 1e12 / peak,
                 "traffic": traffic_from_profile("dnnmg_patch_gather_forward", w.name),
                 "avg_launch_ms": t, "flop_per_launch": flop}
-    per_node = {"residual_b_indicator": flops.ALG_RESIDUAL_B_GENERAL_PER_NODE,
-                "prolong_residual_b": flops.ALG_PROLONG_RESIDUAL_B_PER_NODE,
-                "rhs": flops.ALG_RHS_PER_NODE}
+    per_node = {"residual_rhs_b_indicator": flops.ALG_RESIDUAL_RHS_B_GENERAL_PER_NODE,
+                "prolong_residual_b": flops.ALG_PROLONG_RESIDUAL_B_PER_NODE}
     if name in per_node:
         flop = per_node[name] * nf
-        entry = {"residual_b_indicator": "dnnmg_residual_b", "prolong_residual_b": "dnnmg_prolong_residual_b",
-                 "rhs": "dnnmg_rhs"}[name]
+        entry = {"residual_rhs_b_indicator": "dnnmg_residual_rhs_b",
+                 "prolong_residual_b": "dnnmg_prolong_residual_b"}[name]
         ach = flop / (t * 1e-3) / 1e12
         return {"kernel": entry, "bound": "alu", "achieved": ach, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": ach / FP32_VALU_PEAK_TFLOPS, "traffic": traffic_from_profile(entry, w.name),
@@ -588,9 +591,10 @@ def q2_step(dtype="fp8", hidden=512, seed=0):
     return w, st
 
 
-def run_q2_step(steps, warmup):
+def run_q2_step(steps, warmup, with_oracle=True):
     """Graph replays of the Q2 correction step (each replay's right-hand side
-    feeds the next one's residual) and each launch timed alone."""
+    feeds the next one's residual) and each launch timed alone; with_oracle:
+    also the accuracy of one step against the FP64 Q2 oracle."""
     from paper_2307_14837_amd import _lib as L
     from paper_2307_14837_amd import flops
 
@@ -612,7 +616,7 @@ def run_q2_step(steps, warmup):
     st.b2 = st.b.clone()  # the fused form's second output while timed alone
     kms = {name: time_kernel(fn, 10) for name, fn in k.items()}
     ne = st.np
-    acc = q2_accuracy() if not args.no_cpu else None
+    acc = q2_accuracy() if with_oracle else None
     res_flop = flops.q2_residual_flops_per_element() * ne
     rhs_flop = flops.q2_rhs_flops_per_element() * ne
     n = st.norms.cpu().numpy()
@@ -878,9 +882,12 @@ def pmc_probe():
     st, _ = build_step(w, "fp8")
     st.step()
     r2 = torch.empty_like(st.r)
+    b_io, b_save = st.b.clone(), torch.empty_like(st.b)
     torch.cuda.synchronize()
     for _ in range(3):
         L.dnnmg_residual_b(st.box, st.ns, st.xcorr, st.b, r2, st.ws_res)
+    for _ in range(3):
+        L.dnnmg_residual_rhs_b(st.box, st.ns, st.xcorr, b_io, r2, st.ws_res, b_save=b_save)
     for _ in range(3):
         L.dnnmg_prolong_residual_b(st.box, st.ns, st.xc, st.b, st.xt, st.r)
     for _ in range(3):
@@ -1019,7 +1026,7 @@ def main():
             run_coarse_step(),
             run_time_loop(w, params, shift, inv),
             run_config4(),
-            run_q2_step(sv, wv),
+            run_q2_step(sv, wv, with_oracle=not args.no_cpu),
         ]
         out["variants"] = variants
         print("[bench] kernels on the large channel", file=sys.stderr, flush=True)

@@ -140,6 +140,19 @@ int dnnmg_residual(const dnnmg_box *box, const dnnmg_ns *ns, const float *x, con
 int dnnmg_residual_b(const dnnmg_box *box, const dnnmg_ns *ns, const float *x, const float *b, float *r, void *ws,
                      size_t ws_bytes, void *stream);
 
+/* The indicator's residual and the next right-hand side in one pass
+ * (Algorithm 1: the residual of the corrected iterate, then Rhs of its
+ * velocity, both at x): r = b - A(x) as dnnmg_residual_b computes it, and b
+ * is replaced by dnnmg_rhs(x's velocity, NULL) (up to FP32 rounding order)
+ * in place.  Each node's b is read before it is overwritten.  b_save, if
+ * not NULL, receives b as it was on entry (the right-hand side a fallback
+ * of this step still needs).
+ *   x FP32 [4][n_fine]; b FP32 [4][n_fine] in/out; r FP32 [4][n_fine]
+ *   output; b_save FP32 [4][n_fine] output or NULL; x, b, r and b_save must
+ *   not alias (DNNMG_ERR_ARG); ws as for dnnmg_residual. */
+int dnnmg_residual_rhs_b(const dnnmg_box *box, const dnnmg_ns *ns, const float *x, float *b, float *r, float *b_save,
+                         void *ws, size_t ws_bytes, void *stream);
+
 /* dnnmg_residual_b for callers that cannot allocate (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * kernels and the same results, bit for bit, with the LPS workspace taken
@@ -192,6 +205,14 @@ int dnnmg_prolong_residual_b(const dnnmg_box *box, const dnnmg_ns *ns, const dou
  *   b FP32 [4][n_fine]. */
 int dnnmg_rhs(const dnnmg_box *box, const dnnmg_ns *ns, const float *v, const float *fmid,
               float *b, void *stream);
+
+/* dnnmg_rhs predicated on a device flag (Algorithm 1: the right-hand side of
+ * the velocity the fallback produced): computes b = Rhs(v, fmid) when *flag
+ * != 0 at run time and leaves b untouched otherwise, so a graph holds it
+ * unconditionally.  flag: device int (e.g. dnnmg_fallback's flag_out),
+ * required; other arguments as for dnnmg_rhs. */
+int dnnmg_rhs_if(const dnnmg_box *box, const dnnmg_ns *ns, const float *v, const float *fmid, float *b,
+                 const int *flag, void *stream);
 
 
 /* Restriction of Algorithm 1: bc = P^T bf, the transpose of dnnmg_prolong,

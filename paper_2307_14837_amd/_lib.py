@@ -109,6 +109,8 @@ _sig("dnnmg_residual_b_noalloc", [_P(Box), _P(NS), c_vp, c_vp, c_vp, c_vp])
 _sig("dnnmg_fallback_b", [_P(Box), _P(NS), c_vp, c_vp, c_vp, ctypes.c_double, ctypes.c_int, c_f, c_vp, c_vp, c_vp,
                           c_sz, c_vp])
 _sig("dnnmg_rhs", [_P(Box), _P(NS), c_vp, c_vp, c_vp, c_vp])
+_sig("dnnmg_residual_rhs_b", [_P(Box), _P(NS), c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp])
+_sig("dnnmg_rhs_if", [_P(Box), _P(NS), c_vp, c_vp, c_vp, c_vp, c_vp])
 _sig("dnnmg_prolong_residual", [_P(Box), _P(NS), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp])
 _sig("dnnmg_prolong_residual_b", [_P(Box), _P(NS), c_vp, c_vp, c_vp, c_vp, c_vp])
 _sig("dnnmg_restrict", [_P(Box), ctypes.c_int, c_vp, c_vp, c_vp])
@@ -186,7 +188,7 @@ EXPORTS = [
     "dnnmg_residual_workspace", "dnnmg_residual", "dnnmg_rhs", "dnnmg_restrict",
     "dnnmg_patch_gather", "dnnmg_mlp_packed_bytes", "dnnmg_mlp_pack", "dnnmg_patch_forward",
     "dnnmg_patch_forward_tiles", "dnnmg_prolong_residual", "dnnmg_prolong_residual_b",
-    "dnnmg_residual_b", "dnnmg_residual_b_noalloc", "dnnmg_fallback_b",
+    "dnnmg_residual_b", "dnnmg_residual_b_noalloc", "dnnmg_fallback_b", "dnnmg_residual_rhs_b", "dnnmg_rhs_if",
     "dnnmg_patch_saved_bytes", "dnnmg_scatter_avg", "dnnmg_scatter_avg_form", "dnnmg_norm2_workspace", "dnnmg_norm2_f64",
     "dnnmg_mse_grad", "dnnmg_patch_backward_workspace", "dnnmg_patch_backward", "dnnmg_adamw_step",
     "dnnmg_vanka_workspace", "dnnmg_vanka_sweeps", "dnnmg_fallback_workspace", "dnnmg_fallback",
@@ -276,6 +278,26 @@ def dnnmg_residual_b(box, ns, x, b, r, ws, stream=None):
     _check(_lib.dnnmg_residual_b(ctypes.byref(bx), ctypes.byref(NS.of(ns)), _ptr(x, torch.float32, 4 * nf, "x"),
                                  _ptr(b, torch.float32, 4 * nf, "b"), _ptr(r, torch.float32, 4 * nf, "r"),
                                  _ptr(ws, None, None, "ws"), ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def dnnmg_residual_rhs_b(box, ns, x, b, r, ws, b_save=None, stream=None):
+    """r = b - A(x) and b <- Rhs(x's velocity) in one pass; b_save (optional)
+    receives b as it was."""
+    bx = Box.of(box)
+    nf, _, _ = box_sizes(bx)
+    _check(_lib.dnnmg_residual_rhs_b(ctypes.byref(bx), ctypes.byref(NS.of(ns)),
+                                     _ptr(x, torch.float32, 4 * nf, "x"), _ptr(b, torch.float32, 4 * nf, "b"),
+                                     _ptr(r, torch.float32, 4 * nf, "r"), _ptr(b_save, torch.float32, 4 * nf, "b_save"),
+                                     _ptr(ws, None, None, "ws"), ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def dnnmg_rhs_if(box, ns, v, b_out, flag, fmid=None, stream=None):
+    """dnnmg_rhs when the device int *flag is nonzero at run time."""
+    b = Box.of(box)
+    nf, _, _ = box_sizes(b)
+    _check(_lib.dnnmg_rhs_if(ctypes.byref(b), ctypes.byref(NS.of(ns)), _ptr(v, torch.float32, 3 * nf, "v"),
+                             _ptr(fmid, torch.float32, 3 * nf, "fmid"), _ptr(b_out, torch.float32, 4 * nf, "b"),
+                             _ptr(flag, torch.int32, 1, "flag"), _stream(stream)))
 
 
 NOALLOC_SCRATCH_BYTES = 33 << 20  # DNNMG_NOALLOC_SCRATCH_BYTES of include/dnnmg.h

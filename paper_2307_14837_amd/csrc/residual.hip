@@ -368,19 +368,28 @@ struct ResTile {
 // in a fixed order (and, for the LPS corner terms, thread 8 P + j the 8
 // cells of owned patch P at corner j), so the sums need no atomics and the
 // result does not depend on scheduling.
-template <int MODE, bool DELTA_MERGED = false>
+//
+// RHS_OUT (general residual against b only): the tile also evaluates the
+// next step's right-hand side Rhs(v) at the same iterate (no forcing) and
+// replaces b by it at the owned nodes: b is then read from and written to
+// b_io (vp unused), each owned node's b is loaded by its owner before any
+// store, and b_save (optional) receives the b read.
+template <int MODE, bool DELTA_MERGED = false, bool RHS_OUT = false>
 __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P, int bx, int by, int bz,
                                               const float *__restrict__ x, const float *__restrict__ vp,
                                               const float *__restrict__ fmid, float *__restrict__ out,
                                               float *__restrict__ aux, int *__restrict__ tflag,
                                               const double *__restrict__ xc = nullptr,
-                                              float *__restrict__ xt_out = nullptr) {
+                                              float *__restrict__ xt_out = nullptr, float *b_io = nullptr,
+                                              float *__restrict__ b_save = nullptr) {
+    static_assert(!RHS_OUT || MODE == MODE_RESB, "the right-hand side output is built for r = b - A(x)");
     using T = ResTile<MODE>;
     __shared__ float sX[T::NF_STAGE > 0 ? T::NF_STAGE * T::SN : 1];
     __shared__ float sV[T::NF_V > 0 ? T::NF_V * T::VN : 1];
     __shared__ float sF[mode_against_b(MODE) ? 1 : 3 * T::VN]; // forcing, when given
     __shared__ float sCell[8 * T::NCELL]; // [vertex j][cell]
     __shared__ float sCor[mode_general(MODE) ? 8 * T::NCELL : 1];
+    __shared__ float sRhs[RHS_OUT ? 8 * T::NCELL : 1]; // [vertex j][cell], Rhs integrals
     __shared__ float sC[mode_prolongs(MODE) ? 4 * T::CN : 1]; // coarse iterate, rounded to FP32
 
     const int x0 = bx * T::TX, y0 = by * T::TY, z0 = bz * T::TZ;
@@ -402,7 +411,7 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
         if (tid < T::NOWN && gi < m.nf[0] && gj < m.nf[1] && gk < m.nf[2]) {
             const int64_t g = gi + (int64_t)m.nf[0] * (gj + (int64_t)m.nf[1] * gk);
 #pragma unroll
-            for (int f = 0; f < 4; ++f) bown[f] = vp[f * nfn + g];
+            for (int f = 0; f < 4; ++f) bown[f] = RHS_OUT ? b_io[f * nfn + g] : vp[f * nfn + g];
         }
     }
     // all loads of a thread are issued before its LDS stores, so the staging
@@ -513,6 +522,7 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
     for (int s = tid; s < 8 * T::NCELL; s += T::NT) {
         sCell[s] = 0.0f;
         if constexpr (mode_general(MODE)) sCor[s] = 0.0f;
+        if constexpr (RHS_OUT) sRhs[s] = 0.0f;
     }
     __syncthreads();
 
@@ -562,9 +572,23 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
     const int nb = (lx + 1) + T::EX * ((ly + 1) + T::EY * (lz + 1));
     auto ncell = [](int j) { return -((j & 1) + T::EX * (((j >> 1) & 1) + T::EY * (j >> 2))); };
     float res[T::NACC];
+    // RHS_OUT: the owned node's Rhs of the three momentum equations; a
+    // Rhs integral staged in sRhs is summed in the barrier phase of the
+    // next reduction that is given its destination rs
+    float rhsv[3] = {0.0f, 0.0f, 0.0f};
+    auto take_rhs = [&](float *rs) {
+        if constexpr (RHS_OUT) {
+            if (rs && owner) {
+                float t = 0.0f;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) t += sRhs[j * T::NCELL + nb + ncell(j)];
+                *rs = t;
+            }
+        }
+    };
 
     // Cell integrals of equation a -> LDS; the owners sum them.
-    auto reduce = [&](const float c[8], float wq) -> float {
+    auto reduce = [&](const float c[8], float wq, float *rs = nullptr) -> float {
         if (live)
 #pragma unroll
             for (int j = 0; j < 8; ++j) sCell[j * T::NCELL + ce] = c[j] * wq;
@@ -573,6 +597,7 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
         if (owner)
 #pragma unroll
             for (int j = 0; j < 8; ++j) s += sCell[j * T::NCELL + nb + ncell(j)];
+        take_rhs(rs);
         __syncthreads();
         return s;
     };
@@ -596,7 +621,8 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
     // equation a's cell integrals (own vertices c, patch corners cr) -> LDS;
     // the owners sum their 8 cells, the patch-corner threads the 8 cells of
     // their patch, after one barrier
-    auto reduce_c = [&](const float c[8], const float cr[8], float wq, float &corner_out) -> float {
+    auto reduce_c = [&](const float c[8], const float cr[8], float wq, float &corner_out,
+                        float *rs = nullptr) -> float {
         if (live)
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
@@ -615,6 +641,7 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
                 t += sCor[pj * T::NCELL + pcb + (o & 1) + T::EX * (((o >> 1) & 1) + T::EY * (o >> 2))];
             corner_out = t;
         }
+        take_rhs(rs);
         __syncthreads();
         return s;
     };
@@ -794,6 +821,18 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
                         G2[q] = -P.half_nu * g2[q];
                     }
                 }
+                if constexpr (RHS_OUT) {
+                    // Rhs(v) of this equation at the same velocity:
+                    // (1/k) v_a - 1/2 v . grad v_a tested with phi and
+                    // -nu/2 grad v_a (G here) with grad phi
+                    float Fr[8], accr[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        Fr[q] = P.inv_dt * xv[a][q] - 0.5f * (xv[0][q] * g0[q] + xv[1][q] * g1[q] + xv[2][q] * g2[q]);
+                    integrate<true, true, true>(Fr, G0, G1, G2, ih0, ih1, ih2, accr);
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) sRhs[j * T::NCELL + ce] = accr[j] * P.wq;
+                }
                 const float *ga = a == 0 ? g0 : (a == 1 ? g1 : g2);
                 float *Ga = a == 0 ? G0 : (a == 1 ? G1 : G2);
 #pragma unroll
@@ -829,8 +868,9 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
                 }
                 integrate<true, true, true>(F, G0, G1, G2, ih0, ih1, ih2, acc);
             }
-            if (DELTA_MERGED && any_v) res[a] = reduce_c(acc, cor, P.wq, corner[a]);
-            else res[a] = reduce(acc, P.wq);
+            float *rs = RHS_OUT ? &rhsv[a] : nullptr;
+            if (DELTA_MERGED && any_v) res[a] = reduce_c(acc, cor, P.wq, corner[a], rs);
+            else res[a] = reduce(acc, P.wq, rs);
         }
         // continuity: -(div v, xi)
         {
@@ -933,6 +973,14 @@ __device__ __forceinline__ void residual_tile(const Mesh &m, const ResParams &P,
 #pragma unroll
                 for (int f = 0; f < 3; ++f) out[f * nfn + g] = dir ? 0.0f : bown[f] + res[f];
                 out[3 * nfn + g] = bown[3] + res[3];
+                if constexpr (RHS_OUT) {
+                    if (b_save)
+#pragma unroll
+                        for (int f = 0; f < 4; ++f) b_save[f * nfn + g] = bown[f];
+#pragma unroll
+                    for (int f = 0; f < 3; ++f) b_io[f * nfn + g] = dir ? 0.0f : rhsv[f];
+                    b_io[3 * nfn + g] = 0.0f;
+                }
             } else {
 #pragma unroll
                 for (int f = 0; f < 3; ++f) out[f * nfn + g] = dir ? 0.0f : res[f];
@@ -1006,16 +1054,13 @@ __device__ __forceinline__ void tile_of(int64_t t64, const int G[3], const int F
     c[2] = (int)(q / f1);
 }
 
-// STRIDED = false: one tile per block (the grid covers the tiles);
-// STRIDED = true: blocks walk the tiles with stride gridDim.x, for launches
-// that a device flag may skip on a small grid.
-template <int MODE, bool STRIDED = false>
-__global__ void __launch_bounds__(ResTile<MODE>::NT, ResTile<MODE>::WAVES_PER_SIMD)
-    k_residual(Mesh m, ResParams P, const float *__restrict__ x, const float *__restrict__ vp,
-               const float *__restrict__ fmid, float *__restrict__ out, float *__restrict__ aux,
-               int *__restrict__ tflag, const int *__restrict__ flag, const double *__restrict__ xc,
-               float *__restrict__ xt_out) {
-    if (flag && *flag == 0) return; // predicated launch (fallback path not taken)
+// The tiles of a block, in the order of tile_of: fn(c, tl) with c the tile
+// coordinates and tl its index in the tile grid.  STRIDED = false: one tile
+// per block (the grid covers the tiles); STRIDED = true: blocks walk the
+// tiles with stride gridDim.x, for launches that a device flag may skip on a
+// small grid.
+template <int MODE, bool STRIDED, class Fn>
+__device__ __forceinline__ void walk_tiles(const Mesh &m, Fn fn) {
     using T = ResTile<MODE>;
     const int G[3] = {(m.nf[0] + T::TX - 1) / T::TX, (m.nf[1] + T::TY - 1) / T::TY, (m.nf[2] + T::TZ - 1) / T::TZ};
     const int F[3] = {m.nf[0] / T::TX, m.nf[1] / T::TY, m.nf[2] / T::TZ};
@@ -1032,11 +1077,36 @@ __global__ void __launch_bounds__(ResTile<MODE>::NT, ResTile<MODE>::WAVES_PER_SI
         }
         int c[3];
         tile_of(t, G, F, c);
-        const int tl = c[0] + G[0] * (c[1] + G[1] * c[2]);
-        residual_tile<MODE, MODE == MODE_RESB && !STRIDED>(m, P, c[0], c[1], c[2], x, vp, fmid, out, aux,
-                                                            mode_general(MODE) ? tflag + tl : nullptr, xc, xt_out);
+        fn(c, c[0] + G[0] * (c[1] + G[1] * c[2]));
         if constexpr (STRIDED) __syncthreads(); // the tile's LDS reads are done before the next stages
     }
+}
+
+// The strided (predicated, fallback) forms run at three waves per SIMD: the
+// right-hand side's would spill at six, and its skipped launches would then
+// set up scratch memory for nothing.
+template <int MODE, bool STRIDED = false>
+__global__ void __launch_bounds__(ResTile<MODE>::NT, STRIDED ? 3 : ResTile<MODE>::WAVES_PER_SIMD)
+    k_residual(Mesh m, ResParams P, const float *__restrict__ x, const float *__restrict__ vp,
+               const float *__restrict__ fmid, float *__restrict__ out, float *__restrict__ aux,
+               int *__restrict__ tflag, const int *__restrict__ flag, const double *__restrict__ xc,
+               float *__restrict__ xt_out) {
+    if (flag && *flag == 0) return; // predicated launch (fallback path not taken)
+    walk_tiles<MODE, STRIDED>(m, [&](const int c[3], int tl) {
+        residual_tile<MODE, MODE == MODE_RESB && !STRIDED>(m, P, c[0], c[1], c[2], x, vp, fmid, out, aux,
+                                                            mode_general(MODE) ? tflag + tl : nullptr, xc, xt_out);
+    });
+}
+
+// r = b - A(x) and, in place of b, the next right-hand side Rhs(v) at the
+// same iterate (b_save, if not null, receives b as it was read).
+__global__ void __launch_bounds__(ResTile<MODE_RESB>::NT, ResTile<MODE_RESB>::WAVES_PER_SIMD)
+    k_residual_rhs_b(Mesh m, ResParams P, const float *__restrict__ x, float *__restrict__ out,
+                     float *__restrict__ aux, int *__restrict__ tflag, float *b_io, float *__restrict__ b_save) {
+    walk_tiles<MODE_RESB, false>(m, [&](const int c[3], int tl) {
+        residual_tile<MODE_RESB, true, true>(m, P, c[0], c[1], c[2], x, nullptr, nullptr, out, aux, tflag + tl,
+                                             nullptr, nullptr, b_io, b_save);
+    });
 }
 
 // Launch size of a tile grid in the order of tile_of.
@@ -1312,6 +1382,30 @@ extern "C" int dnnmg_residual_b(const dnnmg_box *box, const dnnmg_ns *ns, const 
     return residual_launch_b(m, ns, x, b, r, (float *)ws, nullptr, (hipStream_t)stream);
 }
 
+extern "C" int dnnmg_residual_rhs_b(const dnnmg_box *box, const dnnmg_ns *ns, const float *x, float *b, float *r,
+                                    float *b_save, void *ws, size_t ws_bytes, void *stream) {
+    Mesh m;
+    int rc = make_mesh(box, &m);
+    if (rc) return rc;
+    if ((rc = check_ns(ns))) return rc;
+    if (!x || !b || !r || !ws) return fail(DNNMG_ERR_ARG, "dnnmg_residual_rhs_b: NULL pointer");
+    if (b == r || (const float *)b == x || (const float *)r == x)
+        return fail(DNNMG_ERR_ARG, "dnnmg_residual_rhs_b: x, b and r must not alias");
+    if (b_save && (b_save == b || b_save == r || (const float *)b_save == x))
+        return fail(DNNMG_ERR_ARG, "dnnmg_residual_rhs_b: b_save must not alias x, b or r");
+    if (!aligned16(ws)) return fail(DNNMG_ERR_ARG, "dnnmg_residual_rhs_b: workspace not 16-byte aligned");
+    if (ws_bytes < lps_ws_bytes(m))
+        return fail(DNNMG_ERR_SHAPE, "dnnmg_residual_rhs_b: workspace %zu < %zu bytes", ws_bytes, lps_ws_bytes(m));
+    hipStream_t s = (hipStream_t)stream;
+    ResParams P = make_params(m, ns);
+    dim3 g = res_grid<MODE_RES>(m);
+    float *aux = (float *)ws;
+    int *tflag = (int *)((char *)aux + up256(sizeof(float) * 32 * m.n_patches));
+    k_residual_rhs_b<<<tile_blocks<MODE_RESB>(m), ResTile<MODE_RESB>::NT, 0, s>>>(m, P, x, r, aux, tflag, b, b_save);
+    k_lps_corners<<<blocks_for(m.n_coarse, 256), 256, 0, s>>>(m, aux, tflag, g.x, g.y, g.z, r, nullptr);
+    return hip_check(hipGetLastError(), "dnnmg_residual_rhs_b launch");
+}
+
 // ------------------------------------------- allocation-free residual_b --
 // Scratch of dnnmg_residual_b_noalloc: the LPS corner sums and tile flags of
 // one box, in a device array of fixed size that every GPU the library runs
@@ -1379,6 +1473,20 @@ extern "C" int dnnmg_rhs(const dnnmg_box *box, const dnnmg_ns *ns, const float *
     k_residual<MODE_RHS><<<tile_blocks<MODE_RHS>(m), ResTile<MODE_RHS>::NT, 0, (hipStream_t)stream>>>(
         m, P, v, nullptr, fmid, b, nullptr, nullptr, nullptr, nullptr, nullptr);
     return hip_check(hipGetLastError(), "dnnmg_rhs launch");
+}
+
+extern "C" int dnnmg_rhs_if(const dnnmg_box *box, const dnnmg_ns *ns, const float *v, const float *fmid, float *b,
+                            const int *flag, void *stream) {
+    Mesh m;
+    int rc = make_mesh(box, &m);
+    if (rc) return rc;
+    if ((rc = check_ns(ns))) return rc;
+    if (!v || !b || !flag) return fail(DNNMG_ERR_ARG, "dnnmg_rhs_if: NULL pointer");
+    ResParams P = make_params(m, ns);
+    k_residual<MODE_RHS, true><<<predicated_grid(tile_blocks<MODE_RHS>(m), flag, 2), ResTile<MODE_RHS>::NT, 0,
+                                 (hipStream_t)stream>>>(m, P, v, nullptr, fmid, b, nullptr, nullptr, flag, nullptr,
+                                                        nullptr);
+    return hip_check(hipGetLastError(), "dnnmg_rhs_if launch");
 }
 
 extern "C" int dnnmg_prolong_residual_b(const dnnmg_box *box, const dnnmg_ns *ns, const double *xc,

@@ -90,6 +90,8 @@ BYTES_PER_FINE_NODE = {
     "prolong": 4 * 4 + 4 * 8 / 8,        # write 4 FP32 fields; read 4 FP64 coarse fields (1/8 node)
     "residual": 4 * 4 + 3 * 4 + 4 * 4,   # read x (4), vp (3); write r (4)
     "rhs": 3 * 4 + 4 * 4,                # read v (3); write b (4)
+    # read x (4), b (4); write r (4), the next b (4) and the saved b (4)
+    "residual_rhs_b": 4 * 4 + 4 * 4 + 3 * 4 * 4,
     "scatter": 81 * 4 / 8 + 4 * 4 + 4 * 4,  # read Y (81 per patch), x~ (4); write x_corr (4)
     "restrict": 4 * 4 + 4 * 8 / 8,       # read b (4); write 4 FP64 coarse fields
 }
@@ -129,6 +131,8 @@ def _share_residual_b_general() -> float:
 ALG_PROLONG_RESIDUAL_B_PER_NODE = round(
     (ALG_PROLONG_PER_NODE + ALG_RESIDUAL_AT_PROLONGATION_PER_NODE) * _share_prolong_residual_b())
 ALG_RESIDUAL_B_GENERAL_PER_NODE = round(ALG_RESIDUAL_GENERAL_PER_NODE * _share_residual_b_general())
+# the indicator's residual and the next step's right-hand side at one iterate
+ALG_RESIDUAL_RHS_B_GENERAL_PER_NODE = ALG_RESIDUAL_B_GENERAL_PER_NODE + ALG_RHS_PER_NODE
 
 
 # ---- Q2/Q2 elements on curved hexahedra (27 Gauss points per element) -----

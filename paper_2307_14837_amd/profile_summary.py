@@ -34,6 +34,7 @@ import json
 from collections import defaultdict
 
 ENTRY_KERNELS = {"dnnmg_residual_b": ("k_residual<4, false>", "k_lps_corners"),
+                 "dnnmg_residual_rhs_b": ("k_residual_rhs_b", "k_lps_corners"),
                  "dnnmg_prolong_residual_b": ("k_residual<3, false>",),
                  "dnnmg_patch_gather_forward": ("k_mlp_fwd<2, 512",),
                  "dnnmg_q2_residual_b": ("k_q2_element<0>", "k_q2_sum_nodes<0>")}

@@ -83,6 +83,9 @@ class CorrectionStep:
             self.ws_norm = torch.zeros(2 * L.norm2_workspace_bytes(), dtype=torch.uint8, device=self.dev)
             self.ws_fb = torch.zeros(L.fallback_workspace_bytes(self.fbox), dtype=torch.uint8, device=self.dev)
             self.fell_back = torch.zeros(1, dtype=torch.int32, device=self.dev)
+            # the step's right-hand side, kept for the fallback while b takes
+            # the next one (carried form)
+            self.b_prev = torch.zeros(4 * self.nf, **f32) if self.carry_rhs else None
         self.shift = None if shift is None else torch.as_tensor(np.asarray(shift, np.float32)).to(self.dev)
         self.inv_scale = None if inv_scale is None else torch.as_tensor(np.asarray(inv_scale, np.float32)).to(self.dev)
         self.set_params(params)
@@ -131,24 +134,33 @@ class CorrectionStep:
             L.dnnmg_patch_forward(self.net, self.np, self.X, LDX, self.Y, stream=stream)
         # corrected iterate (v~ + d, p~)
         L.dnnmg_scatter_avg(box, self.Y, self.xcorr, vbase=self.xt, stream=stream)
-        if self.indicator:
-            # eta = ||r(x_corr)|| / ||r(x~)||; above theta the plain fine
-            # correction replaces the network's (decided on the device)
-            if self.carry_rhs:
-                L.dnnmg_residual_b(box, ns, self.xcorr, self.b, self.r2, self.ws_res, stream=stream)
-            else:
-                L.dnnmg_residual(box, ns, self.xcorr, self.vprev, self.r2, self.ws_res, stream=stream)
-            L.dnnmg_norm2_pair_f64(self.r, self.r2, self.norms, self.ws_norm, stream=stream)
-            if self.carry_rhs:
-                L.dnnmg_fallback_b(box, ns, self.xt, self.b, self.norms, self.xcorr, self.ws_fb,
-                                   theta=self.theta, sweeps=self.fallback_sweeps, flag_out=self.fell_back,
-                                   stream=stream)
-            else:
-                L.dnnmg_fallback(box, ns, self.xt, self.vprev, self.norms, self.xcorr, self.ws_fb,
-                                 theta=self.theta, sweeps=self.fallback_sweeps, flag_out=self.fell_back,
-                                 stream=stream)
-        L.dnnmg_rhs(box, ns, self.xcorr, self.b, stream=stream)
+        self._indicator_rhs(box, stream)
         L.dnnmg_restrict(box, self.b, self.bc, stream=stream)
+
+    def _indicator_rhs(self, fb, stream):
+        """[Indicator and fallback,] then b = Rhs(v_corr) on the fine box fb.
+        eta = ||r(x_corr)|| / ||r(x~)||; above theta the plain fine correction
+        replaces the network's (decided on the device).  Carried form: the
+        indicator's residual and the next Rhs are one pass (b replaced in
+        place, its old value kept in b_prev for the fallback), and the Rhs is
+        taken again only where the fallback changed x_corr."""
+        ns = self.ns
+        if not self.indicator:
+            L.dnnmg_rhs(fb, ns, self.xcorr, self.b, stream=stream)
+            return
+        if self.carry_rhs:
+            L.dnnmg_residual_rhs_b(fb, ns, self.xcorr, self.b, self.r2, self.ws_res, b_save=self.b_prev,
+                                   stream=stream)
+            L.dnnmg_norm2_pair_f64(self.r, self.r2, self.norms, self.ws_norm, stream=stream)
+            L.dnnmg_fallback_b(fb, ns, self.xt, self.b_prev, self.norms, self.xcorr, self.ws_fb, theta=self.theta,
+                               sweeps=self.fallback_sweeps, flag_out=self.fell_back, stream=stream)
+            L.dnnmg_rhs_if(fb, ns, self.xcorr, self.b, self.fell_back, stream=stream)
+            return
+        L.dnnmg_residual(fb, ns, self.xcorr, self.vprev, self.r2, self.ws_res, stream=stream)
+        L.dnnmg_norm2_pair_f64(self.r, self.r2, self.norms, self.ws_norm, stream=stream)
+        L.dnnmg_fallback(fb, ns, self.xt, self.vprev, self.norms, self.xcorr, self.ws_fb, theta=self.theta,
+                         sweeps=self.fallback_sweeps, flag_out=self.fell_back, stream=stream)
+        L.dnnmg_rhs(fb, ns, self.xcorr, self.b, stream=stream)
 
     def _step_levels(self, stream=None):
         """The step with the prediction J levels above the coarse mesh (and
@@ -171,19 +183,7 @@ class CorrectionStep:
                                         self.inv_scale, stream=stream)
             L.dnnmg_patch_forward(self.net, self.np, self.X, self.ldx, self.Y, stream=stream)
         L.dnnmg_scatter_avg_levels(box, J, self.Y, self.xcorr, vbase=self.xt, stream=stream)
-        if self.indicator:
-            if self.carry_rhs:
-                L.dnnmg_residual_b(fb, ns, self.xcorr, self.b, self.r2, self.ws_res, stream=stream)
-            else:
-                L.dnnmg_residual(fb, ns, self.xcorr, self.vprev, self.r2, self.ws_res, stream=stream)
-            L.dnnmg_norm2_pair_f64(self.r, self.r2, self.norms, self.ws_norm, stream=stream)
-            if self.carry_rhs:
-                L.dnnmg_fallback_b(fb, ns, self.xt, self.b, self.norms, self.xcorr, self.ws_fb, theta=self.theta,
-                                   sweeps=self.fallback_sweeps, flag_out=self.fell_back, stream=stream)
-            else:
-                L.dnnmg_fallback(fb, ns, self.xt, self.vprev, self.norms, self.xcorr, self.ws_fb, theta=self.theta,
-                                 sweeps=self.fallback_sweeps, flag_out=self.fell_back, stream=stream)
-        L.dnnmg_rhs(fb, ns, self.xcorr, self.b, stream=stream)
+        self._indicator_rhs(fb, stream)
         L.dnnmg_restrict_levels(box, J, self.b, self.bc, stream=stream)
 
     def attach_coarse(self, opts, coarse_bc):

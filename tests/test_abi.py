@@ -159,3 +159,30 @@ def test_q2_host_validation_without_gpu():
     rc = lib.dnnmg_patch_gather_forward_geom(ctypes.byref(even), ctypes.byref(net), None, p, p, ctypes.byref(feat),
                                              p, None)
     assert rc < 0
+
+
+def test_residual_rhs_b_host_validation_without_gpu():
+    """The fused indicator residual + Rhs and the predicated Rhs reject NULL
+    and aliased pointers and a short workspace before anything is enqueued."""
+    import dnnmg_synth as syn
+    import paper_2307_14837_amd as L
+
+    lib = L._lib.lib()
+    ns = L.NS.of(syn.cfg2().ns)
+    box = L.Box.of(syn.channel_box((4, 2, 2)))
+    f = lib.dnnmg_residual_rhs_b
+    x, b, r, s, ws = (ctypes.c_void_p(a) for a in (16, 32, 48, 64, 80))
+    big = L.residual_workspace_bytes(box)
+    assert f(ctypes.byref(box), ctypes.byref(ns), None, b, r, s, ws, big, None) == -1
+    assert b"NULL" in lib.dnnmg_last_error()
+    assert f(ctypes.byref(box), ctypes.byref(ns), x, b, b, s, ws, big, None) == -1
+    assert f(ctypes.byref(box), ctypes.byref(ns), x, x, r, s, ws, big, None) == -1
+    assert b"alias" in lib.dnnmg_last_error()
+    assert f(ctypes.byref(box), ctypes.byref(ns), x, b, r, b, ws, big, None) == -1
+    assert b"b_save" in lib.dnnmg_last_error()
+    assert f(ctypes.byref(box), ctypes.byref(ns), x, b, r, s, ws, big - 1, None) == -2
+    assert b"workspace" in lib.dnnmg_last_error()
+    bad = L.NS(1e-3, 0.0, 0.02, 0.1)
+    assert f(ctypes.byref(box), ctypes.byref(bad), x, b, r, s, ws, big, None) == -1
+    rc = lib.dnnmg_rhs_if(ctypes.byref(box), ctypes.byref(ns), x, None, b, None, None)
+    assert rc == -1 and b"NULL" in lib.dnnmg_last_error()

@@ -255,6 +255,67 @@ def test_rhs(L, orc, name):
         assert np.all(got[3] == 0)
 
 
+@pytest.mark.parametrize("name", list(BOXES))
+def test_residual_rhs_b(L, orc, name):
+    """The indicator's residual and the next right-hand side in one pass:
+    r equals dnnmg_residual_b's bit for bit, b_save the b given, and the new
+    b matches dnnmg_rhs at the same velocity (FP32 rounding order) and the
+    oracle's Rhs; on a field with active LPS terms, r matches the oracle's
+    Crank-Nicolson residual."""
+    box = BOXES[name]
+    say("residual + next rhs in one pass", name)
+    ns = syn.NSParams(0.05, 0.02, 0.5, 0.8)
+    x, vp = fields(box, 11, False, orc)
+    nf = box.n_fine
+    xg, vpg = to_gpu(x.ravel()), to_gpu(vp.ravel())
+    ws = torch.empty(L.residual_workspace_bytes(box), dtype=torch.uint8, device=dev())
+    new = lambda: torch.full((4 * nf,), float("nan"), dtype=torch.float32, device=dev())
+    b = new()
+    L.dnnmg_rhs(box, ns, vpg, b)
+    r_sep, b_sep = new(), new()
+    L.dnnmg_residual_b(box, ns, xg, b, r_sep, ws)
+    L.dnnmg_rhs(box, ns, xg, b_sep)
+    b_io, r, b_save = b.clone(), new(), new()
+    L.dnnmg_residual_rhs_b(box, ns, xg, b_io, r, ws, b_save=b_save)
+    torch.cuda.synchronize()
+    assert torch.equal(r, r_sep)
+    assert torch.equal(b_save, b)
+    got, sep = (t.cpu().numpy().reshape(4, -1).astype(np.float64) for t in (b_io, b_sep))
+    assert np.all(got[3] == 0)
+    scale = np.abs(sep).max()
+    say(f"  next rhs vs dnnmg_rhs: max |diff| {np.abs(got - sep).max() / scale:.1e} of the scale")
+    assert np.abs(got - sep).max() <= 1e-6 * scale
+    ref_b = orc.rhs(box, ns, x[:3].astype(np.float64))
+    assert rel_l2(got, ref_b) <= 1e-5
+    ref_r = orc.residual(box, ns, x.astype(np.float64), vp.astype(np.float64))
+    assert rel_l2(r.cpu().numpy().reshape(4, -1), ref_r) <= 1e-5
+    # without b_save; a second call on the replaced b gives the same next b
+    r2 = new()
+    L.dnnmg_residual_rhs_b(box, ns, xg, b_io, r2, ws)
+    torch.cuda.synchronize()
+    assert np.array_equal(b_io.cpu().numpy().reshape(4, -1), got.astype(np.float32))
+
+
+def test_rhs_if(L, orc):
+    """The predicated right-hand side: b untouched under a clear flag, equal
+    to dnnmg_rhs bit for bit under a set one."""
+    box = BOXES["mixed"]
+    say("rhs under a device flag")
+    ns = syn.NSParams(1e-3, 0.01)
+    rng = np.random.default_rng(12)
+    v = to_gpu(f32(rng.standard_normal((3, box.n_fine))).ravel())
+    fm = to_gpu(f32(rng.standard_normal((3, box.n_fine))).ravel())
+    ref = torch.empty(4 * box.n_fine, dtype=torch.float32, device=dev())
+    L.dnnmg_rhs(box, ns, v, ref, fmid=fm)
+    b0 = to_gpu(f32(rng.standard_normal(4 * box.n_fine)))
+    for fl in (0, 1):
+        flag = torch.full((1,), fl, dtype=torch.int32, device=dev())
+        b = b0.clone()
+        L.dnnmg_rhs_if(box, ns, v, b, flag, fmid=fm)
+        torch.cuda.synchronize()
+        assert torch.equal(b, ref if fl else b0), fl
+
+
 @pytest.mark.parametrize("name", ["cfg1", "chan_small", "per_uneven", "cfg2"])
 def test_gather_scatter(L, orc, name):
     box = BOXES[name]
