@@ -8,7 +8,8 @@
 // (of dY, dZ2, dZ1, summed from the tiles the weight-gradient products stage).
 // For an FP32 network they run on one tiled GEMM kernel (64x64 output tiles,
 // LDS-staged operands, v_mfma_f32_16x16x4f32); for a BF16 network on BF16
-// MFMA kernels with the operands rounded to BF16 as in the forward pass.
+// MFMA kernels with the operands rounded to BF16 as in the forward pass (the
+// dZ products of widths 128 and 256 weight-stationary, W^T in registers).
 // All accumulate in FP32.  The weight gradients reduce over patches; they are
 // split over K (patch ranges) and the partial tiles are summed in a fixed
 // order, so results are run-to-run identical.
@@ -470,6 +471,167 @@ static void wgrad_bf16(int64_t M, int64_t N, int64_t K, int64_t splits, int64_t 
     k_sum_splits<<<blocks_for(N, 64), 256, 0, s>>>(N, (int)splits, cpart, colsum);
 }
 
+// dZ of a BF16 network of width N = 128 or 256, weight-stationary: the same
+// product and epilogue as k_dz_bf16, C[m][n] = (sum_k A[m][k] W[n][k]) (1 -
+// S[m][n]^2), with W^T held in registers.  Eight waves each keep the BF16
+// fragments of their NT x 16 output units over all NK K chunks (W rows are
+// the MFMA's A operand, so a lane holds 8 consecutive K of one unit) for
+// the whole launch; a persistent grid walks blocks of MB patch rows.  A
+// block's rows of A are staged once in LDS as BF16 (a lane's B fragment is 8
+// consecutive K of one patch row), double buffered: the next block's rows
+// are requested before the current block's products and written to the
+// other buffer after them, so one barrier per block orders the buffers.  A
+// lane's accumulator holds 4 consecutive units of one patch row, which the
+// epilogue scales by (1 - s^2) and writes as one 16-byte store.  The K
+// chunks are summed in ascending order as in k_dz_bf16.
+constexpr int DZ_NW = 8, DZ_NT = 64 * DZ_NW;
+template <int NT, int NK, int MB>
+__global__ void __launch_bounds__(DZ_NT)
+    k_dz_ws(int64_t M, int K, const float *__restrict__ A, int64_t lda, const float *__restrict__ W, int64_t ldw,
+            const uint16_t *__restrict__ S, int64_t lds_, float *__restrict__ C, int64_t ldc) {
+    constexpr int N = 16 * NT * DZ_NW, KP = 32 * NK, PITCH = KP + 8; // LDS row pitch (bf16)
+    constexpr int TPR = DZ_NT / MB, NJ = MB / 16;                    // staging threads per row; m tiles
+    constexpr int EPT = KP / TPR;                                    // K elements a thread stages
+    static_assert(KP % TPR == 0 && EPT % 8 == 0, "staging splits a row into 16-byte pieces");
+    __shared__ __attribute__((aligned(16))) uint16_t sA[2][MB * PITCH];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, i16 = lane & 15;
+    const int nb = 16 * NT * wave; // the wave's first unit
+    // W^T fragments: unit nb + 16 t + i16, K 32 c + 8 g .. + 8 (zero past K)
+    u32x4_t wf[NT][NK];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int c = 0; c < NK; ++c) {
+            const float *wr = W + (int64_t)(nb + 16 * t + i16) * ldw;
+            float v[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = 32 * c + 8 * g + e;
+                v[e] = wr[k < K ? k : K - 1];
+                v[e] = k < K ? v[e] : 0.0f;
+            }
+            wf[t][c] = u32x4_t{pack_bf16x2_hw(v[0], v[1]), pack_bf16x2_hw(v[2], v[3]), pack_bf16x2_hw(v[4], v[5]),
+                               pack_bf16x2_hw(v[6], v[7])};
+        }
+    // staging: thread tid takes row tid / TPR of the block, K (tid % TPR) EPT ..
+    const int srow = tid / TPR, sk = (tid % TPR) * EPT;
+    const bool vec = K == KP && lda % 4 == 0 && ((uintptr_t)A & 15) == 0;
+    float ra[EPT];
+    auto load = [&](int64_t mb) {
+        const int64_t m = mb * MB + srow;
+        const int64_t mr = m < M ? m : M - 1;
+        const float *ar = A + mr * lda;
+        if (vec) {
+#pragma unroll
+            for (int q = 0; q < EPT / 4; ++q) {
+                const float4 x = *(const float4 *)(ar + sk + 4 * q);
+                ra[4 * q] = x.x, ra[4 * q + 1] = x.y, ra[4 * q + 2] = x.z, ra[4 * q + 3] = x.w;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const int k = sk + e;
+                ra[e] = ar[k < K ? k : K - 1];
+            }
+        }
+    };
+    auto store = [&](int buf, int64_t mb) {
+        const bool mok = mb * MB + srow < M;
+#pragma unroll
+        for (int q = 0; q < EPT / 8; ++q) {
+            u32x4_t pk;
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const int e = 8 * q + 2 * h;
+                const bool k0 = mok && sk + e < K, k1 = mok && sk + e + 1 < K;
+                pk[h] = pack_bf16x2_hw(k0 ? ra[e] : 0.0f, k1 ? ra[e + 1] : 0.0f);
+            }
+            *(u32x4_t *)&sA[buf][srow * PITCH + sk + 8 * q] = pk;
+        }
+    };
+    const int64_t nmb = (M + MB - 1) / MB;
+    int64_t mb = blockIdx.x;
+    int buf = 0;
+    if (mb < nmb) {
+        load(mb);
+        store(0, mb);
+    }
+    for (; mb < nmb; mb += gridDim.x, buf ^= 1) {
+        __syncthreads();
+        // the epilogue's saved activations of this block, then the next
+        // block's rows (so waiting for the former does not wait for the latter)
+        uint2 sv[NT][NJ];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const int64_t m = mb * MB + 16 * j + i16;
+                const int64_t mr = m < M ? m : M - 1;
+                sv[t][j] = *(const uint2 *)(S + mr * lds_ + nb + 16 * t + 4 * g);
+            }
+        const int64_t next = mb + gridDim.x;
+        if (next < nmb) load(next);
+        f32x4 acc[NT][NJ];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < NK; ++c) {
+            u32x4_t bf[NJ];
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) bf[j] = *(const u32x4_t *)&sA[buf][(16 * j + i16) * PITCH + 32 * c + 8 * g];
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int j = 0; j < NJ; ++j)
+                    acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, wf[t][c]),
+                                                                        __builtin_bit_cast(bf16x8_t, bf[j]),
+                                                                        acc[t][j], 0, 0, 0);
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const int64_t m = mb * MB + 16 * j + i16;
+                if (m >= M) continue;
+                const float s0 = bf16_to_f32((uint16_t)(sv[t][j].x & 0xffffu));
+                const float s1 = bf16_to_f32((uint16_t)(sv[t][j].x >> 16));
+                const float s2 = bf16_to_f32((uint16_t)(sv[t][j].y & 0xffffu));
+                const float s3 = bf16_to_f32((uint16_t)(sv[t][j].y >> 16));
+                *(float4 *)(C + m * ldc + nb + 16 * t + 4 * g) =
+                    make_float4(acc[t][j][0] * (1.0f - s0 * s0), acc[t][j][1] * (1.0f - s1 * s1),
+                                acc[t][j][2] * (1.0f - s2 * s2), acc[t][j][3] * (1.0f - s3 * s3));
+            }
+        if (next < nmb) store(buf ^ 1, next);
+    }
+}
+
+// The weight-stationary dZ product where its shapes are built (width 128 or
+// 256, K = 81 or the width, 16-byte aligned rows of S and C): true if launched.
+template <int NT, int NK, int MB>
+static void dz_ws_launch(int64_t M, int K, const float *A, int64_t lda, const float *W, int64_t ldw, const uint16_t *S,
+                         int64_t lds_, float *C, int64_t ldc, hipStream_t s) {
+    const int64_t nmb = (M + MB - 1) / MB;
+    const int64_t cap = (int64_t)device_cus();
+    k_dz_ws<NT, NK, MB><<<(unsigned)(nmb < cap ? nmb : cap), DZ_NT, 0, s>>>(M, K, A, lda, W, ldw, S, lds_, C, ldc);
+}
+
+static bool dz_ws(int64_t M, int64_t N, int64_t K, const float *A, int64_t lda, const float *W, int64_t ldw,
+                  const uint16_t *S, int64_t lds_, float *C, int64_t ldc, hipStream_t s) {
+    if (M <= 0 || lds_ % 4 || ldc % 4 || ((uintptr_t)S & 7) || ((uintptr_t)C & 15)) return false;
+    // K = 81 takes four chunks (the fourth is zeros), so a staging thread's
+    // share of a row is whole 16-byte pieces
+    // (blocks of 32 rows where the operand fragments take the most registers)
+    if (N == 256 && K == N_OUT) dz_ws_launch<2, 4, 64>(M, (int)K, A, lda, W, ldw, S, lds_, C, ldc, s);
+    else if (N == 256 && K == 256) dz_ws_launch<2, 8, 32>(M, (int)K, A, lda, W, ldw, S, lds_, C, ldc, s);
+    else if (N == 128 && K == N_OUT) dz_ws_launch<1, 4, 64>(M, (int)K, A, lda, W, ldw, S, lds_, C, ldc, s);
+    else if (N == 128 && K == 128) dz_ws_launch<1, 4, 64>(M, (int)K, A, lda, W, ldw, S, lds_, C, ldc, s);
+    else return false;
+    return true;
+}
+
 template <typename TX, typename TS>
 static void backward_impl(const BwdPlan &p, const TX *X, int64_t ldx, const TS *saved, const float *W2,
                           const float *W3, const float *dY, float *dW[3], float *db[3], char *ws,
@@ -482,9 +644,12 @@ static void backward_impl(const BwdPlan &p, const TX *X, int64_t ldx, const TS *
     const TS *A1 = saved, *A2 = saved + n * H;
     if constexpr (sizeof(TS) == 2) {
         // BF16 network: dZ products on BF16 MFMA (W3 is [H][81], W2 [H][H])
+        // (weight-stationary where that kernel is built)
         dim3 grid((unsigned)((n + WB - 1) / WB), (unsigned)((H + WB - 1) / WB));
-        k_dz_bf16<<<grid, 256, 0, s>>>(n, H, N_OUT, dY, N_OUT, W3, N_OUT, (const uint16_t *)A2, H, dz2, H);
-        k_dz_bf16<<<grid, 256, 0, s>>>(n, H, H, dz2, H, W2, H, (const uint16_t *)A1, H, dz1, H);
+        if (!dz_ws(n, H, N_OUT, dY, N_OUT, W3, N_OUT, (const uint16_t *)A2, H, dz2, H, s))
+            k_dz_bf16<<<grid, 256, 0, s>>>(n, H, N_OUT, dY, N_OUT, W3, N_OUT, (const uint16_t *)A2, H, dz2, H);
+        if (!dz_ws(n, H, H, dz2, H, W2, H, (const uint16_t *)A1, H, dz1, H, s))
+            k_dz_bf16<<<grid, 256, 0, s>>>(n, H, H, dz2, H, W2, H, (const uint16_t *)A1, H, dz1, H);
     } else {
         // dZ2 = (dY W3^T) (.) (1 - A2^2): W3 is [H][81] -> op(B)[k=o][n=h] = W3[h][o]
         gemm<false, true, float, float, TS, true>(n, H, N_OUT, 1, N_OUT + BK, dY, N_OUT, W3, N_OUT, dz2, H,
