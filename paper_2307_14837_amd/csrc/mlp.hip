@@ -180,8 +180,12 @@ __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(
 
 // One dense layer for the tile: acc = W^T B over the wave's output tiles,
 // then bias and (unless LAST) tanh into the next layer's fragments, or (LAST)
-// the output rows.
-template <int K, int KN, int NTILES, int NCH, int PT, bool LAST, int H, int NW, int NO = N_OUT, bool SKIP = false>
+// the output rows.  INPLACE: `out` is `in`; every wave's products (all its
+// reads of `in`) end at a workgroup barrier before the first output is
+// written, and a skip connection reads the input only at the positions the
+// same lane then overwrites.
+template <int K, int KN, int NTILES, int NCH, int PT, bool LAST, int H, int NW, int NO = N_OUT, bool SKIP = false,
+          bool INPLACE = false>
 __device__ __forceinline__ void layer(const typename Frag<K>::T *__restrict__ Wl, const float *__restrict__ bias,
                                       const unsigned char *in, unsigned char *out, float scale, float qinv,
                                       int wave, int lane, int64_t base, int64_t n, float *__restrict__ Y,
@@ -232,6 +236,7 @@ __device__ __forceinline__ void layer(const typename Frag<K>::T *__restrict__ Wl
     };
     if (NTILES % NW == 0 || wave + NW * (OTW - 1) < NTILES) products(std::integral_constant<int, OTW>{});
     else if constexpr (OTW > 1) products(std::integral_constant<int, OTW - 1>{});
+    if constexpr (INPLACE) lds_barrier();
 #pragma unroll
     for (int i = 0; i < OTW; ++i) {
         const int ot = wave + NW * i;
@@ -554,6 +559,10 @@ struct DeepShape {
     static constexpr int BUF = IN0 > INH ? (IN0 > YB ? IN0 : YB) : (INH > YB ? INH : YB);
     static constexpr int NW = (PT == 4 || HP > 512) ? 8 : 4;
     static constexpr int NTHR = 64 * NW;
+    // where two activation buffers would not fit LDS, one buffer and every
+    // layer in place
+    static constexpr bool ONEBUF = 2 * BUF > 160 * 1024;
+    static constexpr int SMEM = ONEBUF ? BUF : 2 * BUF;
 };
 
 template <int DT, int HP, int PT, int J>
@@ -562,25 +571,26 @@ __global__ void __launch_bounds__((DeepShape<DT, HP, PT, J>::NTHR))
                float *__restrict__ Y) {
     using S = DeepShape<DT, HP, PT, J>;
     using F = typename Frag<S::K>::T;
-    __shared__ __attribute__((aligned(16))) unsigned char smem[2 * S::BUF];
+    __shared__ __attribute__((aligned(16))) unsigned char smem[S::SMEM];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr bool IP = S::ONEBUF;
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t base = tile * 16 * PT;
-        unsigned char *cur = smem, *nxt = smem + S::BUF;
+        unsigned char *cur = smem, *nxt = IP ? smem : smem + S::BUF;
         stage_rows<S::K, S::NCH0, PT, S::NTHR, S::INP>(Xv, ldx, base, n, cur, tid);
         lds_barrier();
-        layer<S::K, S::K, HP / 16, S::NCH0, PT, false, HP, S::NW>((const F *)a.W[0], a.b[0], cur, nxt, 1.0f, 1.0f,
-                                                                  wave, lane, base, n, Y, nullptr, 0, 0);
+        layer<S::K, S::K, HP / 16, S::NCH0, PT, false, HP, S::NW, N_OUT, false, IP>(
+            (const F *)a.W[0], a.b[0], cur, nxt, 1.0f, 1.0f, wave, lane, base, n, Y, nullptr, 0, 0);
         lds_barrier();
         for (int l = 1; l < depth; ++l) {
             unsigned char *t = cur;
             cur = nxt;
             nxt = t;
-            layer<S::K, S::K, HP / 16, S::NCHH, PT, false, HP, S::NW, S::NO, true>(
+            layer<S::K, S::K, HP / 16, S::NCHH, PT, false, HP, S::NW, S::NO, true, IP>(
                 (const F *)a.W[l], a.b[l], cur, nxt, 1.0f, 1.0f, wave, lane, base, n, Y, nullptr, 0, 0);
             lds_barrier();
         }
-        layer<S::K, S::K, S::OUTP / 16, S::NCHH, PT, true, HP, S::NW, S::NO>(
+        layer<S::K, S::K, S::OUTP / 16, S::NCHH, PT, true, HP, S::NW, S::NO, false, IP>(
             (const F *)a.W[depth], a.b[depth], nxt, cur, 1.0f, 1.0f, wave, lane, base, n, Y, nullptr, 0, 0);
         lds_barrier();
         {
@@ -623,7 +633,7 @@ __global__ void __launch_bounds__(256) k_zero_f32(int n, float *__restrict__ p) 
 // Instantiated (dtype, padded width, PT, J) variants of the paper's network.
 #define DNNMG_DEEP_VARIANTS(X)                                                                          \
     X(DNNMG_F32, 512, 1, 1) X(DNNMG_F32, 768, 1, 1) X(DNNMG_BF16, 512, 2, 1) X(DNNMG_BF16, 512, 4, 1)     \
-    X(DNNMG_BF16, 768, 1, 1) X(DNNMG_BF16, 768, 2, 1)                                                     \
+    X(DNNMG_BF16, 768, 1, 1) X(DNNMG_BF16, 768, 2, 1) X(DNNMG_BF16, 768, 4, 1)                            \
     X(DNNMG_F32, 512, 1, 2) X(DNNMG_F32, 768, 1, 2) X(DNNMG_BF16, 512, 1, 2) X(DNNMG_BF16, 512, 2, 2)     \
     X(DNNMG_BF16, 768, 1, 2) X(DNNMG_BF16, 768, 2, 2)
 

@@ -93,6 +93,40 @@ def test_paper_network_forward(L, dn, n_in, H, n_out, dtype, tol, n):
     assert e <= tol
 
 
+@pytest.mark.parametrize("n", [8192 + 37, 16384 + 37])
+@pytest.mark.parametrize("H", [512, 750])
+def test_paper_network_forward_large_tiles(L, dn, H, n):
+    """From 8,192 patches the BF16 forward takes 32-patch tiles, from 16,384
+    64-patch tiles (width 750: one activation buffer, every layer in place);
+    both sizes here end in a ragged tail of 37.  Rows are independent, so the
+    sampled rows (the first 256, the tail tile and its neighbour) match the
+    oracle, and bit for bit the same rows forwarded alone on 16-patch tiles
+    (every tile geometry sums the K chunks in the same order)."""
+    n_in, n_out = 240, 81
+    say("paper network, 64-patch tiles", H, n)
+    ps = r32(dn.random_params(n_in, H, n_out, 8, seed=5))
+    net = L.DeepNet(L.BF16, *ps)
+    ip = net.in_pad
+    X = f32(np.random.default_rng(6).standard_normal((n, n_in)))
+    Xp = np.zeros((n, ip), np.float32)
+    Xp[:, :n_in] = X
+    Xg = to_gpu(Xp.ravel()).to(torch.bfloat16)
+    Y = torch.full((n * n_out,), float("nan"), dtype=torch.float32, device=dev())
+    L.dnnmg_deepnet_forward(net, n, Xg, ip, Y)
+    rows = np.r_[0:256, n - 101:n]
+    sub = torch.as_tensor(rows, device=dev())
+    Xs = Xg.view(n, ip)[sub].contiguous()
+    Ys = torch.full((len(rows) * n_out,), float("nan"), dtype=torch.float32, device=dev())
+    L.dnnmg_deepnet_forward(net, len(rows), Xs.view(-1), ip, Ys)
+    torch.cuda.synchronize()
+    got = Y.cpu().numpy().reshape(n, n_out)[rows]
+    assert np.array_equal(got, Ys.cpu().numpy().reshape(-1, n_out))
+    ref = dn.forward(X[rows].astype(np.float64), *ps)
+    e = rel_l2(got, ref)
+    say(f"  rel-L2 {e:.2e}")
+    assert e <= 2e-2
+
+
 @pytest.mark.parametrize("levels,dtype,tol", [(1, "fp32", 1e-4), (2, "fp32", 1e-4), (1, "bf16", 2e-2),
                                               (2, "bf16", 2e-2)])
 def test_step_with_paper_network(orc, dn, levels, dtype, tol):
