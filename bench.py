@@ -57,6 +57,10 @@ def parse():
                     help="run only the per-kernel measurements on the large channel (for rocprofv3)")
     ap.add_argument("--q2-step", action="store_true",
                     help="run only the Q2 step's graph replays on the large channel (for rocprofv3)")
+    ap.add_argument("--profile-training", action="store_true",
+                    help="run only the training-step variant for --steps steps (for rocprofv3)")
+    ap.add_argument("--profile-paper-net", action="store_true",
+                    help="run only the paper network form's step variant (for rocprofv3)")
     ap.add_argument("--cpu-worker", type=int, default=None, help=argparse.SUPPRESS)
     return ap.parse_args()
 
@@ -944,6 +948,12 @@ def main():
         return
     if args.q2_step:
         q2_profile(args.steps)
+        return
+    if args.profile_training:
+        print(json.dumps(run_training(args.steps)), flush=True)
+        return
+    if args.profile_paper_net:
+        print(json.dumps(run_paper_network(args.steps, args.warmup)), flush=True)
         return
     if args.profile_step:
         profile_step(args.steps)

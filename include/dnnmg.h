@@ -276,6 +276,14 @@ size_t dnnmg_patch_saved_bytes(const dnnmg_mlp *net, int64_t n);
  * the loss itself is dnnmg_norm2_f64(Y, T) / n. */
 int dnnmg_mse_grad(int64_t n, const float *Y, const float *T, float *dY, void *stream);
 
+/* dnnmg_mse_grad with the loss in the same pass (Sec. 4.2 training
+ * objective): dY as dnnmg_mse_grad, and *loss_sum (FP64, device) = sum of
+ * (Y - T)^2 over the n x 81 outputs, the value dnnmg_norm2_f64(Y, T) gives
+ * (same partition and summation order).  ws: device workspace of at least
+ * dnnmg_norm2_workspace() bytes.  n = 0 gives loss_sum = 0. */
+int dnnmg_mse_grad_loss(int64_t n, const float *Y, const float *T, float *dY, double *loss_sum, void *ws,
+                        size_t ws_bytes, void *stream);
+
 /* Gradients of sum_M <dY_M, Y_M> with respect to the network parameters
  * (chain rule through both tanh layers; the input gradient is not formed),
  * for F32 or BF16 networks.  net gives dtype and width; W2 and W3 are the FP32

@@ -126,6 +126,7 @@ _sig("dnnmg_norm2_workspace", [], c_sz)
 _sig("dnnmg_norm2_f64", [c_i64, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp])
 _sig("dnnmg_norm2_pair_f64", [c_i64, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp])
 _sig("dnnmg_mse_grad", [c_i64, c_vp, c_vp, c_vp, c_vp])
+_sig("dnnmg_mse_grad_loss", [c_i64, c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp])
 _sig("dnnmg_patch_backward_workspace", [_P(MLP), c_i64], c_sz)
 _sig("dnnmg_patch_backward", [_P(MLP), c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, c_vp, c_vp * 3, c_vp * 3,
                               c_vp, c_sz, c_vp])
@@ -190,7 +191,7 @@ EXPORTS = [
     "dnnmg_patch_forward_tiles", "dnnmg_prolong_residual", "dnnmg_prolong_residual_b",
     "dnnmg_residual_b", "dnnmg_residual_b_noalloc", "dnnmg_fallback_b", "dnnmg_residual_rhs_b", "dnnmg_rhs_if",
     "dnnmg_patch_saved_bytes", "dnnmg_scatter_avg", "dnnmg_scatter_avg_form", "dnnmg_norm2_workspace", "dnnmg_norm2_f64",
-    "dnnmg_mse_grad", "dnnmg_patch_backward_workspace", "dnnmg_patch_backward", "dnnmg_adamw_step",
+    "dnnmg_mse_grad", "dnnmg_mse_grad_loss", "dnnmg_patch_backward_workspace", "dnnmg_patch_backward", "dnnmg_adamw_step",
     "dnnmg_vanka_workspace", "dnnmg_vanka_sweeps", "dnnmg_fallback_workspace", "dnnmg_fallback",
     "dnnmg_patch_gather_forward", "dnnmg_plan_workspace", "dnnmg_plan_create", "dnnmg_plan_destroy",
     "dnnmg_plan_sizes", "dnnmg_plan_choice", "dnnmg_batch_step", "dnnmg_plan_autotune",
@@ -645,6 +646,16 @@ def dnnmg_mse_grad(Y, T, dY, n=None, stream=None):
     _check(_lib.dnnmg_mse_grad(int(n), _ptr(Y, torch.float32, n * N_OUT, "Y"),
                                _ptr(T, torch.float32, n * N_OUT, "T"),
                                _ptr(dY, torch.float32, n * N_OUT, "dY"), _stream(stream)))
+
+
+def dnnmg_mse_grad_loss(Y, T, dY, loss_sum, ws, n=None, stream=None):
+    """dY = 2 (Y - T) / n and loss_sum = sum (Y - T)^2 (FP64) in one pass."""
+    n = Y.numel() // N_OUT if n is None else n
+    _check(_lib.dnnmg_mse_grad_loss(int(n), _ptr(Y, torch.float32, n * N_OUT, "Y"),
+                                    _ptr(T, torch.float32, n * N_OUT, "T"),
+                                    _ptr(dY, torch.float32, n * N_OUT, "dY"),
+                                    _ptr(loss_sum, torch.float64, 1, "loss_sum"), _ptr(ws, None, None, "ws"),
+                                    ws.numel() * ws.element_size(), _stream(stream)))
 
 
 def backward_workspace_bytes(net: MLP, n: int) -> int:

@@ -404,6 +404,46 @@ __global__ void k_mse_grad(int64_t len, float scale, const float *__restrict__ Y
     if (i < len) dY[i] = scale * (Y[i] - T[i]);
 }
 
+// The loss gradient and the loss in one pass: dY as k_mse_grad, and per
+// workgroup the FP64 sum of (Y - T)^2 over a grid-stride range of LOSS_BLOCKS
+// x 256 threads, reduced by a fixed tree (the partition and order of
+// dnnmg_norm2_f64, so the sum is that norm's to the bit); k_loss_final adds
+// the partials in a fixed order.
+constexpr int LOSS_BLOCKS = 1024;
+__global__ void __launch_bounds__(256) k_mse_grad_loss(int64_t len, float scale, const float *__restrict__ Y,
+                                                       const float *__restrict__ T, float *__restrict__ dY,
+                                                       double *__restrict__ part) {
+    double s = 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < len; t += (int64_t)gridDim.x * blockDim.x) {
+        const float y = Y[t], tt = T[t];
+        dY[t] = scale * (y - tt);
+        const double e = (double)y - (double)tt;
+        s += e * e;
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) k_loss_final(int nparts, const double *__restrict__ part,
+                                                    double *__restrict__ out) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int t = threadIdx.x; t < nparts; t += 256) s += part[t];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
 __global__ void k_adamw(int64_t n, float *__restrict__ th, float *__restrict__ m, float *__restrict__ v,
                         const float *__restrict__ g, float lr, float b1, float b2, float eps, float wd,
                         float inv_c1, float inv_sqrt_c2) {
@@ -686,6 +726,20 @@ extern "C" int dnnmg_mse_grad(int64_t n, const float *Y, const float *T, float *
     int64_t len = n * N_OUT;
     k_mse_grad<<<blocks_for(len, 256), 256, 0, (hipStream_t)stream>>>(len, 2.0f / (float)n, Y, T, dY);
     return hip_check(hipGetLastError(), "dnnmg_mse_grad launch");
+}
+
+extern "C" int dnnmg_mse_grad_loss(int64_t n, const float *Y, const float *T, float *dY, double *loss_sum,
+                                   void *ws, size_t ws_bytes, void *stream) {
+    if (n < 0) return fail(DNNMG_ERR_SHAPE, "dnnmg_mse_grad_loss: n < 0");
+    if (!Y || !T || !dY || !loss_sum || !ws) return fail(DNNMG_ERR_ARG, "dnnmg_mse_grad_loss: NULL pointer");
+    if (ws_bytes < LOSS_BLOCKS * sizeof(double))
+        return fail(DNNMG_ERR_SHAPE, "dnnmg_mse_grad_loss: workspace %zu < %zu bytes", ws_bytes,
+                    LOSS_BLOCKS * sizeof(double));
+    const int64_t len = n * N_OUT;
+    hipStream_t s = (hipStream_t)stream;
+    k_mse_grad_loss<<<LOSS_BLOCKS, 256, 0, s>>>(len, n > 0 ? 2.0f / (float)n : 0.0f, Y, T, dY, (double *)ws);
+    k_loss_final<<<1, 256, 0, s>>>(LOSS_BLOCKS, (const double *)ws, loss_sum);
+    return hip_check(hipGetLastError(), "dnnmg_mse_grad_loss launch");
 }
 
 extern "C" int dnnmg_adamw_step(int64_t n, float *theta, float *m, float *v, const float *g, float lr,

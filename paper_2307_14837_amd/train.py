@@ -111,8 +111,8 @@ class PatchTrainer:
         if n > self.max_batch:
             raise ValueError("batch larger than max_batch")
         L.dnnmg_patch_forward(self.net, n, X, LDX, self.Y, saved=self.saved, stream=stream)
-        L.dnnmg_mse_grad(self.Y, T, self.dY, n=n, stream=stream)
-        L.dnnmg_norm2_f64(self.Y, self.loss_dev, self.ws_norm, b=T, n=n * L.N_OUT, stream=stream)
+        # the loss gradient and the loss (for loss()) in one pass
+        L.dnnmg_mse_grad_loss(self.Y, T, self.dY, self.loss_dev, self.ws_norm, n=n, stream=stream)
         L.dnnmg_patch_backward(self.net, self.theta[2], self.theta[4], n, X, LDX, self.saved, self.dY,
                                [self.grad[0], self.grad[2], self.grad[4]],
                                [self.grad[1], self.grad[3], self.grad[5]], self.ws, stream=stream)

@@ -186,3 +186,17 @@ def test_residual_rhs_b_host_validation_without_gpu():
     assert f(ctypes.byref(box), ctypes.byref(bad), x, b, r, s, ws, big, None) == -1
     rc = lib.dnnmg_rhs_if(ctypes.byref(box), ctypes.byref(ns), x, None, b, None, None)
     assert rc == -1 and b"NULL" in lib.dnnmg_last_error()
+
+
+def test_mse_grad_loss_host_validation_without_gpu():
+    """The fused loss gradient checks its size, pointers and workspace before
+    anything is enqueued."""
+    import paper_2307_14837_amd as L
+
+    lib = L._lib.lib()
+    p = ctypes.c_void_p(16)
+    assert lib.dnnmg_mse_grad_loss(-1, p, p, p, p, p, 1 << 20, None) == -2
+    assert lib.dnnmg_mse_grad_loss(10, None, p, p, p, p, 1 << 20, None) == -1
+    assert b"NULL" in lib.dnnmg_last_error()
+    assert lib.dnnmg_mse_grad_loss(10, p, p, p, p, p, L.norm2_workspace_bytes() - 1, None) == -2
+    assert b"workspace" in lib.dnnmg_last_error()

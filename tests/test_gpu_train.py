@@ -142,3 +142,31 @@ def test_autograd_function_matches_oracle(L, orc, dtype, H, n, tol):
         e = rel_l2(p.grad.cpu().numpy().astype(np.float64).reshape(b.shape), b)
         say(f"  grad {i} rel-L2 {e:.2e}")
         assert e <= tol, i
+
+
+@pytest.mark.parametrize("n", [0, 1, 333, 70001])
+def test_mse_grad_with_loss(L, orc, n):
+    """The loss gradient and the loss in one pass: dY equals dnnmg_mse_grad's
+    bit for bit, the FP64 loss sum equals dnnmg_norm2_f64(Y, T) (same
+    partition and order) and the oracle's sum of squares."""
+    say("loss gradient with the loss", n)
+    rng = np.random.default_rng(9)
+    Yh = f32(rng.standard_normal((max(n, 1), 81)))
+    Th = f32(rng.standard_normal((max(n, 1), 81)))
+    Y, T = to_gpu(Yh.ravel()), to_gpu(Th.ravel())
+    dY0 = torch.full_like(Y, float("nan"))
+    dY1 = torch.full_like(Y, float("nan"))
+    ws = torch.zeros(L.norm2_workspace_bytes(), dtype=torch.uint8, device=dev())
+    loss0 = torch.zeros(1, dtype=torch.float64, device=dev())
+    loss1 = torch.full((1,), float("nan"), dtype=torch.float64, device=dev())
+    L.dnnmg_mse_grad(Y, T, dY0, n=n)
+    L.dnnmg_norm2_f64(Y, loss0, ws, b=T, n=n * 81)
+    L.dnnmg_mse_grad_loss(Y, T, dY1, loss1, ws, n=n)
+    torch.cuda.synchronize()
+    m = n * 81
+    assert torch.equal(dY0[:m], dY1[:m])
+    ref = float(np.sum((Yh[:n].astype(np.float64) - Th[:n].astype(np.float64)) ** 2))
+    got, sep = float(loss1.item()), float(loss0.item())
+    say(f"  loss {got:.6e} (separate {sep:.6e}, oracle {ref:.6e})")
+    assert abs(got - sep) <= 1e-13 * max(abs(sep), 1e-300)
+    assert abs(got - ref) <= 1e-12 * max(abs(ref), 1e-300)
