@@ -169,11 +169,15 @@ class CorrectionStep:
         side or from v_prev), Q and the network on the J-level patches, L
         back to level L + J, [indicator], Rhs on fbox, b^L = (P^J)^T b."""
         box, fb, ns, J = self.box, self.fbox, self.ns, self.levels
-        L.dnnmg_prolong_levels(box, J, self.xc, self.xt, stream=stream)
-        if self.carry_rhs:
-            L.dnnmg_residual_b(fb, ns, self.xt, self.b, self.r, self.ws_res, stream=stream)
+        if J == 1 and self.carry_rhs:
+            # one level: prolongation and residual in one pass, as in step()
+            L.dnnmg_prolong_residual_b(box, ns, self.xc, self.b, self.xt, self.r, stream=stream)
         else:
-            L.dnnmg_residual(fb, ns, self.xt, self.vprev, self.r, self.ws_res, stream=stream)
+            L.dnnmg_prolong_levels(box, J, self.xc, self.xt, stream=stream)
+            if self.carry_rhs:
+                L.dnnmg_residual_b(fb, ns, self.xt, self.b, self.r, self.ws_res, stream=stream)
+            else:
+                L.dnnmg_residual(fb, ns, self.xt, self.vprev, self.r, self.ws_res, stream=stream)
         if self.network == "paper":
             L.dnnmg_patch_gather_paper(box, J, self.xt, self.r, self.X, self.xdtype, self.ldx, self.shift,
                                        self.inv_scale, stream=stream)
