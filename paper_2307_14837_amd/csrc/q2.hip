@@ -686,14 +686,18 @@ __global__ void __launch_bounds__(256) k_q2_prolong_rows(Mesh m, int ncomp, cons
     for (int t = threadIdx.x; t < ncomp * nc0; t += blockDim.x) {
         const int c = t / nc0, I = t - c * nc0;
         const double *src = xc + c * m.n_coarse + I;
+        // every stencil entry is a node of the mesh, so all nine are
+        // requested at once (zero weights add exact zeros)
+        double v[3][3];
+#pragma unroll
+        for (int z = 0; z < 3; ++z)
+#pragma unroll
+            for (int y = 0; y < 3; ++y) v[z][y] = src[(int64_t)m.nc[0] * (iy[y] + (int64_t)m.nc[1] * iz[z])];
         double s = 0.0;
 #pragma unroll
         for (int z = 0; z < 3; ++z)
 #pragma unroll
-            for (int y = 0; y < 3; ++y) {
-                const double w = wz[z] * wy[y];
-                if (w != 0.0) s += w * src[(int64_t)m.nc[0] * (iy[y] + (int64_t)m.nc[1] * iz[z])];
-            }
+            for (int y = 0; y < 3; ++y) s += (wz[z] * wy[y]) * v[z][y];
         sU[t] = s;
     }
     __syncthreads();
@@ -726,14 +730,19 @@ __global__ void __launch_bounds__(256) k_q2_restrict_rows(Mesh m, int ncomp, con
     for (int t = threadIdx.x; t < ncomp * nf0; t += blockDim.x) {
         const int c = t / nf0, i = t - c * nf0;
         const float *src = bf + c * m.n_fine + i;
+        // padded entries point at a node of the mesh with weight 0, so all 25
+        // are requested at once (zero weights add exact zeros)
+        float v[5][5];
+#pragma unroll
+        for (int z = 0; z < 5; ++z)
+#pragma unroll
+            for (int y = 0; y < 5; ++y) v[z][y] = src[(int64_t)m.nf[0] * (fy[y] + (int64_t)m.nf[1] * fz[z])];
         double s = 0.0;
 #pragma unroll
         for (int z = 0; z < 5; ++z) {
-            if (wz[z] == 0.0) continue;
             double sy = 0.0;
 #pragma unroll
-            for (int y = 0; y < 5; ++y)
-                if (wy[y] != 0.0) sy += wy[y] * (double)src[(int64_t)m.nf[0] * (fy[y] + (int64_t)m.nf[1] * fz[z])];
+            for (int y = 0; y < 5; ++y) sy += wy[y] * (double)v[z][y];
             s += wz[z] * sy;
         }
         sT[t] = s;
