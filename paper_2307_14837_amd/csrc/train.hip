@@ -9,7 +9,9 @@
 // For an FP32 network they run on one tiled GEMM kernel (64x64 output tiles,
 // LDS-staged operands, v_mfma_f32_16x16x4f32); for a BF16 network on BF16
 // MFMA kernels with the operands rounded to BF16 as in the forward pass (the
-// dZ products of widths 128 and 256 weight-stationary, W^T in registers).
+// dZ products of widths 128 and 256 weight-stationary, W^T in registers,
+// writing dZ in BF16 as its consumers stage it and summing its columns for
+// the bias gradients).
 // All accumulate in FP32.  The weight gradients reduce over patches; they are
 // split over K (patch ranges) and the partial tiles are summed in a fixed
 // order, so results are run-to-run identical.
@@ -151,14 +153,18 @@ __global__ void __launch_bounds__(256)
 // staged K-minor in LDS so a fragment (8 consecutive K of one row) is one
 // 16-byte read; the next step's operands are loaded during the current
 // step's products.  colsum != NULL: the blocks of the first M tile also sum
-// B (in FP32, before rounding) over their K range, in a fixed order.
+// B (in FP32, before rounding) over their K range, in a fixed order.  TB =
+// uint16_t: B is already BF16 (rounded by its producer as the staging would
+// round it), and no column sums are formed.
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 constexpr int WB = 128, WK = 32, WKP = WK + 8; // tile, K step, padded LDS row (bf16)
 
+template <typename TB>
 __global__ void __launch_bounds__(256)
     k_wgrad_bf16(int64_t M, int64_t N, int64_t K, int64_t kchunk, const uint16_t *__restrict__ A, int64_t lda,
-                 const float *__restrict__ B, float *__restrict__ C, float *__restrict__ colsum) {
+                 const TB *__restrict__ B, float *__restrict__ C, float *__restrict__ colsum) {
+    constexpr bool BF = sizeof(TB) == 2;
     __shared__ __attribute__((aligned(16))) uint16_t As[WB * WKP];
     __shared__ __attribute__((aligned(16))) uint16_t Bs[WB * WKP];
     __shared__ float cred[2][WB];
@@ -177,13 +183,13 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
     uint16_t ra[8][2];
-    float rb[8][2];
+    TB rb[8][2];
     const int64_t mc = m0 + c < M ? m0 + c : M - 1, nc = n0 + c < N ? n0 + c : N - 1;
     auto load = [&](int64_t k0) {
         if (k0 + WK <= kend) {
             // a whole step inside the range: fixed offsets from the step's rows
             const uint16_t *pa = A + (k0 + kh) * lda + mc;
-            const float *pb = B + (k0 + kh) * N + nc;
+            const TB *pb = B + (k0 + kh) * N + nc;
 #pragma unroll
             for (int r = 0; r < 8; ++r)
 #pragma unroll
@@ -205,7 +211,7 @@ __global__ void __launch_bounds__(256)
                 rb[r][h] = B[gk * N + nc];
             }
     };
-    const bool csum = colsum && blockIdx.x == 0;
+    const bool csum = !BF && colsum && blockIdx.x == 0;
     float cs = 0.f;
     if (kbeg < kend) load(kbeg);
     const bool mok = m0 + c < M, nok = n0 + c < N;
@@ -215,10 +221,15 @@ __global__ void __launch_bounds__(256)
             const int kk = kh + 4 * r;
             const bool k0ok = k0 + kk < kend, k1ok = k0 + kk + 1 < kend;
             const uint16_t a0 = (k0ok && mok) ? ra[r][0] : (uint16_t)0, a1 = (k1ok && mok) ? ra[r][1] : (uint16_t)0;
-            const float b0 = (k0ok && nok) ? rb[r][0] : 0.0f, b1 = (k1ok && nok) ? rb[r][1] : 0.0f;
             *(uint32_t *)&As[c * WKP + kk] = (uint32_t)a0 | ((uint32_t)a1 << 16);
-            *(uint32_t *)&Bs[c * WKP + kk] = pack_bf16x2_hw(b0, b1);
-            if (csum) cs += b0 + b1;
+            if constexpr (BF) {
+                const uint32_t b0 = (k0ok && nok) ? rb[r][0] : 0u, b1 = (k1ok && nok) ? rb[r][1] : 0u;
+                *(uint32_t *)&Bs[c * WKP + kk] = b0 | (b1 << 16);
+            } else {
+                const float b0 = (k0ok && nok) ? rb[r][0] : 0.0f, b1 = (k1ok && nok) ? rb[r][1] : 0.0f;
+                *(uint32_t *)&Bs[c * WKP + kk] = pack_bf16x2_hw(b0, b1);
+                if (csum) cs += b0 + b1;
+            }
         }
         __syncthreads();
         if (k0 + WK < kend) load(k0 + WK);
@@ -459,10 +470,12 @@ __global__ void k_adamw(int64_t n, float *__restrict__ th, float *__restrict__ m
     th[i] = t - lr * wd * t - lr * upd;
 }
 
+constexpr int DZ_MAX_GRID = 1024; // workgroups of a weight-stationary dZ launch (column-sum partials)
+
 struct BwdPlan {
     int64_t n, H, splits, kchunk, rsplits;
     int64_t wsplits, wkchunk; // the BF16 weight-gradient products: more, shorter splits
-    size_t off_dz2, off_dz1, off_part, off_cpart, total;
+    size_t off_dz2, off_dz1, off_part, off_cpart, off_dzc, total;
 };
 
 static BwdPlan plan_bwd(int H, int64_t n) {
@@ -486,7 +499,9 @@ static BwdPlan plan_bwd(int H, int64_t n) {
     p.off_part = up(p.off_dz1 + sizeof(float) * n * H);
     size_t part = sizeof(float) * ps * (size_t)((size_t)N_IN * H + (size_t)H * H + (size_t)H * N_OUT);
     p.off_cpart = up(p.off_part + part);
-    p.total = up(p.off_cpart + sizeof(float) * ps * (size_t)(2 * H + N_OUT));
+    // column-sum partials of the weight-stationary dZ products (dZ2, dZ1)
+    p.off_dzc = up(p.off_cpart + sizeof(float) * ps * (size_t)(2 * H + N_OUT));
+    p.total = up(p.off_dzc + sizeof(float) * 2 * (size_t)DZ_MAX_GRID * H);
     return p;
 }
 
@@ -502,13 +517,14 @@ static void gemm(int64_t M, int64_t N, int64_t K, int64_t splits, int64_t kchunk
     if (colsum) k_sum_splits<<<blocks_for(N, 64), 256, 0, s>>>(N, (int)splits, cpart, colsum);
 }
 
+template <typename TB>
 static void wgrad_bf16(int64_t M, int64_t N, int64_t K, int64_t splits, int64_t kchunk, const uint16_t *A,
-                       int64_t lda, const float *B, float *C, float *part, float *cpart, float *colsum,
+                       int64_t lda, const TB *B, float *C, float *part, float *cpart, float *colsum,
                        hipStream_t s) {
     dim3 grid((unsigned)((M + WB - 1) / WB), (unsigned)((N + WB - 1) / WB), (unsigned)splits);
-    k_wgrad_bf16<<<grid, 256, 0, s>>>(M, N, K, kchunk, A, lda, B, part, cpart);
+    k_wgrad_bf16<TB><<<grid, 256, 0, s>>>(M, N, K, kchunk, A, lda, B, part, colsum ? cpart : nullptr);
     k_sum_splits<<<blocks_for(M * N, 64), 256, 0, s>>>(M * N, (int)splits, part, C);
-    k_sum_splits<<<blocks_for(N, 64), 256, 0, s>>>(N, (int)splits, cpart, colsum);
+    if (colsum) k_sum_splits<<<blocks_for(N, 64), 256, 0, s>>>(N, (int)splits, cpart, colsum);
 }
 
 // dZ of a BF16 network of width N = 128 or 256, weight-stationary: the same
@@ -525,13 +541,22 @@ static void wgrad_bf16(int64_t M, int64_t N, int64_t K, int64_t splits, int64_t 
 // epilogue scales by (1 - s^2) and writes as one 16-byte store.  The K
 // chunks are summed in ascending order as in k_dz_bf16.
 constexpr int DZ_NW = 8, DZ_NT = 64 * DZ_NW;
-template <int NT, int NK, int MB>
+// TA: element type of A (float, or uint16_t for a BF16 dZ from the previous
+// product, staged as it is).  BOUT: C is written in BF16 (rounded as a
+// consumer's staging would round it) to Cb, and each workgroup also sums
+// its rows of C (FP32, before rounding) per unit into cpart[blockIdx.x][N]:
+// lanes accumulate over their rows in block order, the 16 lanes of a unit
+// group are then added by a fixed butterfly, so the partials (and their sum
+// in workgroup order) are run-to-run identical.
+template <int NT, int NK, int MB, typename TA, bool BOUT>
 __global__ void __launch_bounds__(DZ_NT)
-    k_dz_ws(int64_t M, int K, const float *__restrict__ A, int64_t lda, const float *__restrict__ W, int64_t ldw,
-            const uint16_t *__restrict__ S, int64_t lds_, float *__restrict__ C, int64_t ldc) {
+    k_dz_ws(int64_t M, int K, const TA *__restrict__ A, int64_t lda, const float *__restrict__ W, int64_t ldw,
+            const uint16_t *__restrict__ S, int64_t lds_, float *__restrict__ C, uint16_t *__restrict__ Cb,
+            int64_t ldc, float *__restrict__ cpart) {
     constexpr int N = 16 * NT * DZ_NW, KP = 32 * NK, PITCH = KP + 8; // LDS row pitch (bf16)
     constexpr int TPR = DZ_NT / MB, NJ = MB / 16;                    // staging threads per row; m tiles
     constexpr int EPT = KP / TPR;                                    // K elements a thread stages
+    constexpr bool ABF = sizeof(TA) == 2;
     static_assert(KP % TPR == 0 && EPT % 8 == 0, "staging splits a row into 16-byte pieces");
     __shared__ __attribute__((aligned(16))) uint16_t sA[2][MB * PITCH];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -556,17 +581,29 @@ __global__ void __launch_bounds__(DZ_NT)
         }
     // staging: thread tid takes row tid / TPR of the block, K (tid % TPR) EPT ..
     const int srow = tid / TPR, sk = (tid % TPR) * EPT;
-    const bool vec = K == KP && lda % 4 == 0 && ((uintptr_t)A & 15) == 0;
-    float ra[EPT];
+    const bool vec = K == KP && lda % (ABF ? 8 : 4) == 0 && ((uintptr_t)A & 15) == 0;
+    TA ra[EPT];
     auto load = [&](int64_t mb) {
         const int64_t m = mb * MB + srow;
         const int64_t mr = m < M ? m : M - 1;
-        const float *ar = A + mr * lda;
+        const TA *ar = A + mr * lda;
         if (vec) {
+            if constexpr (ABF) {
 #pragma unroll
-            for (int q = 0; q < EPT / 4; ++q) {
-                const float4 x = *(const float4 *)(ar + sk + 4 * q);
-                ra[4 * q] = x.x, ra[4 * q + 1] = x.y, ra[4 * q + 2] = x.z, ra[4 * q + 3] = x.w;
+                for (int q = 0; q < EPT / 8; ++q) {
+                    const u32x4_t x = *(const u32x4_t *)(ar + sk + 8 * q);
+#pragma unroll
+                    for (int h = 0; h < 4; ++h) {
+                        ra[8 * q + 2 * h] = (uint16_t)(x[h] & 0xffffu);
+                        ra[8 * q + 2 * h + 1] = (uint16_t)(x[h] >> 16);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < EPT / 4; ++q) {
+                    const float4 x = *(const float4 *)(ar + sk + 4 * q);
+                    ra[4 * q] = x.x, ra[4 * q + 1] = x.y, ra[4 * q + 2] = x.z, ra[4 * q + 3] = x.w;
+                }
             }
         } else {
 #pragma unroll
@@ -585,11 +622,15 @@ __global__ void __launch_bounds__(DZ_NT)
             for (int h = 0; h < 4; ++h) {
                 const int e = 8 * q + 2 * h;
                 const bool k0 = mok && sk + e < K, k1 = mok && sk + e + 1 < K;
-                pk[h] = pack_bf16x2_hw(k0 ? ra[e] : 0.0f, k1 ? ra[e + 1] : 0.0f);
+                if constexpr (ABF)
+                    pk[h] = (k0 ? (uint32_t)ra[e] : 0u) | ((k1 ? (uint32_t)ra[e + 1] : 0u) << 16);
+                else
+                    pk[h] = pack_bf16x2_hw(k0 ? ra[e] : 0.0f, k1 ? ra[e + 1] : 0.0f);
             }
             *(u32x4_t *)&sA[buf][srow * PITCH + sk + 8 * q] = pk;
         }
     };
+    float cs[NT][4] = {};
     const int64_t nmb = (M + MB - 1) / MB;
     int64_t mb = blockIdx.x;
     int buf = 0;
@@ -636,40 +677,58 @@ __global__ void __launch_bounds__(DZ_NT)
             for (int j = 0; j < NJ; ++j) {
                 const int64_t m = mb * MB + 16 * j + i16;
                 if (m >= M) continue;
-                const float s0 = bf16_to_f32((uint16_t)(sv[t][j].x & 0xffffu));
-                const float s1 = bf16_to_f32((uint16_t)(sv[t][j].x >> 16));
-                const float s2 = bf16_to_f32((uint16_t)(sv[t][j].y & 0xffffu));
-                const float s3 = bf16_to_f32((uint16_t)(sv[t][j].y >> 16));
-                *(float4 *)(C + m * ldc + nb + 16 * t + 4 * g) =
-                    make_float4(acc[t][j][0] * (1.0f - s0 * s0), acc[t][j][1] * (1.0f - s1 * s1),
-                                acc[t][j][2] * (1.0f - s2 * s2), acc[t][j][3] * (1.0f - s3 * s3));
+                float v[4];
+                v[0] = bf16_to_f32((uint16_t)(sv[t][j].x & 0xffffu));
+                v[1] = bf16_to_f32((uint16_t)(sv[t][j].x >> 16));
+                v[2] = bf16_to_f32((uint16_t)(sv[t][j].y & 0xffffu));
+                v[3] = bf16_to_f32((uint16_t)(sv[t][j].y >> 16));
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[e] = acc[t][j][e] * (1.0f - v[e] * v[e]);
+                if constexpr (BOUT) {
+                    *(uint2 *)(Cb + m * ldc + nb + 16 * t + 4 * g) =
+                        make_uint2(pack_bf16x2_hw(v[0], v[1]), pack_bf16x2_hw(v[2], v[3]));
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) cs[t][e] += v[e];
+                } else {
+                    *(float4 *)(C + m * ldc + nb + 16 * t + 4 * g) = make_float4(v[0], v[1], v[2], v[3]);
+                }
             }
         if (next < nmb) store(buf ^ 1, next);
     }
+    if constexpr (BOUT) {
+        // the 16 rows a unit's lanes hold, by a fixed butterfly
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                float x = cs[t][e];
+                x += __shfl_xor(x, 8, 16);
+                x += __shfl_xor(x, 4, 16);
+                x += __shfl_xor(x, 2, 16);
+                x += __shfl_xor(x, 1, 16);
+                if (i16 == 0) cpart[(int64_t)blockIdx.x * N + nb + 16 * t + 4 * g + e] = x;
+            }
+    }
 }
 
-// The weight-stationary dZ product where its shapes are built (width 128 or
-// 256, K = 81 or the width, 16-byte aligned rows of S and C): true if launched.
-template <int NT, int NK, int MB>
-static void dz_ws_launch(int64_t M, int K, const float *A, int64_t lda, const float *W, int64_t ldw, const uint16_t *S,
-                         int64_t lds_, float *C, int64_t ldc, hipStream_t s) {
+// One weight-stationary dZ product on a persistent grid of at most one
+// workgroup per compute unit; returns the grid size (BOUT: the number of
+// column-sum partials written to cpart, one row of N per workgroup).
+template <int NT, int NK, int MB, typename TA, bool BOUT>
+static int dz_ws_launch(int64_t M, int K, const TA *A, int64_t lda, const float *W, int64_t ldw, const uint16_t *S,
+                        int64_t lds_, float *C, uint16_t *Cb, int64_t ldc, float *cpart, hipStream_t s) {
     const int64_t nmb = (M + MB - 1) / MB;
-    const int64_t cap = (int64_t)device_cus();
-    k_dz_ws<NT, NK, MB><<<(unsigned)(nmb < cap ? nmb : cap), DZ_NT, 0, s>>>(M, K, A, lda, W, ldw, S, lds_, C, ldc);
+    int64_t cap = (int64_t)device_cus();
+    if (cap > DZ_MAX_GRID) cap = DZ_MAX_GRID;
+    const unsigned grid = (unsigned)(nmb < cap ? nmb : cap);
+    k_dz_ws<NT, NK, MB, TA, BOUT><<<grid, DZ_NT, 0, s>>>(M, K, A, lda, W, ldw, S, lds_, C, Cb, ldc, cpart);
+    return (int)grid;
 }
 
-static bool dz_ws(int64_t M, int64_t N, int64_t K, const float *A, int64_t lda, const float *W, int64_t ldw,
-                  const uint16_t *S, int64_t lds_, float *C, int64_t ldc, hipStream_t s) {
-    if (M <= 0 || lds_ % 4 || ldc % 4 || ((uintptr_t)S & 7) || ((uintptr_t)C & 15)) return false;
-    // K = 81 takes four chunks (the fourth is zeros), so a staging thread's
-    // share of a row is whole 16-byte pieces
-    // (blocks of 32 rows where the operand fragments take the most registers)
-    if (N == 256 && K == N_OUT) dz_ws_launch<2, 4, 64>(M, (int)K, A, lda, W, ldw, S, lds_, C, ldc, s);
-    else if (N == 256 && K == 256) dz_ws_launch<2, 8, 32>(M, (int)K, A, lda, W, ldw, S, lds_, C, ldc, s);
-    else if (N == 128 && K == N_OUT) dz_ws_launch<1, 4, 64>(M, (int)K, A, lda, W, ldw, S, lds_, C, ldc, s);
-    else if (N == 128 && K == 128) dz_ws_launch<1, 4, 64>(M, (int)K, A, lda, W, ldw, S, lds_, C, ldc, s);
-    else return false;
-    return true;
+// The shapes the weight-stationary dZ products are built for: width 128 or
+// 256 (K = 81, then the width), 8-byte aligned rows of S and of the BF16 dZ.
+static bool dz_ws_shape(int64_t M, int64_t N, const void *S, int64_t lds_, int64_t ldc) {
+    return M > 0 && (N == 128 || N == 256) && lds_ % 4 == 0 && ldc % 8 == 0 && ((uintptr_t)S & 7) == 0;
 }
 
 template <typename TX, typename TS>
@@ -682,14 +741,39 @@ static void backward_impl(const BwdPlan &p, const TX *X, int64_t ldx, const TS *
     float *part = (float *)(ws + p.off_part);
     float *cpart = (float *)(ws + p.off_cpart);
     const TS *A1 = saved, *A2 = saved + n * H;
+    if constexpr (sizeof(TS) == 2 && sizeof(TX) == 2) {
+        if (dz_ws_shape(n, H, A2, H, H)) {
+            // BF16 network of width 128 or 256: the weight-stationary dZ
+            // products keep dZ2 and dZ1 in BF16 (as every consumer stages
+            // them) and sum their columns for the bias gradients on the way
+            uint16_t *dz2b = (uint16_t *)(ws + p.off_dz2), *dz1b = (uint16_t *)(ws + p.off_dz1);
+            float *cs2 = (float *)(ws + p.off_dzc), *cs1 = cs2 + (size_t)DZ_MAX_GRID * H;
+            const uint16_t *S2 = (const uint16_t *)A2, *S1 = (const uint16_t *)A1;
+            int g2, g1;
+            if (H == 256) {
+                g2 = dz_ws_launch<2, 4, 64, float, true>(n, N_OUT, dY, N_OUT, W3, N_OUT, S2, H, nullptr, dz2b, H, cs2,
+                                                         s);
+                g1 = dz_ws_launch<2, 8, 32, uint16_t, true>(n, (int)H, dz2b, H, W2, H, S1, H, nullptr, dz1b, H, cs1,
+                                                            s);
+            } else {
+                g2 = dz_ws_launch<1, 4, 64, float, true>(n, N_OUT, dY, N_OUT, W3, N_OUT, S2, H, nullptr, dz2b, H, cs2,
+                                                         s);
+                g1 = dz_ws_launch<1, 4, 64, uint16_t, true>(n, (int)H, dz2b, H, W2, H, S1, H, nullptr, dz1b, H, cs1,
+                                                            s);
+            }
+            k_sum_splits<<<blocks_for(H, 64), 256, 0, s>>>(H, g2, cs2, db[1]);
+            k_sum_splits<<<blocks_for(H, 64), 256, 0, s>>>(H, g1, cs1, db[0]);
+            wgrad_bf16<float>(H, N_OUT, n, p.wsplits, p.wkchunk, A2, H, dY, dW[2], part, cpart, db[2], s);
+            wgrad_bf16<uint16_t>(H, H, n, p.wsplits, p.wkchunk, A1, H, dz2b, dW[1], part, cpart, nullptr, s);
+            wgrad_bf16<uint16_t>(N_IN, H, n, p.wsplits, p.wkchunk, X, ldx, dz1b, dW[0], part, cpart, nullptr, s);
+            return;
+        }
+    }
     if constexpr (sizeof(TS) == 2) {
         // BF16 network: dZ products on BF16 MFMA (W3 is [H][81], W2 [H][H])
-        // (weight-stationary where that kernel is built)
         dim3 grid((unsigned)((n + WB - 1) / WB), (unsigned)((H + WB - 1) / WB));
-        if (!dz_ws(n, H, N_OUT, dY, N_OUT, W3, N_OUT, (const uint16_t *)A2, H, dz2, H, s))
-            k_dz_bf16<<<grid, 256, 0, s>>>(n, H, N_OUT, dY, N_OUT, W3, N_OUT, (const uint16_t *)A2, H, dz2, H);
-        if (!dz_ws(n, H, H, dz2, H, W2, H, (const uint16_t *)A1, H, dz1, H, s))
-            k_dz_bf16<<<grid, 256, 0, s>>>(n, H, H, dz2, H, W2, H, (const uint16_t *)A1, H, dz1, H);
+        k_dz_bf16<<<grid, 256, 0, s>>>(n, H, N_OUT, dY, N_OUT, W3, N_OUT, (const uint16_t *)A2, H, dz2, H);
+        k_dz_bf16<<<grid, 256, 0, s>>>(n, H, H, dz2, H, W2, H, (const uint16_t *)A1, H, dz1, H);
     } else {
         // dZ2 = (dY W3^T) (.) (1 - A2^2): W3 is [H][81] -> op(B)[k=o][n=h] = W3[h][o]
         gemm<false, true, float, float, TS, true>(n, H, N_OUT, 1, N_OUT + BK, dY, N_OUT, W3, N_OUT, dz2, H,
@@ -702,9 +786,9 @@ static void backward_impl(const BwdPlan &p, const TX *X, int64_t ldx, const TS *
     // of dY, dZ2, dZ1) come from the same staged tiles
     if constexpr (sizeof(TS) == 2 && sizeof(TX) == 2) {
         // BF16 network: BF16 products with FP32 accumulation
-        wgrad_bf16(H, N_OUT, n, p.wsplits, p.wkchunk, A2, H, dY, dW[2], part, cpart, db[2], s);
-        wgrad_bf16(H, H, n, p.wsplits, p.wkchunk, A1, H, dz2, dW[1], part, cpart, db[1], s);
-        wgrad_bf16(N_IN, H, n, p.wsplits, p.wkchunk, X, ldx, dz1, dW[0], part, cpart, db[0], s);
+        wgrad_bf16<float>(H, N_OUT, n, p.wsplits, p.wkchunk, A2, H, dY, dW[2], part, cpart, db[2], s);
+        wgrad_bf16<float>(H, H, n, p.wsplits, p.wkchunk, A1, H, dz2, dW[1], part, cpart, db[1], s);
+        wgrad_bf16<float>(N_IN, H, n, p.wsplits, p.wkchunk, X, ldx, dz1, dW[0], part, cpart, db[0], s);
     } else {
         gemm<true, false, TS, float, float, false>(H, N_OUT, n, p.splits, p.kchunk, A2, H, dY, N_OUT, dW[2],
                                                    N_OUT, part, nullptr, 0, s, cpart, db[2]);
