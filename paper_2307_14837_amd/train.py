@@ -85,10 +85,19 @@ class PatchTrainer:
         self.hidden = int(np.shape(params[0])[1])
         self.lr, self.wd, self.betas, self.eps = lr, weight_decay, betas, eps
         f32 = dict(dtype=torch.float32, device=self.dev)
-        self.theta = [torch.as_tensor(np.asarray(p, np.float32)).contiguous().view(-1).to(self.dev) for p in params]
-        self.m = [torch.zeros_like(t) for t in self.theta]
-        self.v = [torch.zeros_like(t) for t in self.theta]
-        self.grad = [torch.zeros_like(t) for t in self.theta]
+        # parameters, moments and gradients are views into flat buffers (each
+        # tensor padded to 256 bytes; the padding stays zero under AdamW), so
+        # one AdamW launch updates them all
+        sizes = [int(np.prod(np.shape(p))) for p in params]
+        offs, total = [], 0
+        for n in sizes:
+            offs.append(total)
+            total += (n + 63) // 64 * 64
+        self._flat = {k: torch.zeros(total, **f32) for k in ("theta", "m", "v", "grad")}
+        views = lambda k: [self._flat[k][o:o + n] for o, n in zip(offs, sizes)]
+        self.theta, self.m, self.v, self.grad = views("theta"), views("m"), views("v"), views("grad")
+        for t, p in zip(self.theta, params):
+            t.copy_(torch.as_tensor(np.asarray(p, np.float32)).reshape(-1))
         self.t = 0
         H = self.hidden
         self.Wp = [torch.zeros(L.packed_bytes(self.dtype, H, l), dtype=torch.uint8, device=self.dev) for l in range(3)]
@@ -117,9 +126,9 @@ class PatchTrainer:
                                [self.grad[0], self.grad[2], self.grad[4]],
                                [self.grad[1], self.grad[3], self.grad[5]], self.ws, stream=stream)
         self.t += 1
-        for p, m, v, g in zip(self.theta, self.m, self.v, self.grad):
-            L.dnnmg_adamw_step(p, m, v, g, self.lr, self.t, b1=self.betas[0], b2=self.betas[1], eps=self.eps,
-                               wd=self.wd, stream=stream)
+        f = self._flat
+        L.dnnmg_adamw_step(f["theta"], f["m"], f["v"], f["grad"], self.lr, self.t, b1=self.betas[0], b2=self.betas[1],
+                           eps=self.eps, wd=self.wd, stream=stream)
         self._repack(stream)
 
     def loss(self, n):
