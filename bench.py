@@ -61,6 +61,8 @@ def parse():
                     help="run only the training-step variant for --steps steps (for rocprofv3)")
     ap.add_argument("--profile-paper-net", action="store_true",
                     help="run only the paper network form's step variant (for rocprofv3)")
+    ap.add_argument("--profile-levels", action="store_true",
+                    help="run only the two-level prediction's step variant (for rocprofv3)")
     ap.add_argument("--cpu-worker", type=int, default=None, help=argparse.SUPPRESS)
     return ap.parse_args()
 
@@ -954,6 +956,9 @@ def main():
         return
     if args.profile_paper_net:
         print(json.dumps(run_paper_network(args.steps, args.warmup)), flush=True)
+        return
+    if args.profile_levels:
+        print(json.dumps(run_levels("fp8", args.steps, args.warmup)), flush=True)
         return
     if args.profile_step:
         profile_step(args.steps)

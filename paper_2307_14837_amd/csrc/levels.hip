@@ -82,6 +82,49 @@ __global__ void __launch_bounds__(256) k_prolong2(Mesh m, Mesh m2, int ncomp, co
     xf[t] = interp2(v1, off1[0], off1[1], off1[2]);
 }
 
+// Row form of k_prolong2 (the same values, bit for bit): one workgroup per
+// level L + 2 lattice row (j, k) and component.  The level L + 1 values of
+// the (up to) 2 x 2 level L + 1 rows above it are formed once per x node
+// (interp2 of their 8 level L corners, as k_prolong2 forms them per node)
+// into LDS; each fine node of the row then interpolates its 8 level L + 1
+// values from there.  LDS: 4 x (level L + 1 nodes along x) floats.
+__global__ void __launch_bounds__(256) k_prolong2_rows(Mesh m, Mesh m2, const double *__restrict__ xc,
+                                                       float *__restrict__ xf) {
+    extern __shared__ float sV[]; // [y, z slot][level L + 1 x node]
+    const int comp = blockIdx.y;
+    const int64_t row = blockIdx.x;
+    const int j = (int)(row % m2.nf[1]), k = (int)(row / m2.nf[1]);
+    int lo1y, hi1y, offy, lo1z, hi1z, offz;
+    coarse_pair(j, m2.nc[1], m2.per[1], lo1y, hi1y, offy);
+    coarse_pair(k, m2.nc[2], m2.per[2], lo1z, hi1z, offz);
+    const int nc1x = m2.nc[0];
+    const double *x = xc + (int64_t)comp * m.n_coarse;
+    for (int t = threadIdx.x; t < 4 * nc1x; t += blockDim.x) {
+        const int yz = t / nc1x, x1 = t - yz * nc1x;
+        const int c1[3] = {x1, (yz & 1) ? hi1y : lo1y, (yz & 2) ? hi1z : lo1z};
+        int lo0[3], hi0[3], off0[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) coarse_pair(c1[a], m.nc[a], m.per[a], lo0[a], hi0[a], off0[a]);
+        float v0[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int ii = (r & 1) ? hi0[0] : lo0[0], jj = (r & 2) ? hi0[1] : lo0[1], kk = (r & 4) ? hi0[2] : lo0[2];
+            v0[r] = (float)x[ii + (int64_t)m.nc[0] * (jj + (int64_t)m.nc[1] * kk)];
+        }
+        sV[t] = interp2(v0, off0[0], off0[1], off0[2]);
+    }
+    __syncthreads();
+    float *out = xf + (int64_t)comp * m2.n_fine + (int64_t)m2.nf[0] * (j + (int64_t)m2.nf[1] * k);
+    for (int i = threadIdx.x; i < m2.nf[0]; i += blockDim.x) {
+        int lo1x, hi1x, offx;
+        coarse_pair(i, m2.nc[0], m2.per[0], lo1x, hi1x, offx);
+        float v1[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v1[q] = sV[(q >> 1) * nc1x + ((q & 1) ? hi1x : lo1x)];
+        out[i] = interp2(v1, offx, offy, offz);
+    }
+}
+
 // --------------------------------------------------- two-level restriction --
 // bc(I) = sum over fine indices i = 4I + d, |d| <= 3, of prod_a (1 - |d_a|/4)
 // bf(i) (the transpose of the two-level Q1 prolongation), FP64 accumulation;
@@ -123,6 +166,68 @@ __global__ void __launch_bounds__(256) k_restrict2(Mesh m, Mesh m2, int ncomp, c
             acc += w[1][bb] * w[2][c] * row;
         }
     bc[t] = acc;
+}
+
+// Row form of k_restrict2: one workgroup per level L lattice row (J, K) and
+// component.  Every level L + 2 node along x is first summed over the row's
+// 7 x 7 (y, z) stencil (weights and wrapping as in k_restrict2, absent nodes
+// read at a present one with weight 0; the 49 loads requested together)
+// into LDS in FP64, then each coarse node of the row takes its 7 x terms
+// from there.  The same weights as k_restrict2, summed (y, z) first.  LDS:
+// the level L + 2 nodes along x, in doubles.
+__global__ void __launch_bounds__(256) k_restrict2_rows(Mesh m, Mesh m2, const float *__restrict__ bf,
+                                                        double *__restrict__ bc) {
+    extern __shared__ double sT[];
+    const int comp = blockIdx.y;
+    const int64_t row = blockIdx.x;
+    const int J = (int)(row % m.nc[1]), K = (int)(row / m.nc[1]);
+    const int C[2] = {J, K};
+    int fi[2][7];
+    double w[2][7];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int d = 0; d < 7; ++d) {
+            int q = 4 * C[a] + d - 3;
+            bool ok = true;
+            if (m2.per[a + 1]) q = wrap(q, m2.nf[a + 1], 1);
+            else if (q < 0 || q >= m2.nf[a + 1]) { ok = false; q = 4 * C[a]; }
+            fi[a][d] = q;
+            w[a][d] = ok ? 1.0 - 0.25 * (double)(d > 3 ? d - 3 : 3 - d) : 0.0;
+        }
+    const float *b = bf + (int64_t)comp * m2.n_fine;
+    const int nf0 = m2.nf[0];
+    for (int i = threadIdx.x; i < nf0; i += blockDim.x) {
+        float v[7][7];
+#pragma unroll
+        for (int c = 0; c < 7; ++c)
+#pragma unroll
+            for (int bb = 0; bb < 7; ++bb) v[c][bb] = b[i + (int64_t)nf0 * (fi[0][bb] + (int64_t)m2.nf[1] * fi[1][c])];
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < 7; ++c) {
+            double col = 0.0;
+#pragma unroll
+            for (int bb = 0; bb < 7; ++bb) col += w[0][bb] * (double)v[c][bb];
+            acc += w[1][c] * col;
+        }
+        sT[i] = acc;
+    }
+    __syncthreads();
+    double *out = bc + (int64_t)comp * m.n_coarse + (int64_t)m.nc[0] * (J + (int64_t)m.nc[1] * K);
+    for (int I = threadIdx.x; I < m.nc[0]; I += blockDim.x) {
+        double acc = 0.0;
+#pragma unroll
+        for (int d = 0; d < 7; ++d) {
+            int q = 4 * I + d - 3;
+            bool ok = true;
+            if (m2.per[0]) q = wrap(q, nf0, 1);
+            else if (q < 0 || q >= nf0) { ok = false; q = 4 * I; }
+            const double wx = ok ? 1.0 - 0.25 * (double)(d > 3 ? d - 3 : 3 - d) : 0.0;
+            acc += wx * sT[q];
+        }
+        out[I] = acc;
+    }
 }
 
 // ------------------------------------------------------- dof map, valence --
@@ -427,7 +532,13 @@ extern "C" int dnnmg_prolong_levels(const dnnmg_box *box, int levels, int ncomp,
     if ((rc = level2_meshes(box, &m, &m2))) return rc;
     if (ncomp < 1 || ncomp > 4) return fail(DNNMG_ERR_ARG, "dnnmg_prolong_levels: ncomp %d not in 1..4", ncomp);
     if (!xc || !xf) return fail(DNNMG_ERR_ARG, "dnnmg_prolong_levels: NULL pointer");
-    k_prolong2<<<blocks_for((int64_t)ncomp * m2.n_fine, 256), 256, 0, STREAM>>>(m, m2, ncomp, xc, xf);
+    // the row form where its LDS row fits 64 KB, else the per-node form
+    const size_t lds = sizeof(float) * 4 * (size_t)m2.nc[0];
+    if (lds <= 65536)
+        k_prolong2_rows<<<dim3((unsigned)((int64_t)m2.nf[1] * m2.nf[2]), (unsigned)ncomp), 256, lds, STREAM>>>(m, m2, xc,
+                                                                                                          xf);
+    else
+        k_prolong2<<<blocks_for((int64_t)ncomp * m2.n_fine, 256), 256, 0, STREAM>>>(m, m2, ncomp, xc, xf);
     return hip_check(hipGetLastError(), "dnnmg_prolong_levels launch");
 }
 
@@ -440,7 +551,13 @@ extern "C" int dnnmg_restrict_levels(const dnnmg_box *box, int levels, int ncomp
     if ((rc = level2_meshes(box, &m, &m2))) return rc;
     if (ncomp < 1 || ncomp > 4) return fail(DNNMG_ERR_ARG, "dnnmg_restrict_levels: ncomp %d not in 1..4", ncomp);
     if (!bf || !bc) return fail(DNNMG_ERR_ARG, "dnnmg_restrict_levels: NULL pointer");
-    k_restrict2<<<blocks_for((int64_t)ncomp * m.n_coarse, 256), 256, 0, STREAM>>>(m, m2, ncomp, bf, bc);
+    // the row form where its LDS row fits 64 KB, else the per-node form
+    const size_t lds = sizeof(double) * (size_t)m2.nf[0];
+    if (lds <= 65536)
+        k_restrict2_rows<<<dim3((unsigned)((int64_t)m.nc[1] * m.nc[2]), (unsigned)ncomp), 256, lds, STREAM>>>(m, m2, bf,
+                                                                                                         bc);
+    else
+        k_restrict2<<<blocks_for((int64_t)ncomp * m.n_coarse, 256), 256, 0, STREAM>>>(m, m2, ncomp, bf, bc);
     return hip_check(hipGetLastError(), "dnnmg_restrict_levels launch");
 }
 
