@@ -63,6 +63,8 @@ def parse():
                     help="run only the paper network form's step variant (for rocprofv3)")
     ap.add_argument("--profile-levels", action="store_true",
                     help="run only the two-level prediction's step variant (for rocprofv3)")
+    ap.add_argument("--profile-batched", action="store_true",
+                    help="run only the batched step of the 32 uneven boxes (for rocprofv3)")
     ap.add_argument("--cpu-worker", type=int, default=None, help=argparse.SUPPRESS)
     return ap.parse_args()
 
@@ -959,6 +961,9 @@ def main():
         return
     if args.profile_levels:
         print(json.dumps(run_levels("fp8", args.steps, args.warmup)), flush=True)
+        return
+    if args.profile_batched:
+        print(json.dumps(run_batched("bf16", args.steps, args.warmup)), flush=True)
         return
     if args.profile_step:
         profile_step(args.steps)

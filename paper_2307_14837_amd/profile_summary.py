@@ -60,14 +60,18 @@ def find(avgs, needle):
     return hits[0]
 
 
-def trace_stats(path, after):
+def trace_stats(path, after, tail=0):
     """kernel_stats-like rows from a kernel_trace.csv, over the dispatches
     after the last one whose name contains `after` (the setup before the
-    measured section, e.g. network training, is left out)."""
+    measured section, e.g. network training, is left out), or over the last
+    `tail` dispatches when tail > 0."""
     rows = list(csv.DictReader(open(path)))
     rows.sort(key=lambda r: int(r["Start_Timestamp"]))
-    last = max((i for i, r in enumerate(rows) if after in r["Kernel_Name"]), default=-1)
-    rows = rows[last + 1:]
+    if tail > 0:
+        rows = rows[-tail:]
+    else:
+        last = max((i for i, r in enumerate(rows) if after in r["Kernel_Name"]), default=-1)
+        rows = rows[last + 1:]
     per = defaultdict(list)
     for r in rows:
         per[r["Kernel_Name"]].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
@@ -80,7 +84,7 @@ def trace_stats(path, after):
 
 
 def stats(a):
-    rows = trace_stats(a.trace, a.after) if a.trace else list(csv.DictReader(open(a.csv)))
+    rows = trace_stats(a.trace, a.after, a.last) if a.trace else list(csv.DictReader(open(a.csv)))
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     lines = [f"# {a.title}", "", "Command:", "", "```", a.command, "```", "",
              "| kernel | calls | avg us | min us | max us | share % |", "|---|---:|---:|---:|---:|---:|"]
@@ -119,6 +123,7 @@ def main():
     sp.add_argument("--csv", default=None, help="kernel_stats.csv of a --stats run")
     sp.add_argument("--trace", default=None, help="kernel_trace.csv (with --after)")
     sp.add_argument("--after", default="", help="count only dispatches after the last kernel matching this")
+    sp.add_argument("--last", type=int, default=0, help="count only the last N dispatches (with --trace)")
     sp.add_argument("--out", required=True)
     sp.add_argument("--command", default="")
     sp.add_argument("--title", default="rocprofv3 kernel statistics")
