@@ -454,7 +454,9 @@ def run_batched(dtype, steps, warmup):
     t = time_graph(bs, steps, warmup)
     npch, nf = bs.plan.n_patches, bs.plan.n_fine
     return {"workload": "cfg3_32_periodic_boxes", "boxes": len(boxes), "patches": npch, "fine_nodes": nf,
-            "dtype": dtype, "fused_batched": True, "autotuned": {"patches_per_tile": ppt, "grid": grid},
+            "dtype": dtype, "fused_batched": True,
+            "autotuned": {"patches_per_tile": ppt, "grid": grid,
+                          "extension": "tiled" if bs.plan.scatter_form() == 2 else "per node"},
             "ms_per_step": t["ms"], "median_ms": t["median_ms"], "patches_per_s": npch / (t["ms"] * 1e-3),
             "fine_dof_per_s": 4 * nf / (t["ms"] * 1e-3)}
 

@@ -416,12 +416,21 @@ int dnnmg_plan_sizes(const dnnmg_plan *plan, int64_t *n_fine, int64_t *n_coarse,
  * 32 until tuned) and the persistent grid size (0 = one workgroup per tile). */
 int dnnmg_plan_choice(const dnnmg_plan *plan, int *patches_per_tile, int *grid);
 
+/* Form of the plan's extension stage (eq. defL; the same sums in either
+ * form, bit for bit): DNNMG_SCATTER_NODES (one thread per fine node) or
+ * DNNMG_SCATTER_TILED (workgroups over the extension tiles of all boxes,
+ * patch rows staged in LDS; the default until tuned).  *form receives it;
+ * the setter fixes it (any other value: DNNMG_ERR_ARG). */
+int dnnmg_plan_scatter_form(const dnnmg_plan *plan, int *form);
+int dnnmg_plan_set_scatter_form(dnnmg_plan *plan, int form);
+
 /* One correction step (Algorithm 1 after the coarse solve) for every box of
  * the plan in five kernel launches, independent of the number of boxes (not
  * one fused launch): prolongation fused with the residual (as
  * dnnmg_prolong_residual), gather + network in one persistent launch over
  * the patch tiles of all boxes, extension giving the corrected iterate
- * (v~ + d, p~), right-hand side, restriction (FP64).
+ * (v~ + d, p~; per node or tiled, dnnmg_plan_scatter_form), right-hand
+ * side, restriction (FP64).
  * Buffers (batch layout): xc FP64 [4 comps], vprev FP32 [3], xt, r, xcorr,
  * b FP32 [4], Y FP32 [patches][81], bc FP64 [4].  No forcing.  The step can
  * be captured in a HIP graph. */
@@ -446,7 +455,9 @@ int dnnmg_batch_rhs(const dnnmg_plan *plan, const float *v, float *b, void *stre
  * on the batch's own inputs for every candidate (16, 32 or 64 patches per
  * workgroup tile, as built for the network's type and width; one workgroup
  * per tile or a persistent grid of 1, 2 or 4 workgroups per compute unit)
- * with `reps` launches each, and keeps the fastest. */
+ * with `reps` launches each, and keeps the fastest; then times the
+ * extension stage in both forms (per node, tiled) on the network's outputs
+ * and keeps the faster.  Overwrites xt, r, Y and xcorr. */
 int dnnmg_plan_autotune(dnnmg_plan *plan, const dnnmg_mlp *net, const float *shift, const float *inv_scale,
                         const double *xc, const float *vprev, float *xt, float *r, float *Y, float *xcorr,
                         float *b, double *bc, int reps, void *stream);

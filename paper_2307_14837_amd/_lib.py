@@ -142,6 +142,8 @@ _sig("dnnmg_plan_create", [c_vp, ctypes.c_int, _P(NS), c_vp, c_sz, _P(c_vp), c_v
 _sig("dnnmg_plan_destroy", [c_vp])
 _sig("dnnmg_plan_sizes", [c_vp, _P(c_i64), _P(c_i64), _P(c_i64)])
 _sig("dnnmg_plan_choice", [c_vp, _P(ctypes.c_int), _P(ctypes.c_int)])
+_sig("dnnmg_plan_scatter_form", [c_vp, _P(ctypes.c_int)])
+_sig("dnnmg_plan_set_scatter_form", [c_vp, ctypes.c_int])
 _sig("dnnmg_batch_step", [c_vp, _P(MLP), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp])
 _sig("dnnmg_batch_step_b", [c_vp, _P(MLP), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp])
 _sig("dnnmg_batch_rhs", [c_vp, c_vp, c_vp, c_vp])
@@ -194,7 +196,7 @@ EXPORTS = [
     "dnnmg_mse_grad", "dnnmg_mse_grad_loss", "dnnmg_patch_backward_workspace", "dnnmg_patch_backward", "dnnmg_adamw_step",
     "dnnmg_vanka_workspace", "dnnmg_vanka_sweeps", "dnnmg_fallback_workspace", "dnnmg_fallback",
     "dnnmg_patch_gather_forward", "dnnmg_plan_workspace", "dnnmg_plan_create", "dnnmg_plan_destroy",
-    "dnnmg_plan_sizes", "dnnmg_plan_choice", "dnnmg_batch_step", "dnnmg_plan_autotune",
+    "dnnmg_plan_sizes", "dnnmg_plan_choice", "dnnmg_plan_scatter_form", "dnnmg_plan_set_scatter_form", "dnnmg_batch_step", "dnnmg_plan_autotune",
     "dnnmg_batch_step_b", "dnnmg_batch_rhs", "dnnmg_norm2_pair_f64", "dnnmg_mlp_prepare",
     "dnnmg_graph_capture_begin", "dnnmg_graph_capture_end", "dnnmg_graph_replay", "dnnmg_graph_destroy",
     "dnnmg_mlp_packed_bytes_io", "dnnmg_mlp_pack_io", "dnnmg_mlp_prepare_io", "dnnmg_level_sizes",
@@ -757,6 +759,14 @@ class Plan:
         a, b = ctypes.c_int(), ctypes.c_int()
         _check(_lib.dnnmg_plan_choice(self.handle, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
+
+    def scatter_form(self):
+        f = ctypes.c_int()
+        _check(_lib.dnnmg_plan_scatter_form(self.handle, ctypes.byref(f)))
+        return f.value
+
+    def set_scatter_form(self, form):
+        _check(_lib.dnnmg_plan_set_scatter_form(self.handle, int(form)))
 
     def _args(self, net, shift, inv_scale, bufs):
         nf, nc, npch = self.n_fine, self.n_coarse, self.n_patches

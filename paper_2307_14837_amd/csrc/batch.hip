@@ -3,9 +3,10 @@
 // (BoxDesc); one step is five kernel launches whatever the number of boxes:
 //   prolongation fused with the residual, fused gather + network
 //   (persistent: blocks walk the patch tiles of all boxes), extension
-//   (v~ + d), right-hand side, restriction.
+//   (v~ + d, per node or in LDS-staged tiles), right-hand side, restriction.
 // The plan keeps the layout, the launch geometry and the tuned choices of
-// the network stage (patches per workgroup tile, persistent grid size).
+// the network stage (patches per workgroup tile, persistent grid size) and
+// of the extension (per node or tiled).
 #include <vector>
 
 #include "common.hpp"
@@ -24,6 +25,9 @@ void prolong_residual_b_batch_launch(const BoxDesc *D, int nbox, int64_t nfull, 
                                      const float *b, float *xt, float *r, hipStream_t s);
 void scatter_batch_launch(const BoxDesc *D, int nbox, int64_t nblk, const float *Y, const float *vbase, float *xc,
                           hipStream_t s);
+int64_t scatter_tiles(const Mesh &m);
+void scatter_tiled_batch_launch(const BoxDesc *D, int nbox, int64_t ntiles, const float *Y, const float *vbase,
+                                float *xc, hipStream_t s);
 
 } // namespace dnnmg
 
@@ -35,16 +39,17 @@ struct dnnmg_plan {
     std::vector<BoxDesc> desc;
     BoxDesc *d_desc;   // in the caller's workspace
     int64_t n_fine, n_coarse, n_patches;
-    int64_t blk_fine, blk_coarse, tiles_full, tiles_part, ptiles;
+    int64_t blk_fine, blk_coarse, tiles_full, tiles_part, ptiles, stiles;
     int pt;            // tuned: patches per network tile / 16
     int grid;          // tuned: persistent grid of the network stage (0 = one block per tile)
+    int scatter_form;  // tuned: extension per node or in LDS-staged tiles (DNNMG_SCATTER_*)
 };
 
 static size_t up256(size_t b) { return (b + 255) / 256 * 256; }
 
 static int layout(dnnmg_plan *p, const dnnmg_box *boxes, int nbox) {
     p->desc.resize(nbox);
-    int64_t of = 0, oc = 0, op = 0, bf = 0, bc = 0, bt = 0, bpart = 0, bp = 0;
+    int64_t of = 0, oc = 0, op = 0, bf = 0, bc = 0, bt = 0, bpart = 0, bp = 0, bs = 0;
     for (int i = 0; i < nbox; ++i) {
         BoxDesc &d = p->desc[i];
         int rc = make_mesh(&boxes[i], &d.m);
@@ -64,6 +69,7 @@ static int layout(dnnmg_plan *p, const dnnmg_box *boxes, int nbox) {
         d.blk_full = bt;
         d.blk_part = bpart;
         d.blk_ptile = bp;
+        d.blk_stile = bs;
         of += d.m.n_fine;
         oc += d.m.n_coarse;
         op += d.m.n_patches;
@@ -73,6 +79,7 @@ static int layout(dnnmg_plan *p, const dnnmg_box *boxes, int nbox) {
         bt += nfull;
         bpart += (int64_t)rt[0] * rt[1] * rt[2] - nfull;
         bp += (d.m.n_patches + 16 * p->pt - 1) / (16 * p->pt);
+        bs += scatter_tiles(d.m);
     }
     p->n_fine = of;
     p->n_coarse = oc;
@@ -82,6 +89,7 @@ static int layout(dnnmg_plan *p, const dnnmg_box *boxes, int nbox) {
     p->tiles_full = bt;
     p->tiles_part = bpart;
     p->ptiles = bp;
+    p->stiles = bs;
     return DNNMG_OK;
 }
 
@@ -111,6 +119,7 @@ extern "C" int dnnmg_plan_create(const dnnmg_box *boxes, int nbox, const dnnmg_n
     p->ns = *ns;
     p->pt = 2; // instantiated for every network; the autotuner may change it
     p->grid = 0;
+    p->scatter_form = DNNMG_SCATTER_TILED;
     int rc = layout(p, boxes, nbox);
     if (rc) {
         delete p;
@@ -145,6 +154,26 @@ extern "C" int dnnmg_plan_choice(const dnnmg_plan *p, int *patches_per_tile, int
     return DNNMG_OK;
 }
 
+extern "C" int dnnmg_plan_scatter_form(const dnnmg_plan *p, int *form) {
+    if (!p || !form) return fail(DNNMG_ERR_ARG, "dnnmg_plan_scatter_form: NULL argument");
+    *form = p->scatter_form;
+    return DNNMG_OK;
+}
+
+extern "C" int dnnmg_plan_set_scatter_form(dnnmg_plan *p, int form) {
+    if (!p) return fail(DNNMG_ERR_ARG, "dnnmg_plan_set_scatter_form: plan is NULL");
+    if (form != DNNMG_SCATTER_NODES && form != DNNMG_SCATTER_TILED)
+        return fail(DNNMG_ERR_ARG, "dnnmg_plan_set_scatter_form: form %d is neither nodes nor tiled", form);
+    p->scatter_form = form;
+    return DNNMG_OK;
+}
+
+static void scatter_stage(const dnnmg_plan *p, int form, const float *Y, const float *xt, float *xcorr,
+                          hipStream_t s) {
+    if (form == DNNMG_SCATTER_TILED) scatter_tiled_batch_launch(p->d_desc, p->nbox, p->stiles, Y, xt, xcorr, s);
+    else scatter_batch_launch(p->d_desc, p->nbox, p->blk_fine, Y, xt, xcorr, s);
+}
+
 // vprev == NULL: b holds the previous step's right-hand side on entry and
 // the residual is r = b - A(x~); b is then overwritten with the new one.
 static int step_impl(const dnnmg_plan *p, const dnnmg_mlp *net, const float *shift, const float *inv,
@@ -157,7 +186,7 @@ static int step_impl(const dnnmg_plan *p, const dnnmg_mlp *net, const float *shi
     int rc = fwd_launch(net, p->pt, true, p->ptiles, p->grid, 0, nullptr, 0, D, p->nbox, none, xt, r, shift, inv,
                         Y, nullptr, s);
     if (rc) return rc;
-    scatter_batch_launch(D, p->nbox, p->blk_fine, Y, xt, xcorr, s);
+    scatter_stage(p, p->scatter_form, Y, xt, xcorr, s);
     rhs_batch_launch(D, p->nbox, p->tiles_full, p->tiles_part, xcorr, b, s);
     restrict_batch_launch(D, p->nbox, p->blk_coarse, b, bc, s);
     return hip_check(hipGetLastError(), "dnnmg_batch_step launch");
@@ -259,10 +288,28 @@ extern "C" int dnnmg_plan_autotune(dnnmg_plan *p, const dnnmg_mlp *net, const fl
             }
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     p->grid = best_grid;
     if (!rc) rc = set_pt(best_pt);
+    // the extension stage: per node or in tiles, on the network's outputs
+    float best_s = 1e30f;
+    int best_form = p->scatter_form;
+    const int forms[2] = {DNNMG_SCATTER_NODES, DNNMG_SCATTER_TILED};
+    for (int fi = 0; fi < 2 && !rc; ++fi) {
+        scatter_stage(p, forms[fi], Y, xt, xcorr, s);
+        if ((rc = hip_check(hipEventRecord(e0, s), "autotune event record"))) break;
+        for (int k = 0; k < reps; ++k) scatter_stage(p, forms[fi], Y, xt, xcorr, s);
+        if ((rc = hip_check(hipEventRecord(e1, s), "autotune event record"))) break;
+        if ((rc = hip_check(hipEventSynchronize(e1), "autotune launch"))) break;
+        float ms = 0.f;
+        if ((rc = hip_check(hipEventElapsedTime(&ms, e0, e1), "autotune timing"))) break;
+        if (ms < best_s) {
+            best_s = ms;
+            best_form = forms[fi];
+        }
+    }
+    p->scatter_form = best_form;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (!rc) rc = hip_check(hipStreamSynchronize(s), "autotune sync");
     return rc;
 }

@@ -98,6 +98,7 @@ struct BoxDesc {
     ResParams rp;
     int64_t off_fine, off_coarse, off_patch;
     int64_t blk_fine, blk_coarse, blk_ptile;
+    int64_t blk_stile;          // extension (scatter) tiles: prefix sum over the boxes
     int64_t blk_full, blk_part; // residual tiles: prefix sums of full / partial tiles
     int32_t rtiles[3];          // residual tile grid of the box
     int32_t rfull[3];           // its box of full tiles (no node beyond the mesh)

@@ -484,9 +484,27 @@ __global__ void __launch_bounds__(ST_NT) k_scatter_tiled(Mesh m, int gx, int gy,
                               vbase, d);
 }
 
-// -------------------------------------------------------------- norms -----
 constexpr int NORM_BLOCKS = 1024;
 
+// Batched tiled extension: one flat grid over the scatter tiles of all boxes
+// (prefix sums blk_stile), in the XCD-contiguous order of the single box.
+template <int ST_Z, int ST_NT>
+__global__ void __launch_bounds__(ST_NT) k_scatter_tiled_batch(const BoxDesc *__restrict__ D, int nbox,
+                                                               int64_t ntiles, const float *__restrict__ Y,
+                                                               const float *__restrict__ vbase,
+                                                               float *__restrict__ xc) {
+    const int64_t t = xcd_item(blockIdx.x, gridDim.x);
+    if (t >= ntiles) return;
+    const int b = find_box(nbox, t, [&](int i) { return D[i].blk_stile; });
+    const BoxDesc &dd = D[b];
+    const Mesh m = dd.m;
+    const int gx = stiles_axis(m.nf[0], ST_X), gy = stiles_axis(m.nf[1], ST_Y), gz = stiles_axis(m.nf[2], ST_Z);
+    const int64_t l = t - dd.blk_stile;
+    scatter_tile<ST_Z, ST_NT>(m, (int)(l % gx), (int)((l / gx) % gy), (int)(l / ((int64_t)gx * gy)), gx, gy, gz,
+                              Y + 81 * dd.off_patch, vbase + 4 * dd.off_fine, xc + 4 * dd.off_fine);
+}
+
+// -------------------------------------------------------------- norms -----
 // Block (x, y) sums vector y (a, or a1 for y = 1) over the grid-stride
 // range of x; part[y][x].  Every vector is reduced over the same partition
 // in the same order, whichever launch it is in.
@@ -543,6 +561,15 @@ void restrict_batch_launch(const BoxDesc *D, int nbox, int64_t nblk, const float
 void scatter_batch_launch(const BoxDesc *D, int nbox, int64_t nblk, const float *Y, const float *vbase, float *xc,
                           hipStream_t s) {
     k_scatter_batch<<<(unsigned)nblk, 256, 0, s>>>(D, nbox, Y, vbase, xc);
+}
+// Extension tiles of one box (the tiled form's grid).
+int64_t scatter_tiles(const Mesh &m) {
+    return (int64_t)stiles_axis(m.nf[0], ST_X) * stiles_axis(m.nf[1], ST_Y) * stiles_axis(m.nf[2], SCATTER_TZ);
+}
+void scatter_tiled_batch_launch(const BoxDesc *D, int nbox, int64_t ntiles, const float *Y, const float *vbase,
+                                float *xc, hipStream_t s) {
+    k_scatter_tiled_batch<SCATTER_TZ, SCATTER_NT>
+        <<<xcd_blocks(ntiles), SCATTER_NT, 0, s>>>(D, nbox, ntiles, Y, vbase, xc);
 }
 
 

@@ -54,13 +54,48 @@ def test_batched_matches_single(mods, dtype):
         assert np.array_equal(out[b]["bc"], ref["bc"]), b
     # autotuned choice gives the same numbers
     ppt, grid = bs.autotune(reps=3)
-    say(f"  autotuned: {ppt} patches per tile, persistent grid {grid}")
+    say(f"  autotuned: {ppt} patches per tile, persistent grid {grid}, extension form {bs.plan.scatter_form()}")
     assert ppt in (16, 32, 64)
+    assert bs.plan.scatter_form() in (L.SCATTER_NODES, L.SCATTER_TILED)
     bs.load(xcs, vps)  # the step carries the right-hand side: start again
     bs.step()
     out2 = bs.results()
     for b in range(len(BOXES)):
         assert np.array_equal(out2[b]["bc"], out[b]["bc"]), b
+
+
+MIXED = BOXES[:3] + [syn.BoxSpec((10, 4, 4), (2.5, 0.41, 0.41), 0, 0b110110),  # channel-like, walls
+                      syn.BoxSpec((6, 5, 3), (1.0, 1.0, 1.0), 1, 0),
+                      syn.BoxSpec((20, 6, 6), (2.0, 1.0, 1.0), 4, 0b000011)]
+
+
+def test_batched_scatter_forms_agree(mods):
+    """The plan's extension stage per node and in tiles: the same sums in the
+    same order, so the corrected iterate is bit for bit the same, on periodic,
+    partly periodic and walled boxes of uneven sizes (tiles cut by the mesh
+    end, periodic axes shorter than a tile)."""
+    L, batched, stepper = mods
+    ns = syn.NSParams(1e-3, 0.01)
+    params = syn.mlp_params(165, 256, 81, seed=6)
+    xcs, vps = batch_inputs(MIXED, seed=20)
+    outs = {}
+    for form in (L.SCATTER_NODES, L.SCATTER_TILED):
+        bs = batched.BatchedStep(MIXED, ns, params, dtype="bf16")
+        bs.plan.set_scatter_form(form)
+        assert bs.plan.scatter_form() == form
+        bs.load(xcs, vps)
+        bs.step()
+        outs[form] = bs.results()
+    for b in range(len(MIXED)):
+        for key in ("xcorr", "bc"):
+            assert np.array_equal(outs[L.SCATTER_NODES][b][key], outs[L.SCATTER_TILED][b][key]), (b, key)
+    # each box's tiled extension equals the single box's
+    for b, box in enumerate(MIXED):
+        st = stepper.CorrectionStep(box, ns, params, dtype="bf16")
+        ref = st.run_numpy(xcs[b], vps[b])
+        assert np.array_equal(outs[L.SCATTER_TILED][b]["xcorr"][:3], ref["vcorr"].astype(np.float32)), b
+    with pytest.raises(Exception):
+        bs.plan.set_scatter_form(L.SCATTER_AUTO)
 
 
 def test_batched_graph_replay(mods):
