@@ -485,6 +485,24 @@ int dnnmg_prolong_levels(const dnnmg_box *box, int levels, int ncomp, const doub
 /* Its transpose (restriction of the rhs, Algorithm 1), FP64 accumulation:
  * bf FP32 [ncomp][n_fine(L+J)] -> bc FP64 [ncomp][n_coarse]. */
 int dnnmg_restrict_levels(const dnnmg_box *box, int levels, int ncomp, const float *bf, double *bc, void *stream);
+
+/* Prolongation J levels up fused with the residual of level L + J against a
+ * given right-hand side (Algorithm 1, the fine residual at x~ = P^J x^L;
+ * Sec. 4.2 for J): xt = dnnmg_prolong_levels(xc) bit for bit and
+ * r = b - A(xt) with A the new-iterate terms of eq. (4cranknicholson3), as
+ * dnnmg_prolong_residual_b on the box of level L + J.  The local projection
+ * terms of eq. (disc:ns) project onto level L + J - 1, of which xt is the
+ * patchwise Q1 interpolant, so they vanish and are not evaluated.  J = 1 is
+ * dnnmg_prolong_residual_b (ws unused, may be NULL).  J = 2 first writes
+ * level L + 1 (FP32 values, widened to FP64) to ws, then runs the one-level
+ * pass on the doubled box.
+ *   xc FP64 [4][n_coarse]; b, xt, r FP32 [4][n_fine of level L + J];
+ *   ws device, 16-byte aligned, dnnmg_prolong_residual_b_levels_workspace()
+ *   bytes (0 for J = 1; 0 also for an invalid box or J); b == r is
+ *   DNNMG_ERR_ARG, a short workspace DNNMG_ERR_SHAPE. */
+size_t dnnmg_prolong_residual_b_levels_workspace(const dnnmg_box *box, int levels);
+int dnnmg_prolong_residual_b_levels(const dnnmg_box *box, int levels, const dnnmg_ns *ns, const double *xc,
+                                    const float *b, float *xt, float *r, void *ws, size_t ws_bytes, void *stream);
 /* Operator Q of eq. (defQ) on the J-level patches: row M = [u(nodes), v, w,
  * r_u, r_v, r_w, H0, H1, H2] standardised by `feat` (device arrays of
  * 6 (2^J+1)^3 + 3 floats or NULL), FP32 or BF16, X [n_patches][ldx]

@@ -156,6 +156,8 @@ _sig("dnnmg_mlp_prepare_io", [ctypes.c_int] * 4 + [c_vp * 3, c_vp * 3, c_vp * 3,
 _sig("dnnmg_level_sizes", [_P(Box), ctypes.c_int, _P(c_i64), _P(c_i64), _P(c_i64)])
 _sig("dnnmg_patch_dofmap_levels", [_P(Box), ctypes.c_int, c_vp, c_vp, c_vp])
 _sig("dnnmg_prolong_levels", [_P(Box), ctypes.c_int, ctypes.c_int, c_vp, c_vp, c_vp])
+_sig("dnnmg_prolong_residual_b_levels_workspace", [_P(Box), ctypes.c_int], c_sz)
+_sig("dnnmg_prolong_residual_b_levels", [_P(Box), ctypes.c_int, _P(NS), c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp])
 _sig("dnnmg_restrict_levels", [_P(Box), ctypes.c_int, ctypes.c_int, c_vp, c_vp, c_vp])
 _sig("dnnmg_patch_gather_levels", [_P(Box), ctypes.c_int, c_vp, c_vp, _P(Feat), ctypes.c_int, c_vp, c_i64, c_vp])
 _sig("dnnmg_scatter_avg_levels", [_P(Box), ctypes.c_int, c_vp, c_vp, c_vp, c_vp])
@@ -200,7 +202,8 @@ EXPORTS = [
     "dnnmg_batch_step_b", "dnnmg_batch_rhs", "dnnmg_norm2_pair_f64", "dnnmg_mlp_prepare",
     "dnnmg_graph_capture_begin", "dnnmg_graph_capture_end", "dnnmg_graph_replay", "dnnmg_graph_destroy",
     "dnnmg_mlp_packed_bytes_io", "dnnmg_mlp_pack_io", "dnnmg_mlp_prepare_io", "dnnmg_level_sizes",
-    "dnnmg_patch_dofmap_levels", "dnnmg_prolong_levels", "dnnmg_restrict_levels", "dnnmg_patch_gather_levels",
+    "dnnmg_patch_dofmap_levels", "dnnmg_prolong_levels", "dnnmg_prolong_residual_b_levels_workspace",
+    "dnnmg_prolong_residual_b_levels", "dnnmg_restrict_levels", "dnnmg_patch_gather_levels",
     "dnnmg_scatter_avg_levels", "dnnmg_deepnet_widths", "dnnmg_deepnet_packed_bytes", "dnnmg_deepnet_prepare",
     "dnnmg_deepnet_forward", "dnnmg_patch_gather_paper", "dnnmg_coarse_levels", "dnnmg_coarse_workspace",
     "dnnmg_coarse_solve", "dnnmg_coarse_jv", "dnnmg_coarse_vcycle", "dnnmg_q2_residual_b", "dnnmg_q2_rhs", "dnnmg_q2_workspace", "dnnmg_q2_residual_rhs",
@@ -429,6 +432,22 @@ def dnnmg_prolong_levels(box, levels, xc, xf, ncomp=4, stream=None):
     nf, nc, _ = level_sizes(b, levels)
     _check(_lib.dnnmg_prolong_levels(ctypes.byref(b), int(levels), ncomp, _ptr(xc, torch.float64, ncomp * nc, "xc"),
                                      _ptr(xf, torch.float32, ncomp * nf, "xf"), _stream(stream)))
+
+
+def prolong_residual_b_levels_workspace_bytes(box, levels):
+    return int(_lib.dnnmg_prolong_residual_b_levels_workspace(ctypes.byref(Box.of(box)), int(levels)))
+
+
+def dnnmg_prolong_residual_b_levels(box, levels, ns, xc, b, xt, r, ws=None, stream=None):
+    bx = Box.of(box)
+    nf, nc, _ = level_sizes(bx, levels)
+    nbytes = 0 if ws is None else ws.numel() * ws.element_size()
+    _check(_lib.dnnmg_prolong_residual_b_levels(ctypes.byref(bx), int(levels), ctypes.byref(NS.of(ns)),
+                                                _ptr(xc, torch.float64, 4 * nc, "xc"),
+                                                _ptr(b, torch.float32, 4 * nf, "b"),
+                                                _ptr(xt, torch.float32, 4 * nf, "xt"),
+                                                _ptr(r, torch.float32, 4 * nf, "r"),
+                                                None if ws is None else _ptr(ws), nbytes, _stream(stream)))
 
 
 def dnnmg_restrict_levels(box, levels, bf, bc, ncomp=4, stream=None):

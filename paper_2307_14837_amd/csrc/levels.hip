@@ -486,6 +486,8 @@ static int level2_meshes(const dnnmg_box *box, Mesh *m, Mesh *m2) {
     return make_mesh(&b2, m2);
 }
 
+void prolong_wide_launch(const Mesh &m, int ncomp, const double *xc, double *xf, hipStream_t s);
+
 } // namespace dnnmg
 
 using namespace dnnmg;
@@ -540,6 +542,40 @@ extern "C" int dnnmg_prolong_levels(const dnnmg_box *box, int levels, int ncomp,
     else
         k_prolong2<<<blocks_for((int64_t)ncomp * m2.n_fine, 256), 256, 0, STREAM>>>(m, m2, ncomp, xc, xf);
     return hip_check(hipGetLastError(), "dnnmg_prolong_levels launch");
+}
+
+extern "C" size_t dnnmg_prolong_residual_b_levels_workspace(const dnnmg_box *box, int levels) {
+    if (check_levels(levels, "dnnmg_prolong_residual_b_levels_workspace")) return 0;
+    Mesh m;
+    if (make_mesh(box, &m)) return 0;
+    return levels == 1 ? 0 : (sizeof(double) * 4 * (size_t)m.n_fine + 255) / 256 * 256;
+}
+
+// J = 2: level L + 1 = P x^L in FP32 operations (widened to FP64 in the
+// workspace), then the one-level fused pass on the doubled box prolongs it
+// to level L + 2 with the same operations -- x~ is the two-level
+// prolongation bit for bit -- and evaluates only the new iterate's terms:
+// x~ is the patch interpolant of level L + 1 exactly, so the local
+// projection terms (onto level L + 1) vanish and are not evaluated.
+extern "C" int dnnmg_prolong_residual_b_levels(const dnnmg_box *box, int levels, const dnnmg_ns *ns,
+                                               const double *xc, const float *b, float *xt, float *r, void *ws,
+                                               size_t ws_bytes, void *stream) {
+    int rc = check_levels(levels, "dnnmg_prolong_residual_b_levels");
+    if (rc) return rc;
+    if (levels == 1) return dnnmg_prolong_residual_b(box, ns, xc, b, xt, r, stream);
+    Mesh m, m2;
+    if ((rc = level2_meshes(box, &m, &m2))) return rc;
+    if (!xc || !b || !xt || !r || !ws) return fail(DNNMG_ERR_ARG, "dnnmg_prolong_residual_b_levels: NULL pointer");
+    const size_t need = dnnmg_prolong_residual_b_levels_workspace(box, levels);
+    if (ws_bytes < need)
+        return fail(DNNMG_ERR_SHAPE, "dnnmg_prolong_residual_b_levels: workspace %zu < %zu bytes", ws_bytes, need);
+    if ((uintptr_t)ws % 16) return fail(DNNMG_ERR_ARG, "dnnmg_prolong_residual_b_levels: ws not 16-byte aligned");
+    double *x1 = (double *)ws;
+    prolong_wide_launch(m, 4, xc, x1, STREAM);
+    if ((rc = hip_check(hipGetLastError(), "dnnmg_prolong_residual_b_levels launch"))) return rc;
+    dnnmg_box b2 = *box;
+    for (int a = 0; a < 3; ++a) b2.n[a] = 2 * box->n[a];
+    return dnnmg_prolong_residual_b(&b2, ns, x1, b, xt, r, stream);
 }
 
 extern "C" int dnnmg_restrict_levels(const dnnmg_box *box, int levels, int ncomp, const float *bf, double *bc,

@@ -55,8 +55,9 @@ __global__ void k_mult(Mesh m, uint8_t *__restrict__ mult) {
 // rounded to FP32 and averaged axis by axis (x, then y, then z) in FP32, the
 // same operations the residual kernel uses for the patch interpolant, so a
 // prolongated field equals its own patch interpolant bit for bit.
+template <typename TO>
 __device__ __forceinline__ void prolong_node(const Mesh &m, int64_t t, int ncomp, const double *__restrict__ xc,
-                                             float *__restrict__ xf) {
+                                             TO *__restrict__ xf) {
     if (t >= (int64_t)ncomp * m.n_coarse) return;
     const int comp = (int)(t / m.n_coarse);
     t -= (int64_t)comp * m.n_coarse;
@@ -95,14 +96,14 @@ __device__ __forceinline__ void prolong_node(const Mesh &m, int64_t t, int ncomp
 #pragma unroll
     for (int ab = 0; ab < 4; ++ab) { pz[ab] = py[ab]; pz[ab + 4] = 0.5f * (py[ab] + py[ab + 4]); }
     const int64_t f0 = 2 * (int64_t)I + (int64_t)m.nf[0] * (2 * (int64_t)J + (int64_t)m.nf[1] * 2 * K);
-    float *out = xf + (int64_t)comp * m.n_fine + f0;
+    TO *out = xf + (int64_t)comp * m.n_fine + f0;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         if (c && !odd[2]) break;
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
             if (b && !odd[1]) break;
-            float *row = out + (int64_t)m.nf[0] * (b + (int64_t)m.nf[1] * c);
+            TO *row = out + (int64_t)m.nf[0] * (b + (int64_t)m.nf[1] * c);
             row[0] = pz[2 * b + 4 * c];
             if (odd[0]) row[1] = pz[1 + 2 * b + 4 * c];
         }
@@ -112,6 +113,16 @@ __device__ __forceinline__ void prolong_node(const Mesh &m, int64_t t, int ncomp
 __global__ void __launch_bounds__(256) k_prolong(Mesh m, int ncomp, const double *__restrict__ xc,
                                                  float *__restrict__ xf) {
     prolong_node(m, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, ncomp, xc, xf);
+}
+
+// The same FP32 values widened to FP64 (exact): the level L + 1 iterate of a
+// two-level prolongation, which the level L + 2 residual pass prolongs again.
+__global__ void __launch_bounds__(256) k_prolong_wide(Mesh m, int ncomp, const double *__restrict__ xc,
+                                                      double *__restrict__ xf) {
+    prolong_node(m, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, ncomp, xc, xf);
+}
+void prolong_wide_launch(const Mesh &m, int ncomp, const double *xc, double *xf, hipStream_t s) {
+    k_prolong_wide<<<blocks_for((int64_t)ncomp * m.n_coarse, 256), 256, 0, s>>>(m, ncomp, xc, xf);
 }
 
 

@@ -69,6 +69,9 @@ class CorrectionStep:
         self.vprev = torch.zeros(3 * self.nf, **f32)
         self.r = torch.zeros(4 * self.nf, **f32)
         self.ws_res = torch.zeros(L.residual_workspace_bytes(self.fbox), dtype=torch.uint8, device=self.dev)
+        # level L + 1 of the fused two-level prolongation and residual
+        nws = L.prolong_residual_b_levels_workspace_bytes(self.box, self.levels)
+        self.ws_pr = torch.zeros(nws, dtype=torch.uint8, device=self.dev) if nws else None
         # FP8 networks take BF16 inputs (their first layer is BF16)
         self.xdtype = L.F32 if self.dtype == L.F32 else L.BF16
         self.X = torch.zeros(self.np * self.ldx, dtype=_TORCH[self.xdtype], device=self.dev)
@@ -169,9 +172,11 @@ class CorrectionStep:
         side or from v_prev), Q and the network on the J-level patches, L
         back to level L + J, [indicator], Rhs on fbox, b^L = (P^J)^T b."""
         box, fb, ns, J = self.box, self.fbox, self.ns, self.levels
-        if J == 1 and self.carry_rhs:
-            # one level: prolongation and residual in one pass, as in step()
-            L.dnnmg_prolong_residual_b(box, ns, self.xc, self.b, self.xt, self.r, stream=stream)
+        if self.carry_rhs:
+            # prolongation and residual in one pass (J = 2: level L + 1
+            # first), the local projection terms vanishing on x~
+            L.dnnmg_prolong_residual_b_levels(box, J, ns, self.xc, self.b, self.xt, self.r, ws=self.ws_pr,
+                                              stream=stream)
         else:
             L.dnnmg_prolong_levels(box, J, self.xc, self.xt, stream=stream)
             if self.carry_rhs:

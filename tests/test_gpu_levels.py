@@ -203,3 +203,39 @@ def test_step_levels_fallback(orc):
         e = rel_l2(out[key], ref[key])
         say(f"  fallback {key} rel-L2 {e:.2e}")
         assert e <= 1e-4, key
+
+
+@pytest.mark.parametrize("name", list(BOXES))
+def test_prolong_residual_b_levels(L, orc, name):
+    """Two-level prolongation fused with the level L + 2 residual against
+    b = Rhs(v_prev): x~ is dnnmg_prolong_levels' bit for bit, and r is the
+    oracle's Crank-Nicolson residual at x~ (whose local projection terms
+    vanish, x~ being the patch interpolant of level L + 1)."""
+    box = BOXES[name]
+    say("two-level prolongation + residual", name)
+    ns = syn.NSParams(1e-3, 0.01)
+    fb = L.level_box(box, 2)
+    nf, nc, _ = L.level_sizes(box, 2)
+    rng = np.random.default_rng(31)
+    xc = rng.standard_normal((4, nc))
+    vp = f32(rng.standard_normal((3, nf)))
+    xcg, vpg = to_gpu(xc.ravel()), to_gpu(vp.ravel())
+    new = lambda: torch.full((4 * nf,), float("nan"), dtype=torch.float32, device=dev())
+    xt0 = new()
+    L.dnnmg_prolong_levels(box, 2, xcg, xt0)
+    b = new()
+    L.dnnmg_rhs(fb, ns, vpg, b)
+    ws = torch.empty(L.prolong_residual_b_levels_workspace_bytes(box, 2), dtype=torch.uint8, device=dev())
+    assert ws.numel() == (8 * 4 * L.level_sizes(box, 1)[0] + 255) // 256 * 256
+    xt, r = new(), new()
+    L.dnnmg_prolong_residual_b_levels(box, 2, ns, xcg, b, xt, r, ws=ws)
+    torch.cuda.synchronize()
+    assert torch.equal(xt0, xt)
+    ref = orc.residual(fb, ns, xt.cpu().numpy().reshape(4, -1).astype(np.float64), vp.astype(np.float64))
+    e = rel_l2(r.cpu().numpy().reshape(4, -1), ref)
+    say(f"  rel-L2 {e:.2e}")
+    assert e <= 1e-5
+    with pytest.raises(L.DnnmgError):
+        L.dnnmg_prolong_residual_b_levels(box, 2, ns, xcg, b, xt, b, ws=ws)
+    with pytest.raises(L.DnnmgError):
+        L.dnnmg_prolong_residual_b_levels(box, 2, ns, xcg, b, xt, r, ws=ws[:8])
